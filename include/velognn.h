@@ -1,0 +1,170 @@
+/*
+ * velognn.h -- C ABI of the MI355X (gfx950) VELO GNN track-finding library.
+ *
+ * The library runs the data-parallel inference path of the GNN track finder of
+ * "Graph Neural Network-Based Track Finding in the LHCb Vertex Detector"
+ * (arXiv 2407.12119) over a batch of independent events:
+ *
+ *   hits (x, y, z, plane) of many events
+ *     -> hit embedding MLP                     (Sec. 5.1)
+ *     -> rough graph: hits on plane p joined to hits on p+1, p+2 within a
+ *        squared embedding distance, at most k_max per hit   (Sec. 5.1, 7.2)
+ *     -> interaction-network GNN edge logits   (Sec. 5.2)
+ *     -> edge cut and connected components     (Sec. 5, 7.3)
+ *   -> per-hit track labels and per-edge scores.
+ *
+ * Conventions shared by every call:
+ *   - All array pointers are DEVICE pointers unless the name says otherwise;
+ *     the caller owns every input and output buffer.  The library owns the
+ *     context, its workspace and its converted copy of the parameters.
+ *   - `stream` is a hipStream_t passed as void*.  Every call is asynchronous
+ *     on that stream and allocates nothing; velo_create/velo_destroy allocate
+ *     and free.  A context is not thread-safe: one context per host thread.
+ *   - Hits are grouped by event: event b owns hits
+ *     [event_offsets[b], event_offsets[b+1]).  Within an event the hits are
+ *     sorted by plane (non-decreasing); plane lies in [0, VELO_N_PLANES).
+ *   - Every index in an output is EVENT-LOCAL (0 .. hits of that event - 1),
+ *     so an event gives identical outputs alone or inside a batch.
+ *   - Errors found on the host are returned at once.  Errors found on the
+ *     device (invalid input, capacity overflow) are latched in the context
+ *     and returned by velo_check(), which synchronises the stream; while an
+ *     error is latched the device stages of later calls do no work.
+ *   - No call aborts the process and no C++ exception crosses this ABI.
+ */
+#ifndef VELOGNN_H
+#define VELOGNN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VELO_N_PLANES 26      /* VELO planes (Sec. 2) */
+#define VELO_EMB_HIDDEN 128   /* embedding MLP width: 3 -> 128 -> 128 -> 4 */
+#define VELO_EMB_DIM 4        /* embedding dimension n_dim (Sec. 5.1) */
+
+typedef enum {
+    VELO_OK = 0,
+    VELO_ERR_INVALID_ARG = 1,   /* bad host argument (null pointer, size, config) */
+    VELO_ERR_CAPACITY = 2,      /* more hits/edges/events than the context holds */
+    VELO_ERR_OOM = 3,           /* device allocation failed in velo_create */
+    VELO_ERR_DEVICE = 4,        /* a HIP runtime call failed */
+    VELO_ERR_UNSUPPORTED = 5,   /* configuration not compiled in (e.g. hidden width) */
+    VELO_ERR_INPUT = 6          /* device-side validation of the hits failed */
+} velo_status;
+
+typedef enum {
+    VELO_FP32 = 0,   /* MLP operands and state in float32 */
+    VELO_BF16 = 1,   /* MLP operands bfloat16, float32 accumulation */
+    VELO_FP8 = 2     /* MLP operands FP8 E4M3 with per-tensor scales */
+} velo_precision;
+
+/* Network and capacity configuration, fixed for the life of a context. */
+typedef struct {
+    int32_t gnn_hidden;      /* H = n_h = n_e (Sec. 5.2); 32, 64 or 128 */
+    int32_t gnn_iters;       /* message-passing steps n (Sec. 5.2); 0..16 */
+    float d2_max;            /* edge iff squared distance < d2_max (Sec. 5.1) */
+    int32_t k_max;           /* most edges per hit (Sec. 5.1); 1..64 */
+    float edge_logit_min;    /* keep an edge iff logit >= this (0 == score 0.5) */
+    int32_t precision;       /* velo_precision */
+    int64_t max_hits;        /* capacity: hits per call */
+    int64_t max_edges;       /* capacity: edges per call (< 2^31) */
+    int32_t max_events;      /* capacity: events per call */
+    int32_t max_event_hits;  /* capacity: hits of one event (<= 32768) */
+} velo_config;
+
+/* A batch of hits.  n_events and n_hits are HOST values; n_hits must equal
+ * event_offsets[n_events] (checked on the device). */
+typedef struct {
+    int32_t n_events;
+    int64_t n_hits;
+    const int32_t *event_offsets;   /* [n_events + 1], event_offsets[0] == 0 */
+    const float *x, *y, *z;         /* [n_hits], mm */
+    const int32_t *plane;           /* [n_hits] */
+} velo_hits;
+
+/* Per-edge and per-hit results.  Any pointer a call does not write may be
+ * NULL.  n_edges receives the total edge count even when it exceeds
+ * edge_capacity (then the edge arrays hold only the first edge_capacity
+ * edges and velo_check returns VELO_ERR_CAPACITY). */
+typedef struct {
+    int32_t *labels;          /* [n_hits] track label: smallest event-local hit index of the component */
+    int32_t *edge_offsets;    /* [n_events + 1] edges of event b: [edge_offsets[b], edge_offsets[b+1]) */
+    int32_t *edge_src;        /* [edge_capacity] event-local source hit (lower plane) */
+    int32_t *edge_dst;        /* [edge_capacity] event-local destination hit */
+    float *edge_logit;        /* [edge_capacity] classifier logit; score = sigmoid(logit) */
+    int64_t edge_capacity;
+    int32_t *n_edges;         /* [1] total edges of the batch */
+} velo_outputs;
+
+typedef struct velo_ctx velo_ctx;
+
+/* Number of float32 entries of the parameter blob for hidden width H and n
+ * steps.  Blob layout (every Linear row-major [out x in], then its bias):
+ *   norm[12] = emb_mu[3], emb_sigma[3] (over r, phi, z; Sec. 5.1 footnote),
+ *              gnn_mu[3], gnn_sigma[3] (over x, y, z; Sec. 5.2)
+ *   embedding [128x3] [128x128] [4x128]
+ *   node encoder [Hx3] [HxH]; edge encoder [Hx2H] [HxH]
+ *   for each step k: node net [Hx3H] [HxH], edge net [Hx3H] [HxH]
+ *   edge classifier [HxH] [1xH]
+ * Every MLP has a ReLU between its layers and none after the last.
+ * Returns -1 for an unsupported shape. */
+int64_t velo_param_count(int32_t gnn_hidden, int32_t gnn_iters);
+
+/* Create a context: validates `cfg`, allocates the workspace for its
+ * capacities and a parameter buffer.  *out is NULL on failure. */
+velo_status velo_create(const velo_config *cfg, velo_ctx **out);
+
+/* Free everything the context owns (waits for its work).  NULL is a no-op. */
+void velo_destroy(velo_ctx *ctx);
+
+/* Copy the float32 parameter blob (device pointer, n entries, layout above)
+ * into the context and convert it for the context's precision.  Must be
+ * called before any compute call; may be called again (e.g. after an
+ * optimiser step) and is ordered with later work on the same stream. */
+velo_status velo_set_params(velo_ctx *ctx, const float *params, int64_t n, void *stream);
+
+/* Whole path: embedding, rough graph, GNN, edge cut, components.  Writes
+ * labels, edge_offsets, edge_src, edge_dst, edge_logit and n_edges. */
+velo_status velo_infer(velo_ctx *ctx, const velo_hits *hits, velo_outputs *out, void *stream);
+
+/* Stage: embedding of every hit, emb[i * VELO_EMB_DIM + c], float32 (Sec. 5.1). */
+velo_status velo_embed(velo_ctx *ctx, const velo_hits *hits, float *emb, void *stream);
+
+/* Stage: rough graph from a given embedding (float32 [n_hits x 4]).  Writes
+ * edge_offsets, edge_src, edge_dst, n_edges.  Within an event edges are
+ * sorted by source hit, then destination hit.  The squared distance is
+ * evaluated in float32 as d = a_c - b_c, s = d_0*d_0, s = fma(d_c, d_c, s)
+ * for c = 1..3; among more than k_max candidates the k_max smallest under
+ * (s, destination index) are kept (Sec. 5.1, 7.2). */
+velo_status velo_build_graph(velo_ctx *ctx, const velo_hits *hits, const float *emb,
+                             velo_outputs *graph, void *stream);
+
+/* Stage: GNN edge logits (Sec. 5.2) for a given graph: reads
+ * graph->edge_offsets, edge_src, edge_dst and n_edges (edges grouped by event
+ * and sorted by source within an event, as velo_build_graph writes them)
+ * and writes graph->edge_logit. */
+velo_status velo_gnn(velo_ctx *ctx, const velo_hits *hits, velo_outputs *graph, void *stream);
+
+/* Stage: connected components of the edges with logit >= edge_logit_min
+ * (Sec. 7.3), taken as undirected; reads the graph and logits of `graph` and
+ * writes graph->labels. */
+velo_status velo_components(velo_ctx *ctx, const velo_hits *hits, velo_outputs *graph, void *stream);
+
+/* Synchronise `stream` and return (and clear) the error latched on the
+ * device by earlier calls: VELO_OK, VELO_ERR_INPUT or VELO_ERR_CAPACITY. */
+velo_status velo_check(velo_ctx *ctx, void *stream);
+
+/* Static description of a status code. */
+const char *velo_status_str(velo_status s);
+
+/* Detail of the last host-side error of the context ("" if none). */
+const char *velo_last_error(const velo_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VELOGNN_H */

@@ -1,0 +1,646 @@
+/*
+ * oracle.c -- plain, slow, CPU reference of the VELO GNN track-finding path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing on the product path may link, load or
+ * call this file; only the tests, the smoke check and the benchmark's CPU
+ * baseline leg do.  It shares no code, header, table or constant with the HIP
+ * library.
+ *
+ * Everything is computed in float64 from float32 inputs promoted exactly,
+ * except the one place where floating point decides an integer: the
+ * neighbour-set decision is taken in float32 (the precision the paper's
+ * implementation runs in), with the evaluation order fixed below, so that
+ * both sides decide identically on identical embeddings.
+ *
+ * Stages (paper, Sec. 5):
+ *   features      Sec. 5.1: normalised cylindrical (r, phi, z) for the embedding
+ *   embedding     Sec. 5.1: hit -> e_h in R^{n_dim}, an MLP
+ *   rough graph   Sec. 5.1, squared-distance equation: hits on plane p joined
+ *                 to hits on p+1 and p+2 with d^2 < d2max, at most k_max per
+ *                 node (Sec. 7.2 describes the per-node bounded list)
+ *   GNN           Sec. 5.2: node/edge encoders, n message-passing steps with
+ *                 the scatter_add message equation and residual node/edge
+ *                 networks, distinct per step; edge classifier
+ *   threshold     Sec. 5 (pipeline overview): edges scoring below the cut are
+ *                 dropped
+ *   components    Sec. 5 and Sec. 7.3: connected components of the purified
+ *                 hit graph give the track labels
+ *   loss/gradient weighted binary cross-entropy on the edge logits and its
+ *                 exact gradient (training form; the paper trains with a
+ *                 sigmoid focal loss, Sec. 5.2)
+ *
+ * Parameter blob (float32, every Linear row-major [out x in] then its bias):
+ *   norm[12]: emb_mu[3] emb_sigma[3] gnn_mu[3] gnn_sigma[3]
+ *   embedding: [Ce x 3], [Ce x Ce], [D x Ce]
+ *   node encoder: [H x 3], [H x H];  edge encoder: [H x 2H], [H x H]
+ *   per step k: node net [H x 3H], [H x H]; edge net [H x 3H], [H x H]
+ *   classifier: [H x H], [1 x H]
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------ */
+/* parameter offsets                                                   */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    int64_t w, b;      /* offsets of weight and bias in the blob */
+    int out, in;
+} lin_t;
+
+typedef struct {
+    int H, iters, Ce, D;
+    lin_t emb[3];
+    lin_t nenc[2], eenc[2];
+    lin_t node[64][2], edge[64][2];
+    lin_t cls[2];
+    int64_t total;
+} layout_t;
+
+static int64_t put(lin_t *l, int64_t off, int out, int in)
+{
+    l->w = off;
+    l->b = off + (int64_t)out * in;
+    l->out = out;
+    l->in = in;
+    return l->b + out;
+}
+
+static int make_layout(layout_t *L, int H, int iters, int Ce, int D)
+{
+    if (iters < 0 || iters > 64 || H <= 0 || Ce <= 0 || D <= 0)
+        return -1;
+    int64_t o = 12;
+    L->H = H; L->iters = iters; L->Ce = Ce; L->D = D;
+    o = put(&L->emb[0], o, Ce, 3);
+    o = put(&L->emb[1], o, Ce, Ce);
+    o = put(&L->emb[2], o, D, Ce);
+    o = put(&L->nenc[0], o, H, 3);
+    o = put(&L->nenc[1], o, H, H);
+    o = put(&L->eenc[0], o, H, 2 * H);
+    o = put(&L->eenc[1], o, H, H);
+    for (int k = 0; k < iters; k++) {
+        o = put(&L->node[k][0], o, H, 3 * H);
+        o = put(&L->node[k][1], o, H, H);
+        o = put(&L->edge[k][0], o, H, 3 * H);
+        o = put(&L->edge[k][1], o, H, H);
+    }
+    o = put(&L->cls[0], o, H, H);
+    o = put(&L->cls[1], o, 1, H);
+    L->total = o;
+    return 0;
+}
+
+int64_t oracle_param_count(int H, int iters, int Ce, int D)
+{
+    layout_t L;
+    if (make_layout(&L, H, iters, Ce, D))
+        return -1;
+    return L.total;
+}
+
+/* y = W x + b for one Linear layer, float64, W row-major [out x in]. */
+static void linear(const float *blob, const lin_t *l, const double *x, double *y)
+{
+    const float *W = blob + l->w, *b = blob + l->b;
+    for (int o = 0; o < l->out; o++) {
+        double s = (double)b[o];
+        for (int i = 0; i < l->in; i++)
+            s += (double)W[(int64_t)o * l->in + i] * x[i];
+        y[o] = s;
+    }
+}
+
+static void relu(double *v, int n)
+{
+    for (int i = 0; i < n; i++)
+        if (!(v[i] > 0.0))
+            v[i] = 0.0;
+}
+
+/* Two-layer MLP with a ReLU between: y = W1 relu(W0 x + b0) + b1.
+ * `hid` (size l0->out) receives the pre-activation of the hidden layer. */
+static void mlp2(const float *blob, const lin_t *l0, const lin_t *l1,
+                 const double *x, double *hid, double *y)
+{
+    double a[1024];
+    linear(blob, l0, x, hid);
+    memcpy(a, hid, sizeof(double) * l0->out);
+    relu(a, l0->out);
+    linear(blob, l1, a, y);
+}
+
+/* ------------------------------------------------------------------ */
+/* Sec. 5.1: features and embedding                                    */
+/* ------------------------------------------------------------------ */
+
+/* Normalised cylindrical coordinates (r, phi, z) of one hit, phi = atan2(y, x). */
+static void embed_features(const float *norm, float x, float y, float z, double u[3])
+{
+    double X = x, Y = y, Z = z;
+    double f[3] = { sqrt(X * X + Y * Y), atan2(Y, X), Z };
+    for (int c = 0; c < 3; c++)
+        u[c] = (f[c] - (double)norm[c]) / (double)norm[3 + c];
+}
+
+/* Embedding of every hit of one event: emb[i*D + c], float64. */
+int oracle_embed(int64_t n, const float *x, const float *y, const float *z,
+                 const float *blob, int Ce, int D, double *emb)
+{
+    layout_t L;
+    if (make_layout(&L, 1, 0, Ce, D) || Ce > 1024)
+        return -1;
+    double u[3], h1[1024], h2[1024], pre[1024];
+    for (int64_t i = 0; i < n; i++) {
+        embed_features(blob, x[i], y[i], z[i], u);
+        linear(blob, &L.emb[0], u, h1);
+        relu(h1, Ce);
+        linear(blob, &L.emb[1], h1, pre);
+        memcpy(h2, pre, sizeof(double) * Ce);
+        relu(h2, Ce);
+        linear(blob, &L.emb[2], h2, emb + i * D);
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Sec. 5.1: rough graph                                               */
+/* ------------------------------------------------------------------ */
+
+/* Squared distance, decided in float32: d_c = a_c - b_c rounded to float32,
+ * s = d_0*d_0 rounded, then s = fma(d_c, d_c, s) for c = 1..D-1. */
+static float d2_f32(const float *a, const float *b, int D)
+{
+    float d = a[0] - b[0];
+    float s = d * d;
+    for (int c = 1; c < D; c++) {
+        d = a[c] - b[c];
+        s = fmaf(d, d, s);
+    }
+    return s;
+}
+
+typedef struct { float d2; int32_t j; } cand_t;
+
+static int cand_less(const cand_t *a, const cand_t *b)
+{
+    return a->d2 < b->d2 || (a->d2 == b->d2 && a->j < b->j);
+}
+
+static int cmp_j(const void *a, const void *b)
+{
+    int32_t x = ((const cand_t *)a)->j, y = ((const cand_t *)b)->j;
+    return (x > y) - (x < y);
+}
+
+/*
+ * For every hit i of one event, with plane p, the candidates are the hits j
+ * with plane(j) - p in {1, 2}; j is kept when d2(i, j) < d2max.  If more than
+ * k_max are kept, the k_max smallest under the order (d2, j) remain (a
+ * deterministic form of the bounded nearest-neighbour list).  Rows come out
+ * sorted by j.  row_ptr has n+1 entries; col has room for `cap` entries.
+ * Returns the edge count, or -(edge count) if it exceeds cap (nothing is
+ * written past cap), or INT64_MIN on bad arguments.
+ */
+int64_t oracle_neighbours(int64_t n, const int32_t *plane, const float *emb, int D,
+                          float d2max, int k_max, int32_t *row_ptr, int32_t *col, int64_t cap)
+{
+    if (n < 0 || D <= 0 || k_max <= 0)
+        return INT64_MIN;
+    cand_t *buf = (cand_t *)malloc(sizeof(cand_t) * (size_t)(n > 0 ? n : 1));
+    if (!buf)
+        return INT64_MIN;
+    int64_t E = 0;
+    row_ptr[0] = 0;
+    for (int64_t i = 0; i < n; i++) {
+        int m = 0;
+        for (int64_t j = 0; j < n; j++) {
+            int dp = plane[j] - plane[i];
+            if (dp != 1 && dp != 2)
+                continue;
+            float d2 = d2_f32(emb + i * D, emb + j * D, D);
+            if (d2 < d2max) {
+                buf[m].d2 = d2;
+                buf[m].j = (int32_t)j;
+                m++;
+            }
+        }
+        if (m > k_max) {
+            /* selection: move the k_max smallest (d2, j) to the front */
+            for (int a = 0; a < k_max; a++) {
+                int best = a;
+                for (int b = a + 1; b < m; b++)
+                    if (cand_less(&buf[b], &buf[best]))
+                        best = b;
+                cand_t t = buf[a]; buf[a] = buf[best]; buf[best] = t;
+            }
+            m = k_max;
+        }
+        qsort(buf, (size_t)m, sizeof(cand_t), cmp_j);
+        for (int a = 0; a < m; a++) {
+            if (E + a < cap)
+                col[E + a] = buf[a].j;
+        }
+        E += m;
+        row_ptr[i + 1] = (int32_t)(E < cap ? E : cap);
+    }
+    free(buf);
+    return E <= cap ? E : -E;
+}
+
+/* ------------------------------------------------------------------ */
+/* Sec. 5.2: interaction-network GNN                                   */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    /* states per step: h[k] is n x H, e[k] is E x H, k = 0..iters */
+    double **h, **e;
+    /* hidden pre-activations: node/edge nets per step, encoders, classifier */
+    double **hn, **he;
+    double *hnenc, *heenc, *hcls;
+    double *xhat;         /* n x 3 normalised Cartesian inputs */
+    double *mo, *mi;      /* messages of every step: iters x n x H each */
+} fwd_t;
+
+static void fwd_free(fwd_t *F, int iters)
+{
+    if (F->h) for (int k = 0; k <= iters; k++) free(F->h[k]);
+    if (F->e) for (int k = 0; k <= iters; k++) free(F->e[k]);
+    if (F->hn) for (int k = 0; k < iters; k++) free(F->hn[k]);
+    if (F->he) for (int k = 0; k < iters; k++) free(F->he[k]);
+    free(F->h); free(F->e); free(F->hn); free(F->he);
+    free(F->hnenc); free(F->heenc); free(F->hcls); free(F->xhat);
+    free(F->mo); free(F->mi);
+    memset(F, 0, sizeof(*F));
+}
+
+#define ALLOC(p, cnt) do { (p) = calloc((size_t)(cnt) > 0 ? (size_t)(cnt) : 1, sizeof(*(p))); if (!(p)) goto oom; } while (0)
+
+/* Full forward pass of one event keeping every intermediate. */
+static int gnn_forward_full(const layout_t *L, const float *blob, int64_t n,
+                            const float *x, const float *y, const float *z,
+                            int64_t E, const int32_t *src, const int32_t *dst,
+                            fwd_t *F, double *logit)
+{
+    const int H = L->H, it = L->iters;
+    const float *norm = blob;
+    double *cat = NULL, *upd = NULL;
+    memset(F, 0, sizeof(*F));
+    ALLOC(F->h, it + 1); ALLOC(F->e, it + 1); ALLOC(F->hn, it > 0 ? it : 1); ALLOC(F->he, it > 0 ? it : 1);
+    for (int k = 0; k <= it; k++) { ALLOC(F->h[k], n * H); ALLOC(F->e[k], E * H); }
+    for (int k = 0; k < it; k++) { ALLOC(F->hn[k], n * H); ALLOC(F->he[k], E * H); }
+    ALLOC(F->hnenc, n * H); ALLOC(F->heenc, E * H); ALLOC(F->hcls, E * H); ALLOC(F->xhat, n * 3);
+    ALLOC(F->mo, (int64_t)it * n * H); ALLOC(F->mi, (int64_t)it * n * H);
+
+    /* node encoder on normalised Cartesian coordinates */
+    for (int64_t i = 0; i < n; i++) {
+        double *xh = F->xhat + i * 3;
+        xh[0] = ((double)x[i] - norm[6]) / (double)norm[9];
+        xh[1] = ((double)y[i] - norm[7]) / (double)norm[10];
+        xh[2] = ((double)z[i] - norm[8]) / (double)norm[11];
+        mlp2(blob, &L->nenc[0], &L->nenc[1], xh, F->hnenc + i * H, F->h[0] + i * H);
+    }
+    /* edge encoder on [h0_src, h0_dst] */
+    ALLOC(cat, 3 * H);
+    for (int64_t q = 0; q < E; q++) {
+        memcpy(cat, F->h[0] + (int64_t)src[q] * H, sizeof(double) * H);
+        memcpy(cat + H, F->h[0] + (int64_t)dst[q] * H, sizeof(double) * H);
+        mlp2(blob, &L->eenc[0], &L->eenc[1], cat, F->heenc + q * H, F->e[0] + q * H);
+    }
+    ALLOC(upd, H);
+    for (int k = 0; k < it; k++) {
+        double *mo = F->mo + (int64_t)k * n * H, *mi = F->mi + (int64_t)k * n * H;
+        /* message: outgoing and incoming sums of e^k (scatter_add) */
+        for (int64_t q = 0; q < E; q++)
+            for (int c = 0; c < H; c++) {
+                mo[(int64_t)src[q] * H + c] += F->e[k][q * H + c];
+                mi[(int64_t)dst[q] * H + c] += F->e[k][q * H + c];
+            }
+        /* node network with residual: h^{k+1} = h^k + phi_k([h^k, m_out, m_in]) */
+        for (int64_t i = 0; i < n; i++) {
+            memcpy(cat, F->h[k] + i * H, sizeof(double) * H);
+            memcpy(cat + H, mo + i * H, sizeof(double) * H);
+            memcpy(cat + 2 * H, mi + i * H, sizeof(double) * H);
+            mlp2(blob, &L->node[k][0], &L->node[k][1], cat, F->hn[k] + i * H, upd);
+            for (int c = 0; c < H; c++)
+                F->h[k + 1][i * H + c] = F->h[k][i * H + c] + upd[c];
+        }
+        /* edge network with residual, using the updated hit encodings */
+        for (int64_t q = 0; q < E; q++) {
+            memcpy(cat, F->e[k] + q * H, sizeof(double) * H);
+            memcpy(cat + H, F->h[k + 1] + (int64_t)src[q] * H, sizeof(double) * H);
+            memcpy(cat + 2 * H, F->h[k + 1] + (int64_t)dst[q] * H, sizeof(double) * H);
+            mlp2(blob, &L->edge[k][0], &L->edge[k][1], cat, F->he[k] + q * H, upd);
+            for (int c = 0; c < H; c++)
+                F->e[k + 1][q * H + c] = F->e[k][q * H + c] + upd[c];
+        }
+    }
+    /* edge classifier on e^n: a logit (score = sigmoid(logit)) */
+    for (int64_t q = 0; q < E; q++)
+        mlp2(blob, &L->cls[0], &L->cls[1], F->e[it] + q * H, F->hcls + q * H, logit + q);
+    free(cat);
+    free(upd);
+    return 0;
+oom:
+    free(cat);
+    free(upd);
+    fwd_free(F, it);
+    return -2;
+}
+
+int oracle_gnn_forward(int64_t n, const float *x, const float *y, const float *z,
+                       int64_t E, const int32_t *src, const int32_t *dst,
+                       const float *blob, int H, int iters, int Ce, int D, double *logit,
+                       double *h_final, double *e_final)
+{
+    layout_t L;
+    if (make_layout(&L, H, iters, Ce, D) || 3 * H > 1024)
+        return -1;
+    for (int64_t q = 0; q < E; q++)
+        if (src[q] < 0 || src[q] >= n || dst[q] < 0 || dst[q] >= n)
+            return -1;
+    fwd_t F;
+    int rc = gnn_forward_full(&L, blob, n, x, y, z, E, src, dst, &F, logit);
+    if (rc)
+        return rc;
+    if (h_final) memcpy(h_final, F.h[iters], sizeof(double) * n * H);
+    if (e_final) memcpy(e_final, F.e[iters], sizeof(double) * E * H);
+    fwd_free(&F, iters);
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* training form: weighted BCE and the exact gradient                  */
+/* ------------------------------------------------------------------ */
+
+/* L = (1/E) sum_q w_q [softplus(z_q) - y_q z_q], w = pos_weight if y = 1 else 1.
+ * dL/dz_q = w_q (sigmoid(z_q) - y_q) / E.  Returns L (0 when E = 0). */
+double oracle_bce(int64_t E, const double *z, const uint8_t *yv, double pos_weight, double *dz)
+{
+    double L = 0.0;
+    for (int64_t q = 0; q < E; q++) {
+        double w = yv[q] ? pos_weight : 1.0;
+        double zz = z[q];
+        double sp = zz > 0 ? zz + log1p(exp(-zz)) : log1p(exp(zz));
+        double sig = zz >= 0 ? 1.0 / (1.0 + exp(-zz)) : exp(zz) / (1.0 + exp(zz));
+        L += w * (sp - (yv[q] ? zz : 0.0));
+        if (dz)
+            dz[q] = w * (sig - (yv[q] ? 1.0 : 0.0)) / (double)E;
+    }
+    return E > 0 ? L / (double)E : 0.0;
+}
+
+/* Backward of y = W1 relu(W0 x + b0) + b1 given dy; accumulates dW/db into
+ * g (blob-shaped, float64) and writes dx (size l0->in). `pre` is the saved
+ * hidden pre-activation. */
+static void mlp2_backward(const float *blob, const lin_t *l0, const lin_t *l1,
+                          const double *x, const double *pre, const double *dy,
+                          double *g, double *dx)
+{
+    const int Hh = l0->out, I = l0->in, O = l1->out;
+    double da[1024];
+    for (int o = 0; o < O; o++)
+        g[l1->b + o] += dy[o];
+    for (int h = 0; h < Hh; h++) {
+        double a = pre[h] > 0.0 ? pre[h] : 0.0;
+        double s = 0.0;
+        for (int o = 0; o < O; o++) {
+            g[l1->w + (int64_t)o * Hh + h] += dy[o] * a;
+            s += (double)blob[l1->w + (int64_t)o * Hh + h] * dy[o];
+        }
+        da[h] = pre[h] > 0.0 ? s : 0.0;
+    }
+    for (int i = 0; i < I; i++)
+        dx[i] = 0.0;
+    for (int h = 0; h < Hh; h++) {
+        g[l0->b + h] += da[h];
+        for (int i = 0; i < I; i++) {
+            g[l0->w + (int64_t)h * I + i] += da[h] * x[i];
+            dx[i] += (double)blob[l0->w + (int64_t)h * I + i] * da[h];
+        }
+    }
+}
+
+/*
+ * Gradient of sum_q dlogit[q] * logit[q] with respect to every GNN parameter
+ * (node/edge encoders, node/edge networks, classifier), by reverse-mode
+ * differentiation of the forward above.  grad is blob-shaped float64; the
+ * normalisation and embedding entries stay zero (graph building is not
+ * differentiable).  The forward is recomputed here.
+ */
+int oracle_gnn_backward(int64_t n, const float *x, const float *y, const float *z,
+                        int64_t E, const int32_t *src, const int32_t *dst,
+                        const float *blob, int H, int iters, int Ce, int D,
+                        const double *dlogit, double *grad)
+{
+    layout_t L;
+    if (make_layout(&L, H, iters, Ce, D) || 3 * H > 1024)
+        return -1;
+    for (int64_t q = 0; q < E; q++)
+        if (src[q] < 0 || src[q] >= n || dst[q] < 0 || dst[q] >= n)
+            return -1;
+    memset(grad, 0, sizeof(double) * L.total);
+    double *logit = NULL, *de = NULL, *dh = NULL, *dhn = NULL, *den = NULL, *cat = NULL, *dx = NULL;
+    fwd_t F;
+    memset(&F, 0, sizeof(F));
+    ALLOC(logit, E);
+    if (gnn_forward_full(&L, blob, n, x, y, z, E, src, dst, &F, logit)) {
+        free(logit);
+        return -2;
+    }
+    ALLOC(de, E * H); ALLOC(dh, n * H); ALLOC(dhn, n * H); ALLOC(den, E * H);
+    ALLOC(cat, 3 * H); ALLOC(dx, 3 * H);
+
+    /* classifier */
+    for (int64_t q = 0; q < E; q++) {
+        double dy = dlogit[q];
+        mlp2_backward(blob, &L.cls[0], &L.cls[1], F.e[iters] + q * H, F.hcls + q * H, &dy, grad, dx);
+        memcpy(de + q * H, dx, sizeof(double) * H);
+    }
+    /* de = dL/de^{k+1}, dh = dL/dh^{k+1} (contributions from step k+1 already in) */
+    for (int k = iters - 1; k >= 0; k--) {
+        double *mo = F.mo + (int64_t)k * n * H, *mi = F.mi + (int64_t)k * n * H;
+        /* edge net k */
+        for (int64_t q = 0; q < E; q++) {
+            memcpy(cat, F.e[k] + q * H, sizeof(double) * H);
+            memcpy(cat + H, F.h[k + 1] + (int64_t)src[q] * H, sizeof(double) * H);
+            memcpy(cat + 2 * H, F.h[k + 1] + (int64_t)dst[q] * H, sizeof(double) * H);
+            mlp2_backward(blob, &L.edge[k][0], &L.edge[k][1], cat, F.he[k] + q * H, de + q * H, grad, dx);
+            for (int c = 0; c < H; c++) {
+                den[q * H + c] = de[q * H + c] + dx[c];
+                dh[(int64_t)src[q] * H + c] += dx[H + c];
+                dh[(int64_t)dst[q] * H + c] += dx[2 * H + c];
+            }
+        }
+        /* node net k */
+        for (int64_t i = 0; i < n; i++) {
+            memcpy(cat, F.h[k] + i * H, sizeof(double) * H);
+            memcpy(cat + H, mo + i * H, sizeof(double) * H);
+            memcpy(cat + 2 * H, mi + i * H, sizeof(double) * H);
+            mlp2_backward(blob, &L.node[k][0], &L.node[k][1], cat, F.hn[k] + i * H, dh + i * H, grad, dx);
+            for (int c = 0; c < H; c++) {
+                dhn[i * H + c] = dh[i * H + c] + dx[c];
+                mo[i * H + c] = dx[H + c];       /* reuse as dm_out */
+                mi[i * H + c] = dx[2 * H + c];   /* reuse as dm_in */
+            }
+        }
+        /* messages: the sums pass their gradient back to every summed edge */
+        for (int64_t q = 0; q < E; q++)
+            for (int c = 0; c < H; c++)
+                den[q * H + c] += mo[(int64_t)src[q] * H + c] + mi[(int64_t)dst[q] * H + c];
+        double *t = de; de = den; den = t;
+        t = dh; dh = dhn; dhn = t;
+    }
+    /* edge encoder */
+    for (int64_t q = 0; q < E; q++) {
+        memcpy(cat, F.h[0] + (int64_t)src[q] * H, sizeof(double) * H);
+        memcpy(cat + H, F.h[0] + (int64_t)dst[q] * H, sizeof(double) * H);
+        mlp2_backward(blob, &L.eenc[0], &L.eenc[1], cat, F.heenc + q * H, de + q * H, grad, dx);
+        for (int c = 0; c < H; c++) {
+            dh[(int64_t)src[q] * H + c] += dx[c];
+            dh[(int64_t)dst[q] * H + c] += dx[H + c];
+        }
+    }
+    /* node encoder */
+    for (int64_t i = 0; i < n; i++)
+        mlp2_backward(blob, &L.nenc[0], &L.nenc[1], F.xhat + i * 3, F.hnenc + i * H, dh + i * H, grad, dx);
+
+    fwd_free(&F, iters);
+    free(logit); free(de); free(dh); free(dhn); free(den); free(cat); free(dx);
+    return 0;
+oom:
+    fwd_free(&F, iters);
+    free(logit); free(de); free(dh); free(dhn); free(den); free(cat); free(dx);
+    return -2;
+}
+
+/* ------------------------------------------------------------------ */
+/* Sec. 5 / Sec. 7.3: connected components of the purified hit graph  */
+/* ------------------------------------------------------------------ */
+
+/*
+ * Exact weakly connected components by breadth-first search over the kept
+ * edges taken as undirected.  Hits are visited as BFS roots in increasing
+ * index order, so each label is the smallest hit index of its component.
+ * Hits without kept edges are their own component.
+ */
+int oracle_components(int64_t n, int64_t E, const int32_t *src, const int32_t *dst,
+                      const uint8_t *keep, int32_t *labels)
+{
+    int64_t *deg = calloc((size_t)n + 1, sizeof(int64_t));
+    int64_t *adj_ptr = calloc((size_t)n + 1, sizeof(int64_t));
+    int32_t *adj = malloc(sizeof(int32_t) * (size_t)(2 * E + 1));
+    int64_t *fill = calloc((size_t)n + 1, sizeof(int64_t));
+    int32_t *queue = malloc(sizeof(int32_t) * (size_t)(n + 1));
+    int rc = 0;
+    if (!deg || !adj_ptr || !adj || !fill || !queue) { rc = -2; goto done; }
+    for (int64_t q = 0; q < E; q++) {
+        if (src[q] < 0 || src[q] >= n || dst[q] < 0 || dst[q] >= n) { rc = -1; goto done; }
+        if (keep[q]) { deg[src[q]]++; deg[dst[q]]++; }
+    }
+    for (int64_t i = 0; i < n; i++)
+        adj_ptr[i + 1] = adj_ptr[i] + deg[i];
+    for (int64_t q = 0; q < E; q++)
+        if (keep[q]) {
+            adj[adj_ptr[src[q]] + fill[src[q]]++] = dst[q];
+            adj[adj_ptr[dst[q]] + fill[dst[q]]++] = src[q];
+        }
+    for (int64_t i = 0; i < n; i++)
+        labels[i] = -1;
+    for (int64_t r = 0; r < n; r++) {
+        if (labels[r] >= 0)
+            continue;
+        int64_t head = 0, tail = 0;
+        labels[r] = (int32_t)r;
+        queue[tail++] = (int32_t)r;
+        while (head < tail) {
+            int32_t u = queue[head++];
+            for (int64_t a = adj_ptr[u]; a < adj_ptr[u + 1]; a++) {
+                int32_t v = adj[a];
+                if (labels[v] < 0) {
+                    labels[v] = (int32_t)r;
+                    queue[tail++] = v;
+                }
+            }
+        }
+    }
+done:
+    free(deg); free(adj_ptr); free(adj); free(fill); free(queue);
+    return rc;
+}
+
+/* ------------------------------------------------------------------ */
+/* whole path over a batch of independent events                       */
+/* ------------------------------------------------------------------ */
+
+/*
+ * Runs features -> embedding -> rough graph -> GNN -> threshold -> components
+ * for every event of a batch (events are independent; OpenMP over events).
+ * The float64 embedding is rounded to float32 before the neighbour decision.
+ * Outputs: labels (event-local), per-event edge lists concatenated in event
+ * order with edge_offsets[B+1] (event-local src/dst), logits in float64, and
+ * the float64 embedding.  edge capacity must be k_max * total hits.
+ */
+int oracle_pipeline(int32_t B, const int32_t *event_offsets,
+                    const float *x, const float *y, const float *z, const int32_t *plane,
+                    const float *blob, int H, int iters, int Ce, int D,
+                    float d2max, int k_max, double logit_min,
+                    double *emb_out, int32_t *labels, int64_t *edge_offsets,
+                    int32_t *esrc, int32_t *edst, double *elogit)
+{
+    int rc = 0;
+    int64_t *cnt = calloc((size_t)B + 1, sizeof(int64_t));
+    if (!cnt)
+        return -2;
+    /* pass 1: embedding and rough graph per event, edges in a per-event slot */
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (int32_t b = 0; b < B; b++) {
+        int64_t s = event_offsets[b], n = event_offsets[b + 1] - s;
+        int64_t slot = s * k_max;
+        float *e32 = malloc(sizeof(float) * (size_t)(n * D + 1));
+        int32_t *rp = malloc(sizeof(int32_t) * (size_t)(n + 1));
+        if (!e32 || !rp) { rc = -2; free(e32); free(rp); continue; }
+        if (oracle_embed(n, x + s, y + s, z + s, blob, Ce, D, emb_out + s * D)) rc = -1;
+        for (int64_t i = 0; i < n * D; i++)
+            e32[i] = (float)emb_out[s * D + i];
+        int64_t E = oracle_neighbours(n, plane + s, e32, D, d2max, k_max, rp, edst + slot, n * k_max);
+        if (E < 0) { rc = -1; E = 0; }
+        for (int64_t i = 0; i < n; i++)
+            for (int64_t a = rp[i]; a < rp[i + 1]; a++)
+                esrc[slot + a] = (int32_t)i;
+        cnt[b + 1] = E;
+        free(e32);
+        free(rp);
+    }
+    if (rc) { free(cnt); return rc; }
+    /* pass 2: GNN, threshold and components per event */
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (int32_t b = 0; b < B; b++) {
+        int64_t s = event_offsets[b], n = event_offsets[b + 1] - s;
+        int64_t slot = s * k_max, E = cnt[b + 1];
+        uint8_t *keep = malloc((size_t)E + 1);
+        if (!keep) { rc = -2; continue; }
+        if (oracle_gnn_forward(n, x + s, y + s, z + s, E, esrc + slot, edst + slot,
+                               blob, H, iters, Ce, D, elogit + slot, NULL, NULL)) rc = -1;
+        for (int64_t q = 0; q < E; q++)
+            keep[q] = elogit[slot + q] >= logit_min;
+        if (oracle_components(n, E, esrc + slot, edst + slot, keep, labels + s)) rc = -1;
+        free(keep);
+    }
+    /* compact the per-event slots into one concatenated list */
+    edge_offsets[0] = 0;
+    for (int32_t b = 0; b < B; b++)
+        edge_offsets[b + 1] = edge_offsets[b] + cnt[b + 1];
+    for (int32_t b = 0; b < B; b++) {
+        int64_t slot = (int64_t)event_offsets[b] * k_max, o = edge_offsets[b];
+        if (o != slot) {
+            memmove(esrc + o, esrc + slot, sizeof(int32_t) * (size_t)cnt[b + 1]);
+            memmove(edst + o, edst + slot, sizeof(int32_t) * (size_t)cnt[b + 1]);
+            memmove(elogit + o, elogit + slot, sizeof(double) * (size_t)cnt[b + 1]);
+        }
+    }
+    free(cnt);
+    return rc;
+}

@@ -1,0 +1,311 @@
+// api.hip -- host side of the C ABI declared in include/velognn.h.
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+
+#include "internal.h"
+
+namespace velo {
+
+bool make_param_layout(int H, int iters, ParamLayout *L) {
+    if (H <= 0 || iters < 0 || iters > 16) return false;
+    int64_t o = 12;
+    auto put = [&o](Lin &l, int out, int in) {
+        l.w = o;
+        l.b = o + (int64_t)out * in;
+        l.out = out;
+        l.in = in;
+        o = l.b + out;
+    };
+    L->H = H;
+    L->iters = iters;
+    put(L->emb[0], VELO_EMB_HIDDEN, 3);
+    put(L->emb[1], VELO_EMB_HIDDEN, VELO_EMB_HIDDEN);
+    put(L->emb[2], VELO_EMB_DIM, VELO_EMB_HIDDEN);
+    put(L->nenc[0], H, 3);
+    put(L->nenc[1], H, H);
+    put(L->eenc[0], H, 2 * H);
+    put(L->eenc[1], H, H);
+    for (int k = 0; k < iters; k++) {
+        put(L->node[k][0], H, 3 * H);
+        put(L->node[k][1], H, H);
+        put(L->edge[k][0], H, 3 * H);
+        put(L->edge[k][1], H, H);
+    }
+    put(L->cls[0], H, H);
+    put(L->cls[1], 1, H);
+    L->total = o;
+    return true;
+}
+
+}  // namespace velo
+
+using namespace velo;
+
+namespace {
+
+velo_status fail(velo_ctx *c, velo_status st, const char *msg) {
+    if (c) c->last_error = msg;
+    return st;
+}
+
+template <typename T>
+bool dalloc(T **p, int64_t count) {
+    if (count < 1) count = 1;
+    return hipMalloc((void **)p, sizeof(T) * (size_t)count) == hipSuccess;
+}
+
+void free_ws(Workspace &w) {
+    void *ptrs[] = {w.emb, w.hit_event, w.plane_off, w.deg, w.row_ptr, w.nbr, w.src_g, w.dst_g,
+                    w.out_ptr, w.out_list, w.in_ptr, w.in_list, w.cnt, w.scan_tmp, w.h[0], w.h[1],
+                    w.m, w.e, w.n_edges, w.flags, w.eoff_tmp};
+    for (void *p : ptrs)
+        if (p) hipFree(p);
+    w = Workspace();
+}
+
+velo_status check_hits(velo_ctx *c, const velo_hits *h) {
+    if (!h) return fail(c, VELO_ERR_INVALID_ARG, "hits is NULL");
+    if (!c->params_set) return fail(c, VELO_ERR_INVALID_ARG, "parameters not set (velo_set_params)");
+    if (h->n_events < 0 || h->n_hits < 0) return fail(c, VELO_ERR_INVALID_ARG, "negative n_events or n_hits");
+    if (h->n_events > c->cfg.max_events) return fail(c, VELO_ERR_CAPACITY, "n_events exceeds max_events");
+    if (h->n_hits > c->cfg.max_hits) return fail(c, VELO_ERR_CAPACITY, "n_hits exceeds max_hits");
+    if (h->n_events == 0 && h->n_hits != 0) return fail(c, VELO_ERR_INVALID_ARG, "hits without events");
+    if (h->n_events > 0 && !h->event_offsets) return fail(c, VELO_ERR_INVALID_ARG, "event_offsets is NULL");
+    if (h->n_hits > 0 && (!h->x || !h->y || !h->z || !h->plane))
+        return fail(c, VELO_ERR_INVALID_ARG, "hit coordinate or plane pointer is NULL");
+    return VELO_OK;
+}
+
+velo_status device_status(velo_ctx *c, const char *where) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        char buf[256];
+        snprintf(buf, sizeof buf, "%s: %s", where, hipGetErrorString(e));
+        c->last_error = buf;
+        return VELO_ERR_DEVICE;
+    }
+    return VELO_OK;
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) == hipSuccess && prev != dev) hipSetDevice(dev);
+        else prev = -1;
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) hipSetDevice(prev);
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+int64_t velo_param_count(int32_t gnn_hidden, int32_t gnn_iters) {
+    ParamLayout L;
+    if (!make_param_layout(gnn_hidden, gnn_iters, &L)) return -1;
+    return L.total;
+}
+
+const char *velo_status_str(velo_status s) {
+    switch (s) {
+        case VELO_OK: return "ok";
+        case VELO_ERR_INVALID_ARG: return "invalid argument";
+        case VELO_ERR_CAPACITY: return "capacity exceeded";
+        case VELO_ERR_OOM: return "device out of memory";
+        case VELO_ERR_DEVICE: return "HIP runtime error";
+        case VELO_ERR_UNSUPPORTED: return "unsupported configuration";
+        case VELO_ERR_INPUT: return "invalid input hits (device validation)";
+    }
+    return "unknown status";
+}
+
+const char *velo_last_error(const velo_ctx *c) { return c ? c->last_error.c_str() : "null context"; }
+
+velo_status velo_create(const velo_config *cfg, velo_ctx **out) {
+    if (!out) return VELO_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (!cfg) return VELO_ERR_INVALID_ARG;
+    const velo_config &k = *cfg;
+    if (k.gnn_hidden != 32 && k.gnn_hidden != 64) return VELO_ERR_UNSUPPORTED;
+    if (k.precision != VELO_FP32) return VELO_ERR_UNSUPPORTED;
+    if (k.gnn_iters < 0 || k.gnn_iters > 16 || k.k_max < 1 || k.k_max > 64 || k.max_hits < 0 ||
+        k.max_edges < 0 || k.max_events < 0 || k.max_event_hits < 0 || !(k.d2_max >= 0.f))
+        return VELO_ERR_INVALID_ARG;
+    if (k.max_edges >= (int64_t)1 << 31 || k.max_hits * (int64_t)k.k_max >= (int64_t)1 << 31)
+        return VELO_ERR_UNSUPPORTED;
+    velo_ctx *c = new (std::nothrow) velo_ctx();
+    if (!c) return VELO_ERR_OOM;
+    c->cfg = k;
+    make_param_layout(k.gnn_hidden, k.gnn_iters, &c->layout);
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return VELO_ERR_DEVICE;
+    }
+    int ncu = 0, lds = 0;
+    hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device);
+    hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device);
+    c->n_cu = ncu > 0 ? ncu : 1;
+    c->lds_max = (size_t)lds;
+    if ((size_t)k.max_event_hits * sizeof(int) > c->lds_max) {
+        delete c;
+        return VELO_ERR_UNSUPPORTED;
+    }
+    const int64_t N = k.max_hits, E = k.max_edges, B = k.max_events, H = k.gnn_hidden;
+    Workspace &w = c->ws;
+    w.scan_tmp_len = (std::max<int64_t>(N, E) + 2047) / 2048 + 1;
+    bool ok = dalloc(&c->params, c->layout.total) && dalloc(&w.emb, N * 4) && dalloc(&w.hit_event, N) &&
+              dalloc(&w.plane_off, B * kPlaneSlots) && dalloc(&w.deg, N) && dalloc(&w.row_ptr, N + 1) &&
+              dalloc(&w.nbr, N * k.k_max) && dalloc(&w.src_g, E) && dalloc(&w.dst_g, E) &&
+              dalloc(&w.out_ptr, N + 1) && dalloc(&w.out_list, E) && dalloc(&w.in_ptr, N + 1) &&
+              dalloc(&w.in_list, E) && dalloc(&w.cnt, N) && dalloc(&w.scan_tmp, w.scan_tmp_len) &&
+              dalloc(&w.h[0], N * H) && dalloc(&w.h[1], N * H) && dalloc(&w.m, N * 2 * H) &&
+              dalloc(&w.e, E * H) && dalloc(&w.n_edges, 1) && dalloc(&w.flags, 1) &&
+              dalloc(&w.eoff_tmp, B + 1);
+    if (!ok) {
+        hipGetLastError();
+        free_ws(w);
+        if (c->params) hipFree(c->params);
+        delete c;
+        return VELO_ERR_OOM;
+    }
+    hipMemset(w.flags, 0, sizeof(unsigned));
+    hipMemset(w.n_edges, 0, sizeof(int));
+    if (hipDeviceSynchronize() != hipSuccess) {
+        free_ws(w);
+        hipFree(c->params);
+        delete c;
+        return VELO_ERR_DEVICE;
+    }
+    *out = c;
+    return VELO_OK;
+}
+
+void velo_destroy(velo_ctx *c) {
+    if (!c) return;
+    DeviceGuard g(c->device);
+    hipDeviceSynchronize();
+    free_ws(c->ws);
+    if (c->params) hipFree(c->params);
+    delete c;
+}
+
+velo_status velo_set_params(velo_ctx *c, const float *params, int64_t n, void *stream) {
+    if (!c) return VELO_ERR_INVALID_ARG;
+    if (!params) return fail(c, VELO_ERR_INVALID_ARG, "params is NULL");
+    if (n != c->layout.total) return fail(c, VELO_ERR_INVALID_ARG, "parameter count does not match the layout");
+    DeviceGuard g(c->device);
+    if (hipMemcpyAsync(c->params, params, sizeof(float) * n, hipMemcpyDeviceToDevice, (hipStream_t)stream) !=
+        hipSuccess)
+        return fail(c, VELO_ERR_DEVICE, "parameter copy failed");
+    c->params_set = true;
+    return VELO_OK;
+}
+
+velo_status velo_embed(velo_ctx *c, const velo_hits *h, float *emb, void *stream) {
+    if (!c) return VELO_ERR_INVALID_ARG;
+    velo_status st = check_hits(c, h);
+    if (st) return st;
+    if (h->n_hits > 0 && !emb) return fail(c, VELO_ERR_INVALID_ARG, "emb is NULL");
+    DeviceGuard g(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    launch_prepare(c, h, s);
+    launch_embed(c, h, emb, s);
+    return device_status(c, "velo_embed");
+}
+
+static velo_status graph_args(velo_ctx *c, const velo_hits *h, const velo_outputs *g) {
+    if (!g) return fail(c, VELO_ERR_INVALID_ARG, "graph/outputs is NULL");
+    if (h->n_events > 0 && !g->edge_offsets) return fail(c, VELO_ERR_INVALID_ARG, "edge_offsets is NULL");
+    if (!g->n_edges) return fail(c, VELO_ERR_INVALID_ARG, "n_edges is NULL");
+    if (g->edge_capacity < 0) return fail(c, VELO_ERR_INVALID_ARG, "negative edge_capacity");
+    if (g->edge_capacity > 0 && (!g->edge_src || !g->edge_dst))
+        return fail(c, VELO_ERR_INVALID_ARG, "edge_src/edge_dst is NULL");
+    return VELO_OK;
+}
+
+velo_status velo_build_graph(velo_ctx *c, const velo_hits *h, const float *emb, velo_outputs *g, void *stream) {
+    if (!c) return VELO_ERR_INVALID_ARG;
+    velo_status st = check_hits(c, h);
+    if (st) return st;
+    if ((st = graph_args(c, h, g))) return st;
+    if (h->n_hits > 0 && !emb) return fail(c, VELO_ERR_INVALID_ARG, "emb is NULL");
+    DeviceGuard gd(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    launch_prepare(c, h, s);
+    launch_knn(c, h, emb, s);
+    launch_compact(c, h, g, s);
+    return device_status(c, "velo_build_graph");
+}
+
+velo_status velo_gnn(velo_ctx *c, const velo_hits *h, velo_outputs *g, void *stream) {
+    if (!c) return VELO_ERR_INVALID_ARG;
+    velo_status st = check_hits(c, h);
+    if (st) return st;
+    if ((st = graph_args(c, h, g))) return st;
+    if (g->edge_capacity > 0 && !g->edge_logit) return fail(c, VELO_ERR_INVALID_ARG, "edge_logit is NULL");
+    DeviceGuard gd(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    launch_prepare(c, h, s);
+    launch_globalise(c, h, g, s);
+    launch_lists(c, h, true, s);
+    launch_gnn(c, h, false, g->edge_logit, s);
+    return device_status(c, "velo_gnn");
+}
+
+velo_status velo_components(velo_ctx *c, const velo_hits *h, velo_outputs *g, void *stream) {
+    if (!c) return VELO_ERR_INVALID_ARG;
+    velo_status st = check_hits(c, h);
+    if (st) return st;
+    if ((st = graph_args(c, h, g))) return st;
+    if (h->n_hits > 0 && !g->labels) return fail(c, VELO_ERR_INVALID_ARG, "labels is NULL");
+    if (g->edge_capacity > 0 && !g->edge_logit) return fail(c, VELO_ERR_INVALID_ARG, "edge_logit is NULL");
+    DeviceGuard gd(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    launch_prepare(c, h, s);
+    launch_globalise(c, h, g, s);
+    launch_components(c, h, g, s);
+    return device_status(c, "velo_components");
+}
+
+velo_status velo_infer(velo_ctx *c, const velo_hits *h, velo_outputs *o, void *stream) {
+    if (!c) return VELO_ERR_INVALID_ARG;
+    velo_status st = check_hits(c, h);
+    if (st) return st;
+    if ((st = graph_args(c, h, o))) return st;
+    if (h->n_hits > 0 && !o->labels) return fail(c, VELO_ERR_INVALID_ARG, "labels is NULL");
+    if (o->edge_capacity > 0 && !o->edge_logit) return fail(c, VELO_ERR_INVALID_ARG, "edge_logit is NULL");
+    DeviceGuard gd(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    launch_prepare(c, h, s);
+    launch_embed(c, h, c->ws.emb, s);
+    launch_knn(c, h, c->ws.emb, s);
+    launch_compact(c, h, o, s);
+    launch_lists(c, h, false, s);
+    launch_gnn(c, h, true, o->edge_logit, s);
+    launch_components(c, h, o, s);
+    return device_status(c, "velo_infer");
+}
+
+velo_status velo_check(velo_ctx *c, void *stream) {
+    if (!c) return VELO_ERR_INVALID_ARG;
+    DeviceGuard gd(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    unsigned f = 0;
+    if (hipMemcpyAsync(&f, c->ws.flags, sizeof f, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return fail(c, VELO_ERR_DEVICE, "velo_check: stream synchronisation failed");
+    if (f) {
+        const unsigned zero = 0;
+        hipMemcpy(c->ws.flags, &zero, sizeof zero, hipMemcpyHostToDevice);
+    }
+    if (f & kErrInput) return fail(c, VELO_ERR_INPUT, "device validation of the hits failed");
+    if (f & kErrCapacity) return fail(c, VELO_ERR_CAPACITY, "edge count exceeds the edge capacity");
+    return VELO_OK;
+}
+
+}  // extern "C"

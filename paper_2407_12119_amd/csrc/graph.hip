@@ -1,0 +1,455 @@
+// graph.hip -- batch validation, plane bucketing and the rough hit graph.
+//
+// Rough graph (paper Sec. 5.1 and Sec. 7.2): a hit on plane p is joined to
+// hits on planes p+1 and p+2 whose squared embedding distance is below
+// d2_max, keeping at most k_max per hit.  Hits are sorted by plane inside each
+// event, so the candidates of a hit on plane p are one contiguous index range.
+//
+// Work mapping: one 64-lane wavefront per query hit.  The lanes sweep the
+// candidate range in chunks of 64, compute the float32 distance keys and keep
+// up to kKeyChunks chunks of keys in registers.  The exact k_max smallest
+// under (d2, index) are found by a bitwise binary search on the float bit
+// pattern of d2 driven by wave ballots (no sorting, no scratch memory), and
+// the survivors are written in index order through ballot prefix counts.
+// This parallelises over the candidates of a hit as well as over hits.
+#include "internal.h"
+
+namespace velo {
+
+namespace {
+
+constexpr int kKeyChunks = 8;             // candidates cached in registers: 8 x 64
+constexpr unsigned kInvalidKey = 0xffffffffu;
+
+__device__ inline unsigned long long ballot(bool p) { return __ballot(p); }
+__device__ inline int lanes_below(unsigned long long mask) {
+    return __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+}
+
+// ------------------------------------------------------------------------
+// validation and plane offsets: one block per event
+// ------------------------------------------------------------------------
+__global__ void k_prepare(int B, int64_t n_hits, const int *__restrict__ off,
+                          const float *__restrict__ x, const float *__restrict__ y,
+                          const float *__restrict__ z, const int *__restrict__ plane,
+                          int max_event_hits, int *__restrict__ plane_off,
+                          int *__restrict__ hit_event, unsigned *__restrict__ flags) {
+    const int b = blockIdx.x;
+    const int s = off[b], e = off[b + 1];
+    bool bad = (b == 0 && s != 0) || (b == B - 1 && (int64_t)e != n_hits) || e < s ||
+               s < 0 || (int64_t)e > n_hits || (e - s) > max_event_hits;
+    int *po = plane_off + (int64_t)b * kPlaneSlots;
+    if (bad) {
+        if (threadIdx.x == 0) atomicOr(flags, kErrInput);
+        for (int q = threadIdx.x; q < kPlaneSlots; q += blockDim.x) po[q] = 0;
+        return;
+    }
+    const int n = e - s;
+    if (n == 0) {
+        for (int q = threadIdx.x; q < kPlaneSlots; q += blockDim.x) po[q] = 0;
+        return;
+    }
+    bool err = false;
+    for (int l = threadIdx.x; l < n; l += blockDim.x) {
+        const int64_t i = (int64_t)s + l;
+        const int p = plane[i];
+        const int pp = l == 0 ? -1 : plane[i - 1];
+        if (p < 0 || p >= VELO_N_PLANES || pp > p || !isfinite(x[i]) || !isfinite(y[i]) ||
+            !isfinite(z[i]))
+            err = true;
+        hit_event[i] = b;
+        const int lo = max(pp + 1, 0), hi = min(p, VELO_N_PLANES);
+        for (int q = lo; q <= hi; q++) po[q] = l;
+        if (l == n - 1)
+            for (int q = max(p + 1, 0); q < kPlaneSlots; q++) po[q] = n;
+    }
+    if (err) atomicOr(flags, kErrInput);
+}
+
+// ------------------------------------------------------------------------
+// neighbour search
+// ------------------------------------------------------------------------
+
+// Float32 squared distance with the evaluation order fixed by the ABI:
+// s = d0*d0, then s = fma(d_c, d_c, s).
+__device__ inline float dist2(f32x4 a, f32x4 b) {
+    float d = a[0] - b[0];
+    float s = d * d;
+    d = a[1] - b[1];
+    s = __builtin_fmaf(d, d, s);
+    d = a[2] - b[2];
+    s = __builtin_fmaf(d, d, s);
+    d = a[3] - b[3];
+    s = __builtin_fmaf(d, d, s);
+    return s;
+}
+
+__device__ inline unsigned cand_key(const f32x4 *__restrict__ emb, int64_t base, int C, int c,
+                                    f32x4 q, float d2max) {
+    if (c >= C) return kInvalidKey;
+    const float s = dist2(q, emb[base + c]);
+    return s < d2max ? __float_as_uint(s) : kInvalidKey;
+}
+
+__global__ __launch_bounds__(256) void k_knn(int64_t n_hits, const int *__restrict__ off,
+                                             const int *__restrict__ plane_off,
+                                             const int *__restrict__ hit_event,
+                                             const int *__restrict__ plane,
+                                             const f32x4 *__restrict__ emb, float d2max, int kmax,
+                                             int *__restrict__ nbr, int *__restrict__ deg,
+                                             const unsigned *__restrict__ flags) {
+    if (*flags & kErrInput) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; i < n_hits; i += nwaves) {
+        const int b = hit_event[i];
+        const int64_t s = off[b];
+        const int p = plane[i];
+        const int *po = plane_off + (int64_t)b * kPlaneSlots;
+        const int c0 = po[min(p + 1, VELO_N_PLANES)];
+        const int c1 = po[min(p + 3, VELO_N_PLANES)];
+        const int C = max(c1 - c0, 0);
+        const int64_t base = s + c0;          // batch index of candidate 0
+        const f32x4 q = emb[i];
+        const int nch = (C + 63) >> 6;
+        int *out = nbr + i * kmax;
+
+        unsigned key[kKeyChunks];
+        int m = 0;
+#pragma unroll
+        for (int c = 0; c < kKeyChunks; c++) {
+            key[c] = kInvalidKey;
+            if (c < nch) {
+                key[c] = cand_key(emb, base, C, c * 64 + lane, q, d2max);
+                m += __popcll(ballot(key[c] != kInvalidKey));
+            }
+        }
+        for (int c = kKeyChunks; c < nch; c++)
+            m += __popcll(ballot(cand_key(emb, base, C, c * 64 + lane, q, d2max) != kInvalidKey));
+
+        // threshold T: the kmax-th smallest key (only needed when m > kmax)
+        unsigned T = 0x7fffffffu;
+        int need_ties = 0;
+        if (m > kmax) {
+            T = 0;
+            for (int bit = 30; bit >= 0; bit--) {
+                const unsigned cand = T | (1u << bit);
+                int cnt = 0;
+#pragma unroll
+                for (int c = 0; c < kKeyChunks; c++)
+                    if (c < nch) cnt += __popcll(ballot(key[c] < cand));
+                for (int c = kKeyChunks; c < nch; c++)
+                    cnt += __popcll(ballot(cand_key(emb, base, C, c * 64 + lane, q, d2max) < cand));
+                if (cnt < kmax) T = cand;
+            }
+            int less = 0;
+#pragma unroll
+            for (int c = 0; c < kKeyChunks; c++)
+                if (c < nch) less += __popcll(ballot(key[c] < T));
+            for (int c = kKeyChunks; c < nch; c++)
+                less += __popcll(ballot(cand_key(emb, base, C, c * 64 + lane, q, d2max) < T));
+            need_ties = kmax - less;
+        }
+        // emit survivors in candidate (= destination index) order
+        int written = 0, ties_seen = 0;
+        auto emit = [&](unsigned k, int c) {
+            bool sel;
+            if (m > kmax) {
+                const unsigned long long tie = ballot(k == T);
+                const bool first_ties = ties_seen + lanes_below(tie) < need_ties;
+                sel = k < T || (k == T && first_ties);
+                ties_seen += __popcll(tie);
+            } else {
+                sel = k != kInvalidKey;
+            }
+            const unsigned long long sm = ballot(sel);
+            if (sel) out[written + lanes_below(sm)] = c0 + c * 64 + lane;
+            written += __popcll(sm);
+        };
+#pragma unroll
+        for (int c = 0; c < kKeyChunks; c++)
+            if (c < nch) emit(key[c], c);
+        for (int c = kKeyChunks; c < nch; c++) emit(cand_key(emb, base, C, c * 64 + lane, q, d2max), c);
+        if (lane == 0) deg[i] = written;
+    }
+}
+
+// ------------------------------------------------------------------------
+// exclusive scan of int32 counts: out[0..n] with out[n] = total
+// ------------------------------------------------------------------------
+constexpr int kScanBlock = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanBlock * kScanItems;
+
+__device__ inline int block_exclusive_scan(int v, int *sh, int *total) {
+    // sh: kScanBlock ints
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int d = 1; d < kScanBlock; d <<= 1) {
+        int add = t >= d ? sh[t - d] : 0;
+        __syncthreads();
+        sh[t] += add;
+        __syncthreads();
+    }
+    const int incl = sh[t];
+    *total = sh[kScanBlock - 1];
+    __syncthreads();
+    return incl - v;
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_reduce(const int *__restrict__ in, int64_t n,
+                                                            int *__restrict__ sums) {
+    __shared__ int sh[kScanBlock];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    int v = 0;
+    for (int j = 0; j < kScanItems; j++) {
+        const int64_t i = base + (int64_t)j * kScanBlock + threadIdx.x;
+        if (i < n) v += in[i];
+    }
+    int total;
+    block_exclusive_scan(v, sh, &total);
+    if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_sums(int *__restrict__ sums, int nb,
+                                                          int *__restrict__ out_total) {
+    __shared__ int sh[kScanBlock];
+    int carry = 0;
+    for (int base = 0; base < nb; base += kScanBlock) {
+        const int i = base + threadIdx.x;
+        const int v = i < nb ? sums[i] : 0;
+        int total;
+        const int ex = block_exclusive_scan(v, sh, &total);
+        if (i < nb) sums[i] = carry + ex;
+        carry += total;
+    }
+    if (threadIdx.x == 0) *out_total = carry;
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_apply(const int *__restrict__ in, int64_t n,
+                                                           const int *__restrict__ sums,
+                                                           int *__restrict__ out) {
+    __shared__ int sh[kScanBlock];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int v[kScanItems];
+    int local = 0;
+    for (int j = 0; j < kScanItems; j++) {
+        const int64_t i = base + j;
+        v[j] = i < n ? in[i] : 0;
+        local += v[j];
+    }
+    int total;
+    int run = block_exclusive_scan(local, sh, &total) + sums[blockIdx.x];
+    for (int j = 0; j < kScanItems; j++) {
+        const int64_t i = base + j;
+        if (i < n) out[i] = run;
+        run += v[j];
+    }
+}
+
+__global__ void k_fill(int *__restrict__ p, int v, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// ------------------------------------------------------------------------
+// CSR compaction of the staged neighbour lists
+// ------------------------------------------------------------------------
+__global__ void k_compact(int64_t n_hits, int kmax, const int *__restrict__ off,
+                          const int *__restrict__ hit_event, const int *__restrict__ deg,
+                          const int *__restrict__ row_ptr, const int *__restrict__ nbr,
+                          int64_t cap, int *__restrict__ esrc, int *__restrict__ edst,
+                          int *__restrict__ src_g, int *__restrict__ dst_g,
+                          const unsigned *__restrict__ flags) {
+    if (*flags & kErrInput) return;
+    const int64_t slots = n_hits * kmax;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < slots;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = t / kmax;
+        const int a = (int)(t - i * kmax);
+        if (a >= deg[i]) continue;
+        const int64_t e = (int64_t)row_ptr[i] + a;
+        if (e >= cap) continue;
+        const int s = off[hit_event[i]];
+        const int j = nbr[t];
+        if (esrc) esrc[e] = (int)(i - s);
+        if (edst) edst[e] = j;
+        src_g[e] = (int)i;
+        dst_g[e] = s + j;
+    }
+}
+
+__global__ void k_edge_offsets(int B, const int *__restrict__ off, const int *__restrict__ row_ptr,
+                               int *__restrict__ eoff, const unsigned *__restrict__ flags) {
+    if (*flags & kErrInput) return;
+    for (int b = blockIdx.x * blockDim.x + threadIdx.x; b <= B; b += gridDim.x * blockDim.x)
+        eoff[b] = row_ptr[off[b]];
+}
+
+// n_internal = min(total, cap) is what every later kernel iterates over;
+// n_out (the caller's count, may be null) receives the full total.
+__global__ void k_check_capacity(const int *__restrict__ total, int64_t cap, int *__restrict__ n_internal,
+                                 int *__restrict__ n_out, unsigned *__restrict__ flags) {
+    const int t = *total;
+    const bool over = t < 0 || (int64_t)t > cap;
+    if (n_out) *n_out = t;
+    *n_internal = over ? (t < 0 ? 0 : (int)cap) : t;
+    if (over) atomicOr(flags, t < 0 ? kErrInput : kErrCapacity);
+}
+
+// Caller-supplied edges (event-local) -> batch-global hit indices; one block per event.
+__global__ void k_globalise(int B, const int *__restrict__ off, const int *__restrict__ eoff,
+                            const int *__restrict__ n_edges, int64_t cap, const int *__restrict__ esrc,
+                            const int *__restrict__ edst, int *__restrict__ src_g,
+                            int *__restrict__ dst_g, unsigned *__restrict__ flags) {
+    if (*flags) return;
+    const int E = min((int64_t)*n_edges, cap);
+    if (B == 0) {           // no events: there can be no edges
+        if (E != 0 && threadIdx.x == 0) atomicOr(flags, kErrInput);
+        return;
+    }
+    const int b = blockIdx.x;
+    const int s = off[b], n = off[b + 1] - s;
+    const int e0 = eoff[b], e1 = eoff[b + 1];
+    if ((b == 0 && e0 != 0) || (b == B - 1 && e1 != E) || e1 < e0 || e1 > E) {
+        if (threadIdx.x == 0) atomicOr(flags, kErrInput);
+        return;
+    }
+    bool err = false;
+    for (int q = e0 + threadIdx.x; q < e1; q += blockDim.x) {
+        const int a = esrc[q], c = edst[q];
+        if (a < 0 || a >= n || c < 0 || c >= n) {
+            err = true;
+            src_g[q] = s;
+            dst_g[q] = s;
+            continue;
+        }
+        src_g[q] = s + a;
+        dst_g[q] = s + c;
+    }
+    if (err) atomicOr(flags, kErrInput);
+}
+
+// ------------------------------------------------------------------------
+// incidence lists (edges grouped by hit), deterministic: counting sort, then
+// each list sorted by edge id so sums over it have a fixed order
+// ------------------------------------------------------------------------
+__global__ void k_count(const int *__restrict__ n_edges, int64_t cap, const int *__restrict__ key,
+                        int *__restrict__ cnt, const unsigned *__restrict__ flags) {
+    if (*flags) return;
+    const int64_t E = min((int64_t)*n_edges, cap);
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < E; e += (int64_t)gridDim.x * blockDim.x)
+        atomicAdd(&cnt[key[e]], 1);
+}
+
+__global__ void k_scatter(const int *__restrict__ n_edges, int64_t cap, const int *__restrict__ key,
+                          const int *__restrict__ ptr, int *__restrict__ cur, int *__restrict__ list,
+                          const unsigned *__restrict__ flags) {
+    if (*flags) return;
+    const int64_t E = min((int64_t)*n_edges, cap);
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < E; e += (int64_t)gridDim.x * blockDim.x) {
+        const int k = key[e];
+        const int slot = atomicAdd(&cur[k], 1);
+        list[ptr[k] + slot] = (int)e;
+    }
+}
+
+__global__ void k_sort_lists(int64_t n_hits, const int *__restrict__ ptr, int *__restrict__ list,
+                             const unsigned *__restrict__ flags) {
+    if (*flags) return;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_hits; i += (int64_t)gridDim.x * blockDim.x) {
+        const int a = ptr[i], b = ptr[i + 1];
+        for (int u = a + 1; u < b; u++) {
+            const int v = list[u];
+            int w = u - 1;
+            while (w >= a && list[w] > v) {
+                list[w + 1] = list[w];
+                w--;
+            }
+            list[w + 1] = v;
+        }
+    }
+}
+
+inline int grid_for(int64_t n, int block, int cap_blocks = 65536) {
+    int64_t g = (n + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > cap_blocks) g = cap_blocks;
+    return (int)g;
+}
+
+}  // namespace
+
+void launch_fill(int *p, int v, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    k_fill<<<grid_for(n, 256, 4096), 256, 0, s>>>(p, v, n);
+}
+
+void launch_prepare(velo_ctx *c, const velo_hits *h, hipStream_t s) {
+    if (h->n_events <= 0) return;
+    k_prepare<<<h->n_events, 256, 0, s>>>(h->n_events, h->n_hits, h->event_offsets, h->x, h->y, h->z,
+                                          h->plane, c->cfg.max_event_hits, c->ws.plane_off,
+                                          c->ws.hit_event, c->ws.flags);
+}
+
+void launch_scan(velo_ctx *c, const int *in, int *out, int64_t n, hipStream_t s) {
+    const int nb = (int)((n + kScanTile - 1) / kScanTile);
+    if (nb > 0) k_scan_reduce<<<nb, kScanBlock, 0, s>>>(in, n, c->ws.scan_tmp);
+    k_scan_sums<<<1, kScanBlock, 0, s>>>(c->ws.scan_tmp, nb, out + n);
+    if (nb > 0) k_scan_apply<<<nb, kScanBlock, 0, s>>>(in, n, c->ws.scan_tmp, out);
+}
+
+void launch_knn(velo_ctx *c, const velo_hits *h, const float *emb, hipStream_t s) {
+    if (h->n_hits <= 0) return;
+    const int blocks = grid_for(h->n_hits * 64, 256, persistent_grid(c, 16));
+    k_knn<<<blocks, 256, 0, s>>>(h->n_hits, h->event_offsets, c->ws.plane_off, c->ws.hit_event,
+                                 h->plane, (const f32x4 *)emb, c->cfg.d2_max, c->cfg.k_max,
+                                 c->ws.nbr, c->ws.deg, c->ws.flags);
+}
+
+void launch_compact(velo_ctx *c, const velo_hits *h, velo_outputs *g, hipStream_t s) {
+    Workspace &w = c->ws;
+    const int64_t N = h->n_hits;
+    // row_ptr = exclusive scan of the per-hit degrees; row_ptr[N] = edge total
+    launch_scan(c, w.deg, w.row_ptr, N, s);
+    const int64_t cap = g->edge_capacity < c->cfg.max_edges ? g->edge_capacity : c->cfg.max_edges;
+    k_check_capacity<<<1, 1, 0, s>>>(w.row_ptr + N, cap, w.n_edges, g->n_edges, w.flags);
+    if (N > 0) {
+        const int64_t slots = N * c->cfg.k_max;
+        k_compact<<<grid_for(slots, 256, persistent_grid(c, 32)), 256, 0, s>>>(
+            N, c->cfg.k_max, h->event_offsets, w.hit_event, w.deg, w.row_ptr, w.nbr, cap,
+            g->edge_src, g->edge_dst, w.src_g, w.dst_g, w.flags);
+    }
+    int *eoff = g->edge_offsets ? g->edge_offsets : w.eoff_tmp;
+    k_edge_offsets<<<grid_for(h->n_events + 1, 256), 256, 0, s>>>(h->n_events, h->event_offsets,
+                                                                  w.row_ptr, eoff, w.flags);
+}
+
+void launch_globalise(velo_ctx *c, const velo_hits *h, const velo_outputs *g, hipStream_t s) {
+    Workspace &w = c->ws;
+    const int64_t cap = g->edge_capacity < c->cfg.max_edges ? g->edge_capacity : c->cfg.max_edges;
+    k_check_capacity<<<1, 1, 0, s>>>(g->n_edges, cap, w.n_edges, nullptr, w.flags);
+    k_globalise<<<h->n_events > 0 ? h->n_events : 1, 256, 0, s>>>(h->n_events, h->event_offsets, g->edge_offsets,
+                                                w.n_edges, cap, g->edge_src, g->edge_dst, w.src_g,
+                                                w.dst_g, w.flags);
+}
+
+void launch_lists(velo_ctx *c, const velo_hits *h, bool need_out_lists, hipStream_t s) {
+    Workspace &w = c->ws;
+    const int64_t N = h->n_hits, cap = c->cfg.max_edges;
+    const int eb = persistent_grid(c, 8);
+    for (int dir = need_out_lists ? 0 : 1; dir < 2; dir++) {
+        const int *key = dir == 0 ? w.src_g : w.dst_g;
+        int *ptr = dir == 0 ? w.out_ptr : w.in_ptr;
+        int *list = dir == 0 ? w.out_list : w.in_list;
+        launch_fill(w.cnt, 0, N, s);
+        k_count<<<eb, 256, 0, s>>>(w.n_edges, cap, key, w.cnt, w.flags);
+        launch_scan(c, w.cnt, ptr, N, s);
+        launch_fill(w.cnt, 0, N, s);
+        k_scatter<<<eb, 256, 0, s>>>(w.n_edges, cap, key, ptr, w.cnt, list, w.flags);
+        if (N > 0) k_sort_lists<<<grid_for(N, 256, persistent_grid(c, 8)), 256, 0, s>>>(N, ptr, list, w.flags);
+    }
+}
+
+}  // namespace velo

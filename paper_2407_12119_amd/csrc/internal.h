@@ -1,0 +1,92 @@
+// internal.h -- shared declarations of the HIP implementation (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "velognn.h"
+
+namespace velo {
+
+// Error bits latched on the device.
+constexpr unsigned kErrInput = 1u;     // invalid hits (offsets, planes, order, non-finite)
+constexpr unsigned kErrCapacity = 2u;  // more edges than the edge arrays hold
+
+constexpr int kPlaneSlots = VELO_N_PLANES + 1;   // plane_off entries per event
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// Offsets (in floats) of every tensor of the parameter blob.
+struct Lin { int64_t w, b; int out, in; };
+struct ParamLayout {
+    int H = 0, iters = 0;
+    Lin emb[3];
+    Lin nenc[2], eenc[2];
+    Lin node[16][2], edge[16][2];
+    Lin cls[2];
+    int64_t total = 0;
+};
+bool make_param_layout(int H, int iters, ParamLayout *L);
+
+struct Workspace {
+    float *emb = nullptr;        // [max_hits x 4]
+    int *hit_event = nullptr;    // [max_hits]
+    int *plane_off = nullptr;    // [max_events x 27]
+    int *deg = nullptr;          // [max_hits]
+    int *row_ptr = nullptr;      // [max_hits + 1]
+    int *nbr = nullptr;          // [max_hits x k_max] staging of selected neighbours
+    int *src_g = nullptr;        // [max_edges] batch-global source hit
+    int *dst_g = nullptr;        // [max_edges] batch-global destination hit
+    int *out_ptr = nullptr;      // [max_hits + 1]
+    int *out_list = nullptr;     // [max_edges]
+    int *in_ptr = nullptr;       // [max_hits + 1]
+    int *in_list = nullptr;      // [max_edges]
+    int *cnt = nullptr;          // [max_hits] counters for list building
+    int *scan_tmp = nullptr;     // block sums of the scans
+    int64_t scan_tmp_len = 0;
+    float *h[2] = {nullptr, nullptr};   // [max_hits x H] hit encodings (ping-pong)
+    float *m = nullptr;          // [max_hits x 2H] messages, float32
+    float *e = nullptr;          // [max_edges x H] edge encodings (updated in place)
+    int *n_edges = nullptr;      // [1] internal edge count
+    unsigned *flags = nullptr;   // [1] latched device errors
+    int *eoff_tmp = nullptr;     // [max_events + 1]
+};
+
+}  // namespace velo
+
+struct velo_ctx {
+    velo_config cfg;
+    int device = 0;
+    int n_cu = 0;
+    size_t lds_max = 0;
+    velo::ParamLayout layout;
+    float *params = nullptr;     // float32 copy of the blob
+    bool params_set = false;
+    velo::Workspace ws;
+    std::string last_error;
+};
+
+namespace velo {
+
+// ---- launchers (graph.hip) ----
+void launch_prepare(velo_ctx *c, const velo_hits *h, hipStream_t s);
+void launch_knn(velo_ctx *c, const velo_hits *h, const float *emb, hipStream_t s);
+void launch_scan(velo_ctx *c, const int *in, int *out, int64_t n, hipStream_t s);
+void launch_compact(velo_ctx *c, const velo_hits *h, velo_outputs *g, hipStream_t s);
+void launch_globalise(velo_ctx *c, const velo_hits *h, const velo_outputs *g, hipStream_t s);
+void launch_lists(velo_ctx *c, const velo_hits *h, bool need_out_lists, hipStream_t s);
+void launch_fill(int *p, int v, int64_t n, hipStream_t s);
+
+// ---- launchers (gnn.hip) ----
+void launch_embed(velo_ctx *c, const velo_hits *h, float *emb, hipStream_t s);
+void launch_gnn(velo_ctx *c, const velo_hits *h, bool out_identity, float *logit, hipStream_t s);
+
+// ---- launchers (wcc.hip) ----
+void launch_components(velo_ctx *c, const velo_hits *h, const velo_outputs *g, hipStream_t s);
+
+// Grid size for persistent kernels: `per_cu` blocks on every compute unit.
+inline int persistent_grid(const velo_ctx *c, int per_cu) { return c->n_cu * per_cu; }
+
+}  // namespace velo

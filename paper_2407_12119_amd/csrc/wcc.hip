@@ -1,0 +1,93 @@
+// wcc.hip -- connected components of the purified hit graph (paper Sec. 5
+// overview and Sec. 7.3): edges with logit >= edge_logit_min, taken as
+// undirected, define the components; each hit's label is the smallest
+// event-local hit index of its component.
+//
+// One workgroup per event keeps the event's parent array in LDS.  Kept edges
+// are hooked concurrently with a lock-free union-find: the larger of the two
+// roots is linked under the smaller with an LDS compare-and-swap, retried
+// until the two hits share a root.  Every parent pointer only ever points to
+// a smaller index, so each root is its component's minimum and the labels do
+// not depend on the order in which edges are processed.  (The paper's plane
+// sweep is replaced because it is not exact on every graph.)
+#include "internal.h"
+
+namespace velo {
+
+namespace {
+
+__device__ inline int find_root(volatile int *par, int x) {
+    int p = par[x];
+    while (p != x) {
+        const int gp = par[p];
+        if (gp != p) par[x] = gp;   // path halving; gp is an ancestor of x
+        x = p;
+        p = gp;
+    }
+    return x;
+}
+
+__device__ inline void unite(int *par, int u, int v) {
+    volatile int *vp = par;
+    while (true) {
+        u = find_root(vp, u);
+        v = find_root(vp, v);
+        if (u == v) return;
+        if (u > v) {
+            const int t = u; u = v; v = t;
+        }
+        // link root v under the smaller root u
+        const int old = atomicCAS(&par[v], v, u);
+        if (old == v) return;
+        v = old;
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_wcc(int B, const int *__restrict__ off, const int *__restrict__ eoff,
+                                              const int *__restrict__ n_edges, int64_t cap,
+                                              const int *__restrict__ esrc, const int *__restrict__ edst,
+                                              const float *__restrict__ logit, float thr,
+                                              int *__restrict__ labels, int max_ev,
+                                              unsigned *__restrict__ flags) {
+    extern __shared__ int par[];
+    if (*flags) return;
+    const int b = blockIdx.x;
+    const int s = off[b], n = off[b + 1] - s;
+    if (n > max_ev) return;     // rejected by validation
+    const int E = min((int64_t)*n_edges, cap);
+    const int e0 = min(eoff[b], E), e1 = min(eoff[b + 1], E);
+    for (int l = threadIdx.x; l < n; l += blockDim.x) par[l] = l;
+    __syncthreads();
+    bool err = false;
+    for (int q = e0 + threadIdx.x; q < e1; q += blockDim.x) {
+        if (!(logit[q] >= thr)) continue;
+        const int u = esrc[q], v = edst[q];
+        if (u < 0 || u >= n || v < 0 || v >= n) {
+            err = true;
+            continue;
+        }
+        unite(par, u, v);
+    }
+    if (err) atomicOr(flags, kErrInput);
+    __syncthreads();
+    for (int l = threadIdx.x; l < n; l += blockDim.x) labels[s + l] = find_root(par, l);
+}
+
+}  // namespace
+
+void launch_components(velo_ctx *c, const velo_hits *h, const velo_outputs *g, hipStream_t s) {
+    if (h->n_events <= 0) return;
+    const int64_t cap = g->edge_capacity < c->cfg.max_edges ? g->edge_capacity : c->cfg.max_edges;
+    const size_t lds = sizeof(int) * (size_t)(c->cfg.max_event_hits > 0 ? c->cfg.max_event_hits : 1);
+    static bool attr = false;
+    if (!attr) {
+        hipFuncSetAttribute(reinterpret_cast<const void *>(&k_wcc), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)c->lds_max);
+        attr = true;
+    }
+    k_wcc<<<h->n_events, 1024, lds, s>>>(h->n_events, h->event_offsets, g->edge_offsets, c->ws.n_edges, cap,
+                                         g->edge_src, g->edge_dst, g->edge_logit, c->cfg.edge_logit_min,
+                                         g->labels, c->cfg.max_event_hits, c->ws.flags);
+}
+
+}  // namespace velo

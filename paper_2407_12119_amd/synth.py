@@ -1,0 +1,327 @@
+"""Seeded synthetic VELO-like events and seeded model parameters.
+
+This module is the one input generator shared by the HIP path, the oracle,
+the tests and the benchmark.  It holds none of the track-finding arithmetic:
+it draws hits, truth and parameters, and nothing else.
+
+The paper measures on LHCb minimum-bias simulation (Sec. 4, Datasets), which is
+not available here; these events stand in for it.  Shapes follow the paper's
+detector description: 26 VELO planes (Sec. 2), straight tracks because the VELO
+has no magnetic field (Sec. 3), an interaction region about 45 mm long in z
+(Sec. 5.1), pseudorapidity 2..5 (Sec. 2) and a few proton-proton vertices per
+event (Sec. 2, pileup about five).
+
+Geometry and draws (fixed so that every event is reproducible on its own):
+  * planes at z_p = -290 + 41.6 p mm, p = 0..25; a hit is accepted when the
+    true (unsmeared) radius satisfies 5.1 mm < r < 42 mm;
+  * vertex x, y ~ N(0, 0.01 mm), z ~ N(0, 45 mm);
+  * track eta ~ U(2, 5), phi ~ U(0, 2 pi), theta = 2 atan(exp(-eta)), forward
+    (+z) only, one crossing per plane downstream of the vertex;
+  * each accepted crossing is kept with probability 0.98 and smeared in x, y by
+    N(0, 0.01 mm); z is the plane position;
+  * noise: round(f * n_signal) hits on planes U{0..25}, uniform over the
+    annulus area, pid = -1;
+  * order: a seeded permutation, then a stable sort by plane, so the index of a
+    hit within its plane does not leak truth.
+
+Draw order inside one event: vertex count, track counts, vertex coordinates,
+track eta, track phi, keep uniforms, smear normals, noise plane, noise r^2,
+noise phi, permutation.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+SEED_ROOT = 24071211
+N_PLANES = 26
+Z0, DZ = -290.0, 41.6
+R_MIN, R_MAX = 5.1, 42.0
+HIT_EFF = 0.98
+SMEAR = 0.01
+VTX_XY, VTX_Z = 0.01, 45.0
+
+PLANE_Z = np.array([Z0 + DZ * p for p in range(N_PLANES)], dtype=np.float64)
+
+
+@dataclasses.dataclass(frozen=True)
+class EventRecipe:
+    """How many vertices/tracks an event has and how much noise it carries."""
+    fixed_tracks: Optional[int]     # a single vertex with this many tracks, or None
+    mu_vertices: float              # Poisson mean of vertices (if not fixed)
+    mu_tracks: float                # Poisson mean of tracks per vertex
+    noise_frac: float
+
+
+@dataclasses.dataclass(frozen=True)
+class Workload:
+    """One benchmark/parity workload: event recipe, batch size and network shape."""
+    name: str
+    index: int                      # seed stream of the events
+    n_events: int
+    recipe: EventRecipe
+    hidden: int                     # GNN hidden width H (node and edge encodings)
+    iters: int                      # message-passing iterations n
+    emb_hidden: int = 128
+    emb_dim: int = 4
+    radius: float = 0.1             # embedding-space radius; edge iff d^2 < fl32(radius^2)
+    k_max: int = 32
+    edge_logit_min: float = 0.0     # score threshold 0.5 expressed as a logit
+
+
+_PILEUP = EventRecipe(None, 5.0, 30.0, 0.05)
+
+WORKLOADS = {
+    "single_event": Workload("single_event", 0, 1, EventRecipe(50, 1.0, 50.0, 0.05), 64, 4),
+    "batch256": Workload("batch256", 1, 256, _PILEUP, 64, 4),
+    "batch256_lowp": Workload("batch256_lowp", 1, 256, _PILEUP, 64, 4),
+    "train32": Workload("train32", 3, 32, _PILEUP, 64, 6),
+    "batch1000_h128": Workload("batch1000_h128", 4, 1000, EventRecipe(None, 12.0, 30.0, 0.10), 128, 8),
+}
+
+
+@dataclasses.dataclass
+class Event:
+    x: np.ndarray        # f32 [N]
+    y: np.ndarray        # f32 [N]
+    z: np.ndarray        # f32 [N]
+    plane: np.ndarray    # i32 [N], non-decreasing
+    pid: np.ndarray      # i64 [N], -1 for noise
+    next_hit: np.ndarray # i32 [N], event-local index of the particle's next hit in z, or -1
+
+    @property
+    def n(self) -> int:
+        return int(self.x.shape[0])
+
+
+@dataclasses.dataclass
+class Batch:
+    x: np.ndarray
+    y: np.ndarray
+    z: np.ndarray
+    plane: np.ndarray
+    pid: np.ndarray
+    next_hit: np.ndarray         # event-local
+    event_offsets: np.ndarray    # i32 [B+1]
+
+    @property
+    def n_events(self) -> int:
+        return int(self.event_offsets.shape[0] - 1)
+
+    @property
+    def n_hits(self) -> int:
+        return int(self.event_offsets[-1])
+
+    def event(self, b: int) -> Event:
+        s, e = int(self.event_offsets[b]), int(self.event_offsets[b + 1])
+        return Event(self.x[s:e], self.y[s:e], self.z[s:e], self.plane[s:e],
+                     self.pid[s:e], self.next_hit[s:e])
+
+    def max_event_hits(self) -> int:
+        if self.n_events == 0:
+            return 0
+        return int(np.max(np.diff(self.event_offsets)))
+
+
+def _rng(*words: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(np.random.SeedSequence([SEED_ROOT, *words])))
+
+
+def make_event(recipe: EventRecipe, rng: np.random.Generator) -> Event:
+    """Draw one event (see the module docstring for the recipe and draw order)."""
+    if recipe.fixed_tracks is not None:
+        n_vtx = 1
+        n_trk = np.array([recipe.fixed_tracks], dtype=np.int64)
+    else:
+        n_vtx = int(rng.poisson(recipe.mu_vertices))
+        n_trk = rng.poisson(recipe.mu_tracks, size=n_vtx).astype(np.int64)
+    vtx = np.empty((n_vtx, 3))
+    if n_vtx:
+        vtx[:, 0:2] = rng.normal(0.0, VTX_XY, size=(n_vtx, 2))
+        vtx[:, 2] = rng.normal(0.0, VTX_Z, size=n_vtx)
+    t_vtx = np.repeat(np.arange(n_vtx), n_trk)
+    n_tracks = int(t_vtx.shape[0])
+    eta = rng.uniform(2.0, 5.0, size=n_tracks)
+    phi = rng.uniform(0.0, 2.0 * math.pi, size=n_tracks)
+    keep_u = rng.random(size=(n_tracks, N_PLANES))
+    smear = rng.normal(0.0, SMEAR, size=(n_tracks, N_PLANES, 2))
+
+    theta = 2.0 * np.arctan(np.exp(-eta))
+    tan_t = np.tan(theta)
+    v = vtx[t_vtx] if n_tracks else np.zeros((0, 3))
+    dz = PLANE_Z[None, :] - v[:, 2:3]                       # [T, P]
+    xt = v[:, 0:1] + dz * (tan_t * np.cos(phi))[:, None]
+    yt = v[:, 1:2] + dz * (tan_t * np.sin(phi))[:, None]
+    rt = np.hypot(xt, yt)
+    ok = (dz > 0.0) & (rt > R_MIN) & (rt < R_MAX) & (keep_u < HIT_EFF)
+    ti, pi = np.nonzero(ok)                                  # track-major, plane-ascending
+    sx = xt[ti, pi] + smear[ti, pi, 0]
+    sy = yt[ti, pi] + smear[ti, pi, 1]
+    sz = PLANE_Z[pi]
+    n_sig = int(ti.shape[0])
+
+    n_noise = int(math.floor(recipe.noise_frac * n_sig + 0.5))
+    nplane = rng.integers(0, N_PLANES, size=n_noise)
+    nr = np.sqrt(rng.uniform(R_MIN * R_MIN, R_MAX * R_MAX, size=n_noise))
+    nphi = rng.uniform(0.0, 2.0 * math.pi, size=n_noise)
+
+    x = np.concatenate([sx, nr * np.cos(nphi)])
+    y = np.concatenate([sy, nr * np.sin(nphi)])
+    z = np.concatenate([sz, PLANE_Z[nplane]])
+    plane = np.concatenate([pi, nplane]).astype(np.int32)
+    pid = np.concatenate([ti.astype(np.int64), np.full(n_noise, -1, np.int64)])
+    # next hit of the same particle in z order, in pre-permutation indices
+    nxt = np.full(n_sig + n_noise, -1, np.int64)
+    if n_sig > 1:
+        same = ti[1:] == ti[:-1]
+        idx = np.nonzero(same)[0]
+        nxt[idx] = idx + 1
+
+    n = n_sig + n_noise
+    perm = rng.permutation(n)
+    order = perm[np.argsort(plane[perm], kind="stable")]
+    inv = np.empty(n, np.int64)
+    inv[order] = np.arange(n)
+    nxt_o = nxt[order]
+    nxt_o = np.where(nxt_o >= 0, inv[np.maximum(nxt_o, 0)], -1)
+    return Event(x[order].astype(np.float32), y[order].astype(np.float32),
+                 z[order].astype(np.float32), plane[order], pid[order],
+                 nxt_o.astype(np.int32))
+
+
+def event_rng(workload_index: int, e: int) -> np.random.Generator:
+    return _rng(workload_index, e)
+
+
+def make_events(wl: Workload, n_events: Optional[int] = None, first: int = 0) -> List[Event]:
+    n_events = wl.n_events if n_events is None else n_events
+    return [make_event(wl.recipe, event_rng(wl.index, first + e)) for e in range(n_events)]
+
+
+def to_batch(events: Sequence[Event]) -> Batch:
+    sizes = [ev.n for ev in events]
+    off = np.zeros(len(events) + 1, np.int64)
+    off[1:] = np.cumsum(sizes)
+    assert off[-1] < 2 ** 31
+    cat = (lambda name, dt: np.concatenate([getattr(ev, name) for ev in events]).astype(dt)
+           if events else np.zeros(0, dt))
+    return Batch(cat("x", np.float32), cat("y", np.float32), cat("z", np.float32),
+                 cat("plane", np.int32), cat("pid", np.int64), cat("next_hit", np.int32),
+                 off.astype(np.int32))
+
+
+def make_batch(wl: Workload, n_events: Optional[int] = None, first: int = 0) -> Batch:
+    return to_batch(make_events(wl, n_events, first))
+
+
+# --------------------------------------------------------------------------
+# Parameters: a flat float32 blob, every Linear stored row-major [out x in]
+# followed by its bias, in this order:
+#   norm[12] = emb_mu[3], emb_sigma[3], gnn_mu[3], gnn_sigma[3]
+#   embedding  W1[Ce x 3] b1, W2[Ce x Ce] b2, W3[D x Ce] b3
+#   node enc   W[H x 3] b, W[H x H] b
+#   edge enc   W[H x 2H] b, W[H x H] b
+#   for k < n: node net W[H x 3H] b, W[H x H] b; edge net W[H x 3H] b, W[H x H] b
+#   classifier W[H x H] b, W[1 x H] b
+# --------------------------------------------------------------------------
+
+def param_layout(hidden: int, iters: int, emb_hidden: int = 128, emb_dim: int = 4):
+    """[(name, (out, in))] of every Linear in blob order (after the 12 norm floats)."""
+    H, Ce = hidden, emb_hidden
+    lay = [("emb0", (Ce, 3)), ("emb1", (Ce, Ce)), ("emb2", (emb_dim, Ce)),
+           ("nenc0", (H, 3)), ("nenc1", (H, H)),
+           ("eenc0", (H, 2 * H)), ("eenc1", (H, H))]
+    for k in range(iters):
+        lay += [(f"node{k}_0", (H, 3 * H)), (f"node{k}_1", (H, H)),
+                (f"edge{k}_0", (H, 3 * H)), (f"edge{k}_1", (H, H))]
+    lay += [("cls0", (H, H)), ("cls1", (1, H))]
+    return lay
+
+
+def param_count(hidden: int, iters: int, emb_hidden: int = 128, emb_dim: int = 4) -> int:
+    return 12 + sum(o * i + o for _, (o, i) in param_layout(hidden, iters, emb_hidden, emb_dim))
+
+
+def param_views(blob: np.ndarray, hidden: int, iters: int, emb_hidden: int = 128, emb_dim: int = 4):
+    """Name -> (W view, b view) plus 'norm' -> 12-vector, all views into `blob`."""
+    out = {"norm": blob[:12]}
+    off = 12
+    for name, (o, i) in param_layout(hidden, iters, emb_hidden, emb_dim):
+        w = blob[off:off + o * i].reshape(o, i)
+        off += o * i
+        b = blob[off:off + o]
+        off += o
+        out[name] = (w, b)
+    assert off == blob.shape[0]
+    return out
+
+
+def calibration_norm() -> np.ndarray:
+    """Input scaling constants from a seeded representative set of events.
+
+    The paper normalises network inputs with the mean and standard deviation
+    of a representative set of events (Sec. 5.1, footnote); here that set is
+    64 pile-up events drawn from a seed stream of their own.  Returns
+    emb_mu, emb_sigma (over cylindrical r, phi, z) and gnn_mu, gnn_sigma (over
+    Cartesian x, y, z), computed in float64 and rounded to float32.
+    """
+    evs = [make_event(_PILEUP, _rng(999, i)) for i in range(64)]
+    x = np.concatenate([e.x for e in evs]).astype(np.float64)
+    y = np.concatenate([e.y for e in evs]).astype(np.float64)
+    z = np.concatenate([e.z for e in evs]).astype(np.float64)
+    cyl = np.stack([np.hypot(x, y), np.arctan2(y, x), z])
+    car = np.stack([x, y, z])
+    return np.concatenate([cyl.mean(1), cyl.std(1), car.mean(1), car.std(1)]).astype(np.float32)
+
+
+_NORM_CACHE: Optional[np.ndarray] = None
+
+
+def init_params(wl: Workload, seed_words: Optional[Sequence[int]] = None) -> np.ndarray:
+    """Seeded random init: weights and biases ~ U(-1/sqrt(fan_in), 1/sqrt(fan_in)).
+
+    Drawn in float64 in blob order from PCG64(SeedSequence([root, 100 + index]))
+    and rounded to float32.  The first 12 floats are the scaling constants.
+    """
+    global _NORM_CACHE
+    if _NORM_CACHE is None:
+        _NORM_CACHE = calibration_norm()
+    rng = _rng(*(seed_words if seed_words is not None else (100 + wl.index,)))
+    parts = [_NORM_CACHE.astype(np.float64)]
+    for _, (o, i) in param_layout(wl.hidden, wl.iters, wl.emb_hidden, wl.emb_dim):
+        bound = 1.0 / math.sqrt(i)
+        parts.append(rng.uniform(-bound, bound, size=o * i))
+        parts.append(rng.uniform(-bound, bound, size=o))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def with_classifier_bias(blob: np.ndarray, hidden: int, iters: int, bias: float) -> np.ndarray:
+    """Copy of `blob` with the final classifier bias replaced (bias-centred variant)."""
+    out = blob.copy()
+    out[-1] = np.float32(bias)
+    return out
+
+
+def truth_labels(next_hit_local: np.ndarray, src_local: np.ndarray, dst_local: np.ndarray) -> np.ndarray:
+    """y = 1 iff the edge joins a hit to its particle's next hit in z (same-track, consecutive)."""
+    return (next_hit_local[src_local] == dst_local).astype(np.uint8)
+
+
+_CENTRED_JSON = __import__("os").path.join(
+    __import__("os").path.dirname(__import__("os").path.dirname(__import__("os").path.abspath(__file__))),
+    "tests", "golden", "centred_bias.json")
+
+
+def centred_params(wl: Workload) -> np.ndarray:
+    """Seeded random init with the bias-centred classifier output bias.
+
+    The bias value is stored in tests/golden/centred_bias.json, written from the
+    float64 oracle by tests/golden/make_centred_bias.py.
+    """
+    import json
+    with open(_CENTRED_JSON) as f:
+        tab = json.load(f)
+    return with_classifier_bias(init_params(wl), wl.hidden, wl.iters, tab[wl.name]["centred_bias"])

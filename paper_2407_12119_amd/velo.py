@@ -1,0 +1,248 @@
+"""Python binding of libvelognn.so (include/velognn.h): argument marshalling only.
+
+Every step of the path runs in the library's HIP kernels; torch supplies device
+memory and the current stream.  Loading fails loudly when the library is not
+built: there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import os
+from typing import Dict, Optional
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libvelognn.so")
+
+VELO_OK, VELO_ERR_INVALID_ARG, VELO_ERR_CAPACITY, VELO_ERR_OOM = 0, 1, 2, 3
+VELO_ERR_DEVICE, VELO_ERR_UNSUPPORTED, VELO_ERR_INPUT = 4, 5, 6
+VELO_FP32, VELO_BF16, VELO_FP8 = 0, 1, 2
+PRECISIONS = {"fp32": VELO_FP32, "bf16": VELO_BF16, "fp8": VELO_FP8}
+N_PLANES, EMB_HIDDEN, EMB_DIM = 26, 128, 4
+
+EXPORTS = ("velo_param_count", "velo_create", "velo_destroy", "velo_set_params", "velo_infer",
+           "velo_embed", "velo_build_graph", "velo_gnn", "velo_components", "velo_check",
+           "velo_status_str", "velo_last_error")
+
+
+class VeloError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(msg)
+        self.status = status
+
+
+class _Config(C.Structure):
+    _fields_ = [("gnn_hidden", C.c_int32), ("gnn_iters", C.c_int32), ("d2_max", C.c_float),
+                ("k_max", C.c_int32), ("edge_logit_min", C.c_float), ("precision", C.c_int32),
+                ("max_hits", C.c_int64), ("max_edges", C.c_int64), ("max_events", C.c_int32),
+                ("max_event_hits", C.c_int32)]
+
+
+class _Hits(C.Structure):
+    _fields_ = [("n_events", C.c_int32), ("n_hits", C.c_int64), ("event_offsets", C.c_void_p),
+                ("x", C.c_void_p), ("y", C.c_void_p), ("z", C.c_void_p), ("plane", C.c_void_p)]
+
+
+class _Outputs(C.Structure):
+    _fields_ = [("labels", C.c_void_p), ("edge_offsets", C.c_void_p), ("edge_src", C.c_void_p),
+                ("edge_dst", C.c_void_p), ("edge_logit", C.c_void_p), ("edge_capacity", C.c_int64),
+                ("n_edges", C.c_void_p)]
+
+
+_lib: Optional[C.CDLL] = None
+
+
+def lib() -> C.CDLL:
+    """Load libvelognn.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        vp, st = C.c_void_p, C.c_int
+        L.velo_param_count.argtypes = [C.c_int32, C.c_int32]
+        L.velo_param_count.restype = C.c_int64
+        L.velo_create.argtypes = [C.POINTER(_Config), C.POINTER(vp)]
+        L.velo_create.restype = st
+        L.velo_destroy.argtypes = [vp]
+        L.velo_destroy.restype = None
+        L.velo_set_params.argtypes = [vp, vp, C.c_int64, vp]
+        L.velo_set_params.restype = st
+        for name in ("velo_infer", "velo_gnn", "velo_components"):
+            getattr(L, name).argtypes = [vp, C.POINTER(_Hits), C.POINTER(_Outputs), vp]
+            getattr(L, name).restype = st
+        L.velo_embed.argtypes = [vp, C.POINTER(_Hits), vp, vp]
+        L.velo_embed.restype = st
+        L.velo_build_graph.argtypes = [vp, C.POINTER(_Hits), vp, C.POINTER(_Outputs), vp]
+        L.velo_build_graph.restype = st
+        L.velo_check.argtypes = [vp, vp]
+        L.velo_check.restype = st
+        L.velo_status_str.argtypes = [st]
+        L.velo_status_str.restype = C.c_char_p
+        L.velo_last_error.argtypes = [vp]
+        L.velo_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def param_count(hidden: int, iters: int) -> int:
+    return int(lib().velo_param_count(hidden, iters))
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+@dataclasses.dataclass
+class DeviceHits:
+    """A batch of hits resident on the device (torch tensors)."""
+    event_offsets: "object"     # int32 [B+1]
+    x: "object"
+    y: "object"
+    z: "object"
+    plane: "object"             # int32 [N]
+    n_events: int
+    n_hits: int
+    max_event_hits: int
+
+    @staticmethod
+    def from_batch(batch, device="cuda") -> "DeviceHits":
+        import torch
+        t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a, dtype=dt)).to(device)
+        return DeviceHits(t(batch.event_offsets, np.int32), t(batch.x, np.float32), t(batch.y, np.float32),
+                          t(batch.z, np.float32), t(batch.plane, np.int32), batch.n_events, batch.n_hits,
+                          batch.max_event_hits())
+
+    def c(self) -> _Hits:
+        return _Hits(self.n_events, self.n_hits, _ptr(self.event_offsets), _ptr(self.x), _ptr(self.y),
+                     _ptr(self.z), _ptr(self.plane))
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Context:
+    """A library context: network shape, capacities and parameters."""
+
+    def __init__(self, hidden: int, iters: int, d2_max: float, k_max: int = 32,
+                 edge_logit_min: float = 0.0, precision: str = "fp32", max_hits: int = 1 << 20,
+                 max_edges: Optional[int] = None, max_events: int = 1024, max_event_hits: int = 16384):
+        self._lib = lib()
+        self.hidden, self.iters, self.k_max = hidden, iters, k_max
+        if max_edges is None:
+            max_edges = max(1, k_max * max_hits)
+        self.cfg = _Config(hidden, iters, float(np.float32(d2_max)), k_max, float(edge_logit_min),
+                           PRECISIONS[precision], max_hits, max_edges, max_events, max_event_hits)
+        h = C.c_void_p()
+        st = self._lib.velo_create(C.byref(self.cfg), C.byref(h))
+        if st != VELO_OK:
+            raise VeloError(st, f"velo_create: {self._lib.velo_status_str(st).decode()}")
+        self._h = h
+        self.max_edges = max_edges
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.velo_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _raise(self, st: int, what: str):
+        if st != VELO_OK:
+            detail = self._lib.velo_last_error(self._h).decode()
+            raise VeloError(st, f"{what}: {self._lib.velo_status_str(st).decode()} ({detail})")
+
+    def set_params(self, params):
+        """params: float32 device tensor with the blob layout of include/velognn.h."""
+        self._params_ref = params
+        self._raise(self._lib.velo_set_params(self._h, C.c_void_p(params.data_ptr()), params.numel(),
+                                              _stream()), "velo_set_params")
+
+    def check(self):
+        self._raise(self._lib.velo_check(self._h, _stream()), "velo_check")
+
+    # ---- output allocation ----
+    def alloc_outputs(self, hits: DeviceHits, edge_capacity: Optional[int] = None) -> Dict[str, object]:
+        import torch
+        dev = hits.x.device
+        cap = self.max_edges if edge_capacity is None else edge_capacity
+        return {"labels": torch.empty(max(hits.n_hits, 1), dtype=torch.int32, device=dev),
+                "edge_offsets": torch.empty(hits.n_events + 1, dtype=torch.int32, device=dev),
+                "edge_src": torch.empty(max(cap, 1), dtype=torch.int32, device=dev),
+                "edge_dst": torch.empty(max(cap, 1), dtype=torch.int32, device=dev),
+                "edge_logit": torch.empty(max(cap, 1), dtype=torch.float32, device=dev),
+                "n_edges": torch.zeros(1, dtype=torch.int32, device=dev),
+                "edge_capacity": cap}
+
+    @staticmethod
+    def _out_c(o) -> _Outputs:
+        return _Outputs(_ptr(o.get("labels")), _ptr(o.get("edge_offsets")), _ptr(o.get("edge_src")),
+                        _ptr(o.get("edge_dst")), _ptr(o.get("edge_logit")), int(o["edge_capacity"]),
+                        _ptr(o.get("n_edges")))
+
+    # ---- calls ----
+    def infer(self, hits: DeviceHits, out: Optional[Dict[str, object]] = None, check: bool = True):
+        out = self.alloc_outputs(hits) if out is None else out
+        oc = self._out_c(out)
+        hc = hits.c()
+        self._raise(self._lib.velo_infer(self._h, C.byref(hc), C.byref(oc), _stream()), "velo_infer")
+        if check:
+            self.check()
+        return out
+
+    def embed(self, hits: DeviceHits, check: bool = True):
+        import torch
+        emb = torch.empty((max(hits.n_hits, 1), EMB_DIM), dtype=torch.float32, device=hits.x.device)
+        hc = hits.c()
+        self._raise(self._lib.velo_embed(self._h, C.byref(hc), C.c_void_p(emb.data_ptr()), _stream()),
+                    "velo_embed")
+        if check:
+            self.check()
+        return emb[:hits.n_hits]
+
+    def build_graph(self, hits: DeviceHits, emb, out=None, check: bool = True):
+        out = self.alloc_outputs(hits) if out is None else out
+        oc = self._out_c(out)
+        hc = hits.c()
+        self._raise(self._lib.velo_build_graph(self._h, C.byref(hc), C.c_void_p(emb.data_ptr()), C.byref(oc),
+                                               _stream()), "velo_build_graph")
+        if check:
+            self.check()
+        return out
+
+    def gnn(self, hits: DeviceHits, graph, check: bool = True):
+        oc = self._out_c(graph)
+        hc = hits.c()
+        self._raise(self._lib.velo_gnn(self._h, C.byref(hc), C.byref(oc), _stream()), "velo_gnn")
+        if check:
+            self.check()
+        return graph
+
+    def components(self, hits: DeviceHits, graph, check: bool = True):
+        oc = self._out_c(graph)
+        hc = hits.c()
+        self._raise(self._lib.velo_components(self._h, C.byref(hc), C.byref(oc), _stream()),
+                    "velo_components")
+        if check:
+            self.check()
+        return graph
+
+
+def graph_to_host(out: Dict[str, object], n_hits: Optional[int] = None) -> Dict[str, np.ndarray]:
+    """Copy a result dictionary to numpy (edge arrays cut to n_edges)."""
+    E = int(out["n_edges"].cpu()[0])
+    E = min(E, int(out["edge_capacity"]))
+    res = {"n_edges": E, "edge_offsets": out["edge_offsets"].cpu().numpy().astype(np.int64),
+           "src": out["edge_src"][:E].cpu().numpy(), "dst": out["edge_dst"][:E].cpu().numpy(),
+           "logit": out["edge_logit"][:E].cpu().numpy()}
+    if n_hits is not None:
+        res["labels"] = out["labels"][:n_hits].cpu().numpy()
+    return res

@@ -1,0 +1,107 @@
+"""Pins of the oracle's connected components on the purified hit graph
+(Sec. 5 overview and Sec. 7.3).
+
+Checked against scipy's and networkx's connected components and against the
+invariants of a labelling by component minimum.  Also records why the plane
+sweep of Sec. 7.3 is not used as the definition: it is not exact.
+"""
+import json
+import os
+
+import networkx as nx
+import numpy as np
+import pytest
+from scipy.sparse import coo_matrix
+from scipy.sparse.csgraph import connected_components
+
+import oracle
+from helpers import random_graph
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _min_labels_from_partition(n, comp_ids):
+    lab = np.empty(n, np.int32)
+    for c in np.unique(comp_ids):
+        m = np.nonzero(comp_ids == c)[0]
+        lab[m] = m.min()
+    return lab
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_matches_scipy_and_networkx(seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(1, 80))
+    m = int(rng.integers(0, 2 * n))
+    src, dst = random_graph(n, min(m, n * (n - 1)), rng) if n > 1 else (np.zeros(0, np.int32),) * 2
+    keep = (rng.random(src.shape[0]) < 0.6).astype(np.uint8)
+    lab = oracle.components(n, src, dst, keep)
+    k = keep.astype(bool)
+    A = coo_matrix((np.ones(k.sum()), (src[k], dst[k])), shape=(n, n))
+    _, cid = connected_components(A, directed=True, connection="weak")
+    np.testing.assert_array_equal(lab, _min_labels_from_partition(n, cid))
+    G = nx.Graph(); G.add_nodes_from(range(n)); G.add_edges_from(zip(src[k].tolist(), dst[k].tolist()))
+    exp = np.empty(n, np.int32)
+    for comp in nx.connected_components(G):
+        c = sorted(comp)
+        exp[c] = c[0]
+    np.testing.assert_array_equal(lab, exp)
+
+
+def test_label_invariants():
+    rng = np.random.default_rng(99)
+    n = 200
+    src, dst = random_graph(n, 260, rng)
+    keep = (rng.random(260) < 0.5).astype(np.uint8)
+    lab = oracle.components(n, src, dst, keep)
+    idx = np.arange(n)
+    assert np.all(lab <= idx)                           # label is the component minimum
+    assert np.all(lab[lab] == lab)                      # labels are their own label
+    k = keep.astype(bool)
+    assert np.all(lab[src[k]] == lab[dst[k]])           # kept edges join equal labels
+    # components = n - (edges of a spanning forest)
+    G = nx.Graph(); G.add_nodes_from(range(n)); G.add_edges_from(zip(src[k].tolist(), dst[k].tolist()))
+    forest = sum(len(c) - 1 for c in nx.connected_components(G))
+    assert len(np.unique(lab)) == n - forest
+
+
+def test_dropped_edges_do_not_join():
+    src = np.array([0, 1, 2], np.int32); dst = np.array([1, 2, 3], np.int32)
+    lab = oracle.components(5, src, dst, np.array([1, 0, 1], np.uint8))
+    assert lab.tolist() == [0, 0, 2, 2, 4]
+
+
+def _plane_sweep(n, plane, src, dst, keep):
+    """The two plane sweeps described in Sec. 7.3 (forward with left neighbours,
+    then backward with right neighbours), used only to show they can disagree
+    with exact components."""
+    lab = np.arange(n)
+    left = [[] for _ in range(n)]; right = [[] for _ in range(n)]
+    for s, d, k in zip(src, dst, keep):
+        if k:
+            right[s].append(d); left[d].append(s)
+    P = int(plane.max()) + 1
+    for p in range(1, P):
+        new = lab.copy()
+        for i in np.nonzero(plane == p)[0]:
+            if left[i]:
+                new[i] = min(lab[i], min(lab[j] for j in left[i]))
+        lab = new
+    for p in range(P - 2, -1, -1):
+        new = lab.copy()
+        for i in np.nonzero(plane == p)[0]:
+            if right[i]:
+                new[i] = min(lab[i], min(lab[j] for j in right[i]))
+        lab = new
+    return lab
+
+
+def test_plane_sweep_counterexample_is_not_exact():
+    with open(os.path.join(GOLDEN, "wcc_sweep_counterexample.json")) as f:
+        g = json.load(f)
+    plane = np.array(g["plane"]); src = np.array(g["src"], np.int32); dst = np.array(g["dst"], np.int32)
+    keep = np.ones(len(src), np.uint8)
+    exact = oracle.components(len(plane), src, dst, keep)
+    assert exact.tolist() == g["exact_labels"]
+    sweep = _plane_sweep(len(plane), plane, src, dst, keep)
+    assert sweep.tolist() == g["sweep_labels"] and sweep.tolist() != exact.tolist()
