@@ -153,6 +153,33 @@ velo_status velo_gnn(velo_ctx *ctx, const velo_hits *hits, velo_outputs *graph, 
  * writes graph->labels. */
 velo_status velo_components(velo_ctx *ctx, const velo_hits *hits, velo_outputs *graph, void *stream);
 
+/* Stages of the path, for per-stage device timing. */
+typedef enum {
+    VELO_STAGE_PREPARE = 0,    /* validation and plane bucketing */
+    VELO_STAGE_EMBED = 1,      /* embedding MLP (Sec. 5.1) */
+    VELO_STAGE_KNN = 2,        /* neighbour search with top-k (Sec. 5.1, 7.2) */
+    VELO_STAGE_COMPACT = 3,    /* degree scan and CSR compaction */
+    VELO_STAGE_LISTS = 4,      /* per-hit incidence lists for the incoming sums */
+    VELO_STAGE_NODE_ENC = 5,   /* node encoder (Sec. 5.2) */
+    VELO_STAGE_EDGE_ENC = 6,   /* edge encoder (Sec. 5.2) */
+    VELO_STAGE_MESSAGES = 7,   /* scatter_add message sums, one launch per step */
+    VELO_STAGE_NODE_NET = 8,   /* node network, one launch per step */
+    VELO_STAGE_EDGE_NET = 9,   /* edge network, one launch per step except the last */
+    VELO_STAGE_EDGE_CLS = 10,  /* last step's edge network fused with the edge classifier */
+    VELO_STAGE_COMPONENTS = 11,/* edge cut and connected components (Sec. 7.3) */
+    VELO_N_STAGES = 12
+} velo_stage;
+
+/* Enable (1) or disable (0) per-stage timing: while enabled every call
+ * records a pair of HIP events around each stage launch on its stream.
+ * Not for use under stream capture. */
+velo_status velo_set_timing(velo_ctx *ctx, int32_t enable);
+
+/* Synchronise the recorded events and return, per stage, the summed device
+ * milliseconds (ms[VELO_N_STAGES]) and the number of timed launches
+ * (launches[VELO_N_STAGES]) since the previous read; resets the sums. */
+velo_status velo_read_timing(velo_ctx *ctx, double *ms_host, int64_t *launches_host);
+
 /* Synchronise `stream` and return (and clear) the error latched on the
  * device by earlier calls: VELO_OK, VELO_ERR_INPUT or VELO_ERR_CAPACITY. */
 velo_status velo_check(velo_ctx *ctx, void *stream);

@@ -189,6 +189,10 @@ void velo_destroy(velo_ctx *c) {
     if (!c) return;
     DeviceGuard g(c->device);
     hipDeviceSynchronize();
+    for (auto &e : c->ev_pool) {
+        hipEventDestroy(e.start);
+        hipEventDestroy(e.stop);
+    }
     free_ws(c->ws);
     if (c->params) hipFree(c->params);
     delete c;
@@ -213,8 +217,8 @@ velo_status velo_embed(velo_ctx *c, const velo_hits *h, float *emb, void *stream
     if (h->n_hits > 0 && !emb) return fail(c, VELO_ERR_INVALID_ARG, "emb is NULL");
     DeviceGuard g(c->device);
     hipStream_t s = (hipStream_t)stream;
-    launch_prepare(c, h, s);
-    launch_embed(c, h, emb, s);
+    { StageTimer t(c, VELO_STAGE_PREPARE, s); launch_prepare(c, h, s); }
+    { StageTimer t(c, VELO_STAGE_EMBED, s); launch_embed(c, h, emb, s); }
     return device_status(c, "velo_embed");
 }
 
@@ -236,9 +240,9 @@ velo_status velo_build_graph(velo_ctx *c, const velo_hits *h, const float *emb, 
     if (h->n_hits > 0 && !emb) return fail(c, VELO_ERR_INVALID_ARG, "emb is NULL");
     DeviceGuard gd(c->device);
     hipStream_t s = (hipStream_t)stream;
-    launch_prepare(c, h, s);
-    launch_knn(c, h, emb, s);
-    launch_compact(c, h, g, s);
+    { StageTimer t(c, VELO_STAGE_PREPARE, s); launch_prepare(c, h, s); }
+    { StageTimer t(c, VELO_STAGE_KNN, s); launch_knn(c, h, emb, s); }
+    { StageTimer t(c, VELO_STAGE_COMPACT, s); launch_compact(c, h, g, s); }
     return device_status(c, "velo_build_graph");
 }
 
@@ -250,9 +254,9 @@ velo_status velo_gnn(velo_ctx *c, const velo_hits *h, velo_outputs *g, void *str
     if (g->edge_capacity > 0 && !g->edge_logit) return fail(c, VELO_ERR_INVALID_ARG, "edge_logit is NULL");
     DeviceGuard gd(c->device);
     hipStream_t s = (hipStream_t)stream;
-    launch_prepare(c, h, s);
-    launch_globalise(c, h, g, s);
-    launch_lists(c, h, true, s);
+    { StageTimer t(c, VELO_STAGE_PREPARE, s); launch_prepare(c, h, s); }
+    { StageTimer t(c, VELO_STAGE_COMPACT, s); launch_globalise(c, h, g, s); }
+    { StageTimer t(c, VELO_STAGE_LISTS, s); launch_lists(c, h, true, s); }
     launch_gnn(c, h, false, g->edge_logit, s);
     return device_status(c, "velo_gnn");
 }
@@ -266,9 +270,9 @@ velo_status velo_components(velo_ctx *c, const velo_hits *h, velo_outputs *g, vo
     if (g->edge_capacity > 0 && !g->edge_logit) return fail(c, VELO_ERR_INVALID_ARG, "edge_logit is NULL");
     DeviceGuard gd(c->device);
     hipStream_t s = (hipStream_t)stream;
-    launch_prepare(c, h, s);
-    launch_globalise(c, h, g, s);
-    launch_components(c, h, g, s);
+    { StageTimer t(c, VELO_STAGE_PREPARE, s); launch_prepare(c, h, s); }
+    { StageTimer t(c, VELO_STAGE_COMPACT, s); launch_globalise(c, h, g, s); }
+    { StageTimer t(c, VELO_STAGE_COMPONENTS, s); launch_components(c, h, g, s); }
     return device_status(c, "velo_components");
 }
 
@@ -281,14 +285,49 @@ velo_status velo_infer(velo_ctx *c, const velo_hits *h, velo_outputs *o, void *s
     if (o->edge_capacity > 0 && !o->edge_logit) return fail(c, VELO_ERR_INVALID_ARG, "edge_logit is NULL");
     DeviceGuard gd(c->device);
     hipStream_t s = (hipStream_t)stream;
-    launch_prepare(c, h, s);
-    launch_embed(c, h, c->ws.emb, s);
-    launch_knn(c, h, c->ws.emb, s);
-    launch_compact(c, h, o, s);
-    launch_lists(c, h, false, s);
+    { StageTimer t(c, VELO_STAGE_PREPARE, s); launch_prepare(c, h, s); }
+    { StageTimer t(c, VELO_STAGE_EMBED, s); launch_embed(c, h, c->ws.emb, s); }
+    { StageTimer t(c, VELO_STAGE_KNN, s); launch_knn(c, h, c->ws.emb, s); }
+    { StageTimer t(c, VELO_STAGE_COMPACT, s); launch_compact(c, h, o, s); }
+    { StageTimer t(c, VELO_STAGE_LISTS, s); launch_lists(c, h, false, s); }
     launch_gnn(c, h, true, o->edge_logit, s);
-    launch_components(c, h, o, s);
+    { StageTimer t(c, VELO_STAGE_COMPONENTS, s); launch_components(c, h, o, s); }
     return device_status(c, "velo_infer");
+}
+
+velo_status velo_set_timing(velo_ctx *c, int32_t enable) {
+    if (!c) return VELO_ERR_INVALID_ARG;
+    DeviceGuard gd(c->device);
+    if (enable && c->ev_pool.empty()) {
+        c->ev_pool.resize(8192);
+        for (auto &e : c->ev_pool) {
+            if (hipEventCreate(&e.start) != hipSuccess || hipEventCreate(&e.stop) != hipSuccess)
+                return fail(c, VELO_ERR_DEVICE, "hipEventCreate failed");
+        }
+    }
+    c->timing = enable != 0;
+    return VELO_OK;
+}
+
+velo_status velo_read_timing(velo_ctx *c, double *ms, int64_t *launches) {
+    if (!c || !ms || !launches) return VELO_ERR_INVALID_ARG;
+    DeviceGuard gd(c->device);
+    for (size_t i = 0; i < c->ev_used; i++) {
+        StageEvents &e = c->ev_pool[i];
+        if (hipEventSynchronize(e.stop) != hipSuccess) return fail(c, VELO_ERR_DEVICE, "hipEventSynchronize failed");
+        float t = 0.f;
+        hipEventElapsedTime(&t, e.start, e.stop);
+        c->stage_ms[e.stage] += t;
+        c->stage_launches[e.stage] += 1;
+    }
+    c->ev_used = 0;
+    for (int k = 0; k < VELO_N_STAGES; k++) {
+        ms[k] = c->stage_ms[k];
+        launches[k] = c->stage_launches[k];
+        c->stage_ms[k] = 0;
+        c->stage_launches[k] = 0;
+    }
+    return VELO_OK;
 }
 
 velo_status velo_check(velo_ctx *c, void *stream) {

@@ -381,6 +381,7 @@ void gnn_h(velo_ctx *c, const velo_hits *hits, bool out_identity, float *logit, 
     const int64_t N = hits->n_hits, Ecap = c->cfg.max_edges;
     if (N > 0) {
         const size_t lds = sizeof(float) * (H * (H + 4) + H * 4);
+        StageTimer t(c, VELO_STAGE_NODE_ENC, s);
         k_node_enc<H><<<persistent_grid(c, 1), kMlpBlock, lds, s>>>(N, hits->x, hits->y, hits->z, P,
                                                                    L.nenc[0].w, L.nenc[1].w, w.h[0], w.flags);
     }
@@ -391,24 +392,34 @@ void gnn_h(velo_ctx *c, const velo_hits *hits, bool out_identity, float *logit, 
     a.a = w.h[0]; a.out = w.e; a.o_w1 = L.eenc[0].w; a.o_w2 = L.eenc[1].w;
     const int iters = c->cfg.gnn_iters;
     if (iters == 0) {
+        StageTimer t(c, VELO_STAGE_EDGE_CLS, s);
         run_mlp<H, EDGE_ENC, true>(c, a, s);
         return;
     }
-    run_mlp<H, EDGE_ENC, false>(c, a, s);
+    {
+        StageTimer t(c, VELO_STAGE_EDGE_ENC, s);
+        run_mlp<H, EDGE_ENC, false>(c, a, s);
+    }
     int cur = 0;
     const int *optr = out_identity ? w.row_ptr : w.out_ptr;
     const int *olist = out_identity ? nullptr : w.out_list;
     for (int k = 0; k < iters; k++) {
-        if (N > 0)
+        if (N > 0) {
+            StageTimer t(c, VELO_STAGE_MESSAGES, s);
             k_messages<H><<<persistent_grid(c, 16), 256, 0, s>>>(N, optr, olist, w.in_ptr, w.in_list, w.e,
                                                                w.m, w.flags);
+        }
         MlpArgs nd{};
         nd.n_dev = nullptr; nd.n_host = N; nd.a = w.h[cur]; nd.b = w.m; nd.out = w.h[cur ^ 1];
         nd.P = P; nd.o_w1 = L.node[k][0].w; nd.o_w2 = L.node[k][1].w; nd.flags = w.flags;
-        if (N > 0) run_mlp<H, NODE, false>(c, nd, s);
+        if (N > 0) {
+            StageTimer t(c, VELO_STAGE_NODE_NET, s);
+            run_mlp<H, NODE, false>(c, nd, s);
+        }
         cur ^= 1;
         MlpArgs ed = a;
         ed.a = w.e; ed.b = w.h[cur]; ed.out = w.e; ed.o_w1 = L.edge[k][0].w; ed.o_w2 = L.edge[k][1].w;
+        StageTimer t(c, k == iters - 1 ? VELO_STAGE_EDGE_CLS : VELO_STAGE_EDGE_NET, s);
         if (k == iters - 1)
             run_mlp<H, EDGE, true>(c, ed, s);
         else

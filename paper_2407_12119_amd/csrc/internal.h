@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "velognn.h"
 
@@ -56,6 +57,11 @@ struct Workspace {
 
 }  // namespace velo
 
+struct StageEvents {
+    int stage;
+    hipEvent_t start, stop;
+};
+
 struct velo_ctx {
     velo_config cfg;
     int device = 0;
@@ -66,6 +72,12 @@ struct velo_ctx {
     bool params_set = false;
     velo::Workspace ws;
     std::string last_error;
+    // per-stage timing
+    bool timing = false;
+    std::vector<StageEvents> ev_pool;     // created on first enable
+    size_t ev_used = 0;
+    double stage_ms[VELO_N_STAGES] = {};
+    int64_t stage_launches[VELO_N_STAGES] = {};
 };
 
 namespace velo {
@@ -85,6 +97,23 @@ void launch_gnn(velo_ctx *c, const velo_hits *h, bool out_identity, float *logit
 
 // ---- launchers (wcc.hip) ----
 void launch_components(velo_ctx *c, const velo_hits *h, const velo_outputs *g, hipStream_t s);
+
+// Records events around the launches of one stage while timing is enabled.
+struct StageTimer {
+    velo_ctx *c;
+    hipStream_t s;
+    StageEvents *ev = nullptr;
+    StageTimer(velo_ctx *ctx, int stage, hipStream_t stream) : c(ctx), s(stream) {
+        if (c->timing && c->ev_used < c->ev_pool.size()) {
+            ev = &c->ev_pool[c->ev_used++];
+            ev->stage = stage;
+            hipEventRecord(ev->start, s);
+        }
+    }
+    ~StageTimer() {
+        if (ev) hipEventRecord(ev->stop, s);
+    }
+};
 
 // Grid size for persistent kernels: `per_cu` blocks on every compute unit.
 inline int persistent_grid(const velo_ctx *c, int per_cu) { return c->n_cu * per_cu; }

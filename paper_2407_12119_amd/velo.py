@@ -24,7 +24,9 @@ N_PLANES, EMB_HIDDEN, EMB_DIM = 26, 128, 4
 
 EXPORTS = ("velo_param_count", "velo_create", "velo_destroy", "velo_set_params", "velo_infer",
            "velo_embed", "velo_build_graph", "velo_gnn", "velo_components", "velo_check",
-           "velo_status_str", "velo_last_error")
+           "velo_status_str", "velo_last_error", "velo_set_timing", "velo_read_timing")
+STAGES = ("prepare", "embed", "knn", "compact", "lists", "node_enc", "edge_enc", "messages",
+          "node_net", "edge_net", "edge_cls", "components")
 
 
 class VeloError(RuntimeError):
@@ -83,6 +85,10 @@ def lib() -> C.CDLL:
         L.velo_status_str.restype = C.c_char_p
         L.velo_last_error.argtypes = [vp]
         L.velo_last_error.restype = C.c_char_p
+        L.velo_set_timing.argtypes = [vp, C.c_int32]
+        L.velo_set_timing.restype = st
+        L.velo_read_timing.argtypes = [vp, vp, vp]
+        L.velo_read_timing.restype = st
         _lib = L
     return _lib
 
@@ -165,6 +171,16 @@ class Context:
         self._params_ref = params
         self._raise(self._lib.velo_set_params(self._h, C.c_void_p(params.data_ptr()), params.numel(),
                                               _stream()), "velo_set_params")
+
+    def set_timing(self, enable: bool):
+        self._raise(self._lib.velo_set_timing(self._h, 1 if enable else 0), "velo_set_timing")
+
+    def read_timing(self):
+        """{stage: (milliseconds, launches)} since the last read (synchronises)."""
+        ms = np.zeros(len(STAGES), np.float64)
+        n = np.zeros(len(STAGES), np.int64)
+        self._raise(self._lib.velo_read_timing(self._h, ms.ctypes.data, n.ctypes.data), "velo_read_timing")
+        return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(STAGES)}
 
     def check(self):
         self._raise(self._lib.velo_check(self._h, _stream()), "velo_check")
