@@ -59,7 +59,7 @@ bool dalloc(T **p, int64_t count) {
 
 void free_ws(Workspace &w) {
     void *ptrs[] = {w.emb, w.hit_event, w.plane_off, w.deg, w.row_ptr, w.nbr, w.src_g, w.dst_g,
-                    w.out_ptr, w.out_list, w.in_ptr, w.in_list, w.cnt, w.scan_tmp, w.h[0], w.h[1],
+                    w.out_ptr, w.out_list, w.in_ptr, w.in_list, w.scan_tmp, w.h[0], w.h[1],
                     w.m, w.e, w.n_edges, w.flags, w.eoff_tmp};
     for (void *p : ptrs)
         if (p) hipFree(p);
@@ -131,8 +131,7 @@ velo_status velo_create(const velo_config *cfg, velo_ctx **out) {
     *out = nullptr;
     if (!cfg) return VELO_ERR_INVALID_ARG;
     const velo_config &k = *cfg;
-    if (k.gnn_hidden != 32 && k.gnn_hidden != 64) return VELO_ERR_UNSUPPORTED;
-    if (k.precision != VELO_FP32) return VELO_ERR_UNSUPPORTED;
+    if (!gnn_supported(k.gnn_hidden, k.precision)) return VELO_ERR_UNSUPPORTED;
     if (k.gnn_iters < 0 || k.gnn_iters > 16 || k.k_max < 1 || k.k_max > 64 || k.max_hits < 0 ||
         k.max_edges < 0 || k.max_events < 0 || k.max_event_hits < 0 || !(k.d2_max >= 0.f))
         return VELO_ERR_INVALID_ARG;
@@ -151,20 +150,23 @@ velo_status velo_create(const velo_config *cfg, velo_ctx **out) {
     hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device);
     c->n_cu = ncu > 0 ? ncu : 1;
     c->lds_max = (size_t)lds;
-    if ((size_t)k.max_event_hits * sizeof(int) > c->lds_max) {
+    // one event's hits must fit the LDS of one workgroup (lists, components)
+    if (((size_t)k.max_event_hits + 1024) * sizeof(int) > c->lds_max) {
         delete c;
         return VELO_ERR_UNSUPPORTED;
     }
     const int64_t N = k.max_hits, E = k.max_edges, B = k.max_events, H = k.gnn_hidden;
+    const int64_t sb = (int64_t)state_bytes(k.precision);
     Workspace &w = c->ws;
     w.scan_tmp_len = (std::max<int64_t>(N, E) + 2047) / 2048 + 1;
     bool ok = dalloc(&c->params, c->layout.total) && dalloc(&w.emb, N * 4) && dalloc(&w.hit_event, N) &&
               dalloc(&w.plane_off, B * kPlaneSlots) && dalloc(&w.deg, N) && dalloc(&w.row_ptr, N + 1) &&
               dalloc(&w.nbr, N * k.k_max) && dalloc(&w.src_g, E) && dalloc(&w.dst_g, E) &&
               dalloc(&w.out_ptr, N + 1) && dalloc(&w.out_list, E) && dalloc(&w.in_ptr, N + 1) &&
-              dalloc(&w.in_list, E) && dalloc(&w.cnt, N) && dalloc(&w.scan_tmp, w.scan_tmp_len) &&
-              dalloc(&w.h[0], N * H) && dalloc(&w.h[1], N * H) && dalloc(&w.m, N * 2 * H) &&
-              dalloc(&w.e, E * H) && dalloc(&w.n_edges, 1) && dalloc(&w.flags, 1) &&
+              dalloc(&w.in_list, E) && dalloc(&w.scan_tmp, w.scan_tmp_len) &&
+              dalloc((char **)&w.h[0], N * H * sb) && dalloc((char **)&w.h[1], N * H * sb) &&
+              dalloc(&w.m, N * 2 * H) && dalloc((char **)&w.e, E * H * sb) && dalloc(&w.n_edges, 1) &&
+              dalloc(&w.flags, 1) &&
               dalloc(&w.eoff_tmp, B + 1);
     if (!ok) {
         hipGetLastError();
@@ -256,7 +258,7 @@ velo_status velo_gnn(velo_ctx *c, const velo_hits *h, velo_outputs *g, void *str
     hipStream_t s = (hipStream_t)stream;
     { StageTimer t(c, VELO_STAGE_PREPARE, s); launch_prepare(c, h, s); }
     { StageTimer t(c, VELO_STAGE_COMPACT, s); launch_globalise(c, h, g, s); }
-    { StageTimer t(c, VELO_STAGE_LISTS, s); launch_lists(c, h, true, s); }
+    { StageTimer t(c, VELO_STAGE_LISTS, s); launch_lists(c, h, g, true, s); }
     launch_gnn(c, h, false, g->edge_logit, s);
     return device_status(c, "velo_gnn");
 }
@@ -289,7 +291,7 @@ velo_status velo_infer(velo_ctx *c, const velo_hits *h, velo_outputs *o, void *s
     { StageTimer t(c, VELO_STAGE_EMBED, s); launch_embed(c, h, c->ws.emb, s); }
     { StageTimer t(c, VELO_STAGE_KNN, s); launch_knn(c, h, c->ws.emb, s); }
     { StageTimer t(c, VELO_STAGE_COMPACT, s); launch_compact(c, h, o, s); }
-    { StageTimer t(c, VELO_STAGE_LISTS, s); launch_lists(c, h, false, s); }
+    { StageTimer t(c, VELO_STAGE_LISTS, s); launch_in_lists_plane(c, h, s); }
     launch_gnn(c, h, true, o->edge_logit, s);
     { StageTimer t(c, VELO_STAGE_COMPONENTS, s); launch_components(c, h, o, s); }
     return device_status(c, "velo_infer");

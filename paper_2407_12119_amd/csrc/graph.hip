@@ -332,43 +332,204 @@ __global__ void k_globalise(int B, const int *__restrict__ off, const int *__res
 }
 
 // ------------------------------------------------------------------------
-// incidence lists (edges grouped by hit), deterministic: counting sort, then
-// each list sorted by edge id so sums over it have a fixed order
+// incidence lists (edges grouped by hit), one workgroup per event:
+// counts with LDS atomics, a block scan, a fill through LDS cursors, then
+// every list is put in edge-id order (rank sort in registers, one wavefront
+// per hit) so that sums over a list always run in the same order.
 // ------------------------------------------------------------------------
-__global__ void k_count(const int *__restrict__ n_edges, int64_t cap, const int *__restrict__ key,
-                        int *__restrict__ cnt, const unsigned *__restrict__ flags) {
-    if (*flags) return;
-    const int64_t E = min((int64_t)*n_edges, cap);
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < E; e += (int64_t)gridDim.x * blockDim.x)
-        atomicAdd(&cnt[key[e]], 1);
-}
+constexpr int kListBlock = 1024;
 
-__global__ void k_scatter(const int *__restrict__ n_edges, int64_t cap, const int *__restrict__ key,
-                          const int *__restrict__ ptr, int *__restrict__ cur, int *__restrict__ list,
-                          const unsigned *__restrict__ flags) {
+__global__ __launch_bounds__(kListBlock) void k_lists(int B, const int *__restrict__ off,
+                                                      const int *__restrict__ eoff,
+                                                      const int *__restrict__ n_edges,
+                                                      const int *__restrict__ key_g, int *__restrict__ ptr_g,
+                                                      int *__restrict__ list, int max_ev,
+                                                      const unsigned *__restrict__ flags) {
+    extern __shared__ int sh[];
     if (*flags) return;
-    const int64_t E = min((int64_t)*n_edges, cap);
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < E; e += (int64_t)gridDim.x * blockDim.x) {
-        const int k = key[e];
-        const int slot = atomicAdd(&cur[k], 1);
-        list[ptr[k] + slot] = (int)e;
+    int *cnt = sh;                 // [max_ev]
+    int *part = sh + max_ev;       // [kListBlock]
+    const int b = blockIdx.x, t = threadIdx.x;
+    const int s = off[b], n = off[b + 1] - s;
+    const int E = *n_edges;
+    const int e0 = min(eoff[b], E), e1 = min(eoff[b + 1], E);
+    if (n > max_ev) return;
+    for (int l = t; l < n; l += kListBlock) cnt[l] = 0;
+    __syncthreads();
+    for (int q = e0 + t; q < e1; q += kListBlock) {
+        const int k = key_g[q] - s;
+        if (k >= 0 && k < n) atomicAdd(&cnt[k], 1);
+    }
+    __syncthreads();
+    // exclusive scan of cnt[0..n): each thread owns a contiguous slice
+    const int per = (n + kListBlock - 1) / kListBlock;
+    const int lo = min(t * per, n), hi = min(lo + per, n);
+    int sum = 0;
+    for (int l = lo; l < hi; l++) sum += cnt[l];
+    part[t] = sum;
+    __syncthreads();
+    for (int d = 1; d < kListBlock; d <<= 1) {
+        const int add = t >= d ? part[t - d] : 0;
+        __syncthreads();
+        part[t] += add;
+        __syncthreads();
+    }
+    int run = e0 + part[t] - sum;
+    for (int l = lo; l < hi; l++) {
+        ptr_g[s + l] = run;
+        run += cnt[l];
+    }
+    if (b == B - 1 && t == 0) ptr_g[s + n] = e1;
+    __syncthreads();
+    for (int l = t; l < n; l += kListBlock) cnt[l] = 0;
+    __threadfence_block();
+    __syncthreads();
+    for (int q = e0 + t; q < e1; q += kListBlock) {
+        const int k = key_g[q] - s;
+        if (k < 0 || k >= n) continue;
+        const int slot = atomicAdd(&cnt[k], 1);
+        list[ptr_g[s + k] + slot] = q;
+    }
+    __threadfence_block();
+    __syncthreads();
+    // order every list by edge id
+    const int lane = t & 63, wave = t >> 6, nw = kListBlock / 64;
+    for (int l = wave; l < n; l += nw) {
+        const int L = cnt[l];
+        if (L <= 1) continue;
+        const int a = ptr_g[s + l];
+        if (L <= 64) {
+            const int v = lane < L ? list[a + lane] : 0x7fffffff;
+            int rank = 0;
+            for (int j = 0; j < L; j++) rank += __shfl(v, j) < v;
+            if (lane < L) list[a + rank] = v;
+        } else if (lane == 0) {
+            for (int u = a + 1; u < a + L; u++) {
+                const int v = list[u];
+                int w = u - 1;
+                while (w >= a && list[w] > v) {
+                    list[w + 1] = list[w];
+                    w--;
+                }
+                list[w + 1] = v;
+            }
+        }
     }
 }
 
-__global__ void k_sort_lists(int64_t n_hits, const int *__restrict__ ptr, int *__restrict__ list,
-                             const unsigned *__restrict__ flags) {
-    if (*flags) return;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_hits; i += (int64_t)gridDim.x * blockDim.x) {
-        const int a = ptr[i], b = ptr[i + 1];
-        for (int u = a + 1; u < b; u++) {
+// ------------------------------------------------------------------------
+// incoming lists of a rough graph built by k_knn, one workgroup per (event,
+// destination plane q): the in-edges of hits on plane q all leave from the
+// CSR rows of planes q-2 and q-1, one contiguous range of edges.  The block
+// counts them per destination with LDS atomics (pass 1, then a global scan of
+// the counts gives in_ptr), then places them through LDS cursors, puts every
+// list in edge-id order inside LDS and writes the plane's lists out in one
+// coalesced sweep (pass 2).  Planes whose window does not fit the LDS budget
+// use the same steps on global memory.
+// ------------------------------------------------------------------------
+constexpr int kPlaneBlock = 256;
+constexpr int kPlaneMaxDst = 2048;     // destinations of one plane held in LDS
+constexpr int kPlaneMaxEdges = 8192;   // in-edges of one plane held in LDS
+
+__device__ inline void plane_window(int b, int q, const int *__restrict__ off, const int *__restrict__ plane_off,
+                                    const int *__restrict__ row_ptr, int &s, int &d0, int &D, int &E0, int &E1) {
+    s = off[b];
+    const int *po = plane_off + (int64_t)b * kPlaneSlots;
+    d0 = po[q];
+    D = po[q + 1] - d0;
+    const int u0 = po[max(q - 2, 0)], u1 = po[q];
+    E0 = row_ptr[s + u0];
+    E1 = row_ptr[s + u1];
+}
+
+// order list[a, a+L) ascending: one wavefront, values distinct
+__device__ inline void wave_sort(int *list, int L, int lane) {
+    if (L <= 1) return;
+    if (L <= 64) {
+        const int v = lane < L ? list[lane] : 0x7fffffff;
+        int rank = 0;
+        for (int j = 0; j < L; j++) rank += __shfl(v, j) < v;
+        if (lane < L) list[rank] = v;
+    } else if (lane == 0) {
+        for (int u = 1; u < L; u++) {
             const int v = list[u];
             int w = u - 1;
-            while (w >= a && list[w] > v) {
+            while (w >= 0 && list[w] > v) {
                 list[w + 1] = list[w];
                 w--;
             }
             list[w + 1] = v;
         }
+    }
+}
+
+__global__ __launch_bounds__(kPlaneBlock) void k_in_count(int B, const int *__restrict__ off,
+                                                          const int *__restrict__ plane_off,
+                                                          const int *__restrict__ row_ptr,
+                                                          const int *__restrict__ dst_g, int *__restrict__ deg,
+                                                          int *__restrict__ cur_g, const unsigned *__restrict__ flags) {
+    __shared__ int cnt[kPlaneMaxDst];
+    if (*flags) return;
+    const int b = blockIdx.x / VELO_N_PLANES, q = blockIdx.x % VELO_N_PLANES, t = threadIdx.x;
+    int s, d0, D, E0, E1;
+    plane_window(b, q, off, plane_off, row_ptr, s, d0, D, E0, E1);
+    if (D <= 0) return;
+    const int lo = s + d0, hi = s + d0 + D;    // batch-global destinations of this plane
+    if (D <= kPlaneMaxDst) {
+        for (int i = t; i < D; i += kPlaneBlock) cnt[i] = 0;
+        __syncthreads();
+        for (int e = E0 + t; e < E1; e += kPlaneBlock) {
+            const int d = dst_g[e];
+            if (d >= lo && d < hi) atomicAdd(&cnt[d - lo], 1);
+        }
+        __syncthreads();
+        for (int i = t; i < D; i += kPlaneBlock) deg[lo + i] = cnt[i];
+    } else {
+        for (int i = t; i < D; i += kPlaneBlock) deg[lo + i] = 0;
+        __syncthreads();
+        for (int e = E0 + t; e < E1; e += kPlaneBlock) {
+            const int d = dst_g[e];
+            if (d >= lo && d < hi) atomicAdd(&deg[d], 1);
+        }
+    }
+    for (int i = t; i < D; i += kPlaneBlock) cur_g[lo + i] = 0;
+}
+
+__global__ __launch_bounds__(kPlaneBlock) void k_in_fill(int B, const int *__restrict__ off,
+                                                         const int *__restrict__ plane_off,
+                                                         const int *__restrict__ row_ptr,
+                                                         const int *__restrict__ dst_g,
+                                                         const int *__restrict__ in_ptr, int *__restrict__ in_list,
+                                                         int *__restrict__ cur_g, const unsigned *__restrict__ flags) {
+    __shared__ int cur[kPlaneMaxDst];
+    __shared__ int buf[kPlaneMaxEdges];
+    if (*flags) return;
+    const int b = blockIdx.x / VELO_N_PLANES, q = blockIdx.x % VELO_N_PLANES, t = threadIdx.x;
+    const int lane = t & 63, wave = t >> 6, nw = kPlaneBlock / 64;
+    int s, d0, D, E0, E1;
+    plane_window(b, q, off, plane_off, row_ptr, s, d0, D, E0, E1);
+    if (D <= 0) return;
+    const int lo = s + d0, hi = s + d0 + D;
+    const int base = in_ptr[lo], tot = in_ptr[hi] - base;
+    if (D <= kPlaneMaxDst && tot <= kPlaneMaxEdges) {
+        for (int i = t; i < D; i += kPlaneBlock) cur[i] = 0;
+        __syncthreads();
+        for (int e = E0 + t; e < E1; e += kPlaneBlock) {
+            const int d = dst_g[e];
+            if (d >= lo && d < hi) buf[in_ptr[d] - base + atomicAdd(&cur[d - lo], 1)] = e;
+        }
+        __syncthreads();
+        for (int i = wave; i < D; i += nw) wave_sort(buf + (in_ptr[lo + i] - base), cur[i], lane);
+        __syncthreads();
+        for (int i = t; i < tot; i += kPlaneBlock) in_list[base + i] = buf[i];
+    } else {
+        for (int e = E0 + t; e < E1; e += kPlaneBlock) {
+            const int d = dst_g[e];
+            if (d >= lo && d < hi) in_list[in_ptr[d] + atomicAdd(&cur_g[d], 1)] = e;
+        }
+        __threadfence_block();
+        __syncthreads();
+        for (int i = wave; i < D; i += nw) wave_sort(in_list + in_ptr[lo + i], in_ptr[lo + i + 1] - in_ptr[lo + i], lane);
     }
 }
 
@@ -435,21 +596,44 @@ void launch_globalise(velo_ctx *c, const velo_hits *h, const velo_outputs *g, hi
                                                 w.dst_g, w.flags);
 }
 
-void launch_lists(velo_ctx *c, const velo_hits *h, bool need_out_lists, hipStream_t s) {
+void launch_lists(velo_ctx *c, const velo_hits *h, const velo_outputs *g, bool need_out_lists, hipStream_t s) {
     Workspace &w = c->ws;
-    const int64_t N = h->n_hits, cap = c->cfg.max_edges;
-    const int eb = persistent_grid(c, 8);
+    if (h->n_events <= 0) return;
+    const int *eoff = g->edge_offsets ? g->edge_offsets : w.eoff_tmp;
+    const size_t lds = sizeof(int) * ((size_t)c->cfg.max_event_hits + kListBlock);
+    static bool attr = false;
+    if (!attr) {
+        hipFuncSetAttribute(reinterpret_cast<const void *>(&k_lists), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)c->lds_max);
+        attr = true;
+    }
     for (int dir = need_out_lists ? 0 : 1; dir < 2; dir++) {
         const int *key = dir == 0 ? w.src_g : w.dst_g;
         int *ptr = dir == 0 ? w.out_ptr : w.in_ptr;
         int *list = dir == 0 ? w.out_list : w.in_list;
-        launch_fill(w.cnt, 0, N, s);
-        k_count<<<eb, 256, 0, s>>>(w.n_edges, cap, key, w.cnt, w.flags);
-        launch_scan(c, w.cnt, ptr, N, s);
-        launch_fill(w.cnt, 0, N, s);
-        k_scatter<<<eb, 256, 0, s>>>(w.n_edges, cap, key, ptr, w.cnt, list, w.flags);
-        if (N > 0) k_sort_lists<<<grid_for(N, 256, persistent_grid(c, 8)), 256, 0, s>>>(N, ptr, list, w.flags);
+        k_lists<<<h->n_events, kListBlock, lds, s>>>(h->n_events, h->event_offsets, eoff, w.n_edges, key, ptr, list,
+                                                     c->cfg.max_event_hits, w.flags);
     }
+}
+
+}  // namespace velo
+
+namespace velo {
+
+void launch_in_lists_plane(velo_ctx *c, const velo_hits *h, hipStream_t s) {
+    Workspace &w = c->ws;
+    const int64_t N = h->n_hits;
+    if (h->n_events <= 0 || N <= 0) {
+        launch_scan(c, w.deg, w.in_ptr, 0, s);
+        return;
+    }
+    const int blocks = h->n_events * VELO_N_PLANES;
+    int *cur_g = w.nbr;   // the neighbour staging buffer is free once the CSR is built
+    k_in_count<<<blocks, kPlaneBlock, 0, s>>>(h->n_events, h->event_offsets, w.plane_off, w.row_ptr, w.dst_g, w.deg,
+                                              cur_g, w.flags);
+    launch_scan(c, w.deg, w.in_ptr, N, s);
+    k_in_fill<<<blocks, kPlaneBlock, 0, s>>>(h->n_events, h->event_offsets, w.plane_off, w.row_ptr, w.dst_g, w.in_ptr,
+                                             w.in_list, cur_g, w.flags);
 }
 
 }  // namespace velo

@@ -44,12 +44,11 @@ struct Workspace {
     int *out_list = nullptr;     // [max_edges]
     int *in_ptr = nullptr;       // [max_hits + 1]
     int *in_list = nullptr;      // [max_edges]
-    int *cnt = nullptr;          // [max_hits] counters for list building
     int *scan_tmp = nullptr;     // block sums of the scans
     int64_t scan_tmp_len = 0;
-    float *h[2] = {nullptr, nullptr};   // [max_hits x H] hit encodings (ping-pong)
-    float *m = nullptr;          // [max_hits x 2H] messages, float32
-    float *e = nullptr;          // [max_edges x H] edge encodings (updated in place)
+    void *h[2] = {nullptr, nullptr};    // [max_hits x H] hit encodings (ping-pong), fp32 or bf16
+    float *m = nullptr;          // [max_hits x 2H] messages, float32 in every precision
+    void *e = nullptr;           // [max_edges x H] edge encodings (updated in place), fp32 or bf16
     int *n_edges = nullptr;      // [1] internal edge count
     unsigned *flags = nullptr;   // [1] latched device errors
     int *eoff_tmp = nullptr;     // [max_events + 1]
@@ -88,10 +87,13 @@ void launch_knn(velo_ctx *c, const velo_hits *h, const float *emb, hipStream_t s
 void launch_scan(velo_ctx *c, const int *in, int *out, int64_t n, hipStream_t s);
 void launch_compact(velo_ctx *c, const velo_hits *h, velo_outputs *g, hipStream_t s);
 void launch_globalise(velo_ctx *c, const velo_hits *h, const velo_outputs *g, hipStream_t s);
-void launch_lists(velo_ctx *c, const velo_hits *h, bool need_out_lists, hipStream_t s);
+void launch_lists(velo_ctx *c, const velo_hits *h, const velo_outputs *g, bool need_out_lists, hipStream_t s);
 void launch_fill(int *p, int v, int64_t n, hipStream_t s);
+void launch_in_lists_plane(velo_ctx *c, const velo_hits *h, hipStream_t s);
 
 // ---- launchers (gnn.hip) ----
+size_t state_bytes(int precision);              // bytes per stored encoding element
+bool gnn_supported(int hidden, int precision);  // compiled (hidden, precision) pairs
 void launch_embed(velo_ctx *c, const velo_hits *h, float *emb, hipStream_t s);
 void launch_gnn(velo_ctx *c, const velo_hits *h, bool out_identity, float *logit, hipStream_t s);
 

@@ -1,0 +1,156 @@
+"""GPU: the bf16 path against the float64 oracle.
+
+The bf16 path rounds every MLP operand (weights, activations) to bfloat16
+(8-bit significand, unit roundoff u = 2^-8) and accumulates in float32;
+distances, message sums and the edge cut stay float32.  Each rounded operand
+pair contributes a relative error of at most about 2u per product; summed
+over K-term dot products of mixed signs the error of a layer output stays
+near u times its magnitude, and the residual chain adds one such term per
+layer of depth (encoder, n steps, classifier).  The tests bound the logit
+error by (n + 2) u + 4 u |z| and report what they measure.  Decisions are compared only on
+edges whose oracle logit is farther from the cut than the error bound;
+closer edges are counted as ambiguous.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle                                           # noqa: E402
+from paper_2407_12119_amd import synth, velo           # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+U = 2.0 ** -8
+EMB_REL = 4 * U         # three layers, operands rounded once each
+
+
+def logit_bound(iters):
+    """|dz| bound: about one u of accumulated error per layer of depth (the
+    encoder, n steps and the classifier), absolute for |z| < 1, relative above."""
+    return (iters + 2) * U, 4 * U
+
+
+def _ctx(wl, batch, precision, **kw):
+    args = dict(max_hits=max(batch.n_hits, 1), max_events=max(batch.n_events, 1),
+                max_event_hits=max(batch.max_event_hits(), 1))
+    args.update(kw)
+    ctx = velo.Context(wl.hidden, wl.iters, oracle.d2max_f32(wl.radius), wl.k_max, wl.edge_logit_min,
+                       precision, **args)
+    return ctx
+
+
+def _setup(wl, batch, precision, blob):
+    print(f"\n[case] {wl.name} {precision} events={batch.n_events} hits={batch.n_hits}", flush=True)
+    ctx = _ctx(wl, batch, precision)
+    ctx.set_params(torch.from_numpy(blob).cuda())
+    return ctx, velo.DeviceHits.from_batch(batch)
+
+
+@pytest.mark.parametrize("name,events_from,check", [("batch256", "batch256", (0, 2)),
+                                                    ("batch1000_h128", "single_event", (0,))])
+def test_bf16_gnn_on_a_given_graph(name, events_from, check):
+    """Stage-isolated: bf16 GNN on a given graph vs the float64 oracle on the same graph."""
+    wl = synth.WORKLOADS[name]
+    src_wl = synth.WORKLOADS[events_from]
+    batch = synth.make_batch(src_wl, n_events=min(3, src_wl.n_events), first=0 if src_wl.n_events == 1 else 5)
+    blob = synth.centred_params(wl)
+    c32, hits = _setup(wl, batch, "fp32", blob) if wl.hidden <= 64 else (None, None)
+    cbf, hbf = _setup(wl, batch, "bf16", blob)
+    if c32 is not None:
+        g = c32.infer(hits)
+    else:
+        emb = cbf.embed(hbf)
+        g = cbf.build_graph(hbf, emb)
+    cbf.gnn(hbf, g)
+    gh = velo.graph_to_host(g, batch.n_hits)
+    worst = 0.0
+    for b in check:
+        ev = batch.event(b)
+        s, e = int(gh["edge_offsets"][b]), int(gh["edge_offsets"][b + 1])
+        src, dst, z_bf = gh["src"][s:e], gh["dst"][s:e], gh["logit"][s:e]
+        z = oracle.gnn_forward(ev.x, ev.y, ev.z, src, dst, blob, wl.hidden, wl.iters)
+        err = np.abs(z_bf - z)
+        la, lr = logit_bound(wl.iters)
+        bound = la + lr * np.abs(z)
+        print(f"  event {b}: {len(z)} edges, max |dz| {err.max():.4g}, mean {err.mean():.3g}, "
+              f"|z| mean {np.abs(z).mean():.3g}", flush=True)
+        assert np.all(err <= bound), (b, err.max())
+        worst = max(worst, float(err.max()))
+        far = np.abs(z) > bound
+        agree = ((z_bf >= 0) == (z >= 0))[far].mean() if far.any() else 1.0
+        assert agree == 1.0
+
+
+def test_bf16_embedding_and_graph_stage():
+    wl = synth.WORKLOADS["batch256"]
+    batch = synth.make_batch(wl, n_events=4, first=20)
+    blob = synth.centred_params(wl)
+    ctx, hits = _setup(wl, batch, "bf16", blob)
+    emb = ctx.embed(hits).cpu().numpy()
+    for b in range(batch.n_events):
+        ev = batch.event(b)
+        o0 = int(batch.event_offsets[b])
+        e_or = oracle.embed(ev.x, ev.y, ev.z, blob)
+        err = np.abs(emb[o0:o0 + ev.n] - e_or).max() / max(np.abs(e_or).max(), 1e-3)
+        print(f"  event {b}: bf16 embedding max rel err {err:.3g}", flush=True)
+        assert err <= EMB_REL
+    # the neighbour search is float32 in every precision: exact on the bf16 embedding
+    g = velo.graph_to_host(ctx.build_graph(hits, torch.from_numpy(emb).cuda()), batch.n_hits)
+    r2 = oracle.d2max_f32(wl.radius)
+    for b in range(batch.n_events):
+        ev = batch.event(b)
+        o0 = int(batch.event_offsets[b])
+        rp, col = oracle.neighbours(ev.plane, emb[o0:o0 + ev.n], r2, wl.k_max)
+        src, dst = oracle.csr_to_edges(rp, col)
+        s, e = int(g["edge_offsets"][b]), int(g["edge_offsets"][b + 1])
+        np.testing.assert_array_equal(g["src"][s:e], src)
+        np.testing.assert_array_equal(g["dst"][s:e], dst)
+
+
+def test_bf16_end_to_end_decisions_over_the_union_of_edges():
+    """Decisions compared over the union of both edge sets (an edge missing from
+    one graph counts as rejected there); labels from the bf16 decisions exact."""
+    wl = synth.WORKLOADS["batch256"]
+    batch = synth.make_batch(wl, n_events=2, first=50)
+    blob = synth.centred_params(wl)
+    ctx, hits = _setup(wl, batch, "bf16", blob)
+    g = velo.graph_to_host(ctx.infer(hits), batch.n_hits)
+    ref = oracle.pipeline(batch, blob, wl.hidden, wl.iters, wl.radius, wl.k_max)
+    for b in range(batch.n_events):
+        s, e = int(g["edge_offsets"][b]), int(g["edge_offsets"][b + 1])
+        rs, re_ = int(ref["edge_offsets"][b]), int(ref["edge_offsets"][b + 1])
+        A = dict(zip(zip(g["src"][s:e].tolist(), g["dst"][s:e].tolist()), g["logit"][s:e].tolist()))
+        B = dict(zip(zip(ref["src"][rs:re_].tolist(), ref["dst"][rs:re_].tolist()),
+                     ref["logit"][rs:re_].tolist()))
+        union = set(A) | set(B)
+        jac = len(set(A) & set(B)) / max(len(union), 1)
+        dec_a = np.array([A.get(k, -np.inf) >= 0 for k in union])
+        dec_b = np.array([B.get(k, -np.inf) >= 0 for k in union])
+        zb = np.array([B.get(k, 0.0) for k in union])
+        clear = np.abs(zb) > logit_bound(wl.iters)[0]
+        agree = (dec_a == dec_b).mean()
+        agree_clear = (dec_a == dec_b)[clear].mean() if clear.any() else 1.0
+        print(f"  event {b}: edges {len(A)} vs {len(B)}, Jaccard {jac:.4f}, decision agreement "
+              f"{agree:.4f} (clear of the cut: {agree_clear:.4f}, {clear.mean():.3f} of edges)", flush=True)
+        assert jac > 0.98
+        o0, o1 = int(batch.event_offsets[b]), int(batch.event_offsets[b + 1])
+        keep = (g["logit"][s:e] >= 0).astype(np.uint8)
+        lab = oracle.components(o1 - o0, g["src"][s:e], g["dst"][s:e], keep)
+        np.testing.assert_array_equal(g["labels"][o0:o1], lab)
+
+
+def test_bf16_batch_invariance_and_determinism():
+    wl = synth.WORKLOADS["batch256"]
+    batch = synth.make_batch(wl, n_events=6, first=70)
+    blob = synth.centred_params(wl)
+    ctx, hits = _setup(wl, batch, "bf16", blob)
+    a = velo.graph_to_host(ctx.infer(hits), batch.n_hits)
+    b = velo.graph_to_host(ctx.infer(hits), batch.n_hits)
+    for k in ("src", "dst", "logit", "labels"):
+        np.testing.assert_array_equal(a[k], b[k])
+    one = synth.to_batch([batch.event(3)])
+    g1 = velo.graph_to_host(ctx.infer(velo.DeviceHits.from_batch(one)), one.n_hits)
+    s, e = int(a["edge_offsets"][3]), int(a["edge_offsets"][4])
+    np.testing.assert_array_equal(a["logit"][s:e], g1["logit"])
+    np.testing.assert_array_equal(a["dst"][s:e], g1["dst"])
