@@ -69,10 +69,16 @@ def roofline(stages, H, prec, n_edges, n_hits):
 def run_batched(velo, synth, torch, wl, batch, hits, blob, prec, steps, warmup):
     import numpy as np
     r2 = float(np.float32(wl.radius * wl.radius))
+    mx = batch.max_event_hits()
+    if prec == "fp8":
+        mx = max(mx, synth.calibration_batch(wl, 16).max_event_hits())
     ctx = velo.Context(wl.hidden, wl.iters, r2, wl.k_max, wl.edge_logit_min, prec,
-                       max_hits=batch.n_hits, max_events=batch.n_events,
-                       max_event_hits=batch.max_event_hits())
+                       max_hits=batch.n_hits, max_events=batch.n_events, max_event_hits=mx)
     ctx.set_params(torch.from_numpy(blob).cuda())
+    if prec == "fp8":
+        calib = synth.calibration_batch(wl, 16)
+        log(f"fp8: calibrating on {calib.n_events} events")
+        ctx.calibrate(velo.DeviceHits.from_batch(calib))
     out = ctx.alloc_outputs(hits)
     log(f"{prec}: warmup {warmup}")
     for _ in range(warmup):
@@ -105,8 +111,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="batch256")
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"])
-    ap.add_argument("--variants", default="bf16",
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp8"])
+    ap.add_argument("--variants", default="bf16,fp8",
                     help="comma list of extra precisions timed in the same run ('' for none)")
     ap.add_argument("--cpu-sample-events", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -52,13 +52,15 @@ typedef enum {
     VELO_ERR_OOM = 3,           /* device allocation failed in velo_create */
     VELO_ERR_DEVICE = 4,        /* a HIP runtime call failed */
     VELO_ERR_UNSUPPORTED = 5,   /* configuration not compiled in (e.g. hidden width) */
-    VELO_ERR_INPUT = 6          /* device-side validation of the hits failed */
+    VELO_ERR_INPUT = 6,         /* device-side validation of the hits failed */
+    VELO_ERR_NOT_CALIBRATED = 7 /* fp8 context used before velo_calibrate */
 } velo_status;
 
 typedef enum {
     VELO_FP32 = 0,   /* MLP operands and state in float32 */
     VELO_BF16 = 1,   /* MLP operands bfloat16, float32 accumulation */
-    VELO_FP8 = 2     /* MLP operands FP8 E4M3 with per-tensor scales */
+    VELO_FP8 = 2     /* MLP operands OCP FP8 E4M3 with static per-tensor scales,
+                        float32 accumulation; encodings stored bf16 */
 } velo_precision;
 
 /* Network and capacity configuration, fixed for the life of a context. */
@@ -72,7 +74,9 @@ typedef struct {
     int64_t max_hits;        /* capacity: hits per call */
     int64_t max_edges;       /* capacity: edges per call (< 2^31) */
     int32_t max_events;      /* capacity: events per call */
-    int32_t max_event_hits;  /* capacity: hits of one event (<= 32768) */
+    int32_t max_event_hits;  /* capacity: hits of one event; (max_event_hits + 1024) ints
+                                must fit one workgroup's LDS (160 KB on MI355X) */
+    int32_t training;        /* 1: also allocate the training workspace (fp32 only) */
 } velo_config;
 
 /* A batch of hits.  n_events and n_hits are HOST values; n_hits must equal
@@ -125,6 +129,15 @@ void velo_destroy(velo_ctx *ctx);
  * called before any compute call; may be called again (e.g. after an
  * optimiser step) and is ordered with later work on the same stream. */
 velo_status velo_set_params(velo_ctx *ctx, const float *params, int64_t n, void *stream);
+
+/* fp8 contexts: derive the static per-tensor activation scales from a
+ * calibration batch (the paper calibrates its INT8 embedding on 5,000 events,
+ * Sec. 7.4).  Runs the path with bf16 operands on `hits`, records the largest
+ * |value| entering every MLP layer and sets s_x = max / 448 (the largest E4M3
+ * value); weight scales s_w = max |W| / 448 are set by velo_set_params, which
+ * also invalidates earlier activation scales.  Compute calls on an fp8
+ * context return VELO_ERR_NOT_CALIBRATED until this has been called. */
+velo_status velo_calibrate(velo_ctx *ctx, const velo_hits *hits, void *stream);
 
 /* Whole path: embedding, rough graph, GNN, edge cut, components.  Writes
  * labels, edge_offsets, edge_src, edge_dst, edge_logit and n_edges. */
@@ -179,6 +192,56 @@ velo_status velo_set_timing(velo_ctx *ctx, int32_t enable);
  * milliseconds (ms[VELO_N_STAGES]) and the number of timed launches
  * (launches[VELO_N_STAGES]) since the previous read; resets the sums. */
 velo_status velo_read_timing(velo_ctx *ctx, double *ms_host, int64_t *launches_host);
+
+/* ---- graph capture ---- */
+
+typedef struct velo_graph velo_graph;
+
+/* Capture one velo_infer call on `stream` into a HIP graph and instantiate
+ * it.  The graph keeps the device pointers of `hits` and `out` (and
+ * n_events/n_hits): to run it on new data, write the new hits into the same
+ * buffers (same event and hit counts) and call velo_graph_launch.  Timing
+ * must be off, and `stream` must not be the legacy default stream (NULL).
+ * The context must stay alive while the graph is used. */
+velo_status velo_graph_capture(velo_ctx *ctx, const velo_hits *hits, velo_outputs *out, void *stream,
+                               velo_graph **graph);
+
+/* Launch a captured graph on `stream` (asynchronous). */
+velo_status velo_graph_launch(velo_graph *graph, void *stream);
+
+/* Free a captured graph.  NULL is a no-op. */
+void velo_graph_destroy(velo_graph *graph);
+
+/* ---- training form (fp32 contexts created with training = 1) ---- */
+
+/* Forward pass of the GNN for training: like velo_gnn on the given graph
+ * (edges grouped by event, event-local indices, n_edges), but with the
+ * caller's float32 parameter blob `params` (device, velo_param_count entries)
+ * and keeping the step-boundary hit/edge encodings and messages in the
+ * context for velo_train_backward.  Writes graph->edge_logit. */
+velo_status velo_train_forward(velo_ctx *ctx, const velo_hits *hits, velo_outputs *graph, const float *params,
+                               void *stream);
+
+/* Weighted binary cross-entropy on n logits (training loss):
+ *   loss = (1/n) sum_q w_q [softplus(z_q) - y_q z_q], w = pos_weight if y = 1 else 1,
+ *   dlogit_q = w_q (sigmoid(z_q) - y_q) / n.
+ * logit, y (uint8 0/1), dlogit: [n] device; loss: [1] device. */
+velo_status velo_bce(velo_ctx *ctx, const float *logit, const uint8_t *y, float pos_weight, int64_t n,
+                     float *loss, float *dlogit, void *stream);
+
+/* Reverse-mode pass of the last velo_train_forward: given dL/dlogit (device,
+ * one per edge of that graph) writes dL/dparams (device, blob-shaped; the
+ * normalisation and embedding entries are zero, graph building being not
+ * differentiable).  Hidden activations are recomputed from the kept
+ * step-boundary states; no floating-point atomics, so it is deterministic. */
+velo_status velo_train_backward(velo_ctx *ctx, const velo_hits *hits, const float *params, const float *dlogit,
+                                float *dparams, void *stream);
+
+/* One Adam step with bias correction on n float32 parameters (all device):
+ * m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+ * p -= lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps); step >= 1. */
+velo_status velo_adam_step(velo_ctx *ctx, float *params, const float *grad, float *m, float *v, int64_t n, float lr,
+                           float b1, float b2, float eps, int32_t step, void *stream);
 
 /* Synchronise `stream` and return (and clear) the error latched on the
  * device by earlier calls: VELO_OK, VELO_ERR_INPUT or VELO_ERR_CAPACITY. */

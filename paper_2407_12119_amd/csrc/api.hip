@@ -60,7 +60,9 @@ bool dalloc(T **p, int64_t count) {
 void free_ws(Workspace &w) {
     void *ptrs[] = {w.emb, w.hit_event, w.plane_off, w.deg, w.row_ptr, w.nbr, w.src_g, w.dst_g,
                     w.out_ptr, w.out_list, w.in_ptr, w.in_list, w.scan_tmp, w.h[0], w.h[1],
-                    w.m, w.e, w.n_edges, w.flags, w.eoff_tmp};
+                    w.m, w.e, w.n_edges, w.flags, w.eoff_tmp, w.ck_h, w.ck_e, w.ck_m, w.g_e[0], w.g_e[1],
+                    w.g_h[0], w.g_h[1], w.g_xs, w.g_xd, w.g_da, w.g_r, w.g_m, w.g_part, w.g_loss,
+                    w.scales, w.amax, w.tmp_logit};
     for (void *p : ptrs)
         if (p) hipFree(p);
     w = Workspace();
@@ -120,6 +122,7 @@ const char *velo_status_str(velo_status s) {
         case VELO_ERR_DEVICE: return "HIP runtime error";
         case VELO_ERR_UNSUPPORTED: return "unsupported configuration";
         case VELO_ERR_INPUT: return "invalid input hits (device validation)";
+        case VELO_ERR_NOT_CALIBRATED: return "fp8 activation scales not calibrated";
     }
     return "unknown status";
 }
@@ -132,6 +135,7 @@ velo_status velo_create(const velo_config *cfg, velo_ctx **out) {
     if (!cfg) return VELO_ERR_INVALID_ARG;
     const velo_config &k = *cfg;
     if (!gnn_supported(k.gnn_hidden, k.precision)) return VELO_ERR_UNSUPPORTED;
+    if (k.training && !train_supported(k.gnn_hidden, k.precision)) return VELO_ERR_UNSUPPORTED;
     if (k.gnn_iters < 0 || k.gnn_iters > 16 || k.k_max < 1 || k.k_max > 64 || k.max_hits < 0 ||
         k.max_edges < 0 || k.max_events < 0 || k.max_event_hits < 0 || !(k.d2_max >= 0.f))
         return VELO_ERR_INVALID_ARG;
@@ -168,6 +172,23 @@ velo_status velo_create(const velo_config *cfg, velo_ctx **out) {
               dalloc(&w.m, N * 2 * H) && dalloc((char **)&w.e, E * H * sb) && dalloc(&w.n_edges, 1) &&
               dalloc(&w.flags, 1) &&
               dalloc(&w.eoff_tmp, B + 1);
+    if (ok && k.precision == VELO_FP8) {
+        const int ns = n_slots(k.gnn_iters);
+        ok = dalloc(&w.scales, 4 * ns) && dalloc(&w.amax, 2 * ns) && dalloc(&w.tmp_logit, E);
+        if (ok) {
+            std::vector<float> ones(4 * ns, 1.f);
+            ok = hipMemcpy(w.scales, ones.data(), sizeof(float) * 4 * ns, hipMemcpyHostToDevice) == hipSuccess;
+        }
+    }
+    if (ok && k.training) {
+        const int64_t it = k.gnn_iters, R = std::max<int64_t>(N, E);
+        ok = dalloc((char **)&w.ck_h, (it + 1) * N * H * sb) && dalloc((char **)&w.ck_e, (it + 1) * E * H * sb) &&
+             dalloc(&w.ck_m, std::max<int64_t>(it, 1) * N * 2 * H) && dalloc(&w.g_e[0], E * H) &&
+             dalloc(&w.g_e[1], E * H) && dalloc(&w.g_h[0], N * H) && dalloc(&w.g_h[1], N * H) &&
+             dalloc(&w.g_xs, E * H) && dalloc(&w.g_xd, E * H) && dalloc(&w.g_da, R * H) && dalloc(&w.g_r, R * H) &&
+             dalloc(&w.g_m, N * 2 * H) && dalloc(&w.g_part, (int64_t)train_part_floats(k.gnn_hidden)) &&
+             dalloc(&w.g_loss, 256);
+    }
     if (!ok) {
         hipGetLastError();
         free_ws(w);
@@ -209,18 +230,47 @@ velo_status velo_set_params(velo_ctx *c, const float *params, int64_t n, void *s
         hipSuccess)
         return fail(c, VELO_ERR_DEVICE, "parameter copy failed");
     c->params_set = true;
-    return VELO_OK;
+    if (c->cfg.precision == VELO_FP8) {
+        launch_weight_scales(c, (hipStream_t)stream);
+        c->calibrated = false;    // activation scales belong to the previous parameters
+    }
+    return device_status(c, "velo_set_params");
+}
+
+velo_status velo_calibrate(velo_ctx *c, const velo_hits *h, void *stream) {
+    if (!c) return VELO_ERR_INVALID_ARG;
+    if (c->cfg.precision != VELO_FP8) return fail(c, VELO_ERR_UNSUPPORTED, "calibration is for fp8 contexts");
+    velo_status st = check_hits(c, h);
+    if (st) return st;
+    DeviceGuard gd(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    Workspace &w = c->ws;
+    launch_fill((int *)w.amax, 0, 2 * n_slots(c->cfg.gnn_iters), s);
+    velo_outputs g{};
+    g.edge_offsets = w.eoff_tmp;
+    g.edge_capacity = c->cfg.max_edges;
+    launch_prepare(c, h, s);
+    launch_embed(c, h, w.emb, true, s);
+    launch_knn(c, h, w.emb, s);
+    launch_compact(c, h, &g, s);
+    launch_in_lists_plane(c, h, s);
+    launch_gnn(c, h, true, w.tmp_logit, c->params, false, true, s);
+    launch_act_scales(c, s);
+    c->calibrated = true;
+    return device_status(c, "velo_calibrate");
 }
 
 velo_status velo_embed(velo_ctx *c, const velo_hits *h, float *emb, void *stream) {
     if (!c) return VELO_ERR_INVALID_ARG;
+    if (c->cfg.precision == VELO_FP8 && !c->calibrated)
+        return fail(c, VELO_ERR_NOT_CALIBRATED, "fp8 context: call velo_calibrate first");
     velo_status st = check_hits(c, h);
     if (st) return st;
     if (h->n_hits > 0 && !emb) return fail(c, VELO_ERR_INVALID_ARG, "emb is NULL");
     DeviceGuard g(c->device);
     hipStream_t s = (hipStream_t)stream;
     { StageTimer t(c, VELO_STAGE_PREPARE, s); launch_prepare(c, h, s); }
-    { StageTimer t(c, VELO_STAGE_EMBED, s); launch_embed(c, h, emb, s); }
+    { StageTimer t(c, VELO_STAGE_EMBED, s); launch_embed(c, h, emb, false, s); }
     return device_status(c, "velo_embed");
 }
 
@@ -250,6 +300,8 @@ velo_status velo_build_graph(velo_ctx *c, const velo_hits *h, const float *emb, 
 
 velo_status velo_gnn(velo_ctx *c, const velo_hits *h, velo_outputs *g, void *stream) {
     if (!c) return VELO_ERR_INVALID_ARG;
+    if (c->cfg.precision == VELO_FP8 && !c->calibrated)
+        return fail(c, VELO_ERR_NOT_CALIBRATED, "fp8 context: call velo_calibrate first");
     velo_status st = check_hits(c, h);
     if (st) return st;
     if ((st = graph_args(c, h, g))) return st;
@@ -259,7 +311,7 @@ velo_status velo_gnn(velo_ctx *c, const velo_hits *h, velo_outputs *g, void *str
     { StageTimer t(c, VELO_STAGE_PREPARE, s); launch_prepare(c, h, s); }
     { StageTimer t(c, VELO_STAGE_COMPACT, s); launch_globalise(c, h, g, s); }
     { StageTimer t(c, VELO_STAGE_LISTS, s); launch_lists(c, h, g, true, s); }
-    launch_gnn(c, h, false, g->edge_logit, s);
+    launch_gnn(c, h, false, g->edge_logit, c->params, false, false, s);
     return device_status(c, "velo_gnn");
 }
 
@@ -280,6 +332,8 @@ velo_status velo_components(velo_ctx *c, const velo_hits *h, velo_outputs *g, vo
 
 velo_status velo_infer(velo_ctx *c, const velo_hits *h, velo_outputs *o, void *stream) {
     if (!c) return VELO_ERR_INVALID_ARG;
+    if (c->cfg.precision == VELO_FP8 && !c->calibrated)
+        return fail(c, VELO_ERR_NOT_CALIBRATED, "fp8 context: call velo_calibrate first");
     velo_status st = check_hits(c, h);
     if (st) return st;
     if ((st = graph_args(c, h, o))) return st;
@@ -288,11 +342,11 @@ velo_status velo_infer(velo_ctx *c, const velo_hits *h, velo_outputs *o, void *s
     DeviceGuard gd(c->device);
     hipStream_t s = (hipStream_t)stream;
     { StageTimer t(c, VELO_STAGE_PREPARE, s); launch_prepare(c, h, s); }
-    { StageTimer t(c, VELO_STAGE_EMBED, s); launch_embed(c, h, c->ws.emb, s); }
+    { StageTimer t(c, VELO_STAGE_EMBED, s); launch_embed(c, h, c->ws.emb, false, s); }
     { StageTimer t(c, VELO_STAGE_KNN, s); launch_knn(c, h, c->ws.emb, s); }
     { StageTimer t(c, VELO_STAGE_COMPACT, s); launch_compact(c, h, o, s); }
     { StageTimer t(c, VELO_STAGE_LISTS, s); launch_in_lists_plane(c, h, s); }
-    launch_gnn(c, h, true, o->edge_logit, s);
+    launch_gnn(c, h, true, o->edge_logit, c->params, false, false, s);
     { StageTimer t(c, VELO_STAGE_COMPONENTS, s); launch_components(c, h, o, s); }
     return device_status(c, "velo_infer");
 }
@@ -330,6 +384,112 @@ velo_status velo_read_timing(velo_ctx *c, double *ms, int64_t *launches) {
         c->stage_launches[k] = 0;
     }
     return VELO_OK;
+}
+
+}  // extern "C"
+
+struct velo_graph {
+    velo_ctx *ctx = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+extern "C" {
+
+velo_status velo_graph_capture(velo_ctx *c, const velo_hits *h, velo_outputs *o, void *stream, velo_graph **out) {
+    if (!c || !out) return VELO_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (c->timing) return fail(c, VELO_ERR_INVALID_ARG, "disable timing before capturing a graph");
+    if (!stream) return fail(c, VELO_ERR_INVALID_ARG, "the legacy default stream cannot be captured");
+    DeviceGuard gd(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    // one eager call first: argument checks, one-time kernel attributes and occupancy queries
+    velo_status st = velo_infer(c, h, o, stream);
+    if (st) return st;
+    if (hipStreamSynchronize(s) != hipSuccess) return fail(c, VELO_ERR_DEVICE, "stream synchronisation failed");
+    velo_graph *g = new (std::nothrow) velo_graph();
+    if (!g) return VELO_ERR_OOM;
+    g->ctx = c;
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        delete g;
+        return fail(c, VELO_ERR_DEVICE, "hipStreamBeginCapture failed");
+    }
+    st = velo_infer(c, h, o, stream);
+    const hipError_t e = hipStreamEndCapture(s, &g->graph);
+    if (st || e != hipSuccess || hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) != hipSuccess) {
+        if (g->graph) hipGraphDestroy(g->graph);
+        delete g;
+        hipGetLastError();
+        return st ? st : fail(c, VELO_ERR_DEVICE, "graph capture or instantiation failed");
+    }
+    *out = g;
+    return VELO_OK;
+}
+
+velo_status velo_graph_launch(velo_graph *g, void *stream) {
+    if (!g) return VELO_ERR_INVALID_ARG;
+    DeviceGuard gd(g->ctx->device);
+    if (hipGraphLaunch(g->exec, (hipStream_t)stream) != hipSuccess) return fail(g->ctx, VELO_ERR_DEVICE, "hipGraphLaunch failed");
+    return VELO_OK;
+}
+
+void velo_graph_destroy(velo_graph *g) {
+    if (!g) return;
+    DeviceGuard gd(g->ctx->device);
+    if (g->exec) hipGraphExecDestroy(g->exec);
+    if (g->graph) hipGraphDestroy(g->graph);
+    delete g;
+}
+
+velo_status velo_train_forward(velo_ctx *c, const velo_hits *h, velo_outputs *g, const float *params, void *stream) {
+    if (!c) return VELO_ERR_INVALID_ARG;
+    if (!c->cfg.training) return fail(c, VELO_ERR_UNSUPPORTED, "context created without training = 1");
+    velo_status st = check_hits(c, h);
+    if (st) return st;
+    if ((st = graph_args(c, h, g))) return st;
+    if (!params) return fail(c, VELO_ERR_INVALID_ARG, "params is NULL");
+    if (g->edge_capacity > 0 && !g->edge_logit) return fail(c, VELO_ERR_INVALID_ARG, "edge_logit is NULL");
+    DeviceGuard gd(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    { StageTimer t(c, VELO_STAGE_PREPARE, s); launch_prepare(c, h, s); }
+    { StageTimer t(c, VELO_STAGE_COMPACT, s); launch_globalise(c, h, g, s); }
+    { StageTimer t(c, VELO_STAGE_LISTS, s); launch_lists(c, h, g, true, s); }
+    launch_gnn(c, h, false, g->edge_logit, params, true, false, s);
+    c->train_ready = true;
+    return device_status(c, "velo_train_forward");
+}
+
+velo_status velo_bce(velo_ctx *c, const float *logit, const uint8_t *y, float pos_weight, int64_t n, float *loss,
+                     float *dlogit, void *stream) {
+    if (!c) return VELO_ERR_INVALID_ARG;
+    if (!c->cfg.training) return fail(c, VELO_ERR_UNSUPPORTED, "context created without training = 1");
+    if (n < 0 || !loss || (n > 0 && (!logit || !y || !dlogit))) return fail(c, VELO_ERR_INVALID_ARG, "velo_bce arguments");
+    DeviceGuard gd(c->device);
+    launch_bce(c, logit, y, pos_weight, n, loss, dlogit, (hipStream_t)stream);
+    return device_status(c, "velo_bce");
+}
+
+velo_status velo_train_backward(velo_ctx *c, const velo_hits *h, const float *params, const float *dlogit,
+                                float *dparams, void *stream) {
+    if (!c) return VELO_ERR_INVALID_ARG;
+    if (!c->cfg.training) return fail(c, VELO_ERR_UNSUPPORTED, "context created without training = 1");
+    if (!c->train_ready) return fail(c, VELO_ERR_INVALID_ARG, "velo_train_backward needs a velo_train_forward first");
+    velo_status st = check_hits(c, h);
+    if (st) return st;
+    if (!params || !dlogit || !dparams) return fail(c, VELO_ERR_INVALID_ARG, "params/dlogit/dparams is NULL");
+    DeviceGuard gd(c->device);
+    launch_gnn_backward(c, h, params, dlogit, dparams, (hipStream_t)stream);
+    return device_status(c, "velo_train_backward");
+}
+
+velo_status velo_adam_step(velo_ctx *c, float *params, const float *grad, float *m, float *v, int64_t n, float lr,
+                           float b1, float b2, float eps, int32_t step, void *stream) {
+    if (!c) return VELO_ERR_INVALID_ARG;
+    if (n < 0 || step < 1 || (n > 0 && (!params || !grad || !m || !v)))
+        return fail(c, VELO_ERR_INVALID_ARG, "velo_adam_step arguments");
+    DeviceGuard gd(c->device);
+    if (n > 0) launch_adam(params, grad, m, v, n, lr, b1, b2, eps, step, (hipStream_t)stream);
+    return device_status(c, "velo_adam_step");
 }
 
 velo_status velo_check(velo_ctx *c, void *stream) {

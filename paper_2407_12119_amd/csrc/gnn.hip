@@ -23,192 +23,36 @@
 //
 // Messages (the scatter_add of the message equation, Sec. 5.2) are fp32 sums
 // in a fixed order over per-hit incidence lists, in every precision.
-#include "internal.h"
+#include "mfma.h"
 
 namespace velo {
 
 namespace {
 
-typedef __bf16 bf16;
-typedef bf16 bf16x4 __attribute__((ext_vector_type(4)));
-typedef bf16 bf16x8 __attribute__((ext_vector_type(8)));
-
-__device__ inline f32x4 zero4() { return f32x4{0.f, 0.f, 0.f, 0.f}; }
-
-// ------------------------------------------------------------------------
-// precision traits
-// ------------------------------------------------------------------------
-struct F32 {
-    using state_t = float;       // hit/edge encodings in HBM
-    using frag_t = f32x4;        // per-lane B operand of one K block
-    using wfrag_t = f32x4;       // per-lane A operand of one (output block, K block)
-    static constexpr int KBLK = 16;
-    static constexpr int WJ = 4;
-    __device__ static int col(int kb, int g, int j) { return 16 * kb + 4 * g + j; }
-    __device__ static float wconv(float v) { return v; }
-    __device__ static frag_t load(const float *row, int kb, int g) { return *(const f32x4 *)(row + 16 * kb + 4 * g); }
-    __device__ static frag_t load_f32(const float *row, int kb, int g) { return load(row, kb, g); }
-    template <int MO>
-    __device__ static void mma(const wfrag_t *a, const frag_t &x, f32x4 *acc) {
-#pragma unroll
-        for (int i = 0; i < 4; i++)
-#pragma unroll
-            for (int mo = 0; mo < MO; mo++)
-                acc[mo] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mo][i], x[i], acc[mo], 0, 0, 0);
-    }
-    // accumulators of MO output blocks -> B fragments of the next layer (MO*16/KBLK of them)
-    template <int MO>
-    __device__ static void chain(const f32x4 *h, frag_t *x) {
-#pragma unroll
-        for (int kb = 0; kb < MO; kb++) x[kb] = h[kb];
-    }
-    // value of input channel 16 mo + 4 g + i of segment 0
-    __device__ static float seg0(const frag_t *x, int mo, int i) { return x[mo][i]; }
-    // stored offset of logical channels 16 mo + 4 g + (0..3)
-    __device__ static int stored(int mo, int g) { return 16 * mo + 4 * g; }
-    template <int MO>
-    __device__ static void store_all(float *row, int g, const f32x4 *o) {
-#pragma unroll
-        for (int mo = 0; mo < MO; mo++) *(f32x4 *)(row + 16 * mo + 4 * g) = o[mo];
-    }
-    __device__ static f32x4 load4(const float *p) { return *(const f32x4 *)p; }
-};
-
-struct BF16 {
-    using state_t = bf16;
-    using frag_t = bf16x8;
-    using wfrag_t = bf16x8;
-    static constexpr int KBLK = 32;
-    static constexpr int WJ = 8;
-    __device__ static int col(int kb, int g, int j) { return 32 * kb + (j < 4 ? 4 * g + j : 16 + 4 * g + j - 4); }
-    __device__ static bf16 wconv(float v) { return (bf16)v; }
-    __device__ static frag_t cat(bf16x4 lo, bf16x4 hi) {
-        return frag_t{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
-    }
-    __device__ static bf16x4 cvt(f32x4 v) { return bf16x4{(bf16)v[0], (bf16)v[1], (bf16)v[2], (bf16)v[3]}; }
-    // Encodings are stored with each 32-channel block permuted so that the 8
-    // channels a lane owns are contiguous: logical channel col(kb, g, j) sits
-    // at 32 kb + 8 g + j.  Every internal state row (hit and edge encodings,
-    // messages) uses this order; a lane moves its block with one 16-byte access.
-    __device__ static frag_t load(const bf16 *row, int kb, int g) { return *(const bf16x8 *)(row + 32 * kb + 8 * g); }
-    __device__ static frag_t load_f32(const float *row, int kb, int g) {
-        return cat(cvt(*(const f32x4 *)(row + 32 * kb + 8 * g)), cvt(*(const f32x4 *)(row + 32 * kb + 8 * g + 4)));
-    }
-    __device__ static int stored(int mo, int g) { return 32 * (mo >> 1) + 8 * g + 4 * (mo & 1); }
-    template <int MO>
-    __device__ static void store_all(bf16 *row, int g, const f32x4 *o) {
-#pragma unroll
-        for (int kb = 0; kb < MO / 2; kb++) *(bf16x8 *)(row + 32 * kb + 8 * g) = cat(cvt(o[2 * kb]), cvt(o[2 * kb + 1]));
-    }
-    template <int MO>
-    __device__ static void mma(const wfrag_t *a, const frag_t &x, f32x4 *acc) {
-#pragma unroll
-        for (int mo = 0; mo < MO; mo++) acc[mo] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mo], x, acc[mo], 0, 0, 0);
-    }
-    template <int MO>
-    __device__ static void chain(const f32x4 *h, frag_t *x) {
-#pragma unroll
-        for (int kb = 0; kb < MO / 2; kb++) x[kb] = cat(cvt(h[2 * kb]), cvt(h[2 * kb + 1]));
-    }
-    __device__ static float seg0(const frag_t *x, int mo, int i) { return (float)x[mo >> 1][4 * (mo & 1) + i]; }
-    __device__ static f32x4 load4(const bf16 *p) {
-        const bf16x4 v = *(const bf16x4 *)p;
-        return f32x4{(float)v[0], (float)v[1], (float)v[2], (float)v[3]};
-    }
-};
-
-// Stage a row-major [rows x K] float32 weight into LDS in fragment order:
-// entry (mo, kb, lane) holds W[16 mo + (lane & 15)][col(kb, lane >> 4, j)],
-// rows >= `rows` (padding up to 16*MO) are zero.
-template <class P>
-__device__ inline void stage(typename P::wfrag_t *dst, const float *__restrict__ W, int rows, int K, int MO) {
-    const int KBn = K / P::KBLK;
-    const int total = MO * KBn * 64;
-    for (int f = threadIdx.x; f < total; f += blockDim.x) {
-        const int lane = f & 63, mk = f >> 6, kb = mk % KBn, mo = mk / KBn;
-        const int row = 16 * mo + (lane & 15), g = lane >> 4;
-        typename P::wfrag_t v;
-#pragma unroll
-        for (int j = 0; j < P::WJ; j++) v[j] = P::wconv(row < rows ? W[(int64_t)row * K + P::col(kb, g, j)] : 0.f);
-        dst[f] = v;
-    }
-}
-
-template <class P>
-constexpr size_t frag_bytes(int rows_pad, int K) {
-    return (size_t)rows_pad * K * sizeof(typename P::wfrag_t) / P::WJ;
-}
-
-// acc[mo] += W[16 mo .., K] * X   (KB = K / KBLK blocks)
-template <class P, int MO, int KB>
-__device__ inline void gemm(const typename P::wfrag_t *sW, const typename P::frag_t *X, f32x4 *acc, int lane) {
-#pragma unroll
-    for (int kb = 0; kb < KB; kb++) {
-        // keep one K block of weight fragments live at a time
-        __builtin_amdgcn_sched_barrier(0);
-        typename P::wfrag_t a[MO];
-#pragma unroll
-        for (int mo = 0; mo < MO; mo++) a[mo] = sW[(mo * KB + kb) * 64 + lane];
-        P::template mma<MO>(a, X[kb], acc);
-    }
-}
-
-template <int MO>
-__device__ inline void load_bias(const float *__restrict__ b, f32x4 *rb, int g) {
-#pragma unroll
-    for (int mo = 0; mo < MO; mo++) rb[mo] = *(const f32x4 *)(b + 16 * mo + 4 * g);
-}
-
-template <int MO>
-__device__ inline void bias_relu(f32x4 *acc, const f32x4 *rb) {
-#pragma unroll
-    for (int mo = 0; mo < MO; mo++)
-#pragma unroll
-        for (int i = 0; i < 4; i++) acc[mo][i] = fmaxf(acc[mo][i] + rb[mo][i], 0.f);
-}
-
-template <int MO>
-__device__ inline void zero(f32x4 *acc) {
-#pragma unroll
-    for (int mo = 0; mo < MO; mo++) acc[mo] = zero4();
-}
-
-__device__ inline int wave_id() { return (blockIdx.x * blockDim.x + threadIdx.x) >> 6; }
-__device__ inline int n_waves() { return (gridDim.x * blockDim.x) >> 6; }
-
-// First layer with three inputs (K = 3) on the vector ALU, written in the
-// accumulator layout: h[mo][i] = relu(W[c] . u + b[c]), c = 16 mo + 4 g + i.
-// sW holds W [C x 3] followed by b [C].
-template <int MO>
-__device__ inline void first_layer3(const float *sW, int C, float u0, float u1, float u2, int g, f32x4 *h) {
-#pragma unroll
-    for (int mo = 0; mo < MO; mo++)
-#pragma unroll
-        for (int i = 0; i < 4; i++) {
-            const int c = 16 * mo + 4 * g + i;
-            h[mo][i] = fmaxf(sW[c * 3] * u0 + sW[c * 3 + 1] * u1 + sW[c * 3 + 2] * u2 + sW[C * 3 + c], 0.f);
-        }
-}
+using namespace mfma;
 
 // ------------------------------------------------------------------------
 // embedding MLP 3 -> 128 -> 128 -> 4 on normalised (r, phi, z)  (Sec. 5.1)
 // ------------------------------------------------------------------------
 constexpr int kCe = VELO_EMB_HIDDEN;
 
+// sc: the embedding's scales {s_x2, s_w2, s_x3, s_w3} (fp8, else null);
+// amax: its two layer inputs' calibration maxima (else null).
 template <class P>
 __global__ __launch_bounds__(512) void k_embed(int64_t n_hits, const float *__restrict__ x,
                                                const float *__restrict__ y, const float *__restrict__ z,
                                                const float *__restrict__ P_, int64_t o_w1, int64_t o_w2,
-                                               int64_t o_w3, float *__restrict__ emb,
-                                               const unsigned *__restrict__ flags) {
+                                               int64_t o_w3, float *__restrict__ emb, const float *__restrict__ sc,
+                                               float *__restrict__ amax, const unsigned *__restrict__ flags) {
     using W = typename P::wfrag_t;
     constexpr int MO = kCe / 16, KB = kCe / P::KBLK;
     extern __shared__ __align__(16) unsigned char lds_raw[];
     W *sW2 = (W *)lds_raw;
     W *sW3 = (W *)(lds_raw + frag_bytes<P>(kCe, kCe));
     float *sW1 = (float *)(lds_raw + frag_bytes<P>(kCe, kCe) + frag_bytes<P>(16, kCe));
-    stage<P>(sW2, P_ + o_w2, kCe, kCe, MO);
-    stage<P>(sW3, P_ + o_w3, VELO_EMB_DIM, kCe, 1);
+    const MlpScales S = read_scales(sc);
+    stage<P>(sW2, P_ + o_w2, kCe, kCe, MO, S.iw1);
+    stage<P>(sW3, P_ + o_w3, VELO_EMB_DIM, kCe, 1, S.iw2);
     for (int t = threadIdx.x; t < kCe * 4; t += blockDim.x) sW1[t] = P_[o_w1 + t];   // W1 then b1
     __syncthreads();
     if (*flags & kErrInput) return;
@@ -228,17 +72,21 @@ __global__ __launch_bounds__(512) void k_embed(int64_t n_hits, const float *__re
         const float u2 = (Z - mu2) / sg2;
         f32x4 h1[MO];
         first_layer3<MO>(sW1, kCe, u0, u1, u2, g, h1);
+        if (amax) record_amax(absmax4<MO>(h1), amax);
         typename P::frag_t x1[KB];
-        P::template chain<MO>(h1, x1);
+        P::template chain<MO>(h1, x1, S.ix1);
         f32x4 h2[MO];
         zero<MO>(h2);
         gemm<P, MO, KB>(sW2, x1, h2, lane);
+        if (P::kScaled) rescale<MO>(h2, S.d1);
         bias_relu<MO>(h2, rb2);
+        if (amax) record_amax(absmax4<MO>(h2), amax + 1);
         typename P::frag_t x2[KB];
-        P::template chain<MO>(h2, x2);
+        P::template chain<MO>(h2, x2, S.ix2);
         f32x4 o[1];
         zero<1>(o);
         gemm<P, 1, KB>(sW3, x2, o, lane);
+        if (P::kScaled) rescale<1>(o, S.d2);
         if (g == 0 && i < n_hits) {
             f32x4 r;
 #pragma unroll
@@ -249,20 +97,22 @@ __global__ __launch_bounds__(512) void k_embed(int64_t n_hits, const float *__re
 }
 
 // ------------------------------------------------------------------------
-// node encoder 3 -> H -> H on normalised (x, y, z)  (Sec. 5.2)
+// node encoder 3 -> H -> H on normalised (x, y, z)  (Sec. 5.2); the first
+// layer runs on the vector ALU, the second on MFMA (scales sc[2], sc[3]).
 // ------------------------------------------------------------------------
 template <class P, int H>
 __global__ __launch_bounds__(512) void k_node_enc(int64_t n_hits, const float *__restrict__ x,
                                                   const float *__restrict__ y, const float *__restrict__ z,
                                                   const float *__restrict__ P_, int64_t o_w1, int64_t o_w2,
-                                                  typename P::state_t *__restrict__ h,
-                                                  const unsigned *__restrict__ flags) {
+                                                  typename P::state_t *__restrict__ h, const float *__restrict__ sc,
+                                                  float *__restrict__ amax, const unsigned *__restrict__ flags) {
     using W = typename P::wfrag_t;
     constexpr int MO = H / 16, KB = H / P::KBLK;
     extern __shared__ __align__(16) unsigned char lds_raw[];
     W *sW2 = (W *)lds_raw;
     float *sW1 = (float *)(lds_raw + frag_bytes<P>(H, H));
-    stage<P>(sW2, P_ + o_w2, H, H, MO);
+    const MlpScales S = read_scales(sc);
+    stage<P>(sW2, P_ + o_w2, H, H, MO, S.iw2);
     for (int t = threadIdx.x; t < H * 4; t += blockDim.x) sW1[t] = P_[o_w1 + t];
     __syncthreads();
     if (*flags) return;
@@ -277,11 +127,13 @@ __global__ __launch_bounds__(512) void k_node_enc(int64_t n_hits, const float *_
         const float u0 = (x[ic] - mu0) / sg0, u1 = (y[ic] - mu1) / sg1, u2 = (z[ic] - mu2) / sg2;
         f32x4 h1[MO];
         first_layer3<MO>(sW1, H, u0, u1, u2, g, h1);
+        if (amax) record_amax(absmax4<MO>(h1), amax + 1);
         typename P::frag_t x1[KB];
-        P::template chain<MO>(h1, x1);
+        P::template chain<MO>(h1, x1, S.ix2);
         f32x4 o[MO];
         zero<MO>(o);
         gemm<P, MO, KB>(sW2, x1, o, lane);
+        if (P::kScaled) rescale<MO>(o, S.d2);
         if (i < n_hits) {
 #pragma unroll
             for (int mo = 0; mo < MO; mo++) o[mo] += rb2[mo];
@@ -312,6 +164,8 @@ struct MlpArgs {
     int64_t o_w1, o_w2;    // this MLP's layers
     int64_t o_c1, o_c2;    // classifier layers (CLS)
     float *logit;
+    const float *sc, *sc_cls;      // fp8 scales of this MLP and of the classifier (else null)
+    float *amax, *amax_cls;        // calibration maxima (else null)
     const unsigned *flags;
 };
 
@@ -326,15 +180,17 @@ constexpr size_t mlp_lds() {
 
 template <class P, int H>
 __device__ inline void classify(const typename P::wfrag_t *sC1, const float *__restrict__ Pw, int64_t o_c1,
-                                int64_t o_c2, const f32x4 *ev, int lane, bool ok, int64_t q,
-                                float *__restrict__ logit) {
+                                int64_t o_c2, const f32x4 *ev, const MlpScales &S, float *amax, int lane, bool ok,
+                                int64_t q, float *__restrict__ logit) {
     constexpr int MO = H / 16, KB = H / P::KBLK;
     const int g = lane >> 4;
+    if (amax) record_amax(absmax4<MO>(ev), amax);
     typename P::frag_t xe[KB];
-    P::template chain<MO>(ev, xe);
+    P::template chain<MO>(ev, xe, S.ix1);
     f32x4 hc[MO];
     zero<MO>(hc);
     gemm<P, MO, KB>(sC1, xe, hc, lane);
+    if (P::kScaled) rescale<MO>(hc, S.d1);
     f32x4 rb[MO], w2[MO];
     load_bias<MO>(Pw + o_c1 + H * H, rb, g);
     load_bias<MO>(Pw + o_c2, w2, g);
@@ -358,11 +214,12 @@ __global__ __launch_bounds__(512) void k_mlp(MlpArgs A) {
     W *sW1 = (W *)lds_raw;
     W *sW2 = (W *)(lds_raw + (NSEG ? frag_bytes<P>(H, K1) : 0));
     W *sC1 = (W *)(lds_raw + (NSEG ? frag_bytes<P>(H, K1) + frag_bytes<P>(H, H) : 0));
+    const MlpScales SC = read_scales(A.sc), SCc = read_scales(A.sc_cls);
     if (NSEG) {
-        stage<P>(sW1, A.P + A.o_w1, H, K1, MO);
-        stage<P>(sW2, A.P + A.o_w2, H, H, MO);
+        stage<P>(sW1, A.P + A.o_w1, H, K1, MO, SC.iw1);
+        stage<P>(sW2, A.P + A.o_w2, H, H, MO, SC.iw2);
     }
-    if (CLS) stage<P>(sC1, A.P + A.o_c1, H, H, MO);
+    if (CLS) stage<P>(sC1, A.P + A.o_c1, H, H, MO, SCc.iw1);
     __syncthreads();
     if (*A.flags) return;
 
@@ -377,6 +234,7 @@ __global__ __launch_bounds__(512) void k_mlp(MlpArgs A) {
     const S *sa = (const S *)A.a;
     const int64_t units = (N + 15) >> 4;
     constexpr int NX = NSEG > 0 ? NSEG * KB : KB;
+    const float ix = SC.ix1;
     // gather the inputs of unit u into X
     auto load_unit = [&](int64_t u, typename P::frag_t *X) {
         const int64_t q = u * 16 + n;
@@ -385,25 +243,25 @@ __global__ __launch_bounds__(512) void k_mlp(MlpArgs A) {
             const float *m = (const float *)A.b + qc * 2 * H;
 #pragma unroll
             for (int kb = 0; kb < KB; kb++) {
-                X[kb] = P::load(sa + qc * H, kb, g);
-                X[KB + kb] = P::load_f32(m, kb, g);
-                X[2 * KB + kb] = P::load_f32(m + H, kb, g);
+                X[kb] = P::load(sa + qc * H, kb, g, ix);
+                X[KB + kb] = P::load_f32(m, kb, g, ix);
+                X[2 * KB + kb] = P::load_f32(m + H, kb, g, ix);
             }
         } else if (MODE == EDGE) {
             const S *hb = (const S *)A.b;
             const int64_t s = A.src_g[qc], d = A.dst_g[qc];
 #pragma unroll
             for (int kb = 0; kb < KB; kb++) {
-                X[kb] = P::load(sa + qc * H, kb, g);
-                X[KB + kb] = P::load(hb + s * H, kb, g);
-                X[2 * KB + kb] = P::load(hb + d * H, kb, g);
+                X[kb] = P::load(sa + qc * H, kb, g, ix);
+                X[KB + kb] = P::load(hb + s * H, kb, g, ix);
+                X[2 * KB + kb] = P::load(hb + d * H, kb, g, ix);
             }
         } else if (MODE == EDGE_ENC) {
             const int64_t s = A.src_g[qc], d = A.dst_g[qc];
 #pragma unroll
             for (int kb = 0; kb < KB; kb++) {
-                X[kb] = P::load(sa + s * H, kb, g);
-                X[KB + kb] = P::load(sa + d * H, kb, g);
+                X[kb] = P::load(sa + s * H, kb, g, ix);
+                X[KB + kb] = P::load(sa + d * H, kb, g, ix);
             }
         }
     };
@@ -426,27 +284,41 @@ __global__ __launch_bounds__(512) void k_mlp(MlpArgs A) {
         }
         f32x4 o[MO];
         if (NSEG) {
+            if (A.amax) {
+                float mx = 0.f;
+#pragma unroll
+                for (int k = 0; k < NX; k++) mx = fmaxf(mx, P::absmax(X[k]));
+                record_amax(mx, A.amax);
+            }
             f32x4 hid[MO];
             zero<MO>(hid);
             gemm<P, MO, NSEG * KB>(sW1, X, hid, lane);
+            if (P::kScaled) rescale<MO>(hid, SC.d1);
             bias_relu<MO>(hid, rb1);
+            if (A.amax) record_amax(absmax4<MO>(hid), A.amax + 1);
             typename P::frag_t xh[KB];
-            P::template chain<MO>(hid, xh);
+            P::template chain<MO>(hid, xh, SC.ix2);
             zero<MO>(o);
             gemm<P, MO, KB>(sW2, xh, o, lane);
+            if (P::kScaled) rescale<MO>(o, SC.d2);
 #pragma unroll
             for (int mo = 0; mo < MO; mo++) {
                 o[mo] += rb2[mo];
-                if (MODE != EDGE_ENC)   // residual (Sec. 5.2)
+                if (MODE != EDGE_ENC) {   // residual (Sec. 5.2), from the unquantised state
+                    if constexpr (P::kScaled) {
+                        o[mo] += P::load4(sa + qc * H + P::stored(mo, g));
+                    } else {
 #pragma unroll
-                    for (int i = 0; i < 4; i++) o[mo][i] += P::seg0(X, mo, i);
+                        for (int i = 0; i < 4; i++) o[mo][i] += P::seg0(X, mo, i);
+                    }
+                }
             }
             if (ok && !(CLS && MODE == EDGE)) P::template store_all<MO>((S *)A.out + q * H, g, o);
         } else {
 #pragma unroll
             for (int mo = 0; mo < MO; mo++) o[mo] = P::load4(sa + qc * H + P::stored(mo, g));
         }
-        if (CLS) classify<P, H>(sC1, A.P, A.o_c1, A.o_c2, o, lane, ok, q, A.logit);
+        if (CLS) classify<P, H>(sC1, A.P, A.o_c1, A.o_c2, o, SCc, A.amax_cls, lane, ok, q, A.logit);
     }
 }
 
@@ -516,53 +388,64 @@ void run_mlp(velo_ctx *c, const MlpArgs &a, hipStream_t s) {
     k_mlp<P, H, MODE, CLS><<<persistent_grid(c, per_cu), kMlpBlock, lds, s>>>(a);
 }
 
+// The GNN forward pass.  Inference updates the edge state in place and fuses
+// the classifier into the last edge network; training (train = true) keeps
+// every step's hit and edge encodings and messages as checkpoints for the
+// backward pass (ck_h[k], ck_e[k], ck_m[k]) and reads the caller's parameters.
 template <class P, int H>
-void gnn_ph(velo_ctx *c, const velo_hits *hits, bool out_identity, float *logit, hipStream_t s) {
+void gnn_ph(velo_ctx *c, const velo_hits *hits, bool out_identity, float *logit, const float *Pw, bool train,
+            bool calib, hipStream_t s) {
     using S = typename P::state_t;
     Workspace &w = c->ws;
     const ParamLayout &L = c->layout;
-    const float *Pw = c->params;
     const int64_t N = hits->n_hits, Ecap = c->cfg.max_edges;
-    S *h[2] = {(S *)w.h[0], (S *)w.h[1]};
-    S *e = (S *)w.e;
+    const int64_t Nmax = c->cfg.max_hits;
+    const int iters = c->cfg.gnn_iters;
+    // per-MLP fp8 scales {s_x1, s_w1, s_x2, s_w2} and calibration maxima
+    auto sc = [&](int slot) -> const float * { return P::kScaled ? w.scales + 4 * slot : nullptr; };
+    auto am = [&](int slot) -> float * { return calib ? w.amax + 2 * slot : nullptr; };
+    const int s_nenc = kSlotNodeEnc, s_eenc = kSlotEdgeEnc, s_cls = slot_cls(iters);
+    auto hk = [&](int k) -> S * { return train ? (S *)w.ck_h + (int64_t)k * Nmax * H : (S *)w.h[k & 1]; };
+    auto ek = [&](int k) -> S * { return train ? (S *)w.ck_e + (int64_t)k * Ecap * H : (S *)w.e; };
+    auto mk = [&](int k) -> float * { return train ? w.ck_m + (int64_t)k * Nmax * 2 * H : w.m; };
     // the classifier is fused into the last edge network when its weights fit in LDS too
-    const bool fuse_cls = mlp_lds<P, H, EDGE, true>() <= c->lds_max;
+    const bool fuse_cls = !train && mlp_lds<P, H, EDGE, true>() <= c->lds_max;
     if (N > 0) {
         const size_t lds = frag_bytes<P>(H, H) + sizeof(float) * H * 4;
         static const int per_cu = blocks_per_cu(reinterpret_cast<const void *>(&k_node_enc<P, H>), kMlpBlock, lds);
         StageTimer t(c, VELO_STAGE_NODE_ENC, s);
-        k_node_enc<P, H><<<persistent_grid(c, per_cu), kMlpBlock, lds, s>>>(N, hits->x, hits->y, hits->z, Pw,
-                                                                      L.nenc[0].w, L.nenc[1].w, h[0], w.flags);
+        k_node_enc<P, H><<<persistent_grid(c, per_cu), kMlpBlock, lds, s>>>(
+            N, hits->x, hits->y, hits->z, Pw, L.nenc[0].w, L.nenc[1].w, hk(0), sc(s_nenc), am(s_nenc), w.flags);
     }
     MlpArgs a{};
     a.n_dev = w.n_edges; a.n_host = Ecap; a.src_g = w.src_g; a.dst_g = w.dst_g;
     a.P = Pw; a.flags = w.flags; a.logit = logit;
     a.o_c1 = L.cls[0].w; a.o_c2 = L.cls[1].w;
-    a.a = h[0]; a.out = e; a.o_w1 = L.eenc[0].w; a.o_w2 = L.eenc[1].w;
-    const int iters = c->cfg.gnn_iters;
+    a.a = hk(0); a.out = ek(0); a.o_w1 = L.eenc[0].w; a.o_w2 = L.eenc[1].w;
+    a.sc = sc(s_eenc); a.amax = am(s_eenc); a.sc_cls = sc(s_cls); a.amax_cls = am(s_cls);
     {
         StageTimer t(c, VELO_STAGE_EDGE_ENC, s);
         run_mlp<P, H, EDGE_ENC, false>(c, a, s);
     }
-    int cur = 0;
     const int *optr = out_identity ? w.row_ptr : w.out_ptr;
     const int *olist = out_identity ? nullptr : w.out_list;
     for (int k = 0; k < iters; k++) {
         if (N > 0) {
             StageTimer t(c, VELO_STAGE_MESSAGES, s);
-            k_messages<P, H><<<persistent_grid(c, 16), 256, 0, s>>>(N, optr, olist, w.in_ptr, w.in_list, e, w.m,
+            k_messages<P, H><<<persistent_grid(c, 16), 256, 0, s>>>(N, optr, olist, w.in_ptr, w.in_list, ek(k), mk(k),
                                                                   w.flags);
         }
         MlpArgs nd{};
-        nd.n_dev = nullptr; nd.n_host = N; nd.a = h[cur]; nd.b = w.m; nd.out = h[cur ^ 1];
+        nd.n_dev = nullptr; nd.n_host = N; nd.a = hk(k); nd.b = mk(k); nd.out = hk(k + 1);
         nd.P = Pw; nd.o_w1 = L.node[k][0].w; nd.o_w2 = L.node[k][1].w; nd.flags = w.flags;
+        nd.sc = sc(slot_node(k)); nd.amax = am(slot_node(k));
         if (N > 0) {
             StageTimer t(c, VELO_STAGE_NODE_NET, s);
             run_mlp<P, H, NODE, false>(c, nd, s);
         }
-        cur ^= 1;
         MlpArgs ed = a;
-        ed.a = e; ed.b = h[cur]; ed.out = e; ed.o_w1 = L.edge[k][0].w; ed.o_w2 = L.edge[k][1].w;
+        ed.a = ek(k); ed.b = hk(k + 1); ed.out = ek(k + 1); ed.o_w1 = L.edge[k][0].w; ed.o_w2 = L.edge[k][1].w;
+        ed.sc = sc(slot_edge(k)); ed.amax = am(slot_edge(k));
         const bool last = k == iters - 1;
         StageTimer t(c, last && fuse_cls ? VELO_STAGE_EDGE_CLS : VELO_STAGE_EDGE_NET, s);
         if (last && fuse_cls)
@@ -572,48 +455,131 @@ void gnn_ph(velo_ctx *c, const velo_hits *hits, bool out_identity, float *logit,
     }
     if (iters == 0 || !fuse_cls) {
         MlpArgs cl = a;
-        cl.a = e;
+        cl.a = ek(iters);
         StageTimer t(c, VELO_STAGE_EDGE_CLS, s);
         run_mlp<P, H, CLS_ONLY, true>(c, cl, s);
     }
 }
 
 template <class P>
-void embed_p(velo_ctx *c, const velo_hits *h, float *emb, hipStream_t s) {
+void embed_p(velo_ctx *c, const velo_hits *h, float *emb, bool calib, hipStream_t s) {
     const size_t lds = frag_bytes<P>(kCe, kCe) + frag_bytes<P>(16, kCe) + sizeof(float) * kCe * 4;
     static const int per_cu = blocks_per_cu(reinterpret_cast<const void *>(&k_embed<P>), kMlpBlock, lds);
     const ParamLayout &L = c->layout;
     k_embed<P><<<persistent_grid(c, per_cu), kMlpBlock, lds, s>>>(h->n_hits, h->x, h->y, h->z, c->params, L.emb[0].w,
-                                                             L.emb[1].w, L.emb[2].w, emb, c->ws.flags);
+                                                             L.emb[1].w, L.emb[2].w, emb,
+                                                             P::kScaled ? c->ws.scales + 4 * kSlotEmbed : nullptr,
+                                                             calib ? c->ws.amax + 2 * kSlotEmbed : nullptr,
+                                                             c->ws.flags);
 }
 
 }  // namespace
+
+namespace {
+
+constexpr float kE4M3Max = 448.f;   // largest finite OCP E4M3 value
+constexpr int kMaxWeightScales = 2 * (4 + 2 * 16);
+
+struct WeightScaleDesc {
+    int64_t off[kMaxWeightScales];
+    int cnt[kMaxWeightScales];
+    int dst[kMaxWeightScales];
+    int n;
+};
+
+// s_w = max |W| / 448 for every fp8 weight matrix (one block per matrix)
+__global__ __launch_bounds__(256) void k_weight_scales(const float *__restrict__ P, WeightScaleDesc d,
+                                                       float *__restrict__ scales) {
+    __shared__ float sh[256];
+    const int j = blockIdx.x;
+    if (j >= d.n) return;
+    float m = 0.f;
+    for (int i = threadIdx.x; i < d.cnt[j]; i += blockDim.x) m = fmaxf(m, fabsf(P[d.off[j] + i]));
+    sh[threadIdx.x] = m;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (threadIdx.x < k) sh[threadIdx.x] = fmaxf(sh[threadIdx.x], sh[threadIdx.x + k]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) scales[d.dst[j]] = sh[0] > 0.f ? sh[0] / kE4M3Max : 1.f;
+}
+
+// s_x = max |x| / 448 from the calibration maxima of every MLP input
+__global__ void k_act_scales(const float *__restrict__ amax, float *__restrict__ scales, int n_slots) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= n_slots) return;
+    for (int j = 0; j < 2; j++) {
+        const float a = amax[2 * m + j];
+        scales[4 * m + 2 * j] = a > 0.f ? a / kE4M3Max : 1.f;
+    }
+}
+
+}  // namespace
+
+void launch_weight_scales(velo_ctx *c, hipStream_t s) {
+    const ParamLayout &L = c->layout;
+    WeightScaleDesc d{};
+    auto add = [&](const Lin &l, int slot, int which) {
+        d.off[d.n] = l.w;
+        d.cnt[d.n] = l.out * l.in;
+        d.dst[d.n] = 4 * slot + (which == 1 ? 1 : 3);
+        d.n++;
+    };
+    add(L.emb[1], kSlotEmbed, 1);
+    add(L.emb[2], kSlotEmbed, 2);
+    add(L.nenc[1], kSlotNodeEnc, 2);
+    add(L.eenc[0], kSlotEdgeEnc, 1);
+    add(L.eenc[1], kSlotEdgeEnc, 2);
+    for (int k = 0; k < c->cfg.gnn_iters; k++) {
+        add(L.node[k][0], slot_node(k), 1);
+        add(L.node[k][1], slot_node(k), 2);
+        add(L.edge[k][0], slot_edge(k), 1);
+        add(L.edge[k][1], slot_edge(k), 2);
+    }
+    add(L.cls[0], slot_cls(c->cfg.gnn_iters), 1);
+    k_weight_scales<<<d.n, 256, 0, s>>>(c->params, d, c->ws.scales);
+}
+
+void launch_act_scales(velo_ctx *c, hipStream_t s) {
+    const int n = n_slots(c->cfg.gnn_iters);
+    k_act_scales<<<(n + 63) / 64, 64, 0, s>>>(c->ws.amax, c->ws.scales, n);
+}
 
 size_t state_bytes(int precision) { return precision == VELO_FP32 ? sizeof(float) : sizeof(uint16_t); }
 
 bool gnn_supported(int hidden, int precision) {
     if (precision == VELO_FP32) return hidden == 32 || hidden == 64;
-    if (precision == VELO_BF16) return hidden == 32 || hidden == 64 || hidden == 128;
+    if (precision == VELO_BF16 || precision == VELO_FP8) return hidden == 32 || hidden == 64 || hidden == 128;
     return false;
 }
 
-void launch_embed(velo_ctx *c, const velo_hits *h, float *emb, hipStream_t s) {
+// calib: run the bf16 kernels of an fp8 context and record every MLP input's
+// largest |value| (the activation scales are derived from them).
+void launch_embed(velo_ctx *c, const velo_hits *h, float *emb, bool calib, hipStream_t s) {
     if (h->n_hits <= 0) return;
-    if (c->cfg.precision == VELO_FP32)
-        embed_p<F32>(c, h, emb, s);
+    const int p = c->cfg.precision;
+    if (p == VELO_FP32)
+        embed_p<F32>(c, h, emb, false, s);
+    else if (p == VELO_BF16 || calib)
+        embed_p<BF16>(c, h, emb, calib, s);
     else
-        embed_p<BF16>(c, h, emb, s);
+        embed_p<FP8>(c, h, emb, false, s);
 }
 
-void launch_gnn(velo_ctx *c, const velo_hits *h, bool out_identity, float *logit, hipStream_t s) {
-    const int H = c->cfg.gnn_hidden;
-    if (c->cfg.precision == VELO_FP32) {
-        if (H == 32) gnn_ph<F32, 32>(c, h, out_identity, logit, s);
-        if (H == 64) gnn_ph<F32, 64>(c, h, out_identity, logit, s);
+void launch_gnn(velo_ctx *c, const velo_hits *h, bool out_identity, float *logit, const float *params, bool train,
+                bool calib, hipStream_t s) {
+    const int H = c->cfg.gnn_hidden, p = c->cfg.precision;
+    if (p == VELO_FP32) {
+        if (H == 32) gnn_ph<F32, 32>(c, h, out_identity, logit, params, train, false, s);
+        if (H == 64) gnn_ph<F32, 64>(c, h, out_identity, logit, params, train, false, s);
+    } else if (p == VELO_BF16 || calib) {
+        if (H == 32) gnn_ph<BF16, 32>(c, h, out_identity, logit, params, train, calib, s);
+        if (H == 64) gnn_ph<BF16, 64>(c, h, out_identity, logit, params, train, calib, s);
+        if (H == 128) gnn_ph<BF16, 128>(c, h, out_identity, logit, params, train, calib, s);
     } else {
-        if (H == 32) gnn_ph<BF16, 32>(c, h, out_identity, logit, s);
-        if (H == 64) gnn_ph<BF16, 64>(c, h, out_identity, logit, s);
-        if (H == 128) gnn_ph<BF16, 128>(c, h, out_identity, logit, s);
+        if (H == 32) gnn_ph<FP8, 32>(c, h, out_identity, logit, params, train, false, s);
+        if (H == 64) gnn_ph<FP8, 64>(c, h, out_identity, logit, params, train, false, s);
+        if (H == 128) gnn_ph<FP8, 128>(c, h, out_identity, logit, params, train, false, s);
     }
 }
 

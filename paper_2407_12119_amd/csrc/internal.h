@@ -52,6 +52,20 @@ struct Workspace {
     int *n_edges = nullptr;      // [1] internal edge count
     unsigned *flags = nullptr;   // [1] latched device errors
     int *eoff_tmp = nullptr;     // [max_events + 1]
+    float *scales = nullptr;     // [4 x n_slots] fp8 per-tensor scales
+    float *amax = nullptr;       // [2 x n_slots] calibration maxima of the MLP inputs
+    float *tmp_logit = nullptr;  // [max_edges] logits of the calibration pass (fp8 contexts)
+    // training (allocated when the config asks for it)
+    void *ck_h = nullptr;        // [(n+1) x max_hits x H] hit encodings h^0..h^n
+    void *ck_e = nullptr;        // [(n+1) x max_edges x H] edge encodings e^0..e^n
+    float *ck_m = nullptr;       // [n x max_hits x 2H] messages of every step
+    float *g_e[2] = {nullptr, nullptr};   // [max_edges x H] dL/de (ping-pong)
+    float *g_h[2] = {nullptr, nullptr};   // [max_hits x H] dL/dh (ping-pong)
+    float *g_xs = nullptr, *g_xd = nullptr;  // [max_edges x H] per-edge input gradients
+    float *g_da = nullptr, *g_r = nullptr;   // [max(E,N) x H] hidden gradient / activation
+    float *g_m = nullptr;        // [max_hits x 2H] dL/dm
+    float *g_part = nullptr;     // [n_chunks x part_len] weight-gradient partial sums
+    float *g_loss = nullptr;     // [n_chunks] loss partial sums
 };
 
 }  // namespace velo
@@ -69,6 +83,8 @@ struct velo_ctx {
     velo::ParamLayout layout;
     float *params = nullptr;     // float32 copy of the blob
     bool params_set = false;
+    bool train_ready = false;    // a velo_train_forward has filled the checkpoints
+    bool calibrated = false;     // fp8 activation scales are set
     velo::Workspace ws;
     std::string last_error;
     // per-stage timing
@@ -94,8 +110,31 @@ void launch_in_lists_plane(velo_ctx *c, const velo_hits *h, hipStream_t s);
 // ---- launchers (gnn.hip) ----
 size_t state_bytes(int precision);              // bytes per stored encoding element
 bool gnn_supported(int hidden, int precision);  // compiled (hidden, precision) pairs
-void launch_embed(velo_ctx *c, const velo_hits *h, float *emb, hipStream_t s);
-void launch_gnn(velo_ctx *c, const velo_hits *h, bool out_identity, float *logit, hipStream_t s);
+void launch_embed(velo_ctx *c, const velo_hits *h, float *emb, bool calib, hipStream_t s);
+void launch_gnn(velo_ctx *c, const velo_hits *h, bool out_identity, float *logit, const float *params, bool train,
+                bool calib, hipStream_t s);
+
+// fp8 scale table: one slot of four floats {s_x1, s_w1, s_x2, s_w2} per MLP
+// (inputs and weights of its two matrix layers) and two calibration maxima.
+constexpr int kSlotEmbed = 0;     // embedding layers 2 and 3
+constexpr int kSlotNodeEnc = 1;   // node encoder layer 2 (x2, w2)
+constexpr int kSlotEdgeEnc = 2;
+inline int slot_node(int k) { return 3 + 2 * k; }
+inline int slot_edge(int k) { return 4 + 2 * k; }
+inline int slot_cls(int iters) { return 3 + 2 * iters; }   // classifier layer 1 (x1, w1)
+inline int n_slots(int iters) { return 4 + 2 * iters; }
+void launch_weight_scales(velo_ctx *c, hipStream_t s);
+void launch_act_scales(velo_ctx *c, hipStream_t s);
+
+// ---- launchers (train.hip) ----
+bool train_supported(int hidden, int precision);
+size_t train_part_floats(int H);
+void launch_adam(float *p, const float *g, float *m, float *v, int64_t n, float lr, float b1, float b2, float eps,
+                 int step, hipStream_t s);
+void launch_bce(velo_ctx *c, const float *logit, const uint8_t *y, float pos_weight, int64_t n, float *loss,
+                float *dlogit, hipStream_t s);
+void launch_gnn_backward(velo_ctx *c, const velo_hits *h, const float *params, const float *dlogit, float *dparams,
+                         hipStream_t s);
 
 // ---- launchers (wcc.hip) ----
 void launch_components(velo_ctx *c, const velo_hits *h, const velo_outputs *g, hipStream_t s);

@@ -1,0 +1,573 @@
+// train.hip -- the training form of the GNN: weighted binary cross-entropy on
+// the edge logits and the reverse-mode pass through the classifier, the n
+// message-passing steps and the encoders (paper Sec. 5.2 defines the
+// forward; the paper trains with a sigmoid focal loss, here weighted BCE).
+//
+// Memory: the forward pass keeps only the step-boundary states h^k, e^k and
+// the messages m^k; every MLP's hidden activation is recomputed from them in
+// the backward kernel (one recompute per MLP, no stored activations).
+//
+// Per step k, in reverse:
+//   k_bwd<EDGE>   recompute a = W1 X + b1, r = relu(a) for X = [e^k, h^{k+1}_s,
+//                 h^{k+1}_d]; da = (W2^T dout) * [a > 0]; dX = W1^T da.
+//                 dL/de^k = dout + dX_e (residual); dX_s, dX_d per edge.
+//   k_gather_add  dL/dh^{k+1} += sum over out-edges of dX_s + over in-edges of
+//                 dX_d (the dual of the gather, in a fixed order).
+//   k_bwd<NODE>   the same for the node network; dL/dh^k, dL/dm^k.
+//   k_msg_bwd     dL/de^k += dL/dm_out[src] + dL/dm_in[dst] (the dual of the
+//                 message sums).
+//   k_dw          weight and bias gradients, dW = G^T Y summed over rows, on
+//                 MFMA with the row dimension as K, split over chunks of rows;
+//                 k_dw_reduce adds the chunk partials in a fixed order.
+// No floating-point atomics: gradients are bitwise reproducible.
+#include "mfma.h"
+
+namespace velo {
+
+namespace {
+
+using namespace mfma;
+using P = F32;
+
+enum BMode { B_EDGE = 0, B_NODE = 1, B_EDGE_ENC = 2, B_NODE_ENC = 3, B_CLS = 4 };
+
+constexpr int kBwdBlock = 256;
+constexpr int kChunks = 1024;       // row chunks of the weight-gradient reduction
+
+struct BwdArgs {
+    const int *n_dev;       // device row count (edges) or null
+    int64_t n_host;         // host row count (hits) or the edge capacity
+    const int *src_g, *dst_g;
+    const float *a;         // EDGE: e^k; NODE: h^k; EDGE_ENC: h^0; CLS: e^n
+    const float *b;         // EDGE: h^{k+1}; NODE: m^k
+    const float *dout;      // dL/d(output) rows [rows x H]; CLS: dL/dlogit [rows]
+    float *dres;            // EDGE, NODE: dout + dX(seg 0); CLS: dL/de^n
+    float *dx1, *dx2;       // EDGE, EDGE_ENC: dX of the src/dst hit segment [rows x H];
+                            // NODE: dL/dm [rows x 2H] (dx1 = out, dx2 = in part)
+    float *da, *r;          // hidden gradient and activation [rows x H]
+    const float *x, *y, *z; // hit coordinates (NODE_ENC)
+    const float *P;
+    int64_t o_w1, o_w2;
+    const unsigned *flags;
+};
+
+template <int MODE>
+constexpr int bseg() { return MODE == B_EDGE || MODE == B_NODE ? 3 : (MODE == B_EDGE_ENC ? 2 : 1); }
+
+__device__ inline int64_t row_count(const BwdArgs &A) {
+    return A.n_dev ? min((int64_t)*A.n_dev, A.n_host) : A.n_host;
+}
+
+// ------------------------------------------------------------------------
+// recompute + backward of one two-layer MLP over 16-row units
+// ------------------------------------------------------------------------
+template <int H, int MODE>
+__global__ __launch_bounds__(kBwdBlock) void k_bwd(BwdArgs A) {
+    constexpr int MO = H / 16, NSEG = bseg<MODE>(), K1 = NSEG * H;
+    constexpr bool CLS = MODE == B_CLS;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    f32x4 *sW1 = (f32x4 *)lds_raw;                                  // W1 [H x K1]
+    f32x4 *sW2T = sW1 + frag_bytes<P>(H, K1) / sizeof(f32x4);       // W2^T [H x H] (not CLS)
+    f32x4 *sW1T = sW2T + (CLS ? 0 : frag_bytes<P>(H, H) / sizeof(f32x4));   // W1^T [K1 x H]
+    stage<P>(sW1, A.P + A.o_w1, H, K1, MO);
+    if (!CLS) stage<P, true>(sW2T, A.P + A.o_w2, H, H, MO);
+    stage<P, true>(sW1T, A.P + A.o_w1, K1, H, K1 / 16);
+    __syncthreads();
+    if (*A.flags) return;
+    const int lane = threadIdx.x & 63, n = lane & 15, g = lane >> 4;
+    const int64_t N = row_count(A);
+    f32x4 rb1[MO], w2[MO];
+    load_bias<MO>(A.P + A.o_w1 + (int64_t)H * K1, rb1, g);
+    if (CLS) load_bias<MO>(A.P + A.o_w2, w2, g);     // classifier output weights (1 x H)
+    const int64_t units = (N + 15) >> 4;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t u = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; u < units; u += nw) {
+        const int64_t q = u * 16 + n;
+        const bool ok = q < N;
+        const int64_t qc = ok ? q : N - 1;
+        f32x4 X[NSEG * MO];
+        if (MODE == B_EDGE) {
+            const int64_t s = A.src_g[qc], d = A.dst_g[qc];
+#pragma unroll
+            for (int kb = 0; kb < MO; kb++) {
+                X[kb] = P::load(A.a + qc * H, kb, g);
+                X[MO + kb] = P::load(A.b + s * H, kb, g);
+                X[2 * MO + kb] = P::load(A.b + d * H, kb, g);
+            }
+        } else if (MODE == B_NODE) {
+#pragma unroll
+            for (int kb = 0; kb < MO; kb++) {
+                X[kb] = P::load(A.a + qc * H, kb, g);
+                X[MO + kb] = P::load(A.b + qc * 2 * H, kb, g);
+                X[2 * MO + kb] = P::load(A.b + qc * 2 * H + H, kb, g);
+            }
+        } else if (MODE == B_EDGE_ENC) {
+            const int64_t s = A.src_g[qc], d = A.dst_g[qc];
+#pragma unroll
+            for (int kb = 0; kb < MO; kb++) {
+                X[kb] = P::load(A.a + s * H, kb, g);
+                X[MO + kb] = P::load(A.a + d * H, kb, g);
+            }
+        } else {   // B_CLS
+#pragma unroll
+            for (int kb = 0; kb < MO; kb++) X[kb] = P::load(A.a + qc * H, kb, g);
+        }
+        // recompute the hidden layer
+        f32x4 r[MO];
+        zero<MO>(r);
+        gemm<P, MO, NSEG * MO>(sW1, X, r, lane);
+        bias_relu<MO>(r, rb1);
+        // dL/d(hidden) = W2^T dout, masked by the ReLU
+        f32x4 da[MO];
+        if (CLS) {
+            const float dz = ok ? A.dout[q] : 0.f;
+#pragma unroll
+            for (int mo = 0; mo < MO; mo++)
+#pragma unroll
+                for (int i = 0; i < 4; i++) da[mo][i] = r[mo][i] > 0.f ? w2[mo][i] * dz : 0.f;
+        } else {
+            f32x4 dO[MO];
+#pragma unroll
+            for (int kb = 0; kb < MO; kb++) dO[kb] = ok ? P::load(A.dout + q * H, kb, g) : zero4();
+            zero<MO>(da);
+            gemm<P, MO, MO>(sW2T, dO, da, lane);
+#pragma unroll
+            for (int mo = 0; mo < MO; mo++)
+#pragma unroll
+                for (int i = 0; i < 4; i++) da[mo][i] = r[mo][i] > 0.f ? da[mo][i] : 0.f;
+            // dX = W1^T da, then the per-segment outputs
+            f32x4 dX[NSEG * MO];
+            zero<NSEG * MO>(dX);
+            gemm<P, NSEG * MO, MO>(sW1T, da, dX, lane);
+            if (ok) {
+                if (MODE == B_EDGE || MODE == B_NODE) {
+                    // residual path: the output gradient reaches segment 0 unchanged
+#pragma unroll
+                    for (int mo = 0; mo < MO; mo++) dX[mo] += dO[mo];
+                    P::store_all<MO>(A.dres + q * H, g, dX);
+                }
+                if (MODE == B_EDGE) {
+                    P::store_all<MO>(A.dx1 + q * H, g, dX + MO);
+                    P::store_all<MO>(A.dx2 + q * H, g, dX + 2 * MO);
+                } else if (MODE == B_NODE) {
+                    P::store_all<MO>(A.dx1 + q * 2 * H, g, dX + MO);
+                    P::store_all<MO>(A.dx1 + q * 2 * H + H, g, dX + 2 * MO);
+                } else if (MODE == B_EDGE_ENC) {
+                    P::store_all<MO>(A.dx1 + q * H, g, dX);
+                    P::store_all<MO>(A.dx2 + q * H, g, dX + MO);
+                }
+            }
+        }
+        if (CLS) {
+            f32x4 dX[MO];
+            zero<MO>(dX);
+            gemm<P, MO, MO>(sW1T, da, dX, lane);
+            if (ok) P::store_all<MO>(A.dres + q * H, g, dX);
+        }
+        if (ok) {
+            P::store_all<MO>(A.da + q * H, g, da);
+            P::store_all<MO>(A.r + q * H, g, r);
+        }
+    }
+}
+
+// Node encoder backward: recompute the hidden layer on the VALU (K = 3) and
+// write dL/d(hidden) and the activation for the weight gradients.
+template <int H>
+__global__ __launch_bounds__(kBwdBlock) void k_bwd_node_enc(BwdArgs A) {
+    constexpr int MO = H / 16;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    f32x4 *sW2T = (f32x4 *)lds_raw;
+    float *sW1 = (float *)(lds_raw + frag_bytes<P>(H, H));
+    stage<P, true>(sW2T, A.P + A.o_w2, H, H, MO);
+    for (int t = threadIdx.x; t < H * 4; t += blockDim.x) sW1[t] = A.P[A.o_w1 + t];
+    __syncthreads();
+    if (*A.flags) return;
+    const int lane = threadIdx.x & 63, n = lane & 15, g = lane >> 4;
+    const int64_t N = A.n_host;
+    const float *Pn = A.P;
+    const float mu0 = Pn[6], mu1 = Pn[7], mu2 = Pn[8], sg0 = Pn[9], sg1 = Pn[10], sg2 = Pn[11];
+    const int64_t units = (N + 15) >> 4;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t u = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; u < units; u += nw) {
+        const int64_t q = u * 16 + n;
+        const bool ok = q < N;
+        const int64_t qc = ok ? q : N - 1;
+        const float u0 = (A.x[qc] - mu0) / sg0, u1 = (A.y[qc] - mu1) / sg1, u2 = (A.z[qc] - mu2) / sg2;
+        f32x4 r[MO];
+#pragma unroll
+        for (int mo = 0; mo < MO; mo++)
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                const int c = 16 * mo + 4 * g + i;
+                r[mo][i] = fmaxf(sW1[c * 3] * u0 + sW1[c * 3 + 1] * u1 + sW1[c * 3 + 2] * u2 + sW1[H * 3 + c], 0.f);
+            }
+        f32x4 dO[MO], da[MO];
+#pragma unroll
+        for (int kb = 0; kb < MO; kb++) dO[kb] = ok ? P::load(A.dout + q * H, kb, g) : zero4();
+        zero<MO>(da);
+        gemm<P, MO, MO>(sW2T, dO, da, lane);
+#pragma unroll
+        for (int mo = 0; mo < MO; mo++)
+#pragma unroll
+            for (int i = 0; i < 4; i++) da[mo][i] = r[mo][i] > 0.f ? da[mo][i] : 0.f;
+        if (ok) {
+            P::store_all<MO>(A.da + q * H, g, da);
+            P::store_all<MO>(A.r + q * H, g, r);
+        }
+    }
+}
+
+// ------------------------------------------------------------------------
+// weight gradients of one MLP:
+//   dW1 = sum_rows da (x) X,  db1 = sum da,  dW2 = sum dout (x) r,  db2 = sum dout
+// written as one blob-shaped partial [dW1 | db1 | dW2 | db2] per row chunk.
+// MFMA 16x16x4 with the row dimension as K: lane l supplies G[row][16 m + l%16]
+// and Y[row][16 nb + l%16] for row = base + l/16.  Wave w of the block owns the
+// output rows 16 w .. 16 w + 15.
+// ------------------------------------------------------------------------
+template <int H, int MODE>
+__global__ __launch_bounds__(kBwdBlock) void k_dw(BwdArgs A, float *__restrict__ part) {
+    constexpr int MO = H / 16;
+    constexpr int K1 = MODE == B_NODE_ENC ? 3 : bseg<MODE>() * H;
+    constexpr int NB1 = (K1 + 15) / 16;
+    constexpr int M2 = MODE == B_CLS ? 1 : H;
+    constexpr int PL = H * K1 + H + M2 * H + M2;
+    if (*A.flags) return;
+    const int lane = threadIdx.x & 63, n = lane & 15, g = lane >> 4, w = threadIdx.x >> 6;
+    const int64_t N = row_count(A);
+    const int64_t per = (((N + kChunks - 1) / kChunks) + 3) & ~(int64_t)3;
+    const int64_t r0 = (int64_t)blockIdx.x * per, r1 = min(r0 + per, N);
+    float *out = part + (int64_t)blockIdx.x * PL;
+    const bool active = w < MO;                        // waves beyond the output rows idle
+    const int m = active ? w : 0;
+    f32x4 acc1[NB1], acc2[MO];
+    zero<NB1>(acc1);
+    zero<MO>(acc2);
+    float sb1 = 0.f, sb2 = 0.f;
+    const float *Pn = A.P;
+    for (int64_t base = r0; active && base < r1; base += 4) {
+        const int64_t row = base + g;
+        const bool ok = row < r1;
+        const int64_t rc = ok ? row : (r1 > 0 ? r1 - 1 : 0);
+        const float ga = ok ? A.da[rc * H + 16 * m + n] : 0.f;
+        sb1 += ga;
+        // layer-1 inputs of this row
+        if (MODE == B_NODE_ENC) {
+            float v = 0.f;
+            if (n == 0) v = (A.x[rc] - Pn[6]) / Pn[9];
+            if (n == 1) v = (A.y[rc] - Pn[7]) / Pn[10];
+            if (n == 2) v = (A.z[rc] - Pn[8]) / Pn[11];
+            acc1[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(ga, v, acc1[0], 0, 0, 0);
+        } else {
+            const float *seg[3];
+            if (MODE == B_EDGE) {
+                seg[0] = A.a + rc * H;
+                seg[1] = A.b + (int64_t)A.src_g[rc] * H;
+                seg[2] = A.b + (int64_t)A.dst_g[rc] * H;
+            } else if (MODE == B_NODE) {
+                seg[0] = A.a + rc * H;
+                seg[1] = A.b + rc * 2 * H;
+                seg[2] = A.b + rc * 2 * H + H;
+            } else if (MODE == B_EDGE_ENC) {
+                seg[0] = A.a + (int64_t)A.src_g[rc] * H;
+                seg[1] = A.a + (int64_t)A.dst_g[rc] * H;
+                seg[2] = seg[1];
+            } else {
+                seg[0] = A.a + rc * H;
+                seg[1] = seg[2] = seg[0];
+            }
+#pragma unroll
+            for (int nb = 0; nb < NB1; nb++) {
+                const float y = seg[nb / MO][16 * (nb % MO) + n];
+                acc1[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ga, y, acc1[nb], 0, 0, 0);
+            }
+        }
+        // layer 2
+        float gd;
+        if (MODE == B_CLS)
+            gd = ok && m == 0 && n == 0 ? A.dout[rc] : 0.f;
+        else
+            gd = ok ? A.dout[rc * H + 16 * m + n] : 0.f;
+        sb2 += gd;
+        if (MODE != B_CLS || m == 0) {
+#pragma unroll
+            for (int nb = 0; nb < MO; nb++) {
+                const float y = ok ? A.r[rc * H + 16 * nb + n] : 0.f;
+                acc2[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(gd, y, acc2[nb], 0, 0, 0);
+            }
+        }
+    }
+    if (!active) return;
+    // reduce the bias sums over the 4 row groups of the wave
+    sb1 += __shfl_xor(sb1, 16);
+    sb1 += __shfl_xor(sb1, 32);
+    sb2 += __shfl_xor(sb2, 16);
+    sb2 += __shfl_xor(sb2, 32);
+#pragma unroll
+    for (int nb = 0; nb < NB1; nb++)
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            const int row = 16 * m + 4 * g + i, col = 16 * nb + n;
+            if (col < K1) out[row * K1 + col] = acc1[nb][i];
+        }
+    if (g == 0) out[H * K1 + 16 * m + n] = sb1;
+    float *o2 = out + H * K1 + H;
+    if (MODE == B_CLS) {
+        if (m == 0) {
+#pragma unroll
+            for (int nb = 0; nb < MO; nb++)
+                if (g == 0) o2[16 * nb + n] = acc2[nb][0];    // output row 0
+            if (lane == 0) o2[H] = sb2;
+        }
+    } else {
+#pragma unroll
+        for (int nb = 0; nb < MO; nb++)
+#pragma unroll
+            for (int i = 0; i < 4; i++) o2[(16 * m + 4 * g + i) * H + 16 * nb + n] = acc2[nb][i];
+        if (g == 0) o2[M2 * H + 16 * m + n] = sb2;
+    }
+}
+
+// Sum the chunk partials in chunk order into the blob-shaped gradient.
+__global__ void k_dw_reduce(const float *__restrict__ part, int PL, float *__restrict__ grad,
+                            const unsigned *__restrict__ flags) {
+    if (*flags) return;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < PL; i += gridDim.x * blockDim.x) {
+        float s = 0.f;
+        for (int c = 0; c < kChunks; c++) s += part[(int64_t)c * PL + i];
+        grad[i] = s;
+    }
+}
+
+// ------------------------------------------------------------------------
+// duals of the gathers and of the message sums
+// ------------------------------------------------------------------------
+// dh[l] (+)= sum_{l -> j} xs[edge] + sum_{i -> l} xd[edge]; H/4 lanes per hit.
+template <int H>
+__global__ __launch_bounds__(256) void k_gather_add(int64_t n_hits, const int *__restrict__ out_ptr,
+                                                    const int *__restrict__ out_list, const int *__restrict__ in_ptr,
+                                                    const int *__restrict__ in_list, const float *__restrict__ xs,
+                                                    const float *__restrict__ xd, float *__restrict__ dh,
+                                                    bool accumulate, const unsigned *__restrict__ flags) {
+    if (*flags) return;
+    constexpr int LPN = H / 4, NPW = 64 / LPN;
+    const int lane = threadIdx.x & 63, sub = lane / LPN, c = 4 * (lane % LPN);
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t base = (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6) * NPW; base < n_hits; base += nw * NPW) {
+        const int64_t i = base + sub;
+        if (i >= n_hits) continue;
+        f32x4 sum = accumulate ? *(const f32x4 *)(dh + i * H + c) : zero4();
+        for (int a = out_ptr[i]; a < out_ptr[i + 1]; a++) sum += *(const f32x4 *)(xs + (int64_t)out_list[a] * H + c);
+        for (int b = in_ptr[i]; b < in_ptr[i + 1]; b++) sum += *(const f32x4 *)(xd + (int64_t)in_list[b] * H + c);
+        *(f32x4 *)(dh + i * H + c) = sum;
+    }
+}
+
+// de[q] += dm[src q][0:H] + dm[dst q][H:2H]
+template <int H>
+__global__ __launch_bounds__(256) void k_msg_bwd(const int *__restrict__ n_edges, int64_t cap,
+                                                 const int *__restrict__ src_g, const int *__restrict__ dst_g,
+                                                 const float *__restrict__ dm, float *__restrict__ de,
+                                                 const unsigned *__restrict__ flags) {
+    if (*flags) return;
+    constexpr int LPN = H / 4;
+    const int64_t E = min((int64_t)*n_edges, cap);
+    const int64_t total = E * LPN;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t q = t / LPN;
+        const int c = 4 * (int)(t - q * LPN);
+        f32x4 v = *(const f32x4 *)(de + q * H + c);
+        v += *(const f32x4 *)(dm + (int64_t)src_g[q] * 2 * H + c);
+        v += *(const f32x4 *)(dm + (int64_t)dst_g[q] * 2 * H + H + c);
+        *(f32x4 *)(de + q * H + c) = v;
+    }
+}
+
+__global__ void k_zero(float *__restrict__ p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0.f;
+}
+
+// ------------------------------------------------------------------------
+// weighted binary cross-entropy:  L = (1/E) sum w_y [softplus(z) - y z],
+// w_1 = pos_weight, w_0 = 1;  dL/dz = w_y (sigmoid(z) - y) / E
+// ------------------------------------------------------------------------
+constexpr int kLossBlocks = 256;
+
+__global__ __launch_bounds__(256) void k_bce(const float *__restrict__ z, const uint8_t *__restrict__ y, float pw,
+                                             int64_t n, float *__restrict__ dz, float *__restrict__ part) {
+    __shared__ float sh[256];
+    float acc = 0.f;
+    const float inv = n > 0 ? 1.f / (float)n : 0.f;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float v = z[i];
+        const bool pos = y[i] != 0;
+        const float w = pos ? pw : 1.f;
+        const float sp = v > 0.f ? v + log1pf(expf(-v)) : log1pf(expf(v));
+        // sigmoid(t) without cancellation; sigmoid(z) - 1 = -sigmoid(-z)
+        const float t = pos ? -v : v;
+        const float sg = t >= 0.f ? 1.f / (1.f + expf(-t)) : expf(t) / (1.f + expf(t));
+        acc += w * (sp - (pos ? v : 0.f));
+        dz[i] = w * (pos ? -sg : sg) * inv;
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int d = 128; d > 0; d >>= 1) {
+        if (threadIdx.x < d) sh[threadIdx.x] += sh[threadIdx.x + d];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ void k_bce_total(const float *__restrict__ part, int64_t n, float *__restrict__ loss) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        float s = 0.f;
+        for (int b = 0; b < kLossBlocks; b++) s += part[b];
+        *loss = n > 0 ? s / (float)n : 0.f;
+    }
+}
+
+inline int blocks_for(int64_t n, int block, int cap) {
+    int64_t b = (n + block - 1) / block;
+    return (int)(b < 1 ? 1 : (b > cap ? cap : b));
+}
+
+template <int H, int MODE>
+void run_bwd(velo_ctx *c, const BwdArgs &a, hipStream_t s) {
+    constexpr int NSEG = bseg<MODE>(), K1 = NSEG * H;
+    constexpr bool CLS = MODE == B_CLS;
+    constexpr size_t lds = frag_bytes<P>(H, K1) + (CLS ? 0 : frag_bytes<P>(H, H)) + frag_bytes<P>(K1, H);
+    static const int per_cu = [] {
+        hipFuncSetAttribute(reinterpret_cast<const void *>(&k_bwd<H, MODE>), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds);
+        int n = 0;
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void *>(&k_bwd<H, MODE>), kBwdBlock, lds);
+        return n < 1 ? 1 : n;
+    }();
+    k_bwd<H, MODE><<<persistent_grid(c, per_cu), kBwdBlock, lds, s>>>(a);
+}
+
+template <int H, int MODE>
+void run_dw(velo_ctx *c, const BwdArgs &a, float *grad_dst, hipStream_t s) {
+    constexpr int K1 = MODE == B_NODE_ENC ? 3 : bseg<MODE>() * H;
+    constexpr int M2 = MODE == B_CLS ? 1 : H;
+    constexpr int PL = H * K1 + H + M2 * H + M2;
+    k_dw<H, MODE><<<kChunks, kBwdBlock, 0, s>>>(a, c->ws.g_part);
+    k_dw_reduce<<<blocks_for(PL, 256, 1024), 256, 0, s>>>(c->ws.g_part, PL, grad_dst, c->ws.flags);
+}
+
+template <int H>
+void backward_h(velo_ctx *c, const velo_hits *hits, const float *Pw, const float *dlogit, float *dparams,
+                hipStream_t s) {
+    Workspace &w = c->ws;
+    const ParamLayout &L = c->layout;
+    const int64_t N = hits->n_hits, Ecap = c->cfg.max_edges, Nmax = c->cfg.max_hits;
+    const int n = c->cfg.gnn_iters;
+    const float *ck_h = (const float *)w.ck_h, *ck_e = (const float *)w.ck_e;
+    auto hk = [&](int k) { return ck_h + (int64_t)k * Nmax * H; };
+    auto ek = [&](int k) { return ck_e + (int64_t)k * Ecap * H; };
+    const int eb = persistent_grid(c, 8);
+    // parameters without gradient (normalisation, embedding) are zero
+    k_zero<<<blocks_for(L.nenc[0].w, 256, 1024), 256, 0, s>>>(dparams, L.nenc[0].w);
+
+    BwdArgs base{};
+    base.src_g = w.src_g; base.dst_g = w.dst_g; base.P = Pw; base.flags = w.flags;
+    base.da = w.g_da; base.r = w.g_r;
+    // classifier: dL/de^n
+    BwdArgs cl = base;
+    cl.n_dev = w.n_edges; cl.n_host = Ecap; cl.a = ek(n); cl.dout = dlogit; cl.dres = w.g_e[0];
+    cl.o_w1 = L.cls[0].w; cl.o_w2 = L.cls[1].w;
+    run_bwd<H, B_CLS>(c, cl, s);
+    run_dw<H, B_CLS>(c, cl, dparams + L.cls[0].w, s);
+    int ce = 0, ch = 0;
+    if (N > 0) k_zero<<<blocks_for(N * H, 256, 4096), 256, 0, s>>>(w.g_h[0], N * H);
+    for (int k = n - 1; k >= 0; k--) {
+        // edge network k
+        BwdArgs ed = base;
+        ed.n_dev = w.n_edges; ed.n_host = Ecap; ed.a = ek(k); ed.b = hk(k + 1);
+        ed.dout = w.g_e[ce]; ed.dres = w.g_e[ce ^ 1]; ed.dx1 = w.g_xs; ed.dx2 = w.g_xd;
+        ed.o_w1 = L.edge[k][0].w; ed.o_w2 = L.edge[k][1].w;
+        run_bwd<H, B_EDGE>(c, ed, s);
+        run_dw<H, B_EDGE>(c, ed, dparams + L.edge[k][0].w, s);
+        if (N > 0)
+            k_gather_add<H><<<persistent_grid(c, 16), 256, 0, s>>>(N, w.out_ptr, w.out_list, w.in_ptr, w.in_list,
+                                                                 w.g_xs, w.g_xd, w.g_h[ch], true, w.flags);
+        ce ^= 1;
+        // node network k
+        BwdArgs nd = base;
+        nd.n_dev = nullptr; nd.n_host = N; nd.a = hk(k); nd.b = w.ck_m + (int64_t)k * Nmax * 2 * H;
+        nd.dout = w.g_h[ch]; nd.dres = w.g_h[ch ^ 1]; nd.dx1 = w.g_m;
+        nd.o_w1 = L.node[k][0].w; nd.o_w2 = L.node[k][1].w;
+        if (N > 0) {
+            run_bwd<H, B_NODE>(c, nd, s);
+            run_dw<H, B_NODE>(c, nd, dparams + L.node[k][0].w, s);
+        } else {
+            run_dw<H, B_NODE>(c, nd, dparams + L.node[k][0].w, s);
+        }
+        ch ^= 1;
+        // message sums of step k
+        if (N > 0)
+            k_msg_bwd<H><<<eb, 256, 0, s>>>(w.n_edges, Ecap, w.src_g, w.dst_g, w.g_m, w.g_e[ce], w.flags);
+    }
+    // edge encoder
+    BwdArgs ee = base;
+    ee.n_dev = w.n_edges; ee.n_host = Ecap; ee.a = hk(0); ee.dout = w.g_e[ce]; ee.dx1 = w.g_xs; ee.dx2 = w.g_xd;
+    ee.o_w1 = L.eenc[0].w; ee.o_w2 = L.eenc[1].w;
+    run_bwd<H, B_EDGE_ENC>(c, ee, s);
+    run_dw<H, B_EDGE_ENC>(c, ee, dparams + L.eenc[0].w, s);
+    if (N > 0)
+        k_gather_add<H><<<persistent_grid(c, 16), 256, 0, s>>>(N, w.out_ptr, w.out_list, w.in_ptr, w.in_list, w.g_xs,
+                                                             w.g_xd, w.g_h[ch], true, w.flags);
+    // node encoder
+    BwdArgs ne = base;
+    ne.n_dev = nullptr; ne.n_host = N; ne.dout = w.g_h[ch]; ne.x = hits->x; ne.y = hits->y; ne.z = hits->z;
+    ne.o_w1 = L.nenc[0].w; ne.o_w2 = L.nenc[1].w;
+    if (N > 0) {
+        constexpr size_t lds = frag_bytes<P>(H, H) + sizeof(float) * H * 4;
+        k_bwd_node_enc<H><<<persistent_grid(c, 2), kBwdBlock, lds, s>>>(ne);
+    }
+    run_dw<H, B_NODE_ENC>(c, ne, dparams + L.nenc[0].w, s);
+}
+
+// Adam with bias correction (one float32 parameter per thread).
+__global__ void k_adam(float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m,
+                       float *__restrict__ v, int64_t n, float lr, float b1, float b2, float eps, float c1, float c2) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float gi = g[i];
+        const float mi = b1 * m[i] + (1.f - b1) * gi;
+        const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    }
+}
+
+}  // namespace
+
+void launch_adam(float *p, const float *g, float *m, float *v, int64_t n, float lr, float b1, float b2, float eps,
+                 int step, hipStream_t s) {
+    const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
+    k_adam<<<blocks_for(n, 256, 4096), 256, 0, s>>>(p, g, m, v, n, lr, b1, b2, eps, c1, c2);
+}
+
+bool train_supported(int hidden, int precision) { return precision == VELO_FP32 && (hidden == 32 || hidden == 64); }
+
+size_t train_part_floats(int H) {
+    // the largest blob-shaped partial: an edge or node network, [H x 3H | H | H x H | H]
+    return (size_t)kChunks * (3 * H * H + H + H * H + H);
+}
+
+void launch_bce(velo_ctx *c, const float *logit, const uint8_t *y, float pos_weight, int64_t n, float *loss,
+                float *dlogit, hipStream_t s) {
+    k_bce<<<kLossBlocks, 256, 0, s>>>(logit, y, pos_weight, n, dlogit, c->ws.g_loss);
+    k_bce_total<<<1, 64, 0, s>>>(c->ws.g_loss, n, loss);
+}
+
+void launch_gnn_backward(velo_ctx *c, const velo_hits *h, const float *params, const float *dlogit, float *dparams,
+                         hipStream_t s) {
+    if (c->cfg.gnn_hidden == 32) backward_h<32>(c, h, params, dlogit, dparams, s);
+    if (c->cfg.gnn_hidden == 64) backward_h<64>(c, h, params, dlogit, dparams, s);
+}
+
+}  // namespace velo

@@ -325,3 +325,9 @@ def centred_params(wl: Workload) -> np.ndarray:
     with open(_CENTRED_JSON) as f:
         tab = json.load(f)
     return with_classifier_bias(init_params(wl), wl.hidden, wl.iters, tab[wl.name]["centred_bias"])
+
+
+def calibration_batch(wl: Workload, n_events: int = 16) -> Batch:
+    """Seeded calibration events (fp8 activation scales), drawn with the
+    workload's recipe from a seed stream of their own."""
+    return to_batch([make_event(wl.recipe, _rng(998, i)) for i in range(n_events)])

@@ -17,14 +17,16 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libvelognn.so")
 
 VELO_OK, VELO_ERR_INVALID_ARG, VELO_ERR_CAPACITY, VELO_ERR_OOM = 0, 1, 2, 3
-VELO_ERR_DEVICE, VELO_ERR_UNSUPPORTED, VELO_ERR_INPUT = 4, 5, 6
+VELO_ERR_DEVICE, VELO_ERR_UNSUPPORTED, VELO_ERR_INPUT, VELO_ERR_NOT_CALIBRATED = 4, 5, 6, 7
 VELO_FP32, VELO_BF16, VELO_FP8 = 0, 1, 2
 PRECISIONS = {"fp32": VELO_FP32, "bf16": VELO_BF16, "fp8": VELO_FP8}
 N_PLANES, EMB_HIDDEN, EMB_DIM = 26, 128, 4
 
 EXPORTS = ("velo_param_count", "velo_create", "velo_destroy", "velo_set_params", "velo_infer",
            "velo_embed", "velo_build_graph", "velo_gnn", "velo_components", "velo_check",
-           "velo_status_str", "velo_last_error", "velo_set_timing", "velo_read_timing")
+           "velo_status_str", "velo_last_error", "velo_set_timing", "velo_read_timing",
+           "velo_train_forward", "velo_bce", "velo_train_backward", "velo_adam_step",
+           "velo_graph_capture", "velo_graph_launch", "velo_graph_destroy", "velo_calibrate")
 STAGES = ("prepare", "embed", "knn", "compact", "lists", "node_enc", "edge_enc", "messages",
           "node_net", "edge_net", "edge_cls", "components")
 
@@ -39,7 +41,7 @@ class _Config(C.Structure):
     _fields_ = [("gnn_hidden", C.c_int32), ("gnn_iters", C.c_int32), ("d2_max", C.c_float),
                 ("k_max", C.c_int32), ("edge_logit_min", C.c_float), ("precision", C.c_int32),
                 ("max_hits", C.c_int64), ("max_edges", C.c_int64), ("max_events", C.c_int32),
-                ("max_event_hits", C.c_int32)]
+                ("max_event_hits", C.c_int32), ("training", C.c_int32)]
 
 
 class _Hits(C.Structure):
@@ -89,6 +91,23 @@ def lib() -> C.CDLL:
         L.velo_set_timing.restype = st
         L.velo_read_timing.argtypes = [vp, vp, vp]
         L.velo_read_timing.restype = st
+        L.velo_train_forward.argtypes = [vp, C.POINTER(_Hits), C.POINTER(_Outputs), vp, vp]
+        L.velo_train_forward.restype = st
+        L.velo_bce.argtypes = [vp, vp, vp, C.c_float, C.c_int64, vp, vp, vp]
+        L.velo_bce.restype = st
+        L.velo_train_backward.argtypes = [vp, C.POINTER(_Hits), vp, vp, vp, vp]
+        L.velo_train_backward.restype = st
+        L.velo_adam_step.argtypes = [vp, vp, vp, vp, vp, C.c_int64, C.c_float, C.c_float, C.c_float, C.c_float,
+                                     C.c_int32, vp]
+        L.velo_adam_step.restype = st
+        L.velo_graph_capture.argtypes = [vp, C.POINTER(_Hits), C.POINTER(_Outputs), vp, C.POINTER(vp)]
+        L.velo_graph_capture.restype = st
+        L.velo_graph_launch.argtypes = [vp, vp]
+        L.velo_graph_launch.restype = st
+        L.velo_graph_destroy.argtypes = [vp]
+        L.velo_graph_destroy.restype = None
+        L.velo_calibrate.argtypes = [vp, C.POINTER(_Hits), vp]
+        L.velo_calibrate.restype = st
         _lib = L
     return _lib
 
@@ -136,13 +155,15 @@ class Context:
 
     def __init__(self, hidden: int, iters: int, d2_max: float, k_max: int = 32,
                  edge_logit_min: float = 0.0, precision: str = "fp32", max_hits: int = 1 << 20,
-                 max_edges: Optional[int] = None, max_events: int = 1024, max_event_hits: int = 16384):
+                 max_edges: Optional[int] = None, max_events: int = 1024, max_event_hits: int = 16384,
+                 training: bool = False):
         self._lib = lib()
         self.hidden, self.iters, self.k_max = hidden, iters, k_max
         if max_edges is None:
             max_edges = max(1, k_max * max_hits)
         self.cfg = _Config(hidden, iters, float(np.float32(d2_max)), k_max, float(edge_logit_min),
-                           PRECISIONS[precision], max_hits, max_edges, max_events, max_event_hits)
+                           PRECISIONS[precision], max_hits, max_edges, max_events, max_event_hits,
+                           1 if training else 0)
         h = C.c_void_p()
         st = self._lib.velo_create(C.byref(self.cfg), C.byref(h))
         if st != VELO_OK:
@@ -181,6 +202,13 @@ class Context:
         n = np.zeros(len(STAGES), np.int64)
         self._raise(self._lib.velo_read_timing(self._h, ms.ctypes.data, n.ctypes.data), "velo_read_timing")
         return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(STAGES)}
+
+    def calibrate(self, hits: DeviceHits, check: bool = True):
+        """fp8: set the activation scales from a calibration batch."""
+        hc = hits.c()
+        self._raise(self._lib.velo_calibrate(self._h, C.byref(hc), _stream()), "velo_calibrate")
+        if check:
+            self.check()
 
     def check(self):
         self._raise(self._lib.velo_check(self._h, _stream()), "velo_check")
@@ -250,6 +278,75 @@ class Context:
         if check:
             self.check()
         return graph
+
+
+    # ---- graph capture ----
+    def capture(self, hits: DeviceHits, out) -> "Graph":
+        """Capture velo_infer on (hits, out) into a replayable HIP graph."""
+        oc = self._out_c(out)
+        hc = hits.c()
+        g = C.c_void_p()
+        self._raise(self._lib.velo_graph_capture(self._h, C.byref(hc), C.byref(oc), _stream(), C.byref(g)),
+                    "velo_graph_capture")
+        return Graph(self, g, hits, out)
+
+    # ---- training form ----
+    def train_forward(self, hits: DeviceHits, graph, params, check: bool = False):
+        """Logits of `graph` under the float32 blob `params` (device); keeps checkpoints."""
+        oc = self._out_c(graph)
+        hc = hits.c()
+        self._raise(self._lib.velo_train_forward(self._h, C.byref(hc), C.byref(oc), C.c_void_p(params.data_ptr()),
+                                                 _stream()), "velo_train_forward")
+        if check:
+            self.check()
+        return graph
+
+    def bce(self, logit, y, pos_weight: float, n: int):
+        """(loss [1], dlogit [n]) device tensors of the weighted BCE on the first n logits."""
+        import torch
+        loss = torch.empty(1, dtype=torch.float32, device=logit.device)
+        dz = torch.empty(max(n, 1), dtype=torch.float32, device=logit.device)
+        self._raise(self._lib.velo_bce(self._h, C.c_void_p(logit.data_ptr()), C.c_void_p(y.data_ptr()),
+                                       float(pos_weight), n, C.c_void_p(loss.data_ptr()), C.c_void_p(dz.data_ptr()),
+                                       _stream()), "velo_bce")
+        return loss, dz
+
+    def train_backward(self, hits: DeviceHits, params, dlogit, dparams=None):
+        import torch
+        if dparams is None:
+            dparams = torch.empty_like(params)
+        hc = hits.c()
+        self._raise(self._lib.velo_train_backward(self._h, C.byref(hc), C.c_void_p(params.data_ptr()),
+                                                  C.c_void_p(dlogit.data_ptr()), C.c_void_p(dparams.data_ptr()),
+                                                  _stream()), "velo_train_backward")
+        return dparams
+
+    def adam_step(self, params, grad, m, v, step: int, lr: float = 1e-3, b1: float = 0.9, b2: float = 0.999,
+                  eps: float = 1e-8):
+        self._raise(self._lib.velo_adam_step(self._h, C.c_void_p(params.data_ptr()), C.c_void_p(grad.data_ptr()),
+                                             C.c_void_p(m.data_ptr()), C.c_void_p(v.data_ptr()), params.numel(),
+                                             lr, b1, b2, eps, step, _stream()), "velo_adam_step")
+
+
+class Graph:
+    """A captured velo_infer call; keeps its context and buffers alive."""
+
+    def __init__(self, ctx: Context, handle, hits, out):
+        self._ctx, self._g, self.hits, self.out = ctx, handle, hits, out
+
+    def launch(self):
+        self._ctx._raise(self._ctx._lib.velo_graph_launch(self._g, _stream()), "velo_graph_launch")
+
+    def close(self):
+        if getattr(self, "_g", None):
+            self._ctx._lib.velo_graph_destroy(self._g)
+            self._g = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def graph_to_host(out: Dict[str, object], n_hits: Optional[int] = None) -> Dict[str, np.ndarray]:

@@ -33,5 +33,5 @@ def test_param_count_matches_the_generator_layout():
 
 def test_status_strings():
     L = velo.lib()
-    for st in range(7):
+    for st in range(8):
         assert L.velo_status_str(st)

@@ -154,3 +154,75 @@ def test_bf16_batch_invariance_and_determinism():
     s, e = int(a["edge_offsets"][3]), int(a["edge_offsets"][4])
     np.testing.assert_array_equal(a["logit"][s:e], g1["logit"])
     np.testing.assert_array_equal(a["dst"][s:e], g1["dst"])
+
+
+U8 = 2.0 ** -4      # unit roundoff of E4M3 (4-bit significand)
+
+
+def _fp8_ctx(wl, batch, blob):
+    calib = synth.calibration_batch(wl, 8)
+    mx = max(batch.max_event_hits(), calib.max_event_hits(), 1)
+    print(f"\n[case] {wl.name} fp8 events={batch.n_events} hits={batch.n_hits}", flush=True)
+    ctx = velo.Context(wl.hidden, wl.iters, oracle.d2max_f32(wl.radius), wl.k_max, wl.edge_logit_min, "fp8",
+                       max_hits=max(batch.n_hits, calib.n_hits), max_events=max(batch.n_events, calib.n_events),
+                       max_event_hits=mx)
+    ctx.set_params(torch.from_numpy(blob).cuda())
+    return ctx, calib
+
+
+def test_fp8_requires_calibration_and_matches_the_oracle_within_its_bound():
+    wl = synth.WORKLOADS["batch256"]
+    batch = synth.make_batch(wl, n_events=3, first=5)
+    blob = synth.centred_params(wl)
+    ctx, calib = _fp8_ctx(wl, batch, blob)
+    hits = velo.DeviceHits.from_batch(batch)
+    with pytest.raises(velo.VeloError) as ei:
+        ctx.infer(hits)
+    assert ei.value.status == velo.VELO_ERR_NOT_CALIBRATED
+    ctx.calibrate(velo.DeviceHits.from_batch(calib))
+    # stage-isolated: fp8 GNN on the float32 graph
+    c32 = velo.Context(wl.hidden, wl.iters, oracle.d2max_f32(wl.radius), wl.k_max, wl.edge_logit_min, "fp32",
+                       max_hits=batch.n_hits, max_events=batch.n_events, max_event_hits=batch.max_event_hits())
+    c32.set_params(torch.from_numpy(blob).cuda())
+    g = c32.infer(hits)
+    ctx.gnn(hits, g)
+    gh = velo.graph_to_host(g, batch.n_hits)
+    for b in (0, 2):
+        ev = batch.event(b)
+        s, e = int(gh["edge_offsets"][b]), int(gh["edge_offsets"][b + 1])
+        z = oracle.gnn_forward(ev.x, ev.y, ev.z, gh["src"][s:e], gh["dst"][s:e], blob, wl.hidden, wl.iters)
+        err = np.abs(gh["logit"][s:e] - z)
+        print(f"  event {b}: fp8 max |dz| {err.max():.4g}, mean {err.mean():.3g}, |z| mean {np.abs(z).mean():.3g}",
+              flush=True)
+        assert np.all(err <= (wl.iters + 2) * U8 + 4 * U8 * np.abs(z))
+    # fp8 embedding within its bound
+    emb = ctx.embed(hits).cpu().numpy()
+    ev = batch.event(0)
+    e_or = oracle.embed(ev.x, ev.y, ev.z, blob)
+    rel = np.abs(emb[:ev.n] - e_or).max() / np.abs(e_or).max()
+    print(f"  fp8 embedding max rel err {rel:.3g}", flush=True)
+    assert rel <= 4 * U8
+
+
+def test_fp8_end_to_end_batch_invariance_and_determinism():
+    wl = synth.WORKLOADS["batch256"]
+    batch = synth.make_batch(wl, n_events=5, first=60)
+    blob = synth.centred_params(wl)
+    ctx, calib = _fp8_ctx(wl, batch, blob)
+    ctx.calibrate(velo.DeviceHits.from_batch(calib))
+    hits = velo.DeviceHits.from_batch(batch)
+    a = velo.graph_to_host(ctx.infer(hits), batch.n_hits)
+    b = velo.graph_to_host(ctx.infer(hits), batch.n_hits)
+    for k in ("src", "dst", "logit", "labels"):
+        np.testing.assert_array_equal(a[k], b[k])
+    one = synth.to_batch([batch.event(2)])
+    g1 = velo.graph_to_host(ctx.infer(velo.DeviceHits.from_batch(one)), one.n_hits)
+    s, e = int(a["edge_offsets"][2]), int(a["edge_offsets"][3])
+    np.testing.assert_array_equal(a["logit"][s:e], g1["logit"])
+    ref = oracle.pipeline(synth.to_batch([batch.event(0)]), blob, wl.hidden, wl.iters, wl.radius, wl.k_max)
+    s, e = int(a["edge_offsets"][0]), int(a["edge_offsets"][1])
+    A = set(zip(a["src"][s:e].tolist(), a["dst"][s:e].tolist()))
+    B = set(zip(ref["src"].tolist(), ref["dst"].tolist()))
+    jac = len(A & B) / max(len(A | B), 1)
+    print(f"  fp8 edge-set Jaccard vs float64 oracle {jac:.4f}", flush=True)
+    assert jac > 0.8

@@ -237,3 +237,43 @@ def test_full_batch256_sampled():
     sizes = np.diff(batch.event_offsets)
     big = int(np.argmax(sizes))
     _check_stages(wl, batch, blob, emb, g, range(batch.n_events), {0, big})
+
+
+def test_captured_graph_replays_match_eager_calls():
+    """velo_infer captured once and replayed: every replay (with eager work and
+    synchronisations between them, and new hits written into the same buffers)
+    equals the eager result."""
+    wl = synth.WORKLOADS["batch256"]
+    b1 = synth.make_batch(wl, n_events=6, first=100)
+    side = torch.cuda.Stream()
+    torch.cuda.set_stream(side)          # capture needs a stream other than the legacy default one
+    ctx, hits, blob = _setup(wl, b1)
+    out = ctx.alloc_outputs(hits)
+    graph = ctx.capture(hits, out)
+    eager = velo.graph_to_host(ctx.infer(hits), b1.n_hits)
+    for rep in range(3):
+        for k in ("edge_logit", "labels", "edge_src"):
+            out[k].fill_(-7)
+        graph.launch()
+        torch.cuda.synchronize()
+        ctx.check()
+        got = velo.graph_to_host(out, b1.n_hits)
+        for k in ("edge_offsets", "src", "dst", "logit", "labels"):
+            np.testing.assert_array_equal(got[k], eager[k], err_msg=f"replay {rep} {k}")
+        ctx.infer(hits)                      # eager work between replays
+        torch.cuda.synchronize()
+    # new events of the same total size written into the captured buffers
+    b2 = synth.to_batch([b1.event(b) for b in reversed(range(b1.n_events))])
+    for name, arr in (("event_offsets", b2.event_offsets), ("x", b2.x), ("y", b2.y), ("z", b2.z),
+                      ("plane", b2.plane)):
+        getattr(hits, name).copy_(torch.from_numpy(arr))
+    graph.launch()
+    torch.cuda.synchronize()
+    ctx.check()
+    got = velo.graph_to_host(out, b2.n_hits)
+    ref = velo.graph_to_host(ctx.infer(velo.DeviceHits.from_batch(b2)), b2.n_hits)
+    for k in ("edge_offsets", "src", "dst", "logit", "labels"):
+        np.testing.assert_array_equal(got[k], ref[k], err_msg=k)
+    graph.close()
+    torch.cuda.synchronize()
+    torch.cuda.set_stream(torch.cuda.default_stream())

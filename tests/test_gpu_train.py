@@ -1,0 +1,214 @@
+"""GPU: the training form (weighted BCE and the hand-written backward pass)
+against the float64 oracle, whose own gradient is pinned by finite
+differences in tests/test_oracle_grad.py.
+
+Tolerances: the float32 backward differs from the float64 gradient by float32
+rounding through n + 3 layers of MLPs and the message sums; per parameter
+tensor the relative error of the gradient vector (2-norm) must stay below
+1e-3, as must finite differences of the GPU forward on the largest entries.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle                                           # noqa: E402
+from paper_2407_12119_amd import synth, velo           # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+GRAD_REL = 1e-3
+
+
+def _setup(wl, batch, blob):
+    print(f"\n[case] {wl.name} train events={batch.n_events} hits={batch.n_hits}", flush=True)
+    ctx = velo.Context(wl.hidden, wl.iters, oracle.d2max_f32(wl.radius), wl.k_max, wl.edge_logit_min, "fp32",
+                       max_hits=max(batch.n_hits, 1), max_events=max(batch.n_events, 1),
+                       max_event_hits=max(batch.max_event_hits(), 1), training=True)
+    params = torch.from_numpy(blob).cuda()
+    ctx.set_params(params)
+    hits = velo.DeviceHits.from_batch(batch)
+    graph = ctx.build_graph(hits, ctx.embed(hits))
+    return ctx, hits, graph, params
+
+
+def _labels(batch, g):
+    ys = []
+    for b in range(batch.n_events):
+        s, e = int(g["edge_offsets"][b]), int(g["edge_offsets"][b + 1])
+        ys.append(synth.truth_labels(batch.event(b).next_hit, g["src"][s:e], g["dst"][s:e]))
+    return np.concatenate(ys) if ys else np.zeros(0, np.uint8)
+
+
+def _small_batch():
+    wl = synth.WORKLOADS["train32"]
+    return wl, synth.make_batch(synth.WORKLOADS["single_event"])
+
+
+def test_train_forward_equals_inference():
+    wl, batch = _small_batch()
+    blob = synth.centred_params(wl)
+    ctx, hits, graph, params = _setup(wl, batch, blob)
+    ctx.gnn(hits, graph)
+    z_inf = graph["edge_logit"].clone()
+    ctx.train_forward(hits, graph, params, check=True)
+    n = int(graph["n_edges"].cpu()[0])
+    np.testing.assert_array_equal(graph["edge_logit"][:n].cpu().numpy(), z_inf[:n].cpu().numpy())
+
+
+def test_bce_matches_oracle():
+    wl, batch = _small_batch()
+    ctx, hits, graph, params = _setup(wl, batch, synth.centred_params(wl))
+    rng = np.random.default_rng(1)
+    z = rng.normal(0, 3, 5000).astype(np.float32)
+    y = (rng.random(5000) < 0.2).astype(np.uint8)
+    loss, dz = ctx.bce(torch.from_numpy(z).cuda(), torch.from_numpy(y).cuda(), 4.0, 5000)
+    L_or, dz_or = oracle.bce(z.astype(np.float64), y, 4.0)
+    assert float(loss.cpu()[0]) == pytest.approx(L_or, rel=1e-5)
+    np.testing.assert_allclose(dz.cpu().numpy(), dz_or, rtol=1e-5, atol=1e-12)
+
+
+def test_backward_matches_oracle_gradient():
+    wl, batch = _small_batch()
+    blob = synth.centred_params(wl)
+    ctx, hits, graph, params = _setup(wl, batch, blob)
+    ctx.train_forward(hits, graph, params, check=True)
+    g = velo.graph_to_host(graph, batch.n_hits)
+    rng = np.random.default_rng(2)
+    dlogit = rng.normal(0, 1, g["n_edges"]).astype(np.float32)
+    dp = ctx.train_backward(hits, params, torch.from_numpy(dlogit).cuda())
+    ctx.check()
+    dp = dp.cpu().numpy().astype(np.float64)
+    ev = batch.event(0)
+    ref = oracle.gnn_backward(ev.x, ev.y, ev.z, g["src"], g["dst"], blob, wl.hidden, wl.iters,
+                              dlogit.astype(np.float64))
+    views_gpu = synth.param_views(dp, wl.hidden, wl.iters)
+    views_ref = synth.param_views(ref, wl.hidden, wl.iters)
+    assert np.all(dp[:12] == 0)
+    worst = 0.0
+    for name, _ in synth.param_layout(wl.hidden, wl.iters):
+        for j in (0, 1):
+            a, b = views_gpu[name][j], views_ref[name][j]
+            nb = np.linalg.norm(b)
+            if name.startswith("emb"):
+                assert np.all(a == 0)
+                continue
+            rel = np.linalg.norm(a - b) / max(nb, 1e-30)
+            worst = max(worst, rel)
+            assert rel <= GRAD_REL, (name, j, rel)
+    print(f"  worst per-tensor relative gradient error {worst:.3g}", flush=True)
+
+
+def test_backward_against_finite_differences():
+    """The GPU backward against central differences of L = sum dlogit * z.
+
+    Differences of the float64 oracle forward (the method's definition) on the
+    same graph for entries of every parameter tensor, and differences of the
+    float32 GPU forward for the classifier's output layer, in which L is
+    linear (exact differences; elsewhere float32 rounding noise of the forward
+    is about 1e-3 of a difference quotient at usable step sizes).  A probe
+    whose differences at h and h/2 disagree sits on a ReLU kink and is skipped.
+    """
+    wl = synth.dataclasses.replace(synth.WORKLOADS["train32"], iters=2)
+    ev = synth.make_events(synth.WORKLOADS["single_event"])[0]
+    keep = (ev.plane >= 9) & (ev.plane < 13)             # a small event: ~100 hits on four planes
+    small = synth.Event(ev.x[keep], ev.y[keep], ev.z[keep], ev.plane[keep], ev.pid[keep],
+                        np.full(int(keep.sum()), -1, np.int32))
+    batch = synth.to_batch([small])
+    blob = synth.init_params(wl)
+    ctx, hits, graph, params = _setup(wl, batch, blob)
+    g = velo.graph_to_host(graph, batch.n_hits)
+    n = g["n_edges"]
+    assert n > 20
+    dl_np = np.random.default_rng(4).normal(0, 1, n).astype(np.float32)
+    dl = torch.from_numpy(dl_np).cuda()
+    ctx.train_forward(hits, graph, params)
+    grad = ctx.train_backward(hits, params, dl).cpu().numpy()
+    ev1 = batch.event(0)
+
+    def L64(b):
+        z = oracle.gnn_forward(ev1.x, ev1.y, ev1.z, g["src"], g["dst"], b, wl.hidden, wl.iters)
+        return float(z @ dl_np.astype(np.float64))
+
+    def L32(p):
+        ctx.train_forward(hits, graph, p)
+        return float((graph["edge_logit"][:n].double() * dl.double()).sum().cpu())
+
+    lay = synth.param_layout(wl.hidden, wl.iters)
+    offs, o = {}, 12
+    for name, (r_, c_) in lay:
+        offs[name] = (o, o + r_ * c_ + r_)
+        o += r_ * c_ + r_
+    picks = []
+    for name, (a_, b_) in offs.items():
+        if not name.startswith("emb"):
+            picks += [a_ + int(k) for k in np.argsort(-np.abs(grad[a_:b_]))[:2]]
+
+    L0 = L64(blob)
+
+    def fd64(idx):
+        """Central difference at the largest step whose left and right
+        one-sided differences agree (no ReLU kink within the step)."""
+        t = float(blob[idx])
+        for k in range(8, 19):
+            h = 2.0 ** -k * max(abs(t), 2.0 ** -4)
+            bp, bm = blob.copy(), blob.copy()
+            bp[idx] = np.float32(t + h)
+            bm[idx] = np.float32(t - h)
+            hp, hm = float(bp[idx]) - t, t - float(bm[idx])
+            Lp, Lm = L64(bp), L64(bm)
+            right, left = (Lp - L0) / hp, (L0 - Lm) / hm
+            if abs(right - left) <= 1e-5 * max(abs(right), 1e-3):
+                return (Lp - Lm) / (hp + hm)
+        return None
+
+    smooth = 0
+    for idx in picks:
+        f = fd64(idx)
+        if f is None:
+            continue
+        smooth += 1
+        assert f == pytest.approx(float(grad[idx]), rel=GRAD_REL, abs=1e-6 * np.abs(grad).max()), idx
+    print(f"  {smooth} of {len(picks)} oracle-difference probes agree", flush=True)
+    assert smooth >= len(picks) // 2
+
+    a_, b_ = offs["cls1"]
+    for idx in range(a_, b_, 7):
+        t = float(blob[idx])
+        h = 1e-2 * max(abs(t), 0.05)
+        pp, pm = params.clone(), params.clone()
+        pp[idx] = t + h
+        pm[idx] = t - h
+        fd = (L32(pp) - L32(pm)) / (float(pp[idx].cpu()) - float(pm[idx].cpu()))
+        assert fd == pytest.approx(float(grad[idx]), rel=GRAD_REL, abs=1e-6), idx
+
+
+def test_backward_is_deterministic_and_training_reduces_the_loss():
+    wl = synth.WORKLOADS["train32"]
+    batch = synth.make_batch(wl, n_events=4)
+    blob = synth.init_params(wl)
+    ctx, hits, graph, params = _setup(wl, batch, blob)
+    g = velo.graph_to_host(graph, batch.n_hits)
+    n = g["n_edges"]
+    y = _labels(batch, g)
+    pw = float((y == 0).sum()) / max(float(y.sum()), 1.0)
+    yt = torch.from_numpy(y).cuda()
+    ctx.train_forward(hits, graph, params)
+    loss0, dz = ctx.bce(graph["edge_logit"], yt, pw, n)
+    g1 = ctx.train_backward(hits, params, dz).clone()
+    ctx.train_forward(hits, graph, params)
+    g2 = ctx.train_backward(hits, params, dz)
+    assert torch.equal(g1, g2)
+    m = torch.zeros_like(params)
+    v = torch.zeros_like(params)
+    p = params.clone()
+    losses = []
+    for step in range(1, 31):
+        ctx.train_forward(hits, graph, p)
+        loss, dz = ctx.bce(graph["edge_logit"], yt, pw, n)
+        grad = ctx.train_backward(hits, p, dz)
+        ctx.adam_step(p, grad, m, v, step, lr=3e-3)
+        losses.append(float(loss.cpu()[0]))
+    ctx.check()
+    print(f"  loss {losses[0]:.4f} -> {losses[-1]:.4f}", flush=True)
+    assert losses[-1] < 0.8 * losses[0]
