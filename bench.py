@@ -10,7 +10,9 @@ the float64 CPU oracle timed on a bounded sample of the same workload, and
 the plain per-event float32 path (one call per event).
 
 usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload batch256]
-                       [--precision fp32|bf16] [--variants bf16]
+                       [--precision fp32|bf16|fp8] [--variants bf16,fp8] [--graph] [--latency]
+       the 1000-event workload: --workload batch1000_h128 --precision bf16 --variants fp8
+                                --graph --latency --no-cpu-baseline
 """
 import argparse
 import json
@@ -66,7 +68,54 @@ def roofline(stages, H, prec, n_edges, n_hits):
             "mfma_frac": round(flops / (avg_ms * 1e-3) / 1e12 / PEAK_TFLOPS[prec], 4)}
 
 
-def run_batched(velo, synth, torch, wl, batch, hits, blob, prec, steps, warmup):
+def run_training(velo, synth, torch, steps, warmup):
+    """Training step of the 32-event workload (H = 64, n = 6, fp32): forward with
+    checkpoints, weighted BCE, backward, Adam.  Graph building is the input
+    pipeline and stays outside the timed region."""
+    import numpy as np
+    wl = synth.WORKLOADS["train32"]
+    batch = synth.make_batch(wl)
+    blob = synth.init_params(wl)
+    ctx = velo.Context(wl.hidden, wl.iters, float(np.float32(wl.radius * wl.radius)), wl.k_max,
+                       wl.edge_logit_min, "fp32", max_hits=batch.n_hits, max_events=batch.n_events,
+                       max_event_hits=batch.max_event_hits(), training=True)
+    params = torch.from_numpy(blob).cuda()
+    ctx.set_params(params)
+    hits = velo.DeviceHits.from_batch(batch)
+    graph = ctx.build_graph(hits, ctx.embed(hits))
+    g = velo.graph_to_host(graph, batch.n_hits)
+    ys = [synth.truth_labels(batch.event(b).next_hit, g["src"][g["edge_offsets"][b]:g["edge_offsets"][b + 1]],
+                             g["dst"][g["edge_offsets"][b]:g["edge_offsets"][b + 1]]) for b in range(batch.n_events)]
+    y = np.concatenate(ys)
+    pw = float((y == 0).sum()) / max(float(y.sum()), 1.0)
+    yt = torch.from_numpy(y).cuda()
+    n = g["n_edges"]
+    m, v = torch.zeros_like(params), torch.zeros_like(params)
+    grad = torch.empty_like(params)
+
+    def step(t):
+        ctx.train_forward(hits, graph, params)
+        _, dz = ctx.bce(graph["edge_logit"], yt, pw, n)
+        ctx.train_backward(hits, params, dz, grad)
+        ctx.adam_step(params, grad, m, v, t, lr=1e-3)
+
+    for t in range(1, warmup + 1):
+        step(t)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for t in range(warmup + 1, warmup + steps + 1):
+        step(t)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ctx.check()
+    log(f"training: {1e3 * dt / steps:.3f} ms/step")
+    return {"workload": f"{wl.name}: {batch.n_events} events, {batch.n_hits} hits, {n} edges, H={wl.hidden}, "
+                        f"n={wl.iters}, fp32, weighted BCE (pos_weight {pw:.2f}), Adam",
+            "steps_per_s": round(steps / dt, 2), "ms_per_step": round(1e3 * dt / steps, 3)}
+
+
+def run_batched(velo, synth, torch, wl, batch, hits, blob, prec, steps, warmup, graph=False, latency=False,
+                autotune=True):
     import numpy as np
     r2 = float(np.float32(wl.radius * wl.radius))
     mx = batch.max_event_hits()
@@ -84,6 +133,10 @@ def run_batched(velo, synth, torch, wl, batch, hits, blob, prec, steps, warmup):
     for _ in range(warmup):
         ctx.infer(hits, out, check=False)
     ctx.check()
+    tuned = None
+    if autotune:
+        tuned = ctx.autotune(hits, out)
+        log(f"{prec}: autotune choice {tuned}")
     n_edges = int(out["n_edges"].cpu()[0])
     ctx.set_timing(True)
     ctx.read_timing()
@@ -101,7 +154,39 @@ def run_batched(velo, synth, torch, wl, batch, hits, blob, prec, steps, warmup):
            "hits_per_s": round(batch.n_hits * steps / dt, 1), "edges": n_edges,
            "stage_ms_per_step": {k: round(v[0] / steps, 4) for k, v in stages.items()},
            "roofline": roofline(stages, wl.hidden, prec, n_edges, batch.n_hits)}
+    if tuned is not None:
+        res["autotune"] = {k: v for k, v in tuned.items() if k in ("knn", "edge_enc", "messages", "node_net",
+                                                                   "edge_net", "edge_cls")}
     log(f"{prec}: {res['ms_per_step']:.3f} ms/step, {res['value']:.1f} events/s")
+    if graph or latency:
+        # the whole path captured once into a HIP graph and replayed; per-batch
+        # latency from HIP events around each replay
+        side = torch.cuda.Stream()
+        with torch.cuda.stream(side):
+            gr = ctx.capture(hits, out) if graph else None
+            run = gr.launch if gr is not None else (lambda: ctx.infer(hits, out, check=False))
+            for _ in range(warmup):
+                run()
+            side.synchronize()
+            evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                   for _ in range(steps)]
+            t0 = time.perf_counter()
+            for a, b in evs:
+                a.record(side)
+                run()
+                b.record(side)
+            side.synchronize()
+            gdt = time.perf_counter() - t0
+            lat = np.array([a.elapsed_time(b) for a, b in evs])
+        ctx.check()
+        key = "graph" if graph else "eager"
+        res[key] = {"value": round(batch.n_events * steps / gdt, 2), "ms_per_step": round(1e3 * gdt / steps, 4),
+                    "latency_ms_p50": round(float(np.percentile(lat, 50)), 4),
+                    "latency_ms_p99": round(float(np.percentile(lat, 99)), 4)}
+        log(f"{prec} {key}: {res[key]['ms_per_step']:.3f} ms/step, p50 {res[key]['latency_ms_p50']:.3f} ms, "
+            f"p99 {res[key]['latency_ms_p99']:.3f} ms")
+        if gr is not None:
+            gr.close()
     return ctx, res
 
 
@@ -117,6 +202,10 @@ def main():
     ap.add_argument("--cpu-sample-events", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-event", action="store_true")
+    ap.add_argument("--no-train", action="store_true", help="skip the training-step measurement")
+    ap.add_argument("--graph", action="store_true", help="also time hipGraph replays of the whole path")
+    ap.add_argument("--latency", action="store_true", help="per-batch p50/p99 latency (with --graph: of replays)")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the built-in launch parameters")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -138,12 +227,16 @@ def main():
     hits = velo.DeviceHits.from_batch(batch)
 
     ctx, main_res = run_batched(velo, synth, torch, wl, batch, hits, blob, args.precision, args.steps,
-                                args.warmup)
+                                args.warmup, args.graph, args.latency, not args.no_autotune)
     variants = {}
     for prec in [p for p in args.variants.split(",") if p and p != args.precision]:
-        vctx, vres = run_batched(velo, synth, torch, wl, batch, hits, blob, prec, args.steps, args.warmup)
+        vctx, vres = run_batched(velo, synth, torch, wl, batch, hits, blob, prec, args.steps, args.warmup,
+                                 args.graph, args.latency, not args.no_autotune)
         vctx.close()
         variants[prec] = vres
+    training = None
+    if not args.no_train and args.workload == "batch256":
+        training = run_training(velo, synth, torch, max(5, args.steps // 2), 2)
 
     per_event = None
     if not args.no_per_event and wl.hidden <= 64:
@@ -197,7 +290,10 @@ def main():
            "hits_per_s": main_res["hits_per_s"],
            "stage_ms_per_step": main_res["stage_ms_per_step"],
            "roofline": main_res["roofline"], "cpu_baseline": cpu, "per_event_path": per_event,
-           "variants": variants}
+           "variants": variants, "training": training}
+    for k in ("graph", "eager"):
+        if k in main_res:
+            res[k] = main_res[k]
     print(json.dumps(res), flush=True)
 
 

@@ -243,6 +243,15 @@ velo_status velo_train_backward(velo_ctx *ctx, const velo_hits *hits, const floa
 velo_status velo_adam_step(velo_ctx *ctx, float *params, const float *grad, float *m, float *v, int64_t n, float lr,
                            float b1, float b2, float eps, int32_t step, void *stream);
 
+/* Choose launch parameters by measurement: runs velo_infer on (hits, out)
+ * under a fixed list of candidate configurations (blocks per compute unit and
+ * interleaved or XCD-blocked work mapping), times every stage with HIP
+ * events and keeps, per stage, the fastest candidate for later calls on this
+ * context.  choice_host (optional, VELO_N_STAGES entries) receives the
+ * candidate index picked per stage.  Synchronises the stream. */
+velo_status velo_autotune(velo_ctx *ctx, const velo_hits *hits, velo_outputs *out, void *stream,
+                          int32_t *choice_host);
+
 /* Synchronise `stream` and return (and clear) the error latched on the
  * device by earlier calls: VELO_OK, VELO_ERR_INPUT or VELO_ERR_CAPACITY. */
 velo_status velo_check(velo_ctx *ctx, void *stream);

@@ -492,6 +492,54 @@ velo_status velo_adam_step(velo_ctx *c, float *params, const float *grad, float 
     return device_status(c, "velo_adam_step");
 }
 
+velo_status velo_autotune(velo_ctx *c, const velo_hits *h, velo_outputs *o, void *stream, int32_t *choice) {
+    if (!c) return VELO_ERR_INVALID_ARG;
+    // candidate launch parameters, applied to every tunable stage at once;
+    // stages are timed separately, so each picks its own best candidate.
+    // per_cu 0 = the stage's default (occupancy for MFMA kernels).
+    static const int kCand = 6;
+    static const int mlp_cu[kCand] = {0, 0, 1, 2, 0, 1};
+    static const int mem_cu[kCand] = {16, 16, 4, 8, 32, 32};
+    static const int xcd[kCand] = {0, 1, 1, 1, 1, 0};
+    static const int tunable[] = {VELO_STAGE_KNN, VELO_STAGE_EDGE_ENC, VELO_STAGE_MESSAGES, VELO_STAGE_NODE_NET,
+                                  VELO_STAGE_EDGE_NET, VELO_STAGE_EDGE_CLS};
+    const bool was_timing = c->timing;
+    velo_status st = velo_set_timing(c, 1);
+    if (st) return st;
+    double best[VELO_N_STAGES];
+    int pick[VELO_N_STAGES] = {};
+    for (int k = 0; k < VELO_N_STAGES; k++) best[k] = 1e30;
+    double ms[VELO_N_STAGES];
+    int64_t n[VELO_N_STAGES];
+    for (int cand = 0; cand < kCand; cand++) {
+        for (int t : tunable) {
+            const bool mem = t == VELO_STAGE_KNN || t == VELO_STAGE_MESSAGES;
+            c->tune_per_cu[t] = mem ? mem_cu[cand] : mlp_cu[cand];
+            c->tune_xcd[t] = xcd[cand];
+        }
+        // one untimed call, then two timed ones
+        if ((st = velo_infer(c, h, o, stream))) break;
+        if ((st = velo_read_timing(c, ms, n))) break;
+        for (int r = 0; r < 2 && !st; r++) st = velo_infer(c, h, o, stream);
+        if (st || (st = velo_read_timing(c, ms, n))) break;
+        for (int t : tunable)
+            if (n[t] && ms[t] < best[t]) {
+                best[t] = ms[t];
+                pick[t] = cand;
+            }
+    }
+    for (int t : tunable) {
+        const bool mem = t == VELO_STAGE_KNN || t == VELO_STAGE_MESSAGES;
+        c->tune_per_cu[t] = mem ? mem_cu[pick[t]] : mlp_cu[pick[t]];
+        c->tune_xcd[t] = xcd[pick[t]];
+    }
+    if (choice)
+        for (int k = 0; k < VELO_N_STAGES; k++) choice[k] = pick[k];
+    velo_set_timing(c, was_timing ? 1 : 0);
+    if (st) return st;
+    return velo_check(c, stream);
+}
+
 velo_status velo_check(velo_ctx *c, void *stream) {
     if (!c) return VELO_ERR_INVALID_ARG;
     DeviceGuard gd(c->device);

@@ -166,6 +166,7 @@ struct MlpArgs {
     float *logit;
     const float *sc, *sc_cls;      // fp8 scales of this MLP and of the classifier (else null)
     float *amax, *amax_cls;        // calibration maxima (else null)
+    int xcd;                       // XCD-blocked work mapping
     const unsigned *flags;
 };
 
@@ -268,9 +269,10 @@ __global__ __launch_bounds__(512) void k_mlp(MlpArgs A) {
     // memory-bound precisions prefetch the next unit's inputs during the MFMAs
     constexpr bool PREFETCH = sizeof(S) < 4 && NSEG > 0;
     typename P::frag_t Xn[NX];
-    int64_t u = wave_id();
-    if (PREFETCH && u < units) load_unit(u, Xn);
-    for (; u < units; u += n_waves()) {
+    const WaveRange wr = wave_range(units, A.xcd != 0);
+    int64_t u = wr.first;
+    if (PREFETCH && u < wr.end) load_unit(u, Xn);
+    for (; u < wr.end; u += wr.step) {
         const int64_t q = u * 16 + n;
         const bool ok = q < N;
         const int64_t qc = ok ? q : N - 1;
@@ -278,7 +280,7 @@ __global__ __launch_bounds__(512) void k_mlp(MlpArgs A) {
         if (PREFETCH) {
 #pragma unroll
             for (int k = 0; k < NX; k++) X[k] = Xn[k];
-            if (u + n_waves() < units) load_unit(u + n_waves(), Xn);
+            if (u + wr.step < wr.end) load_unit(u + wr.step, Xn);
         } else if (NSEG > 0) {
             load_unit(u, X);
         }
@@ -332,12 +334,13 @@ __global__ __launch_bounds__(256) void k_messages(int64_t n_hits, const int *__r
                                                   const int *__restrict__ in_ptr,
                                                   const int *__restrict__ in_list,
                                                   const typename P::state_t *__restrict__ e,
-                                                  float *__restrict__ m, const unsigned *__restrict__ flags) {
+                                                  float *__restrict__ m, int xcd, const unsigned *__restrict__ flags) {
     if (*flags) return;
     constexpr int LPN = H / 4, NPW = 64 / LPN;
     const int lane = threadIdx.x & 63, sub = lane / LPN, c = 4 * (lane % LPN);
-    for (int64_t base = (int64_t)wave_id() * NPW; base < n_hits; base += (int64_t)n_waves() * NPW) {
-        const int64_t i = base + sub;
+    const WaveRange wr = wave_range((n_hits + NPW - 1) / NPW, xcd != 0);
+    for (int64_t u = wr.first; u < wr.end; u += wr.step) {
+        const int64_t i = u * NPW + sub;
         if (i >= n_hits) continue;
         f32x4 so = zero4(), si = zero4();
         const int a0 = out_ptr[i], a1 = out_ptr[i + 1];
@@ -382,10 +385,11 @@ inline int blocks_per_cu(const void *kernel, int block, size_t lds) {
 }
 
 template <class P, int H, int MODE, bool CLS>
-void run_mlp(velo_ctx *c, const MlpArgs &a, hipStream_t s) {
+void run_mlp(velo_ctx *c, int stage, MlpArgs a, hipStream_t s) {
     constexpr size_t lds = mlp_lds<P, H, MODE, CLS>();
-    static const int per_cu = blocks_per_cu(reinterpret_cast<const void *>(&k_mlp<P, H, MODE, CLS>), kMlpBlock, lds);
-    k_mlp<P, H, MODE, CLS><<<persistent_grid(c, per_cu), kMlpBlock, lds, s>>>(a);
+    static const int occ = blocks_per_cu(reinterpret_cast<const void *>(&k_mlp<P, H, MODE, CLS>), kMlpBlock, lds);
+    a.xcd = c->tune_xcd[stage];
+    k_mlp<P, H, MODE, CLS><<<persistent_grid(c, stage_per_cu(c, stage, occ, occ)), kMlpBlock, lds, s>>>(a);
 }
 
 // The GNN forward pass.  Inference updates the edge state in place and fuses
@@ -425,15 +429,15 @@ void gnn_ph(velo_ctx *c, const velo_hits *hits, bool out_identity, float *logit,
     a.sc = sc(s_eenc); a.amax = am(s_eenc); a.sc_cls = sc(s_cls); a.amax_cls = am(s_cls);
     {
         StageTimer t(c, VELO_STAGE_EDGE_ENC, s);
-        run_mlp<P, H, EDGE_ENC, false>(c, a, s);
+        run_mlp<P, H, EDGE_ENC, false>(c, VELO_STAGE_EDGE_ENC, a, s);
     }
     const int *optr = out_identity ? w.row_ptr : w.out_ptr;
     const int *olist = out_identity ? nullptr : w.out_list;
     for (int k = 0; k < iters; k++) {
         if (N > 0) {
             StageTimer t(c, VELO_STAGE_MESSAGES, s);
-            k_messages<P, H><<<persistent_grid(c, 16), 256, 0, s>>>(N, optr, olist, w.in_ptr, w.in_list, ek(k), mk(k),
-                                                                  w.flags);
+            k_messages<P, H><<<persistent_grid(c, stage_per_cu(c, VELO_STAGE_MESSAGES, 16)), 256, 0, s>>>(
+                N, optr, olist, w.in_ptr, w.in_list, ek(k), mk(k), c->tune_xcd[VELO_STAGE_MESSAGES], w.flags);
         }
         MlpArgs nd{};
         nd.n_dev = nullptr; nd.n_host = N; nd.a = hk(k); nd.b = mk(k); nd.out = hk(k + 1);
@@ -441,7 +445,7 @@ void gnn_ph(velo_ctx *c, const velo_hits *hits, bool out_identity, float *logit,
         nd.sc = sc(slot_node(k)); nd.amax = am(slot_node(k));
         if (N > 0) {
             StageTimer t(c, VELO_STAGE_NODE_NET, s);
-            run_mlp<P, H, NODE, false>(c, nd, s);
+            run_mlp<P, H, NODE, false>(c, VELO_STAGE_NODE_NET, nd, s);
         }
         MlpArgs ed = a;
         ed.a = ek(k); ed.b = hk(k + 1); ed.out = ek(k + 1); ed.o_w1 = L.edge[k][0].w; ed.o_w2 = L.edge[k][1].w;
@@ -449,15 +453,15 @@ void gnn_ph(velo_ctx *c, const velo_hits *hits, bool out_identity, float *logit,
         const bool last = k == iters - 1;
         StageTimer t(c, last && fuse_cls ? VELO_STAGE_EDGE_CLS : VELO_STAGE_EDGE_NET, s);
         if (last && fuse_cls)
-            run_mlp<P, H, EDGE, true>(c, ed, s);
+            run_mlp<P, H, EDGE, true>(c, VELO_STAGE_EDGE_CLS, ed, s);
         else
-            run_mlp<P, H, EDGE, false>(c, ed, s);
+            run_mlp<P, H, EDGE, false>(c, VELO_STAGE_EDGE_NET, ed, s);
     }
     if (iters == 0 || !fuse_cls) {
         MlpArgs cl = a;
         cl.a = ek(iters);
         StageTimer t(c, VELO_STAGE_EDGE_CLS, s);
-        run_mlp<P, H, CLS_ONLY, true>(c, cl, s);
+        run_mlp<P, H, CLS_ONLY, true>(c, VELO_STAGE_EDGE_CLS, cl, s);
     }
 }
 

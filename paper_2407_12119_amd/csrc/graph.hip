@@ -96,12 +96,12 @@ __global__ __launch_bounds__(256) void k_knn(int64_t n_hits, const int *__restri
                                              const int *__restrict__ hit_event,
                                              const int *__restrict__ plane,
                                              const f32x4 *__restrict__ emb, float d2max, int kmax,
-                                             int *__restrict__ nbr, int *__restrict__ deg,
+                                             int *__restrict__ nbr, int *__restrict__ deg, int xcd,
                                              const unsigned *__restrict__ flags) {
     if (*flags & kErrInput) return;
     const int lane = threadIdx.x & 63;
-    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; i < n_hits; i += nwaves) {
+    const WaveRange wr = wave_range(n_hits, xcd != 0);
+    for (int64_t i = wr.first; i < wr.end; i += wr.step) {
         const int b = hit_event[i];
         const int64_t s = off[b];
         const int p = plane[i];
@@ -563,10 +563,10 @@ void launch_scan(velo_ctx *c, const int *in, int *out, int64_t n, hipStream_t s)
 
 void launch_knn(velo_ctx *c, const velo_hits *h, const float *emb, hipStream_t s) {
     if (h->n_hits <= 0) return;
-    const int blocks = grid_for(h->n_hits * 64, 256, persistent_grid(c, 16));
+    const int blocks = persistent_grid(c, stage_per_cu(c, VELO_STAGE_KNN, 16));
     k_knn<<<blocks, 256, 0, s>>>(h->n_hits, h->event_offsets, c->ws.plane_off, c->ws.hit_event,
                                  h->plane, (const f32x4 *)emb, c->cfg.d2_max, c->cfg.k_max,
-                                 c->ws.nbr, c->ws.deg, c->ws.flags);
+                                 c->ws.nbr, c->ws.deg, c->tune_xcd[VELO_STAGE_KNN], c->ws.flags);
 }
 
 void launch_compact(velo_ctx *c, const velo_hits *h, velo_outputs *g, hipStream_t s) {

@@ -87,6 +87,9 @@ struct velo_ctx {
     bool calibrated = false;     // fp8 activation scales are set
     velo::Workspace ws;
     std::string last_error;
+    // launch parameters per stage, chosen by velo_autotune (0 = built-in default)
+    int tune_per_cu[VELO_N_STAGES] = {};
+    int tune_xcd[VELO_N_STAGES] = {};   // 1: XCD-blocked work mapping
     // per-stage timing
     bool timing = false;
     std::vector<StageEvents> ev_pool;     // created on first enable
@@ -158,5 +161,36 @@ struct StageTimer {
 
 // Grid size for persistent kernels: `per_cu` blocks on every compute unit.
 inline int persistent_grid(const velo_ctx *c, int per_cu) { return c->n_cu * per_cu; }
+
+// Blocks per CU for a stage: the tuned value if set (capped by what fits),
+// else `dflt`.
+inline int stage_per_cu(const velo_ctx *c, int stage, int dflt, int cap = 1 << 30) {
+    const int t = c->tune_per_cu[stage];
+    int v = t > 0 ? t : dflt;
+    if (v > cap) v = cap;
+    return v < 1 ? 1 : v;
+}
+
+// Work mapping of persistent kernels over `units` work items.  Interleaved:
+// wave w takes units w, w + W, ...  XCD-blocked: workgroups are dispatched
+// round-robin over the XCDs, so block b runs on XCD b % kXcds; each XCD gets
+// a contiguous slice of the units (consecutive edges and hits belong to the
+// same events), keeping an event's states in one XCD's L2.
+constexpr int kXcds = 8;
+struct WaveRange {
+    int64_t first, step, end;
+};
+__device__ inline WaveRange wave_range(int64_t units, bool xcd) {
+    const int wpb = blockDim.x >> 6, wib = threadIdx.x >> 6;
+    if (!xcd || (gridDim.x % kXcds) != 0) {
+        const int64_t w = (int64_t)blockIdx.x * wpb + wib;
+        return {w, (int64_t)gridDim.x * wpb, units};
+    }
+    const int x = blockIdx.x % kXcds;
+    const int64_t bx = blockIdx.x / kXcds, nbx = gridDim.x / kXcds;
+    const int64_t per = (units + kXcds - 1) / kXcds;
+    const int64_t lo = per * x, hi = min(units, lo + per);
+    return {lo + bx * wpb + wib, nbx * wpb, hi};
+}
 
 }  // namespace velo

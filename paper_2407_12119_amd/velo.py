@@ -26,7 +26,8 @@ EXPORTS = ("velo_param_count", "velo_create", "velo_destroy", "velo_set_params",
            "velo_embed", "velo_build_graph", "velo_gnn", "velo_components", "velo_check",
            "velo_status_str", "velo_last_error", "velo_set_timing", "velo_read_timing",
            "velo_train_forward", "velo_bce", "velo_train_backward", "velo_adam_step",
-           "velo_graph_capture", "velo_graph_launch", "velo_graph_destroy", "velo_calibrate")
+           "velo_graph_capture", "velo_graph_launch", "velo_graph_destroy", "velo_calibrate",
+           "velo_autotune")
 STAGES = ("prepare", "embed", "knn", "compact", "lists", "node_enc", "edge_enc", "messages",
           "node_net", "edge_net", "edge_cls", "components")
 
@@ -108,6 +109,8 @@ def lib() -> C.CDLL:
         L.velo_graph_destroy.restype = None
         L.velo_calibrate.argtypes = [vp, C.POINTER(_Hits), vp]
         L.velo_calibrate.restype = st
+        L.velo_autotune.argtypes = [vp, C.POINTER(_Hits), C.POINTER(_Outputs), vp, vp]
+        L.velo_autotune.restype = st
         _lib = L
     return _lib
 
@@ -209,6 +212,15 @@ class Context:
         self._raise(self._lib.velo_calibrate(self._h, C.byref(hc), _stream()), "velo_calibrate")
         if check:
             self.check()
+
+    def autotune(self, hits: DeviceHits, out):
+        """Pick launch parameters per stage by timing candidates on this batch."""
+        oc = self._out_c(out)
+        hc = hits.c()
+        choice = np.zeros(len(STAGES), np.int32)
+        self._raise(self._lib.velo_autotune(self._h, C.byref(hc), C.byref(oc), _stream(), choice.ctypes.data),
+                    "velo_autotune")
+        return {k: int(choice[i]) for i, k in enumerate(STAGES)}
 
     def check(self):
         self._raise(self._lib.velo_check(self._h, _stream()), "velo_check")

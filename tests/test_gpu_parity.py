@@ -277,3 +277,25 @@ def test_captured_graph_replays_match_eager_calls():
     graph.close()
     torch.cuda.synchronize()
     torch.cuda.set_stream(torch.cuda.default_stream())
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_autotuned_launches_give_identical_results(precision):
+    """Launch parameters (blocks per CU, XCD-blocked work mapping) change only
+    which wave processes which unit: outputs are bitwise those of the default
+    launches."""
+    wl = synth.WORKLOADS["batch256"]
+    batch = synth.make_batch(wl, n_events=24, first=40)
+    print(f"\n[case] autotune {precision} events={batch.n_events} hits={batch.n_hits}", flush=True)
+    r2 = oracle.d2max_f32(wl.radius)
+    ctx = velo.Context(wl.hidden, wl.iters, r2, wl.k_max, wl.edge_logit_min, precision,
+                       max_hits=batch.n_hits, max_events=batch.n_events, max_event_hits=batch.max_event_hits())
+    ctx.set_params(torch.from_numpy(synth.centred_params(wl)).cuda())
+    hits = velo.DeviceHits.from_batch(batch)
+    ref = velo.graph_to_host(ctx.infer(hits), batch.n_hits)
+    out = ctx.alloc_outputs(hits)
+    choice = ctx.autotune(hits, out)
+    print(f"  choice {choice}", flush=True)
+    got = velo.graph_to_host(ctx.infer(hits), batch.n_hits)
+    for k in ("edge_offsets", "src", "dst", "logit", "labels"):
+        np.testing.assert_array_equal(got[k], ref[k], err_msg=k)
