@@ -114,6 +114,74 @@ def run_training(velo, synth, torch, steps, warmup):
             "steps_per_s": round(steps / dt, 2), "ms_per_step": round(1e3 * dt / steps, 3)}
 
 
+def run_quality(velo, synth, torch, wl, batch, centred_blob, precisions, train_steps):
+    """Track-finding quality at every precision on the benchmark batch, for two
+    weight sets: the bias-centred random init the throughput is measured with,
+    and weights trained by the library's training form on other generated
+    events (the same network shape).  Each lower precision is compared with
+    fp32: track-efficiency difference in points, edge-decision agreement over
+    the union of the two edge sets, Jaccard overlap and the largest logit
+    difference |z - z_fp32| / max(|z_fp32|, 1) on common edges."""
+    import dataclasses
+    import numpy as np
+    from paper_2407_12119_amd import metrics, train
+    twl = dataclasses.replace(wl, name=wl.name + "_train", index=3)
+    tbatches = [synth.make_batch(twl, n_events=32, first=32 * i) for i in range(4)]
+    params = torch.from_numpy(synth.init_params(wl)).cuda()
+    log(f"quality: training {train_steps} steps on {sum(b.n_events for b in tbatches)} other events")
+    tr = train.Trainer(wl, params, tbatches, lr=3e-3)
+    l0 = float(tr.step().cpu())
+    last = None
+    for _ in range(train_steps - 1):
+        last = tr.step()
+    l1 = float(last.cpu()) if last is not None else l0
+    tr.vctx.check()
+    trained = params.cpu().numpy()
+    tr.close()
+    hits = velo.DeviceHits.from_batch(batch)
+    r2 = float(np.float32(wl.radius * wl.radius))
+    out = {}
+    for tag, blob in (("trained", trained), ("centred", centred_blob)):
+        res, ref = {}, None
+        for prec in precisions:
+            mx = batch.max_event_hits()
+            if prec == "fp8":
+                mx = max(mx, synth.calibration_batch(wl, 16).max_event_hits())
+            ctx = velo.Context(wl.hidden, wl.iters, r2, wl.k_max, wl.edge_logit_min, prec, max_hits=batch.n_hits,
+                               max_events=batch.n_events, max_event_hits=mx)
+            ctx.set_params(torch.from_numpy(blob).cuda())
+            if prec == "fp8":
+                ctx.calibrate(velo.DeviceHits.from_batch(synth.calibration_batch(wl, 16)))
+            g = velo.graph_to_host(ctx.infer(hits), batch.n_hits)
+            ctx.close()
+            m = metrics.track_metrics(g["labels"], batch.pid, batch.event_offsets)
+            r = {k: round(m[k], 5) for k in ("efficiency", "clone_rate", "fake_rate", "hit_efficiency",
+                                              "hit_purity")}
+            r["edges"] = g["n_edges"]
+            r["kept_edges"] = int((g["logit"] >= wl.edge_logit_min).sum())
+            if ref is None:
+                ref = g
+            else:
+                a = metrics.edge_agreement(ref["edge_offsets"], ref["src"], ref["dst"],
+                                           ref["logit"] >= wl.edge_logit_min, g["edge_offsets"], g["src"],
+                                           g["dst"], g["logit"] >= wl.edge_logit_min)
+                r["d_efficiency_pts"] = round(100 * (m["efficiency"] - res[precisions[0]]["efficiency"]), 4)
+                r["decision_agreement"] = round(a["decision_agreement"], 6)
+                r["jaccard"] = round(a["jaccard"], 6)
+                kr = metrics.edge_keys(ref["edge_offsets"], ref["src"], ref["dst"])
+                kg = metrics.edge_keys(g["edge_offsets"], g["src"], g["dst"])
+                _, ia, ib = np.intersect1d(kr, kg, return_indices=True)
+                if ia.size:
+                    zr = ref["logit"][ia].astype(np.float64)
+                    r["max_logit_err"] = float(np.max(np.abs(g["logit"][ib] - zr) / np.maximum(np.abs(zr), 1.0)))
+            res[prec] = r
+        out[tag] = res
+    out["trained"]["train"] = {"steps": train_steps, "events": sum(b.n_events for b in tbatches),
+                               "loss_first": round(l0, 5), "loss_last": round(l1, 5)}
+    log(f"quality: {json.dumps(out)}")
+    return out
+
+
 def run_batched(velo, synth, torch, wl, batch, hits, blob, prec, steps, warmup, graph=False, latency=False,
                 autotune=True):
     import numpy as np
@@ -206,6 +274,8 @@ def main():
     ap.add_argument("--graph", action="store_true", help="also time hipGraph replays of the whole path")
     ap.add_argument("--latency", action="store_true", help="per-batch p50/p99 latency (with --graph: of replays)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the built-in launch parameters")
+    ap.add_argument("--no-quality", action="store_true", help="skip the track-finding quality block")
+    ap.add_argument("--quality-steps", type=int, default=300, help="training steps before the quality block")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -237,6 +307,12 @@ def main():
     training = None
     if not args.no_train and args.workload == "batch256":
         training = run_training(velo, synth, torch, max(5, args.steps // 2), 2)
+
+    quality = None
+    if not args.no_quality and wl.hidden <= 64:          # the training form covers H <= 64
+        quality = run_quality(velo, synth, torch, wl, batch, blob,
+                              ["fp32"] + [p for p in ("bf16", "fp8") if p in [args.precision] + list(variants)],
+                              args.quality_steps)
 
     per_event = None
     if not args.no_per_event and wl.hidden <= 64:
@@ -290,7 +366,7 @@ def main():
            "hits_per_s": main_res["hits_per_s"],
            "stage_ms_per_step": main_res["stage_ms_per_step"],
            "roofline": main_res["roofline"], "cpu_baseline": cpu, "per_event_path": per_event,
-           "variants": variants, "training": training}
+           "variants": variants, "training": training, "quality": quality}
     for k in ("graph", "eager"):
         if k in main_res:
             res[k] = main_res[k]

@@ -1,0 +1,93 @@
+"""Track-finding metrics of a labelled batch (Physics Performance section,
+metrics table), vectorised over the whole batch on the host.
+
+A track is a connected component of >= 3 hits; a particle with >= 3 hits in
+its event is reconstructible; a track matches a particle when >= 70% of its
+hits carry that particle's id.  Efficiency, clone rate and fake rate are pooled
+over all events; hit efficiency and hit purity are means over the matching
+(track, particle) pairs.  A ratio with a zero denominator is 0 and is listed
+under "undefined".
+
+Inputs are the batch-wide arrays the pipeline returns: `labels` (event-local
+component label per hit), `pid` (particle id per hit, -1 for noise, ids local
+to an event) and `event_offsets` [B+1].
+"""
+from __future__ import annotations
+
+import numpy as np
+
+MIN_TRACK_HITS = 3
+MIN_PARTICLE_HITS = 3
+MATCH_NUM, MATCH_DEN = 7, 10      # 70%, compared in integers: 10 * count >= 7 * size
+
+
+def track_metrics(labels, pid, event_offsets) -> dict:
+    labels = np.asarray(labels, np.int64)
+    pid = np.asarray(pid, np.int64)
+    off = np.asarray(event_offsets, np.int64)
+    n = labels.shape[0]
+    ev = np.repeat(np.arange(off.shape[0] - 1, dtype=np.int64), np.diff(off))
+    assert ev.shape[0] == n == pid.shape[0]
+
+    # tracks: (event, label) groups
+    _, track, track_size = np.unique(np.stack([ev, labels], 1), axis=0, return_inverse=True,
+                                     return_counts=True)
+    track = track.reshape(-1)
+    is_track = track_size >= MIN_TRACK_HITS
+    n_tracks = int(is_track.sum())
+
+    # particles: (event, pid) groups over signal hits
+    sig = pid >= 0
+    _, part, part_size = np.unique(np.stack([ev[sig], pid[sig]], 1), axis=0, return_inverse=True,
+                                   return_counts=True)
+    part = part.reshape(-1)
+    n_particles = int((part_size >= MIN_PARTICLE_HITS).sum())
+
+    # (track, particle) hit counts
+    t_sig = track[sig]
+    pairs, pair_count = np.unique(np.stack([t_sig, part], 1), axis=0, return_counts=True)
+    pt, pp = pairs[:, 0], pairs[:, 1]
+    match = is_track[pt] & (MATCH_DEN * pair_count >= MATCH_NUM * track_size[pt])
+    pt, pp, pc = pt[match], pp[match], pair_count[match]
+    n_pairs = int(pt.shape[0])
+    n_matched = int(np.unique(pp).shape[0])
+    n_fake = n_tracks - n_pairs
+    undefined = []
+
+    def ratio(num, den, name):
+        if den == 0:
+            undefined.append(name)
+            return 0.0
+        return float(num) / float(den)
+
+    return {
+        "efficiency": ratio(n_matched, n_particles, "efficiency"),
+        "clone_rate": ratio(n_pairs - n_matched, n_pairs, "clone_rate"),
+        "fake_rate": ratio(n_fake, n_tracks, "fake_rate"),
+        "hit_efficiency": ratio(np.sum(pc / part_size[pp]), n_pairs, "hit_efficiency"),
+        "hit_purity": ratio(np.sum(pc / track_size[pt]), n_pairs, "hit_purity"),
+        "n_particles": n_particles, "n_tracks": n_tracks, "n_matched_particles": n_matched,
+        "n_pairs": n_pairs, "n_fake": n_fake, "undefined": undefined,
+    }
+
+
+def edge_keys(off, src, dst) -> np.ndarray:
+    """One int64 key per edge: (event, event-local src, event-local dst)."""
+    ev = np.repeat(np.arange(len(off) - 1, dtype=np.int64), np.diff(np.asarray(off, np.int64)))
+    return (ev << 42) | (np.asarray(src, np.int64) << 21) | np.asarray(dst, np.int64)
+
+
+def edge_agreement(a_off, a_src, a_dst, a_keep, b_off, b_src, b_dst, b_keep) -> dict:
+    """Agreement of the keep decisions of two edge sets of one batch, over
+    the union of their edges (an edge absent from a set counts as rejected
+    there), and the Jaccard overlap of the two edge sets."""
+    ka, kb = edge_keys(a_off, a_src, a_dst), edge_keys(b_off, b_src, b_dst)
+    u = np.union1d(ka, kb)
+    da = np.zeros(u.shape[0], bool)
+    db = np.zeros(u.shape[0], bool)
+    da[np.searchsorted(u, ka)] = np.asarray(a_keep, bool)
+    db[np.searchsorted(u, kb)] = np.asarray(b_keep, bool)
+    inter = np.intersect1d(ka, kb).shape[0]
+    return {"decision_agreement": float((da == db).mean()) if u.shape[0] else 1.0,
+            "jaccard": float(inter / u.shape[0]) if u.shape[0] else 1.0,
+            "n_union": int(u.shape[0])}

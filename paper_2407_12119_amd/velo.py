@@ -161,6 +161,7 @@ class Context:
                  max_edges: Optional[int] = None, max_events: int = 1024, max_event_hits: int = 16384,
                  training: bool = False):
         self._lib = lib()
+        self._train_gen = 0
         self.hidden, self.iters, self.k_max = hidden, iters, k_max
         if max_edges is None:
             max_edges = max(1, k_max * max_hits)
@@ -309,6 +310,7 @@ class Context:
         hc = hits.c()
         self._raise(self._lib.velo_train_forward(self._h, C.byref(hc), C.byref(oc), C.c_void_p(params.data_ptr()),
                                                  _stream()), "velo_train_forward")
+        self._train_gen += 1          # the checkpoints now belong to this call
         if check:
             self.check()
         return graph
