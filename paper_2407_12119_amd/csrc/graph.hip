@@ -319,7 +319,8 @@ __global__ void k_globalise(int B, const int *__restrict__ off, const int *__res
     bool err = false;
     for (int q = e0 + threadIdx.x; q < e1; q += blockDim.x) {
         const int a = esrc[q], c = edst[q];
-        if (a < 0 || a >= n || c < 0 || c >= n) {
+        // edges must come grouped by source (non-decreasing esrc)
+        if (a < 0 || a >= n || c < 0 || c >= n || (q > e0 && esrc[q - 1] > a)) {
             err = true;
             src_g[q] = s;
             dst_g[q] = s;

@@ -172,10 +172,12 @@ def test_backward_against_finite_differences():
     print(f"  {smooth} of {len(picks)} oracle-difference probes agree", flush=True)
     assert smooth >= len(picks) // 2
 
+    # L is exactly linear in the classifier's output layer, so a large step
+    # has no truncation error and keeps float32 rounding of the forward small
     a_, b_ = offs["cls1"]
     for idx in range(a_, b_, 7):
         t = float(blob[idx])
-        h = 1e-2 * max(abs(t), 0.05)
+        h = 0.5
         pp, pm = params.clone(), params.clone()
         pp[idx] = t + h
         pm[idx] = t - h
