@@ -47,7 +47,35 @@ def edge_net_work(H, prec, n_edges, n_hits):
     return flops, nbytes
 
 
-def roofline(stages, H, prec, n_edges, n_hits):
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "edge_net_traffic.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2407_12119_amd", "csrc", f) for f in ("gnn.hip", "mfma.h", "internal.h")]
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha1()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(prec, workload):
+    """HBM bytes per edge-network launch from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary, if it was taken on the current kernel
+    source and this workload; else None."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    e = t.get(workload, {}).get(prec)
+    if not e or t.get("source_sha1") != kernel_source_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def roofline(stages, H, prec, n_edges, n_hits, workload):
     ms, n = stages["edge_net"]
     if not n:
         return None
@@ -58,11 +86,11 @@ def roofline(stages, H, prec, n_edges, n_hits):
         achieved = flops / (avg_ms * 1e-3) / 1e12
         return {"kernel": f"edge network ({prec} MFMA)", "bound": "mfma", "achieved": round(achieved, 3),
                 "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS[prec], 4),
-                "traffic": None, "avg_launch_ms": round(avg_ms, 4), "flops_per_launch": flops,
+                "traffic": measured_traffic(prec, workload), "avg_launch_ms": round(avg_ms, 4), "flops_per_launch": flops,
                 "bytes_per_launch": nbytes, "arith_intensity": round(flops / nbytes, 1)}
     achieved = nbytes / (avg_ms * 1e-3) / 1e9
     return {"kernel": f"edge network ({prec} MFMA)", "bound": "hbm", "achieved": round(achieved, 1),
-            "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+            "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(prec, workload),
             "avg_launch_ms": round(avg_ms, 4), "flops_per_launch": flops, "bytes_per_launch": nbytes,
             "arith_intensity": round(flops / nbytes, 1),
             "mfma_frac": round(flops / (avg_ms * 1e-3) / 1e12 / PEAK_TFLOPS[prec], 4)}
@@ -152,7 +180,18 @@ def run_quality(velo, synth, torch, wl, batch, centred_blob, precisions, train_s
             ctx.set_params(torch.from_numpy(blob).cuda())
             if prec == "fp8":
                 ctx.calibrate(velo.DeviceHits.from_batch(synth.calibration_batch(wl, 16)))
-            g = velo.graph_to_host(ctx.infer(hits), batch.n_hits)
+            dev = ctx.infer(hits)
+            g = velo.graph_to_host(dev, batch.n_hits)
+            same = None
+            if ref is not None:
+                # this precision's GNN and components on the fp32 graph: the
+                # GNN's own error, free of graph differences
+                gs = {k: (v.clone() if hasattr(v, "clone") else v) for k, v in ref_dev.items()}
+                ctx.gnn(hits, gs)
+                ctx.components(hits, gs)
+                same = velo.graph_to_host(gs, batch.n_hits)
+            else:
+                ref_dev = {k: (v.clone() if hasattr(v, "clone") else v) for k, v in dev.items()}
             ctx.close()
             m = metrics.track_metrics(g["labels"], batch.pid, batch.event_offsets)
             r = {k: round(m[k], 5) for k in ("efficiency", "clone_rate", "fake_rate", "hit_efficiency",
@@ -174,6 +213,15 @@ def run_quality(velo, synth, torch, wl, batch, centred_blob, precisions, train_s
                 if ia.size:
                     zr = ref["logit"][ia].astype(np.float64)
                     r["max_logit_err"] = float(np.max(np.abs(g["logit"][ib] - zr) / np.maximum(np.abs(zr), 1.0)))
+                zr = ref["logit"].astype(np.float64)
+                dz = np.abs(same["logit"] - zr) / np.maximum(np.abs(zr), 1.0)
+                ms = metrics.track_metrics(same["labels"], batch.pid, batch.event_offsets)
+                r["on_fp32_graph"] = {
+                    "max_logit_err": round(float(dz.max()), 6) if dz.size else 0.0,
+                    "p99_logit_err": round(float(np.percentile(dz, 99)), 6) if dz.size else 0.0,
+                    "decision_agreement": round(float(np.mean((same["logit"] >= wl.edge_logit_min) ==
+                                                              (ref["logit"] >= wl.edge_logit_min))), 6),
+                    "d_efficiency_pts": round(100 * (ms["efficiency"] - res[precisions[0]]["efficiency"]), 4)}
             res[prec] = r
         out[tag] = res
     out["trained"]["train"] = {"steps": train_steps, "events": sum(b.n_events for b in tbatches),
@@ -221,9 +269,9 @@ def run_batched(velo, synth, torch, wl, batch, hits, blob, prec, steps, warmup, 
     res = {"value": round(batch.n_events * steps / dt, 2), "ms_per_step": round(1e3 * dt / steps, 4),
            "hits_per_s": round(batch.n_hits * steps / dt, 1), "edges": n_edges,
            "stage_ms_per_step": {k: round(v[0] / steps, 4) for k, v in stages.items()},
-           "roofline": roofline(stages, wl.hidden, prec, n_edges, batch.n_hits)}
+           "roofline": roofline(stages, wl.hidden, prec, n_edges, batch.n_hits, wl.name)}
     if tuned is not None:
-        res["autotune"] = {k: v for k, v in tuned.items() if k in ("knn", "edge_enc", "messages", "node_net",
+        res["autotune"] = {k: v for k, v in tuned.items() if k in ("edge_enc", "messages", "node_net",
                                                                    "edge_net", "edge_cls")}
     log(f"{prec}: {res['ms_per_step']:.3f} ms/step, {res['value']:.1f} events/s")
     if graph or latency:
@@ -275,12 +323,15 @@ def main():
     ap.add_argument("--latency", action="store_true", help="per-batch p50/p99 latency (with --graph: of replays)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the built-in launch parameters")
     ap.add_argument("--no-quality", action="store_true", help="skip the track-finding quality block")
-    ap.add_argument("--quality-steps", type=int, default=300, help="training steps before the quality block")
+    ap.add_argument("--quality-steps", type=int, default=600, help="training steps before the quality block")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="first run a float32 add of this size (reads and writes known bytes): the reference "
+                         "kernel that scales the HBM traffic counters of a profiled run")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU: events are independent, so the path shards by events "
-              "with no exchange; multi-GPU runs are not part of this build (use --gpus 1).",
+              "with no exchange; multi-GPU runs are not implemented (use --gpus 1).",
               file=sys.stderr)
         sys.exit(2)
 
@@ -288,6 +339,15 @@ def main():
     import torch
 
     from paper_2407_12119_amd import synth, velo
+
+    if args.copy_probe_mib > 0:
+        n = args.copy_probe_mib * (1 << 20) // 4
+        x = torch.ones(n, device="cuda")
+        y = torch.empty_like(x)
+        torch.add(x, 1.0, out=y)
+        torch.cuda.synchronize()
+        log(f"copy probe: {4 * n} bytes read, {4 * n} bytes written")
+        del x, y
 
     wl = synth.WORKLOADS[args.workload]
     log(f"generating {wl.n_events} events ({wl.name})")
