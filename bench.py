@@ -230,6 +230,37 @@ def run_quality(velo, synth, torch, wl, batch, centred_blob, precisions, train_s
     return out
 
 
+def transfer_times(torch, batch, out, n_edges, reps=5):
+    """Host-device copies around one batch, outside the timed region: the hit
+    arrays to the device and labels, edge pairs and logits back, with pinned
+    host buffers (median of a few repetitions)."""
+    import numpy as np
+    host = [torch.from_numpy(np.ascontiguousarray(a)).pin_memory()
+            for a in (batch.event_offsets.astype(np.int32), batch.x, batch.y, batch.z, batch.plane.astype(np.int32))]
+    dev = [torch.empty_like(h, device="cuda") for h in host]
+    srcs = [out["labels"][:batch.n_hits], out["edge_src"][:n_edges], out["edge_dst"][:n_edges],
+            out["edge_logit"][:n_edges], out["edge_offsets"]]
+    back = [torch.empty(t.shape, dtype=t.dtype, pin_memory=True) for t in srcs]
+    h2d, d2h = [], []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for d, h in zip(dev, host):
+            d.copy_(h, non_blocking=True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for b, d in zip(back, srcs):
+            b.copy_(d, non_blocking=True)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        h2d.append(t1 - t0)
+        d2h.append(t2 - t1)
+    nb_in = sum(h.numel() * h.element_size() for h in host)
+    nb_out = sum(b.numel() * b.element_size() for b in back)
+    return {"h2d_ms": round(1e3 * float(np.median(h2d)), 4), "h2d_bytes": nb_in,
+            "d2h_ms": round(1e3 * float(np.median(d2h)), 4), "d2h_bytes": nb_out}
+
+
 def run_batched(velo, synth, torch, wl, batch, hits, blob, prec, steps, warmup, graph=False, latency=False,
                 autotune=True):
     import numpy as np
@@ -270,6 +301,19 @@ def run_batched(velo, synth, torch, wl, batch, hits, blob, prec, steps, warmup, 
            "hits_per_s": round(batch.n_hits * steps / dt, 1), "edges": n_edges,
            "stage_ms_per_step": {k: round(v[0] / steps, 4) for k, v in stages.items()},
            "roofline": roofline(stages, wl.hidden, prec, n_edges, batch.n_hits, wl.name)}
+    # events/s of the path cut after each stage (cumulative, in path order)
+    order = ["prepare", "embed", "knn", "compact", "lists", "node_enc", "edge_enc", "messages", "node_net",
+             "edge_net", "edge_cls", "components"]
+    acc, cum = 0.0, {}
+    for k in order:
+        acc += res["stage_ms_per_step"].get(k, 0.0)
+        if acc > 0:
+            cum[k] = round(batch.n_events / (acc * 1e-3), 1)
+    res["cumulative_events_per_s"] = cum
+    tr = transfer_times(torch, batch, out, n_edges)
+    tr["pcie_inclusive_events_per_s"] = round(batch.n_events / (1e-3 * (tr["h2d_ms"] + res["ms_per_step"] +
+                                                                        tr["d2h_ms"])), 1)
+    res["transfer"] = tr
     if tuned is not None:
         res["autotune"] = {k: v for k, v in tuned.items() if k in ("edge_enc", "messages", "node_net",
                                                                    "edge_net", "edge_cls")}

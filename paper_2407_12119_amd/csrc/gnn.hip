@@ -175,34 +175,35 @@ constexpr int nseg() { return MODE == EDGE_ENC ? 2 : (MODE == CLS_ONLY ? 0 : 3);
 
 template <class P, int H, int MODE, bool CLS>
 constexpr size_t mlp_lds() {
-    return (nseg<MODE>() ? frag_bytes<P>(H, nseg<MODE>() * H) + frag_bytes<P>(H, H) : 0) +
-           (CLS ? frag_bytes<P>(H, H) : 0);
+    return (nseg<MODE>() ? frag_bytes<P>(H, nseg<MODE>() * H) + frag_bytes<P>(H, H) + sizeof(float) * 2 * H : 0) +
+           (CLS ? frag_bytes<P>(H, H) + sizeof(float) * 2 * H : 0);
 }
 
 template <class P, int H>
-__device__ inline void classify(const typename P::wfrag_t *sC1, const float *__restrict__ Pw, int64_t o_c1,
-                                int64_t o_c2, const f32x4 *ev, const MlpScales &S, float *amax, int lane, bool ok,
-                                int64_t q, float *__restrict__ logit) {
+// sCB: the classifier's hidden bias divided by its fp8 descale factor, then
+// its output weights (2H floats in LDS); b_out: its output bias
+__device__ inline void classify(const typename P::wfrag_t *sC1, const float *sCB, float b_out, const f32x4 *ev,
+                                const MlpScales &S, float *amax, int lane, bool ok, int64_t q,
+                                float *__restrict__ logit) {
     constexpr int MO = H / 16, KB = H / P::KBLK;
     const int g = lane >> 4;
     if (amax) record_amax(absmax4<MO>(ev), amax);
     typename P::frag_t xe[KB];
     P::template chain<MO>(ev, xe, S.ix1);
     f32x4 hc[MO];
-    zero<MO>(hc);
+    load_bias<MO>(sCB, hc, g);
     gemm<P, MO, KB>(sC1, xe, hc, lane);
     if (P::kScaled) rescale<MO>(hc, S.d1);
-    f32x4 rb[MO], w2[MO];
-    load_bias<MO>(Pw + o_c1 + H * H, rb, g);
-    load_bias<MO>(Pw + o_c2, w2, g);
+    f32x4 w2[MO];
+    load_bias<MO>(sCB + H, w2, g);
     float part = 0.f;
 #pragma unroll
     for (int mo = 0; mo < MO; mo++)
 #pragma unroll
-        for (int i = 0; i < 4; i++) part += w2[mo][i] * fmaxf(hc[mo][i] + rb[mo][i], 0.f);
+        for (int i = 0; i < 4; i++) part += w2[mo][i] * fmaxf(hc[mo][i], 0.f);
     part += __shfl_xor(part, 16);
     part += __shfl_xor(part, 32);
-    if (g == 0 && ok) logit[q] = part + Pw[o_c2 + H];
+    if (g == 0 && ok) logit[q] = part + b_out;
 }
 
 template <class P, int H, int MODE, bool CLS>
@@ -215,10 +216,26 @@ __global__ __launch_bounds__(512) void k_mlp(MlpArgs A) {
     W *sW1 = (W *)lds_raw;
     W *sW2 = (W *)(lds_raw + (NSEG ? frag_bytes<P>(H, K1) : 0));
     W *sC1 = (W *)(lds_raw + (NSEG ? frag_bytes<P>(H, K1) + frag_bytes<P>(H, H) : 0));
+    // biases, pre-divided by the fp8 descale factor: they initialise the MFMA
+    // accumulators (sB: this MLP's two layers; sCB: the classifier's hidden
+    // layer, then its output weights)
+    float *sB = (float *)(lds_raw + (NSEG ? frag_bytes<P>(H, K1) + frag_bytes<P>(H, H) : 0) +
+                          (CLS ? frag_bytes<P>(H, H) : 0));
+    float *sCB = sB + (NSEG ? 2 * H : 0);
     const MlpScales SC = read_scales(A.sc), SCc = read_scales(A.sc_cls);
+    if (CLS)
+        for (int t = threadIdx.x; t < H; t += blockDim.x) {
+            sCB[t] = A.P[A.o_c1 + (int64_t)H * H + t] / SCc.d1;
+            sCB[H + t] = A.P[A.o_c2 + t];
+        }
+    const float b_out = CLS ? A.P[A.o_c2 + H] : 0.f;
     if (NSEG) {
         stage<P>(sW1, A.P + A.o_w1, H, K1, MO, SC.iw1);
         stage<P>(sW2, A.P + A.o_w2, H, H, MO, SC.iw2);
+        for (int t = threadIdx.x; t < H; t += blockDim.x) {
+            sB[t] = A.P[A.o_w1 + (int64_t)H * K1 + t] / SC.d1;
+            sB[H + t] = A.P[A.o_w2 + (int64_t)H * H + t] / SC.d2;
+        }
     }
     if (CLS) stage<P>(sC1, A.P + A.o_c1, H, H, MO, SCc.iw1);
     __syncthreads();
@@ -227,11 +244,6 @@ __global__ __launch_bounds__(512) void k_mlp(MlpArgs A) {
     const int lane = threadIdx.x & 63, n = lane & 15, g = lane >> 4;
     int64_t N = A.n_host;
     if (A.n_dev) N = min((int64_t)*A.n_dev, A.n_host);
-    f32x4 rb1[MO], rb2[MO];
-    if (NSEG) {
-        load_bias<MO>(A.P + A.o_w1 + (int64_t)H * K1, rb1, g);
-        load_bias<MO>(A.P + A.o_w2 + (int64_t)H * H, rb2, g);
-    }
     const S *sa = (const S *)A.a;
     const int64_t units = (N + 15) >> 4;
     constexpr int NX = NSEG > 0 ? NSEG * KB : KB;
@@ -293,19 +305,18 @@ __global__ __launch_bounds__(512) void k_mlp(MlpArgs A) {
                 record_amax(mx, A.amax);
             }
             f32x4 hid[MO];
-            zero<MO>(hid);
+            load_bias<MO>(sB, hid, g);
             gemm<P, MO, NSEG * KB>(sW1, X, hid, lane);
             if (P::kScaled) rescale<MO>(hid, SC.d1);
-            bias_relu<MO>(hid, rb1);
+            relu<MO>(hid);
             if (A.amax) record_amax(absmax4<MO>(hid), A.amax + 1);
             typename P::frag_t xh[KB];
             P::template chain<MO>(hid, xh, SC.ix2);
-            zero<MO>(o);
+            load_bias<MO>(sB + H, o, g);
             gemm<P, MO, KB>(sW2, xh, o, lane);
             if (P::kScaled) rescale<MO>(o, SC.d2);
 #pragma unroll
             for (int mo = 0; mo < MO; mo++) {
-                o[mo] += rb2[mo];
                 if (MODE != EDGE_ENC) {   // residual (Sec. 5.2), from the unquantised state
                     if constexpr (P::kScaled) {
                         o[mo] += P::load4(sa + qc * H + P::stored(mo, g));
@@ -320,7 +331,7 @@ __global__ __launch_bounds__(512) void k_mlp(MlpArgs A) {
 #pragma unroll
             for (int mo = 0; mo < MO; mo++) o[mo] = P::load4(sa + qc * H + P::stored(mo, g));
         }
-        if (CLS) classify<P, H>(sC1, A.P, A.o_c1, A.o_c2, o, SCc, A.amax_cls, lane, ok, q, A.logit);
+        if (CLS) classify<P, H>(sC1, sCB, b_out, o, SCc, A.amax_cls, lane, ok, q, A.logit);
     }
 }
 

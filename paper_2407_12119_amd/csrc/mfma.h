@@ -230,6 +230,14 @@ __device__ inline void load_bias(const float *__restrict__ b, f32x4 *rb, int g) 
 }
 
 template <int MO>
+__device__ inline void relu(f32x4 *acc) {
+#pragma unroll
+    for (int mo = 0; mo < MO; mo++)
+#pragma unroll
+        for (int i = 0; i < 4; i++) acc[mo][i] = fmaxf(acc[mo][i], 0.f);
+}
+
+template <int MO>
 __device__ inline void bias_relu(f32x4 *acc, const f32x4 *rb) {
 #pragma unroll
     for (int mo = 0; mo < MO; mo++)

@@ -225,6 +225,25 @@ def test_k_max_saturation_and_single_plane_pairs():
     assert np.bincount(g["src"], minlength=n).max() == 4
 
 
+def test_dense_event_candidate_windows_beyond_lds():
+    """One event of ~17k hits whose plane windows hold up to ~2,200
+    candidates: windows above the LDS staging size are read through L2 and
+    must give the oracle's graph exactly, like the staged ones."""
+    wl = synth.WORKLOADS["batch256"]
+    ev = synth.make_event(synth.EventRecipe(1500, 1.0, 1500.0, 0.05), synth.event_rng(77, 0))
+    counts = np.bincount(ev.plane, minlength=synth.N_PLANES)
+    window = counts[1:] + np.concatenate([counts[2:], [0]])
+    assert window.max() > 1024 and window.min() < 1024
+    batch = synth.to_batch([ev])
+    ctx, hits, blob = _setup(wl, batch)
+    emb = ctx.embed(hits)
+    g = velo.graph_to_host(ctx.build_graph(hits, emb), batch.n_hits)
+    rp, col = oracle.neighbours(ev.plane, emb.cpu().numpy(), oracle.d2max_f32(wl.radius), wl.k_max)
+    src, dst = oracle.csr_to_edges(rp, col)
+    np.testing.assert_array_equal(g["src"], src)
+    np.testing.assert_array_equal(g["dst"], dst)
+
+
 @pytest.mark.slow
 def test_full_batch256_sampled():
     """The 256-event workload in the benchmark's launch configuration: every
