@@ -129,17 +129,22 @@ def run_training(velo, synth, torch, steps, warmup):
 
     for t in range(1, warmup + 1):
         step(t)
+    ctx.set_timing(True)
+    ctx.read_timing()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for t in range(warmup + 1, warmup + steps + 1):
         step(t)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    stages = ctx.read_timing()
+    ctx.set_timing(False)
     ctx.check()
     log(f"training: {1e3 * dt / steps:.3f} ms/step")
     return {"workload": f"{wl.name}: {batch.n_events} events, {batch.n_hits} hits, {n} edges, H={wl.hidden}, "
                         f"n={wl.iters}, fp32, weighted BCE (pos_weight {pw:.2f}), Adam",
-            "steps_per_s": round(steps / dt, 2), "ms_per_step": round(1e3 * dt / steps, 3)}
+            "steps_per_s": round(steps / dt, 2), "ms_per_step": round(1e3 * dt / steps, 3),
+            "stage_ms_per_step": {k: round(v[0] / steps, 4) for k, v in stages.items() if v[1]}}
 
 
 def run_quality(velo, synth, torch, wl, batch, centred_blob, precisions, train_steps):

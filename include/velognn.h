@@ -180,7 +180,12 @@ typedef enum {
     VELO_STAGE_EDGE_NET = 9,   /* edge network, one launch per step except the last */
     VELO_STAGE_EDGE_CLS = 10,  /* last step's edge network fused with the edge classifier */
     VELO_STAGE_COMPONENTS = 11,/* edge cut and connected components (Sec. 7.3) */
-    VELO_N_STAGES = 12
+    VELO_STAGE_BCE = 12,       /* training: weighted BCE and dL/dz */
+    VELO_STAGE_BWD_MLP = 13,   /* training: recompute and back-propagate every MLP (dX) */
+    VELO_STAGE_BWD_DW = 14,    /* training: split-K weight gradients and their reduction */
+    VELO_STAGE_BWD_GRAPH = 15, /* training: duals of the gathers and message sums */
+    VELO_STAGE_ADAM = 16,      /* training: Adam update */
+    VELO_N_STAGES = 17
 } velo_stage;
 
 /* Enable (1) or disable (0) per-stage timing: while enabled every call

@@ -465,7 +465,10 @@ velo_status velo_bce(velo_ctx *c, const float *logit, const uint8_t *y, float po
     if (!c->cfg.training) return fail(c, VELO_ERR_UNSUPPORTED, "context created without training = 1");
     if (n < 0 || !loss || (n > 0 && (!logit || !y || !dlogit))) return fail(c, VELO_ERR_INVALID_ARG, "velo_bce arguments");
     DeviceGuard gd(c->device);
-    launch_bce(c, logit, y, pos_weight, n, loss, dlogit, (hipStream_t)stream);
+    {
+        StageTimer t(c, VELO_STAGE_BCE, (hipStream_t)stream);
+        launch_bce(c, logit, y, pos_weight, n, loss, dlogit, (hipStream_t)stream);
+    }
     return device_status(c, "velo_bce");
 }
 
@@ -488,7 +491,10 @@ velo_status velo_adam_step(velo_ctx *c, float *params, const float *grad, float 
     if (n < 0 || step < 1 || (n > 0 && (!params || !grad || !m || !v)))
         return fail(c, VELO_ERR_INVALID_ARG, "velo_adam_step arguments");
     DeviceGuard gd(c->device);
-    if (n > 0) launch_adam(params, grad, m, v, n, lr, b1, b2, eps, step, (hipStream_t)stream);
+    if (n > 0) {
+        StageTimer t(c, VELO_STAGE_ADAM, (hipStream_t)stream);
+        launch_adam(params, grad, m, v, n, lr, b1, b2, eps, step, (hipStream_t)stream);
+    }
     return device_status(c, "velo_adam_step");
 }
 

@@ -478,8 +478,8 @@ void backward_h(velo_ctx *c, const velo_hits *hits, const float *Pw, const float
     BwdArgs cl = base;
     cl.n_dev = w.n_edges; cl.n_host = Ecap; cl.a = ek(n); cl.dout = dlogit; cl.dres = w.g_e[0];
     cl.o_w1 = L.cls[0].w; cl.o_w2 = L.cls[1].w;
-    run_bwd<H, B_CLS>(c, cl, s);
-    run_dw<H, B_CLS>(c, cl, dparams + L.cls[0].w, s);
+    { StageTimer t(c, VELO_STAGE_BWD_MLP, s); run_bwd<H, B_CLS>(c, cl, s); }
+    { StageTimer t(c, VELO_STAGE_BWD_DW, s); run_dw<H, B_CLS>(c, cl, dparams + L.cls[0].w, s); }
     int ce = 0, ch = 0;
     if (N > 0) k_zero<<<blocks_for(N * H, 256, 4096), 256, 0, s>>>(w.g_h[0], N * H);
     for (int k = n - 1; k >= 0; k--) {
@@ -488,11 +488,13 @@ void backward_h(velo_ctx *c, const velo_hits *hits, const float *Pw, const float
         ed.n_dev = w.n_edges; ed.n_host = Ecap; ed.a = ek(k); ed.b = hk(k + 1);
         ed.dout = w.g_e[ce]; ed.dres = w.g_e[ce ^ 1]; ed.dx1 = w.g_xs; ed.dx2 = w.g_xd;
         ed.o_w1 = L.edge[k][0].w; ed.o_w2 = L.edge[k][1].w;
-        run_bwd<H, B_EDGE>(c, ed, s);
-        run_dw<H, B_EDGE>(c, ed, dparams + L.edge[k][0].w, s);
-        if (N > 0)
+        { StageTimer t(c, VELO_STAGE_BWD_MLP, s); run_bwd<H, B_EDGE>(c, ed, s); }
+        { StageTimer t(c, VELO_STAGE_BWD_DW, s); run_dw<H, B_EDGE>(c, ed, dparams + L.edge[k][0].w, s); }
+        if (N > 0) {
+            StageTimer t(c, VELO_STAGE_BWD_GRAPH, s);
             k_gather_add<H><<<persistent_grid(c, 16), 256, 0, s>>>(N, w.out_ptr, w.out_list, w.in_ptr, w.in_list,
                                                                  w.g_xs, w.g_xd, w.g_h[ch], true, w.flags);
+        }
         ce ^= 1;
         // node network k
         BwdArgs nd = base;
@@ -500,34 +502,38 @@ void backward_h(velo_ctx *c, const velo_hits *hits, const float *Pw, const float
         nd.dout = w.g_h[ch]; nd.dres = w.g_h[ch ^ 1]; nd.dx1 = w.g_m;
         nd.o_w1 = L.node[k][0].w; nd.o_w2 = L.node[k][1].w;
         if (N > 0) {
+            StageTimer t(c, VELO_STAGE_BWD_MLP, s);
             run_bwd<H, B_NODE>(c, nd, s);
-            run_dw<H, B_NODE>(c, nd, dparams + L.node[k][0].w, s);
-        } else {
-            run_dw<H, B_NODE>(c, nd, dparams + L.node[k][0].w, s);
         }
+        { StageTimer t(c, VELO_STAGE_BWD_DW, s); run_dw<H, B_NODE>(c, nd, dparams + L.node[k][0].w, s); }
         ch ^= 1;
         // message sums of step k
-        if (N > 0)
+        if (N > 0) {
+            StageTimer t(c, VELO_STAGE_BWD_GRAPH, s);
             k_msg_bwd<H><<<eb, 256, 0, s>>>(w.n_edges, Ecap, w.src_g, w.dst_g, w.g_m, w.g_e[ce], w.flags);
+        }
     }
     // edge encoder
     BwdArgs ee = base;
     ee.n_dev = w.n_edges; ee.n_host = Ecap; ee.a = hk(0); ee.dout = w.g_e[ce]; ee.dx1 = w.g_xs; ee.dx2 = w.g_xd;
     ee.o_w1 = L.eenc[0].w; ee.o_w2 = L.eenc[1].w;
-    run_bwd<H, B_EDGE_ENC>(c, ee, s);
-    run_dw<H, B_EDGE_ENC>(c, ee, dparams + L.eenc[0].w, s);
-    if (N > 0)
+    { StageTimer t(c, VELO_STAGE_BWD_MLP, s); run_bwd<H, B_EDGE_ENC>(c, ee, s); }
+    { StageTimer t(c, VELO_STAGE_BWD_DW, s); run_dw<H, B_EDGE_ENC>(c, ee, dparams + L.eenc[0].w, s); }
+    if (N > 0) {
+        StageTimer t(c, VELO_STAGE_BWD_GRAPH, s);
         k_gather_add<H><<<persistent_grid(c, 16), 256, 0, s>>>(N, w.out_ptr, w.out_list, w.in_ptr, w.in_list, w.g_xs,
                                                              w.g_xd, w.g_h[ch], true, w.flags);
+    }
     // node encoder
     BwdArgs ne = base;
     ne.n_dev = nullptr; ne.n_host = N; ne.dout = w.g_h[ch]; ne.x = hits->x; ne.y = hits->y; ne.z = hits->z;
     ne.o_w1 = L.nenc[0].w; ne.o_w2 = L.nenc[1].w;
     if (N > 0) {
+        StageTimer t(c, VELO_STAGE_BWD_MLP, s);
         constexpr size_t lds = frag_bytes<P>(H, H) + sizeof(float) * H * 4;
         k_bwd_node_enc<H><<<persistent_grid(c, 2), kBwdBlock, lds, s>>>(ne);
     }
-    run_dw<H, B_NODE_ENC>(c, ne, dparams + L.nenc[0].w, s);
+    { StageTimer t(c, VELO_STAGE_BWD_DW, s); run_dw<H, B_NODE_ENC>(c, ne, dparams + L.nenc[0].w, s); }
 }
 
 // Adam with bias correction (one float32 parameter per thread).
