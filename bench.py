@@ -320,7 +320,7 @@ def run_batched(velo, synth, torch, wl, batch, hits, blob, prec, steps, warmup, 
                                                                         tr["d2h_ms"])), 1)
     res["transfer"] = tr
     if tuned is not None:
-        res["autotune"] = {k: v for k, v in tuned.items() if k in ("edge_enc", "messages", "node_net",
+        res["autotune"] = {k: v for k, v in tuned.items() if k in ("knn", "edge_enc", "messages", "node_net",
                                                                    "edge_net", "edge_cls")}
     log(f"{prec}: {res['ms_per_step']:.3f} ms/step, {res['value']:.1f} events/s")
     if graph or latency:

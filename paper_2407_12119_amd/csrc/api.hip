@@ -507,7 +507,7 @@ velo_status velo_autotune(velo_ctx *c, const velo_hits *h, velo_outputs *o, void
     static const int mlp_cu[kCand] = {0, 0, 1, 2, 0, 1};
     static const int mem_cu[kCand] = {16, 16, 4, 8, 32, 32};
     static const int xcd[kCand] = {0, 1, 1, 1, 1, 0};
-    static const int tunable[] = {VELO_STAGE_EDGE_ENC, VELO_STAGE_MESSAGES, VELO_STAGE_NODE_NET,
+    static const int tunable[] = {VELO_STAGE_KNN, VELO_STAGE_EDGE_ENC, VELO_STAGE_MESSAGES, VELO_STAGE_NODE_NET,
                                   VELO_STAGE_EDGE_NET, VELO_STAGE_EDGE_CLS};
     const bool was_timing = c->timing;
     velo_status st = velo_set_timing(c, 1);
@@ -519,7 +519,7 @@ velo_status velo_autotune(velo_ctx *c, const velo_hits *h, velo_outputs *o, void
     int64_t n[VELO_N_STAGES];
     for (int cand = 0; cand < kCand; cand++) {
         for (int t : tunable) {
-            const bool mem = t == VELO_STAGE_MESSAGES;
+            const bool mem = t == VELO_STAGE_KNN || t == VELO_STAGE_MESSAGES;
             c->tune_per_cu[t] = mem ? mem_cu[cand] : mlp_cu[cand];
             c->tune_xcd[t] = xcd[cand];
         }
@@ -535,7 +535,7 @@ velo_status velo_autotune(velo_ctx *c, const velo_hits *h, velo_outputs *o, void
             }
     }
     for (int t : tunable) {
-        const bool mem = t == VELO_STAGE_MESSAGES;
+        const bool mem = t == VELO_STAGE_KNN || t == VELO_STAGE_MESSAGES;
         c->tune_per_cu[t] = mem ? mem_cu[pick[t]] : mlp_cu[pick[t]];
         c->tune_xcd[t] = xcd[pick[t]];
     }

@@ -249,14 +249,25 @@ __global__ __launch_bounds__(512) void k_mlp(MlpArgs A) {
     constexpr int NX = NSEG > 0 ? NSEG * KB : KB;
     const float ix = SC.ix1;
     // gather the inputs of unit u into X
-    auto load_unit = [&](int64_t u, typename P::frag_t *X) {
+    // fp8 keeps the stored (bf16) state of segment 0 for the residual, so it
+    // is not read twice
+    constexpr bool RAW = P::kScaled && (MODE == NODE || MODE == EDGE);
+    using raw_t = BF16::frag_t;
+    auto load_unit = [&](int64_t u, typename P::frag_t *X, raw_t *R) {
         const int64_t q = u * 16 + n;
         const int64_t qc = q < N ? q : N - 1;
+        if constexpr (RAW) {
+#pragma unroll
+            for (int kb = 0; kb < KB; kb++) {
+                R[kb] = BF16::load((const BF16::state_t *)sa + qc * H, kb, g);
+                X[kb] = P::pack(R[kb], ix);
+            }
+        }
         if (MODE == NODE) {
             const float *m = (const float *)A.b + qc * 2 * H;
 #pragma unroll
             for (int kb = 0; kb < KB; kb++) {
-                X[kb] = P::load(sa + qc * H, kb, g, ix);
+                if constexpr (!RAW) X[kb] = P::load(sa + qc * H, kb, g, ix);
                 X[KB + kb] = P::load_f32(m, kb, g, ix);
                 X[2 * KB + kb] = P::load_f32(m + H, kb, g, ix);
             }
@@ -265,7 +276,7 @@ __global__ __launch_bounds__(512) void k_mlp(MlpArgs A) {
             const int64_t s = A.src_g[qc], d = A.dst_g[qc];
 #pragma unroll
             for (int kb = 0; kb < KB; kb++) {
-                X[kb] = P::load(sa + qc * H, kb, g, ix);
+                if constexpr (!RAW) X[kb] = P::load(sa + qc * H, kb, g, ix);
                 X[KB + kb] = P::load(hb + s * H, kb, g, ix);
                 X[2 * KB + kb] = P::load(hb + d * H, kb, g, ix);
             }
@@ -281,20 +292,26 @@ __global__ __launch_bounds__(512) void k_mlp(MlpArgs A) {
     // memory-bound precisions prefetch the next unit's inputs during the MFMAs
     constexpr bool PREFETCH = sizeof(S) < 4 && NSEG > 0;
     typename P::frag_t Xn[NX];
+    raw_t Rn[RAW ? KB : 1];
     const WaveRange wr = wave_range(units, A.xcd != 0);
     int64_t u = wr.first;
-    if (PREFETCH && u < wr.end) load_unit(u, Xn);
+    if (PREFETCH && u < wr.end) load_unit(u, Xn, Rn);
     for (; u < wr.end; u += wr.step) {
         const int64_t q = u * 16 + n;
         const bool ok = q < N;
         const int64_t qc = ok ? q : N - 1;
         typename P::frag_t X[NX];
+        raw_t R[RAW ? KB : 1];
         if (PREFETCH) {
 #pragma unroll
             for (int k = 0; k < NX; k++) X[k] = Xn[k];
-            if (u + wr.step < wr.end) load_unit(u + wr.step, Xn);
+            if constexpr (RAW) {
+#pragma unroll
+                for (int k = 0; k < KB; k++) R[k] = Rn[k];
+            }
+            if (u + wr.step < wr.end) load_unit(u + wr.step, Xn, Rn);
         } else if (NSEG > 0) {
-            load_unit(u, X);
+            load_unit(u, X, R);
         }
         f32x4 o[MO];
         if (NSEG) {
@@ -317,10 +334,11 @@ __global__ __launch_bounds__(512) void k_mlp(MlpArgs A) {
             if (P::kScaled) rescale<MO>(o, SC.d2);
 #pragma unroll
             for (int mo = 0; mo < MO; mo++) {
-                if (MODE != EDGE_ENC) {   // residual (Sec. 5.2), from the unquantised state
-                    if constexpr (P::kScaled) {
-                        o[mo] += P::load4(sa + qc * H + P::stored(mo, g));
-                    } else {
+                if constexpr (MODE != EDGE_ENC) {   // residual (Sec. 5.2), from the unquantised state
+                    if constexpr (RAW) {
+#pragma unroll
+                        for (int i = 0; i < 4; i++) o[mo][i] += BF16::seg0(R, mo, i);
+                    } else if constexpr (!P::kScaled) {
 #pragma unroll
                         for (int i = 0; i < 4; i++) o[mo][i] += P::seg0(X, mo, i);
                     }

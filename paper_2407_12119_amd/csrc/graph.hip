@@ -5,15 +5,13 @@
 // d2_max, keeping at most k_max per hit.  Hits are sorted by plane inside each
 // event, so the candidates of a hit on plane p are one contiguous index range.
 //
-// Work mapping: one workgroup per (event, plane p).  It stages the
-// embeddings of the event's planes p+1 and p+2 (the candidates of every query
-// on plane p) in LDS once; then one 64-lane wavefront per query hit sweeps the
-// candidates in chunks of 64, computes the float32 distance keys and keeps up
-// to kKeyChunks chunks of keys in registers.  The exact k_max smallest under
-// (d2, index) are found by a bitwise binary search on the float bit pattern
-// of d2 driven by wave ballots (no sorting, no scratch memory), and the
-// survivors are written in index order through ballot prefix counts.  This
-// parallelises over the candidates of a hit as well as over hits.
+// Work mapping: one 64-lane wavefront per query hit.  The lanes sweep the
+// candidate range in chunks of 64, compute the float32 distance keys and keep
+// up to kKeyChunks chunks of keys in registers.  The exact k_max smallest
+// under (d2, index) are found by a bitwise binary search on the float bit
+// pattern of d2 driven by wave ballots (no sorting, no scratch memory), and
+// the survivors are written in index order through ballot prefix counts.
+// This parallelises over the candidates of a hit as well as over hits.
 #include "internal.h"
 
 namespace velo {
@@ -86,106 +84,93 @@ __device__ inline float dist2(f32x4 a, f32x4 b) {
     return s;
 }
 
-__device__ inline unsigned cand_key(const f32x4 *cand, int C, int c, f32x4 q, float d2max) {
+__device__ inline unsigned cand_key(const f32x4 *__restrict__ emb, int64_t base, int C, int c,
+                                    f32x4 q, float d2max) {
     if (c >= C) return kInvalidKey;
-    const float s = dist2(q, cand[c]);
+    const float s = dist2(q, emb[base + c]);
     return s < d2max ? __float_as_uint(s) : kInvalidKey;
 }
 
-// One query hit with embedding q against candidates cand[0..C) (event-local
-// indices c0 + c): writes the kept destinations to out[0..) in index order
-// and returns their number (the whole wave returns the same value).
-__device__ inline int knn_query(const f32x4 *cand, int C, int c0, f32x4 q, float d2max, int kmax, int *out,
-                                int lane) {
-    const int nch = (C + 63) >> 6;
-    unsigned key[kKeyChunks];
-    int m = 0;
-#pragma unroll
-    for (int c = 0; c < kKeyChunks; c++) {
-        key[c] = kInvalidKey;
-        if (c < nch) {
-            key[c] = cand_key(cand, C, c * 64 + lane, q, d2max);
-            m += __popcll(ballot(key[c] != kInvalidKey));
-        }
-    }
-    for (int c = kKeyChunks; c < nch; c++)
-        m += __popcll(ballot(cand_key(cand, C, c * 64 + lane, q, d2max) != kInvalidKey));
+__global__ __launch_bounds__(256) void k_knn(int64_t n_hits, const int *__restrict__ off,
+                                             const int *__restrict__ plane_off,
+                                             const int *__restrict__ hit_event,
+                                             const int *__restrict__ plane,
+                                             const f32x4 *__restrict__ emb, float d2max, int kmax,
+                                             int *__restrict__ nbr, int *__restrict__ deg, int xcd,
+                                             const unsigned *__restrict__ flags) {
+    if (*flags & kErrInput) return;
+    const int lane = threadIdx.x & 63;
+    const WaveRange wr = wave_range(n_hits, xcd != 0);
+    for (int64_t i = wr.first; i < wr.end; i += wr.step) {
+        const int b = hit_event[i];
+        const int64_t s = off[b];
+        const int p = plane[i];
+        const int *po = plane_off + (int64_t)b * kPlaneSlots;
+        const int c0 = po[min(p + 1, VELO_N_PLANES)];
+        const int c1 = po[min(p + 3, VELO_N_PLANES)];
+        const int C = max(c1 - c0, 0);
+        const int64_t base = s + c0;          // batch index of candidate 0
+        const f32x4 q = emb[i];
+        const int nch = (C + 63) >> 6;
+        int *out = nbr + i * kmax;
 
-    // threshold T: the kmax-th smallest key (only needed when m > kmax)
-    unsigned T = 0x7fffffffu;
-    int need_ties = 0;
-    if (m > kmax) {
-        T = 0;
-        for (int bit = 30; bit >= 0; bit--) {
-            const unsigned cnd = T | (1u << bit);
-            int cnt = 0;
+        unsigned key[kKeyChunks];
+        int m = 0;
+#pragma unroll
+        for (int c = 0; c < kKeyChunks; c++) {
+            key[c] = kInvalidKey;
+            if (c < nch) {
+                key[c] = cand_key(emb, base, C, c * 64 + lane, q, d2max);
+                m += __popcll(ballot(key[c] != kInvalidKey));
+            }
+        }
+        for (int c = kKeyChunks; c < nch; c++)
+            m += __popcll(ballot(cand_key(emb, base, C, c * 64 + lane, q, d2max) != kInvalidKey));
+
+        // threshold T: the kmax-th smallest key (only needed when m > kmax)
+        unsigned T = 0x7fffffffu;
+        int need_ties = 0;
+        if (m > kmax) {
+            T = 0;
+            for (int bit = 30; bit >= 0; bit--) {
+                const unsigned cand = T | (1u << bit);
+                int cnt = 0;
+#pragma unroll
+                for (int c = 0; c < kKeyChunks; c++)
+                    if (c < nch) cnt += __popcll(ballot(key[c] < cand));
+                for (int c = kKeyChunks; c < nch; c++)
+                    cnt += __popcll(ballot(cand_key(emb, base, C, c * 64 + lane, q, d2max) < cand));
+                if (cnt < kmax) T = cand;
+            }
+            int less = 0;
 #pragma unroll
             for (int c = 0; c < kKeyChunks; c++)
-                if (c < nch) cnt += __popcll(ballot(key[c] < cnd));
+                if (c < nch) less += __popcll(ballot(key[c] < T));
             for (int c = kKeyChunks; c < nch; c++)
-                cnt += __popcll(ballot(cand_key(cand, C, c * 64 + lane, q, d2max) < cnd));
-            if (cnt < kmax) T = cnd;
+                less += __popcll(ballot(cand_key(emb, base, C, c * 64 + lane, q, d2max) < T));
+            need_ties = kmax - less;
         }
-        int less = 0;
+        // emit survivors in candidate (= destination index) order
+        int written = 0, ties_seen = 0;
+        auto emit = [&](unsigned k, int c) {
+            bool sel;
+            if (m > kmax) {
+                const unsigned long long tie = ballot(k == T);
+                const bool first_ties = ties_seen + lanes_below(tie) < need_ties;
+                sel = k < T || (k == T && first_ties);
+                ties_seen += __popcll(tie);
+            } else {
+                sel = k != kInvalidKey;
+            }
+            const unsigned long long sm = ballot(sel);
+            if (sel) out[written + lanes_below(sm)] = c0 + c * 64 + lane;
+            written += __popcll(sm);
+        };
 #pragma unroll
         for (int c = 0; c < kKeyChunks; c++)
-            if (c < nch) less += __popcll(ballot(key[c] < T));
-        for (int c = kKeyChunks; c < nch; c++)
-            less += __popcll(ballot(cand_key(cand, C, c * 64 + lane, q, d2max) < T));
-        need_ties = kmax - less;
-    }
-    // emit survivors in candidate (= destination index) order
-    int written = 0, ties_seen = 0;
-    auto emit = [&](unsigned k, int c) {
-        bool sel;
-        if (m > kmax) {
-            const unsigned long long tie = ballot(k == T);
-            const bool first_ties = ties_seen + lanes_below(tie) < need_ties;
-            sel = k < T || (k == T && first_ties);
-            ties_seen += __popcll(tie);
-        } else {
-            sel = k != kInvalidKey;
-        }
-        const unsigned long long sm = ballot(sel);
-        if (sel) out[written + lanes_below(sm)] = c0 + c * 64 + lane;
-        written += __popcll(sm);
-    };
-#pragma unroll
-    for (int c = 0; c < kKeyChunks; c++)
-        if (c < nch) emit(key[c], c);
-    for (int c = kKeyChunks; c < nch; c++) emit(cand_key(cand, C, c * 64 + lane, q, d2max), c);
-    return written;
-}
-
-constexpr int kKnnBlock = 256;
-constexpr int kCandLds = 1024;   // candidates staged in LDS (16 KB); larger windows read from L2
-
-// one workgroup per (event b, plane p): grid = B * 26
-__global__ __launch_bounds__(kKnnBlock) void k_knn(const int *__restrict__ off, const int *__restrict__ plane_off,
-                                                   const f32x4 *__restrict__ emb, float d2max, int kmax,
-                                                   int *__restrict__ nbr, int *__restrict__ deg,
-                                                   const unsigned *__restrict__ flags) {
-    __shared__ f32x4 sc[kCandLds];
-    if (*flags & kErrInput) return;
-    const int b = blockIdx.x / VELO_N_PLANES, p = blockIdx.x % VELO_N_PLANES;
-    const int64_t s = off[b];
-    const int *po = plane_off + (int64_t)b * kPlaneSlots;
-    const int q0 = po[p], q1 = po[p + 1];
-    if (q0 >= q1) return;
-    const int c0 = po[min(p + 1, VELO_N_PLANES)];
-    const int c1 = po[min(p + 3, VELO_N_PLANES)];
-    const int C = max(c1 - c0, 0);
-    const f32x4 *cand = emb + s + c0;
-    if (C <= kCandLds) {
-        for (int c = threadIdx.x; c < C; c += kKnnBlock) sc[c] = cand[c];
-        __syncthreads();
-        cand = sc;
-    }
-    const int lane = threadIdx.x & 63;
-    for (int i = q0 + (threadIdx.x >> 6); i < q1; i += kKnnBlock / 64) {
-        const int64_t gi = s + i;
-        const int w = knn_query(cand, C, c0, emb[gi], d2max, kmax, nbr + gi * kmax, lane);
-        if (lane == 0) deg[gi] = w;
+            if (c < nch) emit(key[c], c);
+        for (int c = kKeyChunks; c < nch; c++) emit(cand_key(emb, base, C, c * 64 + lane, q, d2max), c);
+        if (lane == 0) deg[i] = written;
     }
 }
 
@@ -578,10 +563,11 @@ void launch_scan(velo_ctx *c, const int *in, int *out, int64_t n, hipStream_t s)
 }
 
 void launch_knn(velo_ctx *c, const velo_hits *h, const float *emb, hipStream_t s) {
-    if (h->n_hits <= 0 || h->n_events <= 0) return;
-    k_knn<<<h->n_events * VELO_N_PLANES, kKnnBlock, 0, s>>>(h->event_offsets, c->ws.plane_off, (const f32x4 *)emb,
-                                                           c->cfg.d2_max, c->cfg.k_max, c->ws.nbr, c->ws.deg,
-                                                           c->ws.flags);
+    if (h->n_hits <= 0) return;
+    const int blocks = persistent_grid(c, stage_per_cu(c, VELO_STAGE_KNN, 16));
+    k_knn<<<blocks, 256, 0, s>>>(h->n_hits, h->event_offsets, c->ws.plane_off, c->ws.hit_event,
+                                 h->plane, (const f32x4 *)emb, c->cfg.d2_max, c->cfg.k_max,
+                                 c->ws.nbr, c->ws.deg, c->tune_xcd[VELO_STAGE_KNN], c->ws.flags);
 }
 
 void launch_compact(velo_ctx *c, const velo_hits *h, velo_outputs *g, hipStream_t s) {

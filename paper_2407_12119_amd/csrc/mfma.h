@@ -140,9 +140,9 @@ struct FP8 {
     }
     __device__ static f32x4 lo4(bf16x8 v) { return f32x4{(float)v[0], (float)v[1], (float)v[2], (float)v[3]}; }
     __device__ static f32x4 hi4(bf16x8 v) { return f32x4{(float)v[4], (float)v[5], (float)v[6], (float)v[7]}; }
+    __device__ static frag_t pack(bf16x8 v, float inv) { return pack8(lo4(v), hi4(v), inv); }
     __device__ static frag_t load(const bf16 *row, int kb, int g, float inv) {
-        const bf16x8 v = BF16::load(row, kb, g);
-        return pack8(lo4(v), hi4(v), inv);
+        return pack(BF16::load(row, kb, g), inv);
     }
     __device__ static frag_t load_f32(const float *row, int kb, int g, float inv) {
         return pack8(*(const f32x4 *)(row + 32 * kb + 8 * g), *(const f32x4 *)(row + 32 * kb + 8 * g + 4), inv);
