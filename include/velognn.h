@@ -158,7 +158,9 @@ velo_status velo_build_graph(velo_ctx *ctx, const velo_hits *hits, const float *
 /* Stage: GNN edge logits (Sec. 5.2) for a given graph: reads
  * graph->edge_offsets, edge_src, edge_dst and n_edges (edges grouped by event
  * and sorted by source within an event, as velo_build_graph writes them)
- * and writes graph->edge_logit. */
+ * and writes graph->edge_logit.  A graph not grouped by source, or with an
+ * index outside its event, is rejected with VELO_ERR_INPUT (reported by the
+ * next synchronising call). */
 velo_status velo_gnn(velo_ctx *ctx, const velo_hits *hits, velo_outputs *graph, void *stream);
 
 /* Stage: connected components of the edges with logit >= edge_logit_min
@@ -220,7 +222,8 @@ void velo_graph_destroy(velo_graph *graph);
 /* ---- training form (fp32 contexts created with training = 1) ---- */
 
 /* Forward pass of the GNN for training: like velo_gnn on the given graph
- * (edges grouped by event, event-local indices, n_edges), but with the
+ * (edges grouped by event and by source within it, event-local indices,
+ * n_edges; other orders are rejected with VELO_ERR_INPUT), but with the
  * caller's float32 parameter blob `params` (device, velo_param_count entries)
  * and keeping the step-boundary hit/edge encodings and messages in the
  * context for velo_train_backward.  Writes graph->edge_logit. */

@@ -59,7 +59,7 @@ bool dalloc(T **p, int64_t count) {
 
 void free_ws(Workspace &w) {
     void *ptrs[] = {w.emb, w.hit_event, w.plane_off, w.deg, w.row_ptr, w.nbr, w.src_g, w.dst_g,
-                    w.out_ptr, w.out_list, w.in_ptr, w.in_list, w.scan_tmp, w.h[0], w.h[1],
+                    w.in_ptr, w.in_list, w.scan_tmp, w.h[0], w.h[1],
                     w.m, w.e, w.n_edges, w.flags, w.eoff_tmp, w.ck_h, w.ck_e, w.ck_m, w.g_e[0], w.g_e[1],
                     w.g_h[0], w.g_h[1], w.g_xs, w.g_xd, w.g_da, w.g_r, w.g_m, w.g_part, w.g_loss,
                     w.scales, w.amax, w.tmp_logit};
@@ -166,7 +166,7 @@ velo_status velo_create(const velo_config *cfg, velo_ctx **out) {
     bool ok = dalloc(&c->params, c->layout.total) && dalloc(&w.emb, N * 4) && dalloc(&w.hit_event, N) &&
               dalloc(&w.plane_off, B * kPlaneSlots) && dalloc(&w.deg, N) && dalloc(&w.row_ptr, N + 1) &&
               dalloc(&w.nbr, N * k.k_max) && dalloc(&w.src_g, E) && dalloc(&w.dst_g, E) &&
-              dalloc(&w.out_ptr, N + 1) && dalloc(&w.out_list, E) && dalloc(&w.in_ptr, N + 1) &&
+              dalloc(&w.in_ptr, N + 1) &&
               dalloc(&w.in_list, E) && dalloc(&w.scan_tmp, w.scan_tmp_len) &&
               dalloc((char **)&w.h[0], N * H * sb) && dalloc((char **)&w.h[1], N * H * sb) &&
               dalloc(&w.m, N * 2 * H) && dalloc((char **)&w.e, E * H * sb) && dalloc(&w.n_edges, 1) &&
@@ -254,7 +254,7 @@ velo_status velo_calibrate(velo_ctx *c, const velo_hits *h, void *stream) {
     launch_knn(c, h, w.emb, s);
     launch_compact(c, h, &g, s);
     launch_in_lists_plane(c, h, s);
-    launch_gnn(c, h, true, w.tmp_logit, c->params, false, true, s);
+    launch_gnn(c, h, w.tmp_logit, c->params, false, true, s);
     launch_act_scales(c, s);
     c->calibrated = true;
     return device_status(c, "velo_calibrate");
@@ -310,8 +310,12 @@ velo_status velo_gnn(velo_ctx *c, const velo_hits *h, velo_outputs *g, void *str
     hipStream_t s = (hipStream_t)stream;
     { StageTimer t(c, VELO_STAGE_PREPARE, s); launch_prepare(c, h, s); }
     { StageTimer t(c, VELO_STAGE_COMPACT, s); launch_globalise(c, h, g, s); }
-    { StageTimer t(c, VELO_STAGE_LISTS, s); launch_lists(c, h, g, true, s); }
-    launch_gnn(c, h, false, g->edge_logit, c->params, false, false, s);
+    {
+        StageTimer t(c, VELO_STAGE_LISTS, s);
+        launch_row_ptr(c, h, g, s);
+        launch_in_lists_plane(c, h, s);
+    }
+    launch_gnn(c, h, g->edge_logit, c->params, false, false, s);
     return device_status(c, "velo_gnn");
 }
 
@@ -346,7 +350,7 @@ velo_status velo_infer(velo_ctx *c, const velo_hits *h, velo_outputs *o, void *s
     { StageTimer t(c, VELO_STAGE_KNN, s); launch_knn(c, h, c->ws.emb, s); }
     { StageTimer t(c, VELO_STAGE_COMPACT, s); launch_compact(c, h, o, s); }
     { StageTimer t(c, VELO_STAGE_LISTS, s); launch_in_lists_plane(c, h, s); }
-    launch_gnn(c, h, true, o->edge_logit, c->params, false, false, s);
+    launch_gnn(c, h, o->edge_logit, c->params, false, false, s);
     { StageTimer t(c, VELO_STAGE_COMPONENTS, s); launch_components(c, h, o, s); }
     return device_status(c, "velo_infer");
 }
@@ -453,8 +457,12 @@ velo_status velo_train_forward(velo_ctx *c, const velo_hits *h, velo_outputs *g,
     hipStream_t s = (hipStream_t)stream;
     { StageTimer t(c, VELO_STAGE_PREPARE, s); launch_prepare(c, h, s); }
     { StageTimer t(c, VELO_STAGE_COMPACT, s); launch_globalise(c, h, g, s); }
-    { StageTimer t(c, VELO_STAGE_LISTS, s); launch_lists(c, h, g, true, s); }
-    launch_gnn(c, h, false, g->edge_logit, params, true, false, s);
+    {
+        StageTimer t(c, VELO_STAGE_LISTS, s);
+        launch_row_ptr(c, h, g, s);
+        launch_in_lists_plane(c, h, s);
+    }
+    launch_gnn(c, h, g->edge_logit, params, true, false, s);
     c->train_ready = true;
     return device_status(c, "velo_train_forward");
 }

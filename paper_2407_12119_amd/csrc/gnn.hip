@@ -359,7 +359,6 @@ __global__ __launch_bounds__(512) void k_mlp(MlpArgs A) {
 // ------------------------------------------------------------------------
 template <class P, int H>
 __global__ __launch_bounds__(256) void k_messages(int64_t n_hits, const int *__restrict__ out_ptr,
-                                                  const int *__restrict__ out_list,
                                                   const int *__restrict__ in_ptr,
                                                   const int *__restrict__ in_list,
                                                   const typename P::state_t *__restrict__ e,
@@ -373,19 +372,15 @@ __global__ __launch_bounds__(256) void k_messages(int64_t n_hits, const int *__r
         if (i >= n_hits) continue;
         f32x4 so = zero4(), si = zero4();
         const int a0 = out_ptr[i], a1 = out_ptr[i + 1];
-        if (out_list) {
-            for (int a = a0; a < a1; a++) so += P::load4(e + (int64_t)out_list[a] * H + c);
-        } else {
-            int a = a0;
-            for (; a + 4 <= a1; a += 4) {
-                const f32x4 v0 = P::load4(e + (int64_t)a * H + c);
-                const f32x4 v1 = P::load4(e + (int64_t)(a + 1) * H + c);
-                const f32x4 v2 = P::load4(e + (int64_t)(a + 2) * H + c);
-                const f32x4 v3 = P::load4(e + (int64_t)(a + 3) * H + c);
-                so += v0; so += v1; so += v2; so += v3;
-            }
-            for (; a < a1; a++) so += P::load4(e + (int64_t)a * H + c);
+        int a = a0;
+        for (; a + 4 <= a1; a += 4) {
+            const f32x4 v0 = P::load4(e + (int64_t)a * H + c);
+            const f32x4 v1 = P::load4(e + (int64_t)(a + 1) * H + c);
+            const f32x4 v2 = P::load4(e + (int64_t)(a + 2) * H + c);
+            const f32x4 v3 = P::load4(e + (int64_t)(a + 3) * H + c);
+            so += v0; so += v1; so += v2; so += v3;
         }
+        for (; a < a1; a++) so += P::load4(e + (int64_t)a * H + c);
         const int b0 = in_ptr[i], b1 = in_ptr[i + 1];
         int b = b0;
         for (; b + 4 <= b1; b += 4) {
@@ -426,7 +421,7 @@ void run_mlp(velo_ctx *c, int stage, MlpArgs a, hipStream_t s) {
 // every step's hit and edge encodings and messages as checkpoints for the
 // backward pass (ck_h[k], ck_e[k], ck_m[k]) and reads the caller's parameters.
 template <class P, int H>
-void gnn_ph(velo_ctx *c, const velo_hits *hits, bool out_identity, float *logit, const float *Pw, bool train,
+void gnn_ph(velo_ctx *c, const velo_hits *hits, float *logit, const float *Pw, bool train,
             bool calib, hipStream_t s) {
     using S = typename P::state_t;
     Workspace &w = c->ws;
@@ -460,13 +455,11 @@ void gnn_ph(velo_ctx *c, const velo_hits *hits, bool out_identity, float *logit,
         StageTimer t(c, VELO_STAGE_EDGE_ENC, s);
         run_mlp<P, H, EDGE_ENC, false>(c, VELO_STAGE_EDGE_ENC, a, s);
     }
-    const int *optr = out_identity ? w.row_ptr : w.out_ptr;
-    const int *olist = out_identity ? nullptr : w.out_list;
     for (int k = 0; k < iters; k++) {
         if (N > 0) {
             StageTimer t(c, VELO_STAGE_MESSAGES, s);
             k_messages<P, H><<<persistent_grid(c, stage_per_cu(c, VELO_STAGE_MESSAGES, 16)), 256, 0, s>>>(
-                N, optr, olist, w.in_ptr, w.in_list, ek(k), mk(k), c->tune_xcd[VELO_STAGE_MESSAGES], w.flags);
+                N, w.row_ptr, w.in_ptr, w.in_list, ek(k), mk(k), c->tune_xcd[VELO_STAGE_MESSAGES], w.flags);
         }
         MlpArgs nd{};
         nd.n_dev = nullptr; nd.n_host = N; nd.a = hk(k); nd.b = mk(k); nd.out = hk(k + 1);
@@ -599,20 +592,20 @@ void launch_embed(velo_ctx *c, const velo_hits *h, float *emb, bool calib, hipSt
         embed_p<FP8>(c, h, emb, false, s);
 }
 
-void launch_gnn(velo_ctx *c, const velo_hits *h, bool out_identity, float *logit, const float *params, bool train,
-                bool calib, hipStream_t s) {
+void launch_gnn(velo_ctx *c, const velo_hits *h, float *logit, const float *params, bool train, bool calib,
+                hipStream_t s) {
     const int H = c->cfg.gnn_hidden, p = c->cfg.precision;
     if (p == VELO_FP32) {
-        if (H == 32) gnn_ph<F32, 32>(c, h, out_identity, logit, params, train, false, s);
-        if (H == 64) gnn_ph<F32, 64>(c, h, out_identity, logit, params, train, false, s);
+        if (H == 32) gnn_ph<F32, 32>(c, h, logit, params, train, false, s);
+        if (H == 64) gnn_ph<F32, 64>(c, h, logit, params, train, false, s);
     } else if (p == VELO_BF16 || calib) {
-        if (H == 32) gnn_ph<BF16, 32>(c, h, out_identity, logit, params, train, calib, s);
-        if (H == 64) gnn_ph<BF16, 64>(c, h, out_identity, logit, params, train, calib, s);
-        if (H == 128) gnn_ph<BF16, 128>(c, h, out_identity, logit, params, train, calib, s);
+        if (H == 32) gnn_ph<BF16, 32>(c, h, logit, params, train, calib, s);
+        if (H == 64) gnn_ph<BF16, 64>(c, h, logit, params, train, calib, s);
+        if (H == 128) gnn_ph<BF16, 128>(c, h, logit, params, train, calib, s);
     } else {
-        if (H == 32) gnn_ph<FP8, 32>(c, h, out_identity, logit, params, train, false, s);
-        if (H == 64) gnn_ph<FP8, 64>(c, h, out_identity, logit, params, train, false, s);
-        if (H == 128) gnn_ph<FP8, 128>(c, h, out_identity, logit, params, train, false, s);
+        if (H == 32) gnn_ph<FP8, 32>(c, h, logit, params, train, false, s);
+        if (H == 64) gnn_ph<FP8, 64>(c, h, logit, params, train, false, s);
+        if (H == 128) gnn_ph<FP8, 128>(c, h, logit, params, train, false, s);
     }
 }
 

@@ -338,83 +338,25 @@ __global__ void k_globalise(int B, const int *__restrict__ off, const int *__res
 // every list is put in edge-id order (rank sort in registers, one wavefront
 // per hit) so that sums over a list always run in the same order.
 // ------------------------------------------------------------------------
-constexpr int kListBlock = 1024;
-
-__global__ __launch_bounds__(kListBlock) void k_lists(int B, const int *__restrict__ off,
-                                                      const int *__restrict__ eoff,
-                                                      const int *__restrict__ n_edges,
-                                                      const int *__restrict__ key_g, int *__restrict__ ptr_g,
-                                                      int *__restrict__ list, int max_ev,
-                                                      const unsigned *__restrict__ flags) {
-    extern __shared__ int sh[];
+// row pointers of a given graph whose edges come grouped by source
+// (validated by k_globalise): row_ptr[i] = first edge of hit i, by binary
+// search within the hit's event
+// ------------------------------------------------------------------------
+__global__ void k_row_ptr(int64_t n_hits, const int *__restrict__ hit_event, const int *__restrict__ eoff,
+                          const int *__restrict__ n_edges, int64_t cap, const int *__restrict__ src_g,
+                          int *__restrict__ row_ptr, const unsigned *__restrict__ flags) {
     if (*flags) return;
-    int *cnt = sh;                 // [max_ev]
-    int *part = sh + max_ev;       // [kListBlock]
-    const int b = blockIdx.x, t = threadIdx.x;
-    const int s = off[b], n = off[b + 1] - s;
-    const int E = *n_edges;
-    const int e0 = min(eoff[b], E), e1 = min(eoff[b + 1], E);
-    if (n > max_ev) return;
-    for (int l = t; l < n; l += kListBlock) cnt[l] = 0;
-    __syncthreads();
-    for (int q = e0 + t; q < e1; q += kListBlock) {
-        const int k = key_g[q] - s;
-        if (k >= 0 && k < n) atomicAdd(&cnt[k], 1);
-    }
-    __syncthreads();
-    // exclusive scan of cnt[0..n): each thread owns a contiguous slice
-    const int per = (n + kListBlock - 1) / kListBlock;
-    const int lo = min(t * per, n), hi = min(lo + per, n);
-    int sum = 0;
-    for (int l = lo; l < hi; l++) sum += cnt[l];
-    part[t] = sum;
-    __syncthreads();
-    for (int d = 1; d < kListBlock; d <<= 1) {
-        const int add = t >= d ? part[t - d] : 0;
-        __syncthreads();
-        part[t] += add;
-        __syncthreads();
-    }
-    int run = e0 + part[t] - sum;
-    for (int l = lo; l < hi; l++) {
-        ptr_g[s + l] = run;
-        run += cnt[l];
-    }
-    if (b == B - 1 && t == 0) ptr_g[s + n] = e1;
-    __syncthreads();
-    for (int l = t; l < n; l += kListBlock) cnt[l] = 0;
-    __threadfence_block();
-    __syncthreads();
-    for (int q = e0 + t; q < e1; q += kListBlock) {
-        const int k = key_g[q] - s;
-        if (k < 0 || k >= n) continue;
-        const int slot = atomicAdd(&cnt[k], 1);
-        list[ptr_g[s + k] + slot] = q;
-    }
-    __threadfence_block();
-    __syncthreads();
-    // order every list by edge id
-    const int lane = t & 63, wave = t >> 6, nw = kListBlock / 64;
-    for (int l = wave; l < n; l += nw) {
-        const int L = cnt[l];
-        if (L <= 1) continue;
-        const int a = ptr_g[s + l];
-        if (L <= 64) {
-            const int v = lane < L ? list[a + lane] : 0x7fffffff;
-            int rank = 0;
-            for (int j = 0; j < L; j++) rank += __shfl(v, j) < v;
-            if (lane < L) list[a + rank] = v;
-        } else if (lane == 0) {
-            for (int u = a + 1; u < a + L; u++) {
-                const int v = list[u];
-                int w = u - 1;
-                while (w >= a && list[w] > v) {
-                    list[w + 1] = list[w];
-                    w--;
-                }
-                list[w + 1] = v;
-            }
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_hits;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int b = hit_event[i];
+        int lo = eoff[b], hi = eoff[b + 1];
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (src_g[mid] < i) lo = mid + 1;
+            else hi = mid;
         }
+        row_ptr[i] = lo;
+        if (i == n_hits - 1) row_ptr[n_hits] = (int)min((int64_t)*n_edges, cap);
     }
 }
 
@@ -597,24 +539,13 @@ void launch_globalise(velo_ctx *c, const velo_hits *h, const velo_outputs *g, hi
                                                 w.dst_g, w.flags);
 }
 
-void launch_lists(velo_ctx *c, const velo_hits *h, const velo_outputs *g, bool need_out_lists, hipStream_t s) {
+void launch_row_ptr(velo_ctx *c, const velo_hits *h, const velo_outputs *g, hipStream_t s) {
     Workspace &w = c->ws;
-    if (h->n_events <= 0) return;
+    if (h->n_hits <= 0 || h->n_events <= 0) return;
     const int *eoff = g->edge_offsets ? g->edge_offsets : w.eoff_tmp;
-    const size_t lds = sizeof(int) * ((size_t)c->cfg.max_event_hits + kListBlock);
-    static bool attr = false;
-    if (!attr) {
-        hipFuncSetAttribute(reinterpret_cast<const void *>(&k_lists), hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)c->lds_max);
-        attr = true;
-    }
-    for (int dir = need_out_lists ? 0 : 1; dir < 2; dir++) {
-        const int *key = dir == 0 ? w.src_g : w.dst_g;
-        int *ptr = dir == 0 ? w.out_ptr : w.in_ptr;
-        int *list = dir == 0 ? w.out_list : w.in_list;
-        k_lists<<<h->n_events, kListBlock, lds, s>>>(h->n_events, h->event_offsets, eoff, w.n_edges, key, ptr, list,
-                                                     c->cfg.max_event_hits, w.flags);
-    }
+    const int64_t cap = g->edge_capacity < c->cfg.max_edges ? g->edge_capacity : c->cfg.max_edges;
+    k_row_ptr<<<grid_for(h->n_hits, 256, 4096), 256, 0, s>>>(h->n_hits, w.hit_event, eoff, w.n_edges, cap, w.src_g,
+                                                              w.row_ptr, w.flags);
 }
 
 }  // namespace velo

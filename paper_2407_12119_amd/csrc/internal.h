@@ -40,8 +40,6 @@ struct Workspace {
     int *nbr = nullptr;          // [max_hits x k_max] staging of selected neighbours
     int *src_g = nullptr;        // [max_edges] batch-global source hit
     int *dst_g = nullptr;        // [max_edges] batch-global destination hit
-    int *out_ptr = nullptr;      // [max_hits + 1]
-    int *out_list = nullptr;     // [max_edges]
     int *in_ptr = nullptr;       // [max_hits + 1]
     int *in_list = nullptr;      // [max_edges]
     int *scan_tmp = nullptr;     // block sums of the scans
@@ -106,7 +104,8 @@ void launch_knn(velo_ctx *c, const velo_hits *h, const float *emb, hipStream_t s
 void launch_scan(velo_ctx *c, const int *in, int *out, int64_t n, hipStream_t s);
 void launch_compact(velo_ctx *c, const velo_hits *h, velo_outputs *g, hipStream_t s);
 void launch_globalise(velo_ctx *c, const velo_hits *h, const velo_outputs *g, hipStream_t s);
-void launch_lists(velo_ctx *c, const velo_hits *h, const velo_outputs *g, bool need_out_lists, hipStream_t s);
+// row_ptr of a given graph (edges grouped by source, checked by launch_globalise)
+void launch_row_ptr(velo_ctx *c, const velo_hits *h, const velo_outputs *g, hipStream_t s);
 void launch_fill(int *p, int v, int64_t n, hipStream_t s);
 void launch_in_lists_plane(velo_ctx *c, const velo_hits *h, hipStream_t s);
 
@@ -114,8 +113,9 @@ void launch_in_lists_plane(velo_ctx *c, const velo_hits *h, hipStream_t s);
 size_t state_bytes(int precision);              // bytes per stored encoding element
 bool gnn_supported(int hidden, int precision);  // compiled (hidden, precision) pairs
 void launch_embed(velo_ctx *c, const velo_hits *h, float *emb, bool calib, hipStream_t s);
-void launch_gnn(velo_ctx *c, const velo_hits *h, bool out_identity, float *logit, const float *params, bool train,
-                bool calib, hipStream_t s);
+// GNN forward over the graph in the workspace (src_g, dst_g, row_ptr, in lists)
+void launch_gnn(velo_ctx *c, const velo_hits *h, float *logit, const float *params, bool train, bool calib,
+                hipStream_t s);
 
 // fp8 scale table: one slot of four floats {s_x1, s_w1, s_x2, s_w2} per MLP
 // (inputs and weights of its two matrix layers) and two calibration maxima.

@@ -346,7 +346,7 @@ __global__ void k_dw_reduce(const float *__restrict__ part, int PL, float *__res
 // dh[l] (+)= sum_{l -> j} xs[edge] + sum_{i -> l} xd[edge]; H/4 lanes per hit.
 template <int H>
 __global__ __launch_bounds__(256) void k_gather_add(int64_t n_hits, const int *__restrict__ out_ptr,
-                                                    const int *__restrict__ out_list, const int *__restrict__ in_ptr,
+                                                    const int *__restrict__ in_ptr,
                                                     const int *__restrict__ in_list, const float *__restrict__ xs,
                                                     const float *__restrict__ xd, float *__restrict__ dh,
                                                     bool accumulate, const unsigned *__restrict__ flags) {
@@ -358,7 +358,7 @@ __global__ __launch_bounds__(256) void k_gather_add(int64_t n_hits, const int *_
         const int64_t i = base + sub;
         if (i >= n_hits) continue;
         f32x4 sum = accumulate ? *(const f32x4 *)(dh + i * H + c) : zero4();
-        for (int a = out_ptr[i]; a < out_ptr[i + 1]; a++) sum += *(const f32x4 *)(xs + (int64_t)out_list[a] * H + c);
+        for (int a = out_ptr[i]; a < out_ptr[i + 1]; a++) sum += *(const f32x4 *)(xs + (int64_t)a * H + c);
         for (int b = in_ptr[i]; b < in_ptr[i + 1]; b++) sum += *(const f32x4 *)(xd + (int64_t)in_list[b] * H + c);
         *(f32x4 *)(dh + i * H + c) = sum;
     }
@@ -492,7 +492,7 @@ void backward_h(velo_ctx *c, const velo_hits *hits, const float *Pw, const float
         { StageTimer t(c, VELO_STAGE_BWD_DW, s); run_dw<H, B_EDGE>(c, ed, dparams + L.edge[k][0].w, s); }
         if (N > 0) {
             StageTimer t(c, VELO_STAGE_BWD_GRAPH, s);
-            k_gather_add<H><<<persistent_grid(c, 16), 256, 0, s>>>(N, w.out_ptr, w.out_list, w.in_ptr, w.in_list,
+            k_gather_add<H><<<persistent_grid(c, 16), 256, 0, s>>>(N, w.row_ptr, w.in_ptr, w.in_list,
                                                                  w.g_xs, w.g_xd, w.g_h[ch], true, w.flags);
         }
         ce ^= 1;
@@ -521,7 +521,7 @@ void backward_h(velo_ctx *c, const velo_hits *hits, const float *Pw, const float
     { StageTimer t(c, VELO_STAGE_BWD_DW, s); run_dw<H, B_EDGE_ENC>(c, ee, dparams + L.eenc[0].w, s); }
     if (N > 0) {
         StageTimer t(c, VELO_STAGE_BWD_GRAPH, s);
-        k_gather_add<H><<<persistent_grid(c, 16), 256, 0, s>>>(N, w.out_ptr, w.out_list, w.in_ptr, w.in_list, w.g_xs,
+        k_gather_add<H><<<persistent_grid(c, 16), 256, 0, s>>>(N, w.row_ptr, w.in_ptr, w.in_list, w.g_xs,
                                                              w.g_xd, w.g_h[ch], true, w.flags);
     }
     // node encoder

@@ -193,6 +193,25 @@ def test_invalid_hits_are_reported():
     ctx.infer(hits)
 
 
+def test_given_graph_must_be_grouped_by_source():
+    """velo_gnn takes a graph whose edges come grouped by source within each
+    event (as velo_build_graph writes it); another order is an input error,
+    and the context works afterwards."""
+    wl = synth.WORKLOADS["batch256"]
+    batch = synth.make_batch(wl, n_events=2, first=3)
+    ctx, hits, _ = _setup(wl, batch)
+    g = ctx.build_graph(hits, ctx.embed(hits))
+    n0 = int(g["edge_offsets"][1].cpu())
+    assert n0 > 2
+    bad = {k: (v.clone() if hasattr(v, "clone") else v) for k, v in g.items()}
+    bad["edge_src"][:n0] = bad["edge_src"][:n0].flip(0)
+    bad["edge_dst"][:n0] = bad["edge_dst"][:n0].flip(0)
+    with pytest.raises(velo.VeloError) as ei:
+        ctx.gnn(hits, bad)
+    assert ei.value.status == velo.VELO_ERR_INPUT
+    ctx.gnn(hits, g)
+
+
 def test_zero_events_and_all_empty_events():
     wl = synth.WORKLOADS["batch256"]
     empty = synth.Event(*(np.zeros(0, dt) for dt in (np.float32, np.float32, np.float32, np.int32, np.int64, np.int32)))
