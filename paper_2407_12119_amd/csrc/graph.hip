@@ -309,15 +309,17 @@ __global__ void k_globalise(int B, const int *__restrict__ off, const int *__res
         if (E != 0 && threadIdx.x == 0) atomicOr(flags, kErrInput);
         return;
     }
+    // block (b, y): event b, the y-th of gridDim.y interleaved slices of its edges
     const int b = blockIdx.x;
     const int s = off[b], n = off[b + 1] - s;
     const int e0 = eoff[b], e1 = eoff[b + 1];
     if ((b == 0 && e0 != 0) || (b == B - 1 && e1 != E) || e1 < e0 || e1 > E) {
-        if (threadIdx.x == 0) atomicOr(flags, kErrInput);
+        if (threadIdx.x == 0 && blockIdx.y == 0) atomicOr(flags, kErrInput);
         return;
     }
     bool err = false;
-    for (int q = e0 + threadIdx.x; q < e1; q += blockDim.x) {
+    const int stride = blockDim.x * gridDim.y;
+    for (int q = e0 + blockIdx.y * blockDim.x + threadIdx.x; q < e1; q += stride) {
         const int a = esrc[q], c = edst[q];
         // edges must come grouped by source (non-decreasing esrc)
         if (a < 0 || a >= n || c < 0 || c >= n || (q > e0 && esrc[q - 1] > a)) {
@@ -534,7 +536,8 @@ void launch_globalise(velo_ctx *c, const velo_hits *h, const velo_outputs *g, hi
     Workspace &w = c->ws;
     const int64_t cap = g->edge_capacity < c->cfg.max_edges ? g->edge_capacity : c->cfg.max_edges;
     k_check_capacity<<<1, 1, 0, s>>>(g->n_edges, cap, w.n_edges, nullptr, w.flags);
-    k_globalise<<<h->n_events > 0 ? h->n_events : 1, 256, 0, s>>>(h->n_events, h->event_offsets, g->edge_offsets,
+    const dim3 grid(h->n_events > 0 ? h->n_events : 1, h->n_events > 0 ? 16 : 1);
+    k_globalise<<<grid, 256, 0, s>>>(h->n_events, h->event_offsets, g->edge_offsets,
                                                 w.n_edges, cap, g->edge_src, g->edge_dst, w.src_g,
                                                 w.dst_g, w.flags);
 }

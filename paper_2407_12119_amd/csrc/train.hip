@@ -329,6 +329,151 @@ __global__ __launch_bounds__(kBwdBlock) void k_dw(BwdArgs A, float *__restrict__
     }
 }
 
+// The same weight gradients with the rows staged in LDS: a tile of kDwRows
+// rows of the layer-1 inputs Y, of da, of r and of dout is loaded with
+// 16-byte loads by the whole block (the next tile's loads are in flight
+// while the current tile is multiplied), then each wave runs its 16 output
+// rows of dW1 and dW2 as MFMA 16x16x4 over the tile with operands read from
+// LDS.  Rows are padded by 16 floats so the 4 rows read by one MFMA operand
+// fall in different LDS banks.  Not used for the node encoder (K1 = 3).
+constexpr int kDwRows = 16;
+
+template <int H, int MODE>
+__global__ __launch_bounds__(kBwdBlock) void k_dw_lds(BwdArgs A, float *__restrict__ part) {
+    constexpr int MO = H / 16;
+    constexpr int K1 = bseg<MODE>() * H;
+    constexpr int NB1 = K1 / 16;
+    constexpr bool CLS = MODE == B_CLS;
+    constexpr int M2 = CLS ? 1 : H;
+    constexpr int PL = H * K1 + H + M2 * H + M2;
+    constexpr int SY = K1 + 16, SH = H + 16;            // padded LDS row strides (floats)
+    constexpr int CY = K1 / 4, CH = H / 4;               // float4 chunks per row
+    __shared__ __align__(16) float sY[kDwRows * SY];
+    __shared__ __align__(16) float sG1[kDwRows * SH];
+    __shared__ __align__(16) float sR[kDwRows * SH];
+    __shared__ __align__(16) float sG2[kDwRows * (CLS ? 1 : SH)];
+    if (*A.flags) return;
+    const int lane = threadIdx.x & 63, n = lane & 15, g = lane >> 4, w = threadIdx.x >> 6;
+    const int64_t N = row_count(A);
+    const int64_t per = (((N + kChunks - 1) / kChunks) + 3) & ~(int64_t)3;
+    const int64_t r0 = (int64_t)blockIdx.x * per, r1 = min(r0 + per, N);
+    float *out = part + (int64_t)blockIdx.x * PL;
+    const bool active = w < MO;                        // waves beyond the output rows only load
+    const int m = active ? w : 0;
+
+    // tile loads: thread (rr, q) = (t / 16, t % 16) loads row rr's float4
+    // chunks q, q + 16, ... of Y (CY chunks), da, r and dout (CH chunks each)
+    static_assert(kBwdBlock == 16 * kDwRows, "one 16-thread group per tile row");
+    constexpr int NY = (CY + 15) / 16, NHC = (CH + 15) / 16;
+    const int rr = threadIdx.x >> 4, q = threadIdx.x & 15;
+    f32x4 ny[NY], ng1[NHC], nr[NHC], ng2[CLS ? 1 : NHC];
+    float g2n = 0.f;
+    auto fetch_tile = [&](int64_t t0) {
+        const int64_t row = t0 + rr;
+        const bool ok = row < r1;
+        const int64_t rc = ok ? row : r0;
+        const float *seg[3];
+        if (MODE == B_EDGE) {
+            seg[0] = A.a + rc * H;
+            seg[1] = A.b + (int64_t)A.src_g[rc] * H;
+            seg[2] = A.b + (int64_t)A.dst_g[rc] * H;
+        } else if (MODE == B_NODE) {
+            seg[0] = A.a + rc * H;
+            seg[1] = A.b + rc * 2 * H;
+            seg[2] = A.b + rc * 2 * H + H;
+        } else if (MODE == B_EDGE_ENC) {
+            seg[0] = A.a + (int64_t)A.src_g[rc] * H;
+            seg[1] = seg[2] = A.a + (int64_t)A.dst_g[rc] * H;
+        } else {
+            seg[0] = seg[1] = seg[2] = A.a + rc * H;
+        }
+#pragma unroll
+        for (int y = 0; y < NY; y++) {
+            const int j = q + 16 * y;
+            ny[y] = zero4();
+            if (ok && j < CY) ny[y] = *(const f32x4 *)(seg[j / CH] + 4 * (j % CH));
+        }
+#pragma unroll
+        for (int y = 0; y < NHC; y++) {
+            const int j = q + 16 * y;
+            const bool v = ok && j < CH;
+            ng1[y] = v ? *(const f32x4 *)(A.da + rc * H + 4 * j) : zero4();
+            nr[y] = v ? *(const f32x4 *)(A.r + rc * H + 4 * j) : zero4();
+            if (!CLS) ng2[y] = v ? *(const f32x4 *)(A.dout + rc * H + 4 * j) : zero4();
+        }
+        if (CLS) g2n = ok ? A.dout[rc] : 0.f;
+    };
+    f32x4 acc1[NB1], acc2[MO];
+    zero<NB1>(acc1);
+    zero<MO>(acc2);
+    float sb1 = 0.f, sb2 = 0.f;
+    if (r0 < r1) fetch_tile(r0);
+    for (int64_t t0 = r0; t0 < r1; t0 += kDwRows) {
+        __syncthreads();                               // the previous tile's reads are done
+#pragma unroll
+        for (int y = 0; y < NY; y++) {
+            const int j = q + 16 * y;
+            if (j < CY) *(f32x4 *)(sY + rr * SY + 4 * j) = ny[y];
+        }
+#pragma unroll
+        for (int y = 0; y < NHC; y++) {
+            const int j = q + 16 * y;
+            if (j < CH) {
+                *(f32x4 *)(sG1 + rr * SH + 4 * j) = ng1[y];
+                *(f32x4 *)(sR + rr * SH + 4 * j) = nr[y];
+                if (!CLS) *(f32x4 *)(sG2 + rr * SH + 4 * j) = ng2[y];
+            }
+        }
+        if (CLS && q == 0) sG2[rr] = g2n;
+        __syncthreads();
+        if (t0 + kDwRows < r1) fetch_tile(t0 + kDwRows);
+        if (!active) continue;
+#pragma unroll 1
+        for (int ks = 0; ks < kDwRows / 4; ks++) {
+            const int kr = 4 * ks + g;
+            const float ga = sG1[kr * SH + 16 * m + n];
+            sb1 += ga;
+#pragma unroll
+            for (int nb = 0; nb < NB1; nb++)
+                acc1[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ga, sY[kr * SY + 16 * nb + n], acc1[nb], 0, 0, 0);
+            float gd;
+            if (CLS) gd = m == 0 && n == 0 ? sG2[kr] : 0.f;
+            else gd = sG2[kr * SH + 16 * m + n];
+            sb2 += gd;
+            if (!CLS || m == 0) {
+#pragma unroll
+                for (int nb = 0; nb < MO; nb++)
+                    acc2[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(gd, sR[kr * SH + 16 * nb + n], acc2[nb], 0, 0, 0);
+            }
+        }
+    }
+    if (!active) return;
+    sb1 += __shfl_xor(sb1, 16);
+    sb1 += __shfl_xor(sb1, 32);
+    sb2 += __shfl_xor(sb2, 16);
+    sb2 += __shfl_xor(sb2, 32);
+#pragma unroll
+    for (int nb = 0; nb < NB1; nb++)
+#pragma unroll
+        for (int i = 0; i < 4; i++) out[(16 * m + 4 * g + i) * K1 + 16 * nb + n] = acc1[nb][i];
+    if (g == 0) out[H * K1 + 16 * m + n] = sb1;
+    float *o2 = out + H * K1 + H;
+    if (CLS) {
+        if (m == 0) {
+#pragma unroll
+            for (int nb = 0; nb < MO; nb++)
+                if (g == 0) o2[16 * nb + n] = acc2[nb][0];    // output row 0
+            if (lane == 0) o2[H] = sb2;
+        }
+    } else {
+#pragma unroll
+        for (int nb = 0; nb < MO; nb++)
+#pragma unroll
+            for (int i = 0; i < 4; i++) o2[(16 * m + 4 * g + i) * H + 16 * nb + n] = acc2[nb][i];
+        if (g == 0) o2[M2 * H + 16 * m + n] = sb2;
+    }
+}
+
 // Sum the chunk partials in chunk order into the blob-shaped gradient.
 __global__ void k_dw_reduce(const float *__restrict__ part, int PL, float *__restrict__ grad,
                             const unsigned *__restrict__ flags) {
@@ -453,7 +598,10 @@ void run_dw(velo_ctx *c, const BwdArgs &a, float *grad_dst, hipStream_t s) {
     constexpr int K1 = MODE == B_NODE_ENC ? 3 : bseg<MODE>() * H;
     constexpr int M2 = MODE == B_CLS ? 1 : H;
     constexpr int PL = H * K1 + H + M2 * H + M2;
-    k_dw<H, MODE><<<kChunks, kBwdBlock, 0, s>>>(a, c->ws.g_part);
+    if constexpr (MODE == B_NODE_ENC)
+        k_dw<H, MODE><<<kChunks, kBwdBlock, 0, s>>>(a, c->ws.g_part);
+    else
+        k_dw_lds<H, MODE><<<kChunks, kBwdBlock, 0, s>>>(a, c->ws.g_part);
     k_dw_reduce<<<blocks_for(PL, 256, 1024), 256, 0, s>>>(c->ws.g_part, PL, grad_dst, c->ws.flags);
 }
 
