@@ -291,11 +291,13 @@ __global__ __launch_bounds__(512) void k_mlp(MlpArgs A) {
     };
     // memory-bound precisions prefetch the next unit's inputs during the MFMAs
     constexpr bool PREFETCH = sizeof(S) < 4 && NSEG > 0;
-    typename P::frag_t Xn[NX];
-    raw_t Rn[RAW ? KB : 1];
+    // two units in flight: Xn holds unit u + step, Xm unit u + 2 step
+    typename P::frag_t Xn[NX], Xm[NX];
+    raw_t Rn[RAW ? KB : 1], Rm[RAW ? KB : 1];
     const WaveRange wr = wave_range(units, A.xcd != 0);
     int64_t u = wr.first;
     if (PREFETCH && u < wr.end) load_unit(u, Xn, Rn);
+    if (PREFETCH && u + wr.step < wr.end) load_unit(u + wr.step, Xm, Rm);
     for (; u < wr.end; u += wr.step) {
         const int64_t q = u * 16 + n;
         const bool ok = q < N;
@@ -304,12 +306,18 @@ __global__ __launch_bounds__(512) void k_mlp(MlpArgs A) {
         raw_t R[RAW ? KB : 1];
         if (PREFETCH) {
 #pragma unroll
-            for (int k = 0; k < NX; k++) X[k] = Xn[k];
+            for (int k = 0; k < NX; k++) {
+                X[k] = Xn[k];
+                Xn[k] = Xm[k];
+            }
             if constexpr (RAW) {
 #pragma unroll
-                for (int k = 0; k < KB; k++) R[k] = Rn[k];
+                for (int k = 0; k < KB; k++) {
+                    R[k] = Rn[k];
+                    Rn[k] = Rm[k];
+                }
             }
-            if (u + wr.step < wr.end) load_unit(u + wr.step, Xn, Rn);
+            if (u + 2 * wr.step < wr.end) load_unit(u + 2 * wr.step, Xm, Rm);
         } else if (NSEG > 0) {
             load_unit(u, X, R);
         }
