@@ -169,7 +169,7 @@ velo_status velo_create(const velo_config *cfg, velo_ctx **out) {
               dalloc(&w.in_ptr, N + 1) &&
               dalloc(&w.in_list, E) && dalloc(&w.scan_tmp, w.scan_tmp_len) &&
               dalloc((char **)&w.h[0], N * H * sb) && dalloc((char **)&w.h[1], N * H * sb) &&
-              dalloc(&w.m, N * 2 * H) && dalloc((char **)&w.e, E * H * sb) && dalloc(&w.n_edges, 1) &&
+              dalloc(&w.m, N * kMsgParts * H) && dalloc((char **)&w.e, E * H * sb) && dalloc(&w.n_edges, 1) &&
               dalloc(&w.flags, 1) &&
               dalloc(&w.eoff_tmp, B + 1);
     if (ok && k.precision == VELO_FP8) {
@@ -183,7 +183,7 @@ velo_status velo_create(const velo_config *cfg, velo_ctx **out) {
     if (ok && k.training) {
         const int64_t it = k.gnn_iters, R = std::max<int64_t>(N, E);
         ok = dalloc((char **)&w.ck_h, (it + 1) * N * H * sb) && dalloc((char **)&w.ck_e, (it + 1) * E * H * sb) &&
-             dalloc(&w.ck_m, std::max<int64_t>(it, 1) * N * 2 * H) && dalloc(&w.g_e[0], E * H) &&
+             dalloc(&w.ck_m, std::max<int64_t>(it, 1) * N * kMsgParts * H) && dalloc(&w.g_e[0], E * H) &&
              dalloc(&w.g_e[1], E * H) && dalloc(&w.g_h[0], N * H) && dalloc(&w.g_h[1], N * H) &&
              dalloc(&w.g_xs, E * H) && dalloc(&w.g_xd, E * H) && dalloc(&w.g_da, R * H) && dalloc(&w.g_r, R * H) &&
              dalloc(&w.g_m, N * 2 * H) && dalloc(&w.g_part, (int64_t)train_part_floats(k.gnn_hidden)) &&

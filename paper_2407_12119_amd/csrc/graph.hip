@@ -301,7 +301,7 @@ __global__ void k_check_capacity(const int *__restrict__ total, int64_t cap, int
 // Caller-supplied edges (event-local) -> batch-global hit indices; one block per event.
 __global__ void k_globalise(int B, const int *__restrict__ off, const int *__restrict__ eoff,
                             const int *__restrict__ n_edges, int64_t cap, const int *__restrict__ esrc,
-                            const int *__restrict__ edst, int *__restrict__ src_g,
+                            const int *__restrict__ edst, const int *__restrict__ plane, int *__restrict__ src_g,
                             int *__restrict__ dst_g, unsigned *__restrict__ flags) {
     if (*flags) return;
     const int E = min((int64_t)*n_edges, cap);
@@ -321,8 +321,10 @@ __global__ void k_globalise(int B, const int *__restrict__ off, const int *__res
     const int stride = blockDim.x * gridDim.y;
     for (int q = e0 + blockIdx.y * blockDim.x + threadIdx.x; q < e1; q += stride) {
         const int a = esrc[q], c = edst[q];
-        // edges must come grouped by source (non-decreasing esrc)
-        if (a < 0 || a >= n || c < 0 || c >= n || (q > e0 && esrc[q - 1] > a)) {
+        // edges must come grouped by source (non-decreasing esrc) and join a
+        // hit to one on the next or the second next plane (Sec. 5.1)
+        const int dp = (a >= 0 && a < n && c >= 0 && c < n) ? plane[s + c] - plane[s + a] : 0;
+        if (a < 0 || a >= n || c < 0 || c >= n || (q > e0 && esrc[q - 1] > a) || dp < 1 || dp > 2) {
             err = true;
             src_g[q] = s;
             dst_g[q] = s;
@@ -537,9 +539,8 @@ void launch_globalise(velo_ctx *c, const velo_hits *h, const velo_outputs *g, hi
     const int64_t cap = g->edge_capacity < c->cfg.max_edges ? g->edge_capacity : c->cfg.max_edges;
     k_check_capacity<<<1, 1, 0, s>>>(g->n_edges, cap, w.n_edges, nullptr, w.flags);
     const dim3 grid(h->n_events > 0 ? h->n_events : 1, h->n_events > 0 ? 16 : 1);
-    k_globalise<<<grid, 256, 0, s>>>(h->n_events, h->event_offsets, g->edge_offsets,
-                                                w.n_edges, cap, g->edge_src, g->edge_dst, w.src_g,
-                                                w.dst_g, w.flags);
+    k_globalise<<<grid, 256, 0, s>>>(h->n_events, h->event_offsets, g->edge_offsets, w.n_edges, cap, g->edge_src,
+                                     g->edge_dst, h->plane, w.src_g, w.dst_g, w.flags);
 }
 
 void launch_row_ptr(velo_ctx *c, const velo_hits *h, const velo_outputs *g, hipStream_t s) {

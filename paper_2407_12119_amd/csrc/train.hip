@@ -98,8 +98,9 @@ __global__ __launch_bounds__(kBwdBlock) void k_bwd(BwdArgs A) {
 #pragma unroll
             for (int kb = 0; kb < MO; kb++) {
                 X[kb] = P::load(A.a + qc * H, kb, g);
-                X[MO + kb] = P::load(A.b + qc * 2 * H, kb, g);
-                X[2 * MO + kb] = P::load(A.b + qc * 2 * H + H, kb, g);
+                X[MO + kb] = P::load(A.b + qc * kMsgParts * H, kb, g);
+                X[2 * MO + kb] = P::load_f32_sum(A.b + qc * kMsgParts * H + H, A.b + qc * kMsgParts * H + 2 * H,
+                                                 kb, g, 1.f);
             }
         } else if (MODE == B_EDGE_ENC) {
             const int64_t s = A.src_g[qc], d = A.dst_g[qc];
@@ -228,10 +229,10 @@ __global__ __launch_bounds__(kBwdBlock) void k_bwd_node_enc(BwdArgs A) {
 // ------------------------------------------------------------------------
 template <int H, int MODE>
 __global__ __launch_bounds__(kBwdBlock) void k_dw(BwdArgs A, float *__restrict__ part) {
+    static_assert(MODE == B_NODE_ENC, "the other MLPs use k_dw_lds");
     constexpr int MO = H / 16;
-    constexpr int K1 = MODE == B_NODE_ENC ? 3 : bseg<MODE>() * H;
-    constexpr int NB1 = (K1 + 15) / 16;
-    constexpr int M2 = MODE == B_CLS ? 1 : H;
+    constexpr int K1 = 3;
+    constexpr int M2 = H;
     constexpr int PL = H * K1 + H + M2 * H + M2;
     if (*A.flags) return;
     const int lane = threadIdx.x & 63, n = lane & 15, g = lane >> 4, w = threadIdx.x >> 6;
@@ -241,8 +242,7 @@ __global__ __launch_bounds__(kBwdBlock) void k_dw(BwdArgs A, float *__restrict__
     float *out = part + (int64_t)blockIdx.x * PL;
     const bool active = w < MO;                        // waves beyond the output rows idle
     const int m = active ? w : 0;
-    f32x4 acc1[NB1], acc2[MO];
-    zero<NB1>(acc1);
+    f32x4 acc1 = zero4(), acc2[MO];
     zero<MO>(acc2);
     float sb1 = 0.f, sb2 = 0.f;
     const float *Pn = A.P;
@@ -252,50 +252,18 @@ __global__ __launch_bounds__(kBwdBlock) void k_dw(BwdArgs A, float *__restrict__
         const int64_t rc = ok ? row : (r1 > 0 ? r1 - 1 : 0);
         const float ga = ok ? A.da[rc * H + 16 * m + n] : 0.f;
         sb1 += ga;
-        // layer-1 inputs of this row
-        if (MODE == B_NODE_ENC) {
-            float v = 0.f;
-            if (n == 0) v = (A.x[rc] - Pn[6]) / Pn[9];
-            if (n == 1) v = (A.y[rc] - Pn[7]) / Pn[10];
-            if (n == 2) v = (A.z[rc] - Pn[8]) / Pn[11];
-            acc1[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(ga, v, acc1[0], 0, 0, 0);
-        } else {
-            const float *seg[3];
-            if (MODE == B_EDGE) {
-                seg[0] = A.a + rc * H;
-                seg[1] = A.b + (int64_t)A.src_g[rc] * H;
-                seg[2] = A.b + (int64_t)A.dst_g[rc] * H;
-            } else if (MODE == B_NODE) {
-                seg[0] = A.a + rc * H;
-                seg[1] = A.b + rc * 2 * H;
-                seg[2] = A.b + rc * 2 * H + H;
-            } else if (MODE == B_EDGE_ENC) {
-                seg[0] = A.a + (int64_t)A.src_g[rc] * H;
-                seg[1] = A.a + (int64_t)A.dst_g[rc] * H;
-                seg[2] = seg[1];
-            } else {
-                seg[0] = A.a + rc * H;
-                seg[1] = seg[2] = seg[0];
-            }
-#pragma unroll
-            for (int nb = 0; nb < NB1; nb++) {
-                const float y = seg[nb / MO][16 * (nb % MO) + n];
-                acc1[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ga, y, acc1[nb], 0, 0, 0);
-            }
-        }
-        // layer 2
-        float gd;
-        if (MODE == B_CLS)
-            gd = ok && m == 0 && n == 0 ? A.dout[rc] : 0.f;
-        else
-            gd = ok ? A.dout[rc * H + 16 * m + n] : 0.f;
+        // layer-1 inputs of this row: the normalised coordinates
+        float v = 0.f;
+        if (n == 0) v = (A.x[rc] - Pn[6]) / Pn[9];
+        if (n == 1) v = (A.y[rc] - Pn[7]) / Pn[10];
+        if (n == 2) v = (A.z[rc] - Pn[8]) / Pn[11];
+        acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(ga, v, acc1, 0, 0, 0);
+        const float gd = ok ? A.dout[rc * H + 16 * m + n] : 0.f;
         sb2 += gd;
-        if (MODE != B_CLS || m == 0) {
 #pragma unroll
-            for (int nb = 0; nb < MO; nb++) {
-                const float y = ok ? A.r[rc * H + 16 * nb + n] : 0.f;
-                acc2[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(gd, y, acc2[nb], 0, 0, 0);
-            }
+        for (int nb = 0; nb < MO; nb++) {
+            const float y = ok ? A.r[rc * H + 16 * nb + n] : 0.f;
+            acc2[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(gd, y, acc2[nb], 0, 0, 0);
         }
     }
     if (!active) return;
@@ -305,28 +273,15 @@ __global__ __launch_bounds__(kBwdBlock) void k_dw(BwdArgs A, float *__restrict__
     sb2 += __shfl_xor(sb2, 16);
     sb2 += __shfl_xor(sb2, 32);
 #pragma unroll
-    for (int nb = 0; nb < NB1; nb++)
-#pragma unroll
-        for (int i = 0; i < 4; i++) {
-            const int row = 16 * m + 4 * g + i, col = 16 * nb + n;
-            if (col < K1) out[row * K1 + col] = acc1[nb][i];
-        }
+    for (int i = 0; i < 4; i++)
+        if (n < K1) out[(16 * m + 4 * g + i) * K1 + n] = acc1[i];
     if (g == 0) out[H * K1 + 16 * m + n] = sb1;
     float *o2 = out + H * K1 + H;
-    if (MODE == B_CLS) {
-        if (m == 0) {
 #pragma unroll
-            for (int nb = 0; nb < MO; nb++)
-                if (g == 0) o2[16 * nb + n] = acc2[nb][0];    // output row 0
-            if (lane == 0) o2[H] = sb2;
-        }
-    } else {
+    for (int nb = 0; nb < MO; nb++)
 #pragma unroll
-        for (int nb = 0; nb < MO; nb++)
-#pragma unroll
-            for (int i = 0; i < 4; i++) o2[(16 * m + 4 * g + i) * H + 16 * nb + n] = acc2[nb][i];
-        if (g == 0) o2[M2 * H + 16 * m + n] = sb2;
-    }
+        for (int i = 0; i < 4; i++) o2[(16 * m + 4 * g + i) * H + 16 * nb + n] = acc2[nb][i];
+    if (g == 0) o2[M2 * H + 16 * m + n] = sb2;
 }
 
 // The same weight gradients with the rows staged in LDS: a tile of kDwRows
@@ -379,8 +334,8 @@ __global__ __launch_bounds__(kBwdBlock) void k_dw_lds(BwdArgs A, float *__restri
             seg[2] = A.b + (int64_t)A.dst_g[rc] * H;
         } else if (MODE == B_NODE) {
             seg[0] = A.a + rc * H;
-            seg[1] = A.b + rc * 2 * H;
-            seg[2] = A.b + rc * 2 * H + H;
+            seg[1] = A.b + rc * kMsgParts * H;
+            seg[2] = A.b + rc * kMsgParts * H + H;       // + the part at + 2H (m_in)
         } else if (MODE == B_EDGE_ENC) {
             seg[0] = A.a + (int64_t)A.src_g[rc] * H;
             seg[1] = seg[2] = A.a + (int64_t)A.dst_g[rc] * H;
@@ -391,7 +346,10 @@ __global__ __launch_bounds__(kBwdBlock) void k_dw_lds(BwdArgs A, float *__restri
         for (int y = 0; y < NY; y++) {
             const int j = q + 16 * y;
             ny[y] = zero4();
-            if (ok && j < CY) ny[y] = *(const f32x4 *)(seg[j / CH] + 4 * (j % CH));
+            if (ok && j < CY) {
+                ny[y] = *(const f32x4 *)(seg[j / CH] + 4 * (j % CH));
+                if (MODE == B_NODE && j / CH == 2) ny[y] += *(const f32x4 *)(seg[2] + H + 4 * (j % CH));
+            }
         }
 #pragma unroll
         for (int y = 0; y < NHC; y++) {
@@ -646,7 +604,7 @@ void backward_h(velo_ctx *c, const velo_hits *hits, const float *Pw, const float
         ce ^= 1;
         // node network k
         BwdArgs nd = base;
-        nd.n_dev = nullptr; nd.n_host = N; nd.a = hk(k); nd.b = w.ck_m + (int64_t)k * Nmax * 2 * H;
+        nd.n_dev = nullptr; nd.n_host = N; nd.a = hk(k); nd.b = w.ck_m + (int64_t)k * Nmax * kMsgParts * H;
         nd.dout = w.g_h[ch]; nd.dres = w.g_h[ch ^ 1]; nd.dx1 = w.g_m;
         nd.o_w1 = L.node[k][0].w; nd.o_w2 = L.node[k][1].w;
         if (N > 0) {
