@@ -253,7 +253,6 @@ velo_status velo_calibrate(velo_ctx *c, const velo_hits *h, void *stream) {
     launch_embed(c, h, w.emb, true, s);
     launch_knn(c, h, w.emb, s);
     launch_compact(c, h, &g, s);
-    launch_in_lists_plane(c, h, s);
     launch_gnn(c, h, w.tmp_logit, c->params, false, true, s);
     launch_act_scales(c, s);
     c->calibrated = true;
@@ -310,11 +309,7 @@ velo_status velo_gnn(velo_ctx *c, const velo_hits *h, velo_outputs *g, void *str
     hipStream_t s = (hipStream_t)stream;
     { StageTimer t(c, VELO_STAGE_PREPARE, s); launch_prepare(c, h, s); }
     { StageTimer t(c, VELO_STAGE_COMPACT, s); launch_globalise(c, h, g, s); }
-    {
-        StageTimer t(c, VELO_STAGE_LISTS, s);
-        launch_row_ptr(c, h, g, s);
-        launch_in_lists_plane(c, h, s);
-    }
+    { StageTimer t(c, VELO_STAGE_LISTS, s); launch_row_ptr(c, h, g, s); }
     launch_gnn(c, h, g->edge_logit, c->params, false, false, s);
     return device_status(c, "velo_gnn");
 }
@@ -349,7 +344,6 @@ velo_status velo_infer(velo_ctx *c, const velo_hits *h, velo_outputs *o, void *s
     { StageTimer t(c, VELO_STAGE_EMBED, s); launch_embed(c, h, c->ws.emb, false, s); }
     { StageTimer t(c, VELO_STAGE_KNN, s); launch_knn(c, h, c->ws.emb, s); }
     { StageTimer t(c, VELO_STAGE_COMPACT, s); launch_compact(c, h, o, s); }
-    { StageTimer t(c, VELO_STAGE_LISTS, s); launch_in_lists_plane(c, h, s); }
     launch_gnn(c, h, o->edge_logit, c->params, false, false, s);
     { StageTimer t(c, VELO_STAGE_COMPONENTS, s); launch_components(c, h, o, s); }
     return device_status(c, "velo_infer");
