@@ -113,11 +113,13 @@ __global__ __launch_bounds__(kBwdBlock) void k_bwd(BwdArgs A) {
 #pragma unroll
             for (int kb = 0; kb < MO; kb++) X[kb] = P::load(A.a + qc * H, kb, g);
         }
-        // recompute the hidden layer
+        // recompute the hidden layer exactly as the forward kernel does
+        // (accumulators seeded with the bias), so the ReLU masks agree
         f32x4 r[MO];
-        zero<MO>(r);
+#pragma unroll
+        for (int mo = 0; mo < MO; mo++) r[mo] = rb1[mo];
         gemm<P, MO, NSEG * MO>(sW1, X, r, lane);
-        bias_relu<MO>(r, rb1);
+        relu<MO>(r);
         // dL/d(hidden) = W2^T dout, masked by the ReLU
         f32x4 da[MO];
         if (CLS) {
