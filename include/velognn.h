@@ -174,7 +174,7 @@ typedef enum {
     VELO_STAGE_EMBED = 1,      /* embedding MLP (Sec. 5.1) */
     VELO_STAGE_KNN = 2,        /* neighbour search with top-k (Sec. 5.1, 7.2) */
     VELO_STAGE_COMPACT = 3,    /* degree scan and CSR compaction */
-    VELO_STAGE_LISTS = 4,      /* row pointers of a given graph; incoming lists (training) */
+    VELO_STAGE_LISTS = 4,      /* incoming lists (and row pointers of a given graph) */
     VELO_STAGE_NODE_ENC = 5,   /* node encoder (Sec. 5.2) */
     VELO_STAGE_EDGE_ENC = 6,   /* edge encoder (Sec. 5.2) */
     VELO_STAGE_MESSAGES = 7,   /* scatter_add message sums, one launch per step */

@@ -169,7 +169,7 @@ velo_status velo_create(const velo_config *cfg, velo_ctx **out) {
               dalloc(&w.in_ptr, N + 1) &&
               dalloc(&w.in_list, E) && dalloc(&w.scan_tmp, w.scan_tmp_len) &&
               dalloc((char **)&w.h[0], N * H * sb) && dalloc((char **)&w.h[1], N * H * sb) &&
-              dalloc(&w.m, N * kMsgParts * H) && dalloc((char **)&w.e, E * H * sb) && dalloc(&w.n_edges, 1) &&
+              dalloc(&w.m, N * 2 * H) && dalloc((char **)&w.e, E * H * sb) && dalloc(&w.n_edges, 1) &&
               dalloc(&w.flags, 1) &&
               dalloc(&w.eoff_tmp, B + 1);
     if (ok && k.precision == VELO_FP8) {
@@ -183,7 +183,7 @@ velo_status velo_create(const velo_config *cfg, velo_ctx **out) {
     if (ok && k.training) {
         const int64_t it = k.gnn_iters, R = std::max<int64_t>(N, E);
         ok = dalloc((char **)&w.ck_h, (it + 1) * N * H * sb) && dalloc((char **)&w.ck_e, (it + 1) * E * H * sb) &&
-             dalloc(&w.ck_m, std::max<int64_t>(it, 1) * N * kMsgParts * H) && dalloc(&w.g_e[0], E * H) &&
+             dalloc(&w.ck_m, std::max<int64_t>(it, 1) * N * 2 * H) && dalloc(&w.g_e[0], E * H) &&
              dalloc(&w.g_e[1], E * H) && dalloc(&w.g_h[0], N * H) && dalloc(&w.g_h[1], N * H) &&
              dalloc(&w.g_xs, E * H) && dalloc(&w.g_xd, E * H) && dalloc(&w.g_da, R * H) && dalloc(&w.g_r, R * H) &&
              dalloc(&w.g_m, N * 2 * H) && dalloc(&w.g_part, (int64_t)train_part_floats(k.gnn_hidden)) &&
@@ -253,6 +253,7 @@ velo_status velo_calibrate(velo_ctx *c, const velo_hits *h, void *stream) {
     launch_embed(c, h, w.emb, true, s);
     launch_knn(c, h, w.emb, s);
     launch_compact(c, h, &g, s);
+    launch_in_lists_plane(c, h, s);
     launch_gnn(c, h, w.tmp_logit, c->params, false, true, s);
     launch_act_scales(c, s);
     c->calibrated = true;
@@ -309,7 +310,11 @@ velo_status velo_gnn(velo_ctx *c, const velo_hits *h, velo_outputs *g, void *str
     hipStream_t s = (hipStream_t)stream;
     { StageTimer t(c, VELO_STAGE_PREPARE, s); launch_prepare(c, h, s); }
     { StageTimer t(c, VELO_STAGE_COMPACT, s); launch_globalise(c, h, g, s); }
-    { StageTimer t(c, VELO_STAGE_LISTS, s); launch_row_ptr(c, h, g, s); }
+    {
+        StageTimer t(c, VELO_STAGE_LISTS, s);
+        launch_row_ptr(c, h, g, s);
+        launch_in_lists_plane(c, h, s);
+    }
     launch_gnn(c, h, g->edge_logit, c->params, false, false, s);
     return device_status(c, "velo_gnn");
 }
@@ -344,6 +349,7 @@ velo_status velo_infer(velo_ctx *c, const velo_hits *h, velo_outputs *o, void *s
     { StageTimer t(c, VELO_STAGE_EMBED, s); launch_embed(c, h, c->ws.emb, false, s); }
     { StageTimer t(c, VELO_STAGE_KNN, s); launch_knn(c, h, c->ws.emb, s); }
     { StageTimer t(c, VELO_STAGE_COMPACT, s); launch_compact(c, h, o, s); }
+    { StageTimer t(c, VELO_STAGE_LISTS, s); launch_in_lists_plane(c, h, s); }
     launch_gnn(c, h, o->edge_logit, c->params, false, false, s);
     { StageTimer t(c, VELO_STAGE_COMPONENTS, s); launch_components(c, h, o, s); }
     return device_status(c, "velo_infer");

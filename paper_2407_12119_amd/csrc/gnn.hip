@@ -264,12 +264,12 @@ __global__ __launch_bounds__(512) void k_mlp(MlpArgs A) {
             }
         }
         if (MODE == NODE) {
-            const float *m = (const float *)A.b + qc * kMsgParts * H;
+            const float *m = (const float *)A.b + qc * 2 * H;
 #pragma unroll
             for (int kb = 0; kb < KB; kb++) {
                 if constexpr (!RAW) X[kb] = P::load(sa + qc * H, kb, g, ix);
                 X[KB + kb] = P::load_f32(m, kb, g, ix);
-                X[2 * KB + kb] = P::load_f32_sum(m + H, m + 2 * H, kb, g, ix);
+                X[2 * KB + kb] = P::load_f32(m + H, kb, g, ix);
             }
         } else if (MODE == EDGE) {
             const S *hb = (const S *)A.b;
@@ -362,135 +362,46 @@ __global__ __launch_bounds__(512) void k_mlp(MlpArgs A) {
 }
 
 // ------------------------------------------------------------------------
-// messages (Sec. 5.2, the two scatter_add sums), one pass over the edge states
-//
-// One workgroup per (event, source plane p) streams the out-edges of the
-// plane's hits: they are one contiguous range, and their destinations are the
-// contiguous hits of planes p+1 and p+2.  Each of the 4 wavefronts owns a
-// quarter of the channels; per source row it
-//   * sums the row's edge states: m_out of the row, complete;
-//   * adds each edge state to its destination's accumulator: the part of
-//     m_in that comes from plane p (from sources one plane back for plane p+1
-//     destinations, two planes back for plane p+2).
-// Accumulators live in LDS when the destinations fit, else in the message
-// array itself; each wavefront only touches its own channels, and rows are
-// taken in order, so every float32 sum has a fixed order.  The node network
-// adds the two incoming parts.  Hits of plane 0 (no sources one or two
-// planes back) and plane 1 (none two back) get zero parts from the plane-0
-// workgroup.
+// messages m_i = [sum_{i->j} e_ij, sum_{j->i} e_ji]  (Sec. 5.2, scatter_add)
+// H/4 lanes per hit, 4 channels per lane, float32 sums in edge-id order
 // ------------------------------------------------------------------------
-constexpr int kMsgBlock = 256;
-constexpr int kMsgLdsBytes = 32768;
-
 template <class P, int H>
-__global__ __launch_bounds__(kMsgBlock) void k_messages(const int *__restrict__ off,
-                                                        const int *__restrict__ plane_off,
-                                                        const int *__restrict__ row_ptr,
-                                                        const int *__restrict__ dst_g,
-                                                        const typename P::state_t *__restrict__ e,
-                                                        float *__restrict__ m, const unsigned *__restrict__ flags) {
-    constexpr int SW = H / 4;                 // channels per wavefront
-    constexpr int LPE = SW / 4;               // lanes per edge (4 channels each)
-    constexpr int EPI = 64 / LPE;             // edges per step
-    constexpr int MR = kMsgParts * H;         // message row
-    constexpr int DCAP = kMsgLdsBytes / (4 * H);
-    __shared__ __align__(16) float sacc[kMsgLdsBytes / 4];
+__global__ __launch_bounds__(256) void k_messages(int64_t n_hits, const int *__restrict__ out_ptr,
+                                                  const int *__restrict__ in_ptr,
+                                                  const int *__restrict__ in_list,
+                                                  const typename P::state_t *__restrict__ e,
+                                                  float *__restrict__ m, int xcd, const unsigned *__restrict__ flags) {
     if (*flags) return;
-    const int b = blockIdx.x / VELO_N_PLANES, p = blockIdx.x % VELO_N_PLANES;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int ep = lane / LPE, c = w * SW + 4 * (lane % LPE);
-    const int64_t s = off[b];
-    const int *po = plane_off + (int64_t)b * kPlaneSlots;
-    const int64_t r0 = s + po[p], r1 = s + po[p + 1];                      // source rows
-    const int64_t d0 = s + po[min(p + 1, VELO_N_PLANES)];                  // destinations: planes p+1, p+2
-    const int64_t dn = s + po[min(p + 2, VELO_N_PLANES)];
-    const int64_t d1 = s + po[min(p + 3, VELO_N_PLANES)];
-    const int D = (int)(d1 - d0), Dn = (int)(dn - d0);
-    if (p == 0) {                 // incoming parts that no workgroup produces
-        const int64_t a0 = s + po[0], a1 = s + po[1], a2 = s + po[min(2, VELO_N_PLANES)];
-        for (int64_t i = a0 + ep; i < a2; i += EPI) {
-            if (i < a1) *(f32x4 *)(m + i * MR + H + c) = zero4();
-            *(f32x4 *)(m + i * MR + 2 * H + c) = zero4();
+    constexpr int LPN = H / 4, NPW = 64 / LPN;
+    const int lane = threadIdx.x & 63, sub = lane / LPN, c = 4 * (lane % LPN);
+    const WaveRange wr = wave_range((n_hits + NPW - 1) / NPW, xcd != 0);
+    for (int64_t u = wr.first; u < wr.end; u += wr.step) {
+        const int64_t i = u * NPW + sub;
+        if (i >= n_hits) continue;
+        f32x4 so = zero4(), si = zero4();
+        const int a0 = out_ptr[i], a1 = out_ptr[i + 1];
+        int a = a0;
+        for (; a + 4 <= a1; a += 4) {
+            const f32x4 v0 = P::load4(e + (int64_t)a * H + c);
+            const f32x4 v1 = P::load4(e + (int64_t)(a + 1) * H + c);
+            const f32x4 v2 = P::load4(e + (int64_t)(a + 2) * H + c);
+            const f32x4 v3 = P::load4(e + (int64_t)(a + 3) * H + c);
+            so += v0; so += v1; so += v2; so += v3;
         }
-    }
-    // stream the block's edges in steps of EPI edges of one row; two steps in flight
-    struct Step {
-        int64_t row;
-        int q0, q1;
-        bool last;
-    };
-    // destinations in chunks of DCAP (one chunk unless the two planes hold
-    // more hits); the first pass also forms the outgoing sums
-    for (int k0 = 0; k0 == 0 || k0 < D; k0 += DCAP) {
-        const int kc = min(D - k0, DCAP);
-        const bool first = k0 == 0;
-        for (int k = ep; k < kc; k += EPI) *(f32x4 *)(sacc + k * H + c) = zero4();
-        int64_t it_row = r0;
-        int it_q = r0 < r1 ? row_ptr[r0] : 0;
-        auto next = [&](Step &st) -> bool {
-            if (it_row >= r1) return false;
-            const int qe = row_ptr[it_row + 1];
-            st.row = it_row;
-            st.q0 = it_q;
-            st.q1 = qe;
-            st.last = it_q + EPI >= qe;
-            if (st.last) {
-                it_row++;
-                it_q = qe;
-            } else {
-                it_q += EPI;
-            }
-            return true;
-        };
-        // this lane's edge of step st: its state (if needed) and its chunk-local destination (-1: none)
-        auto load = [&](const Step &st, f32x4 &v, int &k) {
-            const int q = st.q0 + ep;
-            v = zero4();
-            k = -1;
-            if (q < st.q1) {
-                const int kk = (int)(dst_g[q] - d0) - k0;
-                const bool in = kk >= 0 && kk < kc;
-                if (first || in) v = P::load4(e + (int64_t)q * H + c);
-                if (in) k = kk;
-            }
-        };
-        Step sa, sb;
-        f32x4 va = zero4(), vb = zero4();
-        int ka = -1, kb = -1;
-        bool ha = next(sa), hb = ha && next(sb);
-        if (ha) load(sa, va, ka);
-        if (hb) load(sb, vb, kb);
-        f32x4 so = zero4();
-        while (ha) {
-            const Step st = sa;
-            const f32x4 v = va;
-            const int k = ka;
-            sa = sb; va = vb; ka = kb; ha = hb;
-            if (ha) {
-                hb = next(sb);
-                if (hb) load(sb, vb, kb);
-            }
-            if (k >= 0) {
-                float *a = sacc + k * H + c;
-                *(f32x4 *)a = *(const f32x4 *)a + v;
-            }
-            if (first) {
-                so += v;
-                if (st.last) {
-                    // the row's sum over the step's edge positions (fixed tree)
-#pragma unroll
-                    for (int x = LPE; x < 64; x <<= 1)
-#pragma unroll
-                        for (int i = 0; i < 4; i++) so[i] += __shfl_xor(so[i], x);
-                    if (ep == 0) *(f32x4 *)(m + st.row * MR + c) = so;
-                    so = zero4();
-                }
-            }
+        for (; a < a1; a++) so += P::load4(e + (int64_t)a * H + c);
+        const int b0 = in_ptr[i], b1 = in_ptr[i + 1];
+        int b = b0;
+        for (; b + 4 <= b1; b += 4) {
+            const int q0 = in_list[b], q1 = in_list[b + 1], q2 = in_list[b + 2], q3 = in_list[b + 3];
+            const f32x4 v0 = P::load4(e + (int64_t)q0 * H + c);
+            const f32x4 v1 = P::load4(e + (int64_t)q1 * H + c);
+            const f32x4 v2 = P::load4(e + (int64_t)q2 * H + c);
+            const f32x4 v3 = P::load4(e + (int64_t)q3 * H + c);
+            si += v0; si += v1; si += v2; si += v3;
         }
-        for (int k = ep; k < kc; k += EPI) {
-            const int kk = k0 + k;
-            *(f32x4 *)(m + (d0 + kk) * MR + (kk < Dn ? H : 2 * H) + c) = *(const f32x4 *)(sacc + k * H + c);
-        }
+        for (; b < b1; b++) si += P::load4(e + (int64_t)in_list[b] * H + c);
+        *(f32x4 *)(m + i * 2 * H + c) = so;
+        *(f32x4 *)(m + i * 2 * H + H + c) = si;
     }
 }
 
@@ -532,7 +443,7 @@ void gnn_ph(velo_ctx *c, const velo_hits *hits, float *logit, const float *Pw, b
     const int s_nenc = kSlotNodeEnc, s_eenc = kSlotEdgeEnc, s_cls = slot_cls(iters);
     auto hk = [&](int k) -> S * { return train ? (S *)w.ck_h + (int64_t)k * Nmax * H : (S *)w.h[k & 1]; };
     auto ek = [&](int k) -> S * { return train ? (S *)w.ck_e + (int64_t)k * Ecap * H : (S *)w.e; };
-    auto mk = [&](int k) -> float * { return train ? w.ck_m + (int64_t)k * Nmax * kMsgParts * H : w.m; };
+    auto mk = [&](int k) -> float * { return train ? w.ck_m + (int64_t)k * Nmax * 2 * H : w.m; };
     // the classifier is fused into the last edge network when its weights fit in LDS too
     const bool fuse_cls = !train && mlp_lds<P, H, EDGE, true>() <= c->lds_max;
     if (N > 0) {
@@ -555,8 +466,8 @@ void gnn_ph(velo_ctx *c, const velo_hits *hits, float *logit, const float *Pw, b
     for (int k = 0; k < iters; k++) {
         if (N > 0) {
             StageTimer t(c, VELO_STAGE_MESSAGES, s);
-            k_messages<P, H><<<hits->n_events * VELO_N_PLANES, kMsgBlock, 0, s>>>(
-                hits->event_offsets, w.plane_off, w.row_ptr, w.dst_g, ek(k), mk(k), w.flags);
+            k_messages<P, H><<<persistent_grid(c, stage_per_cu(c, VELO_STAGE_MESSAGES, 16)), 256, 0, s>>>(
+                N, w.row_ptr, w.in_ptr, w.in_list, ek(k), mk(k), c->tune_xcd[VELO_STAGE_MESSAGES], w.flags);
         }
         MlpArgs nd{};
         nd.n_dev = nullptr; nd.n_host = N; nd.a = hk(k); nd.b = mk(k); nd.out = hk(k + 1);

@@ -16,10 +16,7 @@ constexpr unsigned kErrInput = 1u;     // invalid hits (offsets, planes, order, 
 constexpr unsigned kErrCapacity = 2u;  // more edges than the edge arrays hold
 
 constexpr int kPlaneSlots = VELO_N_PLANES + 1;   // plane_off entries per event
-// Messages of a hit, float32, H channels each: [m_out | m_in from the
-// sources one plane back | m_in from the sources two planes back]; the
-// incoming sum is the last two added.
-constexpr int kMsgParts = 3;
+
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 

@@ -33,10 +33,6 @@ struct F32 {
     __device__ static frag_t load_f32(const float *row, int kb, int g) { return load(row, kb, g); }
     __device__ static frag_t load(const float *row, int kb, int g, float) { return load(row, kb, g); }
     __device__ static frag_t load_f32(const float *row, int kb, int g, float) { return load(row, kb, g); }
-    // the elementwise sum of two float32 rows, as an operand
-    __device__ static frag_t load_f32_sum(const float *a, const float *b, int kb, int g, float) {
-        return load(a, kb, g) + load(b, kb, g);
-    }
     template <int MO>
     __device__ static void chain(const f32x4 *h, frag_t *x, float) { chain<MO>(h, x); }
     template <int MO>
@@ -91,11 +87,6 @@ struct BF16 {
     }
     __device__ static frag_t load(const bf16 *row, int kb, int g, float) { return load(row, kb, g); }
     __device__ static frag_t load_f32(const float *row, int kb, int g, float) { return load_f32(row, kb, g); }
-    __device__ static frag_t load_f32_sum(const float *a, const float *b, int kb, int g, float) {
-        const int o = 32 * kb + 8 * g;
-        return cat(cvt(*(const f32x4 *)(a + o) + *(const f32x4 *)(b + o)),
-                   cvt(*(const f32x4 *)(a + o + 4) + *(const f32x4 *)(b + o + 4)));
-    }
     template <int MO>
     __device__ static void chain(const f32x4 *h, frag_t *x, float) { chain<MO>(h, x); }
     __device__ static int stored(int mo, int g) { return 32 * (mo >> 1) + 8 * g + 4 * (mo & 1); }
@@ -155,11 +146,6 @@ struct FP8 {
     }
     __device__ static frag_t load_f32(const float *row, int kb, int g, float inv) {
         return pack8(*(const f32x4 *)(row + 32 * kb + 8 * g), *(const f32x4 *)(row + 32 * kb + 8 * g + 4), inv);
-    }
-    __device__ static frag_t load_f32_sum(const float *a, const float *b, int kb, int g, float inv) {
-        const int o = 32 * kb + 8 * g;
-        return pack8(*(const f32x4 *)(a + o) + *(const f32x4 *)(b + o),
-                     *(const f32x4 *)(a + o + 4) + *(const f32x4 *)(b + o + 4), inv);
     }
     template <int MO>
     __device__ static void mma(const wfrag_t *a, const frag_t &x, f32x4 *acc) {

@@ -98,9 +98,8 @@ __global__ __launch_bounds__(kBwdBlock) void k_bwd(BwdArgs A) {
 #pragma unroll
             for (int kb = 0; kb < MO; kb++) {
                 X[kb] = P::load(A.a + qc * H, kb, g);
-                X[MO + kb] = P::load(A.b + qc * kMsgParts * H, kb, g);
-                X[2 * MO + kb] = P::load_f32_sum(A.b + qc * kMsgParts * H + H, A.b + qc * kMsgParts * H + 2 * H,
-                                                 kb, g, 1.f);
+                X[MO + kb] = P::load(A.b + qc * 2 * H, kb, g);
+                X[2 * MO + kb] = P::load(A.b + qc * 2 * H + H, kb, g);
             }
         } else if (MODE == B_EDGE_ENC) {
             const int64_t s = A.src_g[qc], d = A.dst_g[qc];
@@ -336,8 +335,8 @@ __global__ __launch_bounds__(kBwdBlock) void k_dw_lds(BwdArgs A, float *__restri
             seg[2] = A.b + (int64_t)A.dst_g[rc] * H;
         } else if (MODE == B_NODE) {
             seg[0] = A.a + rc * H;
-            seg[1] = A.b + rc * kMsgParts * H;
-            seg[2] = A.b + rc * kMsgParts * H + H;       // + the part at + 2H (m_in)
+            seg[1] = A.b + rc * 2 * H;
+            seg[2] = A.b + rc * 2 * H + H;
         } else if (MODE == B_EDGE_ENC) {
             seg[0] = A.a + (int64_t)A.src_g[rc] * H;
             seg[1] = seg[2] = A.a + (int64_t)A.dst_g[rc] * H;
@@ -350,7 +349,6 @@ __global__ __launch_bounds__(kBwdBlock) void k_dw_lds(BwdArgs A, float *__restri
             ny[y] = zero4();
             if (ok && j < CY) {
                 ny[y] = *(const f32x4 *)(seg[j / CH] + 4 * (j % CH));
-                if (MODE == B_NODE && j / CH == 2) ny[y] += *(const f32x4 *)(seg[2] + H + 4 * (j % CH));
             }
         }
 #pragma unroll
@@ -606,7 +604,7 @@ void backward_h(velo_ctx *c, const velo_hits *hits, const float *Pw, const float
         ce ^= 1;
         // node network k
         BwdArgs nd = base;
-        nd.n_dev = nullptr; nd.n_host = N; nd.a = hk(k); nd.b = w.ck_m + (int64_t)k * Nmax * kMsgParts * H;
+        nd.n_dev = nullptr; nd.n_host = N; nd.a = hk(k); nd.b = w.ck_m + (int64_t)k * Nmax * 2 * H;
         nd.dout = w.g_h[ch]; nd.dres = w.g_h[ch ^ 1]; nd.dx1 = w.g_m;
         nd.o_w1 = L.node[k][0].w; nd.o_w2 = L.node[k][1].w;
         if (N > 0) {
