@@ -127,7 +127,9 @@ __global__ __launch_bounds__(256) void k_knn(int64_t n_hits, const int *__restri
         for (int c = kKeyChunks; c < nch; c++)
             m += __popcll(ballot(cand_key(emb, base, C, c * 64 + lane, q, d2max) != kInvalidKey));
 
-        // threshold T: the kmax-th smallest key (only needed when m > kmax)
+        // threshold T: the kmax-th smallest key (only needed when m > kmax).
+        // A probe with exactly kmax keys below it ends the search: those
+        // keys are the kmax smallest and none ties with a dropped one.
         unsigned T = 0x7fffffffu;
         int need_ties = 0;
         if (m > kmax) {
@@ -140,6 +142,10 @@ __global__ __launch_bounds__(256) void k_knn(int64_t n_hits, const int *__restri
                     if (c < nch) cnt += __popcll(ballot(key[c] < cand));
                 for (int c = kKeyChunks; c < nch; c++)
                     cnt += __popcll(ballot(cand_key(emb, base, C, c * 64 + lane, q, d2max) < cand));
+                if (cnt == kmax) {
+                    T = cand;
+                    break;
+                }
                 if (cnt < kmax) T = cand;
             }
             int less = 0;
