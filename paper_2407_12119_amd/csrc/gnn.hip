@@ -379,7 +379,10 @@ __global__ __launch_bounds__(512) void k_mlp(MlpArgs A) {
                 for (int i = threadIdx.x; i < nchunk; i += blockDim.x) ((f32x4 *)sh)[i] = src[i];
             }
             __syncthreads();
-            const S *hb = cached ? sh - h0 * H : hg;
+            // end points index rows of hb relative to hoff (both lie in [h0, h1)
+            // for a validated graph: source on plane p, destination on p+1 or p+2)
+            const S *hb = cached ? sh : hg;
+            const int64_t hoff = cached ? h0 : 0;
             const int64_t units = (e1 - e0 + 15) >> 4;
             // in flight: the next tile's edge-row part and end-point indices;
             // the hit states come from LDS when the tile is computed
@@ -408,7 +411,7 @@ __global__ __launch_bounds__(512) void k_mlp(MlpArgs A) {
             for (; u < units; u += nwb) {
                 typename P::frag_t X[NX];
                 raw_t R[RAW ? KB : 1];
-                const int64_t sv = sn, dv = dn;
+                const int64_t sv = sn - hoff, dv = dn - hoff;
                 constexpr int SEG = MODE == EDGE ? 1 : 0;
                 if constexpr (MODE == EDGE) {
 #pragma unroll
