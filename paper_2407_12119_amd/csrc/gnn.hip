@@ -167,35 +167,16 @@ struct MlpArgs {
     const float *sc, *sc_cls;      // fp8 scales of this MLP and of the classifier (else null)
     float *amax, *amax_cls;        // calibration maxima (else null)
     int xcd;                       // XCD-blocked work mapping
-    // plane-blocked edge MLPs: event offsets, plane offsets, source rows
-    const int *ev_off, *plane_off, *rows;
-    int n_events;
     const unsigned *flags;
 };
 
 template <int MODE>
 constexpr int nseg() { return MODE == EDGE_ENC ? 2 : (MODE == CLS_ONLY ? 0 : 3); }
 
-// Edge MLPs on 2-byte states with H <= 64 run on (event, plane) work items
-// whose end-point hit states are staged in LDS (kHitCache rows; larger
-// windows read them from global memory).
-constexpr int kHitCache = 256;
-
-template <class P, int H, int MODE>
-constexpr bool plane_blocked() {
-    return sizeof(typename P::state_t) == 2 && H <= 64 && (MODE == EDGE || MODE == EDGE_ENC);
-}
-
-template <class P, int H, int MODE, bool CLS>
-constexpr size_t mlp_lds_base() {
-    return (nseg<MODE>() ? frag_bytes<P>(H, nseg<MODE>() * H) + frag_bytes<P>(H, H) + sizeof(float) * 2 * H : 0) +
-           (CLS ? frag_bytes<P>(H, H) + sizeof(float) * 2 * H : 0);
-}
-
 template <class P, int H, int MODE, bool CLS>
 constexpr size_t mlp_lds() {
-    return mlp_lds_base<P, H, MODE, CLS>() +
-           (plane_blocked<P, H, MODE>() ? (size_t)kHitCache * H * sizeof(typename P::state_t) : 0);
+    return (nseg<MODE>() ? frag_bytes<P>(H, nseg<MODE>() * H) + frag_bytes<P>(H, H) + sizeof(float) * 2 * H : 0) +
+           (CLS ? frag_bytes<P>(H, H) + sizeof(float) * 2 * H : 0);
 }
 
 template <class P, int H>
@@ -264,19 +245,17 @@ __global__ __launch_bounds__(512) void k_mlp(MlpArgs A) {
     int64_t N = A.n_host;
     if (A.n_dev) N = min((int64_t)*A.n_dev, A.n_host);
     const S *sa = (const S *)A.a;
+    const int64_t units = (N + 15) >> 4;
     constexpr int NX = NSEG > 0 ? NSEG * KB : KB;
     const float ix = SC.ix1;
+    // gather the inputs of unit u into X
     // fp8 keeps the stored (bf16) state of segment 0 for the residual, so it
     // is not read twice
     constexpr bool RAW = P::kScaled && (MODE == NODE || MODE == EDGE);
     using raw_t = BF16::frag_t;
-    // the hit states an edge MLP gathers (EDGE: h^{k+1}; EDGE_ENC: h^0)
-    const S *hg = MODE == EDGE ? (const S *)A.b : sa;
-    // gather the inputs of the tile of items q0 + n (n < 16), q < qe, into X;
-    // gathered hit rows are read at hb + row * H
-    auto load_tile = [&](int64_t q0, int64_t qe, const S *hb, typename P::frag_t *X, raw_t *R) {
-        const int64_t q = q0 + n;
-        const int64_t qc = q < qe ? q : qe - 1;
+    auto load_unit = [&](int64_t u, typename P::frag_t *X, raw_t *R) {
+        const int64_t q = u * 16 + n;
+        const int64_t qc = q < N ? q : N - 1;
         if constexpr (RAW) {
 #pragma unroll
             for (int kb = 0; kb < KB; kb++) {
@@ -293,6 +272,7 @@ __global__ __launch_bounds__(512) void k_mlp(MlpArgs A) {
                 X[2 * KB + kb] = P::load_f32(m + H, kb, g, ix);
             }
         } else if (MODE == EDGE) {
+            const S *hb = (const S *)A.b;
             const int64_t s = A.src_g[qc], d = A.dst_g[qc];
 #pragma unroll
             for (int kb = 0; kb < KB; kb++) {
@@ -304,16 +284,43 @@ __global__ __launch_bounds__(512) void k_mlp(MlpArgs A) {
             const int64_t s = A.src_g[qc], d = A.dst_g[qc];
 #pragma unroll
             for (int kb = 0; kb < KB; kb++) {
-                X[kb] = P::load(hb + s * H, kb, g, ix);
-                X[KB + kb] = P::load(hb + d * H, kb, g, ix);
+                X[kb] = P::load(sa + s * H, kb, g, ix);
+                X[KB + kb] = P::load(sa + d * H, kb, g, ix);
             }
         }
     };
-    // the MLP (and classifier) on a loaded tile
-    auto compute_tile = [&](int64_t q0, int64_t qe, typename P::frag_t *X, raw_t *R) {
-        const int64_t q = q0 + n;
-        const bool ok = q < qe;
-        const int64_t qc = ok ? q : qe - 1;
+    // memory-bound precisions prefetch the next unit's inputs during the MFMAs
+    constexpr bool PREFETCH = sizeof(S) < 4 && NSEG > 0;
+    // two units in flight: Xn holds unit u + step, Xm unit u + 2 step
+    typename P::frag_t Xn[NX], Xm[NX];
+    raw_t Rn[RAW ? KB : 1], Rm[RAW ? KB : 1];
+    const WaveRange wr = wave_range(units, A.xcd != 0);
+    int64_t u = wr.first;
+    if (PREFETCH && u < wr.end) load_unit(u, Xn, Rn);
+    if (PREFETCH && u + wr.step < wr.end) load_unit(u + wr.step, Xm, Rm);
+    for (; u < wr.end; u += wr.step) {
+        const int64_t q = u * 16 + n;
+        const bool ok = q < N;
+        const int64_t qc = ok ? q : N - 1;
+        typename P::frag_t X[NX];
+        raw_t R[RAW ? KB : 1];
+        if (PREFETCH) {
+#pragma unroll
+            for (int k = 0; k < NX; k++) {
+                X[k] = Xn[k];
+                Xn[k] = Xm[k];
+            }
+            if constexpr (RAW) {
+#pragma unroll
+                for (int k = 0; k < KB; k++) {
+                    R[k] = Rn[k];
+                    Rn[k] = Rm[k];
+                }
+            }
+            if (u + 2 * wr.step < wr.end) load_unit(u + 2 * wr.step, Xm, Rm);
+        } else if (NSEG > 0) {
+            load_unit(u, X, R);
+        }
         f32x4 o[MO];
         if (NSEG) {
             if (A.amax) {
@@ -351,145 +358,6 @@ __global__ __launch_bounds__(512) void k_mlp(MlpArgs A) {
             for (int mo = 0; mo < MO; mo++) o[mo] = P::load4(sa + qc * H + P::stored(mo, g));
         }
         if (CLS) classify<P, H>(sC1, sCB, b_out, o, SCc, A.amax_cls, lane, ok, q, A.logit);
-    };
-    // memory-bound precisions prefetch the next tile's inputs during the MFMAs
-    constexpr bool PREFETCH = sizeof(S) < 4 && NSEG > 0;
-    typename P::frag_t Xn[PREFETCH ? NX : 1];
-    raw_t Rn[RAW ? KB : 1];
-    if constexpr (plane_blocked<P, H, MODE>()) {
-        // Work items (event, plane p): the out-edges of the plane's hits (one
-        // contiguous range) with the states of the hits of planes p .. p+2,
-        // which are all their end points, staged in LDS once per item.
-        S *sh = (S *)(lds_raw + mlp_lds_base<P, H, MODE, CLS>());
-        const int wib = threadIdx.x >> 6, nwb = blockDim.x >> 6;
-        const int n_items = A.n_events * VELO_N_PLANES;
-        for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
-            const int b = it / VELO_N_PLANES, p = it - b * VELO_N_PLANES;
-            const int64_t s = A.ev_off[b];
-            const int *po = A.plane_off + (int64_t)b * kPlaneSlots;
-            const int64_t e0 = A.rows[s + po[p]];
-            const int64_t e1 = min((int64_t)A.rows[s + po[p + 1]], N);
-            if (e0 >= e1) continue;                      // uniform over the block
-            const int64_t h0 = s + po[p], h1 = s + po[min(p + 3, VELO_N_PLANES)];
-            const bool cached = h1 - h0 <= kHitCache;
-            __syncthreads();                             // the previous item is done with sh
-            if (cached) {
-                const int nchunk = (int)(h1 - h0) * H * (int)sizeof(S) / 16;
-                const f32x4 *src = (const f32x4 *)(hg + h0 * H);
-                for (int i = threadIdx.x; i < nchunk; i += blockDim.x) ((f32x4 *)sh)[i] = src[i];
-            }
-            __syncthreads();
-            // end points index rows of hb relative to hoff (both lie in [h0, h1)
-            // for a validated graph: source on plane p, destination on p+1 or p+2)
-            const S *hb = cached ? sh : hg;
-            const int64_t hoff = cached ? h0 : 0;
-            const int64_t units = (e1 - e0 + 15) >> 4;
-            // in flight: the next tile's edge-row part and end-point indices;
-            // the hit states come from LDS when the tile is computed
-            typename P::frag_t Xe[MODE == EDGE ? KB : 1];
-            raw_t Re[RAW ? KB : 1];
-            int sn = 0, dn = 0;
-            auto load_edges = [&](int64_t q0) {
-                const int64_t q = q0 + n;
-                const int64_t qc = q < e1 ? q : e1 - 1;
-                sn = A.src_g[qc];
-                dn = A.dst_g[qc];
-                if constexpr (MODE == EDGE) {
-#pragma unroll
-                    for (int kb = 0; kb < KB; kb++) {
-                        if constexpr (RAW) {
-                            Re[kb] = BF16::load((const BF16::state_t *)sa + qc * H, kb, g);
-                            Xe[kb] = P::pack(Re[kb], ix);
-                        } else {
-                            Xe[kb] = P::load(sa + qc * H, kb, g, ix);
-                        }
-                    }
-                }
-            };
-            int64_t u = wib;
-            if (u < units) load_edges(e0 + 16 * u);
-            for (; u < units; u += nwb) {
-                typename P::frag_t X[NX];
-                raw_t R[RAW ? KB : 1];
-                const int64_t sv = sn - hoff, dv = dn - hoff;
-                constexpr int SEG = MODE == EDGE ? 1 : 0;
-                if constexpr (MODE == EDGE) {
-#pragma unroll
-                    for (int k = 0; k < KB; k++) X[k] = Xe[k];
-                    if constexpr (RAW) {
-#pragma unroll
-                        for (int k = 0; k < KB; k++) R[k] = Re[k];
-                    }
-                }
-                if (u + nwb < units) load_edges(e0 + 16 * (u + nwb));
-#pragma unroll
-                for (int kb = 0; kb < KB; kb++) {
-                    X[SEG * KB + kb] = P::load(hb + sv * H, kb, g, ix);
-                    X[(SEG + 1) * KB + kb] = P::load(hb + dv * H, kb, g, ix);
-                }
-                compute_tile(e0 + 16 * u, e1, X, R);
-            }
-        }
-    } else {
-        const int64_t units = (N + 15) >> 4;
-        const WaveRange wr = wave_range(units, A.xcd != 0);
-        int64_t u = wr.first;
-        if (PREFETCH && u < wr.end) load_tile(16 * u, N, hg, Xn, Rn);
-        for (; u < wr.end; u += wr.step) {
-            const int64_t q = u * 16 + n;
-            const bool ok = q < N;
-            const int64_t qc = ok ? q : N - 1;
-            typename P::frag_t X[NX];
-            raw_t R[RAW ? KB : 1];
-            if (PREFETCH) {
-#pragma unroll
-                for (int k = 0; k < NX; k++) X[k] = Xn[k];
-                if constexpr (RAW) {
-#pragma unroll
-                    for (int k = 0; k < KB; k++) R[k] = Rn[k];
-                }
-                if (u + wr.step < wr.end) load_tile(16 * (u + wr.step), N, hg, Xn, Rn);
-            } else if (NSEG > 0) {
-                load_tile(16 * u, N, hg, X, R);
-            }
-            f32x4 o[MO];
-            if (NSEG) {
-                if (A.amax) {
-                    float mx = 0.f;
-#pragma unroll
-                    for (int k = 0; k < NX; k++) mx = fmaxf(mx, P::absmax(X[k]));
-                    record_amax(mx, A.amax);
-                }
-                f32x4 hid[MO];
-                load_bias<MO>(sB, hid, g);
-                gemm<P, MO, NSEG * KB>(sW1, X, hid, lane);
-                if (P::kScaled) rescale<MO>(hid, SC.d1);
-                relu<MO>(hid);
-                if (A.amax) record_amax(absmax4<MO>(hid), A.amax + 1);
-                typename P::frag_t xh[KB];
-                P::template chain<MO>(hid, xh, SC.ix2);
-                load_bias<MO>(sB + H, o, g);
-                gemm<P, MO, KB>(sW2, xh, o, lane);
-                if (P::kScaled) rescale<MO>(o, SC.d2);
-#pragma unroll
-                for (int mo = 0; mo < MO; mo++) {
-                    if constexpr (MODE != EDGE_ENC) {   // residual (Sec. 5.2), from the unquantised state
-                        if constexpr (RAW) {
-#pragma unroll
-                            for (int i = 0; i < 4; i++) o[mo][i] += BF16::seg0(R, mo, i);
-                        } else if constexpr (!P::kScaled) {
-#pragma unroll
-                            for (int i = 0; i < 4; i++) o[mo][i] += P::seg0(X, mo, i);
-                        }
-                    }
-                }
-                if (ok && !(CLS && MODE == EDGE)) P::template store_all<MO>((S *)A.out + q * H, g, o);
-            } else {
-#pragma unroll
-                for (int mo = 0; mo < MO; mo++) o[mo] = P::load4(sa + qc * H + P::stored(mo, g));
-            }
-            if (CLS) classify<P, H>(sC1, sCB, b_out, o, SCc, A.amax_cls, lane, ok, q, A.logit);
-        }
     }
 }
 
@@ -591,7 +459,6 @@ void gnn_ph(velo_ctx *c, const velo_hits *hits, float *logit, const float *Pw, b
     a.o_c1 = L.cls[0].w; a.o_c2 = L.cls[1].w;
     a.a = hk(0); a.out = ek(0); a.o_w1 = L.eenc[0].w; a.o_w2 = L.eenc[1].w;
     a.sc = sc(s_eenc); a.amax = am(s_eenc); a.sc_cls = sc(s_cls); a.amax_cls = am(s_cls);
-    a.ev_off = hits->event_offsets; a.plane_off = w.plane_off; a.rows = w.row_ptr; a.n_events = hits->n_events;
     {
         StageTimer t(c, VELO_STAGE_EDGE_ENC, s);
         run_mlp<P, H, EDGE_ENC, false>(c, VELO_STAGE_EDGE_ENC, a, s);
