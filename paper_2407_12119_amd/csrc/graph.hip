@@ -371,118 +371,101 @@ __global__ void k_row_ptr(int64_t n_hits, const int *__restrict__ hit_event, con
 }
 
 // ------------------------------------------------------------------------
-// incoming lists of a rough graph built by k_knn, one workgroup per (event,
-// destination plane q): the in-edges of hits on plane q all leave from the
-// CSR rows of planes q-2 and q-1, one contiguous range of edges.  The block
-// counts them per destination with LDS atomics (pass 1, then a global scan of
-// the counts gives in_ptr), then places them through LDS cursors, puts every
-// list in edge-id order inside LDS and writes the plane's lists out in one
-// coalesced sweep (pass 2).  Planes whose window does not fit the LDS budget
-// use the same steps on global memory.
+// incoming lists, one workgroup per (event, destination plane q).  The
+// in-edges of hits on plane q all leave from the CSR rows of planes q-2 and
+// q-1, one contiguous edge window [E0, E1); an edge in it points below the
+// plane (q-2 -> q-1), into it, or above it (q-1 -> q+1).  Hence the first
+// incoming slot of the plane is E0 plus the edges of the window that point
+// below it, and in_ptr needs no global scan.  Each wavefront takes one
+// contiguous quarter of the window and counts its edges per destination in
+// LDS; a block scan over destinations (and over the quarters of each
+// destination) turns the counts into per-quarter cursors.  Every wavefront
+// then walks its quarter in edge order, 64 edges at a time: lanes with the
+// same destination find each other with one ballot per bit of the
+// destination offset, take consecutive slots in lane order, and the lowest of
+// them advances the cursor.  So every list comes out in edge-id order (a
+// stable counting sort) with no atomics on global memory and no sorting.
+// Planes with more than kListMaxDst hits are handled in slices of that size.
 // ------------------------------------------------------------------------
-constexpr int kPlaneBlock = 256;
-constexpr int kPlaneMaxDst = 2048;     // destinations of one plane held in LDS
-constexpr int kPlaneMaxEdges = 8192;   // in-edges of one plane held in LDS
+constexpr int kListBlock = 256;
+constexpr int kListWaves = kListBlock / 64;
+constexpr int kListMaxDst = 2048;    // destinations of one slice held in LDS
 
-__device__ inline void plane_window(int b, int q, const int *__restrict__ off, const int *__restrict__ plane_off,
-                                    const int *__restrict__ row_ptr, int &s, int &d0, int &D, int &E0, int &E1) {
-    s = off[b];
-    const int *po = plane_off + (int64_t)b * kPlaneSlots;
-    d0 = po[q];
-    D = po[q + 1] - d0;
-    const int u0 = po[max(q - 2, 0)], u1 = po[q];
-    E0 = row_ptr[s + u0];
-    E1 = row_ptr[s + u1];
-}
-
-// order list[a, a+L) ascending: one wavefront, values distinct
-__device__ inline void wave_sort(int *list, int L, int lane) {
-    if (L <= 1) return;
-    if (L <= 64) {
-        const int v = lane < L ? list[lane] : 0x7fffffff;
-        int rank = 0;
-        for (int j = 0; j < L; j++) rank += __shfl(v, j) < v;
-        if (lane < L) list[rank] = v;
-    } else if (lane == 0) {
-        for (int u = 1; u < L; u++) {
-            const int v = list[u];
-            int w = u - 1;
-            while (w >= 0 && list[w] > v) {
-                list[w + 1] = list[w];
-                w--;
-            }
-            list[w + 1] = v;
-        }
-    }
-}
-
-__global__ __launch_bounds__(kPlaneBlock) void k_in_count(int B, const int *__restrict__ off,
-                                                          const int *__restrict__ plane_off,
-                                                          const int *__restrict__ row_ptr,
-                                                          const int *__restrict__ dst_g, int *__restrict__ deg,
-                                                          int *__restrict__ cur_g, const unsigned *__restrict__ flags) {
-    __shared__ int cnt[kPlaneMaxDst];
-    if (*flags) return;
-    const int b = blockIdx.x / VELO_N_PLANES, q = blockIdx.x % VELO_N_PLANES, t = threadIdx.x;
-    int s, d0, D, E0, E1;
-    plane_window(b, q, off, plane_off, row_ptr, s, d0, D, E0, E1);
-    if (D <= 0) return;
-    const int lo = s + d0, hi = s + d0 + D;    // batch-global destinations of this plane
-    if (D <= kPlaneMaxDst) {
-        for (int i = t; i < D; i += kPlaneBlock) cnt[i] = 0;
-        __syncthreads();
-        for (int e = E0 + t; e < E1; e += kPlaneBlock) {
-            const int d = dst_g[e];
-            if (d >= lo && d < hi) atomicAdd(&cnt[d - lo], 1);
-        }
-        __syncthreads();
-        for (int i = t; i < D; i += kPlaneBlock) deg[lo + i] = cnt[i];
-    } else {
-        for (int i = t; i < D; i += kPlaneBlock) deg[lo + i] = 0;
-        __syncthreads();
-        for (int e = E0 + t; e < E1; e += kPlaneBlock) {
-            const int d = dst_g[e];
-            if (d >= lo && d < hi) atomicAdd(&deg[d], 1);
-        }
-    }
-    for (int i = t; i < D; i += kPlaneBlock) cur_g[lo + i] = 0;
-}
-
-__global__ __launch_bounds__(kPlaneBlock) void k_in_fill(int B, const int *__restrict__ off,
+__global__ __launch_bounds__(kListBlock) void k_in_lists(int64_t n_hits, const int *__restrict__ off,
                                                          const int *__restrict__ plane_off,
                                                          const int *__restrict__ row_ptr,
-                                                         const int *__restrict__ dst_g,
-                                                         const int *__restrict__ in_ptr, int *__restrict__ in_list,
-                                                         int *__restrict__ cur_g, const unsigned *__restrict__ flags) {
-    __shared__ int cur[kPlaneMaxDst];
-    __shared__ int buf[kPlaneMaxEdges];
+                                                         const int *__restrict__ dst_g, int *__restrict__ in_ptr,
+                                                         int *__restrict__ in_list, const unsigned *__restrict__ flags) {
+    __shared__ int cnt[kListWaves][kListMaxDst];
+    __shared__ int below_w[kListWaves];
+    __shared__ int scan_sh[kListBlock];
     if (*flags) return;
-    const int b = blockIdx.x / VELO_N_PLANES, q = blockIdx.x % VELO_N_PLANES, t = threadIdx.x;
-    const int lane = t & 63, wave = t >> 6, nw = kPlaneBlock / 64;
-    int s, d0, D, E0, E1;
-    plane_window(b, q, off, plane_off, row_ptr, s, d0, D, E0, E1);
-    if (D <= 0) return;
-    const int lo = s + d0, hi = s + d0 + D;
-    const int base = in_ptr[lo], tot = in_ptr[hi] - base;
-    if (D <= kPlaneMaxDst && tot <= kPlaneMaxEdges) {
-        for (int i = t; i < D; i += kPlaneBlock) cur[i] = 0;
+    const int b = blockIdx.x / VELO_N_PLANES, q = blockIdx.x % VELO_N_PLANES;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int s = off[b];
+    const int *po = plane_off + (int64_t)b * kPlaneSlots;
+    const int d0 = po[q], D = po[q + 1] - d0;
+    if (D <= 0) return;                                   // uniform over the block
+    const int E0 = row_ptr[s + po[max(q - 2, 0)]], E1 = row_ptr[s + d0];
+    const int quarter = (E1 - E0 + kListWaves - 1) / kListWaves;
+    const int w0 = E0 + min(w * quarter, E1 - E0), w1 = E0 + min((w + 1) * quarter, E1 - E0);
+    for (int c0 = 0; c0 < D; c0 += kListMaxDst) {
+        const int Dc = min(D - c0, kListMaxDst);
+        const int lo = s + d0 + c0, hi = lo + Dc;     // batch-global destinations of this slice
+        __syncthreads();                              // the previous slice is done with cnt
+        for (int i = t; i < Dc; i += kListBlock)
+#pragma unroll
+            for (int v = 0; v < kListWaves; v++) cnt[v][i] = 0;
         __syncthreads();
-        for (int e = E0 + t; e < E1; e += kPlaneBlock) {
+        int below = 0;
+        for (int e = w0 + lane; e < w1; e += 64) {
             const int d = dst_g[e];
-            if (d >= lo && d < hi) buf[in_ptr[d] - base + atomicAdd(&cur[d - lo], 1)] = e;
+            if (d < lo) below++;
+            else if (d < hi) atomicAdd(&cnt[w][d - lo], 1);
         }
+        for (int o = 32; o > 0; o >>= 1) below += __shfl_xor(below, o);
+        if (lane == 0) below_w[w] = below;
         __syncthreads();
-        for (int i = wave; i < D; i += nw) wave_sort(buf + (in_ptr[lo + i] - base), cur[i], lane);
-        __syncthreads();
-        for (int i = t; i < tot; i += kPlaneBlock) in_list[base + i] = buf[i];
-    } else {
-        for (int e = E0 + t; e < E1; e += kPlaneBlock) {
-            const int d = dst_g[e];
-            if (d >= lo && d < hi) in_list[in_ptr[d] + atomicAdd(&cur_g[d], 1)] = e;
+        int base = E0;
+#pragma unroll
+        for (int v = 0; v < kListWaves; v++) base += below_w[v];
+        // thread t owns destinations [i0, i1) of the slice
+        const int per = (Dc + kListBlock - 1) / kListBlock;
+        const int i0 = min(t * per, Dc), i1 = min(i0 + per, Dc);
+        int run = 0;
+        for (int i = i0; i < i1; i++)
+#pragma unroll
+            for (int v = 0; v < kListWaves; v++) run += cnt[v][i];
+        int total;
+        int p = base + block_exclusive_scan(run, scan_sh, &total);
+        for (int i = i0; i < i1; i++) {
+            in_ptr[lo + i] = p;
+#pragma unroll
+            for (int v = 0; v < kListWaves; v++) {
+                const int c = cnt[v][i];
+                cnt[v][i] = p;                        // quarter v's cursor for this destination
+                p += c;
+            }
         }
-        __threadfence_block();
+        if ((int64_t)hi == n_hits && i0 < i1 && i1 == Dc) in_ptr[hi] = p;
         __syncthreads();
-        for (int i = wave; i < D; i += nw) wave_sort(in_list + in_ptr[lo + i], in_ptr[lo + i + 1] - in_ptr[lo + i], lane);
+        const int nbits = Dc > 1 ? 32 - __clz(Dc - 1) : 0;
+        for (int e0 = w0; e0 < w1; e0 += 64) {        // uniform over the wavefront
+            const int e = e0 + lane;
+            const int d = e < w1 ? dst_g[e] : -1;
+            const bool mine = d >= lo && d < hi;
+            const int key = mine ? d - lo : 0;
+            unsigned long long peers = ballot(mine);
+            for (int k = 0; k < nbits; k++) {
+                const bool bit = (key >> k) & 1;
+                const unsigned long long m = ballot(mine && bit);
+                peers &= bit ? m : ~m;
+            }
+            const int rank = lanes_below(peers);
+            const int cur = mine ? cnt[w][key] : 0;
+            if (mine) in_list[cur + rank] = e;
+            if (mine && rank == 0) cnt[w][key] = cur + __popcll(peers);
+        }
     }
 }
 
@@ -569,13 +552,8 @@ void launch_in_lists_plane(velo_ctx *c, const velo_hits *h, hipStream_t s) {
         launch_scan(c, w.deg, w.in_ptr, 0, s);
         return;
     }
-    const int blocks = h->n_events * VELO_N_PLANES;
-    int *cur_g = w.nbr;   // the neighbour staging buffer is free once the CSR is built
-    k_in_count<<<blocks, kPlaneBlock, 0, s>>>(h->n_events, h->event_offsets, w.plane_off, w.row_ptr, w.dst_g, w.deg,
-                                              cur_g, w.flags);
-    launch_scan(c, w.deg, w.in_ptr, N, s);
-    k_in_fill<<<blocks, kPlaneBlock, 0, s>>>(h->n_events, h->event_offsets, w.plane_off, w.row_ptr, w.dst_g, w.in_ptr,
-                                             w.in_list, cur_g, w.flags);
+    k_in_lists<<<h->n_events * VELO_N_PLANES, kListBlock, 0, s>>>(N, h->event_offsets, w.plane_off, w.row_ptr,
+                                                                  w.dst_g, w.in_ptr, w.in_list, w.flags);
 }
 
 }  // namespace velo

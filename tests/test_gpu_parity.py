@@ -212,6 +212,57 @@ def test_given_graph_must_be_grouped_by_source():
     ctx.gnn(hits, g)
 
 
+def _hub_event(rng, counts):
+    """Hits on a few planes with the given counts; an event plus a given graph
+    whose destinations are skewed onto 20 hub hits per plane."""
+    plane = np.repeat(np.arange(len(counts)), counts).astype(np.int32)
+    n = plane.size
+    r = np.sqrt(rng.uniform(5.1 ** 2, 42.0 ** 2, n))
+    phi = rng.uniform(0, 2 * np.pi, n)
+    ev = synth.Event((r * np.cos(phi)).astype(np.float32), (r * np.sin(phi)).astype(np.float32),
+                     synth.PLANE_Z[plane].astype(np.float32), plane, np.full(n, -1, np.int64),
+                     np.full(n, -1, np.int32))
+    po = np.concatenate([[0], np.cumsum(counts)])
+    src, dst = [], []
+    for i in range(n):
+        p = plane[i]
+        targets = []
+        for dp in (1, 2):
+            if p + dp < len(counts) and counts[p + dp] > 0:
+                lo, hi = po[p + dp], po[p + dp + 1]
+                hubs = np.arange(lo, min(lo + 20, hi))
+                k = int(rng.integers(1, 9))
+                pick = np.where(rng.random(k) < 0.5, rng.choice(hubs, k), rng.integers(lo, hi, k))
+                targets.extend(np.unique(pick).tolist())
+        for j in sorted(set(targets)):
+            src.append(i)
+            dst.append(j)
+    return ev, np.array(src, np.int32), np.array(dst, np.int32)
+
+
+def test_incoming_lists_of_large_planes_and_hubs():
+    """Incoming lists on a plane of more hits than one LDS slice holds (2,048)
+    and on hub hits with hundreds of incoming edges: the GNN on this given
+    graph must match the oracle's logits."""
+    wl = synth.WORKLOADS["batch256"]
+    rng = np.random.default_rng(2407)
+    ev, src, dst = _hub_event(rng, [0, 0, 0, 300, 300, 2600, 300, 200])
+    indeg = np.bincount(dst, minlength=ev.n)
+    assert indeg.max() > 128
+    batch = synth.to_batch([ev])
+    ctx, hits, blob = _setup(wl, batch, max_edges=max(len(src), 1))
+    out = ctx.alloc_outputs(hits, edge_capacity=len(src))
+    out["edge_src"][:len(src)] = torch.from_numpy(src).cuda()
+    out["edge_dst"][:len(dst)] = torch.from_numpy(dst).cuda()
+    out["edge_offsets"].copy_(torch.tensor([0, len(src)], dtype=torch.int32))
+    out["n_edges"].fill_(len(src))
+    ctx.gnn(hits, out)
+    gz = out["edge_logit"][:len(src)].cpu().numpy()
+    z = oracle.gnn_forward(ev.x, ev.y, ev.z, src, dst, blob, wl.hidden, wl.iters)
+    err = np.abs(gz - z) / np.maximum(np.abs(z), 1.0)
+    assert err.max() <= LOGIT_TOL, err.max()
+
+
 def test_zero_events_and_all_empty_events():
     wl = synth.WORKLOADS["batch256"]
     empty = synth.Event(*(np.zeros(0, dt) for dt in (np.float32, np.float32, np.float32, np.int32, np.int64, np.int32)))
