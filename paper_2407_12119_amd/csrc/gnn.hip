@@ -167,16 +167,54 @@ struct MlpArgs {
     const float *sc, *sc_cls;      // fp8 scales of this MLP and of the classifier (else null)
     float *amax, *amax_cls;        // calibration maxima (else null)
     int xcd;                       // XCD-blocked work mapping
+    // edge MLPs on 2-byte states: source rows (batch-global CSR over hits)
+    // and where the outgoing message sums of the new edge states go (m rows
+    // of 2H floats, first half; null: not wanted)
+    const int *rows;
+    int64_t n_rows;
+    float *mout;
     const unsigned *flags;
 };
+
+constexpr int kMlpBlock = 512;
 
 template <int MODE>
 constexpr int nseg() { return MODE == EDGE_ENC ? 2 : (MODE == CLS_ONLY ? 0 : 3); }
 
+// Edge MLPs on 2-byte states (bf16, fp8) that feed a message step walk the
+// edges source hit by source hit, 16 at a time, and also produce the
+// outgoing message sums of the states they write.
+template <class P, int MODE, bool CLS>
+constexpr bool src_aligned() {
+    return sizeof(typename P::state_t) == 2 && (MODE == EDGE || MODE == EDGE_ENC) && !CLS;
+}
+
 template <class P, int H, int MODE, bool CLS>
 constexpr size_t mlp_lds() {
     return (nseg<MODE>() ? frag_bytes<P>(H, nseg<MODE>() * H) + frag_bytes<P>(H, H) + sizeof(float) * 2 * H : 0) +
-           (CLS ? frag_bytes<P>(H, H) + sizeof(float) * 2 * H : 0);
+           (CLS ? frag_bytes<P>(H, H) + sizeof(float) * 2 * H : 0) +
+           (src_aligned<P, MODE, CLS>() ? sizeof(float) * H * (kMlpBlock / 64) : 0);
+}
+
+// Sum over the 16 lanes of each DPP row (every lane gets the row's sum):
+// partners n^8 (row rotate by 8), n^7 (half-row mirror), n^2 and n^1 (quad
+// permutations) generate the whole row.  Fixed order, so deterministic.
+__device__ inline int64_t uniform64(int64_t v) {
+    const uint64_t u = (uint64_t)v;
+    return (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(u >> 32)) << 32) |
+                     (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u));
+}
+
+template <int CTRL>
+__device__ inline float dpp_add(float v) {
+    return v + __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF,
+                                                                     true));
+}
+__device__ inline float row_sum16(float v) {
+    v = dpp_add<0x128>(v);     // row_ror:8
+    v = dpp_add<0x141>(v);     // row_half_mirror
+    v = dpp_add<0x4E>(v);      // quad_perm [2,3,0,1]
+    return dpp_add<0xB1>(v);   // quad_perm [1,0,3,2]
 }
 
 template <class P, int H>
@@ -289,6 +327,133 @@ __global__ __launch_bounds__(512) void k_mlp(MlpArgs A) {
             }
         }
     };
+    if constexpr (src_aligned<P, MODE, CLS>()) {
+        // Work units are source hits (edges are grouped by source), walked in
+        // chunks of 16 of their out-edges, two chunks in flight.  After a
+        // chunk's states are stored, their stored values are summed over the
+        // chunk's edges per channel (row_sum16) and added up over the hit's
+        // chunks in order: the outgoing message sum of the hit (Sec. 5.2),
+        // written by lane n = 0 of each row.  Partial sums of a hit with more
+        // than 16 edges wait in this wave's LDS slot.
+        float *carry = sB + 2 * H + (threadIdx.x >> 6) * H;
+        // the walk is uniform over the wavefront: keep it in scalar registers
+        const WaveRange wv = wave_range(A.n_rows, A.xcd != 0);
+        const WaveRange wr{uniform64(wv.first), uniform64(wv.step), uniform64(wv.end)};
+        struct Chunk {
+            int64_t i, a0, c0, a1;   // source hit, its first edge, this chunk's first edge, its end
+        };
+        auto from_hit = [&](int64_t i) -> Chunk {
+            for (; i < wr.end; i += wr.step) {
+                const int64_t a0 = uniform64(A.rows[i]), a1 = min(uniform64(A.rows[i + 1]), N);
+                if (a0 < a1) return Chunk{i, a0, a0, a1};
+            }
+            return Chunk{wr.end, 0, 0, 0};
+        };
+        auto next = [&](const Chunk &c) -> Chunk {
+            if (c.i >= wr.end) return c;
+            if (c.c0 + 16 < c.a1) return Chunk{c.i, c.a0, c.c0 + 16, c.a1};
+            return from_hit(c.i + wr.step);
+        };
+        auto load_chunk = [&](const Chunk &c, typename P::frag_t *X, raw_t *R) {
+            const int64_t q = c.c0 + n;
+            const int64_t qc = q < c.a1 ? q : c.a1 - 1;
+            const int64_t d = A.dst_g[qc];
+            if constexpr (MODE == EDGE) {
+                const S *hb = (const S *)A.b;
+#pragma unroll
+                for (int kb = 0; kb < KB; kb++) {
+                    if constexpr (RAW) {
+                        R[kb] = BF16::load((const BF16::state_t *)sa + qc * H, kb, g);
+                        X[kb] = P::pack(R[kb], ix);
+                    } else {
+                        X[kb] = P::load(sa + qc * H, kb, g, ix);
+                    }
+                    X[KB + kb] = P::load(hb + c.i * H, kb, g, ix);
+                    X[2 * KB + kb] = P::load(hb + d * H, kb, g, ix);
+                }
+            } else {
+#pragma unroll
+                for (int kb = 0; kb < KB; kb++) {
+                    X[kb] = P::load(sa + c.i * H, kb, g, ix);
+                    X[KB + kb] = P::load(sa + d * H, kb, g, ix);
+                }
+            }
+        };
+        typename P::frag_t Xn[NX], Xm[NX];
+        raw_t Rn[RAW ? KB : 1], Rm[RAW ? KB : 1];
+        Chunk cur = from_hit(wr.first);
+        Chunk nx1 = next(cur);
+        if (cur.i < wr.end) load_chunk(cur, Xn, Rn);
+        if (nx1.i < wr.end) load_chunk(nx1, Xm, Rm);
+        while (cur.i < wr.end) {
+            typename P::frag_t X[NX];
+            raw_t R[RAW ? KB : 1];
+#pragma unroll
+            for (int k = 0; k < NX; k++) {
+                X[k] = Xn[k];
+                Xn[k] = Xm[k];
+            }
+            if constexpr (RAW) {
+#pragma unroll
+                for (int k = 0; k < KB; k++) {
+                    R[k] = Rn[k];
+                    Rn[k] = Rm[k];
+                }
+            }
+            const Chunk nx2 = next(nx1);
+            if (nx2.i < wr.end) load_chunk(nx2, Xm, Rm);
+            const int64_t q = cur.c0 + n;
+            const bool ok = q < cur.a1;
+            if (A.amax) {
+                float mx = 0.f;
+#pragma unroll
+                for (int k = 0; k < NX; k++) mx = fmaxf(mx, P::absmax(X[k]));
+                record_amax(mx, A.amax);
+            }
+            f32x4 hid[MO], o[MO];
+            load_bias<MO>(sB, hid, g);
+            gemm<P, MO, NSEG * KB>(sW1, X, hid, lane);
+            if (P::kScaled) rescale<MO>(hid, SC.d1);
+            relu<MO>(hid);
+            if (A.amax) record_amax(absmax4<MO>(hid), A.amax + 1);
+            typename P::frag_t xh[KB];
+            P::template chain<MO>(hid, xh, SC.ix2);
+            load_bias<MO>(sB + H, o, g);
+            gemm<P, MO, KB>(sW2, xh, o, lane);
+            if (P::kScaled) rescale<MO>(o, SC.d2);
+            if constexpr (MODE == EDGE) {   // residual (Sec. 5.2), from the unquantised state
+#pragma unroll
+                for (int mo = 0; mo < MO; mo++)
+#pragma unroll
+                    for (int i = 0; i < 4; i++) {
+                        if constexpr (RAW) o[mo][i] += BF16::seg0(R, mo, i);
+                        else o[mo][i] += P::seg0(X, mo, i);
+                    }
+            }
+            if (ok) P::template store_all<MO>((S *)A.out + q * H, g, o);
+            if (A.mout) {
+                // the states as stored, summed over the chunk's edges
+#pragma unroll
+                for (int mo = 0; mo < MO; mo++)
+#pragma unroll
+                    for (int i = 0; i < 4; i++) o[mo][i] = row_sum16(ok ? (float)(S)o[mo][i] : 0.f);
+                if (n == 0) {
+#pragma unroll
+                    for (int mo = 0; mo < MO; mo++) {
+                        f32x4 *cm = (f32x4 *)(carry + P::stored(mo, g));
+                        if (cur.c0 != cur.a0) o[mo] = *cm + o[mo];
+                        if (cur.c0 + 16 >= cur.a1)
+                            *(f32x4 *)(A.mout + cur.i * 2 * H + P::stored(mo, g)) = o[mo];
+                        else
+                            *cm = o[mo];
+                    }
+                }
+            }
+            cur = nx1;
+            nx1 = nx2;
+        }
+        return;
+    }
     // memory-bound precisions prefetch the next unit's inputs during the MFMAs
     constexpr bool PREFETCH = sizeof(S) < 4 && NSEG > 0;
     // two units in flight: Xn holds unit u + step, Xm unit u + 2 step
@@ -370,7 +535,8 @@ __global__ __launch_bounds__(256) void k_messages(int64_t n_hits, const int *__r
                                                   const int *__restrict__ in_ptr,
                                                   const int *__restrict__ in_list,
                                                   const typename P::state_t *__restrict__ e,
-                                                  float *__restrict__ m, int xcd, const unsigned *__restrict__ flags) {
+                                                  float *__restrict__ m, int xcd, int in_only,
+                                                  const unsigned *__restrict__ flags) {
     if (*flags) return;
     constexpr int LPN = H / 4, NPW = 64 / LPN;
     const int lane = threadIdx.x & 63, sub = lane / LPN, c = 4 * (lane % LPN);
@@ -379,7 +545,7 @@ __global__ __launch_bounds__(256) void k_messages(int64_t n_hits, const int *__r
         const int64_t i = u * NPW + sub;
         if (i >= n_hits) continue;
         f32x4 so = zero4(), si = zero4();
-        const int a0 = out_ptr[i], a1 = out_ptr[i + 1];
+        const int a0 = out_ptr[i], a1 = in_only ? out_ptr[i] : out_ptr[i + 1];
         int a = a0;
         for (; a + 4 <= a1; a += 4) {
             const f32x4 v0 = P::load4(e + (int64_t)a * H + c);
@@ -400,12 +566,12 @@ __global__ __launch_bounds__(256) void k_messages(int64_t n_hits, const int *__r
             si += v0; si += v1; si += v2; si += v3;
         }
         for (; b < b1; b++) si += P::load4(e + (int64_t)in_list[b] * H + c);
-        *(f32x4 *)(m + i * 2 * H + c) = so;
+        // in_only: the edge network wrote the outgoing sums of hits with out-edges
+        if (!in_only || out_ptr[i] == out_ptr[i + 1]) *(f32x4 *)(m + i * 2 * H + c) = so;
         *(f32x4 *)(m + i * 2 * H + H + c) = si;
     }
 }
 
-constexpr int kMlpBlock = 512;
 
 // Blocks of `block` threads with `lds` bytes of LDS that fit on one compute
 // unit together (at least 1); also lifts the dynamic-LDS launch limit.
@@ -459,6 +625,10 @@ void gnn_ph(velo_ctx *c, const velo_hits *hits, float *logit, const float *Pw, b
     a.o_c1 = L.cls[0].w; a.o_c2 = L.cls[1].w;
     a.a = hk(0); a.out = ek(0); a.o_w1 = L.eenc[0].w; a.o_w2 = L.eenc[1].w;
     a.sc = sc(s_eenc); a.amax = am(s_eenc); a.sc_cls = sc(s_cls); a.amax_cls = am(s_cls);
+    // 2-byte states: the edge encoder and every edge network but the last
+    // also write the outgoing message sums of their output states
+    constexpr bool out_fused = src_aligned<P, EDGE, false>();
+    a.rows = w.row_ptr; a.n_rows = N; a.mout = mk(0);
     {
         StageTimer t(c, VELO_STAGE_EDGE_ENC, s);
         run_mlp<P, H, EDGE_ENC, false>(c, VELO_STAGE_EDGE_ENC, a, s);
@@ -467,7 +637,8 @@ void gnn_ph(velo_ctx *c, const velo_hits *hits, float *logit, const float *Pw, b
         if (N > 0) {
             StageTimer t(c, VELO_STAGE_MESSAGES, s);
             k_messages<P, H><<<persistent_grid(c, stage_per_cu(c, VELO_STAGE_MESSAGES, 16)), 256, 0, s>>>(
-                N, w.row_ptr, w.in_ptr, w.in_list, ek(k), mk(k), c->tune_xcd[VELO_STAGE_MESSAGES], w.flags);
+                N, w.row_ptr, w.in_ptr, w.in_list, ek(k), mk(k), c->tune_xcd[VELO_STAGE_MESSAGES], out_fused ? 1 : 0,
+                w.flags);
         }
         MlpArgs nd{};
         nd.n_dev = nullptr; nd.n_host = N; nd.a = hk(k); nd.b = mk(k); nd.out = hk(k + 1);
@@ -481,6 +652,7 @@ void gnn_ph(velo_ctx *c, const velo_hits *hits, float *logit, const float *Pw, b
         ed.a = ek(k); ed.b = hk(k + 1); ed.out = ek(k + 1); ed.o_w1 = L.edge[k][0].w; ed.o_w2 = L.edge[k][1].w;
         ed.sc = sc(slot_edge(k)); ed.amax = am(slot_edge(k));
         const bool last = k == iters - 1;
+        ed.mout = last ? nullptr : mk(k + 1);
         StageTimer t(c, last && fuse_cls ? VELO_STAGE_EDGE_CLS : VELO_STAGE_EDGE_NET, s);
         if (last && fuse_cls)
             run_mlp<P, H, EDGE, true>(c, VELO_STAGE_EDGE_CLS, ed, s);
