@@ -342,9 +342,13 @@ __global__ __launch_bounds__(512) void k_mlp(MlpArgs A) {
         struct Chunk {
             int64_t i, a0, c0, a1;   // source hit, its first edge, this chunk's first edge, its end
         };
+        // the row pointers do not change during the kernel: read them through
+        // the constant address space, so uniform reads become scalar loads
+        // (which do not count against the vector-memory wait counter)
+        const __attribute__((address_space(4))) int *rows4 = (const __attribute__((address_space(4))) int *)A.rows;
         auto from_hit = [&](int64_t i) -> Chunk {
             for (; i < wr.end; i += wr.step) {
-                const int64_t a0 = uniform64(A.rows[i]), a1 = min(uniform64(A.rows[i + 1]), N);
+                const int64_t a0 = rows4[i], a1 = min((int64_t)rows4[i + 1], N);
                 if (a0 < a1) return Chunk{i, a0, a0, a1};
             }
             return Chunk{wr.end, 0, 0, 0};
@@ -379,29 +383,7 @@ __global__ __launch_bounds__(512) void k_mlp(MlpArgs A) {
                 }
             }
         };
-        typename P::frag_t Xn[NX], Xm[NX];
-        raw_t Rn[RAW ? KB : 1], Rm[RAW ? KB : 1];
-        Chunk cur = from_hit(wr.first);
-        Chunk nx1 = next(cur);
-        if (cur.i < wr.end) load_chunk(cur, Xn, Rn);
-        if (nx1.i < wr.end) load_chunk(nx1, Xm, Rm);
-        while (cur.i < wr.end) {
-            typename P::frag_t X[NX];
-            raw_t R[RAW ? KB : 1];
-#pragma unroll
-            for (int k = 0; k < NX; k++) {
-                X[k] = Xn[k];
-                Xn[k] = Xm[k];
-            }
-            if constexpr (RAW) {
-#pragma unroll
-                for (int k = 0; k < KB; k++) {
-                    R[k] = Rn[k];
-                    Rn[k] = Rm[k];
-                }
-            }
-            const Chunk nx2 = next(nx1);
-            if (nx2.i < wr.end) load_chunk(nx2, Xm, Rm);
+        auto process = [&](const Chunk &cur, const typename P::frag_t *X, const raw_t *R) {
             const int64_t q = cur.c0 + n;
             const bool ok = q < cur.a1;
             if (A.amax) {
@@ -449,8 +431,22 @@ __global__ __launch_bounds__(512) void k_mlp(MlpArgs A) {
                     }
                 }
             }
-            cur = nx1;
-            nx1 = nx2;
+        };
+        // two input buffers in alternation (no register copies): the loads
+        // of the next chunk are in flight while this one is computed
+        typename P::frag_t XA[NX], XB[NX];
+        raw_t RA[RAW ? KB : 1], RB[RAW ? KB : 1];
+        Chunk c0 = from_hit(wr.first);
+        Chunk c1 = next(c0);
+        if (c0.i < wr.end) load_chunk(c0, XA, RA);
+        while (c0.i < wr.end) {
+            if (c1.i < wr.end) load_chunk(c1, XB, RB);
+            process(c0, XA, RA);
+            c0 = c1; c1 = next(c1);
+            if (c0.i >= wr.end) break;
+            if (c1.i < wr.end) load_chunk(c1, XA, RA);
+            process(c0, XB, RB);
+            c0 = c1; c1 = next(c1);
         }
         return;
     }
@@ -528,7 +524,13 @@ __global__ __launch_bounds__(512) void k_mlp(MlpArgs A) {
 
 // ------------------------------------------------------------------------
 // messages m_i = [sum_{i->j} e_ij, sum_{j->i} e_ji]  (Sec. 5.2, scatter_add)
-// H/4 lanes per hit, 4 channels per lane, float32 sums in edge-id order
+// H/4 lanes per hit, 4 channels per lane, float32 sums in edge-id order.
+// Edges are taken in batches of up to 16: the group's lanes first read the
+// batch's incoming edge ids (one each), the ids are passed round the group,
+// and all of the batch's rows are requested before the first is added, so a
+// hit waits for two memory round trips per batch rather than per edge.
+// in_only: the outgoing sums of hits with out-edges were written by the
+// edge network that produced e; only hits without out-edges get them here.
 // ------------------------------------------------------------------------
 template <class P, int H>
 __global__ __launch_bounds__(256) void k_messages(int64_t n_hits, const int *__restrict__ out_ptr,
@@ -538,40 +540,56 @@ __global__ __launch_bounds__(256) void k_messages(int64_t n_hits, const int *__r
                                                   float *__restrict__ m, int xcd, int in_only,
                                                   const unsigned *__restrict__ flags) {
     if (*flags) return;
-    constexpr int LPN = H / 4, NPW = 64 / LPN;
-    const int lane = threadIdx.x & 63, sub = lane / LPN, c = 4 * (lane % LPN);
+    // batches of 16 stored rows of 2-byte states, 8 of float32 ones (registers)
+    constexpr int LPN = H / 4, NPW = 64 / LPN, BMAX = sizeof(typename P::state_t) == 2 ? 16 : 8;
+    constexpr int BATCH = LPN < BMAX ? LPN : BMAX;
+    const int lane = threadIdx.x & 63, sub = lane / LPN, l = lane % LPN, c = 4 * l, gbase = sub * LPN;
     const WaveRange wr = wave_range((n_hits + NPW - 1) / NPW, xcd != 0);
     for (int64_t u = wr.first; u < wr.end; u += wr.step) {
-        const int64_t i = u * NPW + sub;
-        if (i >= n_hits) continue;
+        const int64_t i0 = u * NPW + sub;
+        const bool live = i0 < n_hits;
+        const int64_t i = live ? i0 : n_hits - 1;
         f32x4 so = zero4(), si = zero4();
-        const int a0 = out_ptr[i], a1 = in_only ? out_ptr[i] : out_ptr[i + 1];
-        int a = a0;
-        for (; a + 4 <= a1; a += 4) {
-            const f32x4 v0 = P::load4(e + (int64_t)a * H + c);
-            const f32x4 v1 = P::load4(e + (int64_t)(a + 1) * H + c);
-            const f32x4 v2 = P::load4(e + (int64_t)(a + 2) * H + c);
-            const f32x4 v3 = P::load4(e + (int64_t)(a + 3) * H + c);
-            so += v0; so += v1; so += v2; so += v3;
+        const int a0 = out_ptr[i], a1 = in_only ? a0 : out_ptr[i + 1];
+        // rows are kept as loaded (4 stored values) until they are added
+        using raw4 = typename std::conditional<sizeof(typename P::state_t) == 2, uint2, f32x4>::type;
+        auto widen = [](const raw4 &r) -> f32x4 {
+            if constexpr (sizeof(typename P::state_t) == 2)
+                return f32x4{__uint_as_float(r.x << 16), __uint_as_float(r.x & 0xffff0000u),
+                             __uint_as_float(r.y << 16), __uint_as_float(r.y & 0xffff0000u)};
+            else
+                return r;
+        };
+        for (int a = a0; a < a1; a += BATCH) {
+            const int cnt = min(BATCH, a1 - a);
+            raw4 v[BATCH];
+#pragma unroll
+            for (int j = 0; j < BATCH; j++)
+                if (j < cnt) v[j] = *(const raw4 *)(e + (int64_t)(a + j) * H + c);
+#pragma unroll
+            for (int j = 0; j < BATCH; j++)
+                if (j < cnt) so += widen(v[j]);
         }
-        for (; a < a1; a++) so += P::load4(e + (int64_t)a * H + c);
         const int b0 = in_ptr[i], b1 = in_ptr[i + 1];
-        int b = b0;
-        for (; b + 4 <= b1; b += 4) {
-            const int q0 = in_list[b], q1 = in_list[b + 1], q2 = in_list[b + 2], q3 = in_list[b + 3];
-            const f32x4 v0 = P::load4(e + (int64_t)q0 * H + c);
-            const f32x4 v1 = P::load4(e + (int64_t)q1 * H + c);
-            const f32x4 v2 = P::load4(e + (int64_t)q2 * H + c);
-            const f32x4 v3 = P::load4(e + (int64_t)q3 * H + c);
-            si += v0; si += v1; si += v2; si += v3;
+        for (int b = b0; b < b1; b += BATCH) {   // the group's lanes share the trip count
+            const int cnt = min(BATCH, b1 - b);
+            const int mine = l < cnt ? in_list[b + l] : 0;
+            raw4 v[BATCH];
+#pragma unroll
+            for (int j = 0; j < BATCH; j++) {
+                const int q = __shfl(mine, gbase + j);
+                if (j < cnt) v[j] = *(const raw4 *)(e + (int64_t)q * H + c);
+            }
+#pragma unroll
+            for (int j = 0; j < BATCH; j++)
+                if (j < cnt) si += widen(v[j]);
         }
-        for (; b < b1; b++) si += P::load4(e + (int64_t)in_list[b] * H + c);
-        // in_only: the edge network wrote the outgoing sums of hits with out-edges
-        if (!in_only || out_ptr[i] == out_ptr[i + 1]) *(f32x4 *)(m + i * 2 * H + c) = so;
-        *(f32x4 *)(m + i * 2 * H + H + c) = si;
+        if (live) {
+            if (!in_only || a0 == out_ptr[i + 1]) *(f32x4 *)(m + i * 2 * H + c) = so;
+            *(f32x4 *)(m + i * 2 * H + H + c) = si;
+        }
     }
 }
-
 
 // Blocks of `block` threads with `lds` bytes of LDS that fit on one compute
 // unit together (at least 1); also lifts the dynamic-LDS launch limit.
