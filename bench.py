@@ -39,12 +39,34 @@ def edge_net_work(H, prec, n_edges, n_hits):
 
     flops: two layers per edge, 3H -> H and H -> H, 2 flops per multiply-add.
     bytes: the edge state read and written once, its two hit indices, and
-    every hit state read once.
+    every hit state read once; with 2-byte states the launch also writes the
+    float32 outgoing message sum of every hit (H floats).
     """
     s = STATE_BYTES[prec]
     flops = 2 * (3 * H * H + H * H) * n_edges
     nbytes = (2 * H * s + 8) * n_edges + H * s * n_hits
+    if s == 2:
+        nbytes += 4 * H * n_hits
     return flops, nbytes
+
+
+def copy_probe_gbs(torch, mib=1024, reps=10):
+    """Device-to-device copy rate (bytes read + written per second, GB/s) of a
+    plain `copy_` of `mib` MiB: what a streaming kernel reaches on this GPU."""
+    n = mib * (1 << 20) // 4
+    x = torch.ones(n, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        y.copy_(x)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    del x, y
+    return round(2 * 4 * n / (ms * 1e-3) / 1e9, 1)
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "edge_net_traffic.json")
@@ -75,7 +97,7 @@ def measured_traffic(prec, workload):
     return e.get("bytes_per_launch")
 
 
-def roofline(stages, H, prec, n_edges, n_hits, workload):
+def roofline(stages, H, prec, n_edges, n_hits, workload, copy_gbs=None):
     ms, n = stages["edge_net"]
     if not n:
         return None
@@ -89,11 +111,15 @@ def roofline(stages, H, prec, n_edges, n_hits, workload):
                 "traffic": measured_traffic(prec, workload), "avg_launch_ms": round(avg_ms, 4), "flops_per_launch": flops,
                 "bytes_per_launch": nbytes, "arith_intensity": round(flops / nbytes, 1)}
     achieved = nbytes / (avg_ms * 1e-3) / 1e9
-    return {"kernel": f"edge network ({prec} MFMA)", "bound": "hbm", "achieved": round(achieved, 1),
-            "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(prec, workload),
-            "avg_launch_ms": round(avg_ms, 4), "flops_per_launch": flops, "bytes_per_launch": nbytes,
-            "arith_intensity": round(flops / nbytes, 1),
-            "mfma_frac": round(flops / (avg_ms * 1e-3) / 1e12 / PEAK_TFLOPS[prec], 4)}
+    res = {"kernel": f"edge network ({prec} MFMA)", "bound": "hbm", "achieved": round(achieved, 1),
+           "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+           "traffic": measured_traffic(prec, workload),
+           "avg_launch_ms": round(avg_ms, 4), "flops_per_launch": flops, "bytes_per_launch": nbytes,
+           "arith_intensity": round(flops / nbytes, 1),
+           "mfma_frac": round(flops / (avg_ms * 1e-3) / 1e12 / PEAK_TFLOPS[prec], 4)}
+    if copy_gbs:
+        res["copy_frac"] = round(achieved / copy_gbs, 4)
+    return res
 
 
 def run_training(velo, synth, torch, steps, warmup):
@@ -267,7 +293,7 @@ def transfer_times(torch, batch, out, n_edges, reps=5):
 
 
 def run_batched(velo, synth, torch, wl, batch, hits, blob, prec, steps, warmup, graph=False, latency=False,
-                autotune=True):
+                autotune=True, copy_gbs=None):
     import numpy as np
     r2 = float(np.float32(wl.radius * wl.radius))
     mx = batch.max_event_hits()
@@ -305,7 +331,7 @@ def run_batched(velo, synth, torch, wl, batch, hits, blob, prec, steps, warmup, 
     res = {"value": round(batch.n_events * steps / dt, 2), "ms_per_step": round(1e3 * dt / steps, 4),
            "hits_per_s": round(batch.n_hits * steps / dt, 1), "edges": n_edges,
            "stage_ms_per_step": {k: round(v[0] / steps, 4) for k, v in stages.items()},
-           "roofline": roofline(stages, wl.hidden, prec, n_edges, batch.n_hits, wl.name)}
+           "roofline": roofline(stages, wl.hidden, prec, n_edges, batch.n_hits, wl.name, copy_gbs)}
     # events/s of the path cut after each stage (cumulative, in path order)
     order = ["prepare", "embed", "knn", "compact", "lists", "node_enc", "edge_enc", "messages", "node_net",
              "edge_net", "edge_cls", "components"]
@@ -404,13 +430,15 @@ def main():
     blob = synth.centred_params(wl)
     torch.cuda.set_device(0)
     hits = velo.DeviceHits.from_batch(batch)
+    copy_gbs = copy_probe_gbs(torch)
+    log(f"device copy probe: {copy_gbs} GB/s (read + write)")
 
     ctx, main_res = run_batched(velo, synth, torch, wl, batch, hits, blob, args.precision, args.steps,
-                                args.warmup, args.graph, args.latency, not args.no_autotune)
+                                args.warmup, args.graph, args.latency, not args.no_autotune, copy_gbs)
     variants = {}
     for prec in [p for p in args.variants.split(",") if p and p != args.precision]:
         vctx, vres = run_batched(velo, synth, torch, wl, batch, hits, blob, prec, args.steps, args.warmup,
-                                 args.graph, args.latency, not args.no_autotune)
+                                 args.graph, args.latency, not args.no_autotune, copy_gbs)
         vctx.close()
         variants[prec] = vres
     training = None
@@ -474,7 +502,7 @@ def main():
                       "precision": args.precision},
            "hits_per_s": main_res["hits_per_s"],
            "stage_ms_per_step": main_res["stage_ms_per_step"],
-           "roofline": main_res["roofline"], "cpu_baseline": cpu, "per_event_path": per_event,
+           "roofline": main_res["roofline"], "hbm_copy_GBps": copy_gbs, "cpu_baseline": cpu, "per_event_path": per_event,
            "variants": variants, "training": training, "quality": quality}
     for k in ("graph", "eager"):
         if k in main_res:

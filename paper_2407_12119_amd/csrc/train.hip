@@ -454,16 +454,43 @@ __global__ __launch_bounds__(256) void k_gather_add(int64_t n_hits, const int *_
                                                     const float *__restrict__ xd, float *__restrict__ dh,
                                                     bool accumulate, const unsigned *__restrict__ flags) {
     if (*flags) return;
-    constexpr int LPN = H / 4, NPW = 64 / LPN;
-    const int lane = threadIdx.x & 63, sub = lane / LPN, c = 4 * (lane % LPN);
+    // rows are added in edge order; up to BATCH of them are requested before
+    // the first is added (incoming ids are read one per lane and passed round
+    // the hit's lane group)
+    constexpr int LPN = H / 4, NPW = 64 / LPN, BATCH = LPN < 8 ? LPN : 8;
+    const int lane = threadIdx.x & 63, sub = lane / LPN, l = lane % LPN, c = 4 * l, gbase = sub * LPN;
     const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
     for (int64_t base = (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6) * NPW; base < n_hits; base += nw * NPW) {
-        const int64_t i = base + sub;
-        if (i >= n_hits) continue;
+        const int64_t i0 = base + sub;
+        const bool live = i0 < n_hits;
+        const int64_t i = live ? i0 : n_hits - 1;
         f32x4 sum = accumulate ? *(const f32x4 *)(dh + i * H + c) : zero4();
-        for (int a = out_ptr[i]; a < out_ptr[i + 1]; a++) sum += *(const f32x4 *)(xs + (int64_t)a * H + c);
-        for (int b = in_ptr[i]; b < in_ptr[i + 1]; b++) sum += *(const f32x4 *)(xd + (int64_t)in_list[b] * H + c);
-        *(f32x4 *)(dh + i * H + c) = sum;
+        const int a1 = out_ptr[i + 1];
+        for (int a = out_ptr[i]; a < a1; a += BATCH) {
+            const int cnt = min(BATCH, a1 - a);
+            f32x4 v[BATCH];
+#pragma unroll
+            for (int j = 0; j < BATCH; j++)
+                if (j < cnt) v[j] = *(const f32x4 *)(xs + (int64_t)(a + j) * H + c);
+#pragma unroll
+            for (int j = 0; j < BATCH; j++)
+                if (j < cnt) sum += v[j];
+        }
+        const int b1 = in_ptr[i + 1];
+        for (int b = in_ptr[i]; b < b1; b += BATCH) {   // the group's lanes share the trip count
+            const int cnt = min(BATCH, b1 - b);
+            const int mine = l < cnt ? in_list[b + l] : 0;
+            f32x4 v[BATCH];
+#pragma unroll
+            for (int j = 0; j < BATCH; j++) {
+                const int q = __shfl(mine, gbase + j);
+                if (j < cnt) v[j] = *(const f32x4 *)(xd + (int64_t)q * H + c);
+            }
+#pragma unroll
+            for (int j = 0; j < BATCH; j++)
+                if (j < cnt) sum += v[j];
+        }
+        if (live) *(f32x4 *)(dh + i * H + c) = sum;
     }
 }
 
