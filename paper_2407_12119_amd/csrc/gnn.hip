@@ -181,13 +181,15 @@ constexpr int kMlpBlock = 512;
 template <int MODE>
 constexpr int nseg() { return MODE == EDGE_ENC ? 2 : (MODE == CLS_ONLY ? 0 : 3); }
 
-// Edge MLPs that feed a message step (the edge encoder and every edge
-// network but the one fused with the classifier) walk the edges source hit
-// by source hit, 16 at a time, and also produce the outgoing message sums of
-// the states they write.
+// Edge MLPs on 2-byte states (bf16, fp8) that feed a message step (the edge
+// encoder and every edge network but the one fused with the classifier) walk
+// the edges source hit by source hit, 16 at a time, and also produce the
+// outgoing message sums of the states they write.  The float32 ones are
+// MFMA-bound: there the padding of each source's last chunk would cost more
+// than the message kernel saves, so they keep 16-edge tiles.
 template <class P, int MODE, bool CLS>
 constexpr bool src_aligned() {
-    return (MODE == EDGE || MODE == EDGE_ENC) && !CLS;
+    return sizeof(typename P::state_t) == 2 && (MODE == EDGE || MODE == EDGE_ENC) && !CLS;
 }
 
 template <class P, int H, int MODE, bool CLS>
@@ -433,15 +435,6 @@ __global__ __launch_bounds__(512) void k_mlp(MlpArgs A) {
                 }
             }
         };
-        if constexpr (sizeof(S) == 4) {   // MFMA-bound: no prefetch, fewer registers
-            typename P::frag_t X[NX];
-            raw_t R[RAW ? KB : 1];
-            for (Chunk c = from_hit(wr.first); c.i < wr.end; c = next(c)) {
-                load_chunk(c, X, R);
-                process(c, X, R);
-            }
-            return;
-        }
         // two input buffers in alternation (no register copies): the loads
         // of the next chunk are in flight while this one is computed
         typename P::frag_t XA[NX], XB[NX];
@@ -534,16 +527,16 @@ __global__ __launch_bounds__(512) void k_mlp(MlpArgs A) {
 
 // ------------------------------------------------------------------------
 // messages m_i = [sum_{i->j} e_ij, sum_{j->i} e_ji]  (Sec. 5.2, scatter_add)
-// The outgoing sums of hits with out-edges are written by the edge MLP that
-// produced e (it walks the edges source by source); this kernel writes the
-// incoming sums, and zero outgoing sums for hits without out-edges.
 // H/4 lanes per hit, 4 channels per lane, float32 sums in edge-id order.
+// IN_ONLY: the outgoing sums of hits with out-edges were written by the
+// edge MLP that produced e (it walks the edges source by source); only hits
+// without out-edges get theirs (zero) here.
 // Edges are taken in batches of up to 16: the group's lanes first read the
 // batch's incoming edge ids (one each), the ids are passed round the group,
 // and all of the batch's rows are requested before the first is added, so a
 // hit waits for two memory round trips per batch rather than per edge.
 // ------------------------------------------------------------------------
-template <class P, int H>
+template <class P, int H, bool IN_ONLY>
 __global__ __launch_bounds__(256) void k_messages(int64_t n_hits, const int *__restrict__ out_ptr,
                                                   const int *__restrict__ in_ptr,
                                                   const int *__restrict__ in_list,
@@ -554,21 +547,32 @@ __global__ __launch_bounds__(256) void k_messages(int64_t n_hits, const int *__r
     constexpr int LPN = H / 4, NPW = 64 / LPN, BMAX = sizeof(typename P::state_t) == 2 ? 16 : 8;
     constexpr int BATCH = LPN < BMAX ? LPN : BMAX;
     const int lane = threadIdx.x & 63, sub = lane / LPN, l = lane % LPN, c = 4 * l, gbase = sub * LPN;
-    // rows are kept as loaded (4 stored values) until they are added
-    using raw4 = typename std::conditional<sizeof(typename P::state_t) == 2, uint2, f32x4>::type;
-    auto widen = [](const raw4 &r) -> f32x4 {
-        if constexpr (sizeof(typename P::state_t) == 2)
-            return f32x4{__uint_as_float(r.x << 16), __uint_as_float(r.x & 0xffff0000u),
-                         __uint_as_float(r.y << 16), __uint_as_float(r.y & 0xffff0000u)};
-        else
-            return r;
-    };
     const WaveRange wr = wave_range((n_hits + NPW - 1) / NPW, xcd != 0);
     for (int64_t u = wr.first; u < wr.end; u += wr.step) {
         const int64_t i0 = u * NPW + sub;
         const bool live = i0 < n_hits;
         const int64_t i = live ? i0 : n_hits - 1;
-        f32x4 si = zero4();
+        f32x4 so = zero4(), si = zero4();
+        const int a0 = out_ptr[i], a1 = IN_ONLY ? a0 : out_ptr[i + 1];
+        // rows are kept as loaded (4 stored values) until they are added
+        using raw4 = typename std::conditional<sizeof(typename P::state_t) == 2, uint2, f32x4>::type;
+        auto widen = [](const raw4 &r) -> f32x4 {
+            if constexpr (sizeof(typename P::state_t) == 2)
+                return f32x4{__uint_as_float(r.x << 16), __uint_as_float(r.x & 0xffff0000u),
+                             __uint_as_float(r.y << 16), __uint_as_float(r.y & 0xffff0000u)};
+            else
+                return r;
+        };
+        for (int a = a0; !IN_ONLY && a < a1; a += BATCH) {
+            const int cnt = min(BATCH, a1 - a);
+            raw4 v[BATCH];
+#pragma unroll
+            for (int j = 0; j < BATCH; j++)
+                if (j < cnt) v[j] = *(const raw4 *)(e + (int64_t)(a + j) * H + c);
+#pragma unroll
+            for (int j = 0; j < BATCH; j++)
+                if (j < cnt) so += widen(v[j]);
+        }
         const int b0 = in_ptr[i], b1 = in_ptr[i + 1];
         for (int b = b0; b < b1; b += BATCH) {   // the group's lanes share the trip count
             const int cnt = min(BATCH, b1 - b);
@@ -584,7 +588,7 @@ __global__ __launch_bounds__(256) void k_messages(int64_t n_hits, const int *__r
                 if (j < cnt) si += widen(v[j]);
         }
         if (live) {
-            if (out_ptr[i] == out_ptr[i + 1]) *(f32x4 *)(m + i * 2 * H + c) = zero4();
+            if (!IN_ONLY || a0 == out_ptr[i + 1]) *(f32x4 *)(m + i * 2 * H + c) = so;
             *(f32x4 *)(m + i * 2 * H + H + c) = si;
         }
     }
@@ -642,9 +646,10 @@ void gnn_ph(velo_ctx *c, const velo_hits *hits, float *logit, const float *Pw, b
     a.o_c1 = L.cls[0].w; a.o_c2 = L.cls[1].w;
     a.a = hk(0); a.out = ek(0); a.o_w1 = L.eenc[0].w; a.o_w2 = L.eenc[1].w;
     a.sc = sc(s_eenc); a.amax = am(s_eenc); a.sc_cls = sc(s_cls); a.amax_cls = am(s_cls);
-    // the edge encoder and every edge network but the last also write the
-    // outgoing message sums of their output states
-    static_assert(src_aligned<P, EDGE, false>() && src_aligned<P, EDGE_ENC, false>(), "outgoing sums");
+    // 2-byte states: the edge encoder and every edge network but the last
+    // also write the outgoing message sums of their output states
+    constexpr bool out_fused = src_aligned<P, EDGE, false>();
+    static_assert(out_fused == src_aligned<P, EDGE_ENC, false>(), "both edge MLPs write the outgoing sums or neither");
     a.rows = w.row_ptr; a.n_rows = N; a.mout = mk(0);
     {
         StageTimer t(c, VELO_STAGE_EDGE_ENC, s);
@@ -653,7 +658,7 @@ void gnn_ph(velo_ctx *c, const velo_hits *hits, float *logit, const float *Pw, b
     for (int k = 0; k < iters; k++) {
         if (N > 0) {
             StageTimer t(c, VELO_STAGE_MESSAGES, s);
-            k_messages<P, H><<<persistent_grid(c, stage_per_cu(c, VELO_STAGE_MESSAGES, 16)), 256, 0, s>>>(
+            k_messages<P, H, out_fused><<<persistent_grid(c, stage_per_cu(c, VELO_STAGE_MESSAGES, 16)), 256, 0, s>>>(
                 N, w.row_ptr, w.in_ptr, w.in_list, ek(k), mk(k), c->tune_xcd[VELO_STAGE_MESSAGES], w.flags);
         }
         MlpArgs nd{};
