@@ -404,7 +404,7 @@ def main():
     ap.add_argument("--latency", action="store_true", help="per-batch p50/p99 latency (with --graph: of replays)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the built-in launch parameters")
     ap.add_argument("--no-quality", action="store_true", help="skip the track-finding quality block")
-    ap.add_argument("--quality-steps", type=int, default=600, help="training steps before the quality block")
+    ap.add_argument("--quality-steps", type=int, default=1500, help="training steps before the quality block")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run a float32 add of this size (reads and writes known bytes): the reference "
                          "kernel that scales the HBM traffic counters of a profiled run")
