@@ -60,7 +60,7 @@ bool dalloc(T **p, int64_t count) {
 void free_ws(Workspace &w) {
     void *ptrs[] = {w.emb, w.hit_event, w.plane_off, w.deg, w.row_ptr, w.nbr, w.src_g, w.dst_g,
                     w.in_ptr, w.in_list, w.scan_tmp, w.h[0], w.h[1],
-                    w.m, w.e, w.n_edges, w.flags, w.eoff_tmp, w.ck_h, w.ck_e, w.ck_m, w.g_e[0], w.g_e[1],
+                    w.m, w.ab, w.e, w.n_edges, w.flags, w.eoff_tmp, w.ck_h, w.ck_e, w.ck_m, w.g_e[0], w.g_e[1],
                     w.g_h[0], w.g_h[1], w.g_xs, w.g_xd, w.g_da, w.g_r, w.g_m, w.g_part, w.g_loss,
                     w.scales, w.amax, w.tmp_logit};
     for (void *p : ptrs)
@@ -169,7 +169,7 @@ velo_status velo_create(const velo_config *cfg, velo_ctx **out) {
               dalloc(&w.in_ptr, N + 1) &&
               dalloc(&w.in_list, E) && dalloc(&w.scan_tmp, w.scan_tmp_len) &&
               dalloc((char **)&w.h[0], N * H * sb) && dalloc((char **)&w.h[1], N * H * sb) &&
-              dalloc(&w.m, N * 2 * H) && dalloc((char **)&w.e, E * H * sb) && dalloc(&w.n_edges, 1) &&
+              dalloc(&w.m, N * 2 * H) && dalloc(&w.ab, N * 2 * H) && dalloc((char **)&w.e, E * H * sb) && dalloc(&w.n_edges, 1) &&
               dalloc(&w.flags, 1) &&
               dalloc(&w.eoff_tmp, B + 1);
     if (ok && k.precision == VELO_FP8) {

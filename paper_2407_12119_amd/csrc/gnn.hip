@@ -143,6 +143,51 @@ __global__ __launch_bounds__(512) void k_node_enc(int64_t n_hits, const float *_
 }
 
 // ------------------------------------------------------------------------
+// per-hit first-layer products of an edge MLP (the AB modes below):
+//   AB[i] = [W1[:, cs:cs+H] h_i, W1[:, cd:cd+H] h_i]
+// with the MLP's operand precision and float32 accumulation; for fp8 the raw
+// accumulators (the edge kernel descales them with its own products).  W1 is
+// the row-major [H x k1f] first-layer weight of that MLP.
+// ------------------------------------------------------------------------
+template <class P, int H>
+__global__ __launch_bounds__(512) void k_hit_proj(int64_t n_hits, const typename P::state_t *__restrict__ h,
+                                                  const float *__restrict__ P_, int64_t o_w1, int k1f, int cs, int cd,
+                                                  const float *__restrict__ sc, float *__restrict__ ab,
+                                                  const unsigned *__restrict__ flags) {
+    using W = typename P::wfrag_t;
+    constexpr int MO = H / 16, KB = H / P::KBLK;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    W *sWs = (W *)lds_raw;
+    W *sWd = (W *)(lds_raw + frag_bytes<P>(H, H));
+    const MlpScales S = read_scales(sc);
+    stage<P>(sWs, P_ + o_w1 + cs, H, H, MO, S.iw1, k1f);
+    stage<P>(sWd, P_ + o_w1 + cd, H, H, MO, S.iw1, k1f);
+    __syncthreads();
+    if (*flags) return;
+    const int lane = threadIdx.x & 63, n = lane & 15, g = lane >> 4;
+    const int64_t units = (n_hits + 15) >> 4;
+    for (int64_t u = wave_id(); u < units; u += n_waves()) {
+        const int64_t i = u * 16 + n;
+        const int64_t ic = i < n_hits ? i : n_hits - 1;
+        typename P::frag_t X[KB];
+#pragma unroll
+        for (int kb = 0; kb < KB; kb++) X[kb] = P::load(h + ic * H, kb, g, S.ix1);
+        f32x4 a[MO], b[MO];
+        zero<MO>(a);
+        zero<MO>(b);
+        gemm<P, MO, KB>(sWs, X, a, lane);
+        gemm<P, MO, KB>(sWd, X, b, lane);
+        if (i < n_hits) {
+#pragma unroll
+            for (int mo = 0; mo < MO; mo++) {
+                *(f32x4 *)(ab + i * 2 * H + 16 * mo + 4 * g) = a[mo];
+                *(f32x4 *)(ab + i * 2 * H + H + 16 * mo + 4 * g) = b[mo];
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------------
 // generic two-layer MLP over gathered segments
 //   NODE:     X = [h_in[i], m[i, 0:H], m[i, H:2H]],  h_out[i] = h_in[i] + MLP(X)
 //   EDGE:     X = [e[q], h[src q], h[dst q]],        e[q] = e[q] + MLP(X) (in place)
@@ -150,8 +195,14 @@ __global__ __launch_bounds__(512) void k_node_enc(int64_t n_hits, const float *_
 //   CLS_ONLY: X = e[q]                               (classifier only)
 // With CLS the edge classifier H -> H -> 1 runs on the result (Sec. 5.2) and
 // writes the logit; the final edge state is then not stored.
+// The first layer is linear in its concatenated input, so its products with
+// the two hit segments can be formed once per hit (k_hit_proj: AB[i] =
+// [W1_src h_i, W1_dst h_i], float32) instead of once per edge:
+//   EDGE_AB:  X = [e[q]],   hidden = relu(b1 + W1_e e + AB[src][0:H] + AB[dst][H:2H])
+//   ENC_AB:   no product,   hidden = relu(b1 + AB[src][0:H] + AB[dst][H:2H])
+// the same sums as EDGE / EDGE_ENC in another order.
 // ------------------------------------------------------------------------
-enum Mode { NODE = 0, EDGE = 1, EDGE_ENC = 2, CLS_ONLY = 3 };
+enum Mode { NODE = 0, EDGE = 1, EDGE_ENC = 2, CLS_ONLY = 3, EDGE_AB = 4, ENC_AB = 5 };
 
 struct MlpArgs {
     const int *n_dev;      // device item count (edges) or null
@@ -173,13 +224,23 @@ struct MlpArgs {
     const int *rows;
     int64_t n_rows;
     float *mout;
+    const float *ab;               // EDGE_AB / ENC_AB: per-hit first-layer products [N x 2H]
     const unsigned *flags;
 };
 
 constexpr int kMlpBlock = 512;
 
+// input segments of the first layer's weight (in the parameter blob)
 template <int MODE>
-constexpr int nseg() { return MODE == EDGE_ENC ? 2 : (MODE == CLS_ONLY ? 0 : 3); }
+constexpr int kseg() { return (MODE == EDGE_ENC || MODE == ENC_AB) ? 2 : (MODE == CLS_ONLY ? 0 : 3); }
+// segments multiplied per item (the AB modes take the hit segments from AB)
+template <int MODE>
+constexpr int nseg() { return MODE == EDGE_AB ? 1 : (MODE == ENC_AB ? 0 : kseg<MODE>()); }
+template <int MODE>
+constexpr bool has_ab() { return MODE == EDGE_AB || MODE == ENC_AB; }
+// modes that update an edge state in place (residual from e)
+template <int MODE>
+constexpr bool edge_update() { return MODE == EDGE || MODE == EDGE_AB; }
 
 // Edge MLPs on 2-byte states (bf16, fp8) that feed a message step (the edge
 // encoder and every edge network but the one fused with the classifier) walk
@@ -192,9 +253,15 @@ constexpr bool src_aligned() {
     return sizeof(typename P::state_t) == 2 && (MODE == EDGE || MODE == EDGE_ENC) && !CLS;
 }
 
+// LDS: [W1 fragments (nseg H wide)] [W2] [classifier W1] [biases] [classifier biases] [carries]
+template <class P, int H, int MODE>
+constexpr size_t mlp_w_bytes() {
+    return MODE == CLS_ONLY ? 0 : (nseg<MODE>() ? frag_bytes<P>(H, nseg<MODE>() * H) : 0) + frag_bytes<P>(H, H);
+}
+
 template <class P, int H, int MODE, bool CLS>
 constexpr size_t mlp_lds() {
-    return (nseg<MODE>() ? frag_bytes<P>(H, nseg<MODE>() * H) + frag_bytes<P>(H, H) + sizeof(float) * 2 * H : 0) +
+    return mlp_w_bytes<P, H, MODE>() + (MODE == CLS_ONLY ? 0 : sizeof(float) * 2 * H) +
            (CLS ? frag_bytes<P>(H, H) + sizeof(float) * 2 * H : 0) +
            (src_aligned<P, MODE, CLS>() ? sizeof(float) * H * (kMlpBlock / 64) : 0);
 }
@@ -252,17 +319,17 @@ __global__ __launch_bounds__(512) void k_mlp(MlpArgs A) {
     using S = typename P::state_t;
     using W = typename P::wfrag_t;
     constexpr int MO = H / 16, KB = H / P::KBLK, NSEG = nseg<MODE>();
-    constexpr int K1 = NSEG * H;
+    constexpr bool MLP = MODE != CLS_ONLY;
+    constexpr int K1 = NSEG * H, K1F = kseg<MODE>() * H;   // multiplied / stored width of W1
     extern __shared__ __align__(16) unsigned char lds_raw[];
     W *sW1 = (W *)lds_raw;
     W *sW2 = (W *)(lds_raw + (NSEG ? frag_bytes<P>(H, K1) : 0));
-    W *sC1 = (W *)(lds_raw + (NSEG ? frag_bytes<P>(H, K1) + frag_bytes<P>(H, H) : 0));
+    W *sC1 = (W *)(lds_raw + mlp_w_bytes<P, H, MODE>());
     // biases, pre-divided by the fp8 descale factor: they initialise the MFMA
     // accumulators (sB: this MLP's two layers; sCB: the classifier's hidden
     // layer, then its output weights)
-    float *sB = (float *)(lds_raw + (NSEG ? frag_bytes<P>(H, K1) + frag_bytes<P>(H, H) : 0) +
-                          (CLS ? frag_bytes<P>(H, H) : 0));
-    float *sCB = sB + (NSEG ? 2 * H : 0);
+    float *sB = (float *)(lds_raw + mlp_w_bytes<P, H, MODE>() + (CLS ? frag_bytes<P>(H, H) : 0));
+    float *sCB = sB + (MLP ? 2 * H : 0);
     const MlpScales SC = read_scales(A.sc), SCc = read_scales(A.sc_cls);
     if (CLS)
         for (int t = threadIdx.x; t < H; t += blockDim.x) {
@@ -270,11 +337,11 @@ __global__ __launch_bounds__(512) void k_mlp(MlpArgs A) {
             sCB[H + t] = A.P[A.o_c2 + t];
         }
     const float b_out = CLS ? A.P[A.o_c2 + H] : 0.f;
-    if (NSEG) {
-        stage<P>(sW1, A.P + A.o_w1, H, K1, MO, SC.iw1);
+    if (MLP) {
+        if (NSEG) stage<P>(sW1, A.P + A.o_w1, H, K1, MO, SC.iw1, K1F);
         stage<P>(sW2, A.P + A.o_w2, H, H, MO, SC.iw2);
         for (int t = threadIdx.x; t < H; t += blockDim.x) {
-            sB[t] = A.P[A.o_w1 + (int64_t)H * K1 + t] / SC.d1;
+            sB[t] = A.P[A.o_w1 + (int64_t)H * K1F + t] / SC.d1;
             sB[H + t] = A.P[A.o_w2 + (int64_t)H * H + t] / SC.d2;
         }
     }
@@ -292,9 +359,18 @@ __global__ __launch_bounds__(512) void k_mlp(MlpArgs A) {
     // gather the inputs of unit u into X
     // fp8 keeps the stored (bf16) state of segment 0 for the residual, so it
     // is not read twice
-    constexpr bool RAW = P::kScaled && (MODE == NODE || MODE == EDGE);
+    constexpr bool RAW = P::kScaled && (MODE == NODE || edge_update<MODE>());
     using raw_t = BF16::frag_t;
-    auto load_unit = [&](int64_t u, typename P::frag_t *X, raw_t *R) {
+    constexpr bool AB = has_ab<MODE>();
+    // AB modes: the two per-hit first-layer products of an item (2 MO fragments)
+    auto load_ab = [&](int64_t s, int64_t d, f32x4 *G) {
+#pragma unroll
+        for (int mo = 0; mo < MO; mo++) {
+            G[mo] = *(const f32x4 *)(A.ab + s * 2 * H + 16 * mo + 4 * g);
+            G[MO + mo] = *(const f32x4 *)(A.ab + d * 2 * H + H + 16 * mo + 4 * g);
+        }
+    };
+    auto load_unit = [&](int64_t u, typename P::frag_t *X, raw_t *R, f32x4 *G) {
         const int64_t q = u * 16 + n;
         const int64_t qc = q < N ? q : N - 1;
         if constexpr (RAW) {
@@ -328,6 +404,15 @@ __global__ __launch_bounds__(512) void k_mlp(MlpArgs A) {
                 X[kb] = P::load(sa + s * H, kb, g, ix);
                 X[KB + kb] = P::load(sa + d * H, kb, g, ix);
             }
+        } else if (MODE == EDGE_AB) {
+            const int64_t s = A.src_g[qc], d = A.dst_g[qc];
+            if constexpr (!RAW) {
+#pragma unroll
+                for (int kb = 0; kb < KB; kb++) X[kb] = P::load(sa + qc * H, kb, g, ix);
+            }
+            load_ab(s, d, G);
+        } else if (MODE == ENC_AB) {
+            load_ab(A.src_g[qc], A.dst_g[qc], G);
         }
     };
     if constexpr (src_aligned<P, MODE, CLS>()) {
@@ -454,20 +539,23 @@ __global__ __launch_bounds__(512) void k_mlp(MlpArgs A) {
         return;
     }
     // memory-bound precisions prefetch the next unit's inputs during the MFMAs
-    constexpr bool PREFETCH = sizeof(S) < 4 && NSEG > 0;
+    constexpr bool PREFETCH = sizeof(S) < 4 && MLP;
+    constexpr int NG = AB ? 2 * MO : 1;
     // two units in flight: Xn holds unit u + step, Xm unit u + 2 step
     typename P::frag_t Xn[NX], Xm[NX];
     raw_t Rn[RAW ? KB : 1], Rm[RAW ? KB : 1];
+    f32x4 Gn[NG], Gm[NG];
     const WaveRange wr = wave_range(units, A.xcd != 0);
     int64_t u = wr.first;
-    if (PREFETCH && u < wr.end) load_unit(u, Xn, Rn);
-    if (PREFETCH && u + wr.step < wr.end) load_unit(u + wr.step, Xm, Rm);
+    if (PREFETCH && u < wr.end) load_unit(u, Xn, Rn, Gn);
+    if (PREFETCH && u + wr.step < wr.end) load_unit(u + wr.step, Xm, Rm, Gm);
     for (; u < wr.end; u += wr.step) {
         const int64_t q = u * 16 + n;
         const bool ok = q < N;
         const int64_t qc = ok ? q : N - 1;
         typename P::frag_t X[NX];
         raw_t R[RAW ? KB : 1];
+        f32x4 G[NG];
         if (PREFETCH) {
 #pragma unroll
             for (int k = 0; k < NX; k++) {
@@ -481,13 +569,20 @@ __global__ __launch_bounds__(512) void k_mlp(MlpArgs A) {
                     Rn[k] = Rm[k];
                 }
             }
-            if (u + 2 * wr.step < wr.end) load_unit(u + 2 * wr.step, Xm, Rm);
-        } else if (NSEG > 0) {
-            load_unit(u, X, R);
+            if constexpr (AB) {
+#pragma unroll
+                for (int k = 0; k < NG; k++) {
+                    G[k] = Gn[k];
+                    Gn[k] = Gm[k];
+                }
+            }
+            if (u + 2 * wr.step < wr.end) load_unit(u + 2 * wr.step, Xm, Rm, Gm);
+        } else if (MLP) {
+            load_unit(u, X, R, G);
         }
         f32x4 o[MO];
-        if (NSEG) {
-            if (A.amax) {
+        if (MLP) {
+            if (!AB && A.amax) {   // calibration runs the unsplit modes
                 float mx = 0.f;
 #pragma unroll
                 for (int k = 0; k < NX; k++) mx = fmaxf(mx, P::absmax(X[k]));
@@ -495,7 +590,14 @@ __global__ __launch_bounds__(512) void k_mlp(MlpArgs A) {
             }
             f32x4 hid[MO];
             load_bias<MO>(sB, hid, g);
-            gemm<P, MO, NSEG * KB>(sW1, X, hid, lane);
+            if constexpr (AB) {
+#pragma unroll
+                for (int mo = 0; mo < MO; mo++) {
+                    hid[mo] += G[mo];
+                    hid[mo] += G[MO + mo];
+                }
+            }
+            if constexpr (NSEG > 0) gemm<P, MO, NSEG * KB>(sW1, X, hid, lane);
             if (P::kScaled) rescale<MO>(hid, SC.d1);
             relu<MO>(hid);
             if (A.amax) record_amax(absmax4<MO>(hid), A.amax + 1);
@@ -506,7 +608,7 @@ __global__ __launch_bounds__(512) void k_mlp(MlpArgs A) {
             if (P::kScaled) rescale<MO>(o, SC.d2);
 #pragma unroll
             for (int mo = 0; mo < MO; mo++) {
-                if constexpr (MODE != EDGE_ENC) {   // residual (Sec. 5.2), from the unquantised state
+                if constexpr (MODE != EDGE_ENC && MODE != ENC_AB) {   // residual (Sec. 5.2), from the unquantised state
                     if constexpr (RAW) {
 #pragma unroll
                         for (int i = 0; i < 4; i++) o[mo][i] += BF16::seg0(R, mo, i);
@@ -516,7 +618,7 @@ __global__ __launch_bounds__(512) void k_mlp(MlpArgs A) {
                     }
                 }
             }
-            if (ok && !(CLS && MODE == EDGE)) P::template store_all<MO>((S *)A.out + q * H, g, o);
+            if (ok && !(CLS && edge_update<MODE>())) P::template store_all<MO>((S *)A.out + q * H, g, o);
         } else {
 #pragma unroll
             for (int mo = 0; mo < MO; mo++) o[mo] = P::load4(sa + qc * H + P::stored(mo, g));
@@ -611,6 +713,25 @@ void run_mlp(velo_ctx *c, int stage, MlpArgs a, hipStream_t s) {
     k_mlp<P, H, MODE, CLS><<<persistent_grid(c, stage_per_cu(c, stage, occ, occ)), kMlpBlock, lds, s>>>(a);
 }
 
+// float32 MLPs are MFMA-bound: in inference their edge MLPs take the hit
+// segments' first-layer products from k_hit_proj (the AB modes), which
+// removes two thirds of the edge encoder's and half of the edge network's
+// per-edge matrix work.  Training and fp8 calibration keep the concatenated
+// form (the backward pass recomputes the hidden layers the same way).
+template <class P>
+constexpr bool uses_ab() { return sizeof(typename P::state_t) == 4; }
+
+template <class P, int H, int MODE, int MODE_AB, bool CLS>
+void run_mlp_ab(velo_ctx *c, int stage, const MlpArgs &a, bool ab, hipStream_t s) {
+    if constexpr (uses_ab<P>()) {
+        if (ab) {
+            run_mlp<P, H, MODE_AB, CLS>(c, stage, a, s);
+            return;
+        }
+    }
+    run_mlp<P, H, MODE, CLS>(c, stage, a, s);
+}
+
 // The GNN forward pass.  Inference updates the edge state in place and fuses
 // the classifier into the last edge network; training (train = true) keeps
 // every step's hit and edge encodings and messages as checkpoints for the
@@ -631,8 +752,20 @@ void gnn_ph(velo_ctx *c, const velo_hits *hits, float *logit, const float *Pw, b
     auto hk = [&](int k) -> S * { return train ? (S *)w.ck_h + (int64_t)k * Nmax * H : (S *)w.h[k & 1]; };
     auto ek = [&](int k) -> S * { return train ? (S *)w.ck_e + (int64_t)k * Ecap * H : (S *)w.e; };
     auto mk = [&](int k) -> float * { return train ? w.ck_m + (int64_t)k * Nmax * 2 * H : w.m; };
+    const bool ab = uses_ab<P>() && !train && !calib;
+    auto hit_proj = [&](const S *h, int64_t o_w1, int k1f, int cs, int cd, const float *scp) {
+        if constexpr (uses_ab<P>()) {
+            if (N <= 0) return;
+            constexpr size_t lds = 2 * frag_bytes<P>(H, H);
+            static const int per_cu =
+                blocks_per_cu(reinterpret_cast<const void *>(&k_hit_proj<P, H>), kMlpBlock, lds);
+            k_hit_proj<P, H><<<persistent_grid(c, per_cu), kMlpBlock, lds, s>>>(N, h, Pw, o_w1, k1f, cs, cd, scp,
+                                                                                w.ab, w.flags);
+        }
+    };
     // the classifier is fused into the last edge network when its weights fit in LDS too
-    const bool fuse_cls = !train && mlp_lds<P, H, EDGE, true>() <= c->lds_max;
+    const bool fuse_cls =
+        !train && (ab ? mlp_lds<P, H, EDGE_AB, true>() : mlp_lds<P, H, EDGE, true>()) <= c->lds_max;
     if (N > 0) {
         const size_t lds = frag_bytes<P>(H, H) + sizeof(float) * H * 4;
         static const int per_cu = blocks_per_cu(reinterpret_cast<const void *>(&k_node_enc<P, H>), kMlpBlock, lds);
@@ -650,10 +783,11 @@ void gnn_ph(velo_ctx *c, const velo_hits *hits, float *logit, const float *Pw, b
     // also write the outgoing message sums of their output states
     constexpr bool out_fused = src_aligned<P, EDGE, false>();
     static_assert(out_fused == src_aligned<P, EDGE_ENC, false>(), "both edge MLPs write the outgoing sums or neither");
-    a.rows = w.row_ptr; a.n_rows = N; a.mout = mk(0);
+    a.rows = w.row_ptr; a.n_rows = N; a.mout = mk(0); a.ab = w.ab;
     {
         StageTimer t(c, VELO_STAGE_EDGE_ENC, s);
-        run_mlp<P, H, EDGE_ENC, false>(c, VELO_STAGE_EDGE_ENC, a, s);
+        if (ab) hit_proj(hk(0), L.eenc[0].w, 2 * H, 0, H, sc(s_eenc));
+        run_mlp_ab<P, H, EDGE_ENC, ENC_AB, false>(c, VELO_STAGE_EDGE_ENC, a, ab, s);
     }
     for (int k = 0; k < iters; k++) {
         if (N > 0) {
@@ -675,10 +809,11 @@ void gnn_ph(velo_ctx *c, const velo_hits *hits, float *logit, const float *Pw, b
         const bool last = k == iters - 1;
         ed.mout = last ? nullptr : mk(k + 1);
         StageTimer t(c, last && fuse_cls ? VELO_STAGE_EDGE_CLS : VELO_STAGE_EDGE_NET, s);
+        if (ab) hit_proj(hk(k + 1), L.edge[k][0].w, 3 * H, H, 2 * H, sc(slot_edge(k)));
         if (last && fuse_cls)
-            run_mlp<P, H, EDGE, true>(c, VELO_STAGE_EDGE_CLS, ed, s);
+            run_mlp_ab<P, H, EDGE, EDGE_AB, true>(c, VELO_STAGE_EDGE_CLS, ed, ab, s);
         else
-            run_mlp<P, H, EDGE, false>(c, VELO_STAGE_EDGE_NET, ed, s);
+            run_mlp_ab<P, H, EDGE, EDGE_AB, false>(c, VELO_STAGE_EDGE_NET, ed, ab, s);
     }
     if (iters == 0 || !fuse_cls) {
         MlpArgs cl = a;

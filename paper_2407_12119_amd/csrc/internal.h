@@ -47,6 +47,7 @@ struct Workspace {
     int64_t scan_tmp_len = 0;
     void *h[2] = {nullptr, nullptr};    // [max_hits x H] hit encodings (ping-pong), fp32 or bf16
     float *m = nullptr;          // [max_hits x 2H] messages, float32 in every precision
+    float *ab = nullptr;         // [max_hits x 2H] per-hit first-layer products of an edge MLP
     void *e = nullptr;           // [max_edges x H] edge encodings (updated in place), fp32 or bf16
     int *n_edges = nullptr;      // [1] internal edge count
     unsigned *flags = nullptr;   // [1] latched device errors
