@@ -38,16 +38,23 @@ def log(msg):
 def edge_net_work(H, prec, n_edges, n_hits):
     """Algorithmic work of one edge-network launch (non-final message-passing step).
 
-    flops: two layers per edge, 3H -> H and H -> H, 2 flops per multiply-add.
-    bytes: the edge state read and written once, its two hit indices, and
-    every hit state read once; with 2-byte states the launch also writes the
-    float32 outgoing message sum of every hit (H floats).
+    bf16/fp8 (concatenated first layer): two layers per edge, 3H -> H and
+    H -> H, 2 flops per multiply-add; bytes: the edge state read and written
+    once, its two hit indices, every hit state read once, and the float32
+    outgoing message sum of every hit (H floats) written.
+    fp32 (factorised first layer): the hit segments' products come from the
+    per-hit projection (timed as its own stage), so per edge the launch does
+    the e segment of the first layer (H -> H) and the second layer; bytes:
+    the edge state read and written once, its two hit indices and every
+    hit's pair of float32 products (2H floats) read once.
     """
     s = STATE_BYTES[prec]
+    if s == 4:
+        flops = 2 * (H * H + H * H) * n_edges
+        nbytes = (2 * H * s + 8) * n_edges + 2 * H * 4 * n_hits
+        return flops, nbytes
     flops = 2 * (3 * H * H + H * H) * n_edges
-    nbytes = (2 * H * s + 8) * n_edges + H * s * n_hits
-    if s == 2:
-        nbytes += 4 * H * n_hits
+    nbytes = (2 * H * s + 8) * n_edges + H * s * n_hits + 4 * H * n_hits
     return flops, nbytes
 
 
@@ -339,8 +346,8 @@ def run_batched(velo, synth, torch, wl, batch, hits, blob, prec, steps, warmup, 
            "stage_ms_per_step": {k: round(v[0] / steps, 4) for k, v in stages.items()},
            "roofline": roofline(stages, wl.hidden, prec, n_edges, batch.n_hits, wl.name, copy_gbs)}
     # events/s of the path cut after each stage (cumulative, in path order)
-    order = ["prepare", "embed", "knn", "compact", "lists", "node_enc", "edge_enc", "messages", "node_net",
-             "edge_net", "edge_cls", "components"]
+    order = ["prepare", "embed", "knn", "compact", "lists", "node_enc", "hit_proj", "edge_enc", "messages",
+             "node_net", "edge_net", "edge_cls", "components"]
     acc, cum = 0.0, {}
     for k in order:
         acc += res["stage_ms_per_step"].get(k, 0.0)

@@ -187,7 +187,8 @@ typedef enum {
     VELO_STAGE_BWD_DW = 14,    /* training: split-K weight gradients and their reduction */
     VELO_STAGE_BWD_GRAPH = 15, /* training: duals of the gathers and message sums */
     VELO_STAGE_ADAM = 16,      /* training: Adam update */
-    VELO_N_STAGES = 17
+    VELO_STAGE_HIT_PROJ = 17,  /* fp32 inference: per-hit first-layer products of the edge MLPs */
+    VELO_N_STAGES = 18
 } velo_stage;
 
 /* Enable (1) or disable (0) per-stage timing: while enabled every call

@@ -242,15 +242,17 @@ constexpr bool has_ab() { return MODE == EDGE_AB || MODE == ENC_AB; }
 template <int MODE>
 constexpr bool edge_update() { return MODE == EDGE || MODE == EDGE_AB; }
 
-// Edge MLPs on 2-byte states (bf16, fp8) that feed a message step (the edge
-// encoder and every edge network but the one fused with the classifier) walk
-// the edges source hit by source hit, 16 at a time, and also produce the
-// outgoing message sums of the states they write.  The float32 ones are
+// Edge MLPs that feed a message step (the edge encoder and every edge
+// network but the one fused with the classifier) walk the edges source hit
+// by source hit, 16 at a time, and also produce the outgoing message sums of
+// the states they write: with 2-byte states, and with float32 states in the
+// factorised (AB) form.  The concatenated float32 MLPs (training) are
 // MFMA-bound: there the padding of each source's last chunk would cost more
 // than the message kernel saves, so they keep 16-edge tiles.
 template <class P, int MODE, bool CLS>
 constexpr bool src_aligned() {
-    return sizeof(typename P::state_t) == 2 && (MODE == EDGE || MODE == EDGE_ENC) && !CLS;
+    return (sizeof(typename P::state_t) == 2 || has_ab<MODE>()) &&
+           (MODE == EDGE || MODE == EDGE_ENC || MODE == EDGE_AB || MODE == ENC_AB) && !CLS;
 }
 
 // LDS: [W1 fragments (nseg H wide)] [W2] [classifier W1] [biases] [classifier biases] [carries]
@@ -446,11 +448,24 @@ __global__ __launch_bounds__(512) void k_mlp(MlpArgs A) {
             if (c.c0 + 16 < c.a1) return Chunk{c.i, c.a0, c.c0 + 16, c.a1};
             return from_hit(c.i + wr.step);
         };
-        auto load_chunk = [&](const Chunk &c, typename P::frag_t *X, raw_t *R) {
+        auto load_chunk = [&](const Chunk &c, typename P::frag_t *X, raw_t *R, f32x4 *G) {
             const int64_t q = c.c0 + n;
             const int64_t qc = q < c.a1 ? q : c.a1 - 1;
             const int64_t d = A.dst_g[qc];
-            if constexpr (MODE == EDGE) {
+            if constexpr (AB) {
+                if constexpr (MODE == EDGE_AB) {
+#pragma unroll
+                    for (int kb = 0; kb < KB; kb++) {
+                        if constexpr (RAW) {
+                            R[kb] = BF16::load((const BF16::state_t *)sa + qc * H, kb, g);
+                            X[kb] = P::pack(R[kb], ix);
+                        } else {
+                            X[kb] = P::load(sa + qc * H, kb, g, ix);
+                        }
+                    }
+                }
+                load_ab(c.i, d, G);
+            } else if constexpr (MODE == EDGE) {
                 const S *hb = (const S *)A.b;
 #pragma unroll
                 for (int kb = 0; kb < KB; kb++) {
@@ -471,10 +486,10 @@ __global__ __launch_bounds__(512) void k_mlp(MlpArgs A) {
                 }
             }
         };
-        auto process = [&](const Chunk &cur, const typename P::frag_t *X, const raw_t *R) {
+        auto process = [&](const Chunk &cur, const typename P::frag_t *X, const raw_t *R, const f32x4 *G) {
             const int64_t q = cur.c0 + n;
             const bool ok = q < cur.a1;
-            if (A.amax) {
+            if (!AB && A.amax) {   // calibration runs the unsplit modes
                 float mx = 0.f;
 #pragma unroll
                 for (int k = 0; k < NX; k++) mx = fmaxf(mx, P::absmax(X[k]));
@@ -482,7 +497,14 @@ __global__ __launch_bounds__(512) void k_mlp(MlpArgs A) {
             }
             f32x4 hid[MO], o[MO];
             load_bias<MO>(sB, hid, g);
-            gemm<P, MO, NSEG * KB>(sW1, X, hid, lane);
+            if constexpr (AB) {
+#pragma unroll
+                for (int mo = 0; mo < MO; mo++) {
+                    hid[mo] += G[mo];
+                    hid[mo] += G[MO + mo];
+                }
+            }
+            if constexpr (NSEG > 0) gemm<P, MO, NSEG * KB>(sW1, X, hid, lane);
             if (P::kScaled) rescale<MO>(hid, SC.d1);
             relu<MO>(hid);
             if (A.amax) record_amax(absmax4<MO>(hid), A.amax + 1);
@@ -491,7 +513,7 @@ __global__ __launch_bounds__(512) void k_mlp(MlpArgs A) {
             load_bias<MO>(sB + H, o, g);
             gemm<P, MO, KB>(sW2, xh, o, lane);
             if (P::kScaled) rescale<MO>(o, SC.d2);
-            if constexpr (MODE == EDGE) {   // residual (Sec. 5.2), from the unquantised state
+            if constexpr (edge_update<MODE>()) {   // residual (Sec. 5.2), from the unquantised state
 #pragma unroll
                 for (int mo = 0; mo < MO; mo++)
 #pragma unroll
@@ -520,20 +542,32 @@ __global__ __launch_bounds__(512) void k_mlp(MlpArgs A) {
                 }
             }
         };
+        constexpr int NG = AB ? 2 * MO : 1;
+        if constexpr (sizeof(S) == 4) {   // MFMA-bound: no prefetch, fewer registers
+            typename P::frag_t X[NX];
+            raw_t R[RAW ? KB : 1];
+            f32x4 G[NG];
+            for (Chunk c = from_hit(wr.first); c.i < wr.end; c = next(c)) {
+                load_chunk(c, X, R, G);
+                process(c, X, R, G);
+            }
+            return;
+        }
         // two input buffers in alternation (no register copies): the loads
         // of the next chunk are in flight while this one is computed
         typename P::frag_t XA[NX], XB[NX];
         raw_t RA[RAW ? KB : 1], RB[RAW ? KB : 1];
+        f32x4 GA[NG], GB[NG];
         Chunk c0 = from_hit(wr.first);
         Chunk c1 = next(c0);
-        if (c0.i < wr.end) load_chunk(c0, XA, RA);
+        if (c0.i < wr.end) load_chunk(c0, XA, RA, GA);
         while (c0.i < wr.end) {
-            if (c1.i < wr.end) load_chunk(c1, XB, RB);
-            process(c0, XA, RA);
+            if (c1.i < wr.end) load_chunk(c1, XB, RB, GB);
+            process(c0, XA, RA, GA);
             c0 = c1; c1 = next(c1);
             if (c0.i >= wr.end) break;
-            if (c1.i < wr.end) load_chunk(c1, XA, RA);
-            process(c0, XB, RB);
+            if (c1.i < wr.end) load_chunk(c1, XA, RA, GA);
+            process(c0, XB, RB, GB);
             c0 = c1; c1 = next(c1);
         }
         return;
@@ -756,6 +790,7 @@ void gnn_ph(velo_ctx *c, const velo_hits *hits, float *logit, const float *Pw, b
     auto hit_proj = [&](const S *h, int64_t o_w1, int k1f, int cs, int cd, const float *scp) {
         if constexpr (uses_ab<P>()) {
             if (N <= 0) return;
+            StageTimer t(c, VELO_STAGE_HIT_PROJ, s);
             constexpr size_t lds = 2 * frag_bytes<P>(H, H);
             static const int per_cu =
                 blocks_per_cu(reinterpret_cast<const void *>(&k_hit_proj<P, H>), kMlpBlock, lds);
@@ -781,19 +816,26 @@ void gnn_ph(velo_ctx *c, const velo_hits *hits, float *logit, const float *Pw, b
     a.sc = sc(s_eenc); a.amax = am(s_eenc); a.sc_cls = sc(s_cls); a.amax_cls = am(s_cls);
     // 2-byte states: the edge encoder and every edge network but the last
     // also write the outgoing message sums of their output states
-    constexpr bool out_fused = src_aligned<P, EDGE, false>();
-    static_assert(out_fused == src_aligned<P, EDGE_ENC, false>(), "both edge MLPs write the outgoing sums or neither");
+    static_assert(src_aligned<P, EDGE, false>() == src_aligned<P, EDGE_ENC, false>() &&
+                      src_aligned<P, EDGE_AB, false>() == src_aligned<P, ENC_AB, false>(),
+                  "both edge MLPs of a form write the outgoing sums or neither");
+    const bool out_fused = ab ? src_aligned<P, EDGE_AB, false>() : src_aligned<P, EDGE, false>();
     a.rows = w.row_ptr; a.n_rows = N; a.mout = mk(0); a.ab = w.ab;
+    if (ab) hit_proj(hk(0), L.eenc[0].w, 2 * H, 0, H, sc(s_eenc));
     {
         StageTimer t(c, VELO_STAGE_EDGE_ENC, s);
-        if (ab) hit_proj(hk(0), L.eenc[0].w, 2 * H, 0, H, sc(s_eenc));
         run_mlp_ab<P, H, EDGE_ENC, ENC_AB, false>(c, VELO_STAGE_EDGE_ENC, a, ab, s);
     }
     for (int k = 0; k < iters; k++) {
         if (N > 0) {
             StageTimer t(c, VELO_STAGE_MESSAGES, s);
-            k_messages<P, H, out_fused><<<persistent_grid(c, stage_per_cu(c, VELO_STAGE_MESSAGES, 16)), 256, 0, s>>>(
-                N, w.row_ptr, w.in_ptr, w.in_list, ek(k), mk(k), c->tune_xcd[VELO_STAGE_MESSAGES], w.flags);
+            const int grid = persistent_grid(c, stage_per_cu(c, VELO_STAGE_MESSAGES, 16));
+            if (out_fused)
+                k_messages<P, H, true><<<grid, 256, 0, s>>>(N, w.row_ptr, w.in_ptr, w.in_list, ek(k), mk(k),
+                                                             c->tune_xcd[VELO_STAGE_MESSAGES], w.flags);
+            else
+                k_messages<P, H, false><<<grid, 256, 0, s>>>(N, w.row_ptr, w.in_ptr, w.in_list, ek(k), mk(k),
+                                                              c->tune_xcd[VELO_STAGE_MESSAGES], w.flags);
         }
         MlpArgs nd{};
         nd.n_dev = nullptr; nd.n_host = N; nd.a = hk(k); nd.b = mk(k); nd.out = hk(k + 1);
@@ -808,8 +850,8 @@ void gnn_ph(velo_ctx *c, const velo_hits *hits, float *logit, const float *Pw, b
         ed.sc = sc(slot_edge(k)); ed.amax = am(slot_edge(k));
         const bool last = k == iters - 1;
         ed.mout = last ? nullptr : mk(k + 1);
-        StageTimer t(c, last && fuse_cls ? VELO_STAGE_EDGE_CLS : VELO_STAGE_EDGE_NET, s);
         if (ab) hit_proj(hk(k + 1), L.edge[k][0].w, 3 * H, H, 2 * H, sc(slot_edge(k)));
+        StageTimer t(c, last && fuse_cls ? VELO_STAGE_EDGE_CLS : VELO_STAGE_EDGE_NET, s);
         if (last && fuse_cls)
             run_mlp_ab<P, H, EDGE, EDGE_AB, true>(c, VELO_STAGE_EDGE_CLS, ed, ab, s);
         else

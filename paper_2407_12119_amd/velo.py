@@ -29,7 +29,8 @@ EXPORTS = ("velo_param_count", "velo_create", "velo_destroy", "velo_set_params",
            "velo_graph_capture", "velo_graph_launch", "velo_graph_destroy", "velo_calibrate",
            "velo_autotune")
 STAGES = ("prepare", "embed", "knn", "compact", "lists", "node_enc", "edge_enc", "messages",
-          "node_net", "edge_net", "edge_cls", "components", "bce", "bwd_mlp", "bwd_dw", "bwd_graph", "adam")
+          "node_net", "edge_net", "edge_cls", "components", "bce", "bwd_mlp", "bwd_dw", "bwd_graph", "adam",
+          "hit_proj")
 
 
 class VeloError(RuntimeError):
