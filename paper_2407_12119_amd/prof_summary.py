@@ -26,7 +26,9 @@ import subprocess
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 KERNEL_SOURCES = ["paper_2407_12119_amd/csrc/gnn.hip", "paper_2407_12119_amd/csrc/mfma.h",
                   "paper_2407_12119_amd/csrc/internal.h"]
-EDGE_NET = {"fp32": "k_mlp<F32, {H}, 1, false>", "bf16": "k_mlp<BF16, {H}, 1, false>",
+# the non-final edge network of each precision's inference path (k_mlp<P, H,
+# mode, classifier>: mode 1 = concatenated first layer, 4 = factorised)
+EDGE_NET = {"fp32": "k_mlp<F32, {H}, 4, false>", "bf16": "k_mlp<BF16, {H}, 1, false>",
             "fp8": "k_mlp<FP8, {H}, 1, false>"}
 PROBE = "CUDAFunctorOnSelf_add"
 
