@@ -60,8 +60,8 @@ bool dalloc(T **p, int64_t count) {
 void free_ws(Workspace &w) {
     void *ptrs[] = {w.emb, w.hit_event, w.plane_off, w.deg, w.row_ptr, w.nbr, w.src_g, w.dst_g,
                     w.in_ptr, w.in_list, w.scan_tmp, w.h[0], w.h[1],
-                    w.m, w.ab, w.e, w.n_edges, w.flags, w.eoff_tmp, w.ck_h, w.ck_e, w.ck_m, w.g_e[0], w.g_e[1],
-                    w.g_h[0], w.g_h[1], w.g_xs, w.g_xd, w.g_da, w.g_r, w.g_m, w.g_part, w.g_loss,
+                    w.m, w.ab, w.e, w.n_edges, w.flags, w.eoff_tmp, w.ck_h, w.ck_e, w.ck_m, w.ck_ab, w.g_sd, w.g_e[0], w.g_e[1],
+                    w.g_h[0], w.g_h[1], w.g_da, w.g_r, w.g_m, w.g_part, w.g_loss,
                     w.scales, w.amax, w.tmp_logit};
     for (void *p : ptrs)
         if (p) hipFree(p);
@@ -183,9 +183,10 @@ velo_status velo_create(const velo_config *cfg, velo_ctx **out) {
     if (ok && k.training) {
         const int64_t it = k.gnn_iters, R = std::max<int64_t>(N, E);
         ok = dalloc((char **)&w.ck_h, (it + 1) * N * H * sb) && dalloc((char **)&w.ck_e, (it + 1) * E * H * sb) &&
-             dalloc(&w.ck_m, std::max<int64_t>(it, 1) * N * 2 * H) && dalloc(&w.g_e[0], E * H) &&
+             dalloc(&w.ck_m, std::max<int64_t>(it, 1) * N * 2 * H) && dalloc(&w.ck_ab, (it + 1) * N * 2 * H) &&
+             dalloc(&w.g_sd, N * 2 * H) && dalloc(&w.g_e[0], E * H) &&
              dalloc(&w.g_e[1], E * H) && dalloc(&w.g_h[0], N * H) && dalloc(&w.g_h[1], N * H) &&
-             dalloc(&w.g_xs, E * H) && dalloc(&w.g_xd, E * H) && dalloc(&w.g_da, R * H) && dalloc(&w.g_r, R * H) &&
+             dalloc(&w.g_da, R * H) && dalloc(&w.g_r, R * H) &&
              dalloc(&w.g_m, N * 2 * H) && dalloc(&w.g_part, (int64_t)train_part_floats(k.gnn_hidden)) &&
              dalloc(&w.g_loss, 256);
     }

@@ -747,11 +747,12 @@ void run_mlp(velo_ctx *c, int stage, MlpArgs a, hipStream_t s) {
     k_mlp<P, H, MODE, CLS><<<persistent_grid(c, stage_per_cu(c, stage, occ, occ)), kMlpBlock, lds, s>>>(a);
 }
 
-// float32 MLPs are MFMA-bound: in inference their edge MLPs take the hit
-// segments' first-layer products from k_hit_proj (the AB modes), which
-// removes two thirds of the edge encoder's and half of the edge network's
-// per-edge matrix work.  Training and fp8 calibration keep the concatenated
-// form (the backward pass recomputes the hidden layers the same way).
+// float32 MLPs are MFMA-bound: their edge MLPs take the hit segments'
+// first-layer products from k_hit_proj (the AB modes), which removes two
+// thirds of the edge encoder's and half of the edge network's per-edge
+// matrix work.  The training form does the same and keeps the products of
+// every step, so the backward pass recomputes the hidden layers with the
+// same sums.  fp8 calibration keeps the concatenated form.
 template <class P>
 constexpr bool uses_ab() { return sizeof(typename P::state_t) == 4; }
 
@@ -786,8 +787,11 @@ void gnn_ph(velo_ctx *c, const velo_hits *hits, float *logit, const float *Pw, b
     auto hk = [&](int k) -> S * { return train ? (S *)w.ck_h + (int64_t)k * Nmax * H : (S *)w.h[k & 1]; };
     auto ek = [&](int k) -> S * { return train ? (S *)w.ck_e + (int64_t)k * Ecap * H : (S *)w.e; };
     auto mk = [&](int k) -> float * { return train ? w.ck_m + (int64_t)k * Nmax * 2 * H : w.m; };
-    const bool ab = uses_ab<P>() && !train && !calib;
-    auto hit_proj = [&](const S *h, int64_t o_w1, int k1f, int cs, int cd, const float *scp) {
+    const bool ab = uses_ab<P>() && !calib;
+    // where the per-hit products of edge MLP `slot` go (0..n-1: edge networks,
+    // n: the edge encoder); training keeps every step's for the backward pass
+    auto abk = [&](int slot) -> float * { return train ? w.ck_ab + (int64_t)slot * Nmax * 2 * H : w.ab; };
+    auto hit_proj = [&](const S *h, int64_t o_w1, int k1f, int cs, int cd, const float *scp, float *dst) {
         if constexpr (uses_ab<P>()) {
             if (N <= 0) return;
             StageTimer t(c, VELO_STAGE_HIT_PROJ, s);
@@ -795,7 +799,7 @@ void gnn_ph(velo_ctx *c, const velo_hits *hits, float *logit, const float *Pw, b
             static const int per_cu =
                 blocks_per_cu(reinterpret_cast<const void *>(&k_hit_proj<P, H>), kMlpBlock, lds);
             k_hit_proj<P, H><<<persistent_grid(c, per_cu), kMlpBlock, lds, s>>>(N, h, Pw, o_w1, k1f, cs, cd, scp,
-                                                                                w.ab, w.flags);
+                                                                                dst, w.flags);
         }
     };
     // the classifier is fused into the last edge network when its weights fit in LDS too
@@ -820,8 +824,8 @@ void gnn_ph(velo_ctx *c, const velo_hits *hits, float *logit, const float *Pw, b
                       src_aligned<P, EDGE_AB, false>() == src_aligned<P, ENC_AB, false>(),
                   "both edge MLPs of a form write the outgoing sums or neither");
     const bool out_fused = ab ? src_aligned<P, EDGE_AB, false>() : src_aligned<P, EDGE, false>();
-    a.rows = w.row_ptr; a.n_rows = N; a.mout = mk(0); a.ab = w.ab;
-    if (ab) hit_proj(hk(0), L.eenc[0].w, 2 * H, 0, H, sc(s_eenc));
+    a.rows = w.row_ptr; a.n_rows = N; a.mout = mk(0); a.ab = abk(iters);
+    if (ab) hit_proj(hk(0), L.eenc[0].w, 2 * H, 0, H, sc(s_eenc), abk(iters));
     {
         StageTimer t(c, VELO_STAGE_EDGE_ENC, s);
         run_mlp_ab<P, H, EDGE_ENC, ENC_AB, false>(c, VELO_STAGE_EDGE_ENC, a, ab, s);
@@ -850,7 +854,8 @@ void gnn_ph(velo_ctx *c, const velo_hits *hits, float *logit, const float *Pw, b
         ed.sc = sc(slot_edge(k)); ed.amax = am(slot_edge(k));
         const bool last = k == iters - 1;
         ed.mout = last ? nullptr : mk(k + 1);
-        if (ab) hit_proj(hk(k + 1), L.edge[k][0].w, 3 * H, H, 2 * H, sc(slot_edge(k)));
+        ed.ab = abk(k);
+        if (ab) hit_proj(hk(k + 1), L.edge[k][0].w, 3 * H, H, 2 * H, sc(slot_edge(k)), abk(k));
         StageTimer t(c, last && fuse_cls ? VELO_STAGE_EDGE_CLS : VELO_STAGE_EDGE_NET, s);
         if (last && fuse_cls)
             run_mlp_ab<P, H, EDGE, EDGE_AB, true>(c, VELO_STAGE_EDGE_CLS, ed, ab, s);

@@ -59,9 +59,11 @@ struct Workspace {
     void *ck_h = nullptr;        // [(n+1) x max_hits x H] hit encodings h^0..h^n
     void *ck_e = nullptr;        // [(n+1) x max_edges x H] edge encodings e^0..e^n
     float *ck_m = nullptr;       // [n x max_hits x 2H] messages of every step
+    float *ck_ab = nullptr;      // [(n+1) x max_hits x 2H] per-hit first-layer products (slot k: edge
+                                 // network k, slot n: edge encoder)
+    float *g_sd = nullptr;       // [max_hits x 2H] per-hit sums of dL/d(hidden) over out- and in-edges
     float *g_e[2] = {nullptr, nullptr};   // [max_edges x H] dL/de (ping-pong)
     float *g_h[2] = {nullptr, nullptr};   // [max_hits x H] dL/dh (ping-pong)
-    float *g_xs = nullptr, *g_xd = nullptr;  // [max_edges x H] per-edge input gradients
     float *g_da = nullptr, *g_r = nullptr;   // [max(E,N) x H] hidden gradient / activation
     float *g_m = nullptr;        // [max_hits x 2H] dL/dm
     float *g_part = nullptr;     // [n_chunks x part_len] weight-gradient partial sums

@@ -176,7 +176,8 @@ __device__ inline typename P::wfrag_t pack_weights(const float *w, float inv);
 template <class P, bool TRANS = false>
 __device__ inline void stage(typename P::wfrag_t *dst, const float *__restrict__ W, int rows, int K, int MO,
                              float inv_scale = 1.f, int ld = 0) {
-    if (ld == 0) ld = K;   // row stride of W (a column block of a wider matrix has ld > K)
+    // row stride of W (a column block of a wider matrix has a larger one)
+    if (ld == 0) ld = TRANS ? rows : K;
     const int KBn = K / P::KBLK;
     const int total = MO * KBn * 64;
     for (int f = threadIdx.x; f < total; f += blockDim.x) {
@@ -186,7 +187,7 @@ __device__ inline void stage(typename P::wfrag_t *dst, const float *__restrict__
 #pragma unroll
         for (int j = 0; j < P::WJ; j++) {
             const int col = P::col(kb, g, j);
-            w[j] = row < rows ? (TRANS ? W[(int64_t)col * rows + row] : W[(int64_t)row * ld + col]) : 0.f;
+            w[j] = row < rows ? (TRANS ? W[(int64_t)col * ld + row] : W[(int64_t)row * ld + col]) : 0.f;
         }
         dst[f] = pack_weights<P>(w, inv_scale);
     }

@@ -7,12 +7,16 @@
 // the messages m^k; every MLP's hidden activation is recomputed from them in
 // the backward kernel (one recompute per MLP, no stored activations).
 //
+// The edge MLPs' first layers are factorised as in the forward pass:
+// W1 [e, h_s, h_d] = W1_e e + AB[s][0:H] + AB[d][H:2H] with the per-hit
+// products AB of every step kept by the forward pass.
 // Per step k, in reverse:
-//   k_bwd<EDGE>   recompute a = W1 X + b1, r = relu(a) for X = [e^k, h^{k+1}_s,
-//                 h^{k+1}_d]; da = (W2^T dout) * [a > 0]; dX = W1^T da.
-//                 dL/de^k = dout + dX_e (residual); dX_s, dX_d per edge.
-//   k_gather_add  dL/dh^{k+1} += sum over out-edges of dX_s + over in-edges of
-//                 dX_d (the dual of the gather, in a fixed order).
+//   k_bwd<EDGE_AB> recompute a = b1 + AB_s + AB_d + W1_e e^k exactly as the
+//                 forward kernel does, r = relu(a); da = (W2^T dout) * [a > 0];
+//                 dL/de^k = dout + W1_e^T da (residual).
+//   k_gather_pair per hit: S = sum of da over out-edges, D = over in-edges
+//                 (the dual of the gathers, in a fixed order).
+//   k_hit_dual    dL/dh^{k+1} += W1_s^T S + W1_d^T D.
 //   k_bwd<NODE>   the same for the node network; dL/dh^k, dL/dm^k.
 //   k_msg_bwd     dL/de^k += dL/dm_out[src] + dL/dm_in[dst] (the dual of the
 //                 message sums).
@@ -29,7 +33,9 @@ namespace {
 using namespace mfma;
 using P = F32;
 
-enum BMode { B_EDGE = 0, B_NODE = 1, B_EDGE_ENC = 2, B_NODE_ENC = 3, B_CLS = 4 };
+// B_EDGE / B_EDGE_ENC: the concatenated first layer (weight gradients);
+// B_EDGE_AB / B_ENC_AB: the factorised one (recompute and input gradients)
+enum BMode { B_EDGE = 0, B_NODE = 1, B_EDGE_ENC = 2, B_NODE_ENC = 3, B_CLS = 4, B_EDGE_AB = 5, B_ENC_AB = 6 };
 
 constexpr int kBwdBlock = 256;
 constexpr int kChunks = 1024;       // row chunks of the weight-gradient reduction
@@ -42,17 +48,22 @@ struct BwdArgs {
     const float *b;         // EDGE: h^{k+1}; NODE: m^k
     const float *dout;      // dL/d(output) rows [rows x H]; CLS: dL/dlogit [rows]
     float *dres;            // EDGE, NODE: dout + dX(seg 0); CLS: dL/de^n
-    float *dx1, *dx2;       // EDGE, EDGE_ENC: dX of the src/dst hit segment [rows x H];
-                            // NODE: dL/dm [rows x 2H] (dx1 = out, dx2 = in part)
+    float *dx1;             // NODE: dL/dm [rows x 2H]
     float *da, *r;          // hidden gradient and activation [rows x H]
     const float *x, *y, *z; // hit coordinates (NODE_ENC)
+    const float *ab;        // EDGE_AB, ENC_AB: per-hit first-layer products [N x 2H]
     const float *P;
     int64_t o_w1, o_w2;
     const unsigned *flags;
 };
 
+// first-layer input segments multiplied per row, and stored in the weight
 template <int MODE>
-constexpr int bseg() { return MODE == B_EDGE || MODE == B_NODE ? 3 : (MODE == B_EDGE_ENC ? 2 : 1); }
+constexpr int bseg() {
+    return MODE == B_EDGE || MODE == B_NODE ? 3 : (MODE == B_EDGE_ENC ? 2 : (MODE == B_ENC_AB ? 0 : 1));
+}
+template <int MODE>
+constexpr int bkseg() { return MODE == B_EDGE_AB ? 3 : (MODE == B_ENC_AB ? 2 : bseg<MODE>()); }
 
 __device__ inline int64_t row_count(const BwdArgs &A) {
     return A.n_dev ? min((int64_t)*A.n_dev, A.n_host) : A.n_host;
@@ -63,21 +74,22 @@ __device__ inline int64_t row_count(const BwdArgs &A) {
 // ------------------------------------------------------------------------
 template <int H, int MODE>
 __global__ __launch_bounds__(kBwdBlock) void k_bwd(BwdArgs A) {
-    constexpr int MO = H / 16, NSEG = bseg<MODE>(), K1 = NSEG * H;
-    constexpr bool CLS = MODE == B_CLS;
+    constexpr int MO = H / 16, NSEG = bseg<MODE>(), K1 = NSEG * H, K1F = bkseg<MODE>() * H;
+    constexpr bool CLS = MODE == B_CLS, AB = MODE == B_EDGE_AB || MODE == B_ENC_AB;
+    static_assert(MODE != B_EDGE && MODE != B_EDGE_ENC, "the edge MLPs are recomputed in factorised form");
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    f32x4 *sW1 = (f32x4 *)lds_raw;                                  // W1 [H x K1]
+    f32x4 *sW1 = (f32x4 *)lds_raw;                                  // W1 [H x K1] (its first K1 columns)
     f32x4 *sW2T = sW1 + frag_bytes<P>(H, K1) / sizeof(f32x4);       // W2^T [H x H] (not CLS)
     f32x4 *sW1T = sW2T + (CLS ? 0 : frag_bytes<P>(H, H) / sizeof(f32x4));   // W1^T [K1 x H]
-    stage<P>(sW1, A.P + A.o_w1, H, K1, MO);
+    if (NSEG) stage<P>(sW1, A.P + A.o_w1, H, K1, MO, 1.f, K1F);
     if (!CLS) stage<P, true>(sW2T, A.P + A.o_w2, H, H, MO);
-    stage<P, true>(sW1T, A.P + A.o_w1, K1, H, K1 / 16);
+    if (NSEG) stage<P, true>(sW1T, A.P + A.o_w1, K1, H, K1 / 16, 1.f, K1F);
     __syncthreads();
     if (*A.flags) return;
     const int lane = threadIdx.x & 63, n = lane & 15, g = lane >> 4;
     const int64_t N = row_count(A);
     f32x4 rb1[MO], w2[MO];
-    load_bias<MO>(A.P + A.o_w1 + (int64_t)H * K1, rb1, g);
+    load_bias<MO>(A.P + A.o_w1 + (int64_t)H * K1F, rb1, g);
     if (CLS) load_bias<MO>(A.P + A.o_w2, w2, g);     // classifier output weights (1 x H)
     const int64_t units = (N + 15) >> 4;
     const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
@@ -85,14 +97,18 @@ __global__ __launch_bounds__(kBwdBlock) void k_bwd(BwdArgs A) {
         const int64_t q = u * 16 + n;
         const bool ok = q < N;
         const int64_t qc = ok ? q : N - 1;
-        f32x4 X[NSEG * MO];
-        if (MODE == B_EDGE) {
+        f32x4 X[NSEG ? NSEG * MO : 1];
+        f32x4 G[AB ? 2 * MO : 1];
+        if (AB) {
             const int64_t s = A.src_g[qc], d = A.dst_g[qc];
 #pragma unroll
-            for (int kb = 0; kb < MO; kb++) {
-                X[kb] = P::load(A.a + qc * H, kb, g);
-                X[MO + kb] = P::load(A.b + s * H, kb, g);
-                X[2 * MO + kb] = P::load(A.b + d * H, kb, g);
+            for (int mo = 0; mo < MO; mo++) {
+                G[mo] = *(const f32x4 *)(A.ab + s * 2 * H + 16 * mo + 4 * g);
+                G[MO + mo] = *(const f32x4 *)(A.ab + d * 2 * H + H + 16 * mo + 4 * g);
+            }
+            if (MODE == B_EDGE_AB) {
+#pragma unroll
+                for (int kb = 0; kb < MO; kb++) X[kb] = P::load(A.a + qc * H, kb, g);
             }
         } else if (MODE == B_NODE) {
 #pragma unroll
@@ -100,13 +116,6 @@ __global__ __launch_bounds__(kBwdBlock) void k_bwd(BwdArgs A) {
                 X[kb] = P::load(A.a + qc * H, kb, g);
                 X[MO + kb] = P::load(A.b + qc * 2 * H, kb, g);
                 X[2 * MO + kb] = P::load(A.b + qc * 2 * H + H, kb, g);
-            }
-        } else if (MODE == B_EDGE_ENC) {
-            const int64_t s = A.src_g[qc], d = A.dst_g[qc];
-#pragma unroll
-            for (int kb = 0; kb < MO; kb++) {
-                X[kb] = P::load(A.a + s * H, kb, g);
-                X[MO + kb] = P::load(A.a + d * H, kb, g);
             }
         } else {   // B_CLS
 #pragma unroll
@@ -117,7 +126,14 @@ __global__ __launch_bounds__(kBwdBlock) void k_bwd(BwdArgs A) {
         f32x4 r[MO];
 #pragma unroll
         for (int mo = 0; mo < MO; mo++) r[mo] = rb1[mo];
-        gemm<P, MO, NSEG * MO>(sW1, X, r, lane);
+        if (AB) {
+#pragma unroll
+            for (int mo = 0; mo < MO; mo++) {
+                r[mo] += G[mo];
+                r[mo] += G[MO + mo];
+            }
+        }
+        if constexpr (NSEG > 0) gemm<P, MO, NSEG * MO>(sW1, X, r, lane);
         relu<MO>(r);
         // dL/d(hidden) = W2^T dout, masked by the ReLU
         f32x4 da[MO];
@@ -137,26 +153,21 @@ __global__ __launch_bounds__(kBwdBlock) void k_bwd(BwdArgs A) {
             for (int mo = 0; mo < MO; mo++)
 #pragma unroll
                 for (int i = 0; i < 4; i++) da[mo][i] = r[mo][i] > 0.f ? da[mo][i] : 0.f;
-            // dX = W1^T da, then the per-segment outputs
-            f32x4 dX[NSEG * MO];
-            zero<NSEG * MO>(dX);
-            gemm<P, NSEG * MO, MO>(sW1T, da, dX, lane);
-            if (ok) {
-                if (MODE == B_EDGE || MODE == B_NODE) {
+            // dX = W1^T da over the multiplied segments, then the outputs (the
+            // hit segments of the edge MLPs are handled per hit from da)
+            if constexpr (NSEG > 0) {
+                f32x4 dX[NSEG * MO];
+                zero<NSEG * MO>(dX);
+                gemm<P, NSEG * MO, MO>(sW1T, da, dX, lane);
+                if (ok) {
                     // residual path: the output gradient reaches segment 0 unchanged
 #pragma unroll
                     for (int mo = 0; mo < MO; mo++) dX[mo] += dO[mo];
                     P::store_all<MO>(A.dres + q * H, g, dX);
-                }
-                if (MODE == B_EDGE) {
-                    P::store_all<MO>(A.dx1 + q * H, g, dX + MO);
-                    P::store_all<MO>(A.dx2 + q * H, g, dX + 2 * MO);
-                } else if (MODE == B_NODE) {
-                    P::store_all<MO>(A.dx1 + q * 2 * H, g, dX + MO);
-                    P::store_all<MO>(A.dx1 + q * 2 * H + H, g, dX + 2 * MO);
-                } else if (MODE == B_EDGE_ENC) {
-                    P::store_all<MO>(A.dx1 + q * H, g, dX);
-                    P::store_all<MO>(A.dx2 + q * H, g, dX + MO);
+                    if (MODE == B_NODE) {
+                        P::store_all<MO>(A.dx1 + q * 2 * H, g, dX + MO);
+                        P::store_all<MO>(A.dx1 + q * 2 * H + H, g, dX + 2 * MO);
+                    }
                 }
             }
         }
@@ -446,17 +457,16 @@ __global__ void k_dw_reduce(const float *__restrict__ part, int PL, float *__res
 // ------------------------------------------------------------------------
 // duals of the gathers and of the message sums
 // ------------------------------------------------------------------------
-// dh[l] (+)= sum_{l -> j} xs[edge] + sum_{i -> l} xd[edge]; H/4 lanes per hit.
+// sd[l] = [sum_{l -> j} x[edge], sum_{i -> l} x[edge]]; H/4 lanes per hit.
+// Rows are added in edge order; up to BATCH of them are requested before the
+// first is added (incoming ids are read one per lane and passed round the
+// hit's lane group).
 template <int H>
-__global__ __launch_bounds__(256) void k_gather_add(int64_t n_hits, const int *__restrict__ out_ptr,
-                                                    const int *__restrict__ in_ptr,
-                                                    const int *__restrict__ in_list, const float *__restrict__ xs,
-                                                    const float *__restrict__ xd, float *__restrict__ dh,
-                                                    bool accumulate, const unsigned *__restrict__ flags) {
+__global__ __launch_bounds__(256) void k_gather_pair(int64_t n_hits, const int *__restrict__ out_ptr,
+                                                     const int *__restrict__ in_ptr,
+                                                     const int *__restrict__ in_list, const float *__restrict__ x,
+                                                     float *__restrict__ sd, const unsigned *__restrict__ flags) {
     if (*flags) return;
-    // rows are added in edge order; up to BATCH of them are requested before
-    // the first is added (incoming ids are read one per lane and passed round
-    // the hit's lane group)
     constexpr int LPN = H / 4, NPW = 64 / LPN, BATCH = LPN < 8 ? LPN : 8;
     const int lane = threadIdx.x & 63, sub = lane / LPN, l = lane % LPN, c = 4 * l, gbase = sub * LPN;
     const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
@@ -464,17 +474,17 @@ __global__ __launch_bounds__(256) void k_gather_add(int64_t n_hits, const int *_
         const int64_t i0 = base + sub;
         const bool live = i0 < n_hits;
         const int64_t i = live ? i0 : n_hits - 1;
-        f32x4 sum = accumulate ? *(const f32x4 *)(dh + i * H + c) : zero4();
+        f32x4 so = zero4(), si = zero4();
         const int a1 = out_ptr[i + 1];
         for (int a = out_ptr[i]; a < a1; a += BATCH) {
             const int cnt = min(BATCH, a1 - a);
             f32x4 v[BATCH];
 #pragma unroll
             for (int j = 0; j < BATCH; j++)
-                if (j < cnt) v[j] = *(const f32x4 *)(xs + (int64_t)(a + j) * H + c);
+                if (j < cnt) v[j] = *(const f32x4 *)(x + (int64_t)(a + j) * H + c);
 #pragma unroll
             for (int j = 0; j < BATCH; j++)
-                if (j < cnt) sum += v[j];
+                if (j < cnt) so += v[j];
         }
         const int b1 = in_ptr[i + 1];
         for (int b = in_ptr[i]; b < b1; b += BATCH) {   // the group's lanes share the trip count
@@ -484,13 +494,52 @@ __global__ __launch_bounds__(256) void k_gather_add(int64_t n_hits, const int *_
 #pragma unroll
             for (int j = 0; j < BATCH; j++) {
                 const int q = __shfl(mine, gbase + j);
-                if (j < cnt) v[j] = *(const f32x4 *)(xd + (int64_t)q * H + c);
+                if (j < cnt) v[j] = *(const f32x4 *)(x + (int64_t)q * H + c);
             }
 #pragma unroll
             for (int j = 0; j < BATCH; j++)
-                if (j < cnt) sum += v[j];
+                if (j < cnt) si += v[j];
         }
-        if (live) *(f32x4 *)(dh + i * H + c) = sum;
+        if (live) {
+            *(f32x4 *)(sd + i * 2 * H + c) = so;
+            *(f32x4 *)(sd + i * 2 * H + H + c) = si;
+        }
+    }
+}
+
+// The hit segments' input gradients of a factorised edge MLP:
+//   dh[i] += W1[:, cs:cs+H]^T S_i + W1[:, cd:cd+H]^T D_i,   [S_i, D_i] = sd[i]
+// on MFMA, 16 hits per wavefront unit; W1 is row-major [H x k1f].
+template <int H>
+__global__ __launch_bounds__(kBwdBlock) void k_hit_dual(int64_t n_hits, const float *__restrict__ sd,
+                                                        const float *__restrict__ P_, int64_t o_w1, int k1f, int cs,
+                                                        int cd, float *__restrict__ dh,
+                                                        const unsigned *__restrict__ flags) {
+    constexpr int MO = H / 16;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    f32x4 *sTs = (f32x4 *)lds_raw;                              // W1_s^T [H x H]
+    f32x4 *sTd = sTs + frag_bytes<P>(H, H) / sizeof(f32x4);     // W1_d^T [H x H]
+    stage<P, true>(sTs, P_ + o_w1 + cs, H, H, MO, 1.f, k1f);
+    stage<P, true>(sTd, P_ + o_w1 + cd, H, H, MO, 1.f, k1f);
+    __syncthreads();
+    if (*flags) return;
+    const int lane = threadIdx.x & 63, n = lane & 15, g = lane >> 4;
+    const int64_t units = (n_hits + 15) >> 4;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t u = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; u < units; u += nw) {
+        const int64_t i = u * 16 + n;
+        const bool ok = i < n_hits;
+        const int64_t ic = ok ? i : n_hits - 1;
+        f32x4 Xs[MO], Xd[MO], acc[MO];
+#pragma unroll
+        for (int kb = 0; kb < MO; kb++) {
+            Xs[kb] = P::load(sd + ic * 2 * H, kb, g);
+            Xd[kb] = P::load(sd + ic * 2 * H + H, kb, g);
+            acc[kb] = *(const f32x4 *)(dh + ic * H + 16 * kb + 4 * g);
+        }
+        gemm<P, MO, MO>(sTs, Xs, acc, lane);
+        gemm<P, MO, MO>(sTd, Xd, acc, lane);
+        if (ok) P::store_all<MO>(dh + i * H, g, acc);
     }
 }
 
@@ -615,19 +664,38 @@ void backward_h(velo_ctx *c, const velo_hits *hits, const float *Pw, const float
     { StageTimer t(c, VELO_STAGE_BWD_DW, s); run_dw<H, B_CLS>(c, cl, dparams + L.cls[0].w, s); }
     int ce = 0, ch = 0;
     if (N > 0) k_zero<<<blocks_for(N * H, 256, 4096), 256, 0, s>>>(w.g_h[0], N * H);
+    // the hit segments of a factorised edge MLP: per-hit sums of da over out-
+    // and in-edges, then dL/dh += W1_s^T S + W1_d^T D
+    auto hit_duals = [&](int64_t o_w1, int k1f, int cs, int cd, float *dh) {
+        if (N <= 0) return;
+        {
+            StageTimer t(c, VELO_STAGE_BWD_GRAPH, s);
+            k_gather_pair<H><<<persistent_grid(c, 16), 256, 0, s>>>(N, w.row_ptr, w.in_ptr, w.in_list, w.g_da,
+                                                                  w.g_sd, w.flags);
+        }
+        StageTimer t(c, VELO_STAGE_BWD_MLP, s);
+        constexpr size_t lds = 2 * frag_bytes<P>(H, H);
+        static const int per_cu = [] {
+            hipFuncSetAttribute(reinterpret_cast<const void *>(&k_hit_dual<H>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            int m = 0;
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&m, reinterpret_cast<const void *>(&k_hit_dual<H>), kBwdBlock,
+                                                         lds);
+            return m < 1 ? 1 : m;
+        }();
+        k_hit_dual<H><<<persistent_grid(c, per_cu), kBwdBlock, lds, s>>>(N, w.g_sd, Pw, o_w1, k1f, cs, cd, dh,
+                                                                        w.flags);
+    };
+    auto abk = [&](int slot) -> const float * { return w.ck_ab + (int64_t)slot * Nmax * 2 * H; };
     for (int k = n - 1; k >= 0; k--) {
         // edge network k
         BwdArgs ed = base;
         ed.n_dev = w.n_edges; ed.n_host = Ecap; ed.a = ek(k); ed.b = hk(k + 1);
-        ed.dout = w.g_e[ce]; ed.dres = w.g_e[ce ^ 1]; ed.dx1 = w.g_xs; ed.dx2 = w.g_xd;
+        ed.dout = w.g_e[ce]; ed.dres = w.g_e[ce ^ 1]; ed.ab = abk(k);
         ed.o_w1 = L.edge[k][0].w; ed.o_w2 = L.edge[k][1].w;
-        { StageTimer t(c, VELO_STAGE_BWD_MLP, s); run_bwd<H, B_EDGE>(c, ed, s); }
+        { StageTimer t(c, VELO_STAGE_BWD_MLP, s); run_bwd<H, B_EDGE_AB>(c, ed, s); }
         { StageTimer t(c, VELO_STAGE_BWD_DW, s); run_dw<H, B_EDGE>(c, ed, dparams + L.edge[k][0].w, s); }
-        if (N > 0) {
-            StageTimer t(c, VELO_STAGE_BWD_GRAPH, s);
-            k_gather_add<H><<<persistent_grid(c, 16), 256, 0, s>>>(N, w.row_ptr, w.in_ptr, w.in_list,
-                                                                 w.g_xs, w.g_xd, w.g_h[ch], true, w.flags);
-        }
+        hit_duals(L.edge[k][0].w, 3 * H, H, 2 * H, w.g_h[ch]);
         ce ^= 1;
         // node network k
         BwdArgs nd = base;
@@ -648,15 +716,11 @@ void backward_h(velo_ctx *c, const velo_hits *hits, const float *Pw, const float
     }
     // edge encoder
     BwdArgs ee = base;
-    ee.n_dev = w.n_edges; ee.n_host = Ecap; ee.a = hk(0); ee.dout = w.g_e[ce]; ee.dx1 = w.g_xs; ee.dx2 = w.g_xd;
+    ee.n_dev = w.n_edges; ee.n_host = Ecap; ee.a = hk(0); ee.dout = w.g_e[ce]; ee.ab = abk(n);
     ee.o_w1 = L.eenc[0].w; ee.o_w2 = L.eenc[1].w;
-    { StageTimer t(c, VELO_STAGE_BWD_MLP, s); run_bwd<H, B_EDGE_ENC>(c, ee, s); }
+    { StageTimer t(c, VELO_STAGE_BWD_MLP, s); run_bwd<H, B_ENC_AB>(c, ee, s); }
     { StageTimer t(c, VELO_STAGE_BWD_DW, s); run_dw<H, B_EDGE_ENC>(c, ee, dparams + L.eenc[0].w, s); }
-    if (N > 0) {
-        StageTimer t(c, VELO_STAGE_BWD_GRAPH, s);
-        k_gather_add<H><<<persistent_grid(c, 16), 256, 0, s>>>(N, w.row_ptr, w.in_ptr, w.in_list, w.g_xs,
-                                                             w.g_xd, w.g_h[ch], true, w.flags);
-    }
+    hit_duals(L.eenc[0].w, 2 * H, 0, H, w.g_h[ch]);
     // node encoder
     BwdArgs ne = base;
     ne.n_dev = nullptr; ne.n_host = N; ne.dout = w.g_h[ch]; ne.x = hits->x; ne.y = hits->y; ne.z = hits->z;
