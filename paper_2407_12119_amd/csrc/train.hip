@@ -308,7 +308,7 @@ constexpr int kDwRows = 16;
 template <int H, int MODE>
 __global__ __launch_bounds__(kBwdBlock) void k_dw_lds(BwdArgs A, float *__restrict__ part) {
     constexpr int MO = H / 16;
-    constexpr int K1 = bseg<MODE>() * H;
+    constexpr int K1 = bseg<MODE>() * H;   // the factorised edge MLPs: the e segment only (or none)
     constexpr int NB1 = K1 / 16;
     constexpr bool CLS = MODE == B_CLS;
     constexpr int M2 = CLS ? 1 : H;
@@ -333,7 +333,7 @@ __global__ __launch_bounds__(kBwdBlock) void k_dw_lds(BwdArgs A, float *__restri
     static_assert(kBwdBlock == 16 * kDwRows, "one 16-thread group per tile row");
     constexpr int NY = (CY + 15) / 16, NHC = (CH + 15) / 16;
     const int rr = threadIdx.x >> 4, q = threadIdx.x & 15;
-    f32x4 ny[NY], ng1[NHC], nr[NHC], ng2[CLS ? 1 : NHC];
+    f32x4 ny[NY ? NY : 1], ng1[NHC], nr[NHC], ng2[CLS ? 1 : NHC];
     float g2n = 0.f;
     auto fetch_tile = [&](int64_t t0) {
         const int64_t row = t0 + rr;
@@ -344,6 +344,8 @@ __global__ __launch_bounds__(kBwdBlock) void k_dw_lds(BwdArgs A, float *__restri
             seg[0] = A.a + rc * H;
             seg[1] = A.b + (int64_t)A.src_g[rc] * H;
             seg[2] = A.b + (int64_t)A.dst_g[rc] * H;
+        } else if (MODE == B_EDGE_AB || MODE == B_ENC_AB) {
+            seg[0] = seg[1] = seg[2] = A.a + rc * H;
         } else if (MODE == B_NODE) {
             seg[0] = A.a + rc * H;
             seg[1] = A.b + rc * 2 * H;
@@ -372,8 +374,8 @@ __global__ __launch_bounds__(kBwdBlock) void k_dw_lds(BwdArgs A, float *__restri
         }
         if (CLS) g2n = ok ? A.dout[rc] : 0.f;
     };
-    f32x4 acc1[NB1], acc2[MO];
-    zero<NB1>(acc1);
+    f32x4 acc1[NB1 ? NB1 : 1], acc2[MO];
+    zero<NB1 ? NB1 : 1>(acc1);
     zero<MO>(acc2);
     float sb1 = 0.f, sb2 = 0.f;
     if (r0 < r1) fetch_tile(r0);
@@ -443,14 +445,108 @@ __global__ __launch_bounds__(kBwdBlock) void k_dw_lds(BwdArgs A, float *__restri
     }
 }
 
-// Sum the chunk partials in chunk order into the blob-shaped gradient.
-__global__ void k_dw_reduce(const float *__restrict__ part, int PL, float *__restrict__ grad,
-                            const unsigned *__restrict__ flags) {
+// Sum the chunk partials in chunk order into the blob-shaped gradient.  The
+// partial holds the first layer's [rows x K1] block, then the rest of the
+// MLP's parameters; the first layer is stored with row stride ld >= K1 (the
+// factorised edge MLPs fill its first K1 columns here, the rest per hit).
+__global__ void k_dw_reduce(const float *__restrict__ part, int PL, int rows, int K1, int ld,
+                            float *__restrict__ grad, const unsigned *__restrict__ flags) {
     if (*flags) return;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < PL; i += gridDim.x * blockDim.x) {
         float s = 0.f;
         for (int c = 0; c < kChunks; c++) s += part[(int64_t)c * PL + i];
-        grad[i] = s;
+        const int first = rows * K1;
+        grad[i < first ? (i / K1) * ld + i % K1 : rows * ld + (i - first)] = s;
+    }
+}
+
+// Weight gradients of the hit segments of a factorised edge MLP, summed over
+// hits instead of edges:  dW1[:, cs:cs+H] = sum_i S_i h_i^T,
+// dW1[:, cd:cd+H] = sum_i D_i h_i^T  ([S_i, D_i] = sd[i]).  Chunks of hits
+// as in k_dw_lds; partial [2 x H x H] per chunk.
+template <int H>
+__global__ __launch_bounds__(kBwdBlock) void k_dw_hits(int64_t n_hits, const float *__restrict__ h,
+                                                       const float *__restrict__ sd, float *__restrict__ part,
+                                                       const unsigned *__restrict__ flags) {
+    constexpr int MO = H / 16, CH = H / 4, SH = H + 16;
+    static_assert(kBwdBlock == 16 * kDwRows && CH <= 16 * 2, "tile loads");
+    __shared__ __align__(16) float sY[kDwRows * SH];
+    __shared__ __align__(16) float sS[kDwRows * SH];
+    __shared__ __align__(16) float sD[kDwRows * SH];
+    if (*flags) return;
+    const int lane = threadIdx.x & 63, n = lane & 15, g = lane >> 4, w = threadIdx.x >> 6;
+    const int64_t per = (((n_hits + kChunks - 1) / kChunks) + 3) & ~(int64_t)3;
+    const int64_t r0 = (int64_t)blockIdx.x * per, r1 = min(r0 + per, n_hits);
+    float *out = part + (int64_t)blockIdx.x * 2 * H * H;
+    const bool active = w < MO;
+    const int m = active ? w : 0;
+    constexpr int NHC = (CH + 15) / 16;
+    const int rr = threadIdx.x >> 4, q = threadIdx.x & 15;
+    f32x4 ny[NHC], ns[NHC], nd[NHC];
+    auto fetch_tile = [&](int64_t t0) {
+        const int64_t row = t0 + rr;
+        const bool ok = row < r1;
+        const int64_t rc = ok ? row : r0;
+#pragma unroll
+        for (int y = 0; y < NHC; y++) {
+            const int j = q + 16 * y;
+            const bool v = ok && j < CH;
+            ny[y] = v ? *(const f32x4 *)(h + rc * H + 4 * j) : zero4();
+            ns[y] = v ? *(const f32x4 *)(sd + rc * 2 * H + 4 * j) : zero4();
+            nd[y] = v ? *(const f32x4 *)(sd + rc * 2 * H + H + 4 * j) : zero4();
+        }
+    };
+    f32x4 as[MO], ad[MO];
+    zero<MO>(as);
+    zero<MO>(ad);
+    if (r0 < r1) fetch_tile(r0);
+    for (int64_t t0 = r0; t0 < r1; t0 += kDwRows) {
+        __syncthreads();
+#pragma unroll
+        for (int y = 0; y < NHC; y++) {
+            const int j = q + 16 * y;
+            if (j < CH) {
+                *(f32x4 *)(sY + rr * SH + 4 * j) = ny[y];
+                *(f32x4 *)(sS + rr * SH + 4 * j) = ns[y];
+                *(f32x4 *)(sD + rr * SH + 4 * j) = nd[y];
+            }
+        }
+        __syncthreads();
+        if (t0 + kDwRows < r1) fetch_tile(t0 + kDwRows);
+        if (!active) continue;
+#pragma unroll 1
+        for (int ks = 0; ks < kDwRows / 4; ks++) {
+            const int kr = 4 * ks + g;
+            const float gs = sS[kr * SH + 16 * m + n], gd = sD[kr * SH + 16 * m + n];
+#pragma unroll
+            for (int nb = 0; nb < MO; nb++) {
+                const float y = sY[kr * SH + 16 * nb + n];
+                as[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(gs, y, as[nb], 0, 0, 0);
+                ad[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(gd, y, ad[nb], 0, 0, 0);
+            }
+        }
+    }
+    if (!active) return;
+#pragma unroll
+    for (int nb = 0; nb < MO; nb++)
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            out[(16 * m + 4 * g + i) * H + 16 * nb + n] = as[nb][i];
+            out[H * H + (16 * m + 4 * g + i) * H + 16 * nb + n] = ad[nb][i];
+        }
+}
+
+// chunk-ordered sum of k_dw_hits partials into the two column blocks of W1
+__global__ void k_dw_hits_reduce(const float *__restrict__ part, int H, int ld, int cs, int cd,
+                                 float *__restrict__ grad, const unsigned *__restrict__ flags) {
+    if (*flags) return;
+    const int PL = 2 * H * H;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < PL; i += gridDim.x * blockDim.x) {
+        float s = 0.f;
+        if (part)
+            for (int c = 0; c < kChunks; c++) s += part[(int64_t)c * PL + i];
+        const int b = i / (H * H), r = (i % (H * H)) / H, col = i % H;
+        grad[r * ld + (b ? cd : cs) + col] = s;
     }
 }
 
@@ -630,13 +726,14 @@ void run_bwd(velo_ctx *c, const BwdArgs &a, hipStream_t s) {
 template <int H, int MODE>
 void run_dw(velo_ctx *c, const BwdArgs &a, float *grad_dst, hipStream_t s) {
     constexpr int K1 = MODE == B_NODE_ENC ? 3 : bseg<MODE>() * H;
+    constexpr int LD = MODE == B_NODE_ENC ? 3 : bkseg<MODE>() * H;
     constexpr int M2 = MODE == B_CLS ? 1 : H;
     constexpr int PL = H * K1 + H + M2 * H + M2;
     if constexpr (MODE == B_NODE_ENC)
         k_dw<H, MODE><<<kChunks, kBwdBlock, 0, s>>>(a, c->ws.g_part);
     else
         k_dw_lds<H, MODE><<<kChunks, kBwdBlock, 0, s>>>(a, c->ws.g_part);
-    k_dw_reduce<<<blocks_for(PL, 256, 1024), 256, 0, s>>>(c->ws.g_part, PL, grad_dst, c->ws.flags);
+    k_dw_reduce<<<blocks_for(PL, 256, 1024), 256, 0, s>>>(c->ws.g_part, PL, H, K1, LD, grad_dst, c->ws.flags);
 }
 
 template <int H>
@@ -665,26 +762,37 @@ void backward_h(velo_ctx *c, const velo_hits *hits, const float *Pw, const float
     int ce = 0, ch = 0;
     if (N > 0) k_zero<<<blocks_for(N * H, 256, 4096), 256, 0, s>>>(w.g_h[0], N * H);
     // the hit segments of a factorised edge MLP: per-hit sums of da over out-
-    // and in-edges, then dL/dh += W1_s^T S + W1_d^T D
-    auto hit_duals = [&](int64_t o_w1, int k1f, int cs, int cd, float *dh) {
-        if (N <= 0) return;
+    // and in-edges, then dL/dh += W1_s^T S + W1_d^T D and the two column
+    // blocks of dL/dW1 as sums over hits of S h^T and D h^T
+    auto hit_duals = [&](int64_t o_w1, int k1f, int cs, int cd, float *dh, const float *h, float *grad) {
+        if (N <= 0) {   // no hits, no edges: the hit blocks of dW1 are zero
+            k_dw_hits_reduce<<<blocks_for(2 * H * H, 256, 64), 256, 0, s>>>(nullptr, H, k1f, cs, cd,
+                                                                             grad + o_w1, w.flags);
+            return;
+        }
         {
             StageTimer t(c, VELO_STAGE_BWD_GRAPH, s);
             k_gather_pair<H><<<persistent_grid(c, 16), 256, 0, s>>>(N, w.row_ptr, w.in_ptr, w.in_list, w.g_da,
                                                                   w.g_sd, w.flags);
         }
-        StageTimer t(c, VELO_STAGE_BWD_MLP, s);
-        constexpr size_t lds = 2 * frag_bytes<P>(H, H);
-        static const int per_cu = [] {
-            hipFuncSetAttribute(reinterpret_cast<const void *>(&k_hit_dual<H>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-            int m = 0;
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&m, reinterpret_cast<const void *>(&k_hit_dual<H>), kBwdBlock,
-                                                         lds);
-            return m < 1 ? 1 : m;
-        }();
-        k_hit_dual<H><<<persistent_grid(c, per_cu), kBwdBlock, lds, s>>>(N, w.g_sd, Pw, o_w1, k1f, cs, cd, dh,
-                                                                        w.flags);
+        {
+            StageTimer t(c, VELO_STAGE_BWD_MLP, s);
+            constexpr size_t lds = 2 * frag_bytes<P>(H, H);
+            static const int per_cu = [] {
+                hipFuncSetAttribute(reinterpret_cast<const void *>(&k_hit_dual<H>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+                int m = 0;
+                hipOccupancyMaxActiveBlocksPerMultiprocessor(&m, reinterpret_cast<const void *>(&k_hit_dual<H>),
+                                                             kBwdBlock, lds);
+                return m < 1 ? 1 : m;
+            }();
+            k_hit_dual<H><<<persistent_grid(c, per_cu), kBwdBlock, lds, s>>>(N, w.g_sd, Pw, o_w1, k1f, cs, cd, dh,
+                                                                            w.flags);
+        }
+        StageTimer t(c, VELO_STAGE_BWD_DW, s);
+        k_dw_hits<H><<<kChunks, kBwdBlock, 0, s>>>(N, h, w.g_sd, w.g_part, w.flags);
+        k_dw_hits_reduce<<<blocks_for(2 * H * H, 256, 1024), 256, 0, s>>>(w.g_part, H, k1f, cs, cd, grad + o_w1,
+                                                                          w.flags);
     };
     auto abk = [&](int slot) -> const float * { return w.ck_ab + (int64_t)slot * Nmax * 2 * H; };
     for (int k = n - 1; k >= 0; k--) {
@@ -694,8 +802,8 @@ void backward_h(velo_ctx *c, const velo_hits *hits, const float *Pw, const float
         ed.dout = w.g_e[ce]; ed.dres = w.g_e[ce ^ 1]; ed.ab = abk(k);
         ed.o_w1 = L.edge[k][0].w; ed.o_w2 = L.edge[k][1].w;
         { StageTimer t(c, VELO_STAGE_BWD_MLP, s); run_bwd<H, B_EDGE_AB>(c, ed, s); }
-        { StageTimer t(c, VELO_STAGE_BWD_DW, s); run_dw<H, B_EDGE>(c, ed, dparams + L.edge[k][0].w, s); }
-        hit_duals(L.edge[k][0].w, 3 * H, H, 2 * H, w.g_h[ch]);
+        { StageTimer t(c, VELO_STAGE_BWD_DW, s); run_dw<H, B_EDGE_AB>(c, ed, dparams + L.edge[k][0].w, s); }
+        hit_duals(L.edge[k][0].w, 3 * H, H, 2 * H, w.g_h[ch], hk(k + 1), dparams);
         ce ^= 1;
         // node network k
         BwdArgs nd = base;
@@ -719,8 +827,8 @@ void backward_h(velo_ctx *c, const velo_hits *hits, const float *Pw, const float
     ee.n_dev = w.n_edges; ee.n_host = Ecap; ee.a = hk(0); ee.dout = w.g_e[ce]; ee.ab = abk(n);
     ee.o_w1 = L.eenc[0].w; ee.o_w2 = L.eenc[1].w;
     { StageTimer t(c, VELO_STAGE_BWD_MLP, s); run_bwd<H, B_ENC_AB>(c, ee, s); }
-    { StageTimer t(c, VELO_STAGE_BWD_DW, s); run_dw<H, B_EDGE_ENC>(c, ee, dparams + L.eenc[0].w, s); }
-    hit_duals(L.eenc[0].w, 2 * H, 0, H, w.g_h[ch]);
+    { StageTimer t(c, VELO_STAGE_BWD_DW, s); run_dw<H, B_ENC_AB>(c, ee, dparams + L.eenc[0].w, s); }
+    hit_duals(L.eenc[0].w, 2 * H, 0, H, w.g_h[ch], hk(0), dparams);
     // node encoder
     BwdArgs ne = base;
     ne.n_dev = nullptr; ne.n_host = N; ne.dout = w.g_h[ch]; ne.x = hits->x; ne.y = hits->y; ne.z = hits->z;
