@@ -46,9 +46,9 @@ def _small_batch():
 
 
 def test_train_forward_equals_inference():
-    """The training forward (concatenated first layers, checkpoints) gives the
-    inference logits up to float32 summation order (inference forms the hit
-    segments' first-layer products once per hit), and is bitwise repeatable."""
+    """The training forward (with checkpoints; the classifier as its own
+    kernel) gives the inference logits to float32 rounding and is bitwise
+    repeatable."""
     wl, batch = _small_batch()
     blob = synth.centred_params(wl)
     ctx, hits, graph, params = _setup(wl, batch, blob)
