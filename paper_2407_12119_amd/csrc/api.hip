@@ -61,7 +61,7 @@ void free_ws(Workspace &w) {
     void *ptrs[] = {w.emb, w.hit_event, w.plane_off, w.deg, w.row_ptr, w.nbr, w.src_g, w.dst_g,
                     w.in_ptr, w.in_list, w.scan_tmp, w.h[0], w.h[1],
                     w.m, w.ab, w.e, w.n_edges, w.flags, w.eoff_tmp, w.ck_h, w.ck_e, w.ck_m, w.ck_ab, w.g_sd, w.g_e[0], w.g_e[1],
-                    w.g_h[0], w.g_h[1], w.g_da, w.g_r, w.g_m, w.g_part, w.g_loss,
+                    w.g_h[0], w.g_h[1], w.g_da, w.g_r, w.g_m, w.g_part, w.g_red, w.g_loss,
                     w.scales, w.amax, w.tmp_logit};
     for (void *p : ptrs)
         if (p) hipFree(p);
@@ -188,6 +188,7 @@ velo_status velo_create(const velo_config *cfg, velo_ctx **out) {
              dalloc(&w.g_e[1], E * H) && dalloc(&w.g_h[0], N * H) && dalloc(&w.g_h[1], N * H) &&
              dalloc(&w.g_da, R * H) && dalloc(&w.g_r, R * H) &&
              dalloc(&w.g_m, N * 2 * H) && dalloc(&w.g_part, (int64_t)train_part_floats(k.gnn_hidden)) &&
+             dalloc(&w.g_red, (int64_t)train_red_floats(k.gnn_hidden)) &&
              dalloc(&w.g_loss, 256);
     }
     if (!ok) {

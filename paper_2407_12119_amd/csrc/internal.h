@@ -67,6 +67,7 @@ struct Workspace {
     float *g_da = nullptr, *g_r = nullptr;   // [max(E,N) x H] hidden gradient / activation
     float *g_m = nullptr;        // [max_hits x 2H] dL/dm
     float *g_part = nullptr;     // [n_chunks x part_len] weight-gradient partial sums
+    float *g_red = nullptr;      // [32 x part_len] group sums of the partials
     float *g_loss = nullptr;     // [n_chunks] loss partial sums
 };
 
@@ -136,6 +137,7 @@ void launch_act_scales(velo_ctx *c, hipStream_t s);
 // ---- launchers (train.hip) ----
 bool train_supported(int hidden, int precision);
 size_t train_part_floats(int H);
+size_t train_red_floats(int H);
 void launch_adam(float *p, const float *g, float *m, float *v, int64_t n, float lr, float b1, float b2, float eps,
                  int step, hipStream_t s);
 void launch_bce(velo_ctx *c, const float *logit, const uint8_t *y, float pos_weight, int64_t n, float *loss,

@@ -18,11 +18,13 @@
 //                 (the dual of the gathers, in a fixed order).
 //   k_hit_dual    dL/dh^{k+1} += W1_s^T S + W1_d^T D.
 //   k_bwd<NODE>   the same for the node network; dL/dh^k, dL/dm^k.
-//   k_msg_bwd     dL/de^k += dL/dm_out[src] + dL/dm_in[dst] (the dual of the
-//                 message sums).
-//   k_dw          weight and bias gradients, dW = G^T Y summed over rows, on
+//   The dual of step k's message sums, dL/de^k += dL/dm_out[src] +
+//   dL/dm_in[dst], is added where dL/de^k is read: in the backward kernel of
+//   edge network k-1 (or of the edge encoder), which writes the sum back.
+//   k_dw_lds      weight and bias gradients, dW = G^T Y summed over rows, on
 //                 MFMA with the row dimension as K, split over chunks of rows;
-//                 k_dw_reduce adds the chunk partials in a fixed order.
+//                 k_chunk_groups and k_dw_reduce add the chunk partials in a
+//                 fixed order (groups of chunks, then the groups).
 // No floating-point atomics: gradients are bitwise reproducible.
 #include "mfma.h"
 
@@ -39,6 +41,7 @@ enum BMode { B_EDGE = 0, B_NODE = 1, B_EDGE_ENC = 2, B_NODE_ENC = 3, B_CLS = 4, 
 
 constexpr int kBwdBlock = 256;
 constexpr int kChunks = 1024;       // row chunks of the weight-gradient reduction
+constexpr int kRedGroups = 32;      // the chunk partials are summed in 32 groups of 32, then the groups
 
 struct BwdArgs {
     const int *n_dev;       // device row count (edges) or null
@@ -52,6 +55,8 @@ struct BwdArgs {
     float *da, *r;          // hidden gradient and activation [rows x H]
     const float *x, *y, *z; // hit coordinates (NODE_ENC)
     const float *ab;        // EDGE_AB, ENC_AB: per-hit first-layer products [N x 2H]
+    const float *dm;        // EDGE_AB, ENC_AB: dL/dm of the step this edge state fed, or null
+    float *dout_w;          // with dm: where dout + the message duals are written (dout's rows)
     const float *P;
     int64_t o_w1, o_w2;
     const unsigned *flags;
@@ -147,6 +152,18 @@ __global__ __launch_bounds__(kBwdBlock) void k_bwd(BwdArgs A) {
             f32x4 dO[MO];
 #pragma unroll
             for (int kb = 0; kb < MO; kb++) dO[kb] = ok ? P::load(A.dout + q * H, kb, g) : zero4();
+            if (A.dm) {
+                // the dual of the message sums of this edge state (it fed step
+                // k+1's messages): dL/de += dL/dm_out[src] + dL/dm_in[dst];
+                // the completed gradient is written back for the weight pass
+                const int64_t s = A.src_g[qc], d = A.dst_g[qc];
+#pragma unroll
+                for (int kb = 0; kb < MO; kb++) {
+                    dO[kb] += P::load(A.dm + s * 2 * H, kb, g);
+                    dO[kb] += P::load(A.dm + d * 2 * H + H, kb, g);
+                }
+                if (ok) P::store_all<MO>(A.dout_w + q * H, g, dO);
+            }
             zero<MO>(da);
             gemm<P, MO, MO>(sW2T, dO, da, lane);
 #pragma unroll
@@ -445,16 +462,32 @@ __global__ __launch_bounds__(kBwdBlock) void k_dw_lds(BwdArgs A, float *__restri
     }
 }
 
-// Sum the chunk partials in chunk order into the blob-shaped gradient.  The
-// partial holds the first layer's [rows x K1] block, then the rest of the
-// MLP's parameters; the first layer is stored with row stride ld >= K1 (the
-// factorised edge MLPs fill its first K1 columns here, the rest per hit).
-__global__ void k_dw_reduce(const float *__restrict__ part, int PL, int rows, int K1, int ld,
+// First reduction level: red[g][i] = sum of the partials of chunks
+// g*G .. g*G+G-1 in chunk order (G = kChunks / kRedGroups), one group per
+// blockIdx.y, so the kChunks-long sums run kRedGroups-wide in parallel.
+__global__ void k_chunk_groups(const float *__restrict__ part, int PL, float *__restrict__ red,
+                               const unsigned *__restrict__ flags) {
+    if (*flags) return;
+    constexpr int G = kChunks / kRedGroups;
+    const int grp = blockIdx.y;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < PL; i += gridDim.x * blockDim.x) {
+        float s = 0.f;
+        for (int c = grp * G; c < grp * G + G; c++) s += part[(int64_t)c * PL + i];
+        red[(int64_t)grp * PL + i] = s;
+    }
+}
+
+// Second level: the group sums in group order into the blob-shaped
+// gradient.  The partial holds the first layer's [rows x K1] block, then
+// the rest of the MLP's parameters; the first layer is stored with row
+// stride ld >= K1 (the factorised edge MLPs fill its first K1 columns here,
+// the rest per hit).
+__global__ void k_dw_reduce(const float *__restrict__ red, int PL, int rows, int K1, int ld,
                             float *__restrict__ grad, const unsigned *__restrict__ flags) {
     if (*flags) return;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < PL; i += gridDim.x * blockDim.x) {
         float s = 0.f;
-        for (int c = 0; c < kChunks; c++) s += part[(int64_t)c * PL + i];
+        for (int g = 0; g < kRedGroups; g++) s += red[(int64_t)g * PL + i];
         const int first = rows * K1;
         grad[i < first ? (i / K1) * ld + i % K1 : rows * ld + (i - first)] = s;
     }
@@ -536,15 +569,16 @@ __global__ __launch_bounds__(kBwdBlock) void k_dw_hits(int64_t n_hits, const flo
         }
 }
 
-// chunk-ordered sum of k_dw_hits partials into the two column blocks of W1
-__global__ void k_dw_hits_reduce(const float *__restrict__ part, int H, int ld, int cs, int cd,
+// group sums of k_dw_hits partials (in group order) into the two column
+// blocks of W1; red == null: zero (no hits)
+__global__ void k_dw_hits_reduce(const float *__restrict__ red, int H, int ld, int cs, int cd,
                                  float *__restrict__ grad, const unsigned *__restrict__ flags) {
     if (*flags) return;
     const int PL = 2 * H * H;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < PL; i += gridDim.x * blockDim.x) {
         float s = 0.f;
-        if (part)
-            for (int c = 0; c < kChunks; c++) s += part[(int64_t)c * PL + i];
+        if (red)
+            for (int g = 0; g < kRedGroups; g++) s += red[(int64_t)g * PL + i];
         const int b = i / (H * H), r = (i % (H * H)) / H, col = i % H;
         grad[r * ld + (b ? cd : cs) + col] = s;
     }
@@ -639,26 +673,6 @@ __global__ __launch_bounds__(kBwdBlock) void k_hit_dual(int64_t n_hits, const fl
     }
 }
 
-// de[q] += dm[src q][0:H] + dm[dst q][H:2H]
-template <int H>
-__global__ __launch_bounds__(256) void k_msg_bwd(const int *__restrict__ n_edges, int64_t cap,
-                                                 const int *__restrict__ src_g, const int *__restrict__ dst_g,
-                                                 const float *__restrict__ dm, float *__restrict__ de,
-                                                 const unsigned *__restrict__ flags) {
-    if (*flags) return;
-    constexpr int LPN = H / 4;
-    const int64_t E = min((int64_t)*n_edges, cap);
-    const int64_t total = E * LPN;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t q = t / LPN;
-        const int c = 4 * (int)(t - q * LPN);
-        f32x4 v = *(const f32x4 *)(de + q * H + c);
-        v += *(const f32x4 *)(dm + (int64_t)src_g[q] * 2 * H + c);
-        v += *(const f32x4 *)(dm + (int64_t)dst_g[q] * 2 * H + H + c);
-        *(f32x4 *)(de + q * H + c) = v;
-    }
-}
-
 __global__ void k_zero(float *__restrict__ p, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = 0.f;
@@ -733,7 +747,9 @@ void run_dw(velo_ctx *c, const BwdArgs &a, float *grad_dst, hipStream_t s) {
         k_dw<H, MODE><<<kChunks, kBwdBlock, 0, s>>>(a, c->ws.g_part);
     else
         k_dw_lds<H, MODE><<<kChunks, kBwdBlock, 0, s>>>(a, c->ws.g_part);
-    k_dw_reduce<<<blocks_for(PL, 256, 1024), 256, 0, s>>>(c->ws.g_part, PL, H, K1, LD, grad_dst, c->ws.flags);
+    k_chunk_groups<<<dim3(blocks_for(PL, 256, 1024), kRedGroups), 256, 0, s>>>(c->ws.g_part, PL, c->ws.g_red,
+                                                                              c->ws.flags);
+    k_dw_reduce<<<blocks_for(PL, 256, 1024), 256, 0, s>>>(c->ws.g_red, PL, H, K1, LD, grad_dst, c->ws.flags);
 }
 
 template <int H>
@@ -746,7 +762,6 @@ void backward_h(velo_ctx *c, const velo_hits *hits, const float *Pw, const float
     const float *ck_h = (const float *)w.ck_h, *ck_e = (const float *)w.ck_e;
     auto hk = [&](int k) { return ck_h + (int64_t)k * Nmax * H; };
     auto ek = [&](int k) { return ck_e + (int64_t)k * Ecap * H; };
-    const int eb = persistent_grid(c, 8);
     // parameters without gradient (normalisation, embedding) are zero
     k_zero<<<blocks_for(L.nenc[0].w, 256, 1024), 256, 0, s>>>(dparams, L.nenc[0].w);
 
@@ -791,7 +806,9 @@ void backward_h(velo_ctx *c, const velo_hits *hits, const float *Pw, const float
         }
         StageTimer t(c, VELO_STAGE_BWD_DW, s);
         k_dw_hits<H><<<kChunks, kBwdBlock, 0, s>>>(N, h, w.g_sd, w.g_part, w.flags);
-        k_dw_hits_reduce<<<blocks_for(2 * H * H, 256, 1024), 256, 0, s>>>(w.g_part, H, k1f, cs, cd, grad + o_w1,
+        k_chunk_groups<<<dim3(blocks_for(2 * H * H, 256, 1024), kRedGroups), 256, 0, s>>>(w.g_part, 2 * H * H,
+                                                                                         w.g_red, w.flags);
+        k_dw_hits_reduce<<<blocks_for(2 * H * H, 256, 1024), 256, 0, s>>>(w.g_red, H, k1f, cs, cd, grad + o_w1,
                                                                           w.flags);
     };
     auto abk = [&](int slot) -> const float * { return w.ck_ab + (int64_t)slot * Nmax * 2 * H; };
@@ -800,6 +817,7 @@ void backward_h(velo_ctx *c, const velo_hits *hits, const float *Pw, const float
         BwdArgs ed = base;
         ed.n_dev = w.n_edges; ed.n_host = Ecap; ed.a = ek(k); ed.b = hk(k + 1);
         ed.dout = w.g_e[ce]; ed.dres = w.g_e[ce ^ 1]; ed.ab = abk(k);
+        ed.dm = k < n - 1 ? w.g_m : nullptr; ed.dout_w = w.g_e[ce];   // dL/dm^{k+1} from node network k+1
         ed.o_w1 = L.edge[k][0].w; ed.o_w2 = L.edge[k][1].w;
         { StageTimer t(c, VELO_STAGE_BWD_MLP, s); run_bwd<H, B_EDGE_AB>(c, ed, s); }
         { StageTimer t(c, VELO_STAGE_BWD_DW, s); run_dw<H, B_EDGE_AB>(c, ed, dparams + L.edge[k][0].w, s); }
@@ -816,15 +834,13 @@ void backward_h(velo_ctx *c, const velo_hits *hits, const float *Pw, const float
         }
         { StageTimer t(c, VELO_STAGE_BWD_DW, s); run_dw<H, B_NODE>(c, nd, dparams + L.node[k][0].w, s); }
         ch ^= 1;
-        // message sums of step k
-        if (N > 0) {
-            StageTimer t(c, VELO_STAGE_BWD_GRAPH, s);
-            k_msg_bwd<H><<<eb, 256, 0, s>>>(w.n_edges, Ecap, w.src_g, w.dst_g, w.g_m, w.g_e[ce], w.flags);
-        }
+        // the message sums of step k: their dual is added by the next edge
+        // MLP's backward kernel (edge network k-1, or the edge encoder)
     }
     // edge encoder
     BwdArgs ee = base;
     ee.n_dev = w.n_edges; ee.n_host = Ecap; ee.a = hk(0); ee.dout = w.g_e[ce]; ee.ab = abk(n);
+    ee.dm = n > 0 ? w.g_m : nullptr; ee.dout_w = w.g_e[ce];   // dL/dm^0 from node network 0
     ee.o_w1 = L.eenc[0].w; ee.o_w2 = L.eenc[1].w;
     { StageTimer t(c, VELO_STAGE_BWD_MLP, s); run_bwd<H, B_ENC_AB>(c, ee, s); }
     { StageTimer t(c, VELO_STAGE_BWD_DW, s); run_dw<H, B_ENC_AB>(c, ee, dparams + L.eenc[0].w, s); }
@@ -868,6 +884,8 @@ size_t train_part_floats(int H) {
     // the largest blob-shaped partial: an edge or node network, [H x 3H | H | H x H | H]
     return (size_t)kChunks * (3 * H * H + H + H * H + H);
 }
+
+size_t train_red_floats(int H) { return (size_t)kRedGroups * (3 * H * H + H + H * H + H); }
 
 void launch_bce(velo_ctx *c, const float *logit, const uint8_t *y, float pos_weight, int64_t n, float *loss,
                 float *dlogit, hipStream_t s) {
