@@ -226,3 +226,27 @@ def test_fp8_end_to_end_batch_invariance_and_determinism():
     jac = len(A & B) / max(len(A | B), 1)
     print(f"  fp8 edge-set Jaccard vs float64 oracle {jac:.4f}", flush=True)
     assert jac > 0.8
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_hidden_width_32_on_a_given_graph(precision):
+    """H = 32, the smallest width the library takes (fp32 in the factorised
+    first-layer form, bf16 in the concatenated one), on the fp32 path's rough
+    graph of one event against the oracle."""
+    wl = synth.dataclasses.replace(synth.WORKLOADS["single_event"], hidden=32, iters=2)
+    batch = synth.make_batch(synth.WORKLOADS["single_event"])
+    blob = synth.init_params(wl)
+    c32, hits = _setup(wl, batch, "fp32", blob)
+    g = c32.infer(hits)
+    ctx, h2 = (c32, hits) if precision == "fp32" else _setup(wl, batch, precision, blob)
+    ctx.gnn(h2, g)
+    gh = velo.graph_to_host(g, batch.n_hits)
+    ev = batch.event(0)
+    z = oracle.gnn_forward(ev.x, ev.y, ev.z, gh["src"], gh["dst"], blob, wl.hidden, wl.iters)
+    err = np.abs(gh["logit"] - z)
+    if precision == "fp32":
+        assert np.all(err <= 1e-4 * np.maximum(np.abs(z), 1.0)), err.max()
+    else:
+        la, lr = logit_bound(wl.iters)
+        assert np.all(err <= la + lr * np.abs(z)), err.max()
+    print(f"  {len(z)} edges, max |dz| {err.max():.3g}", flush=True)

@@ -77,7 +77,16 @@ def test_bce_matches_oracle():
 
 def test_backward_matches_oracle_gradient():
     wl, batch = _small_batch()
-    blob = synth.centred_params(wl)
+    _check_gradient(wl, batch, synth.centred_params(wl))
+
+
+def test_backward_matches_oracle_gradient_at_width_32():
+    """H = 32 (the other width the training form takes), two steps."""
+    wl = synth.dataclasses.replace(synth.WORKLOADS["train32"], hidden=32, iters=2)
+    _check_gradient(wl, synth.make_batch(synth.WORKLOADS["single_event"]), synth.init_params(wl))
+
+
+def _check_gradient(wl, batch, blob):
     ctx, hits, graph, params = _setup(wl, batch, blob)
     ctx.train_forward(hits, graph, params, check=True)
     g = velo.graph_to_host(graph, batch.n_hits)
