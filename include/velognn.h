@@ -183,9 +183,10 @@ typedef enum {
     VELO_STAGE_EDGE_CLS = 10,  /* last step's edge network fused with the edge classifier */
     VELO_STAGE_COMPONENTS = 11,/* edge cut and connected components (Sec. 7.3) */
     VELO_STAGE_BCE = 12,       /* training: weighted BCE and dL/dz */
-    VELO_STAGE_BWD_MLP = 13,   /* training: recompute and back-propagate every MLP (dX) */
+    VELO_STAGE_BWD_MLP = 13,   /* training: recompute and back-propagate every MLP (dX, with the
+                                  message sums' dual) */
     VELO_STAGE_BWD_DW = 14,    /* training: split-K weight gradients and their reduction */
-    VELO_STAGE_BWD_GRAPH = 15, /* training: duals of the gathers and message sums */
+    VELO_STAGE_BWD_GRAPH = 15, /* training: per-hit sums of dL/d(hidden) of the edge MLPs */
     VELO_STAGE_ADAM = 16,      /* training: Adam update */
     VELO_STAGE_HIT_PROJ = 17,  /* fp32 inference: per-hit first-layer products of the edge MLPs */
     VELO_N_STAGES = 18
@@ -226,8 +227,9 @@ void velo_graph_destroy(velo_graph *graph);
  * (edges grouped by event and by source within it, event-local indices,
  * n_edges; other orders are rejected with VELO_ERR_INPUT), but with the
  * caller's float32 parameter blob `params` (device, velo_param_count entries)
- * and keeping the step-boundary hit/edge encodings and messages in the
- * context for velo_train_backward.  Writes graph->edge_logit. */
+ * and keeping the step-boundary hit/edge encodings, the messages and the
+ * per-hit first-layer products of the edge MLPs in the context for
+ * velo_train_backward.  Writes graph->edge_logit. */
 velo_status velo_train_forward(velo_ctx *ctx, const velo_hits *hits, velo_outputs *graph, const float *params,
                                void *stream);
 
