@@ -116,45 +116,87 @@ __global__ __launch_bounds__(256) void k_knn(int64_t n_hits, const int *__restri
 
         unsigned key[kKeyChunks];
         int m = 0;
+        unsigned kmin = kInvalidKey, khi = 0;   // smallest and largest valid key (lane-local)
 #pragma unroll
         for (int c = 0; c < kKeyChunks; c++) {
             key[c] = kInvalidKey;
             if (c < nch) {
                 key[c] = cand_key(emb, base, C, c * 64 + lane, q, d2max);
-                m += __popcll(ballot(key[c] != kInvalidKey));
+                const bool v = key[c] != kInvalidKey;
+                m += __popcll(ballot(v));
+                if (v) {
+                    kmin = min(kmin, key[c]);
+                    khi = max(khi, key[c]);
+                }
             }
         }
-        for (int c = kKeyChunks; c < nch; c++)
-            m += __popcll(ballot(cand_key(emb, base, C, c * 64 + lane, q, d2max) != kInvalidKey));
+        for (int c = kKeyChunks; c < nch; c++) {
+            const unsigned k = cand_key(emb, base, C, c * 64 + lane, q, d2max);
+            const bool v = k != kInvalidKey;
+            m += __popcll(ballot(v));
+            if (v) {
+                kmin = min(kmin, k);
+                khi = max(khi, k);
+            }
+        }
+        // number of keys below x over all chunks (uniform over the wavefront)
+        auto count_below = [&](unsigned x) {
+            int cnt = 0;
+#pragma unroll
+            for (int c = 0; c < kKeyChunks; c++)
+                if (c < nch) cnt += __popcll(ballot(key[c] < x));
+            for (int c = kKeyChunks; c < nch; c++)
+                cnt += __popcll(ballot(cand_key(emb, base, C, c * 64 + lane, q, d2max) < x));
+            return cnt;
+        };
 
         // threshold T: the kmax-th smallest key (only needed when m > kmax).
-        // A probe with exactly kmax keys below it ends the search: those
-        // keys are the kmax smallest and none ties with a dropped one.
+        // Search on the key bit pattern (monotone in the non-negative float
+        // d2) between the smallest and largest valid key, keeping
+        // cnt(< lo) < kmax < cnt(< hi): probes alternate between linear
+        // interpolation of the counts (few probes on smooth key sets) and
+        // bisection (a bound on the worst case).  A probe with exactly kmax
+        // keys below it ends the search: those keys are the kmax smallest and
+        // none ties with a dropped one.  Otherwise the search ends with
+        // hi = lo + 1: lo is the kmax-th smallest key, and kmax - cnt(< lo)
+        // of the keys equal to it are taken, in index order.
         unsigned T = 0x7fffffffu;
         int need_ties = 0;
         if (m > kmax) {
-            T = 0;
-            for (int bit = 30; bit >= 0; bit--) {
-                const unsigned cand = T | (1u << bit);
-                int cnt = 0;
-#pragma unroll
-                for (int c = 0; c < kKeyChunks; c++)
-                    if (c < nch) cnt += __popcll(ballot(key[c] < cand));
-                for (int c = kKeyChunks; c < nch; c++)
-                    cnt += __popcll(ballot(cand_key(emb, base, C, c * 64 + lane, q, d2max) < cand));
+            for (int o = 32; o > 0; o >>= 1) {
+                kmin = min(kmin, (unsigned)__shfl_xor((int)kmin, o));
+                khi = max(khi, (unsigned)__shfl_xor((int)khi, o));
+            }
+            unsigned lo = kmin, hi = khi + 1;
+            int clo = 0, chi = m;
+            bool exact = false;
+            for (int it = 0; hi - lo > 1; it++) {
+                const unsigned span = hi - lo;
+                unsigned step = span / 2;
+                if ((it & 1) == 0) {
+                    const float f = ((float)(kmax - clo) + 0.5f) / (float)(chi - clo);
+                    step = (unsigned)(f * (float)span);
+                    step = min(max(step, 1u), span - 1);
+                }
+                const unsigned mid = lo + step;
+                const int cnt = count_below(mid);
                 if (cnt == kmax) {
-                    T = cand;
+                    T = mid;
+                    exact = true;
                     break;
                 }
-                if (cnt < kmax) T = cand;
+                if (cnt < kmax) {
+                    lo = mid;
+                    clo = cnt;
+                } else {
+                    hi = mid;
+                    chi = cnt;
+                }
             }
-            int less = 0;
-#pragma unroll
-            for (int c = 0; c < kKeyChunks; c++)
-                if (c < nch) less += __popcll(ballot(key[c] < T));
-            for (int c = kKeyChunks; c < nch; c++)
-                less += __popcll(ballot(cand_key(emb, base, C, c * 64 + lane, q, d2max) < T));
-            need_ties = kmax - less;
+            if (!exact) {
+                T = lo;
+                need_ties = kmax - clo;
+            }
         }
         // emit survivors in candidate (= destination index) order
         int written = 0, ties_seen = 0;
