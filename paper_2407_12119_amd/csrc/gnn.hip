@@ -663,11 +663,12 @@ __global__ __launch_bounds__(512) void k_mlp(MlpArgs A) {
 
 // ------------------------------------------------------------------------
 // messages m_i = [sum_{i->j} e_ij, sum_{j->i} e_ji]  (Sec. 5.2, scatter_add)
-// H/4 lanes per hit, 4 channels per lane, float32 sums in edge-id order.
+// H/8 lanes per hit (8 channels each) for 2-byte states, H/4 (4 channels)
+// for float32 ones; float32 sums in edge-id order.
 // IN_ONLY: the outgoing sums of hits with out-edges were written by the
 // edge MLP that produced e (it walks the edges source by source); only hits
 // without out-edges get theirs (zero) here.
-// Edges are taken in batches of up to 16: the group's lanes first read the
+// Edges are taken in batches of up to 8: the group's lanes first read the
 // batch's incoming edge ids (one each), the ids are passed round the group,
 // and all of the batch's rows are requested before the first is added, so a
 // hit waits for two memory round trips per batch rather than per edge.
@@ -679,53 +680,63 @@ __global__ __launch_bounds__(256) void k_messages(int64_t n_hits, const int *__r
                                                   const typename P::state_t *__restrict__ e,
                                                   float *__restrict__ m, int xcd, const unsigned *__restrict__ flags) {
     if (*flags) return;
-    // batches of 16 stored rows of 2-byte states, 8 of float32 ones (registers)
-    constexpr int LPN = H / 4, NPW = 64 / LPN, BMAX = sizeof(typename P::state_t) == 2 ? 16 : 8;
-    constexpr int BATCH = LPN < BMAX ? LPN : BMAX;
-    const int lane = threadIdx.x & 63, sub = lane / LPN, l = lane % LPN, c = 4 * l, gbase = sub * LPN;
+    // a lane moves 16 bytes of a row: 8 channels of 2-byte states, 4 of
+    // float32 ones; batches of up to 8 rows (one edge id per lane of the group)
+    constexpr bool HALF = sizeof(typename P::state_t) == 2;
+    constexpr int CPL = HALF ? 8 : 4, LPN = H / CPL, NPW = 64 / LPN, BATCH = LPN < 8 ? LPN : 8;
+    const int lane = threadIdx.x & 63, sub = lane / LPN, l = lane % LPN, c = CPL * l, gbase = sub * LPN;
+    // rows are kept as loaded (16 bytes) until they are added
+    using raw_t = typename std::conditional<HALF, uint4, f32x4>::type;
+    auto add = [](f32x4 *s, const raw_t &r) {
+        if constexpr (HALF) {
+            s[0] += f32x4{__uint_as_float(r.x << 16), __uint_as_float(r.x & 0xffff0000u),
+                          __uint_as_float(r.y << 16), __uint_as_float(r.y & 0xffff0000u)};
+            s[1] += f32x4{__uint_as_float(r.z << 16), __uint_as_float(r.z & 0xffff0000u),
+                          __uint_as_float(r.w << 16), __uint_as_float(r.w & 0xffff0000u)};
+        } else {
+            s[0] += r;
+        }
+    };
+    constexpr int NS = HALF ? 2 : 1;
     const WaveRange wr = wave_range((n_hits + NPW - 1) / NPW, xcd != 0);
     for (int64_t u = wr.first; u < wr.end; u += wr.step) {
         const int64_t i0 = u * NPW + sub;
         const bool live = i0 < n_hits;
         const int64_t i = live ? i0 : n_hits - 1;
-        f32x4 so = zero4(), si = zero4();
+        f32x4 so[NS], si[NS];
+#pragma unroll
+        for (int k = 0; k < NS; k++) so[k] = si[k] = zero4();
         const int a0 = out_ptr[i], a1 = IN_ONLY ? a0 : out_ptr[i + 1];
-        // rows are kept as loaded (4 stored values) until they are added
-        using raw4 = typename std::conditional<sizeof(typename P::state_t) == 2, uint2, f32x4>::type;
-        auto widen = [](const raw4 &r) -> f32x4 {
-            if constexpr (sizeof(typename P::state_t) == 2)
-                return f32x4{__uint_as_float(r.x << 16), __uint_as_float(r.x & 0xffff0000u),
-                             __uint_as_float(r.y << 16), __uint_as_float(r.y & 0xffff0000u)};
-            else
-                return r;
-        };
         for (int a = a0; !IN_ONLY && a < a1; a += BATCH) {
             const int cnt = min(BATCH, a1 - a);
-            raw4 v[BATCH];
+            raw_t v[BATCH];
 #pragma unroll
             for (int j = 0; j < BATCH; j++)
-                if (j < cnt) v[j] = *(const raw4 *)(e + (int64_t)(a + j) * H + c);
+                if (j < cnt) v[j] = *(const raw_t *)(e + (int64_t)(a + j) * H + c);
 #pragma unroll
             for (int j = 0; j < BATCH; j++)
-                if (j < cnt) so += widen(v[j]);
+                if (j < cnt) add(so, v[j]);
         }
         const int b0 = in_ptr[i], b1 = in_ptr[i + 1];
         for (int b = b0; b < b1; b += BATCH) {   // the group's lanes share the trip count
             const int cnt = min(BATCH, b1 - b);
             const int mine = l < cnt ? in_list[b + l] : 0;
-            raw4 v[BATCH];
+            raw_t v[BATCH];
 #pragma unroll
             for (int j = 0; j < BATCH; j++) {
                 const int q = __shfl(mine, gbase + j);
-                if (j < cnt) v[j] = *(const raw4 *)(e + (int64_t)q * H + c);
+                if (j < cnt) v[j] = *(const raw_t *)(e + (int64_t)q * H + c);
             }
 #pragma unroll
             for (int j = 0; j < BATCH; j++)
-                if (j < cnt) si += widen(v[j]);
+                if (j < cnt) add(si, v[j]);
         }
         if (live) {
-            if (!IN_ONLY || a0 == out_ptr[i + 1]) *(f32x4 *)(m + i * 2 * H + c) = so;
-            *(f32x4 *)(m + i * 2 * H + H + c) = si;
+#pragma unroll
+            for (int k = 0; k < NS; k++) {
+                if (!IN_ONLY || a0 == out_ptr[i + 1]) *(f32x4 *)(m + i * 2 * H + c + 4 * k) = so[k];
+                *(f32x4 *)(m + i * 2 * H + H + c + 4 * k) = si[k];
+            }
         }
     }
 }
