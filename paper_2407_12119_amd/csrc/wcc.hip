@@ -59,14 +59,30 @@ __global__ __launch_bounds__(1024) void k_wcc(int B, const int *__restrict__ off
     for (int l = threadIdx.x; l < n; l += blockDim.x) par[l] = l;
     __syncthreads();
     bool err = false;
-    for (int q = e0 + threadIdx.x; q < e1; q += blockDim.x) {
-        if (!(logit[q] >= thr)) continue;
-        const int u = esrc[q], v = edst[q];
-        if (u < 0 || u >= n || v < 0 || v >= n) {
-            err = true;
-            continue;
+    // each thread takes 4 edges at a time, reading all of them before the
+    // first union (the reads of an edge do not wait on the previous unions)
+    constexpr int U = 4;
+    for (int q0 = e0 + threadIdx.x; q0 < e1; q0 += U * blockDim.x) {
+        bool keep[U];
+        int su[U], sv[U];
+#pragma unroll
+        for (int j = 0; j < U; j++) {
+            const int q = q0 + j * blockDim.x;
+            const bool in = q < e1;
+            keep[j] = in && logit[in ? q : e0] >= thr;
+            su[j] = in ? esrc[q] : 0;
+            sv[j] = in ? edst[q] : 0;
         }
-        unite(par, u, v);
+#pragma unroll
+        for (int j = 0; j < U; j++) {
+            if (!keep[j]) continue;
+            const int u = su[j], v = sv[j];
+            if (u < 0 || u >= n || v < 0 || v >= n) {
+                err = true;
+                continue;
+            }
+            unite(par, u, v);
+        }
     }
     if (err) atomicOr(flags, kErrInput);
     __syncthreads();
