@@ -271,12 +271,6 @@ constexpr size_t mlp_lds() {
 // Sum over the 16 lanes of each DPP row (every lane gets the row's sum):
 // partners n^8 (row rotate by 8), n^7 (half-row mirror), n^2 and n^1 (quad
 // permutations) generate the whole row.  Fixed order, so deterministic.
-__device__ inline int64_t uniform64(int64_t v) {
-    const uint64_t u = (uint64_t)v;
-    return (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(u >> 32)) << 32) |
-                     (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u));
-}
-
 template <int CTRL>
 __device__ inline float dpp_add(float v) {
     return v + __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF,

@@ -5,13 +5,14 @@
 // d2_max, keeping at most k_max per hit.  Hits are sorted by plane inside each
 // event, so the candidates of a hit on plane p are one contiguous index range.
 //
-// Work mapping: one 64-lane wavefront per query hit.  The lanes sweep the
-// candidate range in chunks of 64, compute the float32 distance keys and keep
-// up to kKeyChunks chunks of keys in registers.  The exact k_max smallest
-// under (d2, index) are found by a bitwise binary search on the float bit
-// pattern of d2 driven by wave ballots (no sorting, no scratch memory), and
-// the survivors are written in index order through ballot prefix counts.
-// This parallelises over the candidates of a hit as well as over hits.
+// Work mapping: a 64-lane wavefront takes a run of consecutive query hits,
+// one hit at a time.  The lanes hold the candidate range in chunks of 64 (up
+// to kKeyChunks chunks of embeddings stay in registers while the queries
+// share their event and plane), compute the float32 distance keys, and find
+// the exact k_max smallest under (d2, index) by a search on the float bit
+// pattern of d2 driven by wave ballots (no sorting, no scratch memory); the
+// survivors are written in index order through ballot prefix counts.  This
+// parallelises over the candidates of a hit as well as over hits.
 #include "internal.h"
 
 namespace velo {
@@ -91,134 +92,241 @@ __device__ inline unsigned cand_key(const f32x4 *__restrict__ emb, int64_t base,
     return s < d2max ? __float_as_uint(s) : kInvalidKey;
 }
 
-__global__ __launch_bounds__(256) void k_knn(int64_t n_hits, const int *__restrict__ off,
+constexpr int kKnnRun = 16;   // consecutive query hits per wavefront task
+constexpr int kKnnBlock = 256;
+constexpr int kHistBins = 256;   // key histogram of one query: four bins per lane
+
+// Orders one wavefront's LDS accesses (all lanes) before its next ones.
+__device__ inline void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+__global__ __launch_bounds__(kKnnBlock) void k_knn(int64_t n_hits, const int *__restrict__ off,
                                              const int *__restrict__ plane_off,
                                              const int *__restrict__ hit_event,
                                              const int *__restrict__ plane,
                                              const f32x4 *__restrict__ emb, float d2max, int kmax,
                                              int *__restrict__ nbr, int *__restrict__ deg, int xcd,
                                              const unsigned *__restrict__ flags) {
+    __shared__ __align__(16) int hist_sh[kKnnBlock / 64][kHistBins];
     if (*flags & kErrInput) return;
     const int lane = threadIdx.x & 63;
-    const WaveRange wr = wave_range(n_hits, xcd != 0);
-    for (int64_t i = wr.first; i < wr.end; i += wr.step) {
-        const int b = hit_event[i];
-        const int64_t s = off[b];
-        const int p = plane[i];
-        const int *po = plane_off + (int64_t)b * kPlaneSlots;
-        const int c0 = po[min(p + 1, VELO_N_PLANES)];
-        const int c1 = po[min(p + 3, VELO_N_PLANES)];
-        const int C = max(c1 - c0, 0);
-        const int64_t base = s + c0;          // batch index of candidate 0
-        const f32x4 q = emb[i];
-        const int nch = (C + 63) >> 6;
-        int *out = nbr + i * kmax;
-
-        unsigned key[kKeyChunks];
-        int m = 0;
-        unsigned kmin = kInvalidKey, khi = 0;   // smallest and largest valid key (lane-local)
+    // per-hit bookkeeping is wave-uniform: scalar loads
+    const_as<int> *hit_event4 = (const_as<int> *)hit_event;
+    const_as<int> *plane4 = (const_as<int> *)plane;
+    const_as<int> *off4 = (const_as<int> *)off;
+    const_as<int> *plane_off4 = (const_as<int> *)plane_off;
+    const_as<f32x4> *emb4 = (const_as<f32x4> *)emb;
+    const int64_t n_runs = (n_hits + kKnnRun - 1) / kKnnRun;
+    const WaveRange wv = wave_range(n_runs, xcd != 0);
+    const WaveRange wr{uniform64(wv.first), uniform64(wv.step), uniform64(wv.end)};
+    for (int64_t r = wr.first; r < wr.end; r += wr.step) {
+        // Hits are sorted by (event, plane), so consecutive queries mostly share
+        // their candidate range: its first kKeyChunks chunks of embeddings stay
+        // in registers until the (event, plane) changes.
+        int cb = -1, cp = -1;
+        int c0 = 0, C = 0, nch = 0;
+        int64_t base = 0;
+        f32x4 cand[kKeyChunks];
+        const int64_t i_end = min(r * kKnnRun + kKnnRun, n_hits);
+        for (int64_t i = r * kKnnRun; i < i_end; i++) {
+            const int b = hit_event4[i], p = plane4[i];
+            if (b != cb || p != cp) {
+                cb = b;
+                cp = p;
+                const_as<int> *po = plane_off4 + (int64_t)b * kPlaneSlots;
+                c0 = po[min(p + 1, VELO_N_PLANES)];
+                C = max(po[min(p + 3, VELO_N_PLANES)] - c0, 0);
+                base = (int64_t)off4[b] + c0;     // batch index of candidate 0
+                nch = (C + 63) >> 6;
 #pragma unroll
-        for (int c = 0; c < kKeyChunks; c++) {
-            key[c] = kInvalidKey;
-            if (c < nch) {
-                key[c] = cand_key(emb, base, C, c * 64 + lane, q, d2max);
-                const bool v = key[c] != kInvalidKey;
+                for (int c = 0; c < kKeyChunks; c++)
+                    if (c < nch) {
+                        const int j = c * 64 + lane;
+                        cand[c] = j < C ? emb[base + j] : f32x4{0.f, 0.f, 0.f, 0.f};
+                    }
+            }
+            const f32x4 q = emb4[i];
+            int *out = nbr + i * kmax;
+
+            unsigned key[kKeyChunks];
+            int m = 0;
+            unsigned kmin = kInvalidKey, khi = 0;   // smallest and largest valid key (lane-local)
+#pragma unroll
+            for (int c = 0; c < kKeyChunks; c++) {
+                key[c] = kInvalidKey;
+                if (c < nch) {
+                    if (c * 64 + lane < C) {
+                        const float s = dist2(q, cand[c]);
+                        if (s < d2max) key[c] = __float_as_uint(s);
+                    }
+                    const bool v = key[c] != kInvalidKey;
+                    m += __popcll(ballot(v));
+                    if (v) {
+                        kmin = min(kmin, key[c]);
+                        khi = max(khi, key[c]);
+                    }
+                }
+            }
+            for (int c = kKeyChunks; c < nch; c++) {
+                const unsigned k = cand_key(emb, base, C, c * 64 + lane, q, d2max);
+                const bool v = k != kInvalidKey;
                 m += __popcll(ballot(v));
                 if (v) {
-                    kmin = min(kmin, key[c]);
-                    khi = max(khi, key[c]);
+                    kmin = min(kmin, k);
+                    khi = max(khi, k);
                 }
             }
-        }
-        for (int c = kKeyChunks; c < nch; c++) {
-            const unsigned k = cand_key(emb, base, C, c * 64 + lane, q, d2max);
-            const bool v = k != kInvalidKey;
-            m += __popcll(ballot(v));
-            if (v) {
-                kmin = min(kmin, k);
-                khi = max(khi, k);
+            // number of keys below x over all chunks (uniform over the wavefront)
+            auto count_below = [&](unsigned x) {
+                int cnt = 0;
+#pragma unroll
+                for (int c = 0; c < kKeyChunks; c++)
+                    if (c < nch) cnt += __popcll(ballot(key[c] < x));
+                for (int c = kKeyChunks; c < nch; c++)
+                    cnt += __popcll(ballot(cand_key(emb, base, C, c * 64 + lane, q, d2max) < x));
+                return cnt;
+            };
+
+            // threshold T: the kmax-th smallest key (only needed when m > kmax).
+            // Search on the key bit pattern (monotone in the non-negative float
+            // d2) between the smallest and largest valid key of one histogram
+            // bin (below), keeping
+            // cnt(< lo) < kmax < cnt(< hi): probes alternate between linear
+            // interpolation of the counts (few probes on smooth key sets) and
+            // bisection (a bound on the worst case).  A probe with exactly kmax
+            // keys below it ends the search: those keys are the kmax smallest and
+            // none ties with a dropped one.  Otherwise the search ends with
+            // hi = lo + 1: lo is the kmax-th smallest key, and kmax - cnt(< lo)
+            // of the keys equal to it are taken, in index order.
+            unsigned T = 0x7fffffffu;
+            int need_ties = 0;
+            if (m > kmax) {
+                for (int o = 32; o > 0; o >>= 1) {
+                    kmin = min(kmin, (unsigned)__shfl_xor((int)kmin, o));
+                    khi = max(khi, (unsigned)__shfl_xor((int)khi, o));
+                }
+                // First narrow [kmin, khi] to one of kHistBins equal key
+                // intervals: a histogram of the keys in this wave's LDS
+                // slice, a prefix sum over the bins, and the bin holding the
+                // kmax-th smallest key.  The bin index is a monotone function
+                // of the key, so the keys below the bin are exactly those
+                // below its smallest key.
+                int *hist = hist_sh[threadIdx.x >> 6];
+                reinterpret_cast<int4 *>(hist)[lane] = int4{0, 0, 0, 0};
+                wave_lds_sync();
+                const float scale = (float)kHistBins / (float)(khi - kmin + 1u);
+                auto bin = [&](unsigned k) { return min((int)((float)(k - kmin) * scale), kHistBins - 1); };
+#pragma unroll
+                for (int c = 0; c < kKeyChunks; c++)
+                    if (c < nch && key[c] != kInvalidKey) atomicAdd(&hist[bin(key[c])], 1);
+                for (int c = kKeyChunks; c < nch; c++) {
+                    const unsigned k = cand_key(emb, base, C, c * 64 + lane, q, d2max);
+                    if (k != kInvalidKey) atomicAdd(&hist[bin(k)], 1);
+                }
+                wave_lds_sync();
+                const int4 h4 = reinterpret_cast<const int4 *>(hist)[lane];
+                const int hs[4] = {h4.x, h4.y, h4.z, h4.w};
+                const int own = hs[0] + hs[1] + hs[2] + hs[3];
+                int incl = own;
+                for (int o = 1; o < 64; o <<= 1) {
+                    const int v = __shfl_up(incl, o);
+                    if (lane >= o) incl += v;
+                }
+                // the lane whose four bins hold the kmax-th key (exactly one)
+                int bsel = 0, below = incl - own, upto = incl;
+                const bool here = below < kmax && kmax <= incl;
+                if (here) {
+#pragma unroll
+                    for (int j = 0; j < 4; j++)
+                        if (below + hs[j] >= kmax) {
+                            bsel = 4 * lane + j;
+                            upto = below + hs[j];
+                            break;
+                        } else {
+                            below += hs[j];
+                        }
+                }
+                const int src = __builtin_ctzll(ballot(here));
+                const int bstar = __shfl(bsel, src);
+                int clo = __shfl(below, src), chi = __shfl(upto, src);
+                // the bin's smallest and largest key
+                unsigned blo = kInvalidKey, bhi = 0;
+#pragma unroll
+                for (int c = 0; c < kKeyChunks; c++)
+                    if (c < nch && key[c] != kInvalidKey && bin(key[c]) == bstar) {
+                        blo = min(blo, key[c]);
+                        bhi = max(bhi, key[c]);
+                    }
+                for (int c = kKeyChunks; c < nch; c++) {
+                    const unsigned k = cand_key(emb, base, C, c * 64 + lane, q, d2max);
+                    if (k != kInvalidKey && bin(k) == bstar) {
+                        blo = min(blo, k);
+                        bhi = max(bhi, k);
+                    }
+                }
+                for (int o = 32; o > 0; o >>= 1) {
+                    blo = min(blo, (unsigned)__shfl_xor((int)blo, o));
+                    bhi = max(bhi, (unsigned)__shfl_xor((int)bhi, o));
+                }
+                unsigned lo = blo, hi = bhi + 1;    // cnt(< lo) = clo < kmax <= chi = cnt(< hi)
+                bool exact = false;
+                if (chi == kmax) {
+                    T = hi;
+                    exact = true;
+                }
+                for (int it = 0; !exact && hi - lo > 1; it++) {
+                    const unsigned span = hi - lo;
+                    unsigned step = span / 2;
+                    if ((it & 1) == 0) {
+                        const float f = ((float)(kmax - clo) + 0.5f) / (float)(chi - clo);
+                        step = (unsigned)(f * (float)span);
+                        step = min(max(step, 1u), span - 1);
+                    }
+                    const unsigned mid = lo + step;
+                    const int cnt = count_below(mid);
+                    if (cnt == kmax) {
+                        T = mid;
+                        exact = true;
+                        break;
+                    }
+                    if (cnt < kmax) {
+                        lo = mid;
+                        clo = cnt;
+                    } else {
+                        hi = mid;
+                        chi = cnt;
+                    }
+                }
+                if (!exact) {
+                    T = lo;
+                    need_ties = kmax - clo;
+                }
             }
-        }
-        // number of keys below x over all chunks (uniform over the wavefront)
-        auto count_below = [&](unsigned x) {
-            int cnt = 0;
+            // emit survivors in candidate (= destination index) order
+            int written = 0, ties_seen = 0;
+            auto emit = [&](unsigned k, int c) {
+                bool sel;
+                if (m > kmax) {
+                    const unsigned long long tie = ballot(k == T);
+                    const bool first_ties = ties_seen + lanes_below(tie) < need_ties;
+                    sel = k < T || (k == T && first_ties);
+                    ties_seen += __popcll(tie);
+                } else {
+                    sel = k != kInvalidKey;
+                }
+                const unsigned long long sm = ballot(sel);
+                if (sel) out[written + lanes_below(sm)] = c0 + c * 64 + lane;
+                written += __popcll(sm);
+            };
 #pragma unroll
             for (int c = 0; c < kKeyChunks; c++)
-                if (c < nch) cnt += __popcll(ballot(key[c] < x));
-            for (int c = kKeyChunks; c < nch; c++)
-                cnt += __popcll(ballot(cand_key(emb, base, C, c * 64 + lane, q, d2max) < x));
-            return cnt;
-        };
-
-        // threshold T: the kmax-th smallest key (only needed when m > kmax).
-        // Search on the key bit pattern (monotone in the non-negative float
-        // d2) between the smallest and largest valid key, keeping
-        // cnt(< lo) < kmax < cnt(< hi): probes alternate between linear
-        // interpolation of the counts (few probes on smooth key sets) and
-        // bisection (a bound on the worst case).  A probe with exactly kmax
-        // keys below it ends the search: those keys are the kmax smallest and
-        // none ties with a dropped one.  Otherwise the search ends with
-        // hi = lo + 1: lo is the kmax-th smallest key, and kmax - cnt(< lo)
-        // of the keys equal to it are taken, in index order.
-        unsigned T = 0x7fffffffu;
-        int need_ties = 0;
-        if (m > kmax) {
-            for (int o = 32; o > 0; o >>= 1) {
-                kmin = min(kmin, (unsigned)__shfl_xor((int)kmin, o));
-                khi = max(khi, (unsigned)__shfl_xor((int)khi, o));
-            }
-            unsigned lo = kmin, hi = khi + 1;
-            int clo = 0, chi = m;
-            bool exact = false;
-            for (int it = 0; hi - lo > 1; it++) {
-                const unsigned span = hi - lo;
-                unsigned step = span / 2;
-                if ((it & 1) == 0) {
-                    const float f = ((float)(kmax - clo) + 0.5f) / (float)(chi - clo);
-                    step = (unsigned)(f * (float)span);
-                    step = min(max(step, 1u), span - 1);
-                }
-                const unsigned mid = lo + step;
-                const int cnt = count_below(mid);
-                if (cnt == kmax) {
-                    T = mid;
-                    exact = true;
-                    break;
-                }
-                if (cnt < kmax) {
-                    lo = mid;
-                    clo = cnt;
-                } else {
-                    hi = mid;
-                    chi = cnt;
-                }
-            }
-            if (!exact) {
-                T = lo;
-                need_ties = kmax - clo;
-            }
+                if (c < nch) emit(key[c], c);
+            for (int c = kKeyChunks; c < nch; c++) emit(cand_key(emb, base, C, c * 64 + lane, q, d2max), c);
+            if (lane == 0) deg[i] = written;
         }
-        // emit survivors in candidate (= destination index) order
-        int written = 0, ties_seen = 0;
-        auto emit = [&](unsigned k, int c) {
-            bool sel;
-            if (m > kmax) {
-                const unsigned long long tie = ballot(k == T);
-                const bool first_ties = ties_seen + lanes_below(tie) < need_ties;
-                sel = k < T || (k == T && first_ties);
-                ties_seen += __popcll(tie);
-            } else {
-                sel = k != kInvalidKey;
-            }
-            const unsigned long long sm = ballot(sel);
-            if (sel) out[written + lanes_below(sm)] = c0 + c * 64 + lane;
-            written += __popcll(sm);
-        };
-#pragma unroll
-        for (int c = 0; c < kKeyChunks; c++)
-            if (c < nch) emit(key[c], c);
-        for (int c = kKeyChunks; c < nch; c++) emit(cand_key(emb, base, C, c * 64 + lane, q, d2max), c);
-        if (lane == 0) deg[i] = written;
     }
 }
 
@@ -460,10 +568,15 @@ __global__ __launch_bounds__(kListBlock) void k_in_lists(int64_t n_hits, const i
             for (int v = 0; v < kListWaves; v++) cnt[v][i] = 0;
         __syncthreads();
         int below = 0;
-        for (int e = w0 + lane; e < w1; e += 64) {
-            const int d = dst_g[e];
-            if (d < lo) below++;
-            else if (d < hi) atomicAdd(&cnt[w][d - lo], 1);
+        for (int e0 = w0 + lane; e0 < w1; e0 += 4 * 64) {   // four loads in flight per lane
+            int dd[4];
+#pragma unroll
+            for (int j = 0; j < 4; j++) dd[j] = e0 + 64 * j < w1 ? dst_g[e0 + 64 * j] : hi;
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                if (dd[j] < lo) below++;
+                else if (dd[j] < hi) atomicAdd(&cnt[w][dd[j] - lo], 1);
+            }
         }
         for (int o = 32; o > 0; o >>= 1) below += __shfl_xor(below, o);
         if (lane == 0) below_w[w] = below;
@@ -492,9 +605,11 @@ __global__ __launch_bounds__(kListBlock) void k_in_lists(int64_t n_hits, const i
         if ((int64_t)hi == n_hits && i0 < i1 && i1 == Dc) in_ptr[hi] = p;
         __syncthreads();
         const int nbits = Dc > 1 ? 32 - __clz(Dc - 1) : 0;
+        int dn = w0 + lane < w1 ? dst_g[w0 + lane] : -1;   // the next chunk's destination, in flight
         for (int e0 = w0; e0 < w1; e0 += 64) {        // uniform over the wavefront
             const int e = e0 + lane;
-            const int d = e < w1 ? dst_g[e] : -1;
+            const int d = dn;
+            dn = e + 64 < w1 ? dst_g[e + 64] : -1;
             const bool mine = d >= lo && d < hi;
             const int key = mine ? d - lo : 0;
             unsigned long long peers = ballot(mine);
@@ -542,7 +657,7 @@ void launch_scan(velo_ctx *c, const int *in, int *out, int64_t n, hipStream_t s)
 void launch_knn(velo_ctx *c, const velo_hits *h, const float *emb, hipStream_t s) {
     if (h->n_hits <= 0) return;
     const int blocks = persistent_grid(c, stage_per_cu(c, VELO_STAGE_KNN, 16));
-    k_knn<<<blocks, 256, 0, s>>>(h->n_hits, h->event_offsets, c->ws.plane_off, c->ws.hit_event,
+    k_knn<<<blocks, kKnnBlock, 0, s>>>(h->n_hits, h->event_offsets, c->ws.plane_off, c->ws.hit_event,
                                  h->plane, (const f32x4 *)emb, c->cfg.d2_max, c->cfg.k_max,
                                  c->ws.nbr, c->ws.deg, c->tune_xcd[VELO_STAGE_KNN], c->ws.flags);
 }

@@ -199,4 +199,18 @@ __device__ inline WaveRange wave_range(int64_t units, bool xcd) {
     return {lo + bx * wpb + wib, nbx * wpb, hi};
 }
 
+// A value the caller knows to be the same in every lane, moved to scalar
+// registers (lane 0's copy).
+__device__ inline int64_t uniform64(int64_t v) {
+    const uint64_t u = (uint64_t)v;
+    return (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(u >> 32)) << 32) |
+                     (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u));
+}
+
+// Read-only view of device memory through the constant address space: reads
+// at wave-uniform addresses become scalar loads.  For buffers that no kernel
+// running at the same time writes.
+template <typename T>
+using const_as = const __attribute__((address_space(4))) T;
+
 }  // namespace velo

@@ -304,6 +304,35 @@ def test_k_max_saturation_and_single_plane_pairs():
     assert np.bincount(g["src"], minlength=n).max() == 4
 
 
+@pytest.mark.parametrize("k_max", [32, 5])
+def test_exactly_tied_distances_cut_at_k_max(k_max):
+    """Hits on a coarse grid: many candidates share the same embedding, so
+    distances tie exactly and the k_max-th one usually ties with dropped
+    ones; the lowest candidate indices must win, as in the oracle (Sec. 5.1
+    keeps the k_max nearest; ties go by index)."""
+    wl = synth.dataclasses.replace(synth.WORKLOADS["batch256"], k_max=k_max)
+    rng = np.random.default_rng(11)
+    n = 400
+    plane = np.sort(rng.integers(0, 6, n)).astype(np.int32)
+    x = (10 + 0.002 * rng.integers(0, 3, n)).astype(np.float32)
+    y = (10 + 0.002 * rng.integers(0, 2, n)).astype(np.float32)
+    z = synth.PLANE_Z[plane].astype(np.float32)
+    ev = synth.Event(x, y, z, plane, np.zeros(n, np.int64), np.full(n, -1, np.int32))
+    batch = synth.to_batch([ev])
+    ctx, hits, blob = _setup(wl, batch)
+    emb = ctx.embed(hits)
+    g = velo.graph_to_host(ctx.build_graph(hits, emb), batch.n_hits)
+    e32 = emb.cpu().numpy()
+    rp, col = oracle.neighbours(ev.plane, e32, oracle.d2max_f32(wl.radius), wl.k_max)
+    deg = np.diff(rp)
+    full_rp, _ = oracle.neighbours(ev.plane, e32, oracle.d2max_f32(wl.radius), n)
+    assert (np.diff(full_rp) > k_max).mean() > 0.5          # the cut is active for most hits
+    src, dst = oracle.csr_to_edges(rp, col)
+    np.testing.assert_array_equal(g["src"], src)
+    np.testing.assert_array_equal(g["dst"], dst)
+    assert deg.max() == k_max
+
+
 def test_dense_event_candidate_windows_beyond_lds():
     """One event of ~17k hits whose plane windows hold up to ~2,200
     candidates: windows above the LDS staging size are read through L2 and
