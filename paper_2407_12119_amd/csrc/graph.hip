@@ -96,6 +96,42 @@ constexpr int kKnnRun = 16;   // consecutive query hits per wavefront task
 constexpr int kKnnBlock = 256;
 constexpr int kHistBins = 256;   // key histogram of one query: four bins per lane
 
+// Cross-lane steps on DPP (no LDS round trip).  All 64 lanes must be active.
+template <int CTRL>
+__device__ inline unsigned dpp_u32(unsigned v) {
+    return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, true);
+}
+// smallest / largest value over the wavefront (every row of 16 lanes is
+// reduced by a quad swap, a quad rotation, the half-row mirror and the row
+// mirror, then the four rows through scalar registers)
+__device__ inline unsigned wave_min_u32(unsigned v) {
+    v = min(v, dpp_u32<0xB1>(v));    // quad_perm [1,0,3,2]
+    v = min(v, dpp_u32<0x4E>(v));    // quad_perm [2,3,0,1]
+    v = min(v, dpp_u32<0x141>(v));   // row_half_mirror
+    v = min(v, dpp_u32<0x140>(v));   // row_mirror
+    return min(min((unsigned)__builtin_amdgcn_readlane((int)v, 0), (unsigned)__builtin_amdgcn_readlane((int)v, 16)),
+               min((unsigned)__builtin_amdgcn_readlane((int)v, 32), (unsigned)__builtin_amdgcn_readlane((int)v, 48)));
+}
+__device__ inline unsigned wave_max_u32(unsigned v) {
+    v = max(v, dpp_u32<0xB1>(v));
+    v = max(v, dpp_u32<0x4E>(v));
+    v = max(v, dpp_u32<0x141>(v));
+    v = max(v, dpp_u32<0x140>(v));
+    return max(max((unsigned)__builtin_amdgcn_readlane((int)v, 0), (unsigned)__builtin_amdgcn_readlane((int)v, 16)),
+               max((unsigned)__builtin_amdgcn_readlane((int)v, 32), (unsigned)__builtin_amdgcn_readlane((int)v, 48)));
+}
+// inclusive prefix sum over the lanes: row shifts by 1, 2, 4, 8 (lanes
+// shifted in from outside the row read 0), then the totals of earlier rows
+__device__ inline int wave_incl_scan(int v, int lane) {
+    v += (int)dpp_u32<0x111>((unsigned)v);   // row_shr:1
+    v += (int)dpp_u32<0x112>((unsigned)v);   // row_shr:2
+    v += (int)dpp_u32<0x114>((unsigned)v);   // row_shr:4
+    v += (int)dpp_u32<0x118>((unsigned)v);   // row_shr:8
+    const int r0 = __builtin_amdgcn_readlane(v, 15), r1 = __builtin_amdgcn_readlane(v, 31),
+              r2 = __builtin_amdgcn_readlane(v, 47);
+    return v + (lane >= 16 ? r0 : 0) + (lane >= 32 ? r1 : 0) + (lane >= 48 ? r2 : 0);
+}
+
 // Orders one wavefront's LDS accesses (all lanes) before its next ones.
 __device__ inline void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
@@ -204,10 +240,8 @@ __global__ __launch_bounds__(kKnnBlock) void k_knn(int64_t n_hits, const int *__
             unsigned T = 0x7fffffffu;
             int need_ties = 0;
             if (m > kmax) {
-                for (int o = 32; o > 0; o >>= 1) {
-                    kmin = min(kmin, (unsigned)__shfl_xor((int)kmin, o));
-                    khi = max(khi, (unsigned)__shfl_xor((int)khi, o));
-                }
+                kmin = wave_min_u32(kmin);
+                khi = wave_max_u32(khi);
                 // First narrow [kmin, khi] to one of kHistBins equal key
                 // intervals: a histogram of the keys in this wave's LDS
                 // slice, a prefix sum over the bins, and the bin holding the
@@ -219,9 +253,15 @@ __global__ __launch_bounds__(kKnnBlock) void k_knn(int64_t n_hits, const int *__
                 wave_lds_sync();
                 const float scale = (float)kHistBins / (float)(khi - kmin + 1u);
                 auto bin = [&](unsigned k) { return min((int)((float)(k - kmin) * scale), kHistBins - 1); };
+                int kbin[kKeyChunks];
 #pragma unroll
-                for (int c = 0; c < kKeyChunks; c++)
-                    if (c < nch && key[c] != kInvalidKey) atomicAdd(&hist[bin(key[c])], 1);
+                for (int c = 0; c < kKeyChunks; c++) {
+                    kbin[c] = -1;
+                    if (c < nch && key[c] != kInvalidKey) {
+                        kbin[c] = bin(key[c]);
+                        atomicAdd(&hist[kbin[c]], 1);
+                    }
+                }
                 for (int c = kKeyChunks; c < nch; c++) {
                     const unsigned k = cand_key(emb, base, C, c * 64 + lane, q, d2max);
                     if (k != kInvalidKey) atomicAdd(&hist[bin(k)], 1);
@@ -230,11 +270,7 @@ __global__ __launch_bounds__(kKnnBlock) void k_knn(int64_t n_hits, const int *__
                 const int4 h4 = reinterpret_cast<const int4 *>(hist)[lane];
                 const int hs[4] = {h4.x, h4.y, h4.z, h4.w};
                 const int own = hs[0] + hs[1] + hs[2] + hs[3];
-                int incl = own;
-                for (int o = 1; o < 64; o <<= 1) {
-                    const int v = __shfl_up(incl, o);
-                    if (lane >= o) incl += v;
-                }
+                const int incl = wave_incl_scan(own, lane);
                 // the lane whose four bins hold the kmax-th key (exactly one)
                 int bsel = 0, below = incl - own, upto = incl;
                 const bool here = below < kmax && kmax <= incl;
@@ -250,13 +286,13 @@ __global__ __launch_bounds__(kKnnBlock) void k_knn(int64_t n_hits, const int *__
                         }
                 }
                 const int src = __builtin_ctzll(ballot(here));
-                const int bstar = __shfl(bsel, src);
-                int clo = __shfl(below, src), chi = __shfl(upto, src);
+                const int bstar = __builtin_amdgcn_readlane(bsel, src);
+                int clo = __builtin_amdgcn_readlane(below, src), chi = __builtin_amdgcn_readlane(upto, src);
                 // the bin's smallest and largest key
                 unsigned blo = kInvalidKey, bhi = 0;
 #pragma unroll
                 for (int c = 0; c < kKeyChunks; c++)
-                    if (c < nch && key[c] != kInvalidKey && bin(key[c]) == bstar) {
+                    if (c < nch && kbin[c] == bstar) {
                         blo = min(blo, key[c]);
                         bhi = max(bhi, key[c]);
                     }
@@ -267,10 +303,8 @@ __global__ __launch_bounds__(kKnnBlock) void k_knn(int64_t n_hits, const int *__
                         bhi = max(bhi, k);
                     }
                 }
-                for (int o = 32; o > 0; o >>= 1) {
-                    blo = min(blo, (unsigned)__shfl_xor((int)blo, o));
-                    bhi = max(bhi, (unsigned)__shfl_xor((int)bhi, o));
-                }
+                blo = wave_min_u32(blo);
+                bhi = wave_max_u32(bhi);
                 unsigned lo = blo, hi = bhi + 1;    // cnt(< lo) = clo < kmax <= chi = cnt(< hi)
                 bool exact = false;
                 if (chi == kmax) {
@@ -308,24 +342,23 @@ __global__ __launch_bounds__(kKnnBlock) void k_knn(int64_t n_hits, const int *__
             // emit survivors in candidate (= destination index) order
             int written = 0, ties_seen = 0;
             auto emit = [&](unsigned k, int c) {
-                bool sel;
-                if (m > kmax) {
+                // with m <= kmax, T lies above every valid key and below kInvalidKey
+                bool sel = k < T;
+                if (need_ties > 0) {                  // uniform over the wavefront
                     const unsigned long long tie = ballot(k == T);
-                    const bool first_ties = ties_seen + lanes_below(tie) < need_ties;
-                    sel = k < T || (k == T && first_ties);
+                    sel = sel || (k == T && ties_seen + lanes_below(tie) < need_ties);
                     ties_seen += __popcll(tie);
-                } else {
-                    sel = k != kInvalidKey;
                 }
                 const unsigned long long sm = ballot(sel);
-                if (sel) out[written + lanes_below(sm)] = c0 + c * 64 + lane;
+                const int slot = written + lanes_below(sm);
+                if (sel && slot < kmax) out[slot] = c0 + c * 64 + lane;   // the row never overflows
                 written += __popcll(sm);
             };
 #pragma unroll
             for (int c = 0; c < kKeyChunks; c++)
                 if (c < nch) emit(key[c], c);
             for (int c = kKeyChunks; c < nch; c++) emit(cand_key(emb, base, C, c * 64 + lane, q, d2max), c);
-            if (lane == 0) deg[i] = written;
+            if (lane == 0) deg[i] = min(written, kmax);
         }
     }
 }
