@@ -56,6 +56,9 @@ def lib() -> C.CDLL:
         L.oracle_pipeline.argtypes = [i32, p, p, p, p, p, p, C.c_int, C.c_int, C.c_int, C.c_int,
                                       f32, C.c_int, f64, p, p, p, p, p, p]
         L.oracle_pipeline.restype = C.c_int
+        L.oracle_embed_train.argtypes = [i64, p, p, p, p, p, p, p, p, p, C.c_int, C.c_int,
+                                         C.c_int, f32, f64, p, p, p, p]
+        L.oracle_embed_train.restype = C.c_int
         _lib = L
     return _lib
 
@@ -170,6 +173,39 @@ def pipeline(batch, blob, H: int, iters: int, radius: float = 0.1, k_max: int = 
     E = int(eoff[-1])
     return {"emb": emb, "labels": labels, "edge_offsets": eoff, "src": esrc[:E].copy(),
             "dst": edst[:E].copy(), "logit": elog[:E].copy()}
+
+
+def embed_train_sums(x, y, z, plane, pid, query, rnd, emb32, blob, k_train: int = 50,
+                     d2_train: float = 1.5, margin: float = 1.0, Ce: int = 128, D: int = 4):
+    """Raw sums of the embedding loss of one noise-free event (Sec. 5.1, the
+    two loss equations) and their float64 gradients (blob-shaped): returns
+    (S_genuine, S_fake, N_genuine, N_fake, grad S_genuine, grad S_fake)."""
+    x, y, z = _c(x, np.float32), _c(y, np.float32), _c(z, np.float32)
+    plane, pid = _c(plane, np.int32), _c(pid, np.int32)
+    query, rnd = _c(query, np.uint8), _c(rnd, np.uint32)
+    emb32, blob = _c(emb32, np.float32), _c(blob, np.float32)
+    sums = np.zeros(2, np.float64)
+    counts = np.zeros(2, np.int64)
+    gg = np.zeros(blob.shape[0], np.float64)
+    gf = np.zeros(blob.shape[0], np.float64)
+    rc = lib().oracle_embed_train(x.shape[0], _ptr(x), _ptr(y), _ptr(z), _ptr(plane), _ptr(pid),
+                                  _ptr(query), _ptr(rnd), _ptr(emb32), _ptr(blob), Ce, D, int(k_train),
+                                  float(np.float32(d2_train)), float(margin), _ptr(sums), _ptr(counts),
+                                  _ptr(gg), _ptr(gf))
+    assert rc == 0, rc
+    return float(sums[0]), float(sums[1]), int(counts[0]), int(counts[1]), gg, gf
+
+
+def embed_train_loss(parts, w_genuine: float):
+    """Pool per-event sums into the step's loss and gradient:
+    L = w * S_g / N_g + S_f / N_f (a term with no pairs is zero)."""
+    Sg = sum(p[0] for p in parts); Sf = sum(p[1] for p in parts)
+    Ng = sum(p[2] for p in parts); Nf = sum(p[3] for p in parts)
+    cg = w_genuine / Ng if Ng else 0.0
+    cf = 1.0 / Nf if Nf else 0.0
+    grad = sum(cg * p[4] + cf * p[5] for p in parts)
+    return {"loss": cg * Sg + cf * Sf, "loss_genuine": Sg / Ng if Ng else 0.0,
+            "loss_fake": Sf / Nf if Nf else 0.0, "n_genuine": Ng, "n_fake": Nf, "grad": grad}
 
 
 def d2max_f32(radius: float) -> float:

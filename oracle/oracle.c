@@ -28,6 +28,10 @@
  *   loss/gradient weighted binary cross-entropy on the edge logits and its
  *                 exact gradient (training form; the paper trains with a
  *                 sigmoid focal loss, Sec. 5.2)
+ *   embedding     Sec. 5.1, the two loss equations: pairwise hinge
+ *   training      embedding loss over genuine pairs, hard negatives from the
+ *                 bounded neighbour list and one random pair per query, and
+ *                 its exact gradient with respect to the embedding MLP
  *
  * Parameter blob (float32, every Linear row-major [out x in] then its bias):
  *   norm[12]: emb_mu[3] emb_sigma[3] gnn_mu[3] gnn_sigma[3]
@@ -642,5 +646,162 @@ int oracle_pipeline(int32_t B, const int32_t *event_offsets,
         }
     }
     free(cnt);
+    return rc;
+}
+
+/* ------------------------------------------------------------------ */
+/* Sec. 5.1: embedding training (the two loss equations)               */
+/* ------------------------------------------------------------------ */
+
+/*
+ * One event of the embedding's training set and the raw sums of its loss.
+ * The event is given without noise hits (the paper drops them).  Query
+ * hits (query[i] = 1) are chosen by the caller; for each query q on plane p
+ * the candidates are the hits on planes p+1 and p+2, in index order:
+ *   hard negatives  the bounded neighbour list of q (k_train nearest under
+ *                   (d2, j) with d2 < d2_train, on the float32 embedding
+ *                   emb32), those of another particle: fake pairs;
+ *   genuine pairs   every candidate of q's particle (pid >= 0);
+ *   random pair     candidate number floor(rnd[q] * C / 2^32) of the C
+ *                   candidates, genuine or fake by pid (none when C = 0).
+ * The three lists are concatenated (a pair in two lists counts twice).
+ * Sums, with d2 in float64 from the float64 embedding:
+ *   sums[0] = sum over genuine pairs of d2,
+ *   sums[1] = sum over fake pairs of max(0, margin - d2),
+ * counts[0], counts[1] = numbers of genuine and fake pairs.  Whether a fake
+ * pair's hinge is active is decided in float32 on emb32 (the precision the
+ * network runs in), as the neighbour list is.  gg and gf (blob-shaped,
+ * float64, accumulated into) receive the gradients of sums[0] and sums[1]
+ * with respect to the embedding parameters (the normalisation constants are
+ * not trained).  The step's loss, pooled over the events of a batch, is
+ *   L = w_genuine * S_genuine / N_genuine + S_fake / N_fake.
+ */
+int oracle_embed_train(int64_t n, const float *x, const float *y, const float *z,
+                       const int32_t *plane, const int32_t *pid, const uint8_t *query,
+                       const uint32_t *rnd, const float *emb32, const float *blob, int Ce, int D,
+                       int k_train, float d2_train, double margin,
+                       double *sums, int64_t *counts, double *gg, double *gf)
+{
+    layout_t L;
+    if (n < 0 || make_layout(&L, 1, 0, Ce, D) || Ce > 1024 || D > 16 || k_train <= 0)
+        return -1;
+    int64_t nn = n > 0 ? n : 1;
+    double *u = malloc(sizeof(double) * (size_t)nn * 3);
+    double *pre1 = malloc(sizeof(double) * (size_t)nn * Ce);
+    double *pre2 = malloc(sizeof(double) * (size_t)nn * Ce);
+    double *e = malloc(sizeof(double) * (size_t)nn * D);
+    double *dEg = calloc((size_t)nn * D, sizeof(double));
+    double *dEf = calloc((size_t)nn * D, sizeof(double));
+    int32_t *rp = malloc(sizeof(int32_t) * (size_t)(nn + 1));
+    int32_t *col = malloc(sizeof(int32_t) * (size_t)nn * k_train);
+    int rc = 0;
+    if (!u || !pre1 || !pre2 || !e || !dEg || !dEf || !rp || !col) {
+        rc = -2;
+        goto out;
+    }
+    /* forward, keeping the inputs and both hidden pre-activations */
+    for (int64_t i = 0; i < n; i++) {
+        double a[1024];
+        embed_features(blob, x[i], y[i], z[i], u + i * 3);
+        linear(blob, &L.emb[0], u + i * 3, pre1 + i * Ce);
+        memcpy(a, pre1 + i * Ce, sizeof(double) * Ce);
+        relu(a, Ce);
+        linear(blob, &L.emb[1], a, pre2 + i * Ce);
+        memcpy(a, pre2 + i * Ce, sizeof(double) * Ce);
+        relu(a, Ce);
+        linear(blob, &L.emb[2], a, e + i * D);
+    }
+    /* hard-negative candidates: the bounded neighbour list on emb32 */
+    if (oracle_neighbours(n, plane, emb32, D, d2_train, k_train, rp, col, nn * k_train) < 0) {
+        rc = -1;
+        goto out;
+    }
+    sums[0] = sums[1] = 0.0;
+    counts[0] = counts[1] = 0;
+    for (int64_t q = 0; q < n; q++) {
+        if (!query[q])
+            continue;
+        /* one pair (q, j): genuine adds d2, fake adds the active hinge */
+        #define PAIR(J)                                                              \
+        do {                                                                         \
+            int64_t j_ = (J);                                                        \
+            int gen_ = pid[q] >= 0 && pid[j_] == pid[q];                             \
+            double d2_ = 0.0, df_[16];                                               \
+            for (int c = 0; c < D; c++) {                                            \
+                df_[c] = e[q * D + c] - e[j_ * D + c];                               \
+                d2_ += df_[c] * df_[c];                                              \
+            }                                                                        \
+            if (gen_) {                                                              \
+                counts[0]++;                                                         \
+                sums[0] += d2_;                                                      \
+                for (int c = 0; c < D; c++) {                                        \
+                    dEg[q * D + c] += 2.0 * df_[c];                                  \
+                    dEg[j_ * D + c] -= 2.0 * df_[c];                                 \
+                }                                                                    \
+            } else {                                                                 \
+                counts[1]++;                                                         \
+                if (d2_f32(emb32 + q * D, emb32 + j_ * D, D) < (float)margin) {      \
+                    sums[1] += margin - d2_;                                         \
+                    for (int c = 0; c < D; c++) {                                    \
+                        dEf[q * D + c] -= 2.0 * df_[c];                              \
+                        dEf[j_ * D + c] += 2.0 * df_[c];                             \
+                    }                                                                \
+                }                                                                    \
+            }                                                                        \
+        } while (0)
+        /* hard negatives: the fake members of q's neighbour list */
+        for (int32_t a = rp[q]; a < rp[q + 1]; a++)
+            if (!(pid[q] >= 0 && pid[col[a]] == pid[q]))
+                PAIR(col[a]);
+        /* genuine pairs and the candidate count */
+        int64_t C = 0;
+        for (int64_t j = 0; j < n; j++) {
+            int dp = plane[j] - plane[q];
+            if (dp != 1 && dp != 2)
+                continue;
+            C++;
+            if (pid[q] >= 0 && pid[j] == pid[q])
+                PAIR(j);
+        }
+        /* the random pair: candidate number floor(rnd * C / 2^32), index order */
+        if (C > 0) {
+            int64_t r = (int64_t)(((uint64_t)rnd[q] * (uint64_t)C) >> 32), seen = 0;
+            for (int64_t j = 0; j < n; j++) {
+                int dp = plane[j] - plane[q];
+                if (dp != 1 && dp != 2)
+                    continue;
+                if (seen++ == r) {
+                    PAIR(j);
+                    break;
+                }
+            }
+        }
+        #undef PAIR
+    }
+    /* backward of both sums through the three layers */
+    for (int pass = 0; pass < 2; pass++) {
+        const double *dE = pass ? dEf : dEg;
+        double *g = pass ? gf : gg;
+        for (int64_t i = 0; i < n; i++) {
+            double a2[1024], dpre2[1024], dx[3];
+            for (int h = 0; h < Ce; h++)
+                a2[h] = pre2[i * Ce + h] > 0.0 ? pre2[i * Ce + h] : 0.0;
+            for (int c = 0; c < D; c++) {
+                g[L.emb[2].b + c] += dE[i * D + c];
+                for (int h = 0; h < Ce; h++)
+                    g[L.emb[2].w + (int64_t)c * Ce + h] += dE[i * D + c] * a2[h];
+            }
+            for (int h = 0; h < Ce; h++) {
+                double s = 0.0;
+                for (int c = 0; c < D; c++)
+                    s += (double)blob[L.emb[2].w + (int64_t)c * Ce + h] * dE[i * D + c];
+                dpre2[h] = pre2[i * Ce + h] > 0.0 ? s : 0.0;
+            }
+            /* layers 0 and 1: y = W1 relu(W0 u + b0) + b1 with y = pre2 */
+            mlp2_backward(blob, &L.emb[0], &L.emb[1], u + i * 3, pre1 + i * Ce, dpre2, g, dx);
+        }
+    }
+out:
+    free(u); free(pre1); free(pre2); free(e); free(dEg); free(dEf); free(rp); free(col);
     return rc;
 }

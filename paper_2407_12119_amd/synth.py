@@ -331,3 +331,41 @@ def calibration_batch(wl: Workload, n_events: int = 16) -> Batch:
     """Seeded calibration events (fp8 activation scales), drawn with the
     workload's recipe from a seed stream of their own."""
     return to_batch([make_event(wl.recipe, _rng(998, i)) for i in range(n_events)])
+
+
+# --------------------------------------------------------------------------
+# Embedding training set inputs (Sec. 5.1): events without noise hits, the
+# query mask and one 32-bit random draw per hit for the random pair.
+# --------------------------------------------------------------------------
+@dataclasses.dataclass
+class EmbedTrainBatch:
+    batch: Batch             # noise-free events
+    pid: np.ndarray          # i32 [N], particle id (event-local, >= 0)
+    query: np.ndarray        # u8 [N], 1 = hit of a particle with >= 3 hits
+    rnd: np.ndarray          # u32 [N], uniform draw picking the random partner
+
+
+def strip_noise(ev: Event) -> Event:
+    keep = ev.pid >= 0
+    old = np.flatnonzero(keep)
+    new_index = np.full(ev.n, -1, np.int64)
+    new_index[old] = np.arange(old.shape[0])
+    nxt = ev.next_hit[keep]
+    nxt = np.where(nxt >= 0, new_index[np.maximum(nxt, 0)], -1).astype(np.int32)
+    return Event(ev.x[keep], ev.y[keep], ev.z[keep], ev.plane[keep], ev.pid[keep], nxt)
+
+
+def embed_train_batch(events: Sequence[Event], step: int = 0) -> EmbedTrainBatch:
+    """The embedding training inputs of `events`: noise removed; query hits
+    belong to particles with at least three hits (reconstructible); rnd is
+    drawn from PCG64(SeedSequence([root, 997, step, event index]))."""
+    clean = [strip_noise(ev) for ev in events]
+    batch = to_batch(clean)
+    pid, query, rnd = [], [], []
+    for e, ev in enumerate(clean):
+        counts = np.bincount(ev.pid, minlength=1) if ev.n else np.zeros(1, np.int64)
+        pid.append(ev.pid.astype(np.int32))
+        query.append((counts[ev.pid] >= 3).astype(np.uint8) if ev.n else np.zeros(0, np.uint8))
+        rnd.append(_rng(997, step, e).integers(0, 2 ** 32, ev.n, dtype=np.uint64).astype(np.uint32))
+    cat = lambda a, dt: np.concatenate(a).astype(dt) if a else np.zeros(0, dt)
+    return EmbedTrainBatch(batch, cat(pid, np.int32), cat(query, np.uint8), cat(rnd, np.uint32))
