@@ -189,7 +189,9 @@ typedef enum {
     VELO_STAGE_BWD_GRAPH = 15, /* training: per-hit sums of dL/d(hidden) of the edge MLPs */
     VELO_STAGE_ADAM = 16,      /* training: Adam update */
     VELO_STAGE_HIT_PROJ = 17,  /* fp32 inference: per-hit first-layer products of the edge MLPs */
-    VELO_N_STAGES = 18
+    VELO_STAGE_EMB_LOSS = 18,  /* embedding training: training pairs and the hinge loss (Sec. 5.1) */
+    VELO_STAGE_EMB_BWD = 19,   /* embedding training: back-propagation and weight gradients */
+    VELO_N_STAGES = 20
 } velo_stage;
 
 /* Enable (1) or disable (0) per-stage timing: while enabled every call
@@ -253,6 +255,45 @@ velo_status velo_train_backward(velo_ctx *ctx, const velo_hits *hits, const floa
  * p -= lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps); step >= 1. */
 velo_status velo_adam_step(velo_ctx *ctx, float *params, const float *grad, float *m, float *v, int64_t n, float lr,
                            float b1, float b2, float eps, int32_t step, void *stream);
+
+/* Embedding training (Sec. 5.1, the two loss equations).  Truth of the
+ * training events, all device arrays over the hits of the batch:
+ *   pid    particle of each hit (>= 0; events are given without noise hits,
+ *          which the paper removes from the training events),
+ *   query  1 for a query hit (the caller's choice; the paper takes hits of
+ *          reconstructible particles, not electrons),
+ *   rnd    one uniform 32-bit draw per hit, which picks the query's random
+ *          partner: candidate number floor(rnd * C / 2^32) of the C hits on
+ *          planes p+1 and p+2, in index order. */
+typedef struct {
+    const int32_t *pid;
+    const uint8_t *query;
+    const uint32_t *rnd;
+} velo_embed_truth;
+
+#define VELO_EMB_TRAIN_KMAX 64   /* largest k_train accepted */
+
+/* Loss and gradient of one embedding training step (Sec. 5.1).  Runs the
+ * embedding with the caller's float32 parameter blob `params` (device), then
+ * builds the training pairs of every query q: the hard negatives (the members
+ * of another particle in q's bounded neighbour list, k_train nearest with
+ * d2 < d2_train, ties by index, as the graph stage builds it), every genuine
+ * pair (a candidate of q's particle on planes p+1, p+2) and one random pair;
+ * the three lists are concatenated.  The loss is pooled over the batch:
+ *   L = w_genuine * (1/N_g) sum_genuine d2 + (1/N_f) sum_fake max(0, margin - d2),
+ * with d2 and the hinge decision in float32.  Writes dL/dparams for the
+ * embedding entries of the blob-shaped dparams (device; every other entry
+ * is left as it is), loss[3] = {L, genuine term, fake term} (device float)
+ * and counts[2] = {N_g, N_f} (device int64); emb (device [N x 4], optional)
+ * receives the embedding the pairs were built on.  Per-hit gradient sums are
+ * accumulated in 64-bit fixed point (2^-32), so the result does not depend
+ * on the order of the pairs and is bitwise reproducible.  Needs a context
+ * created with training = 1 whose parameters have been set once (as every
+ * call on hits does); 1 <= k_train <= VELO_EMB_TRAIN_KMAX. */
+velo_status velo_embed_train_grad(velo_ctx *ctx, const velo_hits *hits, const velo_embed_truth *truth,
+                                  const float *params, int32_t k_train, float d2_train, float margin,
+                                  float w_genuine, float *dparams, float *loss, int64_t *counts, float *emb,
+                                  void *stream);
 
 /* Choose launch parameters by measurement: runs velo_infer on (hits, out)
  * under a fixed list of candidate configurations (blocks per compute unit and

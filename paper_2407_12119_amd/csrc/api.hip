@@ -3,6 +3,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <new>
 
 #include "internal.h"
@@ -62,7 +63,8 @@ void free_ws(Workspace &w) {
                     w.in_ptr, w.in_list, w.scan_tmp, w.h[0], w.h[1],
                     w.m, w.ab, w.e, w.n_edges, w.flags, w.eoff_tmp, w.ck_h, w.ck_e, w.ck_m, w.ck_ab, w.g_sd, w.g_e[0], w.g_e[1],
                     w.g_h[0], w.g_h[1], w.g_da, w.g_r, w.g_m, w.g_part, w.g_red, w.g_loss,
-                    w.scales, w.amax, w.tmp_logit};
+                    w.scales, w.amax, w.tmp_logit, w.t_u, w.t_a1, w.t_a2, w.t_dz1, w.t_dz2, w.t_dz3,
+                    w.t_nbr, w.t_deg, w.t_acc, w.t_stat, w.t_part};
     for (void *p : ptrs)
         if (p) hipFree(p);
     w = Workspace();
@@ -190,6 +192,13 @@ velo_status velo_create(const velo_config *cfg, velo_ctx **out) {
              dalloc(&w.g_m, N * 2 * H) && dalloc(&w.g_part, (int64_t)train_part_floats(k.gnn_hidden)) &&
              dalloc(&w.g_red, (int64_t)train_red_floats(k.gnn_hidden)) &&
              dalloc(&w.g_loss, 256);
+        // embedding training
+        const int64_t Ce = VELO_EMB_HIDDEN;
+        ok = ok && dalloc(&w.t_u, N * 4) && dalloc(&w.t_a1, N * Ce) && dalloc(&w.t_a2, N * Ce) &&
+             dalloc(&w.t_dz1, N * Ce) && dalloc(&w.t_dz2, N * Ce) && dalloc(&w.t_dz3, N * 4) &&
+             dalloc(&w.t_nbr, N * VELO_EMB_TRAIN_KMAX) && dalloc(&w.t_deg, N) && dalloc(&w.t_acc, N * 8) &&
+             dalloc(&w.t_stat, 4) &&
+             dalloc(&w.t_part, emb_train_chunks(N) * (Ce * 3 + Ce + Ce * Ce + Ce + VELO_EMB_DIM * Ce + VELO_EMB_DIM));
     }
     if (!ok) {
         hipGetLastError();
@@ -554,6 +563,29 @@ velo_status velo_autotune(velo_ctx *c, const velo_hits *h, velo_outputs *o, void
     velo_set_timing(c, was_timing ? 1 : 0);
     if (st) return st;
     return velo_check(c, stream);
+}
+
+velo_status velo_embed_train_grad(velo_ctx *c, const velo_hits *h, const velo_embed_truth *truth,
+                                  const float *params, int32_t k_train, float d2_train, float margin,
+                                  float w_genuine, float *dparams, float *loss, int64_t *counts, float *emb,
+                                  void *stream) {
+    if (!c) return VELO_ERR_INVALID_ARG;
+    if (!c->cfg.training) return fail(c, VELO_ERR_UNSUPPORTED, "context created without training = 1");
+    velo_status st = check_hits(c, h);
+    if (st) return st;
+    if (!truth || !params || !dparams || !loss || !counts)
+        return fail(c, VELO_ERR_INVALID_ARG, "velo_embed_train_grad: a required pointer is NULL");
+    if (h->n_hits > 0 && (!truth->pid || !truth->query || !truth->rnd))
+        return fail(c, VELO_ERR_INVALID_ARG, "velo_embed_train_grad: truth arrays are NULL");
+    if (k_train < 1 || k_train > VELO_EMB_TRAIN_KMAX)
+        return fail(c, VELO_ERR_INVALID_ARG, "velo_embed_train_grad: k_train outside [1, VELO_EMB_TRAIN_KMAX]");
+    if (!(d2_train > 0.f) || !std::isfinite(d2_train) || !std::isfinite(margin) || !(w_genuine >= 0.f) ||
+        !std::isfinite(w_genuine))
+        return fail(c, VELO_ERR_INVALID_ARG, "velo_embed_train_grad: d2_train, margin or w_genuine invalid");
+    DeviceGuard gd(c->device);
+    launch_embed_train_grad(c, h, truth, params, k_train, d2_train, margin, w_genuine, dparams, loss, counts, emb,
+                            (hipStream_t)stream);
+    return device_status(c, "velo_embed_train_grad");
 }
 
 velo_status velo_check(velo_ctx *c, void *stream) {

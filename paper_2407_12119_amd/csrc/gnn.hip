@@ -37,13 +37,17 @@ using namespace mfma;
 constexpr int kCe = VELO_EMB_HIDDEN;
 
 // sc: the embedding's scales {s_x2, s_w2, s_x3, s_w3} (fp8, else null);
-// amax: its two layer inputs' calibration maxima (else null).
+// amax: its two layer inputs' calibration maxima (else null).  Training
+// keeps, per hit, the normalised inputs (sv: u0 u1 u2 0) and both hidden
+// activations after their ReLU (sa1, sa2: [n x 128] rows); null: not kept.
 template <class P>
 __global__ __launch_bounds__(512) void k_embed(int64_t n_hits, const float *__restrict__ x,
                                                const float *__restrict__ y, const float *__restrict__ z,
                                                const float *__restrict__ P_, int64_t o_w1, int64_t o_w2,
                                                int64_t o_w3, float *__restrict__ emb, const float *__restrict__ sc,
-                                               float *__restrict__ amax, const unsigned *__restrict__ flags) {
+                                               float *__restrict__ amax, float *__restrict__ sv,
+                                               float *__restrict__ sa1, float *__restrict__ sa2,
+                                               const unsigned *__restrict__ flags) {
     using W = typename P::wfrag_t;
     constexpr int MO = kCe / 16, KB = kCe / P::KBLK;
     extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -73,6 +77,10 @@ __global__ __launch_bounds__(512) void k_embed(int64_t n_hits, const float *__re
         f32x4 h1[MO];
         first_layer3<MO>(sW1, kCe, u0, u1, u2, g, h1);
         if (amax) record_amax(absmax4<MO>(h1), amax);
+        if (sa1 && i < n_hits) {
+            F32::store_all<MO>(sa1 + i * kCe, g, h1);
+            if (g == 0) *(f32x4 *)(sv + i * 4) = f32x4{u0, u1, u2, 0.f};
+        }
         typename P::frag_t x1[KB];
         P::template chain<MO>(h1, x1, S.ix1);
         f32x4 h2[MO];
@@ -81,6 +89,7 @@ __global__ __launch_bounds__(512) void k_embed(int64_t n_hits, const float *__re
         if (P::kScaled) rescale<MO>(h2, S.d1);
         bias_relu<MO>(h2, rb2);
         if (amax) record_amax(absmax4<MO>(h2), amax + 1);
+        if (sa2 && i < n_hits) F32::store_all<MO>(sa2 + i * kCe, g, h2);
         typename P::frag_t x2[KB];
         P::template chain<MO>(h2, x2, S.ix2);
         f32x4 o[1];
@@ -884,7 +893,7 @@ void embed_p(velo_ctx *c, const velo_hits *h, float *emb, bool calib, hipStream_
                                                              L.emb[1].w, L.emb[2].w, emb,
                                                              P::kScaled ? c->ws.scales + 4 * kSlotEmbed : nullptr,
                                                              calib ? c->ws.amax + 2 * kSlotEmbed : nullptr,
-                                                             c->ws.flags);
+                                                             nullptr, nullptr, nullptr, c->ws.flags);
 }
 
 }  // namespace
@@ -969,6 +978,17 @@ bool gnn_supported(int hidden, int precision) {
 
 // calib: run the bf16 kernels of an fp8 context and record every MLP input's
 // largest |value| (the activation scales are derived from them).
+void launch_embed_train(velo_ctx *c, const velo_hits *h, const float *params, float *emb, float *sv,
+                        float *sa1, float *sa2, hipStream_t s) {
+    if (h->n_hits <= 0) return;
+    const size_t lds = frag_bytes<F32>(kCe, kCe) + frag_bytes<F32>(16, kCe) + sizeof(float) * kCe * 4;
+    static const int per_cu = blocks_per_cu(reinterpret_cast<const void *>(&k_embed<F32>), kMlpBlock, lds);
+    const ParamLayout &L = c->layout;
+    k_embed<F32><<<persistent_grid(c, per_cu), kMlpBlock, lds, s>>>(h->n_hits, h->x, h->y, h->z, params, L.emb[0].w,
+                                                                L.emb[1].w, L.emb[2].w, emb, nullptr, nullptr, sv,
+                                                                sa1, sa2, c->ws.flags);
+}
+
 void launch_embed(velo_ctx *c, const velo_hits *h, float *emb, bool calib, hipStream_t s) {
     if (h->n_hits <= 0) return;
     const int p = c->cfg.precision;

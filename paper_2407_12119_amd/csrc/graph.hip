@@ -687,12 +687,17 @@ void launch_scan(velo_ctx *c, const int *in, int *out, int64_t n, hipStream_t s)
     if (nb > 0) k_scan_apply<<<nb, kScanBlock, 0, s>>>(in, n, c->ws.scan_tmp, out);
 }
 
-void launch_knn(velo_ctx *c, const velo_hits *h, const float *emb, hipStream_t s) {
+void launch_knn_into(velo_ctx *c, const velo_hits *h, const float *emb, int kmax, float d2max, int *nbr, int *deg,
+                     hipStream_t s) {
     if (h->n_hits <= 0) return;
     const int blocks = persistent_grid(c, stage_per_cu(c, VELO_STAGE_KNN, 16));
     k_knn<<<blocks, kKnnBlock, 0, s>>>(h->n_hits, h->event_offsets, c->ws.plane_off, c->ws.hit_event,
-                                 h->plane, (const f32x4 *)emb, c->cfg.d2_max, c->cfg.k_max,
-                                 c->ws.nbr, c->ws.deg, c->tune_xcd[VELO_STAGE_KNN], c->ws.flags);
+                                       h->plane, (const f32x4 *)emb, d2max, kmax, nbr, deg,
+                                       c->tune_xcd[VELO_STAGE_KNN], c->ws.flags);
+}
+
+void launch_knn(velo_ctx *c, const velo_hits *h, const float *emb, hipStream_t s) {
+    launch_knn_into(c, h, emb, c->cfg.k_max, c->cfg.d2_max, c->ws.nbr, c->ws.deg, s);
 }
 
 void launch_compact(velo_ctx *c, const velo_hits *h, velo_outputs *g, hipStream_t s) {

@@ -69,6 +69,16 @@ struct Workspace {
     float *g_part = nullptr;     // [n_chunks x part_len] weight-gradient partial sums
     float *g_red = nullptr;      // [32 x part_len] group sums of the partials
     float *g_loss = nullptr;     // [n_chunks] loss partial sums
+    // embedding training (allocated with training)
+    float *t_u = nullptr;        // [max_hits x 4] normalised inputs u0 u1 u2 0
+    float *t_a1 = nullptr, *t_a2 = nullptr;     // [max_hits x 128] hidden activations
+    float *t_dz1 = nullptr, *t_dz2 = nullptr;   // [max_hits x 128] their gradients (pre-ReLU)
+    float *t_dz3 = nullptr;      // [max_hits x 4] dL/d(embedding)
+    int *t_nbr = nullptr;        // [max_hits x VELO_EMB_TRAIN_KMAX] bounded neighbour lists
+    int *t_deg = nullptr;        // [max_hits]
+    unsigned long long *t_acc = nullptr;   // [max_hits x 8] fixed-point gradient sums (genuine, fake)
+    unsigned long long *t_stat = nullptr;  // [4] fixed-point loss sums and pair counts
+    float *t_part = nullptr;     // [chunks x embedding parameters] weight-gradient partials
 };
 
 }  // namespace velo
@@ -106,6 +116,8 @@ namespace velo {
 // ---- launchers (graph.hip) ----
 void launch_prepare(velo_ctx *c, const velo_hits *h, hipStream_t s);
 void launch_knn(velo_ctx *c, const velo_hits *h, const float *emb, hipStream_t s);
+void launch_knn_into(velo_ctx *c, const velo_hits *h, const float *emb, int kmax, float d2max, int *nbr, int *deg,
+                     hipStream_t s);
 void launch_scan(velo_ctx *c, const int *in, int *out, int64_t n, hipStream_t s);
 void launch_compact(velo_ctx *c, const velo_hits *h, velo_outputs *g, hipStream_t s);
 void launch_globalise(velo_ctx *c, const velo_hits *h, const velo_outputs *g, hipStream_t s);
@@ -118,6 +130,12 @@ void launch_in_lists_plane(velo_ctx *c, const velo_hits *h, hipStream_t s);
 size_t state_bytes(int precision);              // bytes per stored encoding element
 bool gnn_supported(int hidden, int precision);  // compiled (hidden, precision) pairs
 void launch_embed(velo_ctx *c, const velo_hits *h, float *emb, bool calib, hipStream_t s);
+void launch_embed_train(velo_ctx *c, const velo_hits *h, const float *params, float *emb, float *sv,
+                        float *sa1, float *sa2, hipStream_t s);
+int64_t emb_train_chunks(int64_t n_hits);
+void launch_embed_train_grad(velo_ctx *c, const velo_hits *h, const velo_embed_truth *truth, const float *params,
+                             int k_train, float d2_train, float margin, float w_genuine, float *dparams,
+                             float *loss, int64_t *counts, float *emb, hipStream_t s);
 // GNN forward over the graph in the workspace (src_g, dst_g, row_ptr, in lists)
 void launch_gnn(velo_ctx *c, const velo_hits *h, float *logit, const float *params, bool train, bool calib,
                 hipStream_t s);

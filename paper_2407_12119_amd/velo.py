@@ -27,10 +27,10 @@ EXPORTS = ("velo_param_count", "velo_create", "velo_destroy", "velo_set_params",
            "velo_status_str", "velo_last_error", "velo_set_timing", "velo_read_timing",
            "velo_train_forward", "velo_bce", "velo_train_backward", "velo_adam_step",
            "velo_graph_capture", "velo_graph_launch", "velo_graph_destroy", "velo_calibrate",
-           "velo_autotune")
+           "velo_autotune", "velo_embed_train_grad")
 STAGES = ("prepare", "embed", "knn", "compact", "lists", "node_enc", "edge_enc", "messages",
           "node_net", "edge_net", "edge_cls", "components", "bce", "bwd_mlp", "bwd_dw", "bwd_graph", "adam",
-          "hit_proj")
+          "hit_proj", "emb_loss", "emb_bwd")
 
 
 class VeloError(RuntimeError):
@@ -112,6 +112,9 @@ def lib() -> C.CDLL:
         L.velo_calibrate.restype = st
         L.velo_autotune.argtypes = [vp, C.POINTER(_Hits), C.POINTER(_Outputs), vp, vp]
         L.velo_autotune.restype = st
+        L.velo_embed_train_grad.argtypes = [vp, C.POINTER(_Hits), C.POINTER(_EmbedTruth), vp, C.c_int32,
+                                            C.c_float, C.c_float, C.c_float, vp, vp, vp, vp, vp]
+        L.velo_embed_train_grad.restype = st
         _lib = L
     return _lib
 
@@ -122,6 +125,10 @@ def param_count(hidden: int, iters: int) -> int:
 
 def _ptr(t) -> Optional[int]:
     return None if t is None else t.data_ptr()
+
+
+class _EmbedTruth(C.Structure):
+    _fields_ = [("pid", C.c_void_p), ("query", C.c_void_p), ("rnd", C.c_void_p)]
 
 
 @dataclasses.dataclass
@@ -221,7 +228,7 @@ class Context:
         hc = hits.c()
         choice = np.zeros(len(STAGES), np.int32)
         self._raise(self._lib.velo_autotune(self._h, C.byref(hc), C.byref(oc), _stream(), choice.ctypes.data),
-                    "velo_autotune")
+                    "velo_autotune", "velo_embed_train_grad")
         return {k: int(choice[i]) for i, k in enumerate(STAGES)}
 
     def check(self):
@@ -341,6 +348,26 @@ class Context:
         self._raise(self._lib.velo_adam_step(self._h, C.c_void_p(params.data_ptr()), C.c_void_p(grad.data_ptr()),
                                              C.c_void_p(m.data_ptr()), C.c_void_p(v.data_ptr()), params.numel(),
                                              lr, b1, b2, eps, step, _stream()), "velo_adam_step")
+
+    def embed_train_grad(self, hits: DeviceHits, pid, query, rnd, params, k_train: int = 50,
+                         d2_train: float = 1.5, margin: float = 1.0, w_genuine: float = 2.0, dparams=None,
+                         emb=None):
+        """One embedding training step's loss and gradient (Sec. 5.1): returns
+        (dparams, loss [3] = {L, genuine term, fake term}, counts [2] = {N_g, N_f});
+        only the embedding entries of dparams are written.  pid int32, query
+        uint8, rnd int32 (bits of a uint32 draw) device tensors over the hits."""
+        import torch
+        if dparams is None:
+            dparams = torch.zeros_like(params)
+        loss = torch.empty(3, dtype=torch.float32, device=params.device)
+        counts = torch.empty(2, dtype=torch.int64, device=params.device)
+        hc = hits.c()
+        tr = _EmbedTruth(_ptr(pid), _ptr(query), _ptr(rnd))
+        self._raise(self._lib.velo_embed_train_grad(self._h, C.byref(hc), C.byref(tr), _ptr(params), int(k_train),
+                                                    float(d2_train), float(margin), float(w_genuine),
+                                                    _ptr(dparams), _ptr(loss), _ptr(counts), _ptr(emb),
+                                                    _stream()), "velo_embed_train_grad")
+        return dparams, loss, counts
 
 
 class Graph:

@@ -1,0 +1,129 @@
+"""GPU: embedding training (Sec. 5.1, the two loss equations) against the
+float64 oracle, whose pair sets and gradient are pinned in
+tests/test_oracle_embed_train.py.
+
+The oracle builds its pairs on the GPU's own float32 embedding (the
+neighbour list and the hinge decisions are float32 decisions, taken the same
+way on both sides), so the pair counts must agree exactly.  The loss and the
+gradient differ by float32 rounding of the embedding and of the per-pair
+terms: relative 1e-5 on the loss, and per weight tensor a relative error of
+the gradient vector (2-norm) below 1e-4.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle                                           # noqa: E402
+from paper_2407_12119_amd import synth, velo           # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+WL = synth.WORKLOADS["batch256"]
+E0 = 12
+SEGS = {"W1": (0, 384), "b1": (384, 128), "W2": (512, 16384), "b2": (16896, 128), "W3": (17024, 512),
+        "b3": (17536, 4)}
+NE = 17540
+
+
+def _setup(tb):
+    batch = tb.batch
+    print(f"\n[case] embed-train events={batch.n_events} hits={batch.n_hits}", flush=True)
+    ctx = velo.Context(WL.hidden, WL.iters, oracle.d2max_f32(WL.radius), WL.k_max, WL.edge_logit_min, "fp32",
+                       max_hits=max(batch.n_hits, 1), max_events=max(batch.n_events, 1),
+                       max_event_hits=max(batch.max_event_hits(), 1), training=True)
+    ctx.set_params(torch.from_numpy(synth.init_params(WL)).cuda())
+    hits = velo.DeviceHits.from_batch(batch)
+    dev = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a).astype(dt)).cuda()
+    truth = (dev(tb.pid, np.int32), dev(tb.query, np.uint8), dev(tb.rnd.view(np.int32), np.int32))
+    return ctx, hits, truth
+
+
+def _gpu(ctx, hits, truth, params, **kw):
+    emb = torch.empty((max(hits.n_hits, 1), 4), dtype=torch.float32, device="cuda")
+    g, loss, counts = ctx.embed_train_grad(hits, *truth, params, emb=emb, **kw)
+    torch.cuda.synchronize()
+    return g.cpu().numpy().astype(np.float64), loss.cpu().numpy(), counts.cpu().numpy(), emb.cpu().numpy()
+
+
+def _oracle(tb, blob, emb32, k_train=50, d2_train=1.5, margin=1.0, w=2.0):
+    parts = []
+    for b in range(tb.batch.n_events):
+        s, e = int(tb.batch.event_offsets[b]), int(tb.batch.event_offsets[b + 1])
+        ev = tb.batch.event(b)
+        parts.append(oracle.embed_train_sums(ev.x, ev.y, ev.z, ev.plane, tb.pid[s:e], tb.query[s:e], tb.rnd[s:e],
+                                             emb32[s:e], blob, k_train=k_train, d2_train=d2_train, margin=margin))
+    return oracle.embed_train_loss(parts, w)
+
+
+@pytest.mark.parametrize("k_train,d2_train,margin,w", [(50, 1.5, 1.0, 2.0), (7, 0.05, 0.02, 5.0)])
+def test_loss_and_gradient_match_oracle(k_train, d2_train, margin, w):
+    """Two events: the paper's k = 50, d2 = 1.5, m = 1, and a tight setting
+    where the neighbour lists and the hinges cut."""
+    tb = synth.embed_train_batch(synth.make_events(WL, 2, first=10), step=1)
+    blob = synth.init_params(WL)
+    ctx, hits, truth = _setup(tb)
+    params = torch.from_numpy(blob).cuda()
+    g, loss, counts, emb = _gpu(ctx, hits, truth, params, k_train=k_train, d2_train=d2_train, margin=margin,
+                                w_genuine=w)
+    e_or = np.concatenate([oracle.embed(tb.batch.event(b).x, tb.batch.event(b).y, tb.batch.event(b).z, blob)
+                           for b in range(tb.batch.n_events)])
+    assert np.abs(emb - e_or).max() <= 1e-5 * max(1.0, np.abs(e_or).max())
+    r = _oracle(tb, blob, emb, k_train, d2_train, margin, w)
+    assert (int(counts[0]), int(counts[1])) == (r["n_genuine"], r["n_fake"])
+    assert r["n_genuine"] > 100 and r["n_fake"] > 100
+    assert loss[0] == pytest.approx(r["loss"], rel=1e-5)
+    assert loss[1] == pytest.approx(r["loss_genuine"], rel=1e-5)
+    assert loss[2] == pytest.approx(r["loss_fake"], rel=1e-5, abs=1e-7)
+    for name, (o, m) in SEGS.items():
+        a, b = g[E0 + o:E0 + o + m], r["grad"][E0 + o:E0 + o + m]
+        if name == "b3":   # zero in exact arithmetic (translation invariance)
+            assert np.abs(a).max() <= 1e-5 * np.abs(r["grad"][E0:E0 + NE]).max()
+            continue
+        rel = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+        assert rel < 1e-4, (name, rel)
+    # entries outside the embedding are left alone (zeros from the caller)
+    assert not np.any(g[:E0]) and not np.any(g[E0 + NE:])
+
+
+def test_bitwise_repeatable_and_independent_of_pair_order():
+    tb = synth.embed_train_batch(synth.make_events(WL, 3, first=20), step=2)
+    blob = synth.init_params(WL)
+    ctx, hits, truth = _setup(tb)
+    params = torch.from_numpy(blob).cuda()
+    g1, l1, c1, _ = _gpu(ctx, hits, truth, params)
+    g2, l2, c2, _ = _gpu(ctx, hits, truth, params)
+    assert np.array_equal(g1, g2) and np.array_equal(l1, l2) and np.array_equal(c1, c2)
+
+
+def test_empty_batch_and_no_queries():
+    # no hits: zero loss, zero counts, zero embedding gradient
+    tb = synth.embed_train_batch([], step=0)
+    ctx, hits, truth = _setup(synth.embed_train_batch(synth.make_events(WL, 1, first=30), step=0))
+    empty = velo.DeviceHits.from_batch(tb.batch)
+    params = torch.from_numpy(synth.init_params(WL)).cuda()
+    g, loss, counts, _ = _gpu(ctx, empty, truth, params)
+    assert not np.any(g) and not np.any(loss) and not np.any(counts)
+    # hits but no query: nothing to learn from
+    tb = synth.embed_train_batch(synth.make_events(WL, 1, first=30), step=0)
+    q0 = torch.zeros_like(truth[1])
+    g, loss, counts, _ = _gpu(ctx, hits, (truth[0], q0, truth[2]), params)
+    assert not np.any(g) and not np.any(loss) and not np.any(counts)
+
+
+def test_adam_steps_reduce_the_loss():
+    """A few library Adam steps on the embedding entries lower the loss of
+    the same batch (training works end to end on the device)."""
+    tb = synth.embed_train_batch(synth.make_events(WL, 4, first=40), step=3)
+    ctx, hits, truth = _setup(tb)
+    params = torch.from_numpy(synth.init_params(WL)).cuda()
+    m = torch.zeros_like(params)
+    v = torch.zeros_like(params)
+    sl = slice(E0, E0 + NE)
+    losses = []
+    for step in range(1, 31):
+        g, loss, _ = ctx.embed_train_grad(hits, *truth, params, k_train=50, d2_train=1.5, margin=1.0, w_genuine=2.0)
+        losses.append(float(loss[0].cpu()))
+        ctx.adam_step(params[sl], g[sl], m[sl], v[sl], step, lr=1e-3)
+    torch.cuda.synchronize()
+    assert losses[-1] < 0.7 * losses[0], losses
