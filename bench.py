@@ -181,6 +181,104 @@ def run_training(velo, synth, torch, steps, warmup):
             "stage_ms_per_step": {k: round(v[0] / steps, 4) for k, v in stages.items() if v[1]}}
 
 
+EMB_TRAIN = {"k_train": 50, "d2_train": 1.5, "margin": 1.0, "w_genuine": 2.0}   # Sec. 5.1 (w: a reading)
+
+
+def run_embed_training(velo, synth, torch, steps, warmup, train_steps):
+    """Embedding training step (Sec. 5.1) on 32 noise-free events: loss and
+    gradient (pairs, hinge loss, back-propagation) and Adam on the embedding
+    entries.  Then, when train_steps > 0, train_steps steps over four such
+    batches and the rough graph (d2 < 0.9, k = 50: the paper's inference
+    values) of 32 other events with noise, before and after."""
+    import numpy as np
+    wl = synth.WORKLOADS["train32"]
+    tbs = [synth.embed_train_batch(synth.make_events(wl, 32, first=32 * i), step=i) for i in range(4)]
+    cap = max(tb.batch.n_hits for tb in tbs)
+    ctx = velo.Context(wl.hidden, wl.iters, float(np.float32(wl.radius * wl.radius)), wl.k_max,
+                       wl.edge_logit_min, "fp32", max_hits=cap, max_events=32,
+                       max_event_hits=max(tb.batch.max_event_hits() for tb in tbs), training=True)
+    blob = synth.init_params(wl)
+    params = torch.from_numpy(blob).cuda()
+    ctx.set_params(params)
+    dev = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a).astype(dt)).cuda()
+    data = [(velo.DeviceHits.from_batch(tb.batch), dev(tb.pid, np.int32), dev(tb.query, np.uint8),
+             dev(tb.rnd.view(np.int32), np.int32)) for tb in tbs]
+    sl = slice(12, 12 + 17540)
+    m, v = torch.zeros_like(params), torch.zeros_like(params)
+    grad = torch.zeros_like(params)
+    losses = []
+
+    def step(t, d, keep=False):
+        _, loss, _ = ctx.embed_train_grad(*d, params, dparams=grad, **EMB_TRAIN)
+        ctx.adam_step(params[sl], grad[sl], m[sl], v[sl], t, lr=1e-3)
+        if keep:
+            losses.append(loss)
+
+    for t in range(1, warmup + 1):
+        step(t, data[0])
+    ctx.set_timing(True)
+    ctx.read_timing()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for t in range(warmup + 1, warmup + steps + 1):
+        step(t, data[0])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    stages = ctx.read_timing()
+    ctx.set_timing(False)
+    ctx.check()
+    n0 = tbs[0].batch.n_hits
+    log(f"embedding training: {1e3 * dt / steps:.3f} ms/step")
+    res = {"workload": f"embed_train32: 32 noise-free events, {n0} hits, k_train={EMB_TRAIN['k_train']}, "
+                       f"d2_train={EMB_TRAIN['d2_train']}, m={EMB_TRAIN['margin']}, "
+                       f"w_genuine={EMB_TRAIN['w_genuine']}, fp32, Adam",
+           "steps_per_s": round(steps / dt, 2), "ms_per_step": round(1e3 * dt / steps, 3),
+           "stage_ms_per_step": {k: round(v[0] / steps, 4) for k, v in stages.items() if v[1]}}
+    if train_steps <= 0:
+        return res
+
+    # rough graph of 32 held-out events (with noise) at the paper's inference values
+    ev_batch = synth.make_batch(synth.WORKLOADS["batch256"], 32, first=1000)
+    gctx = velo.Context(wl.hidden, wl.iters, 0.9, 50, wl.edge_logit_min, "fp32",
+                        max_hits=ev_batch.n_hits, max_events=32, max_event_hits=ev_batch.max_event_hits())
+    ehits = velo.DeviceHits.from_batch(ev_batch)
+
+    def graph_stats(p):
+        gctx.set_params(p)
+        g = velo.graph_to_host(gctx.build_graph(ehits, gctx.embed(ehits)), ev_batch.n_hits)
+        true_total = found = 0
+        for b in range(ev_batch.n_events):
+            ev = ev_batch.event(b)
+            s, e = int(g["edge_offsets"][b]), int(g["edge_offsets"][b + 1])
+            have = set(zip(g["src"][s:e].tolist(), g["dst"][s:e].tolist()))
+            nh = ev.next_hit
+            for i in np.flatnonzero(nh >= 0):
+                if ev.plane[nh[i]] - ev.plane[i] in (1, 2):
+                    true_total += 1
+                    found += (int(i), int(nh[i])) in have
+        E = int(g["n_edges"])
+        return {"edges_per_hit": round(E / max(ev_batch.n_hits, 1), 2),
+                "true_edge_recall": round(found / max(true_total, 1), 4)}
+
+    before = graph_stats(torch.from_numpy(blob).cuda())
+    params.copy_(torch.from_numpy(blob).cuda())
+    m.zero_(); v.zero_()
+    losses.clear()
+    t0 = time.perf_counter()
+    for t in range(1, train_steps + 1):
+        step(t, data[(t - 1) % 4], keep=(t <= 4 or t > train_steps - 4))
+    torch.cuda.synchronize()
+    ttrain = time.perf_counter() - t0
+    after = graph_stats(params)
+    gctx.close()
+    ls = [float(x[0].cpu()) for x in losses]
+    res["training_run"] = {"steps": train_steps, "seconds": round(ttrain, 2),
+                           "loss_first": round(float(np.mean(ls[:4])), 5), "loss_last": round(float(np.mean(ls[-4:])), 5),
+                           "rough_graph_d2_0.9_k50": {"init": before, "trained": after}}
+    log(f"embedding training run: {json.dumps(res['training_run'])}")
+    return res
+
+
 def run_quality(velo, synth, torch, wl, batch, centred_blob, precisions, train_steps):
     """Track-finding quality at every precision on the benchmark batch, for two
     weight sets: the bias-centred random init the throughput is measured with,
@@ -412,6 +510,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="keep the built-in launch parameters")
     ap.add_argument("--no-quality", action="store_true", help="skip the track-finding quality block")
     ap.add_argument("--quality-steps", type=int, default=1500, help="training steps before the quality block")
+    ap.add_argument("--embed-train-steps", type=int, default=300,
+                    help="embedding training steps before the rough-graph comparison (with the quality block)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run a float32 add of this size (reads and writes known bytes): the reference "
                          "kernel that scales the HBM traffic counters of a profiled run")
@@ -455,8 +555,11 @@ def main():
         vctx.close()
         variants[prec] = vres
     training = None
+    embed_training = None
     if not args.no_train and args.workload == "batch256":
         training = run_training(velo, synth, torch, max(5, args.steps // 2), 2)
+        embed_training = run_embed_training(velo, synth, torch, max(5, args.steps // 2), 2,
+                                            0 if args.no_quality else args.embed_train_steps)
 
     quality = None
     if not args.no_quality and wl.hidden <= 64:          # the training form covers H <= 64
@@ -516,7 +619,7 @@ def main():
            "hits_per_s": main_res["hits_per_s"],
            "stage_ms_per_step": main_res["stage_ms_per_step"],
            "roofline": main_res["roofline"], "hbm_copy_GBps": copy_gbs, "cpu_baseline": cpu, "per_event_path": per_event,
-           "variants": variants, "training": training, "quality": quality}
+           "variants": variants, "training": training, "embed_training": embed_training, "quality": quality}
     for k in ("graph", "eager"):
         if k in main_res:
             res[k] = main_res[k]

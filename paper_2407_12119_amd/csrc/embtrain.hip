@@ -86,6 +86,9 @@ __global__ __launch_bounds__(256) void k_emb_pairs(int64_t n_hits, const int *__
         const int64_t base = s + c0;
         const f32x4 q = emb[i];
         const int pq = pid[i];
+        // this lane's share of the query's own sums (genuine 0..3, fake 4..7),
+        // added up over the wavefront before one atomic per entry
+        unsigned long long qs[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         auto same = [&](int64_t j) { return pq >= 0 && pid[j] == pq; };
         // one pair (i, j), handled by the calling lane
         auto pair = [&](int64_t j) {
@@ -103,11 +106,11 @@ __global__ __launch_bounds__(256) void k_emb_pairs(int64_t n_hits, const int *__
                 sf += to_fix(margin - d2, kLossFix);
                 sign = -1.f;
             }
-            unsigned long long *aq = acc + i * 8 + (gen ? 0 : 4), *aj = acc + j * 8 + (gen ? 0 : 4);
+            unsigned long long *aj = acc + j * 8 + (gen ? 0 : 4);
 #pragma unroll
             for (int c = 0; c < kD; c++) {
                 const float v = sign * 2.f * (q[c] - e[c]);
-                atomicAdd(aq + c, to_fix(v, kGradFix));
+                qs[(gen ? 0 : 4) + c] += to_fix(v, kGradFix);
                 atomicAdd(aj + c, to_fix(-v, kGradFix));
             }
         };
@@ -122,6 +125,15 @@ __global__ __launch_bounds__(256) void k_emb_pairs(int64_t n_hits, const int *__
             if (same(base + c)) pair(base + c);
         // the random pair
         if (C > 0 && lane == 0) pair(base + (int64_t)(((unsigned long long)rnd[i] * (unsigned)C) >> 32));
+#pragma unroll
+        for (int c = 0; c < 8; c++)
+            for (int o = 32; o > 0; o >>= 1) qs[c] += (unsigned long long)__shfl_xor((long long)qs[c], o);
+        if (lane < 8) {
+            unsigned long long v = qs[0];
+#pragma unroll
+            for (int c = 1; c < 8; c++) v = lane == c ? qs[c] : v;
+            if (v) atomicAdd(acc + i * 8 + lane, v);
+        }
     }
     for (int o = 32; o > 0; o >>= 1) {
         sg += (unsigned long long)__shfl_xor((long long)sg, o);

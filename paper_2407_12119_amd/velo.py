@@ -228,7 +228,7 @@ class Context:
         hc = hits.c()
         choice = np.zeros(len(STAGES), np.int32)
         self._raise(self._lib.velo_autotune(self._h, C.byref(hc), C.byref(oc), _stream(), choice.ctypes.data),
-                    "velo_autotune", "velo_embed_train_grad")
+                    "velo_autotune")
         return {k: int(choice[i]) for i, k in enumerate(STAGES)}
 
     def check(self):
