@@ -59,6 +59,8 @@ def lib() -> C.CDLL:
         L.oracle_embed_train.argtypes = [i64, p, p, p, p, p, p, p, p, p, C.c_int, C.c_int,
                                          C.c_int, f32, f64, p, p, p, p]
         L.oracle_embed_train.restype = C.c_int
+        L.oracle_focal.argtypes = [i64, p, p, f64, f64, p]
+        L.oracle_focal.restype = f64
         _lib = L
     return _lib
 
@@ -138,6 +140,14 @@ def bce(logit, y, pos_weight: float):
     logit, y = _c(logit, np.float64), _c(y, np.uint8)
     dz = np.zeros(logit.shape[0], np.float64)
     L = lib().oracle_bce(logit.shape[0], _ptr(logit), _ptr(y), float(pos_weight), _ptr(dz))
+    return float(L), dz
+
+
+def focal(logit, y, alpha: float = 0.25, gamma: float = 2.0):
+    """Sigmoid focal loss (Sec. 5.2) and dL/dlogit (float64); alpha < 0: no class weight."""
+    logit, y = _c(logit, np.float64), _c(y, np.uint8)
+    dz = np.zeros(logit.shape[0], np.float64)
+    L = lib().oracle_focal(logit.shape[0], _ptr(logit), _ptr(y), float(alpha), float(gamma), _ptr(dz))
     return float(L), dz
 
 

@@ -26,8 +26,8 @@
  *   components    Sec. 5 and Sec. 7.3: connected components of the purified
  *                 hit graph give the track labels
  *   loss/gradient weighted binary cross-entropy on the edge logits and its
- *                 exact gradient (training form; the paper trains with a
- *                 sigmoid focal loss, Sec. 5.2)
+ *                 exact gradient (training form), and the sigmoid focal loss
+ *                 the paper trains with (Sec. 5.2)
  *   embedding     Sec. 5.1, the two loss equations: pairwise hinge
  *   training      embedding loss over genuine pairs, hard negatives from the
  *                 bounded neighbour list and one random pair per query, and
@@ -647,6 +647,42 @@ int oracle_pipeline(int32_t B, const int32_t *event_offsets,
     }
     free(cnt);
     return rc;
+}
+
+/* ------------------------------------------------------------------ */
+/* Sec. 5.2: sigmoid focal loss (the paper's classifier loss)          */
+/* ------------------------------------------------------------------ */
+
+/*
+ * Sigmoid focal loss of Lin et al., which the paper trains the edge
+ * classifier with: p = sigmoid(z), p_t = p if y = 1 else 1 - p, the
+ * cross-entropy ce = softplus(z) - y z = -log p_t, a_t = alpha if y = 1 else
+ * 1 - alpha (alpha < 0: a_t = 1), and
+ *   L = (1/E) sum_q a_t (1 - p_t)^gamma ce.
+ * With s = 2y - 1, p_t = sigmoid(s z), 1 - p_t = sigmoid(-s z) and
+ * d p_t / dz = s p_t (1 - p_t), so
+ *   dL/dz = a_t (1 - p_t)^gamma [ (p - y) - gamma s p_t ce ] / E.
+ * Returns L (0 when E = 0); dz may be NULL.
+ */
+static double sigmoid64(double t)
+{
+    return t >= 0 ? 1.0 / (1.0 + exp(-t)) : exp(t) / (1.0 + exp(t));
+}
+
+double oracle_focal(int64_t E, const double *z, const uint8_t *yv, double alpha, double gamma, double *dz)
+{
+    double L = 0.0;
+    for (int64_t q = 0; q < E; q++) {
+        double y = yv[q] ? 1.0 : 0.0, s = 2.0 * y - 1.0, zz = z[q];
+        double at = alpha < 0 ? 1.0 : (yv[q] ? alpha : 1.0 - alpha);
+        double ce = (zz > 0 ? zz + log1p(exp(-zz)) : log1p(exp(zz))) - y * zz;
+        double pt = sigmoid64(s * zz), qt = sigmoid64(-s * zz);
+        double mod = gamma == 0.0 ? 1.0 : pow(qt, gamma);
+        L += at * mod * ce;
+        if (dz)
+            dz[q] = at * mod * ((sigmoid64(zz) - y) - gamma * s * pt * ce) / (double)E;
+    }
+    return E > 0 ? L / (double)E : 0.0;
 }
 
 /* ------------------------------------------------------------------ */
