@@ -242,6 +242,16 @@ velo_status velo_train_forward(velo_ctx *ctx, const velo_hits *hits, velo_output
 velo_status velo_bce(velo_ctx *ctx, const float *logit, const uint8_t *y, float pos_weight, int64_t n,
                      float *loss, float *dlogit, void *stream);
 
+/* Sigmoid focal loss on n logits, the classifier loss the paper trains with
+ * (Sec. 5.2; the form of Lin et al.): p_t = sigmoid(z) if y = 1 else
+ * 1 - sigmoid(z), a_t = alpha if y = 1 else 1 - alpha (alpha < 0: a_t = 1),
+ *   loss = (1/n) sum_q a_t (1 - p_t)^gamma [softplus(z_q) - y_q z_q],
+ *   dlogit_q = a_t (1 - p_t)^gamma [(sigmoid(z_q) - y_q) - gamma (2 y_q - 1) p_t ce_q] / n.
+ * alpha <= 1, gamma >= 0 (gamma = 0 and alpha < 0 give the plain
+ * cross-entropy).  logit, y (uint8 0/1), dlogit: [n] device; loss: [1] device. */
+velo_status velo_focal(velo_ctx *ctx, const float *logit, const uint8_t *y, float alpha, float gamma, int64_t n,
+                       float *loss, float *dlogit, void *stream);
+
 /* Reverse-mode pass of the last velo_train_forward: given dL/dlogit (device,
  * one per edge of that graph) writes dL/dparams (device, blob-shaped; the
  * normalisation and embedding entries are zero, graph building being not

@@ -491,6 +491,22 @@ velo_status velo_bce(velo_ctx *c, const float *logit, const uint8_t *y, float po
     return device_status(c, "velo_bce");
 }
 
+velo_status velo_focal(velo_ctx *c, const float *logit, const uint8_t *y, float alpha, float gamma, int64_t n,
+                       float *loss, float *dlogit, void *stream) {
+    if (!c) return VELO_ERR_INVALID_ARG;
+    if (!c->cfg.training) return fail(c, VELO_ERR_UNSUPPORTED, "context created without training = 1");
+    if (n < 0 || !loss || (n > 0 && (!logit || !y || !dlogit)))
+        return fail(c, VELO_ERR_INVALID_ARG, "velo_focal arguments");
+    if (!std::isfinite(alpha) || alpha > 1.f || !std::isfinite(gamma) || gamma < 0.f)
+        return fail(c, VELO_ERR_INVALID_ARG, "velo_focal: alpha must be <= 1 (negative: none), gamma >= 0");
+    DeviceGuard gd(c->device);
+    {
+        StageTimer t(c, VELO_STAGE_BCE, (hipStream_t)stream);
+        launch_focal(c, logit, y, alpha, gamma, n, loss, dlogit, (hipStream_t)stream);
+    }
+    return device_status(c, "velo_focal");
+}
+
 velo_status velo_train_backward(velo_ctx *c, const velo_hits *h, const float *params, const float *dlogit,
                                 float *dparams, void *stream) {
     if (!c) return VELO_ERR_INVALID_ARG;

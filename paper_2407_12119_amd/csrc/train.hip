@@ -709,6 +709,38 @@ __global__ __launch_bounds__(256) void k_bce(const float *__restrict__ z, const 
     if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
 }
 
+// Sigmoid focal loss (Sec. 5.2; the form of Lin et al.): with s = 2y - 1,
+// p_t = sigmoid(s z), ce = softplus(z) - y z = -log p_t, a_t = alpha (y = 1)
+// or 1 - alpha (alpha < 0: 1), the edge's term is a_t (1 - p_t)^gamma ce and
+// dL/dz = a_t (1 - p_t)^gamma [(sigmoid(z) - y) - gamma s p_t ce] / n.
+// Block partial sums of the terms go to part (summed by k_bce_total).
+__global__ __launch_bounds__(256) void k_focal(const float *__restrict__ z, const uint8_t *__restrict__ y,
+                                               float alpha, float gamma, int64_t n, float *__restrict__ dz,
+                                               float *__restrict__ part) {
+    __shared__ float sh[256];
+    float acc = 0.f;
+    const float inv = n > 0 ? 1.f / (float)n : 0.f;
+    auto sigmoid = [](float t) { return t >= 0.f ? 1.f / (1.f + expf(-t)) : expf(t) / (1.f + expf(t)); };
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float v = z[i];
+        const bool pos = y[i] != 0;
+        const float s = pos ? 1.f : -1.f;
+        const float at = alpha < 0.f ? 1.f : (pos ? alpha : 1.f - alpha);
+        const float ce = (v > 0.f ? v + log1pf(expf(-v)) : log1pf(expf(v))) - (pos ? v : 0.f);
+        const float pt = sigmoid(s * v), qt = sigmoid(-s * v);
+        const float mod = gamma == 0.f ? 1.f : powf(qt, gamma);
+        acc += at * mod * ce;
+        dz[i] = at * mod * ((sigmoid(v) - (pos ? 1.f : 0.f)) - gamma * s * pt * ce) * inv;
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int d = 128; d > 0; d >>= 1) {
+        if (threadIdx.x < d) sh[threadIdx.x] += sh[threadIdx.x + d];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
 __global__ void k_bce_total(const float *__restrict__ part, int64_t n, float *__restrict__ loss) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         float s = 0.f;
@@ -890,6 +922,12 @@ size_t train_red_floats(int H) { return (size_t)kRedGroups * (3 * H * H + H + H 
 void launch_bce(velo_ctx *c, const float *logit, const uint8_t *y, float pos_weight, int64_t n, float *loss,
                 float *dlogit, hipStream_t s) {
     k_bce<<<kLossBlocks, 256, 0, s>>>(logit, y, pos_weight, n, dlogit, c->ws.g_loss);
+    k_bce_total<<<1, 64, 0, s>>>(c->ws.g_loss, n, loss);
+}
+
+void launch_focal(velo_ctx *c, const float *logit, const uint8_t *y, float alpha, float gamma, int64_t n,
+                  float *loss, float *dlogit, hipStream_t s) {
+    k_focal<<<kLossBlocks, 256, 0, s>>>(logit, y, alpha, gamma, n, dlogit, c->ws.g_loss);
     k_bce_total<<<1, 64, 0, s>>>(c->ws.g_loss, n, loss);
 }
 

@@ -27,7 +27,7 @@ EXPORTS = ("velo_param_count", "velo_create", "velo_destroy", "velo_set_params",
            "velo_status_str", "velo_last_error", "velo_set_timing", "velo_read_timing",
            "velo_train_forward", "velo_bce", "velo_train_backward", "velo_adam_step",
            "velo_graph_capture", "velo_graph_launch", "velo_graph_destroy", "velo_calibrate",
-           "velo_autotune", "velo_embed_train_grad")
+           "velo_autotune", "velo_embed_train_grad", "velo_focal")
 STAGES = ("prepare", "embed", "knn", "compact", "lists", "node_enc", "edge_enc", "messages",
           "node_net", "edge_net", "edge_cls", "components", "bce", "bwd_mlp", "bwd_dw", "bwd_graph", "adam",
           "hit_proj", "emb_loss", "emb_bwd")
@@ -115,6 +115,8 @@ def lib() -> C.CDLL:
         L.velo_embed_train_grad.argtypes = [vp, C.POINTER(_Hits), C.POINTER(_EmbedTruth), vp, C.c_int32,
                                             C.c_float, C.c_float, C.c_float, vp, vp, vp, vp, vp]
         L.velo_embed_train_grad.restype = st
+        L.velo_focal.argtypes = [vp, vp, vp, C.c_float, C.c_float, C.c_int64, vp, vp, vp]
+        L.velo_focal.restype = st
         _lib = L
     return _lib
 
@@ -331,6 +333,16 @@ class Context:
         self._raise(self._lib.velo_bce(self._h, C.c_void_p(logit.data_ptr()), C.c_void_p(y.data_ptr()),
                                        float(pos_weight), n, C.c_void_p(loss.data_ptr()), C.c_void_p(dz.data_ptr()),
                                        _stream()), "velo_bce")
+        return loss, dz
+
+    def focal(self, logit, y, alpha: float, gamma: float, n: int):
+        """(loss [1], dlogit [n]) device tensors of the sigmoid focal loss on the first n logits."""
+        import torch
+        loss = torch.empty(1, dtype=torch.float32, device=logit.device)
+        dz = torch.empty(max(n, 1), dtype=torch.float32, device=logit.device)
+        self._raise(self._lib.velo_focal(self._h, C.c_void_p(logit.data_ptr()), C.c_void_p(y.data_ptr()),
+                                         float(alpha), float(gamma), n, C.c_void_p(loss.data_ptr()),
+                                         C.c_void_p(dz.data_ptr()), _stream()), "velo_focal")
         return loss, dz
 
     def train_backward(self, hits: DeviceHits, params, dlogit, dparams=None):

@@ -75,6 +75,25 @@ def test_bce_matches_oracle():
     np.testing.assert_allclose(dz.cpu().numpy(), dz_or, rtol=1e-5, atol=1e-12)
 
 
+@pytest.mark.parametrize("alpha,gamma", [(0.25, 2.0), (-1.0, 0.0), (0.6, 0.5)])
+def test_focal_matches_oracle(alpha, gamma):
+    """The sigmoid focal loss (Sec. 5.2) against the float64 oracle, on
+    logits that include confident ones (|z| up to ~15)."""
+    wl, batch = _small_batch()
+    ctx, hits, graph, params = _setup(wl, batch, synth.centred_params(wl))
+    rng = np.random.default_rng(2)
+    z = rng.normal(0, 5, 7001).astype(np.float32)
+    y = (rng.random(7001) < 0.3).astype(np.uint8)
+    loss, dz = ctx.focal(torch.from_numpy(z).cuda(), torch.from_numpy(y).cuda(), alpha, gamma, 7001)
+    L_or, dz_or = oracle.focal(z.astype(np.float64), y, alpha, gamma)
+    assert float(loss.cpu()[0]) == pytest.approx(L_or, rel=1e-5)
+    np.testing.assert_allclose(dz.cpu().numpy(), dz_or, rtol=1e-4, atol=1e-6 * np.abs(dz_or).max())
+    # gamma = 0 without class weights is the plain cross-entropy
+    if alpha < 0 and gamma == 0.0:
+        lb, db = ctx.bce(torch.from_numpy(z).cuda(), torch.from_numpy(y).cuda(), 1.0, 7001)
+        assert float(lb.cpu()[0]) == pytest.approx(float(loss.cpu()[0]), rel=1e-6)
+
+
 def test_backward_matches_oracle_gradient():
     wl, batch = _small_batch()
     _check_gradient(wl, batch, synth.centred_params(wl))
