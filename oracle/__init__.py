@@ -61,6 +61,8 @@ def lib() -> C.CDLL:
         L.oracle_embed_train.restype = C.c_int
         L.oracle_focal.argtypes = [i64, p, p, f64, f64, p]
         L.oracle_focal.restype = f64
+        L.oracle_components_sweep.argtypes = [i64, p, i64, p, p, p, p]
+        L.oracle_components_sweep.restype = C.c_int
         _lib = L
     return _lib
 
@@ -156,6 +158,16 @@ def components(n: int, src, dst, keep) -> np.ndarray:
     src, dst, keep = _c(src, np.int32), _c(dst, np.int32), _c(keep, np.uint8)
     lab = np.zeros(n, np.int32)
     rc = lib().oracle_components(n, src.shape[0], _ptr(src), _ptr(dst), _ptr(keep), _ptr(lab))
+    assert rc == 0, rc
+    return lab
+
+
+def components_sweep(plane, src, dst, keep) -> np.ndarray:
+    """Labels of the two plane sweeps of Sec. 7.3 (a comparison variant; not exact)."""
+    plane, src, dst, keep = _c(plane, np.int32), _c(src, np.int32), _c(dst, np.int32), _c(keep, np.uint8)
+    lab = np.zeros(plane.shape[0], np.int32)
+    rc = lib().oracle_components_sweep(plane.shape[0], _ptr(plane), src.shape[0], _ptr(src), _ptr(dst),
+                                       _ptr(keep), _ptr(lab))
     assert rc == 0, rc
     return lab
 

@@ -24,7 +24,8 @@
  *   threshold     Sec. 5 (pipeline overview): edges scoring below the cut are
  *                 dropped
  *   components    Sec. 5 and Sec. 7.3: connected components of the purified
- *                 hit graph give the track labels
+ *                 hit graph give the track labels (and, as a comparison
+ *                 variant, the paper's two plane sweeps)
  *   loss/gradient weighted binary cross-entropy on the edge logits and its
  *                 exact gradient (training form), and the sigmoid focal loss
  *                 the paper trains with (Sec. 5.2)
@@ -573,6 +574,40 @@ int oracle_components(int64_t n, int64_t E, const int32_t *src, const int32_t *d
 done:
     free(deg); free(adj_ptr); free(adj); free(fill); free(queue);
     return rc;
+}
+
+/*
+ * The two plane sweeps of Sec. 7.3, kept as a comparison variant (they are
+ * not exact on every graph).  Labels start as the event-local index.
+ * Forward, planes 1 .. N_PLANES-1 in order: each hit on plane p takes the
+ * smallest of its label and the labels of the hits joined to it by kept
+ * edges from planes p-1 and p-2.  Backward, planes N_PLANES-2 .. 0: each hit
+ * on plane p takes the smallest of its label and the labels of the hits its
+ * kept edges reach on planes p+1 and p+2.  Edges whose destination is not
+ * one or two planes after their source take no part.
+ */
+int oracle_components_sweep(int64_t n, const int32_t *plane, int64_t E, const int32_t *src,
+                            const int32_t *dst, const uint8_t *keep, int32_t *labels)
+{
+    const int n_planes = 26;
+    for (int64_t q = 0; q < E; q++)
+        if (src[q] < 0 || src[q] >= n || dst[q] < 0 || dst[q] >= n)
+            return -1;
+    for (int64_t i = 0; i < n; i++)
+        labels[i] = (int32_t)i;
+    for (int p = 1; p < n_planes; p++)
+        for (int64_t q = 0; q < E; q++) {
+            int gap = plane[dst[q]] - plane[src[q]];
+            if (keep[q] && plane[dst[q]] == p && (gap == 1 || gap == 2) && labels[src[q]] < labels[dst[q]])
+                labels[dst[q]] = labels[src[q]];
+        }
+    for (int p = n_planes - 2; p >= 0; p--)
+        for (int64_t q = 0; q < E; q++) {
+            int gap = plane[dst[q]] - plane[src[q]];
+            if (keep[q] && plane[src[q]] == p && (gap == 1 || gap == 2) && labels[dst[q]] < labels[src[q]])
+                labels[src[q]] = labels[dst[q]];
+        }
+    return 0;
 }
 
 /* ------------------------------------------------------------------ */

@@ -105,3 +105,53 @@ def test_plane_sweep_counterexample_is_not_exact():
     assert exact.tolist() == g["exact_labels"]
     sweep = _plane_sweep(len(plane), plane, src, dst, keep)
     assert sweep.tolist() == g["sweep_labels"] and sweep.tolist() != exact.tolist()
+
+
+def test_oracle_sweep_reproduces_the_worked_counterexample():
+    with open(os.path.join(GOLDEN, "wcc_sweep_counterexample.json")) as f:
+        g = json.load(f)
+    lab = oracle.components_sweep(np.array(g["plane"]), np.array(g["src"]), np.array(g["dst"]),
+                                  np.ones(len(g["src"]), np.uint8))
+    assert lab.tolist() == g["sweep_labels"]
+
+
+def _event_graph(seed, keep_frac):
+    from paper_2407_12119_amd import synth
+    ev = synth.make_event(synth.WORKLOADS["batch256"].recipe, synth.event_rng(0, 500 + seed))
+    rng = np.random.default_rng(seed)
+    src, dst = [], []
+    for i in range(ev.n):
+        c = np.flatnonzero(np.isin(ev.plane - ev.plane[i], [1, 2]))
+        if c.size:
+            for j in rng.choice(c, size=min(3, c.size), replace=False):
+                src.append(i); dst.append(int(j))
+    src, dst = np.array(src, np.int32), np.array(dst, np.int32)
+    keep = (rng.random(src.shape[0]) < keep_frac).astype(np.uint8)
+    return ev, src, dst, keep
+
+
+def test_sweep_is_exact_on_chains():
+    # true track segments (each hit joined to its particle's next hit): every
+    # hit has at most one kept edge on each side, and both sweeps then give
+    # exactly the components
+    from paper_2407_12119_amd import synth
+    for e in range(3):
+        ev = synth.make_event(synth.WORKLOADS["batch256"].recipe, synth.event_rng(0, 600 + e))
+        i = np.flatnonzero((ev.next_hit >= 0))
+        i = i[np.isin(ev.plane[ev.next_hit[i]] - ev.plane[i], [1, 2])]
+        src, dst = i.astype(np.int32), ev.next_hit[i].astype(np.int32)
+        keep = np.ones(src.shape[0], np.uint8)
+        assert np.array_equal(oracle.components_sweep(ev.plane, src, dst, keep),
+                              oracle.components(ev.n, src, dst, keep))
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_sweep_invariants_on_branching_graphs(seed):
+    ev, src, dst, keep = _event_graph(seed, 0.3)
+    sweep = oracle.components_sweep(ev.plane, src, dst, keep)
+    exact = oracle.components(ev.n, src, dst, keep)
+    idx = np.arange(ev.n)
+    assert np.all(sweep <= idx) and np.all(sweep >= exact)     # only labels of its component, never above own
+    assert np.all(exact[sweep] == exact)                      # a label is a hit of the same component
+    assert np.array_equal(sweep, _plane_sweep(ev.n, ev.plane, src, dst, keep))
+    assert np.any(sweep != exact)                             # branching graphs do break the sweep
