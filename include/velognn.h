@@ -168,6 +168,18 @@ velo_status velo_gnn(velo_ctx *ctx, const velo_hits *hits, velo_outputs *graph, 
  * writes graph->labels. */
 velo_status velo_components(velo_ctx *ctx, const velo_hits *hits, velo_outputs *graph, void *stream);
 
+/* Comparison variant of velo_components: the paper's two plane sweeps
+ * (Sec. 7.3) instead of exact components.  Labels start as the event-local
+ * index; forward over planes 1 .. 25 each hit takes the smallest of its
+ * label and those of the hits joined to it by kept edges from planes p-1 and
+ * p-2, then backward over planes 24 .. 0 the smallest of its label and those
+ * of the hits its kept edges reach on planes p+1 and p+2.  Edges that do not
+ * go one or two planes forward take no part.  The result can leave one
+ * component with several labels (a hit joined to two hits of an earlier
+ * plane passes on only the smaller label), which is why velo_components is
+ * exact instead.  Same arguments and errors as velo_components. */
+velo_status velo_components_sweep(velo_ctx *ctx, const velo_hits *hits, velo_outputs *graph, void *stream);
+
 /* Stages of the path, for per-stage device timing. */
 typedef enum {
     VELO_STAGE_PREPARE = 0,    /* validation and plane bucketing */

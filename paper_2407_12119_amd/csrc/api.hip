@@ -345,6 +345,21 @@ velo_status velo_components(velo_ctx *c, const velo_hits *h, velo_outputs *g, vo
     return device_status(c, "velo_components");
 }
 
+velo_status velo_components_sweep(velo_ctx *c, const velo_hits *h, velo_outputs *g, void *stream) {
+    if (!c) return VELO_ERR_INVALID_ARG;
+    velo_status st = check_hits(c, h);
+    if (st) return st;
+    if ((st = graph_args(c, h, g))) return st;
+    if (h->n_hits > 0 && !g->labels) return fail(c, VELO_ERR_INVALID_ARG, "labels is NULL");
+    if (g->edge_capacity > 0 && !g->edge_logit) return fail(c, VELO_ERR_INVALID_ARG, "edge_logit is NULL");
+    DeviceGuard gd(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    { StageTimer t(c, VELO_STAGE_PREPARE, s); launch_prepare(c, h, s); }
+    { StageTimer t(c, VELO_STAGE_COMPACT, s); launch_globalise(c, h, g, s); }
+    { StageTimer t(c, VELO_STAGE_COMPONENTS, s); launch_components_sweep(c, h, g, s); }
+    return device_status(c, "velo_components_sweep");
+}
+
 velo_status velo_infer(velo_ctx *c, const velo_hits *h, velo_outputs *o, void *stream) {
     if (!c) return VELO_ERR_INVALID_ARG;
     if (c->cfg.precision == VELO_FP8 && !c->calibrated)

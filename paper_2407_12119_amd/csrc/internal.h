@@ -130,6 +130,7 @@ void launch_in_lists_plane(velo_ctx *c, const velo_hits *h, hipStream_t s);
 size_t state_bytes(int precision);              // bytes per stored encoding element
 bool gnn_supported(int hidden, int precision);  // compiled (hidden, precision) pairs
 void launch_embed(velo_ctx *c, const velo_hits *h, float *emb, bool calib, hipStream_t s);
+void launch_components_sweep(velo_ctx *c, const velo_hits *h, const velo_outputs *g, hipStream_t s);
 void launch_focal(velo_ctx *c, const float *logit, const uint8_t *y, float alpha, float gamma, int64_t n,
                   float *loss, float *dlogit, hipStream_t s);
 void launch_embed_train(velo_ctx *c, const velo_hits *h, const float *params, float *emb, float *sv,

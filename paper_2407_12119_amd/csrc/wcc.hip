@@ -89,7 +89,93 @@ __global__ __launch_bounds__(1024) void k_wcc(int B, const int *__restrict__ off
     for (int l = threadIdx.x; l < n; l += blockDim.x) labels[s + l] = find_root(par, l);
 }
 
+// The two plane sweeps of Sec. 7.3, kept as a comparison variant (not exact
+// on every graph; see the file comment).  One workgroup per event, labels in
+// LDS, starting as the event-local index.  Forward, planes 1 .. 25: each hit
+// on plane p takes the smallest of its label and the labels of the hits
+// joined to it by kept edges from planes p-1 and p-2; backward, planes 24 .. 0:
+// the smallest of its label and those of the hits its kept edges reach on
+// planes p+1 and p+2.  Edges are grouped by source and sources are sorted by
+// plane, so the edges leaving plane q are one range, found by binary search;
+// a plane step reads only labels of other planes, so it is an LDS atomicMin
+// per edge whose result does not depend on the order.
+__global__ __launch_bounds__(1024) void k_wcc_sweep(int B, const int *__restrict__ off, const int *__restrict__ eoff,
+                                                    const int *__restrict__ n_edges, int64_t cap,
+                                                    const int *__restrict__ esrc, const int *__restrict__ edst,
+                                                    const float *__restrict__ logit, float thr,
+                                                    const int *__restrict__ plane, const int *__restrict__ plane_off,
+                                                    int *__restrict__ labels, int max_ev,
+                                                    unsigned *__restrict__ flags) {
+    extern __shared__ int lab[];
+    __shared__ int epl[kPlaneSlots];   // first edge of each source plane (and the end)
+    if (*flags) return;
+    const int b = blockIdx.x;
+    const int s = off[b], n = off[b + 1] - s;
+    if (n > max_ev) return;     // rejected by validation
+    const int E = min((int64_t)*n_edges, cap);
+    const int e0 = min(eoff[b], E), e1 = min(eoff[b + 1], E);
+    const int *po = plane_off + (int64_t)b * kPlaneSlots;
+    for (int l = threadIdx.x; l < n; l += blockDim.x) lab[l] = l;
+    if (threadIdx.x < kPlaneSlots) {
+        const int first = po[threadIdx.x];    // first event-local hit on this plane or later
+        int lo = e0, hi = e1;                 // first edge whose source is at or after it
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (esrc[mid] < first) lo = mid + 1;
+            else hi = mid;
+        }
+        epl[threadIdx.x] = lo;
+    }
+    __syncthreads();
+    bool err = false;
+    auto ok = [&](int u, int v) {
+        if (u < 0 || u >= n || v < 0 || v >= n) {
+            err = true;
+            return false;
+        }
+        return true;
+    };
+    for (int p = 1; p < VELO_N_PLANES; p++) {
+        for (int q = epl[max(p - 2, 0)] + threadIdx.x; q < epl[p]; q += blockDim.x) {
+            const int u = esrc[q], v = edst[q];
+            if (!(logit[q] >= thr) || !ok(u, v)) continue;
+            const int pu = plane[s + u], pv = plane[s + v];
+            if (pv == p && (pv - pu == 1 || pv - pu == 2)) atomicMin(&lab[v], lab[u]);
+        }
+        __syncthreads();
+    }
+    for (int p = VELO_N_PLANES - 2; p >= 0; p--) {
+        for (int q = epl[p] + threadIdx.x; q < epl[p + 1]; q += blockDim.x) {
+            const int u = esrc[q], v = edst[q];
+            if (!(logit[q] >= thr) || !ok(u, v)) continue;
+            const int pu = plane[s + u], pv = plane[s + v];
+            if (pu == p && (pv - pu == 1 || pv - pu == 2)) atomicMin(&lab[u], lab[v]);
+        }
+        __syncthreads();
+    }
+    if (err) atomicOr(flags, kErrInput);
+    for (int l = threadIdx.x; l < n; l += blockDim.x) labels[s + l] = lab[l];
+}
+
 }  // namespace
+
+void launch_components_sweep(velo_ctx *c, const velo_hits *h, const velo_outputs *g, hipStream_t s) {
+    if (h->n_events <= 0) return;
+    const int64_t cap = g->edge_capacity < c->cfg.max_edges ? g->edge_capacity : c->cfg.max_edges;
+    const size_t lds = sizeof(int) * (size_t)(c->cfg.max_event_hits > 0 ? c->cfg.max_event_hits : 1);
+    static bool attr = false;
+    if (!attr) {
+        // the kernel's static LDS (the plane ranges) comes out of the same budget
+        hipFuncSetAttribute(reinterpret_cast<const void *>(&k_wcc_sweep),
+                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)(c->lds_max - sizeof(int) * kPlaneSlots));
+        attr = true;
+    }
+    k_wcc_sweep<<<h->n_events, 1024, lds, s>>>(h->n_events, h->event_offsets, g->edge_offsets, c->ws.n_edges, cap,
+                                               g->edge_src, g->edge_dst, g->edge_logit, c->cfg.edge_logit_min,
+                                               h->plane, c->ws.plane_off, g->labels, c->cfg.max_event_hits,
+                                               c->ws.flags);
+}
 
 void launch_components(velo_ctx *c, const velo_hits *h, const velo_outputs *g, hipStream_t s) {
     if (h->n_events <= 0) return;

@@ -27,7 +27,7 @@ EXPORTS = ("velo_param_count", "velo_create", "velo_destroy", "velo_set_params",
            "velo_status_str", "velo_last_error", "velo_set_timing", "velo_read_timing",
            "velo_train_forward", "velo_bce", "velo_train_backward", "velo_adam_step",
            "velo_graph_capture", "velo_graph_launch", "velo_graph_destroy", "velo_calibrate",
-           "velo_autotune", "velo_embed_train_grad", "velo_focal")
+           "velo_autotune", "velo_embed_train_grad", "velo_focal", "velo_components_sweep")
 STAGES = ("prepare", "embed", "knn", "compact", "lists", "node_enc", "edge_enc", "messages",
           "node_net", "edge_net", "edge_cls", "components", "bce", "bwd_mlp", "bwd_dw", "bwd_graph", "adam",
           "hit_proj", "emb_loss", "emb_bwd")
@@ -117,6 +117,8 @@ def lib() -> C.CDLL:
         L.velo_embed_train_grad.restype = st
         L.velo_focal.argtypes = [vp, vp, vp, C.c_float, C.c_float, C.c_int64, vp, vp, vp]
         L.velo_focal.restype = st
+        L.velo_components_sweep.argtypes = [vp, C.POINTER(_Hits), C.POINTER(_Outputs), vp]
+        L.velo_components_sweep.restype = st
         _lib = L
     return _lib
 
@@ -298,6 +300,16 @@ class Context:
         hc = hits.c()
         self._raise(self._lib.velo_components(self._h, C.byref(hc), C.byref(oc), _stream()),
                     "velo_components")
+        if check:
+            self.check()
+        return graph
+
+    def components_sweep(self, hits: DeviceHits, graph, check: bool = True):
+        """The paper's two plane sweeps (Sec. 7.3) into graph["labels"]: a comparison variant."""
+        oc = self._out_c(graph)
+        hc = hits.c()
+        self._raise(self._lib.velo_components_sweep(self._h, C.byref(hc), C.byref(oc), _stream()),
+                    "velo_components_sweep")
         if check:
             self.check()
         return graph

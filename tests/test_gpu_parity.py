@@ -426,3 +426,52 @@ def test_autotuned_launches_give_identical_results(precision):
     got = velo.graph_to_host(ctx.infer(hits), batch.n_hits)
     for k in ("edge_offsets", "src", "dst", "logit", "labels"):
         np.testing.assert_array_equal(got[k], ref[k], err_msg=k)
+
+
+def test_plane_sweep_variant_matches_oracle_sweep():
+    """The paper's two plane sweeps (Sec. 7.3), kept as a comparison variant:
+    labels bit-exact against the oracle's sweep on the GPU's own decisions,
+    and the share of hits they label differently from exact components."""
+    wl = synth.WORKLOADS["batch256"]
+    batch = synth.make_batch(wl, n_events=6, first=60)
+    ctx, hits, blob = _setup(wl, batch)
+    out = ctx.infer(hits)
+    exact = out["labels"].clone()
+    ctx.components_sweep(hits, out)
+    g = velo.graph_to_host(out, batch.n_hits)
+    sweep = g["labels"]
+    ex = exact.cpu().numpy()
+    differ = 0
+    for b in range(batch.n_events):
+        ev = batch.event(b)
+        o = int(batch.event_offsets[b])
+        s, e = int(g["edge_offsets"][b]), int(g["edge_offsets"][b + 1])
+        keep = (g["logit"][s:e] >= wl.edge_logit_min).astype(np.uint8)
+        ref = oracle.components_sweep(ev.plane, g["src"][s:e], g["dst"][s:e], keep)
+        np.testing.assert_array_equal(sweep[o:o + ev.n], ref, err_msg=f"event {b}")
+        np.testing.assert_array_equal(ex[o:o + ev.n], oracle.components(ev.n, g["src"][s:e], g["dst"][s:e], keep))
+        differ += int(np.sum(ref != ex[o:o + ev.n]))
+    print(f"[sweep] hits labelled differently from exact components: {differ} of {batch.n_hits}", flush=True)
+    assert differ > 0          # the centred init keeps branching graphs, where the sweep is not exact
+
+
+def test_plane_sweep_variant_on_the_worked_counterexample():
+    """Hits sorted by plane: 0, 1 on plane 0 and 2, 3 on plane 1; kept edges
+    0->2, 1->2, 1->3.  The sweeps give [0, 0, 0, 1]; the component is {0..3}."""
+    wl = synth.WORKLOADS["batch256"]
+    plane = np.array([0, 0, 1, 1], np.int32)
+    x = np.array([10.0, 11.0, 10.0, 11.0], np.float32)
+    ev = synth.Event(x, x.copy(), synth.PLANE_Z[plane].astype(np.float32), plane, np.full(4, -1, np.int64),
+                     np.full(4, -1, np.int32))
+    batch = synth.to_batch([ev])
+    ctx, hits, _ = _setup(wl, batch)
+    out = ctx.alloc_outputs(hits)
+    out["edge_offsets"].copy_(torch.tensor([0, 3], dtype=torch.int32))
+    out["edge_src"][:3].copy_(torch.tensor([0, 1, 1], dtype=torch.int32))
+    out["edge_dst"][:3].copy_(torch.tensor([2, 2, 3], dtype=torch.int32))
+    out["edge_logit"][:3].fill_(1.0)
+    out["n_edges"].fill_(3)
+    ctx.components_sweep(hits, out)
+    assert out["labels"].cpu().numpy().tolist() == [0, 0, 0, 1]
+    ctx.components(hits, out)
+    assert out["labels"].cpu().numpy().tolist() == [0, 0, 0, 0]
