@@ -403,6 +403,28 @@ def transfer_times(torch, batch, out, n_edges, reps=5):
             "d2h_ms": round(1e3 * float(np.median(d2h)), 4), "d2h_bytes": nb_out}
 
 
+def sweep_compare(ctx, torch, hits, reps=10):
+    """The paper's plane-sweep components (Sec. 7.3; a comparison variant)
+    against the exact components on the same decisions: the time of each
+    components stage and the share of hits the sweep labels differently."""
+    out = ctx.infer(hits)
+    exact = out["labels"].clone()
+    times = {}
+    for name, fn in (("exact", ctx.components), ("sweep", ctx.components_sweep)):
+        fn(hits, out)
+        ctx.set_timing(True)
+        ctx.read_timing()
+        for _ in range(reps):
+            fn(hits, out, check=False)
+        torch.cuda.synchronize()
+        times[name] = round(ctx.read_timing()["components"][0] / reps, 4)
+        ctx.set_timing(False)
+    differ = int((out["labels"][:hits.n_hits] != exact[:hits.n_hits]).sum().cpu())
+    ctx.check()
+    return {"exact_ms": times["exact"], "sweep_ms": times["sweep"], "hits": hits.n_hits,
+            "hits_labelled_differently": differ, "fraction": round(differ / max(hits.n_hits, 1), 5)}
+
+
 def run_batched(velo, synth, torch, wl, batch, hits, blob, prec, steps, warmup, graph=False, latency=False,
                 autotune=True, copy_gbs=None):
     import numpy as np
@@ -548,6 +570,8 @@ def main():
 
     ctx, main_res = run_batched(velo, synth, torch, wl, batch, hits, blob, args.precision, args.steps,
                                 args.warmup, args.graph, args.latency, not args.no_autotune, copy_gbs)
+    sweep = sweep_compare(ctx, torch, hits)
+    log(f"components, exact vs the paper's plane sweeps: {json.dumps(sweep)}")
     variants = {}
     for prec in [p for p in args.variants.split(",") if p and p != args.precision]:
         vctx, vres = run_batched(velo, synth, torch, wl, batch, hits, blob, prec, args.steps, args.warmup,
@@ -619,7 +643,7 @@ def main():
            "hits_per_s": main_res["hits_per_s"],
            "stage_ms_per_step": main_res["stage_ms_per_step"],
            "roofline": main_res["roofline"], "hbm_copy_GBps": copy_gbs, "cpu_baseline": cpu, "per_event_path": per_event,
-           "variants": variants, "training": training, "embed_training": embed_training, "quality": quality}
+           "variants": variants, "training": training, "embed_training": embed_training, "components_sweep": sweep, "quality": quality}
     for k in ("graph", "eager"):
         if k in main_res:
             res[k] = main_res[k]
