@@ -425,6 +425,30 @@ def sweep_compare(ctx, torch, hits, reps=10):
             "hits_labelled_differently": differ, "fraction": round(differ / max(hits.n_hits, 1), 5)}
 
 
+def knn_compare(ctx, torch, hits, reps=5):
+    """The paper's per-hit neighbour loop (Sec. 7.2; a comparison variant)
+    against the wavefront search, on the same embedding: neighbour-search
+    stage time of each and whether the graphs agree."""
+    emb = ctx.embed(hits)
+    times, graphs = {}, {}
+    for name, fn in (("wavefront", ctx.build_graph), ("paper_loop", ctx.build_graph_loop)):
+        out = fn(hits, emb)
+        ctx.set_timing(True)
+        ctx.read_timing()
+        for _ in range(reps):
+            fn(hits, emb, out=out, check=False)
+        torch.cuda.synchronize()
+        times[name] = round(ctx.read_timing()["knn"][0] / reps, 4)
+        ctx.set_timing(False)
+        n = int(out["n_edges"].cpu()[0])
+        graphs[name] = (out["edge_dst"][:n].clone(), out["edge_offsets"].clone())
+    ctx.check()
+    same = bool(torch.equal(graphs["wavefront"][0], graphs["paper_loop"][0]) and
+                torch.equal(graphs["wavefront"][1], graphs["paper_loop"][1]))
+    return {"wavefront_ms": times["wavefront"], "paper_loop_ms": times["paper_loop"],
+            "speedup": round(times["paper_loop"] / max(times["wavefront"], 1e-9), 2), "same_graph": same}
+
+
 def run_batched(velo, synth, torch, wl, batch, hits, blob, prec, steps, warmup, graph=False, latency=False,
                 autotune=True, copy_gbs=None):
     import numpy as np
@@ -572,6 +596,8 @@ def main():
                                 args.warmup, args.graph, args.latency, not args.no_autotune, copy_gbs)
     sweep = sweep_compare(ctx, torch, hits)
     log(f"components, exact vs the paper's plane sweeps: {json.dumps(sweep)}")
+    knn_loop = knn_compare(ctx, torch, hits)
+    log(f"neighbour search, wavefront vs the paper's per-hit loop: {json.dumps(knn_loop)}")
     variants = {}
     for prec in [p for p in args.variants.split(",") if p and p != args.precision]:
         vctx, vres = run_batched(velo, synth, torch, wl, batch, hits, blob, prec, args.steps, args.warmup,
@@ -643,7 +669,7 @@ def main():
            "hits_per_s": main_res["hits_per_s"],
            "stage_ms_per_step": main_res["stage_ms_per_step"],
            "roofline": main_res["roofline"], "hbm_copy_GBps": copy_gbs, "cpu_baseline": cpu, "per_event_path": per_event,
-           "variants": variants, "training": training, "embed_training": embed_training, "components_sweep": sweep, "quality": quality}
+           "variants": variants, "training": training, "embed_training": embed_training, "components_sweep": sweep, "knn_paper_loop": knn_loop, "quality": quality}
     for k in ("graph", "eager"):
         if k in main_res:
             res[k] = main_res[k]

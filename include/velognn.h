@@ -155,6 +155,15 @@ velo_status velo_embed(velo_ctx *ctx, const velo_hits *hits, float *emb, void *s
 velo_status velo_build_graph(velo_ctx *ctx, const velo_hits *hits, const float *emb,
                              velo_outputs *graph, void *stream);
 
+/* Comparison variant of velo_build_graph with the paper's neighbour search
+ * (Sec. 7.2): one thread per hit loops over its candidates in index order
+ * and keeps at most k_max of them, replacing the list's largest (d2, j)
+ * entry when a closer candidate comes.  Same result as velo_build_graph
+ * (the k_max smallest under (d2, j)); slower, since it does not spread a
+ * hit's candidates over lanes.  Same arguments and errors. */
+velo_status velo_build_graph_loop(velo_ctx *ctx, const velo_hits *hits, const float *emb, velo_outputs *graph,
+                                  void *stream);
+
 /* Stage: GNN edge logits (Sec. 5.2) for a given graph: reads
  * graph->edge_offsets, edge_src, edge_dst and n_edges (edges grouped by event
  * and sorted by source within an event, as velo_build_graph writes them)

@@ -309,6 +309,21 @@ velo_status velo_build_graph(velo_ctx *c, const velo_hits *h, const float *emb, 
     return device_status(c, "velo_build_graph");
 }
 
+velo_status velo_build_graph_loop(velo_ctx *c, const velo_hits *h, const float *emb, velo_outputs *g,
+                                  void *stream) {
+    if (!c) return VELO_ERR_INVALID_ARG;
+    velo_status st = check_hits(c, h);
+    if (st) return st;
+    if ((st = graph_args(c, h, g))) return st;
+    if (h->n_hits > 0 && !emb) return fail(c, VELO_ERR_INVALID_ARG, "emb is NULL");
+    DeviceGuard gd(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    { StageTimer t(c, VELO_STAGE_PREPARE, s); launch_prepare(c, h, s); }
+    { StageTimer t(c, VELO_STAGE_KNN, s); launch_knn_loop(c, h, emb, s); }
+    { StageTimer t(c, VELO_STAGE_COMPACT, s); launch_compact(c, h, g, s); }
+    return device_status(c, "velo_build_graph_loop");
+}
+
 velo_status velo_gnn(velo_ctx *c, const velo_hits *h, velo_outputs *g, void *stream) {
     if (!c) return VELO_ERR_INVALID_ARG;
     if (c->cfg.precision == VELO_FP8 && !c->calibrated)

@@ -364,6 +364,73 @@ __global__ __launch_bounds__(kKnnBlock) void k_knn(int64_t n_hits, const int *__
 }
 
 // ------------------------------------------------------------------------
+// The paper's neighbour search (Sec. 7.2), kept as a comparison variant: one
+// thread per query hit loops over the candidates in index order and keeps a
+// list of at most kmax (d2, j); when the list is full, its largest entry is
+// found and replaced by a closer candidate.  With candidates in increasing j
+// and the largest entry under (d2, j) evicted, the list ends as the kmax
+// smallest under (d2, j): the same selection as k_knn.  Lists live in LDS
+// (kLoopBlock threads x kmax entries); the survivors are written in index
+// order.
+// ------------------------------------------------------------------------
+constexpr int kLoopBlock = 64;
+constexpr int kLoopMaxK = 64;
+
+__global__ __launch_bounds__(kLoopBlock) void k_knn_loop(int64_t n_hits, const int *__restrict__ off,
+                                                         const int *__restrict__ plane_off,
+                                                         const int *__restrict__ hit_event,
+                                                         const int *__restrict__ plane,
+                                                         const f32x4 *__restrict__ emb, float d2max, int kmax,
+                                                         int *__restrict__ nbr, int *__restrict__ deg,
+                                                         const unsigned *__restrict__ flags) {
+    __shared__ float ld[kLoopBlock][kLoopMaxK];
+    __shared__ int lj[kLoopBlock][kLoopMaxK];
+    if (*flags & kErrInput) return;
+    float *dl = ld[threadIdx.x];
+    int *jl = lj[threadIdx.x];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_hits; i += (int64_t)gridDim.x * blockDim.x) {
+        const int b = hit_event[i];
+        const int64_t s = off[b];
+        const int p = plane[i];
+        const int *po = plane_off + (int64_t)b * kPlaneSlots;
+        const int c0 = po[min(p + 1, VELO_N_PLANES)];
+        const int C = max(po[min(p + 3, VELO_N_PLANES)] - c0, 0);
+        const f32x4 q = emb[i];
+        int cnt = 0;
+        for (int c = 0; c < C; c++) {
+            const float d = dist2(q, emb[s + c0 + c]);
+            if (!(d < d2max)) continue;
+            if (cnt < kmax) {
+                dl[cnt] = d;
+                jl[cnt] = c0 + c;
+                cnt++;
+                continue;
+            }
+            int m = 0;   // the largest entry under (d2, j)
+            for (int a = 1; a < kmax; a++)
+                if (dl[a] > dl[m] || (dl[a] == dl[m] && jl[a] > jl[m])) m = a;
+            if (d < dl[m]) {
+                dl[m] = d;
+                jl[m] = c0 + c;
+            }
+        }
+        // index order (insertion sort of the short list)
+        for (int a = 1; a < cnt; a++) {
+            const int v = jl[a];
+            int z = a - 1;
+            while (z >= 0 && jl[z] > v) {
+                jl[z + 1] = jl[z];
+                z--;
+            }
+            jl[z + 1] = v;
+        }
+        int *out = nbr + i * kmax;
+        for (int a = 0; a < cnt; a++) out[a] = jl[a];
+        deg[i] = cnt;
+    }
+}
+
+// ------------------------------------------------------------------------
 // exclusive scan of int32 counts: out[0..n] with out[n] = total
 // ------------------------------------------------------------------------
 constexpr int kScanBlock = 256;
@@ -694,6 +761,13 @@ void launch_knn_into(velo_ctx *c, const velo_hits *h, const float *emb, int kmax
     k_knn<<<blocks, kKnnBlock, 0, s>>>(h->n_hits, h->event_offsets, c->ws.plane_off, c->ws.hit_event,
                                        h->plane, (const f32x4 *)emb, d2max, kmax, nbr, deg,
                                        c->tune_xcd[VELO_STAGE_KNN], c->ws.flags);
+}
+
+void launch_knn_loop(velo_ctx *c, const velo_hits *h, const float *emb, hipStream_t s) {
+    if (h->n_hits <= 0) return;
+    k_knn_loop<<<grid_for(h->n_hits, kLoopBlock), kLoopBlock, 0, s>>>(
+        h->n_hits, h->event_offsets, c->ws.plane_off, c->ws.hit_event, h->plane, (const f32x4 *)emb, c->cfg.d2_max,
+        c->cfg.k_max, c->ws.nbr, c->ws.deg, c->ws.flags);
 }
 
 void launch_knn(velo_ctx *c, const velo_hits *h, const float *emb, hipStream_t s) {

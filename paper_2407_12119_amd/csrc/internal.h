@@ -116,6 +116,7 @@ namespace velo {
 // ---- launchers (graph.hip) ----
 void launch_prepare(velo_ctx *c, const velo_hits *h, hipStream_t s);
 void launch_knn(velo_ctx *c, const velo_hits *h, const float *emb, hipStream_t s);
+void launch_knn_loop(velo_ctx *c, const velo_hits *h, const float *emb, hipStream_t s);
 void launch_knn_into(velo_ctx *c, const velo_hits *h, const float *emb, int kmax, float d2max, int *nbr, int *deg,
                      hipStream_t s);
 void launch_scan(velo_ctx *c, const int *in, int *out, int64_t n, hipStream_t s);

@@ -27,7 +27,8 @@ EXPORTS = ("velo_param_count", "velo_create", "velo_destroy", "velo_set_params",
            "velo_status_str", "velo_last_error", "velo_set_timing", "velo_read_timing",
            "velo_train_forward", "velo_bce", "velo_train_backward", "velo_adam_step",
            "velo_graph_capture", "velo_graph_launch", "velo_graph_destroy", "velo_calibrate",
-           "velo_autotune", "velo_embed_train_grad", "velo_focal", "velo_components_sweep")
+           "velo_autotune", "velo_embed_train_grad", "velo_focal", "velo_components_sweep",
+           "velo_build_graph_loop")
 STAGES = ("prepare", "embed", "knn", "compact", "lists", "node_enc", "edge_enc", "messages",
           "node_net", "edge_net", "edge_cls", "components", "bce", "bwd_mlp", "bwd_dw", "bwd_graph", "adam",
           "hit_proj", "emb_loss", "emb_bwd")
@@ -119,6 +120,8 @@ def lib() -> C.CDLL:
         L.velo_focal.restype = st
         L.velo_components_sweep.argtypes = [vp, C.POINTER(_Hits), C.POINTER(_Outputs), vp]
         L.velo_components_sweep.restype = st
+        L.velo_build_graph_loop.argtypes = [vp, C.POINTER(_Hits), vp, C.POINTER(_Outputs), vp]
+        L.velo_build_graph_loop.restype = st
         _lib = L
     return _lib
 
@@ -283,6 +286,17 @@ class Context:
         hc = hits.c()
         self._raise(self._lib.velo_build_graph(self._h, C.byref(hc), C.c_void_p(emb.data_ptr()), C.byref(oc),
                                                _stream()), "velo_build_graph")
+        if check:
+            self.check()
+        return out
+
+    def build_graph_loop(self, hits: DeviceHits, emb, out=None, check: bool = True):
+        """The paper's per-hit neighbour loop (Sec. 7.2): a comparison variant of build_graph."""
+        out = self.alloc_outputs(hits) if out is None else out
+        oc = self._out_c(out)
+        hc = hits.c()
+        self._raise(self._lib.velo_build_graph_loop(self._h, C.byref(hc), C.c_void_p(emb.data_ptr()), C.byref(oc),
+                                                    _stream()), "velo_build_graph_loop")
         if check:
             self.check()
         return out

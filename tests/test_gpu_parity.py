@@ -475,3 +475,31 @@ def test_plane_sweep_variant_on_the_worked_counterexample():
     assert out["labels"].cpu().numpy().tolist() == [0, 0, 0, 1]
     ctx.components(hits, out)
     assert out["labels"].cpu().numpy().tolist() == [0, 0, 0, 0]
+
+
+@pytest.mark.parametrize("kind", ["batch", "ties", "dense"])
+def test_paper_neighbour_loop_variant_gives_the_same_graph(kind):
+    """The paper's per-hit neighbour loop (Sec. 7.2), kept as a comparison
+    variant, selects the same k_max nearest under (d2, index) as the
+    wavefront search: identical graphs, including exact ties and windows of
+    more than 512 candidates."""
+    wl = synth.WORKLOADS["batch256"]
+    if kind == "batch":
+        batch = synth.make_batch(wl, n_events=8, first=70)
+    elif kind == "ties":
+        rng = np.random.default_rng(11)
+        n = 400
+        plane = np.sort(rng.integers(0, 6, n)).astype(np.int32)
+        x = (10 + 0.002 * rng.integers(0, 3, n)).astype(np.float32)
+        y = (10 + 0.002 * rng.integers(0, 2, n)).astype(np.float32)
+        batch = synth.to_batch([synth.Event(x, y, synth.PLANE_Z[plane].astype(np.float32), plane,
+                                            np.zeros(n, np.int64), np.full(n, -1, np.int32))])
+    else:
+        batch = synth.to_batch([synth.make_event(synth.EventRecipe(1500, 1.0, 1500.0, 0.05),
+                                                 synth.event_rng(77, 0))])
+    ctx, hits, _ = _setup(wl, batch)
+    emb = ctx.embed(hits)
+    a = velo.graph_to_host(ctx.build_graph(hits, emb), batch.n_hits)
+    b = velo.graph_to_host(ctx.build_graph_loop(hits, emb), batch.n_hits)
+    for k in ("edge_offsets", "src", "dst"):
+        np.testing.assert_array_equal(a[k], b[k], err_msg=k)
