@@ -449,6 +449,30 @@ def knn_compare(ctx, torch, hits, reps=5):
             "speedup": round(times["paper_loop"] / max(times["wavefront"], 1e-9), 2), "same_graph": same}
 
 
+def run_multistream(synth, torch, wl, blob, prec, n_streams, events_per_stream, passes=3):
+    """Throughput with n_streams streams on the GPU, each with its own
+    context and events_per_stream events run in batches capped at 2^20 hits
+    and 2^22 edges (the paper's multi-stream setting, Sec. 7.1), against one
+    stream under the same caps.  Every stream gets the same events."""
+    from paper_2407_12119_amd import multistream
+    events = synth.make_events(wl, events_per_stream, first=3000)
+    res = {"precision": prec, "events_per_stream": events_per_stream, "hit_cap": 1 << 20, "edge_cap": 1 << 22}
+    for label, ns in (("one_stream", 1), ("streams", n_streams)):
+        ms = multistream.MultiStream(wl, blob, prec, [events] * ns)
+        ms.run()
+        ms.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(passes):
+            ms.run()
+        ms.synchronize()
+        dt = time.perf_counter() - t0
+        res[label] = {"streams": ns, "batches_per_stream": len(ms.batches[0]),
+                      "events_per_s": round(ms.n_events * passes / dt, 1), "seconds": round(dt, 3)}
+        ms.close()
+    log(f"multi-stream: {json.dumps(res)}")
+    return res
+
+
 def run_batched(velo, synth, torch, wl, batch, hits, blob, prec, steps, warmup, graph=False, latency=False,
                 autotune=True, copy_gbs=None):
     import numpy as np
@@ -556,6 +580,9 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="keep the built-in launch parameters")
     ap.add_argument("--no-quality", action="store_true", help="skip the track-finding quality block")
     ap.add_argument("--quality-steps", type=int, default=1500, help="training steps before the quality block")
+    ap.add_argument("--streams", type=int, default=16,
+                    help="multi-stream throughput mode: streams (0 to skip)")
+    ap.add_argument("--stream-events", type=int, default=500, help="events per stream in the multi-stream mode")
     ap.add_argument("--embed-train-steps", type=int, default=300,
                     help="embedding training steps before the rough-graph comparison (with the quality block)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -604,6 +631,9 @@ def main():
                                  args.graph, args.latency, not args.no_autotune, copy_gbs)
         vctx.close()
         variants[prec] = vres
+    multi = None
+    if args.streams > 0 and args.workload == "batch256":
+        multi = run_multistream(synth, torch, wl, blob, "bf16", args.streams, args.stream_events)
     training = None
     embed_training = None
     if not args.no_train and args.workload == "batch256":
@@ -669,7 +699,7 @@ def main():
            "hits_per_s": main_res["hits_per_s"],
            "stage_ms_per_step": main_res["stage_ms_per_step"],
            "roofline": main_res["roofline"], "hbm_copy_GBps": copy_gbs, "cpu_baseline": cpu, "per_event_path": per_event,
-           "variants": variants, "training": training, "embed_training": embed_training, "components_sweep": sweep, "knn_paper_loop": knn_loop, "quality": quality}
+           "variants": variants, "training": training, "embed_training": embed_training, "components_sweep": sweep, "knn_paper_loop": knn_loop, "multi_stream": multi, "quality": quality}
     for k in ("graph", "eager"):
         if k in main_res:
             res[k] = main_res[k]
