@@ -56,34 +56,46 @@ __device__ inline float sqdist(f32x4 a, f32x4 b) {
     return s;
 }
 
-// Training pairs of every query hit (one wavefront per query) and their
-// contributions.  acc[j * 8 + c]: fixed-point sum of the genuine (c < 4) and
-// fake (c >= 4) pairs' gradients with respect to e_j; stat: {sum of genuine
-// d2, sum of active fake hinges (both 2^-24 fixed point), N_g, N_f}.
-__global__ __launch_bounds__(256) void k_emb_pairs(int64_t n_hits, const int *__restrict__ off,
-                                                   const int *__restrict__ plane_off,
-                                                   const int *__restrict__ hit_event, const int *__restrict__ plane,
-                                                   const f32x4 *__restrict__ emb, const int *__restrict__ pid,
-                                                   const uint8_t *__restrict__ query,
-                                                   const unsigned *__restrict__ rnd, const int *__restrict__ nbr,
-                                                   const int *__restrict__ deg, int kmax, float margin,
-                                                   unsigned long long *__restrict__ acc,
-                                                   unsigned long long *__restrict__ stat,
-                                                   const unsigned *__restrict__ flags) {
+// Training pairs of every query hit and their contributions.  A workgroup
+// takes the queries of one (event, plane p), one wavefront per query: every
+// pair's second hit lies in the shared candidate window (planes p+1, p+2),
+// so the second hits' sums are gathered in LDS (64-bit integer adds) and
+// flushed with one global atomic per entry; windows larger than kPairLds
+// hits add to global memory directly.  acc[j * 8 + c]: fixed-point sum of
+// the genuine (c < 4) and fake (c >= 4) pairs' gradients with respect to
+// e_j; stat: {sum of genuine d2, sum of active fake hinges (both 2^-24 fixed
+// point), N_g, N_f}.
+constexpr int kPairBlock = 256;
+constexpr int kPairLds = 512;    // window hits whose sums fit in LDS (32 KB)
+
+__global__ __launch_bounds__(kPairBlock) void k_emb_pairs(int B, const int *__restrict__ off,
+                                                          const int *__restrict__ plane_off,
+                                                          const f32x4 *__restrict__ emb, const int *__restrict__ pid,
+                                                          const uint8_t *__restrict__ query,
+                                                          const unsigned *__restrict__ rnd, const int *__restrict__ nbr,
+                                                          const int *__restrict__ deg, int kmax, float margin,
+                                                          unsigned long long *__restrict__ acc,
+                                                          unsigned long long *__restrict__ stat,
+                                                          const unsigned *__restrict__ flags) {
+    __shared__ unsigned long long win[kPairLds * 8];
     if (*flags & kErrInput) return;
-    const int lane = threadIdx.x & 63;
-    const WaveRange wv = wave_range(n_hits, false);
-    const WaveRange wr{uniform64(wv.first), uniform64(wv.step), uniform64(wv.end)};
+    const int b = blockIdx.x / VELO_N_PLANES, p = blockIdx.x % VELO_N_PLANES;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t s = off[b];
+    const int *po = plane_off + (int64_t)b * kPlaneSlots;
+    const int q0 = po[p], q1 = po[p + 1];
+    if (q0 >= q1) return;                                   // uniform over the workgroup
+    const int c0 = po[min(p + 1, VELO_N_PLANES)];
+    const int C = max(po[min(p + 3, VELO_N_PLANES)] - c0, 0);
+    const int64_t base = s + c0;
+    const bool in_lds = C <= kPairLds;
+    if (in_lds)
+        for (int k = threadIdx.x; k < C * 8; k += kPairBlock) win[k] = 0;
+    __syncthreads();
     unsigned long long sg = 0, sf = 0, ng = 0, nf = 0;   // this lane's share
-    for (int64_t i = wr.first; i < wr.end; i += wr.step) {
-        if (!query[i]) continue;
-        const int b = hit_event[i];
-        const int64_t s = off[b];
-        const int p = plane[i];
-        const int *po = plane_off + (int64_t)b * kPlaneSlots;
-        const int c0 = po[min(p + 1, VELO_N_PLANES)];
-        const int C = max(po[min(p + 3, VELO_N_PLANES)] - c0, 0);
-        const int64_t base = s + c0;
+    for (int lq = q0 + w; lq < q1; lq += kPairBlock / 64) {
+        const int64_t i = s + lq;
+        if (!query[i]) continue;                            // uniform over the wavefront
         const f32x4 q = emb[i];
         const int pq = pid[i];
         // this lane's share of the query's own sums (genuine 0..3, fake 4..7),
@@ -106,7 +118,8 @@ __global__ __launch_bounds__(256) void k_emb_pairs(int64_t n_hits, const int *__
                 sf += to_fix(margin - d2, kLossFix);
                 sign = -1.f;
             }
-            unsigned long long *aj = acc + j * 8 + (gen ? 0 : 4);
+            unsigned long long *aj = in_lds ? win + (j - base) * 8 : acc + j * 8;
+            aj += gen ? 0 : 4;
 #pragma unroll
             for (int c = 0; c < kD; c++) {
                 const float v = sign * 2.f * (q[c] - e[c]);
@@ -146,6 +159,11 @@ __global__ __launch_bounds__(256) void k_emb_pairs(int64_t n_hits, const int *__
         if (sf) atomicAdd(stat + 1, sf);
         if (ng) atomicAdd(stat + 2, ng);
         if (nf) atomicAdd(stat + 3, nf);
+    }
+    if (in_lds) {
+        __syncthreads();
+        for (int k = threadIdx.x; k < C * 8; k += kPairBlock)
+            if (win[k]) atomicAdd(acc + base * 8 + k, win[k]);
     }
 }
 
@@ -332,10 +350,9 @@ void launch_embed_train_grad(velo_ctx *c, const velo_hits *h, const velo_embed_t
         launch_fill((int *)w.t_acc, 0, N * 16, s);
         launch_fill((int *)w.t_stat, 0, 8, s);
         if (N > 0)
-            k_emb_pairs<<<persistent_grid(c, 16), 256, 0, s>>>(N, h->event_offsets, w.plane_off, w.hit_event,
-                                                              h->plane, (const f32x4 *)e, truth->pid,
-                                                              truth->query, truth->rnd, w.t_nbr, w.t_deg, k_train,
-                                                              margin, w.t_acc, w.t_stat, w.flags);
+            k_emb_pairs<<<h->n_events * VELO_N_PLANES, kPairBlock, 0, s>>>(
+                h->n_events, h->event_offsets, w.plane_off, (const f32x4 *)e, truth->pid, truth->query,
+                truth->rnd, w.t_nbr, w.t_deg, k_train, margin, w.t_acc, w.t_stat, w.flags);
         k_emb_loss<<<1, 64, 0, s>>>(w.t_stat, w_genuine, loss, counts);
     }
     {

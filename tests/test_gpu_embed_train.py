@@ -127,3 +127,26 @@ def test_adam_steps_reduce_the_loss():
         ctx.adam_step(params[sl], g[sl], m[sl], v[sl], step, lr=1e-3)
     torch.cuda.synchronize()
     assert losses[-1] < 0.7 * losses[0], losses
+
+
+def test_dense_event_windows_beyond_lds():
+    """One dense event whose candidate windows hold more hits than the pair
+    kernel gathers in LDS (those add their second hits' sums to global
+    memory directly): same counts, loss and gradient as the oracle."""
+    ev = synth.make_event(synth.EventRecipe(600, 1.0, 600.0, 0.0), synth.event_rng(78, 0))
+    tb = synth.embed_train_batch([ev], step=5)
+    counts = np.bincount(tb.batch.plane, minlength=synth.N_PLANES)
+    assert (counts[1:] + np.concatenate([counts[2:], [0]])).max() > 512
+    blob = synth.init_params(WL)
+    ctx, hits, truth = _setup(tb)
+    params = torch.from_numpy(blob).cuda()
+    g, loss, cnt, emb = _gpu(ctx, hits, truth, params, k_train=7, d2_train=0.05, margin=0.02, w_genuine=3.0)
+    r = _oracle(tb, blob, emb, 7, 0.05, 0.02, 3.0)
+    assert (int(cnt[0]), int(cnt[1])) == (r["n_genuine"], r["n_fake"])
+    assert loss[0] == pytest.approx(r["loss"], rel=1e-5)
+    for name, (o, m) in SEGS.items():
+        if name == "b3":
+            continue
+        a, b = g[E0 + o:E0 + o + m], r["grad"][E0 + o:E0 + o + m]
+        rel = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+        assert rel < 1e-4, (name, rel)
