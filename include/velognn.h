@@ -317,8 +317,9 @@ typedef struct {
  * is left as it is), loss[3] = {L, genuine term, fake term} (device float)
  * and counts[2] = {N_g, N_f} (device int64); emb (device [N x 4], optional)
  * receives the embedding the pairs were built on.  Per-hit gradient sums are
- * accumulated in 64-bit fixed point (2^-32), so the result does not depend
- * on the order of the pairs and is bitwise reproducible.  Needs a context
+ * accumulated in 64-bit fixed point (2^-32; a single pair's term is clamped
+ * to +-1e6), so the result does not depend on the order of the pairs and is
+ * bitwise reproducible.  Needs a context
  * created with training = 1 whose parameters have been set once (as every
  * call on hits does); 1 <= k_train <= VELO_EMB_TRAIN_KMAX. */
 velo_status velo_embed_train_grad(velo_ctx *ctx, const velo_hits *hits, const velo_embed_truth *truth,
