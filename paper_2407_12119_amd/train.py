@@ -31,6 +31,7 @@ class _EdgeLogits:
     imported on first use)."""
     fn = None
     bce = None
+    focal = None
 
 
 def _functions():
@@ -74,7 +75,22 @@ def _functions():
             (dz,) = fctx.saved_tensors
             return dz * g, None, None, None
 
-    _EdgeLogits.fn, _EdgeLogits.bce = EdgeLogits, WeightedBCE
+    class FocalLoss(torch.autograd.Function):
+        """Sigmoid focal loss (the classifier loss of the GNN section):
+        L = (1/n) sum_e a_t (1 - p_t)^gamma ce_e; dL/dz from the same kernel."""
+
+        @staticmethod
+        def forward(fctx, z, vctx, y, alpha, gamma):
+            loss, dz = vctx.focal(z.contiguous(), y, alpha, gamma, z.shape[0])
+            fctx.save_for_backward(dz[:z.shape[0]])
+            return loss[0]
+
+        @staticmethod
+        def backward(fctx, g):
+            (dz,) = fctx.saved_tensors
+            return dz * g, None, None, None, None
+
+    _EdgeLogits.fn, _EdgeLogits.bce, _EdgeLogits.focal = EdgeLogits, WeightedBCE, FocalLoss
     return EdgeLogits, WeightedBCE
 
 
@@ -86,6 +102,12 @@ def edge_logits(vctx: "velo.Context", params, hits: "velo.DeviceHits", graph, n_
 def weighted_bce(vctx: "velo.Context", z, y, pos_weight: float):
     """Differentiable weighted BCE of logits z against uint8 labels y."""
     return _functions()[1].apply(z, vctx, y, float(pos_weight))
+
+
+def focal_loss(vctx: "velo.Context", z, y, alpha: float = 0.25, gamma: float = 2.0):
+    """Differentiable sigmoid focal loss of logits z against uint8 labels y."""
+    _functions()
+    return _EdgeLogits.focal.apply(z, vctx, y, float(alpha), float(gamma))
 
 
 class GraphBatch:

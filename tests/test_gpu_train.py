@@ -280,6 +280,27 @@ def test_autograd_function_gives_the_library_gradient():
         z.sum().backward()
 
 
+def test_focal_autograd_gives_the_library_gradient():
+    """loss.backward() through EdgeLogits and FocalLoss equals the explicit
+    forward / focal / backward calls, bitwise."""
+    from paper_2407_12119_amd import train
+    wl = synth.WORKLOADS["train32"]
+    batch = synth.make_batch(wl, n_events=2)
+    blob = synth.init_params(wl)
+    ctx, hits, graph, params = _setup(wl, batch, blob)
+    g = velo.graph_to_host(graph, batch.n_hits)
+    n = g["n_edges"]
+    yt = torch.from_numpy(_labels(batch, g)).cuda()
+    p = params.clone().requires_grad_(True)
+    loss = train.focal_loss(ctx, train.edge_logits(ctx, p, hits, graph, n), yt, 0.25, 2.0)
+    loss.backward()
+    ctx.train_forward(hits, graph, params)
+    loss2, dz = ctx.focal(graph["edge_logit"], yt, 0.25, 2.0, n)
+    g2 = ctx.train_backward(hits, params, dz)
+    assert float(loss) == float(loss2.cpu()[0])
+    assert torch.equal(p.grad, g2)
+
+
 def test_trainer_learns_edges_of_generated_events():
     """A few hundred Adam steps on generated events: the loss falls and the
     trained classifier separates true from fake edges on held-out events."""
