@@ -150,3 +150,36 @@ def test_dense_event_windows_beyond_lds():
         a, b = g[E0 + o:E0 + o + m], r["grad"][E0 + o:E0 + o + m]
         rel = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
         assert rel < 1e-4, (name, rel)
+
+
+@pytest.mark.parametrize("k_train", [1, 64])
+def test_neighbour_list_bounds(k_train):
+    """The smallest and the largest accepted k_train, against the oracle."""
+    tb = synth.embed_train_batch(synth.make_events(WL, 1, first=50), step=4)
+    blob = synth.init_params(WL)
+    ctx, hits, truth = _setup(tb)
+    params = torch.from_numpy(blob).cuda()
+    g, loss, cnt, emb = _gpu(ctx, hits, truth, params, k_train=k_train, d2_train=1.5, margin=1.0, w_genuine=2.0)
+    r = _oracle(tb, blob, emb, k_train, 1.5, 1.0, 2.0)
+    assert (int(cnt[0]), int(cnt[1])) == (r["n_genuine"], r["n_fake"])
+    assert loss[0] == pytest.approx(r["loss"], rel=1e-5)
+    a, b = g[E0:E0 + NE - 4], r["grad"][E0:E0 + NE - 4]
+    assert np.linalg.norm(a - b) / np.linalg.norm(b) < 1e-4
+
+
+def test_invalid_arguments_are_refused():
+    tb = synth.embed_train_batch(synth.make_events(WL, 1, first=51), step=0)
+    ctx, hits, truth = _setup(tb)
+    params = torch.from_numpy(synth.init_params(WL)).cuda()
+    for kw in ({"k_train": 0}, {"k_train": 65}, {"d2_train": 0.0}, {"w_genuine": -1.0},
+               {"margin": float("nan")}):
+        with pytest.raises(velo.VeloError) as ei:
+            ctx.embed_train_grad(hits, *truth, params, **kw)
+        assert ei.value.status == velo.VELO_ERR_INVALID_ARG, kw
+    # a context without the training buffers
+    plain = velo.Context(WL.hidden, WL.iters, oracle.d2max_f32(WL.radius), WL.k_max, WL.edge_logit_min, "fp32",
+                         max_hits=tb.batch.n_hits, max_events=1, max_event_hits=tb.batch.n_hits)
+    plain.set_params(params)
+    with pytest.raises(velo.VeloError) as ei:
+        plain.embed_train_grad(hits, *truth, params)
+    assert ei.value.status == velo.VELO_ERR_UNSUPPORTED
