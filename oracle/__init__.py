@@ -63,6 +63,22 @@ def lib() -> C.CDLL:
         L.oracle_focal.restype = f64
         L.oracle_components_sweep.argtypes = [i64, p, i64, p, p, p, p]
         L.oracle_components_sweep.restype = C.c_int
+        L.oracle_embed_amax.argtypes = [i64, p, p, p, p, C.c_int, C.c_int, p]
+        L.oracle_embed_amax.restype = C.c_int
+        L.oracle_embed_int8.argtypes = [i64, p, p, p, p, C.c_int, C.c_int, p, p]
+        L.oracle_embed_int8.restype = C.c_int
+        L.oracle_triplets.argtypes = [i64, i64, p, p, p, i64, p, p, p, p, p]
+        L.oracle_triplets.restype = C.c_int
+        L.oracle_triplet_param_count.argtypes = [C.c_int]
+        L.oracle_triplet_param_count.restype = i64
+        L.oracle_triplet_logits.argtypes = [i64, p, i64, p, C.c_int, p, C.c_int, p]
+        L.oracle_triplet_logits.restype = C.c_int
+        L.oracle_build_tracks.argtypes = [i64, i64, p, p, p, p, i64, p, p, i64, p, p, p, p, i64, p]
+        L.oracle_build_tracks.restype = C.c_int
+        L.oracle_track_hits.argtypes = [i64, p, p, p, i64, p, p, p, i64]
+        L.oracle_track_hits.restype = C.c_int
+        L.oracle_set_threads.argtypes = [C.c_int]
+        L.oracle_set_threads.restype = C.c_int
         _lib = L
     return _lib
 
@@ -170,6 +186,121 @@ def components_sweep(plane, src, dst, keep) -> np.ndarray:
                                        _ptr(keep), _ptr(lab))
     assert rc == 0, rc
     return lab
+
+
+def embed_amax(events, blob, Ce: int = 128, D: int = 4) -> np.ndarray:
+    """Largest |input| of the embedding's second and third layers over the
+    hits of `events` (float64), for INT8 calibration."""
+    amax = np.zeros(2, np.float64)
+    blob = _c(blob, np.float32)
+    for ev in events:
+        x, y, z = _c(ev.x, np.float32), _c(ev.y, np.float32), _c(ev.z, np.float32)
+        rc = lib().oracle_embed_amax(x.shape[0], _ptr(x), _ptr(y), _ptr(z), _ptr(blob), Ce, D, _ptr(amax))
+        assert rc == 0, rc
+    return amax
+
+
+def int8_scales(amax, blob, Ce: int = 128, D: int = 4) -> np.ndarray:
+    """{s_x2, s_w2, s_x3, s_w3} as float32: s = fl32(max |value| / 127) for the
+    two layer inputs (from `amax`) and the two weight matrices."""
+    o2 = 12 + Ce * 3 + Ce
+    w2 = np.asarray(blob[o2:o2 + Ce * Ce], np.float32)
+    o3 = o2 + Ce * Ce + Ce
+    w3 = np.asarray(blob[o3:o3 + D * Ce], np.float32)
+    q = np.float32(127.0)
+    sx = [np.float32(np.float32(a) / q) if a > 0 else np.float32(1.0) for a in amax]
+    sw = [np.float32(np.abs(w).max() / q) if np.abs(w).max() > 0 else np.float32(1.0) for w in (w2, w3)]
+    return np.array([sx[0], sw[0], sx[1], sw[1]], np.float32)
+
+
+def embed_int8(x, y, z, blob, scales, Ce: int = 128, D: int = 4) -> np.ndarray:
+    """Embedding with INT8 operands in its second and third layers under the
+    per-tensor float32 scales {s_x2, s_w2, s_x3, s_w3} (Sec. 7.4)."""
+    x, y, z = _c(x, np.float32), _c(y, np.float32), _c(z, np.float32)
+    blob, sc = _c(blob, np.float32), _c(scales, np.float32)
+    out = np.zeros((x.shape[0], D), np.float64)
+    rc = lib().oracle_embed_int8(x.shape[0], _ptr(x), _ptr(y), _ptr(z), _ptr(blob), Ce, D, _ptr(sc), _ptr(out))
+    assert rc == 0, rc
+    return out
+
+
+def triplets(n: int, src, dst, keep):
+    """Triplets of one event's kept edges (Sec. 5.3): (art [Ta x 2], elb [Te x 2],
+    elb_type [Te] with 1 = left, 2 = right elbow), pairs of edge indices."""
+    src, dst = _c(src, np.int32), _c(dst, np.int32)
+    keep = _c(keep, np.uint8)
+    E = src.shape[0]
+    cap = 1 << 10
+    while True:
+        art = np.zeros((cap, 2), np.int32)
+        elb = np.zeros((cap, 2), np.int32)
+        et = np.zeros(cap, np.int8)
+        na, ne = C.c_int64(0), C.c_int64(0)
+        rc = lib().oracle_triplets(n, E, _ptr(src), _ptr(dst), _ptr(keep), cap, _ptr(art), C.byref(na),
+                                   _ptr(elb), _ptr(et), C.byref(ne))
+        if rc == 0:
+            return art[:na.value].copy(), elb[:ne.value].copy(), et[:ne.value].copy()
+        assert rc == -1, rc
+        cap = max(na.value, ne.value)
+
+
+def triplet_param_count(H: int) -> int:
+    return int(lib().oracle_triplet_param_count(H))
+
+
+def triplet_logits(pairs, e, tblob, which: int) -> np.ndarray:
+    """Logits of the articulation (which = 0) or elbow (1) classifier on the
+    pairs of edge encodings [e_a || e_b]; e: [E x H] float64."""
+    pairs = _c(np.asarray(pairs).reshape(-1, 2), np.int32)
+    e = _c(e, np.float64)
+    tblob = _c(tblob, np.float32)
+    z = np.zeros(pairs.shape[0], np.float64)
+    rc = lib().oracle_triplet_logits(pairs.shape[0], _ptr(pairs), e.shape[0], _ptr(e), e.shape[1], _ptr(tblob),
+                                     which, _ptr(z))
+    assert rc == 0, rc
+    return z
+
+
+def build_tracks(n: int, src, dst, plane, keep, art, art_keep, elb, elb_keep):
+    """Tracks from the purified edge graph (Sec. 5.4): (edge_seg [E], tracks
+    [T x 2] of segment labels, the second -1 for one-segment tracks)."""
+    src, dst, plane = _c(src, np.int32), _c(dst, np.int32), _c(plane, np.int32)
+    keep = _c(keep, np.uint8)
+    art, elb = _c(np.asarray(art).reshape(-1, 2), np.int32), _c(np.asarray(elb).reshape(-1, 2), np.int32)
+    ak, ek = _c(art_keep, np.uint8), _c(elb_keep, np.uint8)
+    E = src.shape[0]
+    seg = np.zeros(max(E, 1), np.int32)
+    cap = max(E, 1) + art.shape[0]
+    tr = np.zeros((cap, 2), np.int32)
+    nt = C.c_int64(0)
+    rc = lib().oracle_build_tracks(n, E, _ptr(src), _ptr(dst), _ptr(plane), _ptr(keep), art.shape[0], _ptr(art),
+                                   _ptr(ak), elb.shape[0], _ptr(elb), _ptr(ek), _ptr(seg), _ptr(tr), cap,
+                                   C.byref(nt))
+    assert rc == 0, rc
+    return seg[:E].copy(), tr[:nt.value].copy()
+
+
+def track_hits(src, dst, edge_seg, tracks):
+    """Hits of every track (Sec. 5.4, step 4): a list of ascending int32 arrays."""
+    src, dst, seg = _c(src, np.int32), _c(dst, np.int32), _c(edge_seg, np.int32)
+    tracks = _c(np.asarray(tracks).reshape(-1, 2), np.int32)
+    T = tracks.shape[0]
+    off = np.zeros(T + 1, np.int64)
+    cap = max(1, 4 * src.shape[0])
+    while True:
+        hits = np.zeros(cap, np.int32)
+        rc = lib().oracle_track_hits(src.shape[0], _ptr(src), _ptr(dst), _ptr(seg), T, _ptr(tracks), _ptr(off),
+                                     _ptr(hits), cap)
+        if rc == 0:
+            return [hits[off[k]:off[k + 1]].copy() for k in range(T)]
+        assert rc == -1, rc
+        cap = int(off[-1])
+
+
+def set_threads(n: int) -> int:
+    """Threads of the oracle's loops over events (n <= 0: unchanged); returns
+    the count in effect."""
+    return int(lib().oracle_set_threads(int(n)))
 
 
 def pipeline(batch, blob, H: int, iters: int, radius: float = 0.1, k_max: int = 32,

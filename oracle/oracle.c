@@ -42,6 +42,7 @@
  *   classifier: [H x H], [1 x H]
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -166,6 +167,91 @@ int oracle_embed(int64_t n, const float *x, const float *y, const float *z,
         memcpy(h2, pre, sizeof(double) * Ce);
         relu(h2, Ce);
         linear(blob, &L.emb[2], h2, emb + i * D);
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Sec. 7.4: the embedding with INT8 matrix operands                   */
+/* ------------------------------------------------------------------ */
+
+/* Largest |value| entering the two matrix layers of the embedding that take
+ * INT8 operands (the 128-wide hidden layers, after their ReLU), over the hits
+ * of a calibration set, in float64 (the paper calibrates its INT8 embedding
+ * on a set of events).  amax[0]: input of the second layer, amax[1]: input of
+ * the third.  Accumulates into amax (the caller zeroes it once). */
+int oracle_embed_amax(int64_t n, const float *x, const float *y, const float *z,
+                      const float *blob, int Ce, int D, double *amax)
+{
+    layout_t L;
+    if (make_layout(&L, 1, 0, Ce, D) || Ce > 1024)
+        return -1;
+    double u[3], h1[1024], h2[1024];
+    for (int64_t i = 0; i < n; i++) {
+        embed_features(blob, x[i], y[i], z[i], u);
+        linear(blob, &L.emb[0], u, h1);
+        relu(h1, Ce);
+        linear(blob, &L.emb[1], h1, h2);
+        relu(h2, Ce);
+        for (int c = 0; c < Ce; c++) {
+            if (h1[c] > amax[0]) amax[0] = h1[c];
+            if (h2[c] > amax[1]) amax[1] = h2[c];
+        }
+    }
+    return 0;
+}
+
+/* Symmetric INT8 code of v under the per-tensor scale whose reciprocal is
+ * `inv` (float32): the decision is taken in float32, as on the device:
+ * t = fl32(fl32(v) * inv), rounded to the nearest integer (ties to even),
+ * clamped to [-127, 127]. */
+static int32_t int8_code(double v, float inv)
+{
+    float t = (float)v * inv;
+    t = rintf(t);
+    if (t > 127.0f) t = 127.0f;
+    if (t < -127.0f) t = -127.0f;
+    return (int32_t)t;
+}
+
+/* One matrix layer on INT8 operands: y = s_x s_w (Q_W q_x) + b, with q_x
+ * and Q_W the codes of the input and the weights, the integer products summed
+ * exactly and the result descaled in float64. */
+static void linear_int8(const float *blob, const lin_t *l, const double *x, float s_x, float s_w, double *y)
+{
+    const float *W = blob + l->w, *b = blob + l->b;
+    const float ix = 1.0f / s_x, iw = 1.0f / s_w;
+    int32_t qx[1024];
+    for (int i = 0; i < l->in; i++)
+        qx[i] = int8_code(x[i], ix);
+    for (int o = 0; o < l->out; o++) {
+        int64_t acc = 0;
+        for (int i = 0; i < l->in; i++)
+            acc += (int64_t)int8_code((double)W[(int64_t)o * l->in + i], iw) * qx[i];
+        y[o] = (double)acc * (double)s_x * (double)s_w + (double)b[o];
+    }
+}
+
+/* Embedding with INT8 operands in its two 128-wide-input layers (the first
+ * layer, three inputs, stays in float64 like the rest of the oracle).
+ * sc = {s_x2, s_w2, s_x3, s_w3}: the float32 scales of the inputs and weights
+ * of the second and third layers (s = max |value| / 127). */
+int oracle_embed_int8(int64_t n, const float *x, const float *y, const float *z,
+                      const float *blob, int Ce, int D, const float *sc, double *emb)
+{
+    layout_t L;
+    if (make_layout(&L, 1, 0, Ce, D) || Ce > 1024)
+        return -1;
+    if (!(sc[0] > 0.f) || !(sc[1] > 0.f) || !(sc[2] > 0.f) || !(sc[3] > 0.f))
+        return -1;
+    double u[3], h1[1024], h2[1024];
+    for (int64_t i = 0; i < n; i++) {
+        embed_features(blob, x[i], y[i], z[i], u);
+        linear(blob, &L.emb[0], u, h1);
+        relu(h1, Ce);
+        linear_int8(blob, &L.emb[1], h1, sc[0], sc[1], h2);
+        relu(h2, Ce);
+        linear_int8(blob, &L.emb[2], h2, sc[2], sc[3], emb + i * D);
     }
     return 0;
 }
@@ -522,6 +608,246 @@ oom:
 }
 
 /* ------------------------------------------------------------------ */
+/* Sec. 5.3: triplets of the purified hit graph                       */
+/* ------------------------------------------------------------------ */
+
+/*
+ * The triplets of one event: pairs of kept edges that share a hit C.
+ *   articulation  a = A -> C, b = C -> B   (the common hit in the middle)
+ *   left elbow    a = C -> A, b = C -> B   (both leave C; a < b)
+ *   right elbow   a = A -> C, b = B -> C   (both enter C; a < b)
+ * Edges are event-local indices into src/dst (grouped by source); a and b
+ * are edge indices.  Order: articulations by C, then a, then b; elbows by C,
+ * the left ones of a hit before its right ones, then a, then b (edge
+ * indices ascending).  art[2t], art[2t+1] = (a, b); elb likewise with
+ * elb_type[t] = 1 (left) or 2 (right).  Returns 0, or -1 when a list would
+ * exceed `cap` pairs (the counts still give the required sizes).
+ */
+int oracle_triplets(int64_t n, int64_t E, const int32_t *src, const int32_t *dst, const uint8_t *keep,
+                    int64_t cap, int32_t *art, int64_t *n_art, int32_t *elb, int8_t *elb_type, int64_t *n_elb)
+{
+    int64_t *in_off = calloc((size_t)n + 1, sizeof(int64_t)), *out_off = calloc((size_t)n + 1, sizeof(int64_t));
+    int32_t *in_e = malloc(sizeof(int32_t) * (size_t)(E > 0 ? E : 1)), *out_e = malloc(sizeof(int32_t) * (size_t)(E > 0 ? E : 1));
+    int64_t *fill = calloc((size_t)n + 1, sizeof(int64_t));
+    if (!in_off || !out_off || !in_e || !out_e || !fill) {
+        free(in_off); free(out_off); free(in_e); free(out_e); free(fill);
+        return -2;
+    }
+    for (int64_t q = 0; q < E; q++)
+        if (keep[q]) {
+            if (src[q] < 0 || src[q] >= n || dst[q] < 0 || dst[q] >= n) {
+                free(in_off); free(out_off); free(in_e); free(out_e); free(fill);
+                return -3;
+            }
+            in_off[dst[q] + 1]++;
+            out_off[src[q] + 1]++;
+        }
+    for (int64_t i = 0; i < n; i++) {
+        in_off[i + 1] += in_off[i];
+        out_off[i + 1] += out_off[i];
+    }
+    for (int64_t q = 0; q < E; q++)          /* edge indices ascending within every list */
+        if (keep[q]) in_e[in_off[dst[q]] + fill[dst[q]]++] = (int32_t)q;
+    memset(fill, 0, sizeof(int64_t) * (size_t)(n + 1));
+    for (int64_t q = 0; q < E; q++)
+        if (keep[q]) out_e[out_off[src[q]] + fill[src[q]]++] = (int32_t)q;
+    int64_t na = 0, ne = 0;
+    for (int64_t c = 0; c < n; c++)
+        for (int64_t i = in_off[c]; i < in_off[c + 1]; i++)
+            for (int64_t j = out_off[c]; j < out_off[c + 1]; j++) {
+                if (na < cap) { art[2 * na] = in_e[i]; art[2 * na + 1] = out_e[j]; }
+                na++;
+            }
+    for (int64_t c = 0; c < n; c++) {
+        for (int64_t i = out_off[c]; i < out_off[c + 1]; i++)
+            for (int64_t j = i + 1; j < out_off[c + 1]; j++) {
+                if (ne < cap) { elb[2 * ne] = out_e[i]; elb[2 * ne + 1] = out_e[j]; elb_type[ne] = 1; }
+                ne++;
+            }
+        for (int64_t i = in_off[c]; i < in_off[c + 1]; i++)
+            for (int64_t j = i + 1; j < in_off[c + 1]; j++) {
+                if (ne < cap) { elb[2 * ne] = in_e[i]; elb[2 * ne + 1] = in_e[j]; elb_type[ne] = 2; }
+                ne++;
+            }
+    }
+    *n_art = na;
+    *n_elb = ne;
+    free(in_off); free(out_off); free(in_e); free(out_e); free(fill);
+    return na > cap || ne > cap ? -1 : 0;
+}
+
+/* Offsets of the two triplet classifiers in their parameter blob (Sec. 5.3:
+ * separate classifiers for articulations and elbows): for each, a Linear
+ * [H x 2H] + [H], ReLU, a Linear [1 x H] + [1]; articulations first. */
+static void triplet_layout(int H, int which, lin_t *l0, lin_t *l1)
+{
+    int64_t o = (int64_t)which * ((int64_t)H * 2 * H + H + H + 1);
+    put(l0, o, H, 2 * H);
+    put(l1, l0->b + H, 1, H);
+}
+
+int64_t oracle_triplet_param_count(int H)
+{
+    return 2 * ((int64_t)H * 2 * H + H + H + 1);
+}
+
+/* Triplet logits z_t = MLP_which([e_a || e_b]) of T pairs (a, b) of edge
+ * indices, with e the final edge encodings [E x H] (Sec. 5.3; score =
+ * sigmoid(z), kept iff z >= the cut). */
+int oracle_triplet_logits(int64_t T, const int32_t *pairs, int64_t E, const double *e, int H,
+                          const float *tblob, int which, double *z)
+{
+    if (H < 1 || 2 * H > 1024 || (which != 0 && which != 1))
+        return -1;
+    lin_t l0, l1;
+    triplet_layout(H, which, &l0, &l1);
+    double cat[1024], hid[1024];
+    for (int64_t t = 0; t < T; t++) {
+        const int32_t a = pairs[2 * t], b = pairs[2 * t + 1];
+        if (a < 0 || a >= E || b < 0 || b >= E)
+            return -1;
+        memcpy(cat, e + (int64_t)a * H, sizeof(double) * H);
+        memcpy(cat + H, e + (int64_t)b * H, sizeof(double) * H);
+        mlp2(tblob, &l0, &l1, cat, hid, z + t);
+    }
+    return 0;
+}
+
+/*
+ * Tracks from the purified edge graph (Sec. 5.4), one event.  Inputs: the
+ * kept edges, the triplet lists of oracle_triplets and each triplet's keep
+ * decision.  The four steps:
+ *  1. Kept elbows join their two edges.  When the two edges span different
+ *     numbers of planes, the longer one (a hit skipped) duplicates the path
+ *     through the third hit and takes no part in articulations.
+ *  2. Among the kept articulations without a duplicate edge, one is shared
+ *     when its first edge is the first edge of another of them, or its second
+ *     edge the second edge of another (tracks parting or joining there).
+ *     Every other one joins its two edges.  The joined sets of edges are the
+ *     segments (exact union-find; a segment's label is its smallest edge index).
+ *  3. Every shared articulation makes a track of its two edges' segments (a
+ *     segment shared by several tracks is copied into each), and every
+ *     segment that no shared articulation touches is a track of its own.
+ *  4. (oracle_track_hits) a track's hits are the ends of its edges.
+ * edge_seg[q]: segment of kept edge q, -1 for others.  tracks[2k], [2k+1]:
+ * the track's segments, the second -1 for a single segment; single-segment
+ * tracks come first, by segment label, then the shared articulations' tracks
+ * in articulation order.  Returns 0, or -1 when more than `cap` tracks.
+ */
+static int32_t uf_find(int32_t *par, int32_t x)
+{
+    while (par[x] != x) {
+        par[x] = par[par[x]];
+        x = par[x];
+    }
+    return x;
+}
+
+static void uf_union(int32_t *par, int32_t u, int32_t v)
+{
+    u = uf_find(par, u);
+    v = uf_find(par, v);
+    if (u == v) return;
+    if (u < v) par[v] = u;
+    else par[u] = v;
+}
+
+int oracle_build_tracks(int64_t n, int64_t E, const int32_t *src, const int32_t *dst, const int32_t *plane,
+                        const uint8_t *keep, int64_t n_art, const int32_t *art, const uint8_t *art_keep,
+                        int64_t n_elb, const int32_t *elb, const uint8_t *elb_keep, int32_t *edge_seg,
+                        int32_t *tracks, int64_t cap, int64_t *n_tracks)
+{
+    int32_t *par = malloc(sizeof(int32_t) * (size_t)(E > 0 ? E : 1));
+    uint8_t *dup = calloc((size_t)(E > 0 ? E : 1), 1), *touched = calloc((size_t)(E > 0 ? E : 1), 1);
+    int32_t *first = calloc((size_t)(E > 0 ? E : 1), sizeof(int32_t)), *second = calloc((size_t)(E > 0 ? E : 1), sizeof(int32_t));
+    uint8_t *shared = calloc((size_t)(n_art > 0 ? n_art : 1), 1);
+    int rc = 0;
+    if (!par || !dup || !touched || !first || !second || !shared) { rc = -2; goto done; }
+    (void)n;
+    for (int64_t q = 0; q < E; q++) par[q] = (int32_t)q;
+    /* 1. elbows */
+    for (int64_t t = 0; t < n_elb; t++) {
+        if (!elb_keep[t]) continue;
+        const int32_t a = elb[2 * t], b = elb[2 * t + 1];
+        uf_union(par, a, b);
+        const int ga = plane[dst[a]] - plane[src[a]], gb = plane[dst[b]] - plane[src[b]];
+        if (ga > gb) dup[a] = 1;
+        else if (gb > ga) dup[b] = 1;
+    }
+    /* 2. articulations: shared ones part or join tracks; the others join edges */
+    for (int64_t t = 0; t < n_art; t++) {
+        const int32_t a = art[2 * t], b = art[2 * t + 1];
+        if (art_keep[t] && !dup[a] && !dup[b]) { first[a]++; second[b]++; }
+    }
+    for (int64_t t = 0; t < n_art; t++) {
+        const int32_t a = art[2 * t], b = art[2 * t + 1];
+        if (!art_keep[t] || dup[a] || dup[b]) continue;
+        if (first[a] > 1 || second[b] > 1) shared[t] = 1;
+        else uf_union(par, a, b);
+    }
+    for (int64_t q = 0; q < E; q++)
+        edge_seg[q] = keep[q] ? uf_find(par, (int32_t)q) : -1;
+    /* 3. tracks */
+    for (int64_t t = 0; t < n_art; t++)
+        if (shared[t]) {
+            touched[edge_seg[art[2 * t]]] = 1;
+            touched[edge_seg[art[2 * t + 1]]] = 1;
+        }
+    int64_t k = 0;
+    for (int64_t q = 0; q < E; q++)
+        if (keep[q] && edge_seg[q] == q && !touched[q]) {
+            if (k < cap) { tracks[2 * k] = (int32_t)q; tracks[2 * k + 1] = -1; }
+            k++;
+        }
+    for (int64_t t = 0; t < n_art; t++)
+        if (shared[t]) {
+            if (k < cap) { tracks[2 * k] = edge_seg[art[2 * t]]; tracks[2 * k + 1] = edge_seg[art[2 * t + 1]]; }
+            k++;
+        }
+    *n_tracks = k;
+    if (k > cap) rc = -1;
+done:
+    free(par); free(dup); free(touched); free(first); free(second); free(shared);
+    return rc;
+}
+
+static int cmp_i32(const void *a, const void *b)
+{
+    const int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+    return (x > y) - (x < y);
+}
+
+/* Step 4 of Sec. 5.4: the hits of every track, the ends of the edges of its
+ * segments, ascending and without repeats.  hit_off [n_tracks + 1];
+ * returns 0, or -1 when more than `cap` hits in all. */
+int oracle_track_hits(int64_t E, const int32_t *src, const int32_t *dst, const int32_t *edge_seg,
+                      int64_t n_tracks, const int32_t *tracks, int64_t *hit_off, int32_t *hits, int64_t cap)
+{
+    int32_t *tmp = malloc(sizeof(int32_t) * (size_t)(2 * E + 2));
+    if (!tmp) return -2;
+    int64_t o = 0;
+    hit_off[0] = 0;
+    for (int64_t k = 0; k < n_tracks; k++) {
+        const int32_t s1 = tracks[2 * k], s2 = tracks[2 * k + 1];
+        int64_t m = 0;
+        for (int64_t q = 0; q < E; q++)
+            if (edge_seg[q] >= 0 && (edge_seg[q] == s1 || edge_seg[q] == s2)) {
+                tmp[m++] = src[q];
+                tmp[m++] = dst[q];
+            }
+        qsort(tmp, (size_t)m, sizeof(int32_t), cmp_i32);
+        for (int64_t i = 0; i < m; i++)
+            if (i == 0 || tmp[i] != tmp[i - 1]) {
+                if (o < cap) hits[o] = tmp[i];
+                o++;
+            }
+        hit_off[k + 1] = o;
+    }
+    free(tmp);
+    return o > cap ? -1 : 0;
+}
+
+/* ------------------------------------------------------------------ */
 /* Sec. 5 / Sec. 7.3: connected components of the purified hit graph  */
 /* ------------------------------------------------------------------ */
 
@@ -875,4 +1201,14 @@ int oracle_embed_train(int64_t n, const float *x, const float *y, const float *z
 out:
     free(u); free(pre1); free(pre2); free(e); free(dEg); free(dEf); free(rp); free(col);
     return rc;
+}
+
+/* Threads of the OpenMP loops over events in oracle_pipeline (the benchmark
+ * times the oracle single-threaded and on all host cores).  Returns the
+ * thread count now in effect. */
+int oracle_set_threads(int n)
+{
+    if (n > 0)
+        omp_set_num_threads(n);
+    return omp_get_max_threads();
 }

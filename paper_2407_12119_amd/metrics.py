@@ -91,3 +91,69 @@ def edge_agreement(a_off, a_src, a_dst, a_keep, b_off, b_src, b_dst, b_keep) -> 
     return {"decision_agreement": float((da == db).mean()) if u.shape[0] else 1.0,
             "jaccard": float(inter / u.shape[0]) if u.shape[0] else 1.0,
             "n_union": int(u.shape[0])}
+
+
+def track_list_metrics(tracks, pid, event_offsets) -> dict:
+    """The same metrics for tracks given as hit lists, which may share hits
+    (tracks built from the purified edge graph, Sec. 5.4).  `tracks[b]` is the
+    list of event b's tracks, each an array of event-local hit indices
+    without repeats; a track needs >= 3 hits.  Matching, efficiency, clone
+    rate, fake rate, hit efficiency and hit purity as in track_metrics."""
+    pid = np.asarray(pid, np.int64)
+    off = np.asarray(event_offsets, np.int64)
+    n_particles = n_tracks = n_pairs = n_matched = 0
+    he = hp = 0.0
+    undefined = []
+    for b in range(off.shape[0] - 1):
+        p = pid[off[b]:off[b + 1]]
+        sig = p[p >= 0]
+        ids, sizes = np.unique(sig, return_counts=True)
+        size_of = dict(zip(ids.tolist(), sizes.tolist()))
+        n_particles += int((sizes >= MIN_PARTICLE_HITS).sum())
+        matched = set()
+        for t in tracks[b]:
+            t = np.asarray(t, np.int64)
+            if t.shape[0] < MIN_TRACK_HITS:
+                continue
+            n_tracks += 1
+            tp = p[t]
+            tp = tp[tp >= 0]
+            if tp.shape[0] == 0:
+                continue
+            cand, cnt = np.unique(tp, return_counts=True)
+            for q, c in zip(cand.tolist(), cnt.tolist()):
+                if MATCH_DEN * c >= MATCH_NUM * t.shape[0]:
+                    n_pairs += 1
+                    matched.add(q)
+                    he += c / size_of[q]
+                    hp += c / t.shape[0]
+        n_matched += len(matched)
+
+    def ratio(num, den, name):
+        if den == 0:
+            undefined.append(name)
+            return 0.0
+        return float(num) / float(den)
+
+    return {
+        "efficiency": ratio(n_matched, n_particles, "efficiency"),
+        "clone_rate": ratio(n_pairs - n_matched, n_pairs, "clone_rate"),
+        "fake_rate": ratio(n_tracks - n_pairs, n_tracks, "fake_rate"),
+        "hit_efficiency": ratio(he, n_pairs, "hit_efficiency"),
+        "hit_purity": ratio(hp, n_pairs, "hit_purity"),
+        "n_particles": n_particles, "n_tracks": n_tracks, "n_matched_particles": n_matched,
+        "n_pairs": n_pairs, "n_fake": n_tracks - n_pairs, "undefined": undefined,
+    }
+
+
+def labels_to_tracks(labels, event_offsets):
+    """Connected-component labels -> per-event lists of hit arrays (one per component)."""
+    labels = np.asarray(labels, np.int64)
+    off = np.asarray(event_offsets, np.int64)
+    out = []
+    for b in range(off.shape[0] - 1):
+        lab = labels[off[b]:off[b + 1]]
+        order = np.argsort(lab, kind="stable")
+        _, first = np.unique(lab[order], return_index=True)
+        out.append(np.split(order, first[1:]) if lab.shape[0] else [])
+    return out
