@@ -84,3 +84,21 @@ def test_params_layout_and_bounds():
         bound = 1 / np.sqrt(i)
         assert np.abs(w).max() <= bound and np.abs(b).max() <= bound
     np.testing.assert_array_equal(p, synth.init_params(wl))
+
+
+@pytest.mark.parametrize("name", ["single_event", "batch256", "batch256_lowp", "train32", "batch1000_h128"])
+def test_centred_bias_is_the_oracle_median(name):
+    """The bias-centred variant's classifier bias equals the seeded bias minus
+    the median float64 logit over the calibration event (pile-up recipe, seed
+    words (998, 0)), rounded to float32."""
+    import oracle
+    wl = synth.WORKLOADS[name]
+    calib = synth.make_event(synth.WORKLOADS["batch256"].recipe, synth._rng(998, 0))
+    assert calib.n == 1516
+    blob = synth.init_params(wl)
+    out = oracle.pipeline(synth.to_batch([calib]), blob, wl.hidden, wl.iters, wl.radius, wl.k_max)
+    med = float(np.median(out["logit"]))
+    assert np.float32(float(blob[-1]) - med) == np.float32(synth.CENTRED_BIAS[name])
+    centred = synth.centred_params(wl)
+    assert centred[-1] == np.float32(synth.CENTRED_BIAS[name])
+    np.testing.assert_array_equal(centred[:-1], blob[:-1])
