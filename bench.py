@@ -105,12 +105,69 @@ def measured_traffic(prec, workload):
     return e.get("bytes_per_launch")
 
 
+def stage_roofline(stages, steps, H, iters, prec, N, E):
+    """Per-stage roofline of one step (one pass of the whole path): for each
+    group of stages, the algorithmic flops F and HBM bytes B of the method
+    (not of this implementation), T_roof = max(F / MFMA peak, B / HBM peak),
+    the measured time T and T_roof / T.  s = bytes per stored encoding
+    element; messages are float32 in every precision.
+      embedding       F = 34,560 N                 B = 28 N (inputs, embedding)
+      graph           F = 0 (integer/ALU)          B = 24 N + 16 E (embedding read, row pointers and
+                                                   the event-local edge pairs out; incoming lists 8 E + 4 N)
+      encoders        F = 2(3H + H^2) N + 6 H^2 E  B = 12 N + s H N + (s H + 8) E
+      message passing F = n 8 H^2 (N + E) + 2 (H^2 + H) E (with the classifier)
+                      B = n ((2 s H + 8) E + (2 s H + 16 H) N) + 4 E
+      components      F = 0                        B = 9 E + 16 N
+    The float32 path's per-hit first-layer products (hit_proj) count with
+    message passing."""
+    s = STATE_BYTES[prec]
+    P = PEAK_TFLOPS[prec] * 1e12
+    BW = PEAK_HBM_GBS * 1e9
+    groups = {
+        "embedding": (["embed"], 34560 * N, 28 * N),
+        "graph": (["prepare", "knn", "compact", "lists"], 0, 24 * N + 16 * E),
+        "encoders": (["node_enc", "edge_enc"], 2 * (3 * H + H * H) * N + 6 * H * H * E,
+                     12 * N + s * H * N + (s * H + 8) * E),
+        "message_passing": (["hit_proj", "messages", "node_net", "edge_net", "edge_cls"],
+                            iters * 8 * H * H * (N + E) + 2 * (H * H + H) * E,
+                            iters * ((2 * s * H + 8) * E + (2 * s * H + 16 * H) * N) + 4 * E),
+        "components": (["components"], 0, 9 * E + 16 * N),
+    }
+    out, tr, tm = {}, 0.0, 0.0
+    for name, (keys, F, B) in groups.items():
+        t = sum(stages.get(k, (0.0, 0))[0] for k in keys) / steps
+        roof = max(F / P, B / BW) * 1e3
+        out[name] = {"t_ms": round(t, 4), "t_roof_ms": round(roof, 4), "frac": round(roof / t, 4) if t > 0 else None,
+                     "bound": "mfma" if F / P > B / BW else "hbm", "flops": int(F), "bytes": int(B),
+                     "achieved_GBps": round(B / (t * 1e-3) / 1e9, 1) if t > 0 else None}
+        if F:
+            out[name]["achieved_TFLOPs"] = round(F / (t * 1e-3) / 1e12, 2) if t > 0 else None
+        tr += roof
+        tm += t
+    out["total"] = {"t_ms": round(tm, 4), "t_roof_ms": round(tr, 4), "frac": round(tr / tm, 4) if tm > 0 else None}
+    return out
+
+
 def roofline(stages, H, prec, n_edges, n_hits, workload, copy_gbs=None):
     ms, n = stages["edge_net"]
     if not n:
         return None
     avg_ms = ms / n
     flops, nbytes = edge_net_work(H, prec, n_edges, n_hits)
+    if STATE_BYTES[prec] == 4 and stages.get("hit_proj", (0.0, 0))[1]:
+        # the float32 edge network's hit segments are multiplied per hit by
+        # hit_proj: its launches (one per edge MLP) are part of the work
+        hp_ms, hp_n = stages["hit_proj"]
+        proj = hp_ms / hp_n
+        achieved = (flops + 4 * H * H * n_hits) / ((avg_ms + proj) * 1e-3) / 1e12
+        concat = 2 * (3 * H * H + H * H) * n_edges / ((avg_ms + proj) * 1e-3) / 1e12
+        return {"kernel": "edge network with its per-hit first-layer products (fp32 MFMA)", "bound": "mfma",
+                "achieved": round(achieved, 3), "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_TFLOPS[prec], 4), "traffic": measured_traffic(prec, workload),
+                "avg_launch_ms": round(avg_ms, 4), "hit_proj_ms": round(proj, 4),
+                "flops_per_launch": flops + 4 * H * H * n_hits, "bytes_per_launch": nbytes,
+                "arith_intensity": round(flops / nbytes, 1),
+                "frac_of_concatenated_count": round(concat / PEAK_TFLOPS[prec], 4)}
     ridge = PEAK_TFLOPS[prec] * 1e12 / (PEAK_HBM_GBS * 1e9)
     if flops / nbytes >= ridge:
         achieved = flops / (avg_ms * 1e-3) / 1e12
@@ -279,97 +336,78 @@ def run_embed_training(velo, synth, torch, steps, warmup, train_steps):
     return res
 
 
-def run_quality(velo, synth, torch, wl, batch, centred_blob, precisions, train_steps):
-    """Track-finding quality at every precision on the benchmark batch, for two
-    weight sets: the bias-centred random init the throughput is measured with,
-    and weights trained by the library's training form on other generated
-    events (the same network shape).  Each lower precision is compared with
-    fp32: track-efficiency difference in points, edge-decision agreement over
-    the union of the two edge sets, Jaccard overlap and the largest logit
-    difference |z - z_fp32| / max(|z_fp32|, 1) on common edges."""
-    import dataclasses
+TRAINED_BLOB = os.path.join(ROOT, "tests", "golden", "trained_h64_n4.npy")
+
+
+def run_quality(velo, synth, torch, precisions):
+    """Track-finding quality at every precision with a trained network: the
+    embedding and GNN trained by the float64 oracle on generated events of
+    their own seed stream (tests/golden/make_trained_params.py), run on the
+    256 benchmark events with the paper's inference values of the rough
+    graph (d^2 < 0.9, k_max = 50).  Each lower precision is compared with
+    fp32: end to end (its own embedding, so its own graph: decisions over
+    the union of the two edge sets, Jaccard overlap, largest logit
+    difference on common edges) and on the fp32 graph (the GNN's own
+    error)."""
     import numpy as np
-    from paper_2407_12119_amd import metrics, train
-    twl = dataclasses.replace(wl, name=wl.name + "_train", index=3)
-    tbatches = [synth.make_batch(twl, n_events=32, first=32 * i) for i in range(4)]
-    params = torch.from_numpy(synth.init_params(wl)).cuda()
-    log(f"quality: training {train_steps} steps on {sum(b.n_events for b in tbatches)} other events")
-    # Adam with a cosine learning-rate decay (3e-3 -> 3e-5): a constant rate
-    # leaves the final loss, and so the quality figures, at the mercy of where
-    # a noisy trajectory happens to stop
-    tr = train.Trainer(wl, params, tbatches, lr=3e-3)
-    losses = []
-    for s in range(train_steps):
-        tr.lr = 3e-5 + 0.5 * (3e-3 - 3e-5) * (1 + math.cos(math.pi * s / train_steps))
-        losses.append(tr.step())
-    l0 = float(losses[0].cpu())
-    l1 = float(torch.stack(losses[-len(tbatches):]).mean().cpu())   # one step per training batch
-    tr.vctx.check()
-    trained = params.cpu().numpy()
-    tr.close()
+    from paper_2407_12119_amd import metrics
+    if not os.path.exists(TRAINED_BLOB):
+        return {"skipped": "trained weights not generated"}
+    wl = synth.WORKLOADS["batch256_trained"]
+    blob = np.load(TRAINED_BLOB)
+    batch = synth.make_batch(wl)
     hits = velo.DeviceHits.from_batch(batch)
     r2 = float(np.float32(wl.radius * wl.radius))
-    out = {}
-    for tag, blob in (("trained", trained), ("centred", centred_blob)):
-        res, ref = {}, None
-        for prec in precisions:
-            mx = batch.max_event_hits()
-            if prec == "fp8":
-                mx = max(mx, synth.calibration_batch(wl, 16).max_event_hits())
-            ctx = velo.Context(wl.hidden, wl.iters, r2, wl.k_max, wl.edge_logit_min, prec, max_hits=batch.n_hits,
-                               max_events=batch.n_events, max_event_hits=mx)
-            ctx.set_params(torch.from_numpy(blob).cuda())
-            if prec == "fp8":
-                ctx.calibrate(velo.DeviceHits.from_batch(synth.calibration_batch(wl, 16)))
-            dev = ctx.infer(hits)
-            g = velo.graph_to_host(dev, batch.n_hits)
-            same = None
-            if ref is not None:
-                # this precision's GNN and components on the fp32 graph: the
-                # GNN's own error, free of graph differences
-                gs = {k: (v.clone() if hasattr(v, "clone") else v) for k, v in ref_dev.items()}
-                ctx.gnn(hits, gs)
-                ctx.components(hits, gs)
-                same = velo.graph_to_host(gs, batch.n_hits)
-            else:
-                ref_dev = {k: (v.clone() if hasattr(v, "clone") else v) for k, v in dev.items()}
-            ctx.close()
-            m = metrics.track_metrics(g["labels"], batch.pid, batch.event_offsets)
-            r = {k: round(m[k], 5) for k in ("efficiency", "clone_rate", "fake_rate", "hit_efficiency",
-                                              "hit_purity")}
-            r["edges"] = g["n_edges"]
-            r["kept_edges"] = int((g["logit"] >= wl.edge_logit_min).sum())
-            if ref is None:
-                ref = g
-            else:
-                a = metrics.edge_agreement(ref["edge_offsets"], ref["src"], ref["dst"],
-                                           ref["logit"] >= wl.edge_logit_min, g["edge_offsets"], g["src"],
-                                           g["dst"], g["logit"] >= wl.edge_logit_min)
-                r["d_efficiency_pts"] = round(100 * (m["efficiency"] - res[precisions[0]]["efficiency"]), 4)
-                r["decision_agreement"] = round(a["decision_agreement"], 6)
-                r["jaccard"] = round(a["jaccard"], 6)
-                kr = metrics.edge_keys(ref["edge_offsets"], ref["src"], ref["dst"])
-                kg = metrics.edge_keys(g["edge_offsets"], g["src"], g["dst"])
-                _, ia, ib = np.intersect1d(kr, kg, return_indices=True)
-                if ia.size:
-                    zr = ref["logit"][ia].astype(np.float64)
-                    r["max_logit_err"] = float(np.max(np.abs(g["logit"][ib] - zr) / np.maximum(np.abs(zr), 1.0)))
-                zr = ref["logit"].astype(np.float64)
-                dz = np.abs(same["logit"] - zr) / np.maximum(np.abs(zr), 1.0)
-                ms = metrics.track_metrics(same["labels"], batch.pid, batch.event_offsets)
-                r["on_fp32_graph"] = {
-                    "max_logit_err": round(float(dz.max()), 6) if dz.size else 0.0,
-                    "p99_logit_err": round(float(np.percentile(dz, 99)), 6) if dz.size else 0.0,
-                    "decision_agreement": round(float(np.mean((same["logit"] >= wl.edge_logit_min) ==
-                                                              (ref["logit"] >= wl.edge_logit_min))), 6),
-                    "d_efficiency_pts": round(100 * (ms["efficiency"] - res[precisions[0]]["efficiency"]), 4)}
-            res[prec] = r
-        out[tag] = res
-    out["trained"]["train"] = {"steps": train_steps, "events": sum(b.n_events for b in tbatches),
-                               "lr": "cosine 3e-3 -> 3e-5", "loss_first": round(l0, 5),
-                               "loss_last_mean": round(l1, 5)}
-    log(f"quality: {json.dumps(out)}")
-    return out
+    res, ref, ref_dev = {}, None, None
+    for prec in precisions:
+        mx = batch.max_event_hits()
+        if prec == "fp8":
+            mx = max(mx, synth.calibration_batch(wl, 16).max_event_hits())
+        ctx = velo.Context(wl.hidden, wl.iters, r2, wl.k_max, wl.edge_logit_min, prec, max_hits=batch.n_hits,
+                           max_events=batch.n_events, max_event_hits=mx)
+        ctx.set_params(torch.from_numpy(blob).cuda())
+        if prec == "fp8":
+            ctx.calibrate(velo.DeviceHits.from_batch(synth.calibration_batch(wl, 16)))
+        dev = ctx.infer(hits)
+        g = velo.graph_to_host(dev, batch.n_hits)
+        m = metrics.track_metrics(g["labels"], batch.pid, batch.event_offsets)
+        r = {k: round(m[k], 5) for k in ("efficiency", "clone_rate", "fake_rate", "hit_efficiency", "hit_purity")}
+        r["edges"] = g["n_edges"]
+        r["edges_per_hit"] = round(g["n_edges"] / batch.n_hits, 3)
+        r["kept_edges"] = int((g["logit"] >= wl.edge_logit_min).sum())
+        if ref is None:
+            ref = g
+            ref_dev = {k: (v.clone() if hasattr(v, "clone") else v) for k, v in dev.items()}
+            true_kept = 0
+            for b in range(batch.n_events):
+                s0, s1 = int(g["edge_offsets"][b]), int(g["edge_offsets"][b + 1])
+                true_kept += int(synth.truth_labels(batch.event(b).next_hit, g["src"][s0:s1], g["dst"][s0:s1]).sum())
+            r["true_edges_in_graph"] = round(true_kept / max(int((batch.next_hit >= 0).sum()), 1), 5)
+        else:
+            a = metrics.edge_agreement(ref["edge_offsets"], ref["src"], ref["dst"], ref["logit"] >= wl.edge_logit_min,
+                                       g["edge_offsets"], g["src"], g["dst"], g["logit"] >= wl.edge_logit_min)
+            r["d_efficiency_pts"] = round(100 * (m["efficiency"] - res[precisions[0]]["efficiency"]), 4)
+            r["decision_agreement"] = round(a["decision_agreement"], 6)
+            r["jaccard"] = round(a["jaccard"], 6)
+            gs = {k: (v.clone() if hasattr(v, "clone") else v) for k, v in ref_dev.items()}
+            ctx.gnn(hits, gs)
+            ctx.components(hits, gs)
+            same = velo.graph_to_host(gs, batch.n_hits)
+            zr = ref["logit"].astype(np.float64)
+            dz = np.abs(same["logit"] - zr) / np.maximum(np.abs(zr), 1.0)
+            ms = metrics.track_metrics(same["labels"], batch.pid, batch.event_offsets)
+            r["on_fp32_graph"] = {
+                "max_logit_err": round(float(dz.max()), 6) if dz.size else 0.0,
+                "p99_logit_err": round(float(np.percentile(dz, 99)), 6) if dz.size else 0.0,
+                "decision_agreement": round(float(np.mean((same["logit"] >= wl.edge_logit_min) ==
+                                                          (ref["logit"] >= wl.edge_logit_min))), 6),
+                "d_efficiency_pts": round(100 * (ms["efficiency"] - res[precisions[0]]["efficiency"]), 4)}
+        ctx.close()
+        res[prec] = r
+    res["weights"] = "trained by the float64 oracle (embedding 300 steps, GNN 300 steps; see trained_h64_n4.json)"
+    res["workload"] = f"{wl.name}: the {batch.n_events} benchmark events, d2 < 0.9, k_max = {wl.k_max}"
+    log(f"quality: {json.dumps(res)}")
+    return res
 
 
 def transfer_times(torch, batch, out, n_edges, reps=5):
@@ -449,6 +487,101 @@ def knn_compare(ctx, torch, hits, reps=5):
             "speedup": round(times["paper_loop"] / max(times["wavefront"], 1e-9), 2), "same_graph": same}
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_agreement(synth, wl, sample, ref, gpu):
+    """The GPU path's results on the sampled events against the float64
+    oracle's (from raw hits, end to end): edge sets (Jaccard), decisions
+    over the union of the two edge sets, the largest logit difference
+    |z - z_oracle| / max(|z_oracle|, 1) on common edges, identical labels,
+    and the track-finding efficiency difference in points."""
+    import numpy as np
+    from paper_2407_12119_amd import metrics
+    S, n = sample.n_events, sample.n_hits
+    E = int(gpu["edge_offsets"][S])
+    g = {"off": gpu["edge_offsets"][:S + 1], "src": gpu["src"][:E], "dst": gpu["dst"][:E], "z": gpu["logit"][:E],
+         "labels": gpu["labels"][:n]}
+    cut = wl.edge_logit_min
+    a = metrics.edge_agreement(ref["edge_offsets"], ref["src"], ref["dst"], ref["logit"] >= cut, g["off"], g["src"],
+                               g["dst"], g["z"] >= cut)
+    kr = metrics.edge_keys(ref["edge_offsets"], ref["src"], ref["dst"])
+    kg = metrics.edge_keys(g["off"], g["src"], g["dst"])
+    _, ia, ib = np.intersect1d(kr, kg, return_indices=True)
+    zr = ref["logit"][ia]
+    err = np.abs(g["z"][ib] - zr) / np.maximum(np.abs(zr), 1.0) if ia.size else np.zeros(1)
+    mo = metrics.track_metrics(ref["labels"], sample.pid, sample.event_offsets)
+    mg = metrics.track_metrics(g["labels"], sample.pid, sample.event_offsets)
+    return {"jaccard": round(a["jaccard"], 6), "decision_agreement": round(a["decision_agreement"], 6),
+            "max_logit_err": round(float(err.max()), 6), "p99_logit_err": round(float(np.percentile(err, 99)), 6),
+            "labels_identical": round(float(np.mean(g["labels"] == ref["labels"])), 6),
+            "efficiency_oracle": round(mo["efficiency"], 5),
+            "d_efficiency_pts": round(100 * (mg["efficiency"] - mo["efficiency"]), 4)}
+
+
+def run_cpu_baseline(synth, wl, batch, blob, n_sample, n_single, samples):
+    """The float64 oracle timed on the host: the first n_sample events of
+    the workload on all host threads (OpenMP over events), and the first
+    n_single on one thread; its outputs on the sample then measure each
+    GPU precision's agreement with it."""
+    import oracle
+    S = min(n_sample, batch.n_events)
+    sample = synth.to_batch([batch.event(b) for b in range(S)])
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    oracle.set_threads(threads)
+    log(f"cpu oracle on {S} events, {threads} threads")
+    t0 = time.perf_counter()
+    ref = oracle.pipeline(sample, blob, wl.hidden, wl.iters, wl.radius, wl.k_max, wl.edge_logit_min)
+    cdt = time.perf_counter() - t0
+    S1 = min(n_single, S)
+    one = synth.to_batch([batch.event(b) for b in range(S1)])
+    oracle.set_threads(1)
+    log(f"cpu oracle on {S1} events, 1 thread")
+    t0 = time.perf_counter()
+    oracle.pipeline(one, blob, wl.hidden, wl.iters, wl.radius, wl.k_max, wl.edge_logit_min)
+    sdt = time.perf_counter() - t0
+    oracle.set_threads(threads)
+    cpu = {"value": round(S / cdt, 3), "unit": "events/s", "cores": threads, "kind": "oracle",
+           "sample": f"first {S} events of {wl.name} ({sample.n_hits} hits), whole path, "
+                     f"float64 oracle, OpenMP over events, {cdt:.1f} s",
+           "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+           "single_thread": {"value": round(S1 / sdt, 3), "unit": "events/s", "cores": 1,
+                             "sample": f"first {S1} events ({one.n_hits} hits), {sdt:.1f} s"},
+           "note": "a correctness oracle, not a tuned CPU implementation"}
+    if samples:
+        cpu["gpu_vs_oracle"] = {p: oracle_agreement(synth, wl, sample, ref, g) for p, g in samples.items()}
+        log(f"gpu vs oracle on the sample: {json.dumps(cpu['gpu_vs_oracle'])}")
+    return cpu
+
+
+def run_large(velo, synth, torch, steps, warmup, autotune):
+    """The 1000-event workload (Poisson(12) x Poisson(30) tracks, 10% noise;
+    H = 128, n = 8) with bf16 MLP operands: eager events/s, then the whole
+    path captured once into a HIP graph and replayed, with per-batch latency
+    percentiles."""
+    wl = synth.WORKLOADS["batch1000_h128"]
+    log(f"generating {wl.n_events} events ({wl.name})")
+    batch = synth.make_batch(wl)
+    blob = synth.centred_params(wl)
+    hits = velo.DeviceHits.from_batch(batch)
+    ctx, res = run_batched(velo, synth, torch, wl, batch, hits, blob, "bf16", steps, warmup, True, True, autotune)
+    ctx.close()
+    res.pop("transfer", None)
+    res["workload"] = (f"{wl.name}: {batch.n_events} events, {batch.n_hits} hits (up to "
+                       f"{batch.max_event_hits()} per event), H={wl.hidden}, n={wl.iters}, bf16")
+    del hits
+    torch.cuda.empty_cache()
+    return res
+
+
 def run_multistream(synth, torch, wl, blob, prec, n_streams, events_per_stream, passes=3):
     """Throughput with n_streams streams on the GPU, each with its own
     context and events_per_stream events run in batches capped at 2^20 hits
@@ -474,7 +607,7 @@ def run_multistream(synth, torch, wl, blob, prec, n_streams, events_per_stream, 
 
 
 def run_batched(velo, synth, torch, wl, batch, hits, blob, prec, steps, warmup, graph=False, latency=False,
-                autotune=True, copy_gbs=None):
+                autotune=True, copy_gbs=None, samples=None):
     import numpy as np
     r2 = float(np.float32(wl.radius * wl.radius))
     mx = batch.max_event_hits()
@@ -509,10 +642,13 @@ def run_batched(velo, synth, torch, wl, batch, hits, blob, prec, steps, warmup, 
     stages = ctx.read_timing()
     ctx.set_timing(False)
     ctx.check()
+    if samples is not None:
+        samples[prec] = velo.graph_to_host(out, batch.n_hits)
     res = {"value": round(batch.n_events * steps / dt, 2), "ms_per_step": round(1e3 * dt / steps, 4),
            "hits_per_s": round(batch.n_hits * steps / dt, 1), "edges": n_edges,
            "stage_ms_per_step": {k: round(v[0] / steps, 4) for k, v in stages.items()},
-           "roofline": roofline(stages, wl.hidden, prec, n_edges, batch.n_hits, wl.name, copy_gbs)}
+           "roofline": roofline(stages, wl.hidden, prec, n_edges, batch.n_hits, wl.name, copy_gbs),
+           "stage_roofline": stage_roofline(stages, steps, wl.hidden, wl.iters, prec, batch.n_hits, n_edges)}
     # events/s of the path cut after each stage (cumulative, in path order)
     order = ["prepare", "embed", "knn", "compact", "lists", "node_enc", "hit_proj", "edge_enc", "messages",
              "node_net", "edge_net", "edge_cls", "components"]
@@ -572,6 +708,10 @@ def main():
     ap.add_argument("--variants", default="bf16,fp8",
                     help="comma list of extra precisions timed in the same run ('' for none)")
     ap.add_argument("--cpu-sample-events", type=int, default=32)
+    ap.add_argument("--cpu-single-events", type=int, default=4,
+                    help="events of the single-thread oracle timing")
+    ap.add_argument("--no-large", action="store_true", help="skip the 1000-event H = 128 bf16 block")
+    ap.add_argument("--large-steps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-event", action="store_true")
     ap.add_argument("--no-train", action="store_true", help="skip the training-step measurement")
@@ -579,7 +719,6 @@ def main():
     ap.add_argument("--latency", action="store_true", help="per-batch p50/p99 latency (with --graph: of replays)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the built-in launch parameters")
     ap.add_argument("--no-quality", action="store_true", help="skip the track-finding quality block")
-    ap.add_argument("--quality-steps", type=int, default=1500, help="training steps before the quality block")
     ap.add_argument("--streams", type=int, default=16,
                     help="multi-stream throughput mode: streams (0 to skip)")
     ap.add_argument("--stream-events", type=int, default=500, help="events per stream in the multi-stream mode")
@@ -619,8 +758,9 @@ def main():
     copy_gbs = copy_probe_gbs(torch)
     log(f"device copy probe: {copy_gbs} GB/s (read + write)")
 
+    samples = {}
     ctx, main_res = run_batched(velo, synth, torch, wl, batch, hits, blob, args.precision, args.steps,
-                                args.warmup, args.graph, args.latency, not args.no_autotune, copy_gbs)
+                                args.warmup, args.graph, args.latency, not args.no_autotune, copy_gbs, samples)
     sweep = sweep_compare(ctx, torch, hits)
     log(f"components, exact vs the paper's plane sweeps: {json.dumps(sweep)}")
     knn_loop = knn_compare(ctx, torch, hits)
@@ -628,7 +768,7 @@ def main():
     variants = {}
     for prec in [p for p in args.variants.split(",") if p and p != args.precision]:
         vctx, vres = run_batched(velo, synth, torch, wl, batch, hits, blob, prec, args.steps, args.warmup,
-                                 args.graph, args.latency, not args.no_autotune, copy_gbs)
+                                 args.graph, args.latency, not args.no_autotune, copy_gbs, samples)
         vctx.close()
         variants[prec] = vres
     multi = None
@@ -642,10 +782,9 @@ def main():
                                             0 if args.no_quality else args.embed_train_steps)
 
     quality = None
-    if not args.no_quality and wl.hidden <= 64:          # the training form covers H <= 64
-        quality = run_quality(velo, synth, torch, wl, batch, blob,
-                              ["fp32"] + [p for p in ("bf16", "fp8") if p in [args.precision] + list(variants)],
-                              args.quality_steps)
+    if not args.no_quality and args.workload == "batch256":
+        quality = run_quality(velo, synth, torch,
+                              ["fp32"] + [p for p in ("bf16", "fp8") if p in [args.precision] + list(variants)])
 
     per_event = None
     if not args.no_per_event and wl.hidden <= 64:
@@ -672,17 +811,12 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        import oracle
-        S = min(args.cpu_sample_events, batch.n_events)
-        sample = synth.to_batch([batch.event(b) for b in range(S)])
-        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-        log(f"cpu oracle on {S} events, {threads} threads")
-        t0 = time.perf_counter()
-        oracle.pipeline(sample, blob, wl.hidden, wl.iters, wl.radius, wl.k_max, wl.edge_logit_min)
-        cdt = time.perf_counter() - t0
-        cpu = {"value": round(S / cdt, 3), "unit": "events/s", "cores": threads, "kind": "oracle",
-               "sample": f"first {S} events of {wl.name} ({sample.n_hits} hits), whole path, "
-                         f"float64 oracle, OpenMP over events, {cdt:.1f} s"}
+        cpu = run_cpu_baseline(synth, wl, batch, blob, args.cpu_sample_events, args.cpu_single_events, samples)
+
+    large = None
+    if not args.no_large and args.workload == "batch256":
+        ctx.close()
+        large = run_large(velo, synth, torch, args.large_steps, 2, not args.no_autotune)
 
     recipe = wl.recipe
     comp = (f"1 vertex x {recipe.fixed_tracks} tracks" if recipe.fixed_tracks else
@@ -699,7 +833,8 @@ def main():
            "hits_per_s": main_res["hits_per_s"],
            "stage_ms_per_step": main_res["stage_ms_per_step"],
            "roofline": main_res["roofline"], "hbm_copy_GBps": copy_gbs, "cpu_baseline": cpu, "per_event_path": per_event,
-           "variants": variants, "training": training, "embed_training": embed_training, "components_sweep": sweep, "knn_paper_loop": knn_loop, "multi_stream": multi, "quality": quality}
+           "variants": variants, "training": training, "embed_training": embed_training, "components_sweep": sweep, "knn_paper_loop": knn_loop, "multi_stream": multi, "quality": quality,
+           "stage_roofline": main_res["stage_roofline"], "batch1000_h128": large}
     for k in ("graph", "eager"):
         if k in main_res:
             res[k] = main_res[k]

@@ -103,6 +103,28 @@ typedef struct {
     int32_t *n_edges;         /* [1] total edges of the batch */
 } velo_outputs;
 
+/* Results of the triplet stage (velo_triplets).  Edge indices are
+ * event-local: positions within the event's slice of the graph's edge
+ * arrays.  Every pointer must be valid for the sizes given. */
+typedef struct {
+    int32_t *art;              /* [capacity x 2] articulations (a, b): a = A->C, b = C->B */
+    int32_t *art_offsets;      /* [n_events + 1] */
+    float *art_logit;          /* [capacity] articulation classifier logit */
+    int32_t *elb;              /* [capacity x 2] elbows (a, b), a < b: left C->A, C->B; right A->C, B->C */
+    int8_t *elb_type;          /* [capacity] 1 = left elbow, 2 = right elbow */
+    int32_t *elb_offsets;      /* [n_events + 1] */
+    float *elb_logit;          /* [capacity] elbow classifier logit */
+    int64_t capacity;          /* pairs each of the two lists holds (<= the context's max_triplets) */
+    int32_t *n_triplets;       /* [2] totals: articulations, elbows (required sizes on overflow) */
+    int32_t *edge_seg;         /* [the graph's edge_capacity] segment of each kept edge (its smallest
+                                  event-local edge index), -1 for edges below the cut */
+    int32_t *tracks;           /* [track_capacity x 2] segments of each track; the second is -1 for a
+                                  track of one segment */
+    int32_t *track_offsets;    /* [n_events + 1] */
+    int64_t track_capacity;
+    int32_t *n_tracks;         /* [1] total tracks (required size on overflow) */
+} velo_triplet_outputs;
+
 typedef struct velo_ctx velo_ctx;
 
 /* Number of float32 entries of the parameter blob for hidden width H and n
@@ -138,6 +160,67 @@ velo_status velo_set_params(velo_ctx *ctx, const float *params, int64_t n, void 
  * also invalidates earlier activation scales.  Compute calls on an fp8
  * context return VELO_ERR_NOT_CALIBRATED until this has been called. */
 velo_status velo_calibrate(velo_ctx *ctx, const velo_hits *hits, void *stream);
+
+/* Number of float32 entries of the triplet classifiers' parameters for
+ * hidden width H (Sec. 5.3: separate classifiers for articulations and
+ * elbows): for the articulation classifier, then the elbow classifier, a
+ * Linear [H x 2H] + bias [H], ReLU, a Linear [1 x H] + bias [1], applied to
+ * the concatenated final edge encodings [e_a || e_b].  -1: unsupported H. */
+int64_t velo_triplet_param_count(int32_t gnn_hidden);
+
+/* Enable the triplet stage (Sec. 5.3-5.4) on a context: copies the triplet
+ * classifiers' parameters (device, n floats as velo_triplet_param_count
+ * gives), keeps a triplet iff its logit >= triplet_logit_min, and sizes the
+ * stage's workspace for max_triplets articulations and as many elbows.
+ * From then on velo_gnn and velo_infer keep the final edge encodings for
+ * velo_triplets (the edge classifier then runs as its own kernel).
+ * n == 0 with params NULL disables the stage and frees its workspace. */
+velo_status velo_set_triplet_params(velo_ctx *ctx, const float *params, int64_t n, float triplet_logit_min,
+                                    int64_t max_triplets, void *stream);
+
+/* The triplet stage on the graph of the directly preceding velo_gnn or
+ * velo_infer call on this context (same hits and graph; any other call in
+ * between that takes hits is refused with VELO_ERR_INVALID_ARG):
+ *  1. triplets (Sec. 5.3) of the edges kept by the edge cut (logit >=
+ *     edge_logit_min): for every common hit C, articulations (every kept
+ *     in-edge with every kept out-edge), then left elbows (pairs of kept
+ *     out-edges), then right elbows (pairs of kept in-edges); edges in
+ *     ascending index order, hits in index order;
+ *  2. the two triplet classifiers on [e_a || e_b] of the final edge
+ *     encodings (bf16 operands in bf16 and fp8 contexts);
+ *  3. tracks (Sec. 5.4): kept elbows join their edges and mark the edge
+ *     spanning more planes a duplicate; kept articulations without a
+ *     duplicate edge join theirs, except shared ones (whose first edge starts
+ *     or whose second edge ends another such articulation); the joined edge
+ *     sets are the segments; each shared articulation is a track of its two
+ *     segments, every other segment a track of its own (per event: the
+ *     one-segment tracks by label, then the shared articulations in order).
+ * On overflow of a triplet list the totals are written and nothing else;
+ * on overflow of the tracks everything but the tracks and their offsets.
+ * Either way velo_check returns VELO_ERR_CAPACITY. */
+velo_status velo_triplets(velo_ctx *ctx, const velo_hits *hits, const velo_outputs *graph,
+                          velo_triplet_outputs *out, void *stream);
+
+/* INT8 embedding (Sec. 7.4: the embedding network quantised to INT8 with
+ * calibration, which adds a few percent of extra edges).  With scales set,
+ * velo_embed and velo_infer run the embedding's second and third layers
+ * (the two 128-wide-input ones) on INT8 operands, whatever the context's
+ * precision: an operand v enters as q = clamp(rint(fl32(v * fl32(1/s))),
+ * -127, 127) (ties to even) under its tensor's scale s, the integer products
+ * are summed exactly and each layer's sum is descaled by s_x * s_w in
+ * float32 before the bias.  The first layer (three inputs) stays float32.
+ * scales_host = {s_x2, s_w2, s_x3, s_w3}, all positive and finite (the
+ * inputs and weights of the second and third layers); NULL turns INT8 off.
+ * velo_set_params turns it off too (the scales belong to the weights). */
+velo_status velo_set_embed_int8(velo_ctx *ctx, const float *scales_host);
+
+/* Calibrate and enable the INT8 embedding on a calibration batch: runs the
+ * float32 embedding on `hits`, takes the largest value entering the second
+ * and third layers (after their ReLU) and the largest |W| of those layers'
+ * weights, sets s = max / 127 (float32; 1 for an all-zero tensor), writes the
+ * four scales to scales_host (may be NULL) and enables them as
+ * velo_set_embed_int8 does.  Synchronises the stream. */
+velo_status velo_calibrate_embed_int8(velo_ctx *ctx, const velo_hits *hits, float *scales_host, void *stream);
 
 /* Whole path: embedding, rough graph, GNN, edge cut, components.  Writes
  * labels, edge_offsets, edge_src, edge_dst, edge_logit and n_edges. */
@@ -212,7 +295,8 @@ typedef enum {
     VELO_STAGE_HIT_PROJ = 17,  /* fp32 inference: per-hit first-layer products of the edge MLPs */
     VELO_STAGE_EMB_LOSS = 18,  /* embedding training: training pairs and the hinge loss (Sec. 5.1) */
     VELO_STAGE_EMB_BWD = 19,   /* embedding training: back-propagation and weight gradients */
-    VELO_N_STAGES = 20
+    VELO_STAGE_TRIPLETS = 20,  /* triplet stage: triplets, their classifiers, track building */
+    VELO_N_STAGES = 21
 } velo_stage;
 
 /* Enable (1) or disable (0) per-stage timing: while enabled every call
@@ -222,7 +306,11 @@ velo_status velo_set_timing(velo_ctx *ctx, int32_t enable);
 
 /* Synchronise the recorded events and return, per stage, the summed device
  * milliseconds (ms[VELO_N_STAGES]) and the number of timed launches
- * (launches[VELO_N_STAGES]) since the previous read; resets the sums. */
+ * (launches[VELO_N_STAGES]) since the previous read; resets the sums.
+ * The context holds 8192 event pairs between reads: launches beyond that are
+ * not timed, and the read then still fills both arrays (timed launches only)
+ * but returns VELO_ERR_CAPACITY, with the number of untimed launches in
+ * velo_last_error. */
 velo_status velo_read_timing(velo_ctx *ctx, double *ms_host, int64_t *launches_host);
 
 /* ---- graph capture ---- */

@@ -63,7 +63,7 @@ void free_ws(Workspace &w) {
                     w.in_ptr, w.in_list, w.scan_tmp, w.h[0], w.h[1],
                     w.m, w.ab, w.e, w.n_edges, w.flags, w.eoff_tmp, w.ck_h, w.ck_e, w.ck_m, w.ck_ab, w.g_sd, w.g_e[0], w.g_e[1],
                     w.g_h[0], w.g_h[1], w.g_da, w.g_r, w.g_m, w.g_part, w.g_red, w.g_loss,
-                    w.scales, w.amax, w.tmp_logit, w.t_u, w.t_a1, w.t_a2, w.t_dz1, w.t_dz2, w.t_dz3,
+                    w.scales, w.amax, w.tmp_logit, w.i8_scales, w.i8_amax, w.t_u, w.t_a1, w.t_a2, w.t_dz1, w.t_dz2, w.t_dz3,
                     w.t_nbr, w.t_deg, w.t_acc, w.t_stat, w.t_part};
     for (void *p : ptrs)
         if (p) hipFree(p);
@@ -71,6 +71,7 @@ void free_ws(Workspace &w) {
 }
 
 velo_status check_hits(velo_ctx *c, const velo_hits *h) {
+    c->ws_epoch++;        // every call that takes hits may overwrite the workspace
     if (!h) return fail(c, VELO_ERR_INVALID_ARG, "hits is NULL");
     if (!c->params_set) return fail(c, VELO_ERR_INVALID_ARG, "parameters not set (velo_set_params)");
     if (h->n_events < 0 || h->n_hits < 0) return fail(c, VELO_ERR_INVALID_ARG, "negative n_events or n_hits");
@@ -173,7 +174,7 @@ velo_status velo_create(const velo_config *cfg, velo_ctx **out) {
               dalloc((char **)&w.h[0], N * H * sb) && dalloc((char **)&w.h[1], N * H * sb) &&
               dalloc(&w.m, N * 2 * H) && dalloc(&w.ab, N * 2 * H) && dalloc((char **)&w.e, E * H * sb) && dalloc(&w.n_edges, 1) &&
               dalloc(&w.flags, 1) &&
-              dalloc(&w.eoff_tmp, B + 1);
+              dalloc(&w.eoff_tmp, B + 1) && dalloc(&w.i8_scales, 4) && dalloc(&w.i8_amax, 2);
     if (ok && k.precision == VELO_FP8) {
         const int ns = n_slots(k.gnn_iters);
         ok = dalloc(&w.scales, 4 * ns) && dalloc(&w.amax, 2 * ns) && dalloc(&w.tmp_logit, E);
@@ -219,6 +220,8 @@ velo_status velo_create(const velo_config *cfg, velo_ctx **out) {
     return VELO_OK;
 }
 
+static void free_triplet_ws(TripletWs &T);
+
 void velo_destroy(velo_ctx *c) {
     if (!c) return;
     DeviceGuard g(c->device);
@@ -228,6 +231,7 @@ void velo_destroy(velo_ctx *c) {
         hipEventDestroy(e.stop);
     }
     free_ws(c->ws);
+    free_triplet_ws(c->tri);
     if (c->params) hipFree(c->params);
     delete c;
 }
@@ -241,6 +245,7 @@ velo_status velo_set_params(velo_ctx *c, const float *params, int64_t n, void *s
         hipSuccess)
         return fail(c, VELO_ERR_DEVICE, "parameter copy failed");
     c->params_set = true;
+    c->emb_int8 = false;          // INT8 embedding scales belong to the previous parameters
     if (c->cfg.precision == VELO_FP8) {
         launch_weight_scales(c, (hipStream_t)stream);
         c->calibrated = false;    // activation scales belong to the previous parameters
@@ -269,6 +274,58 @@ velo_status velo_calibrate(velo_ctx *c, const velo_hits *h, void *stream) {
     launch_act_scales(c, s);
     c->calibrated = true;
     return device_status(c, "velo_calibrate");
+}
+
+velo_status velo_set_embed_int8(velo_ctx *c, const float *scales) {
+    if (!c) return VELO_ERR_INVALID_ARG;
+    if (!scales) {
+        c->emb_int8 = false;
+        return VELO_OK;
+    }
+    for (int i = 0; i < 4; i++)
+        if (!(scales[i] > 0.f) || !std::isfinite(scales[i]))
+            return fail(c, VELO_ERR_INVALID_ARG, "INT8 embedding scales must be positive and finite");
+    if (!c->params_set) return fail(c, VELO_ERR_INVALID_ARG, "parameters not set (velo_set_params)");
+    DeviceGuard gd(c->device);
+    if (hipMemcpy(c->ws.i8_scales, scales, 4 * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
+        return fail(c, VELO_ERR_DEVICE, "copy of the INT8 scales failed");
+    c->emb_int8 = true;
+    return VELO_OK;
+}
+
+velo_status velo_calibrate_embed_int8(velo_ctx *c, const velo_hits *h, float *scales, void *stream) {
+    if (!c) return VELO_ERR_INVALID_ARG;
+    velo_status st = check_hits(c, h);
+    if (st) return st;
+    DeviceGuard gd(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    Workspace &w = c->ws;
+    launch_fill((int *)w.i8_amax, 0, 2, s);
+    launch_prepare(c, h, s);
+    launch_embed_int8_amax(c, h, w.emb, s);
+    if ((st = device_status(c, "velo_calibrate_embed_int8"))) return st;
+    float amax[2];
+    const ParamLayout &L = c->layout;
+    std::vector<float> w2((size_t)L.emb[1].out * L.emb[1].in), w3((size_t)L.emb[2].out * L.emb[2].in);
+    if (hipMemcpyAsync(amax, w.i8_amax, sizeof amax, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(w2.data(), c->params + L.emb[1].w, sizeof(float) * w2.size(), hipMemcpyDeviceToHost, s) !=
+            hipSuccess ||
+        hipMemcpyAsync(w3.data(), c->params + L.emb[2].w, sizeof(float) * w3.size(), hipMemcpyDeviceToHost, s) !=
+            hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return fail(c, VELO_ERR_DEVICE, "velo_calibrate_embed_int8: copies failed");
+    unsigned flags = 0;
+    if (hipMemcpy(&flags, w.flags, sizeof flags, hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(c, VELO_ERR_DEVICE, "velo_calibrate_embed_int8: flag read failed");
+    if (flags & kErrInput) return fail(c, VELO_ERR_INPUT, "velo_calibrate_embed_int8: invalid calibration hits");
+    float wmax[2] = {0.f, 0.f};
+    for (float v : w2) wmax[0] = std::max(wmax[0], std::fabs(v));
+    for (float v : w3) wmax[1] = std::max(wmax[1], std::fabs(v));
+    // s = max |value| / 127 in float32; a tensor that is all zeros takes s = 1
+    auto scale = [](float m) { return m > 0.f ? m / 127.f : 1.f; };
+    float sc[4] = {scale(amax[0]), scale(wmax[0]), scale(amax[1]), scale(wmax[1])};
+    if (scales) memcpy(scales, sc, sizeof sc);
+    return velo_set_embed_int8(c, sc);
 }
 
 velo_status velo_embed(velo_ctx *c, const velo_hits *h, float *emb, void *stream) {
@@ -342,7 +399,9 @@ velo_status velo_gnn(velo_ctx *c, const velo_hits *h, velo_outputs *g, void *str
         launch_in_lists_plane(c, h, s);
     }
     launch_gnn(c, h, g->edge_logit, c->params, false, false, s);
-    return device_status(c, "velo_gnn");
+    st = device_status(c, "velo_gnn");
+    if (!st && c->tri_set) c->tri_epoch = c->ws_epoch;
+    return st;
 }
 
 velo_status velo_components(velo_ctx *c, const velo_hits *h, velo_outputs *g, void *stream) {
@@ -393,7 +452,102 @@ velo_status velo_infer(velo_ctx *c, const velo_hits *h, velo_outputs *o, void *s
     { StageTimer t(c, VELO_STAGE_LISTS, s); launch_in_lists_plane(c, h, s); }
     launch_gnn(c, h, o->edge_logit, c->params, false, false, s);
     { StageTimer t(c, VELO_STAGE_COMPONENTS, s); launch_components(c, h, o, s); }
-    return device_status(c, "velo_infer");
+    st = device_status(c, "velo_infer");
+    if (!st && c->tri_set) c->tri_epoch = c->ws_epoch;
+    return st;
+}
+
+int64_t velo_triplet_param_count(int32_t H) {
+    if (!triplet_supported(H)) return -1;
+    return 2 * ((int64_t)2 * H * H + 2 * H + 1);
+}
+
+static void free_triplet_ws(TripletWs &T) {
+    void *ptrs[] = {T.params, T.cnt_art, T.cnt_elb, T.art_ptr, T.elb_ptr, T.art_g, T.elb_g, T.n_int, T.par,
+                    T.first, T.second, T.dup, T.touched, T.single, T.single_ptr, T.shared, T.shared_ptr,
+                    T.scan_tmp};
+    for (void *p : ptrs)
+        if (p) hipFree(p);
+    T = TripletWs();
+}
+
+velo_status velo_set_triplet_params(velo_ctx *c, const float *params, int64_t n, float logit_min,
+                                    int64_t max_triplets, void *stream) {
+    if (!c) return VELO_ERR_INVALID_ARG;
+    DeviceGuard gd(c->device);
+    if (!params && n == 0) {
+        hipDeviceSynchronize();
+        free_triplet_ws(c->tri);
+        c->tri_set = false;
+        return VELO_OK;
+    }
+    if (!triplet_supported(c->cfg.gnn_hidden))
+        return fail(c, VELO_ERR_UNSUPPORTED, "triplet stage: unsupported hidden width");
+    if (!params || n != velo_triplet_param_count(c->cfg.gnn_hidden))
+        return fail(c, VELO_ERR_INVALID_ARG, "triplet parameter count does not match the hidden width");
+    if (!std::isfinite(logit_min)) return fail(c, VELO_ERR_INVALID_ARG, "triplet_logit_min must be finite");
+    if (max_triplets < 0 || max_triplets >= ((int64_t)1 << 30))
+        return fail(c, VELO_ERR_INVALID_ARG, "max_triplets must be in 0 .. 2^30 - 1");
+    TripletWs &T = c->tri;
+    if (!T.params || T.cap != max_triplets) {
+        hipDeviceSynchronize();
+        free_triplet_ws(T);
+        const int64_t N = c->cfg.max_hits, E = c->cfg.max_edges, Tc = max_triplets;
+        const int64_t big = std::max(std::max(N, E), Tc);
+        const bool ok = dalloc(&T.params, n) && dalloc(&T.cnt_art, N) && dalloc(&T.cnt_elb, N) &&
+                        dalloc(&T.art_ptr, N + 1) && dalloc(&T.elb_ptr, N + 1) && dalloc(&T.art_g, 2 * Tc) &&
+                        dalloc(&T.elb_g, 2 * Tc) && dalloc(&T.n_int, 4) && dalloc(&T.par, E) &&
+                        dalloc(&T.first, E) && dalloc(&T.second, E) && dalloc(&T.dup, E) &&
+                        dalloc(&T.touched, E) && dalloc(&T.single, E) && dalloc(&T.single_ptr, E + 1) &&
+                        dalloc(&T.shared, Tc) && dalloc(&T.shared_ptr, Tc + 1) &&
+                        dalloc(&T.scan_tmp, scan_tmp_ints(big));
+        if (!ok) {
+            free_triplet_ws(T);
+            c->tri_set = false;
+            return fail(c, VELO_ERR_OOM, "triplet workspace allocation failed");
+        }
+        T.cap = max_triplets;
+    }
+    if (hipMemcpyAsync(T.params, params, sizeof(float) * n, hipMemcpyDeviceToDevice, (hipStream_t)stream) !=
+        hipSuccess)
+        return fail(c, VELO_ERR_DEVICE, "triplet parameter copy failed");
+    c->tri_cut = logit_min;
+    c->tri_set = true;
+    c->tri_epoch = 0;         // the next GNN pass keeps its final edge states
+    return VELO_OK;
+}
+
+velo_status velo_triplets(velo_ctx *c, const velo_hits *h, const velo_outputs *g, velo_triplet_outputs *t,
+                          void *stream) {
+    if (!c) return VELO_ERR_INVALID_ARG;
+    if (!c->tri_set) return fail(c, VELO_ERR_INVALID_ARG, "triplet parameters not set (velo_set_triplet_params)");
+    const bool follows = c->tri_epoch != 0 && c->tri_epoch == c->ws_epoch;
+    velo_status st = check_hits(c, h);
+    if (st) return st;
+    if (!follows)
+        return fail(c, VELO_ERR_INVALID_ARG,
+                    "velo_triplets must directly follow velo_gnn or velo_infer on the same hits and graph");
+    c->tri_epoch = c->ws_epoch;    // a repeated call still sees the same states
+    if ((st = graph_args(c, h, g))) return st;
+    if (g->edge_capacity > 0 && !g->edge_logit) return fail(c, VELO_ERR_INVALID_ARG, "edge_logit is NULL");
+    if (!t) return fail(c, VELO_ERR_INVALID_ARG, "triplet outputs are NULL");
+    if (t->capacity < 0 || t->capacity > c->tri.cap)
+        return fail(c, VELO_ERR_INVALID_ARG, "triplet capacity must be in 0 .. max_triplets of the context");
+    if (t->track_capacity < 0) return fail(c, VELO_ERR_INVALID_ARG, "negative track_capacity");
+    if (!t->n_triplets || !t->n_tracks) return fail(c, VELO_ERR_INVALID_ARG, "n_triplets / n_tracks is NULL");
+    if (h->n_events > 0 && (!t->art_offsets || !t->elb_offsets || !t->track_offsets))
+        return fail(c, VELO_ERR_INVALID_ARG, "triplet offset arrays are NULL");
+    if (t->capacity > 0 && (!t->art || !t->art_logit || !t->elb || !t->elb_type || !t->elb_logit))
+        return fail(c, VELO_ERR_INVALID_ARG, "triplet list arrays are NULL");
+    if (g->edge_capacity > 0 && !t->edge_seg) return fail(c, VELO_ERR_INVALID_ARG, "edge_seg is NULL");
+    if (t->track_capacity > 0 && !t->tracks) return fail(c, VELO_ERR_INVALID_ARG, "tracks is NULL");
+    DeviceGuard gd(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    {
+        StageTimer tm(c, VELO_STAGE_TRIPLETS, s);
+        launch_triplets(c, h, g, t, s);
+    }
+    return device_status(c, "velo_triplets");
 }
 
 velo_status velo_set_timing(velo_ctx *c, int32_t enable) {
@@ -427,6 +581,15 @@ velo_status velo_read_timing(velo_ctx *c, double *ms, int64_t *launches) {
         launches[k] = c->stage_launches[k];
         c->stage_ms[k] = 0;
         c->stage_launches[k] = 0;
+    }
+    if (c->ev_dropped) {
+        char msg[160];
+        snprintf(msg, sizeof msg,
+                 "%lld stage launches were not timed (the pool holds %zu event pairs between reads); "
+                 "the sums returned cover the timed launches only",
+                 (long long)c->ev_dropped, c->ev_pool.size());
+        c->ev_dropped = 0;
+        return fail(c, VELO_ERR_CAPACITY, msg);
     }
     return VELO_OK;
 }

@@ -817,8 +817,9 @@ void gnn_ph(velo_ctx *c, const velo_hits *hits, float *logit, const float *Pw, b
         }
     };
     // the classifier is fused into the last edge network when its weights fit in LDS too
-    const bool fuse_cls =
-        !train && (ab ? mlp_lds<P, H, EDGE_AB, true>() : mlp_lds<P, H, EDGE, true>()) <= c->lds_max;
+    // (not when the triplet stage needs the final edge states)
+    const bool fuse_cls = !train && !c->tri_set &&
+                          (ab ? mlp_lds<P, H, EDGE_AB, true>() : mlp_lds<P, H, EDGE, true>()) <= c->lds_max;
     if (N > 0) {
         const size_t lds = frag_bytes<P>(H, H) + sizeof(float) * H * 4;
         static const int per_cu = blocks_per_cu(reinterpret_cast<const void *>(&k_node_enc<P, H>), kMlpBlock, lds);
@@ -885,15 +886,13 @@ void gnn_ph(velo_ctx *c, const velo_hits *hits, float *logit, const float *Pw, b
 }
 
 template <class P>
-void embed_p(velo_ctx *c, const velo_hits *h, float *emb, bool calib, hipStream_t s) {
+void embed_p(velo_ctx *c, const velo_hits *h, float *emb, const float *sc, float *amax, hipStream_t s) {
     const size_t lds = frag_bytes<P>(kCe, kCe) + frag_bytes<P>(16, kCe) + sizeof(float) * kCe * 4;
     static const int per_cu = blocks_per_cu(reinterpret_cast<const void *>(&k_embed<P>), kMlpBlock, lds);
     const ParamLayout &L = c->layout;
     k_embed<P><<<persistent_grid(c, per_cu), kMlpBlock, lds, s>>>(h->n_hits, h->x, h->y, h->z, c->params, L.emb[0].w,
-                                                             L.emb[1].w, L.emb[2].w, emb,
-                                                             P::kScaled ? c->ws.scales + 4 * kSlotEmbed : nullptr,
-                                                             calib ? c->ws.amax + 2 * kSlotEmbed : nullptr,
-                                                             nullptr, nullptr, nullptr, c->ws.flags);
+                                                             L.emb[1].w, L.emb[2].w, emb, sc, amax, nullptr,
+                                                             nullptr, nullptr, c->ws.flags);
 }
 
 }  // namespace
@@ -992,12 +991,19 @@ void launch_embed_train(velo_ctx *c, const velo_hits *h, const float *params, fl
 void launch_embed(velo_ctx *c, const velo_hits *h, float *emb, bool calib, hipStream_t s) {
     if (h->n_hits <= 0) return;
     const int p = c->cfg.precision;
-    if (p == VELO_FP32)
-        embed_p<F32>(c, h, emb, false, s);
+    if (c->emb_int8 && !calib)
+        embed_p<I8>(c, h, emb, c->ws.i8_scales, nullptr, s);
+    else if (p == VELO_FP32)
+        embed_p<F32>(c, h, emb, nullptr, nullptr, s);
     else if (p == VELO_BF16 || calib)
-        embed_p<BF16>(c, h, emb, calib, s);
+        embed_p<BF16>(c, h, emb, nullptr, calib ? c->ws.amax + 2 * kSlotEmbed : nullptr, s);
     else
-        embed_p<FP8>(c, h, emb, false, s);
+        embed_p<FP8>(c, h, emb, c->ws.scales + 4 * kSlotEmbed, nullptr, s);
+}
+
+void launch_embed_int8_amax(velo_ctx *c, const velo_hits *h, float *emb, hipStream_t s) {
+    if (h->n_hits <= 0) return;
+    embed_p<F32>(c, h, emb, nullptr, c->ws.i8_amax, s);
 }
 
 void launch_gnn(velo_ctx *c, const velo_hits *h, float *logit, const float *params, bool train, bool calib,

@@ -569,7 +569,9 @@ __global__ void k_globalise(int B, const int *__restrict__ off, const int *__res
     const int b = blockIdx.x;
     const int s = off[b], n = off[b + 1] - s;
     const int e0 = eoff[b], e1 = eoff[b + 1];
-    if ((b == 0 && e0 != 0) || (b == B - 1 && e1 != E) || e1 < e0 || e1 > E) {
+    // every block checks its own window: a negative or inverted offset of any
+    // event must not index the edge arrays
+    if ((b == 0 && e0 != 0) || (b == B - 1 && e1 != E) || e0 < 0 || e1 < e0 || e1 > E) {
         if (threadIdx.x == 0 && blockIdx.y == 0) atomicOr(flags, kErrInput);
         return;
     }
@@ -747,11 +749,17 @@ void launch_prepare(velo_ctx *c, const velo_hits *h, hipStream_t s) {
                                           c->ws.hit_event, c->ws.flags);
 }
 
-void launch_scan(velo_ctx *c, const int *in, int *out, int64_t n, hipStream_t s) {
+void launch_scan_with(const int *in, int *out, int64_t n, int *tmp, hipStream_t s) {
     const int nb = (int)((n + kScanTile - 1) / kScanTile);
-    if (nb > 0) k_scan_reduce<<<nb, kScanBlock, 0, s>>>(in, n, c->ws.scan_tmp);
-    k_scan_sums<<<1, kScanBlock, 0, s>>>(c->ws.scan_tmp, nb, out + n);
-    if (nb > 0) k_scan_apply<<<nb, kScanBlock, 0, s>>>(in, n, c->ws.scan_tmp, out);
+    if (nb > 0) k_scan_reduce<<<nb, kScanBlock, 0, s>>>(in, n, tmp);
+    k_scan_sums<<<1, kScanBlock, 0, s>>>(tmp, nb, out + n);
+    if (nb > 0) k_scan_apply<<<nb, kScanBlock, 0, s>>>(in, n, tmp, out);
+}
+
+int64_t scan_tmp_ints(int64_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
+
+void launch_scan(velo_ctx *c, const int *in, int *out, int64_t n, hipStream_t s) {
+    launch_scan_with(in, out, n, c->ws.scan_tmp, s);
 }
 
 void launch_knn_into(velo_ctx *c, const velo_hits *h, const float *emb, int kmax, float d2max, int *nbr, int *deg,

@@ -55,6 +55,8 @@ struct Workspace {
     float *scales = nullptr;     // [4 x n_slots] fp8 per-tensor scales
     float *amax = nullptr;       // [2 x n_slots] calibration maxima of the MLP inputs
     float *tmp_logit = nullptr;  // [max_edges] logits of the calibration pass (fp8 contexts)
+    float *i8_scales = nullptr;  // [4] INT8 embedding scales {s_x2, s_w2, s_x3, s_w3}
+    float *i8_amax = nullptr;    // [2] INT8 calibration maxima of the embedding's layer inputs
     // training (allocated when the config asks for it)
     void *ck_h = nullptr;        // [(n+1) x max_hits x H] hit encodings h^0..h^n
     void *ck_e = nullptr;        // [(n+1) x max_edges x H] edge encodings e^0..e^n
@@ -81,6 +83,24 @@ struct Workspace {
     float *t_part = nullptr;     // [chunks x embedding parameters] weight-gradient partials
 };
 
+// The triplet stage's workspace (allocated by velo_set_triplet_params).
+struct TripletWs {
+    int64_t cap = 0;             // triplets each list holds
+    float *params = nullptr;     // both triplet classifiers, float32
+    int *cnt_art = nullptr, *cnt_elb = nullptr;     // [max_hits] per common hit
+    int *art_ptr = nullptr, *elb_ptr = nullptr;     // [max_hits + 1] exclusive scans
+    int *art_g = nullptr, *elb_g = nullptr;         // [2 cap] batch-global edge ids
+    int *n_int = nullptr;        // [4] internal counts: articulations, elbows (clamped), tracks
+    int *par = nullptr;          // [max_edges] union-find parents over edges, then segment roots
+    int *first = nullptr, *second = nullptr;        // [max_edges] uses of an edge in articulations
+    unsigned char *dup = nullptr, *touched = nullptr;   // [max_edges]
+    int *single = nullptr;       // [max_edges] 1: a segment root making a track of its own
+    int *single_ptr = nullptr;   // [max_edges + 1]
+    int *shared = nullptr;       // [cap] 1: a shared articulation
+    int *shared_ptr = nullptr;   // [cap + 1]
+    int *scan_tmp = nullptr;     // scan_tmp_ints(max(max_hits, max_edges, cap))
+};
+
 }  // namespace velo
 
 struct StageEvents {
@@ -98,6 +118,14 @@ struct velo_ctx {
     bool params_set = false;
     bool train_ready = false;    // a velo_train_forward has filled the checkpoints
     bool calibrated = false;     // fp8 activation scales are set
+    bool emb_int8 = false;       // the embedding runs on INT8 operands (scales in ws.i8_scales)
+    // triplet stage: with parameters set, the GNN keeps the final edge states
+    // (the classifier is not fused into the last edge network)
+    bool tri_set = false;
+    float tri_cut = 0.f;         // keep a triplet iff logit >= tri_cut
+    velo::TripletWs tri;
+    uint64_t ws_epoch = 0;       // counts calls that use the workspace
+    uint64_t tri_epoch = 0;      // epoch of the last GNN pass whose final edge states are kept
     velo::Workspace ws;
     std::string last_error;
     // launch parameters per stage, chosen by velo_autotune (0 = built-in default)
@@ -107,6 +135,7 @@ struct velo_ctx {
     bool timing = false;
     std::vector<StageEvents> ev_pool;     // created on first enable
     size_t ev_used = 0;
+    int64_t ev_dropped = 0;               // stage launches not timed: the pool was full
     double stage_ms[VELO_N_STAGES] = {};
     int64_t stage_launches[VELO_N_STAGES] = {};
 };
@@ -120,6 +149,9 @@ void launch_knn_loop(velo_ctx *c, const velo_hits *h, const float *emb, hipStrea
 void launch_knn_into(velo_ctx *c, const velo_hits *h, const float *emb, int kmax, float d2max, int *nbr, int *deg,
                      hipStream_t s);
 void launch_scan(velo_ctx *c, const int *in, int *out, int64_t n, hipStream_t s);
+// exclusive scan of n ints into out[0..n] (out[n] = total) with a temporary of scan_tmp_ints(n) ints
+void launch_scan_with(const int *in, int *out, int64_t n, int *tmp, hipStream_t s);
+int64_t scan_tmp_ints(int64_t n);
 void launch_compact(velo_ctx *c, const velo_hits *h, velo_outputs *g, hipStream_t s);
 void launch_globalise(velo_ctx *c, const velo_hits *h, const velo_outputs *g, hipStream_t s);
 // row_ptr of a given graph (edges grouped by source, checked by launch_globalise)
@@ -131,6 +163,8 @@ void launch_in_lists_plane(velo_ctx *c, const velo_hits *h, hipStream_t s);
 size_t state_bytes(int precision);              // bytes per stored encoding element
 bool gnn_supported(int hidden, int precision);  // compiled (hidden, precision) pairs
 void launch_embed(velo_ctx *c, const velo_hits *h, float *emb, bool calib, hipStream_t s);
+// float32 embedding recording the largest input of its second and third layers into ws.i8_amax
+void launch_embed_int8_amax(velo_ctx *c, const velo_hits *h, float *emb, hipStream_t s);
 void launch_components_sweep(velo_ctx *c, const velo_hits *h, const velo_outputs *g, hipStream_t s);
 void launch_focal(velo_ctx *c, const float *logit, const uint8_t *y, float alpha, float gamma, int64_t n,
                   float *loss, float *dlogit, hipStream_t s);
@@ -167,6 +201,11 @@ void launch_bce(velo_ctx *c, const float *logit, const uint8_t *y, float pos_wei
 void launch_gnn_backward(velo_ctx *c, const velo_hits *h, const float *params, const float *dlogit, float *dparams,
                          hipStream_t s);
 
+// ---- launchers (triplets.hip) ----
+bool triplet_supported(int hidden);
+void launch_triplets(velo_ctx *c, const velo_hits *h, const velo_outputs *g, const velo_triplet_outputs *t,
+                     hipStream_t s);
+
 // ---- launchers (wcc.hip) ----
 void launch_components(velo_ctx *c, const velo_hits *h, const velo_outputs *g, hipStream_t s);
 
@@ -176,10 +215,13 @@ struct StageTimer {
     hipStream_t s;
     StageEvents *ev = nullptr;
     StageTimer(velo_ctx *ctx, int stage, hipStream_t stream) : c(ctx), s(stream) {
-        if (c->timing && c->ev_used < c->ev_pool.size()) {
+        if (!c->timing) return;
+        if (c->ev_used < c->ev_pool.size()) {
             ev = &c->ev_pool[c->ev_used++];
             ev->stage = stage;
             hipEventRecord(ev->start, s);
+        } else {
+            c->ev_dropped++;         // reported by velo_read_timing
         }
     }
     ~StageTimer() {

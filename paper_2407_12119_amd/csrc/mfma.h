@@ -165,6 +165,50 @@ struct FP8 {
     __device__ static float absmax(const frag_t &) { return 0.f; }
 };
 
+// I8: symmetric INT8 matrix operands (v_mfma_i32_16x16x64_i8) with static
+// per-tensor scales, for the embedding MLP (Sec. 7.4 quantises the embedding
+// to INT8).  An operand v is fed as the code q = clamp(rint(fl32(v * (1/s))),
+// -127, 127) (ties to even); each 64-wide K block's integer sums (at most
+// 64 * 127^2 in magnitude) are added to float32 accumulators, which stays
+// exact while |sum| < 2^24 (K <= 1024), and the accumulators are descaled by
+// s_x * s_w after the last block.  Lane group g owns channels
+// 64 kb + 16 q + 4 g + (0..3), q = 0..3: the accumulators of output blocks
+// 4 kb + q chain into the next layer's operand without moving.
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+struct I8 {
+    static constexpr bool kScaled = true;
+    using state_t = float;
+    using frag_t = i32x4;        // 16 int8 codes
+    using wfrag_t = i32x4;
+    static constexpr int KBLK = 64;
+    static constexpr int WJ = 16;
+    __device__ static int col(int kb, int g, int j) { return 64 * kb + 16 * (j >> 2) + 4 * g + (j & 3); }
+    __device__ static int code(float v, float inv) {
+        const float t = __builtin_rintf(v * inv);
+        return (int)fminf(fmaxf(t, -127.f), 127.f);
+    }
+    __device__ static int pack4(f32x4 v, float inv) {
+        return (code(v[0], inv) & 0xff) | ((code(v[1], inv) & 0xff) << 8) | ((code(v[2], inv) & 0xff) << 16) |
+               ((unsigned)code(v[3], inv) << 24);
+    }
+    template <int MO>
+    __device__ static void mma(const wfrag_t *a, const frag_t &x, f32x4 *acc) {
+#pragma unroll
+        for (int mo = 0; mo < MO; mo++) {
+            const i32x4 t = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[mo], x, i32x4{0, 0, 0, 0}, 0, 0, 0);
+#pragma unroll
+            for (int i = 0; i < 4; i++) acc[mo][i] += (float)t[i];
+        }
+    }
+    template <int MO>
+    __device__ static void chain(const f32x4 *h, frag_t *x, float inv) {
+#pragma unroll
+        for (int kb = 0; kb < MO / 4; kb++)
+            x[kb] = i32x4{pack4(h[4 * kb], inv), pack4(h[4 * kb + 1], inv), pack4(h[4 * kb + 2], inv),
+                          pack4(h[4 * kb + 3], inv)};
+    }
+};
+
 // Weight staging converts every element with a scale: fp8 stores e4m3(w / s_w).
 template <class P>
 __device__ inline typename P::wfrag_t pack_weights(const float *w, float inv);
@@ -204,6 +248,12 @@ __device__ inline bf16x8 pack_weights<BF16>(const float *w, float) {
 template <>
 __device__ inline long pack_weights<FP8>(const float *w, float inv) {
     return FP8::pack8(f32x4{w[0], w[1], w[2], w[3]}, f32x4{w[4], w[5], w[6], w[7]}, inv);
+}
+
+template <>
+__device__ inline i32x4 pack_weights<I8>(const float *w, float inv) {
+    return i32x4{I8::pack4(f32x4{w[0], w[1], w[2], w[3]}, inv), I8::pack4(f32x4{w[4], w[5], w[6], w[7]}, inv),
+                 I8::pack4(f32x4{w[8], w[9], w[10], w[11]}, inv), I8::pack4(f32x4{w[12], w[13], w[14], w[15]}, inv)};
 }
 
 template <class P>

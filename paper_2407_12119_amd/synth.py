@@ -80,7 +80,12 @@ WORKLOADS = {
     "batch256_lowp": Workload("batch256_lowp", 1, 256, _PILEUP, 64, 4),
     "train32": Workload("train32", 3, 32, _PILEUP, 64, 6),
     "batch1000_h128": Workload("batch1000_h128", 4, 1000, EventRecipe(None, 12.0, 30.0, 0.10), 128, 8),
+    # the 256 pile-up events again, for a trained network at the paper's
+    # inference values of the rough graph (Sec. 5.1: d^2 < 0.9, k_max = 50)
+    "batch256_trained": Workload("batch256_trained", 1, 256, _PILEUP, 64, 4, radius=math.sqrt(0.9), k_max=50),
 }
+# seed stream of the events the trained network was trained on
+TRAINED_TRAIN_INDEX = 5
 
 
 @dataclasses.dataclass
@@ -296,6 +301,29 @@ def init_params(wl: Workload, seed_words: Optional[Sequence[int]] = None) -> np.
         parts.append(rng.uniform(-bound, bound, size=o * i))
         parts.append(rng.uniform(-bound, bound, size=o))
     return np.concatenate(parts).astype(np.float32)
+
+
+def init_triplet_params(hidden: int, seed_words: Sequence[int] = (200,)) -> np.ndarray:
+    """Seeded random init of the two triplet classifiers (articulations, then
+    elbows; each Linear [H x 2H] + [H], Linear [1 x H] + [1]), drawn like
+    init_params: U(-1/sqrt(fan_in), 1/sqrt(fan_in)) in float64, rounded."""
+    rng = _rng(*seed_words)
+    parts = []
+    for _ in range(2):
+        for o, i in ((hidden, 2 * hidden), (1, hidden)):
+            bound = 1.0 / math.sqrt(i)
+            parts.append(rng.uniform(-bound, bound, size=o * i))
+            parts.append(rng.uniform(-bound, bound, size=o))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def with_triplet_biases(tblob: np.ndarray, hidden: int, b_art: float, b_elb: float) -> np.ndarray:
+    """Copy of a triplet parameter blob with both output biases replaced."""
+    out = tblob.copy()
+    per = 2 * hidden * hidden + 2 * hidden + 1
+    out[per - 1] = np.float32(b_art)
+    out[2 * per - 1] = np.float32(b_elb)
+    return out
 
 
 def with_classifier_bias(blob: np.ndarray, hidden: int, iters: int, bias: float) -> np.ndarray:

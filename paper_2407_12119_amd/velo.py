@@ -28,10 +28,11 @@ EXPORTS = ("velo_param_count", "velo_create", "velo_destroy", "velo_set_params",
            "velo_train_forward", "velo_bce", "velo_train_backward", "velo_adam_step",
            "velo_graph_capture", "velo_graph_launch", "velo_graph_destroy", "velo_calibrate",
            "velo_autotune", "velo_embed_train_grad", "velo_focal", "velo_components_sweep",
-           "velo_build_graph_loop")
+           "velo_build_graph_loop", "velo_set_embed_int8", "velo_calibrate_embed_int8",
+           "velo_triplet_param_count", "velo_set_triplet_params", "velo_triplets")
 STAGES = ("prepare", "embed", "knn", "compact", "lists", "node_enc", "edge_enc", "messages",
           "node_net", "edge_net", "edge_cls", "components", "bce", "bwd_mlp", "bwd_dw", "bwd_graph", "adam",
-          "hit_proj", "emb_loss", "emb_bwd")
+          "hit_proj", "emb_loss", "emb_bwd", "triplets")
 
 
 class VeloError(RuntimeError):
@@ -56,6 +57,14 @@ class _Outputs(C.Structure):
     _fields_ = [("labels", C.c_void_p), ("edge_offsets", C.c_void_p), ("edge_src", C.c_void_p),
                 ("edge_dst", C.c_void_p), ("edge_logit", C.c_void_p), ("edge_capacity", C.c_int64),
                 ("n_edges", C.c_void_p)]
+
+
+class _TripletOutputs(C.Structure):
+    _fields_ = [("art", C.c_void_p), ("art_offsets", C.c_void_p), ("art_logit", C.c_void_p),
+                ("elb", C.c_void_p), ("elb_type", C.c_void_p), ("elb_offsets", C.c_void_p),
+                ("elb_logit", C.c_void_p), ("capacity", C.c_int64), ("n_triplets", C.c_void_p),
+                ("edge_seg", C.c_void_p), ("tracks", C.c_void_p), ("track_offsets", C.c_void_p),
+                ("track_capacity", C.c_int64), ("n_tracks", C.c_void_p)]
 
 
 _lib: Optional[C.CDLL] = None
@@ -122,6 +131,16 @@ def lib() -> C.CDLL:
         L.velo_components_sweep.restype = st
         L.velo_build_graph_loop.argtypes = [vp, C.POINTER(_Hits), vp, C.POINTER(_Outputs), vp]
         L.velo_build_graph_loop.restype = st
+        L.velo_set_embed_int8.argtypes = [vp, vp]
+        L.velo_set_embed_int8.restype = st
+        L.velo_calibrate_embed_int8.argtypes = [vp, C.POINTER(_Hits), vp, vp]
+        L.velo_calibrate_embed_int8.restype = st
+        L.velo_triplet_param_count.argtypes = [C.c_int32]
+        L.velo_triplet_param_count.restype = C.c_int64
+        L.velo_set_triplet_params.argtypes = [vp, vp, C.c_int64, C.c_float, C.c_int64, vp]
+        L.velo_set_triplet_params.restype = st
+        L.velo_triplets.argtypes = [vp, C.POINTER(_Hits), C.POINTER(_Outputs), C.POINTER(_TripletOutputs), vp]
+        L.velo_triplets.restype = st
         _lib = L
     return _lib
 
@@ -221,6 +240,70 @@ class Context:
         n = np.zeros(len(STAGES), np.int64)
         self._raise(self._lib.velo_read_timing(self._h, ms.ctypes.data, n.ctypes.data), "velo_read_timing")
         return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(STAGES)}
+
+    def set_triplet_params(self, tparams, logit_min: float = 0.0, max_triplets: int = 1 << 20):
+        """Enable the triplet stage with the two classifiers' parameters (a
+        float32 device tensor); None disables it."""
+        if tparams is None:
+            self._raise(self._lib.velo_set_triplet_params(self._h, None, 0, 0.0, 0, _stream()),
+                        "velo_set_triplet_params")
+            return
+        self._raise(self._lib.velo_set_triplet_params(self._h, _ptr(tparams), tparams.numel(), float(logit_min),
+                                                      int(max_triplets), _stream()), "velo_set_triplet_params")
+        self.max_triplets = int(max_triplets)
+
+    def alloc_triplet_outputs(self, hits: DeviceHits, graph, capacity: int, track_capacity: int):
+        import torch
+        dev = hits.x.device
+        B = hits.n_events
+        return {"art": torch.empty(max(capacity, 1), 2, dtype=torch.int32, device=dev),
+                "art_offsets": torch.empty(B + 1, dtype=torch.int32, device=dev),
+                "art_logit": torch.empty(max(capacity, 1), dtype=torch.float32, device=dev),
+                "elb": torch.empty(max(capacity, 1), 2, dtype=torch.int32, device=dev),
+                "elb_type": torch.empty(max(capacity, 1), dtype=torch.int8, device=dev),
+                "elb_offsets": torch.empty(B + 1, dtype=torch.int32, device=dev),
+                "elb_logit": torch.empty(max(capacity, 1), dtype=torch.float32, device=dev),
+                "capacity": int(capacity),
+                "n_triplets": torch.zeros(2, dtype=torch.int32, device=dev),
+                "edge_seg": torch.empty(max(int(graph["edge_capacity"]), 1), dtype=torch.int32, device=dev),
+                "tracks": torch.empty(max(track_capacity, 1), 2, dtype=torch.int32, device=dev),
+                "track_offsets": torch.empty(B + 1, dtype=torch.int32, device=dev),
+                "track_capacity": int(track_capacity),
+                "n_tracks": torch.zeros(1, dtype=torch.int32, device=dev)}
+
+    def triplets(self, hits: DeviceHits, graph, out=None, capacity: Optional[int] = None,
+                 track_capacity: Optional[int] = None, check: bool = True):
+        """velo_triplets on the graph of the directly preceding gnn/infer call."""
+        if out is None:
+            cap = getattr(self, "max_triplets", 0) if capacity is None else capacity
+            tcap = int(graph["edge_capacity"]) + cap if track_capacity is None else track_capacity
+            out = self.alloc_triplet_outputs(hits, graph, cap, tcap)
+        oc = self._out_c(graph)
+        hc = hits.c()
+        tc = _TripletOutputs(*[(_ptr(out[k]) if k not in ("capacity", "track_capacity") else out[k])
+                               for k, _ in _TripletOutputs._fields_])
+        self._raise(self._lib.velo_triplets(self._h, C.byref(hc), C.byref(oc), C.byref(tc), _stream()),
+                    "velo_triplets")
+        if check:
+            self.check()
+        return out
+
+    def set_embed_int8(self, scales):
+        """INT8 embedding with the four float32 scales {s_x2, s_w2, s_x3, s_w3}; None: off."""
+        if scales is None:
+            self._raise(self._lib.velo_set_embed_int8(self._h, None), "velo_set_embed_int8")
+            return
+        sc = (C.c_float * 4)(*[float(v) for v in scales])
+        self._raise(self._lib.velo_set_embed_int8(self._h, C.cast(sc, C.c_void_p)), "velo_set_embed_int8")
+
+    def calibrate_embed_int8(self, hits: DeviceHits):
+        """Calibrate and enable the INT8 embedding on a batch; returns the four scales."""
+        import numpy as np
+        sc = (C.c_float * 4)()
+        hc = hits.c()
+        self._raise(self._lib.velo_calibrate_embed_int8(self._h, C.byref(hc), C.cast(sc, C.c_void_p), _stream()),
+                    "velo_calibrate_embed_int8")
+        return np.array(list(sc), np.float32)
 
     def calibrate(self, hits: DeviceHits, check: bool = True):
         """fp8: set the activation scales from a calibration batch."""
@@ -427,6 +510,25 @@ class Graph:
             self.close()
         except Exception:
             pass
+
+
+def triplet_param_count(hidden: int) -> int:
+    return int(lib().velo_triplet_param_count(hidden))
+
+
+def triplets_to_host(t: Dict[str, object]) -> Dict[str, np.ndarray]:
+    """Copy velo_triplets results to numpy (lists cut to their counts)."""
+    na, ne = (int(v) for v in t["n_triplets"].cpu())
+    nt = int(t["n_tracks"].cpu()[0])
+    na, ne, nt = min(na, t["capacity"]), min(ne, t["capacity"]), min(nt, t["track_capacity"])
+    return {"art": t["art"][:na].cpu().numpy(), "art_offsets": t["art_offsets"].cpu().numpy().astype(np.int64),
+            "art_logit": t["art_logit"][:na].cpu().numpy(), "elb": t["elb"][:ne].cpu().numpy(),
+            "elb_type": t["elb_type"][:ne].cpu().numpy(),
+            "elb_offsets": t["elb_offsets"].cpu().numpy().astype(np.int64),
+            "elb_logit": t["elb_logit"][:ne].cpu().numpy(), "edge_seg": t["edge_seg"].cpu().numpy(),
+            "tracks": t["tracks"][:nt].cpu().numpy(),
+            "track_offsets": t["track_offsets"].cpu().numpy().astype(np.int64), "n_art": na, "n_elb": ne,
+            "n_tracks": nt}
 
 
 def graph_to_host(out: Dict[str, object], n_hits: Optional[int] = None) -> Dict[str, np.ndarray]:

@@ -13,7 +13,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def _declared():
     with open(os.path.join(ROOT, "include", "velognn.h")) as f:
         src = f.read()
-    return sorted(set(re.findall(r"\b(velo_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(velo_[a-z_0-9]+)\s*\(", src)))
 
 
 def test_library_exports_every_declared_symbol():

@@ -221,6 +221,28 @@ def test_given_graph_must_be_grouped_by_source():
     ctx.gnn(hits, g)
 
 
+def test_given_graph_with_a_negative_interior_edge_offset():
+    """A caller's edge_offsets with a negative entry for an event other than
+    the first (e.g. [0, -5, n, E]) is an input error caught by every event's
+    own window check, before any edge index is formed; the context works
+    afterwards."""
+    wl = synth.WORKLOADS["batch256"]
+    batch = synth.make_batch(wl, n_events=3, first=3)
+    ctx, hits, _ = _setup(wl, batch)
+    g = ctx.build_graph(hits, ctx.embed(hits))
+    for bad_off in (-5, -(1 << 30)):
+        bad = {k: (v.clone() if hasattr(v, "clone") else v) for k, v in g.items()}
+        bad["edge_offsets"][1] = bad_off
+        with pytest.raises(velo.VeloError) as ei:
+            ctx.gnn(hits, bad)
+        assert ei.value.status == velo.VELO_ERR_INPUT
+        with pytest.raises(velo.VeloError) as ei:
+            ctx.components(hits, bad)
+        assert ei.value.status == velo.VELO_ERR_INPUT
+    z = ctx.gnn(hits, g)
+    assert z is not None
+
+
 def _hub_event(rng, counts):
     """Hits on a few planes with the given counts; an event plus a given graph
     whose destinations are skewed onto 20 hub hits per plane."""
@@ -503,3 +525,14 @@ def test_paper_neighbour_loop_variant_gives_the_same_graph(kind):
     b = velo.graph_to_host(ctx.build_graph_loop(hits, emb), batch.n_hits)
     for k in ("edge_offsets", "src", "dst"):
         np.testing.assert_array_equal(a[k], b[k], err_msg=k)
+    # and the oracle's neighbour sets on the same float32 embedding
+    e_host = emb.cpu().numpy()
+    r2 = oracle.d2max_f32(wl.radius)
+    for ev_i in range(batch.n_events):
+        ev = batch.event(ev_i)
+        o0 = int(batch.event_offsets[ev_i])
+        rp, col = oracle.neighbours(ev.plane, e_host[o0:o0 + ev.n], r2, wl.k_max)
+        src, dst = oracle.csr_to_edges(rp, col)
+        s0, s1 = int(b["edge_offsets"][ev_i]), int(b["edge_offsets"][ev_i + 1])
+        np.testing.assert_array_equal(b["src"][s0:s1], src, err_msg=f"loop src event {ev_i}")
+        np.testing.assert_array_equal(b["dst"][s0:s1], dst, err_msg=f"loop dst event {ev_i}")
