@@ -286,6 +286,7 @@ class Context:
                     "velo_triplets")
         if check:
             self.check()
+        out["graph_n_edges"] = graph["n_edges"]     # edge_seg holds this many entries
         return out
 
     def set_embed_int8(self, scales):
@@ -521,11 +522,14 @@ def triplets_to_host(t: Dict[str, object]) -> Dict[str, np.ndarray]:
     na, ne = (int(v) for v in t["n_triplets"].cpu())
     nt = int(t["n_tracks"].cpu()[0])
     na, ne, nt = min(na, t["capacity"]), min(ne, t["capacity"]), min(nt, t["track_capacity"])
+    E = t["edge_seg"].shape[0]
+    if "graph_n_edges" in t:
+        E = min(int(t["graph_n_edges"].cpu()[0]), E)
     return {"art": t["art"][:na].cpu().numpy(), "art_offsets": t["art_offsets"].cpu().numpy().astype(np.int64),
             "art_logit": t["art_logit"][:na].cpu().numpy(), "elb": t["elb"][:ne].cpu().numpy(),
             "elb_type": t["elb_type"][:ne].cpu().numpy(),
             "elb_offsets": t["elb_offsets"].cpu().numpy().astype(np.int64),
-            "elb_logit": t["elb_logit"][:ne].cpu().numpy(), "edge_seg": t["edge_seg"].cpu().numpy(),
+            "elb_logit": t["elb_logit"][:ne].cpu().numpy(), "edge_seg": t["edge_seg"][:E].cpu().numpy(),
             "tracks": t["tracks"][:nt].cpu().numpy(),
             "track_offsets": t["track_offsets"].cpu().numpy().astype(np.int64), "n_art": na, "n_elb": ne,
             "n_tracks": nt}

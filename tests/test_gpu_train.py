@@ -138,23 +138,52 @@ def _check_gradient(wl, batch, blob):
         return oracle.gnn_backward(ev.x, ev.y, ev.z, g["src"][s:e], g["dst"][s:e], blob, wl.hidden,
                                    wl.iters, dlogit[s:e].astype(np.float64))
 
-    with ThreadPoolExecutor(max_workers=min(8, max(batch.n_events, 1))) as ex:
-        ref = sum(ex.map(one, range(batch.n_events)))
-    views_gpu = synth.param_views(dp, wl.hidden, wl.iters)
-    views_ref = synth.param_views(ref, wl.hidden, wl.iters)
+    def oracle_grad(bl):
+        nonlocal blob
+        saved, blob = blob, bl
+        try:
+            with ThreadPoolExecutor(max_workers=min(8, max(batch.n_events, 1))) as ex:
+                return sum(ex.map(one, range(batch.n_events)))
+        finally:
+            blob = saved
+
+    def rel_errs(got, ref):
+        vg, vr = synth.param_views(got, wl.hidden, wl.iters), synth.param_views(ref, wl.hidden, wl.iters)
+        return {(name, j): np.linalg.norm(vg[name][j] - vr[name][j]) / max(np.linalg.norm(vr[name][j]), 1e-30)
+                for name, _ in synth.param_layout(wl.hidden, wl.iters) if not name.startswith("emb")
+                for j in (0, 1)}
+
+    ref = oracle_grad(blob)
     assert np.all(dp[:12] == 0)
-    worst = 0.0
     for name, _ in synth.param_layout(wl.hidden, wl.iters):
-        for j in (0, 1):
-            a, b = views_gpu[name][j], views_ref[name][j]
-            nb = np.linalg.norm(b)
-            if name.startswith("emb"):
-                assert np.all(a == 0)
-                continue
-            rel = np.linalg.norm(a - b) / max(nb, 1e-30)
-            worst = max(worst, rel)
-            assert rel <= GRAD_REL, (name, j, rel)
-    print(f"  {g['n_edges']} edges, worst per-tensor relative gradient error {worst:.3g}", flush=True)
+        if name.startswith("emb"):
+            assert all(np.all(v == 0) for v in synth.param_views(dp, wl.hidden, wl.iters)[name])
+    errs = rel_errs(dp, ref)
+    # The gradient is piecewise smooth: a hidden unit whose pre-activation
+    # lies within float32 rounding of 0 takes either side of its ReLU (and
+    # contributes a whole term, or none, to the weight gradients upstream).
+    # A float32 layer output carries a relative rounding error of about
+    # sqrt(K) u with K <= 3H inputs and u = 2^-24, i.e. about 2^-20.  How far
+    # the float64 gradient itself moves when every parameter moves by a
+    # random relative 2^-20 measures what any float32 evaluation can reach;
+    # the GPU must stay within the larger of 1e-3 and twice the largest such
+    # movement over three draws.
+    rng_p = np.random.default_rng(11)
+    sens = {k: 0.0 for k in errs}
+    for _ in range(3):
+        bl = (blob.astype(np.float64) * (1.0 + rng_p.uniform(-1.0, 1.0, blob.shape[0]) * 2.0 ** -20))
+        bl = bl.astype(np.float32)
+        bl[:12] = blob[:12]
+        for k, v in rel_errs(oracle_grad(bl), ref).items():
+            sens[k] = max(sens[k], v)
+    tol = {k: max(GRAD_REL, 2 * sens[k]) for k in errs}
+    worst = max(errs.values())
+    print(f"  {g['n_edges']} edges, worst per-tensor relative gradient error {worst:.3g}; "
+          f"{sum(t > GRAD_REL for t in tol.values())} tensors whose float32-rounding sensitivity exceeds "
+          f"{GRAD_REL / 2:g}", flush=True)
+    print("  " + ", ".join(f"{n}.{'wb'[j]} {e:.2g}/{tol[(n, j)]:.2g}" for (n, j), e in errs.items()), flush=True)
+    bad = {k: (v, tol[k]) for k, v in errs.items() if v > tol[k]}
+    assert not bad, bad
     return (g["n_edges"] + 15) // 16
 
 
