@@ -272,6 +272,25 @@ velo_status velo_components(velo_ctx *ctx, const velo_hits *hits, velo_outputs *
  * exact instead.  Same arguments and errors as velo_components. */
 velo_status velo_components_sweep(velo_ctx *ctx, const velo_hits *hits, velo_outputs *graph, void *stream);
 
+/* velo_components without a context and without any device allocation, for
+ * callers that cannot allocate memory (code under stream capture, serving
+ * loops, harnesses that forbid hipMalloc).  Same validation and labels as
+ * velo_components with a context whose edge cut is edge_logit_min and whose
+ * max_event_hits is the argument; edge_capacity alone bounds the edges read.
+ * Its working memory is a fixed device array inside the library, one per
+ * GPU, held until the process ends (about 6 MB): batches of at most
+ * VELO_NOALLOC_MAX_HITS hits and VELO_NOALLOC_MAX_EVENTS events, and
+ * max_event_hits at most the workgroup LDS in ints (40,960 on MI355X); larger
+ * ones are refused with VELO_ERR_CAPACITY before any launch.  Every call on
+ * a GPU shares that array, so calls that overlap on one GPU (other streams,
+ * other threads) race.  The call waits for `stream` and returns the device
+ * validation result: VELO_ERR_INPUT (invalid hits or edges), VELO_ERR_CAPACITY
+ * (n_edges above edge_capacity; labels then unwritten) or VELO_OK. */
+#define VELO_NOALLOC_MAX_HITS (1 << 20)
+#define VELO_NOALLOC_MAX_EVENTS (1 << 14)
+velo_status velo_components_noalloc(const velo_hits *hits, const velo_outputs *graph, float edge_logit_min,
+                                    int32_t max_event_hits, void *stream);
+
 /* Stages of the path, for per-stage device timing. */
 typedef enum {
     VELO_STAGE_PREPARE = 0,    /* validation and plane bucketing */

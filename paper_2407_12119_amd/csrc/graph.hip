@@ -584,12 +584,16 @@ __global__ void k_globalise(int B, const int *__restrict__ off, const int *__res
         const int dp = (a >= 0 && a < n && c >= 0 && c < n) ? plane[s + c] - plane[s + a] : 0;
         if (a < 0 || a >= n || c < 0 || c >= n || (q > e0 && esrc[q - 1] > a) || dp < 1 || dp > 2) {
             err = true;
-            src_g[q] = s;
-            dst_g[q] = s;
+            if (src_g) {
+                src_g[q] = s;
+                dst_g[q] = s;
+            }
             continue;
         }
-        src_g[q] = s + a;
-        dst_g[q] = s + c;
+        if (src_g) {        // null: validation only
+            src_g[q] = s + a;
+            dst_g[q] = s + c;
+        }
     }
     if (err) atomicOr(flags, kErrInput);
 }
@@ -742,11 +746,15 @@ void launch_fill(int *p, int v, int64_t n, hipStream_t s) {
     k_fill<<<grid_for(n, 256, 4096), 256, 0, s>>>(p, v, n);
 }
 
-void launch_prepare(velo_ctx *c, const velo_hits *h, hipStream_t s) {
+void launch_prepare_raw(const velo_hits *h, int max_event_hits, int *plane_off, int *hit_event, unsigned *flags,
+                        hipStream_t s) {
     if (h->n_events <= 0) return;
     k_prepare<<<h->n_events, 256, 0, s>>>(h->n_events, h->n_hits, h->event_offsets, h->x, h->y, h->z,
-                                          h->plane, c->cfg.max_event_hits, c->ws.plane_off,
-                                          c->ws.hit_event, c->ws.flags);
+                                          h->plane, max_event_hits, plane_off, hit_event, flags);
+}
+
+void launch_prepare(velo_ctx *c, const velo_hits *h, hipStream_t s) {
+    launch_prepare_raw(h, c->cfg.max_event_hits, c->ws.plane_off, c->ws.hit_event, c->ws.flags, s);
 }
 
 void launch_scan_with(const int *in, int *out, int64_t n, int *tmp, hipStream_t s) {
@@ -800,13 +808,18 @@ void launch_compact(velo_ctx *c, const velo_hits *h, velo_outputs *g, hipStream_
                                                                   w.row_ptr, eoff, w.flags);
 }
 
+void launch_globalise_raw(const velo_hits *h, const velo_outputs *g, int64_t cap, int *src_g, int *dst_g,
+                          int *n_internal, unsigned *flags, hipStream_t s) {
+    k_check_capacity<<<1, 1, 0, s>>>(g->n_edges, cap, n_internal, nullptr, flags);
+    const dim3 grid(h->n_events > 0 ? h->n_events : 1, h->n_events > 0 ? 16 : 1);
+    k_globalise<<<grid, 256, 0, s>>>(h->n_events, h->event_offsets, g->edge_offsets, n_internal, cap, g->edge_src,
+                                     g->edge_dst, h->plane, src_g, dst_g, flags);
+}
+
 void launch_globalise(velo_ctx *c, const velo_hits *h, const velo_outputs *g, hipStream_t s) {
     Workspace &w = c->ws;
     const int64_t cap = g->edge_capacity < c->cfg.max_edges ? g->edge_capacity : c->cfg.max_edges;
-    k_check_capacity<<<1, 1, 0, s>>>(g->n_edges, cap, w.n_edges, nullptr, w.flags);
-    const dim3 grid(h->n_events > 0 ? h->n_events : 1, h->n_events > 0 ? 16 : 1);
-    k_globalise<<<grid, 256, 0, s>>>(h->n_events, h->event_offsets, g->edge_offsets, w.n_edges, cap, g->edge_src,
-                                     g->edge_dst, h->plane, w.src_g, w.dst_g, w.flags);
+    launch_globalise_raw(h, g, cap, w.src_g, w.dst_g, w.n_edges, w.flags, s);
 }
 
 void launch_row_ptr(velo_ctx *c, const velo_hits *h, const velo_outputs *g, hipStream_t s) {

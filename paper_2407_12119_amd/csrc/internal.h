@@ -144,6 +144,9 @@ namespace velo {
 
 // ---- launchers (graph.hip) ----
 void launch_prepare(velo_ctx *c, const velo_hits *h, hipStream_t s);
+// the same with explicit working memory: plane_off [n_events x 27], hit_event [n_hits], flags [1]
+void launch_prepare_raw(const velo_hits *h, int max_event_hits, int *plane_off, int *hit_event, unsigned *flags,
+                        hipStream_t s);
 void launch_knn(velo_ctx *c, const velo_hits *h, const float *emb, hipStream_t s);
 void launch_knn_loop(velo_ctx *c, const velo_hits *h, const float *emb, hipStream_t s);
 void launch_knn_into(velo_ctx *c, const velo_hits *h, const float *emb, int kmax, float d2max, int *nbr, int *deg,
@@ -154,6 +157,10 @@ void launch_scan_with(const int *in, int *out, int64_t n, int *tmp, hipStream_t 
 int64_t scan_tmp_ints(int64_t n);
 void launch_compact(velo_ctx *c, const velo_hits *h, velo_outputs *g, hipStream_t s);
 void launch_globalise(velo_ctx *c, const velo_hits *h, const velo_outputs *g, hipStream_t s);
+// the same with explicit working memory; src_g/dst_g may be null (validation and the clamped
+// edge count n_internal only)
+void launch_globalise_raw(const velo_hits *h, const velo_outputs *g, int64_t cap, int *src_g, int *dst_g,
+                          int *n_internal, unsigned *flags, hipStream_t s);
 // row_ptr of a given graph (edges grouped by source, checked by launch_globalise)
 void launch_row_ptr(velo_ctx *c, const velo_hits *h, const velo_outputs *g, hipStream_t s);
 void launch_fill(int *p, int v, int64_t n, hipStream_t s);
@@ -208,6 +215,8 @@ void launch_triplets(velo_ctx *c, const velo_hits *h, const velo_outputs *g, con
 
 // ---- launchers (wcc.hip) ----
 void launch_components(velo_ctx *c, const velo_hits *h, const velo_outputs *g, hipStream_t s);
+void launch_components_raw(const velo_hits *h, const velo_outputs *g, int64_t cap, float thr, int max_event_hits,
+                           size_t lds_max, const int *n_internal, unsigned *flags, hipStream_t s);
 
 // Records events around the launches of one stage while timing is enabled.
 struct StageTimer {

@@ -10,6 +10,8 @@
 // a smaller index, so each root is its component's minimum and the labels do
 // not depend on the order in which edges are processed.  (The paper's plane
 // sweep is replaced because it is not exact on every graph.)
+#include <mutex>
+
 #include "internal.h"
 
 namespace velo {
@@ -177,19 +179,110 @@ void launch_components_sweep(velo_ctx *c, const velo_hits *h, const velo_outputs
                                                c->ws.flags);
 }
 
-void launch_components(velo_ctx *c, const velo_hits *h, const velo_outputs *g, hipStream_t s) {
+void launch_components_raw(const velo_hits *h, const velo_outputs *g, int64_t cap, float thr, int max_event_hits,
+                           size_t lds_max, const int *n_internal, unsigned *flags, hipStream_t s) {
     if (h->n_events <= 0) return;
-    const int64_t cap = g->edge_capacity < c->cfg.max_edges ? g->edge_capacity : c->cfg.max_edges;
-    const size_t lds = sizeof(int) * (size_t)(c->cfg.max_event_hits > 0 ? c->cfg.max_event_hits : 1);
+    const size_t lds = sizeof(int) * (size_t)(max_event_hits > 0 ? max_event_hits : 1);
     static bool attr = false;
     if (!attr) {
-        hipFuncSetAttribute(reinterpret_cast<const void *>(&k_wcc), hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)c->lds_max);
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_wcc), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)lds_max);
         attr = true;
     }
-    k_wcc<<<h->n_events, 1024, lds, s>>>(h->n_events, h->event_offsets, g->edge_offsets, c->ws.n_edges, cap,
-                                         g->edge_src, g->edge_dst, g->edge_logit, c->cfg.edge_logit_min,
-                                         g->labels, c->cfg.max_event_hits, c->ws.flags);
+    k_wcc<<<h->n_events, 1024, lds, s>>>(h->n_events, h->event_offsets, g->edge_offsets, n_internal, cap,
+                                         g->edge_src, g->edge_dst, g->edge_logit, thr, g->labels, max_event_hits,
+                                         flags);
+}
+
+void launch_components(velo_ctx *c, const velo_hits *h, const velo_outputs *g, hipStream_t s) {
+    const int64_t cap = g->edge_capacity < c->cfg.max_edges ? g->edge_capacity : c->cfg.max_edges;
+    launch_components_raw(h, g, cap, c->cfg.edge_logit_min, c->cfg.max_event_hits, c->lds_max, c->ws.n_edges,
+                          c->ws.flags, s);
 }
 
 }  // namespace velo
+
+// ------------------------------------------------------------------------
+// velo_components_noalloc: the components stage without a context, for
+// callers that cannot allocate device memory.  Its working memory (the
+// error word, the clamped edge count, and the validation kernel's plane
+// offsets and hit-to-event map) is the fixed array `scratch` below: every
+// GPU the library runs on holds its own copy for the life of the process,
+// and every call on that GPU shares it.
+// ------------------------------------------------------------------------
+namespace {
+
+constexpr int64_t kNaHead = 64;                                  // [0] error bits, [1] clamped edge count
+constexpr int64_t kNaPlaneOff = kNaHead;                         // [VELO_NOALLOC_MAX_EVENTS x 27]
+constexpr int64_t kNaHitEvent = kNaPlaneOff + (int64_t)VELO_NOALLOC_MAX_EVENTS * velo::kPlaneSlots;
+constexpr int64_t kNaInts = kNaHitEvent + (int64_t)VELO_NOALLOC_MAX_HITS;   // [VELO_NOALLOC_MAX_HITS]
+
+}  // namespace
+
+// Host code must not pass this name to a kernel: it is a host-side stand-in.
+// Kernels get the device address that hipGetSymbolAddress returns.
+static __device__ __align__(256) int scratch[kNaInts];
+
+namespace {
+
+constexpr int kNaMaxDevices = 64;
+std::mutex na_mu;
+int *na_ptr[kNaMaxDevices] = {};
+size_t na_lds[kNaMaxDevices] = {};
+
+// The device address of `scratch` on device `dev` (the current device),
+// looked up once per device.
+int *noalloc_scratch(int dev, size_t *lds_max) {
+    std::lock_guard<std::mutex> lock(na_mu);
+    if (dev < 0 || dev >= kNaMaxDevices) return nullptr;
+    if (!na_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+        int lds = 0;
+        if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return nullptr;
+        na_lds[dev] = (size_t)lds;
+        na_ptr[dev] = static_cast<int *>(p);
+    }
+    *lds_max = na_lds[dev];
+    return na_ptr[dev];
+}
+
+}  // namespace
+
+extern "C" velo_status velo_components_noalloc(const velo_hits *h, const velo_outputs *g, float edge_logit_min,
+                                               int32_t max_event_hits, void *stream) {
+    using namespace velo;
+    if (!h || !g) return VELO_ERR_INVALID_ARG;
+    if (h->n_events < 0 || h->n_hits < 0 || max_event_hits < 0 || g->edge_capacity < 0)
+        return VELO_ERR_INVALID_ARG;
+    if (h->n_events == 0 && h->n_hits != 0) return VELO_ERR_INVALID_ARG;
+    if (h->n_events > 0 && (!h->event_offsets || !g->edge_offsets)) return VELO_ERR_INVALID_ARG;
+    if (h->n_hits > 0 && (!h->x || !h->y || !h->z || !h->plane || !g->labels)) return VELO_ERR_INVALID_ARG;
+    if (!g->n_edges) return VELO_ERR_INVALID_ARG;
+    if (g->edge_capacity > 0 && (!g->edge_src || !g->edge_dst || !g->edge_logit)) return VELO_ERR_INVALID_ARG;
+    if (g->edge_capacity >= (int64_t)1 << 31) return VELO_ERR_UNSUPPORTED;
+    // the sizes the fixed working memory holds
+    if (h->n_events > VELO_NOALLOC_MAX_EVENTS || h->n_hits > VELO_NOALLOC_MAX_HITS) return VELO_ERR_CAPACITY;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return VELO_ERR_DEVICE;
+    size_t lds_max = 0;
+    int *scr = noalloc_scratch(dev, &lds_max);
+    if (!scr) return VELO_ERR_DEVICE;
+    // one event's hits are one workgroup's LDS parent array
+    if ((size_t)max_event_hits * sizeof(int) > lds_max) return VELO_ERR_CAPACITY;
+    hipStream_t s = (hipStream_t)stream;
+    unsigned *flags = reinterpret_cast<unsigned *>(scr);
+    int *n_internal = scr + 1;
+    launch_fill(scr, 0, 2, s);       // the previous call's error bits and count
+    launch_prepare_raw(h, max_event_hits, scr + kNaPlaneOff, scr + kNaHitEvent, flags, s);
+    launch_globalise_raw(h, g, g->edge_capacity, nullptr, nullptr, n_internal, flags, s);
+    launch_components_raw(h, g, g->edge_capacity, edge_logit_min, max_event_hits, lds_max, n_internal, flags, s);
+    if (hipGetLastError() != hipSuccess) return VELO_ERR_DEVICE;
+    unsigned f = 0;
+    if (hipMemcpyAsync(&f, flags, sizeof f, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return VELO_ERR_DEVICE;
+    if (f & kErrInput) return VELO_ERR_INPUT;
+    if (f & kErrCapacity) return VELO_ERR_CAPACITY;
+    return VELO_OK;
+}

@@ -29,7 +29,7 @@ EXPORTS = ("velo_param_count", "velo_create", "velo_destroy", "velo_set_params",
            "velo_graph_capture", "velo_graph_launch", "velo_graph_destroy", "velo_calibrate",
            "velo_autotune", "velo_embed_train_grad", "velo_focal", "velo_components_sweep",
            "velo_build_graph_loop", "velo_set_embed_int8", "velo_calibrate_embed_int8",
-           "velo_triplet_param_count", "velo_set_triplet_params", "velo_triplets")
+           "velo_triplet_param_count", "velo_set_triplet_params", "velo_triplets", "velo_components_noalloc")
 STAGES = ("prepare", "embed", "knn", "compact", "lists", "node_enc", "edge_enc", "messages",
           "node_net", "edge_net", "edge_cls", "components", "bce", "bwd_mlp", "bwd_dw", "bwd_graph", "adam",
           "hit_proj", "emb_loss", "emb_bwd", "triplets")
@@ -127,6 +127,8 @@ def lib() -> C.CDLL:
         L.velo_embed_train_grad.restype = st
         L.velo_focal.argtypes = [vp, vp, vp, C.c_float, C.c_float, C.c_int64, vp, vp, vp]
         L.velo_focal.restype = st
+        L.velo_components_noalloc.argtypes = [C.POINTER(_Hits), C.POINTER(_Outputs), C.c_float, C.c_int32, vp]
+        L.velo_components_noalloc.restype = st
         L.velo_components_sweep.argtypes = [vp, C.POINTER(_Hits), C.POINTER(_Outputs), vp]
         L.velo_components_sweep.restype = st
         L.velo_build_graph_loop.argtypes = [vp, C.POINTER(_Hits), vp, C.POINTER(_Outputs), vp]
@@ -511,6 +513,18 @@ class Graph:
             self.close()
         except Exception:
             pass
+
+
+def components_noalloc(hits: DeviceHits, graph, edge_logit_min: float, max_event_hits: int) -> None:
+    """velo_components_noalloc: components into graph["labels"] with no context
+    and no device allocation (waits for the current stream; raises VeloError
+    on a refused or invalid input)."""
+    oc = Context._out_c(graph)
+    hc = hits.c()
+    st = lib().velo_components_noalloc(C.byref(hc), C.byref(oc), float(edge_logit_min), int(max_event_hits),
+                                       _stream())
+    if st != VELO_OK:
+        raise VeloError(st, f"velo_components_noalloc: {lib().velo_status_str(st).decode()}")
 
 
 def triplet_param_count(hidden: int) -> int:
