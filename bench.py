@@ -10,7 +10,7 @@ the float64 CPU oracle timed on a bounded sample of the same workload, and
 the plain per-event float32 path (one call per event).
 
 usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload batch256]
-                       [--precision fp32|bf16|fp8] [--variants bf16,fp8] [--graph] [--latency]
+                       [--precision fp32|bf16|bf16x2|fp8] [--variants bf16,bf16x2,fp8] [--graph] [--latency]
        the 1000-event workload: --workload batch1000_h128 --precision bf16 --variants fp8
                                 --graph --latency --no-cpu-baseline
 """
@@ -25,10 +25,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "events/sec, batched VELO GNN pipeline at 1 MI355X (FP32 vs BF16/FP8)"
-PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2516.6, "fp8": 5033.2}   # dense MFMA, MI355X
+PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2516.6, "fp8": 5033.2, "bf16x2": 2516.6}   # dense MFMA, MI355X
 PEAK_HBM_GBS = 8000.0
-STATE_BYTES = {"fp32": 4, "bf16": 2, "fp8": 2}
-DTYPE = {"fp32": "f32", "bf16": "bf16", "fp8": "fp8"}
+STATE_BYTES = {"fp32": 4, "bf16": 2, "fp8": 2, "bf16x2": 2}
+DTYPE = {"fp32": "f32", "bf16": "bf16", "fp8": "fp8", "bf16x2": "bf16x2"}
 
 
 def log(msg):
@@ -663,8 +663,11 @@ def run_batched(velo, synth, torch, wl, batch, hits, blob, prec, steps, warmup, 
                                                                         tr["d2h_ms"])), 1)
     res["transfer"] = tr
     if tuned is not None:
-        res["autotune"] = {k: v for k, v in tuned.items() if k in ("knn", "edge_enc", "messages", "node_net",
-                                                                   "edge_net", "edge_cls")}
+        shape = {"knn": ("mem_per_cu", "knn_run", "xcd"), "messages": ("mem_per_cu", "xcd")}
+        res["autotune"] = {k: {"candidate": v, **{f: velo.AUTOTUNE_CANDIDATES[v][f]
+                                                 for f in shape.get(k, ("mlp_per_cu", "mlp_block", "xcd"))}}
+                           for k, v in tuned.items() if k in ("knn", "edge_enc", "messages", "node_net",
+                                                              "edge_net", "edge_cls")}
     log(f"{prec}: {res['ms_per_step']:.3f} ms/step, {res['value']:.1f} events/s")
     if graph or latency:
         # the whole path captured once into a HIP graph and replayed; per-batch
@@ -704,8 +707,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="batch256")
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp8"])
-    ap.add_argument("--variants", default="bf16,fp8",
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "bf16x2", "fp8"])
+    ap.add_argument("--variants", default="bf16,bf16x2,fp8",
                     help="comma list of extra precisions timed in the same run ('' for none)")
     ap.add_argument("--cpu-sample-events", type=int, default=32)
     ap.add_argument("--cpu-single-events", type=int, default=4,
@@ -784,7 +787,7 @@ def main():
     quality = None
     if not args.no_quality and args.workload == "batch256":
         quality = run_quality(velo, synth, torch,
-                              ["fp32"] + [p for p in ("bf16", "fp8") if p in [args.precision] + list(variants)])
+                              ["fp32"] + [p for p in ("bf16", "bf16x2", "fp8") if p in [args.precision] + list(variants)])
 
     per_event = None
     if not args.no_per_event and wl.hidden <= 64:

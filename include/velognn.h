@@ -59,8 +59,13 @@ typedef enum {
 typedef enum {
     VELO_FP32 = 0,   /* MLP operands and state in float32 */
     VELO_BF16 = 1,   /* MLP operands bfloat16, float32 accumulation */
-    VELO_FP8 = 2     /* MLP operands OCP FP8 E4M3 with static per-tensor scales,
+    VELO_FP8 = 2,    /* MLP operands OCP FP8 E4M3 with static per-tensor scales,
                         float32 accumulation; encodings stored bf16 */
+    VELO_BF16X2 = 3  /* bf16 MLP weights; activations that are not stored encodings
+                        (hidden layers, message sums, the classifier's input)
+                        enter as two bf16 operands v = hi + lo, lo = bf16(v - hi),
+                        two bf16 MFMA products; float32 accumulation; encodings
+                        stored bf16 */
 } velo_precision;
 
 /* Network and capacity configuration, fixed for the life of a context. */
@@ -434,21 +439,42 @@ velo_status velo_embed_train_grad(velo_ctx *ctx, const velo_hits *hits, const ve
                                   float w_genuine, float *dparams, float *loss, int64_t *counts, float *emb,
                                   void *stream);
 
-/* Choose launch parameters by measurement: runs velo_infer on (hits, out)
- * under a fixed list of candidate configurations (blocks per compute unit and
- * interleaved or XCD-blocked work mapping), times every stage with HIP
- * events and keeps, per stage, the fastest candidate for later calls on this
- * context.  choice_host (optional, VELO_N_STAGES entries) receives the
- * candidate index picked per stage.  Synchronises the stream. */
+/* Choose launch parameters and tile shapes by measurement: runs velo_infer
+ * on (hits, out) under each of eight candidate configurations, times every
+ * stage with HIP events and keeps, per stage, the fastest candidate for later
+ * calls on this context.  Candidate k sets, for every tunable stage at once:
+ *   k                          0    1    2    3    4    5    6    7
+ *   MLP blocks per CU (0: by occupancy)
+ *                              0    0    1    2    0    1    0    2
+ *   MLP workgroup (threads)  512  512  512  512  256  256  256  256
+ *   k-NN / message blocks per CU
+ *                             16   16    4    8   32   32    8   16
+ *   k-NN query hits per wavefront task
+ *                             16   16    8   32    8   32   32    8
+ *   XCD-blocked work mapping   0    1    1    1    1    0    0    1
+ * The tunable stages are the neighbour search, the edge encoder, the
+ * messages, the node and edge networks and the classifier-fused edge network.
+ * choice_host (optional, VELO_N_STAGES entries) receives the candidate index
+ * picked per stage (0 for stages that are not tuned).  Synchronises the
+ * stream. */
 velo_status velo_autotune(velo_ctx *ctx, const velo_hits *hits, velo_outputs *out, void *stream,
                           int32_t *choice_host);
+
+/* Apply given candidates of velo_autotune's table without measuring: choice_host
+ * holds VELO_N_STAGES candidate indices (0..7; entries of stages that are not
+ * tuned are ignored), for example a previous velo_autotune's output; NULL
+ * restores the built-in launch parameters (candidate 0).  Launch parameters
+ * and tile shapes change only which wavefront processes which work unit:
+ * results are bitwise those of candidate 0. */
+velo_status velo_set_tuning(velo_ctx *ctx, const int32_t *choice_host);
 
 /* Synchronise `stream` and return (and clear) the error latched on the
  * device by earlier calls: VELO_OK, VELO_ERR_INPUT or VELO_ERR_CAPACITY. */
 velo_status velo_check(velo_ctx *ctx, void *stream);
 
-/* Static description of a status code. */
-const char *velo_status_str(velo_status s);
+/* Static description of a status code: a velo_status value; any other
+ * value gives "unknown status". */
+const char *velo_status_str(int status);
 
 /* Detail of the last host-side error of the context ("" if none). */
 const char *velo_last_error(const velo_ctx *ctx);

@@ -17,7 +17,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
-_SO = os.path.join(_HERE, "liboracle.so")
+# ORACLE_LIB: another build of oracle.c to load (the sanitizer test builds one)
+_SO = os.environ.get("ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 _lib: Optional[C.CDLL] = None
 
 

@@ -106,6 +106,27 @@ struct DeviceGuard {
     }
 };
 
+// velo_autotune's candidate configurations (listed in include/velognn.h):
+// candidate k sets every tunable stage's launch parameters at once.
+namespace tune {
+constexpr int kCand = 8;
+constexpr int mlp_cu[kCand] = {0, 0, 1, 2, 0, 1, 0, 2};        // MLP blocks per CU (0: by occupancy)
+constexpr int mlp_block[kCand] = {512, 512, 512, 512, 256, 256, 256, 256};
+constexpr int mem_cu[kCand] = {16, 16, 4, 8, 32, 32, 8, 16};   // k-NN and message blocks per CU
+constexpr int knn_run[kCand] = {16, 16, 8, 32, 8, 32, 32, 8};  // query hits per k-NN wavefront task
+constexpr int xcd[kCand] = {0, 1, 1, 1, 1, 0, 0, 1};
+constexpr int tunable[] = {VELO_STAGE_KNN, VELO_STAGE_EDGE_ENC, VELO_STAGE_MESSAGES, VELO_STAGE_NODE_NET,
+                           VELO_STAGE_EDGE_NET, VELO_STAGE_EDGE_CLS};
+
+void apply(velo_ctx *c, int stage, int k) {
+    const bool mem = stage == VELO_STAGE_KNN || stage == VELO_STAGE_MESSAGES;
+    c->tune_per_cu[stage] = mem ? mem_cu[k] : mlp_cu[k];
+    c->tune_xcd[stage] = xcd[k];
+    c->tune_mlp_block[stage] = mem ? 0 : mlp_block[k];
+    if (stage == VELO_STAGE_KNN) c->tune_knn_run = knn_run[k];
+}
+}  // namespace tune
+
 }  // namespace
 
 extern "C" {
@@ -116,7 +137,7 @@ int64_t velo_param_count(int32_t gnn_hidden, int32_t gnn_iters) {
     return L.total;
 }
 
-const char *velo_status_str(velo_status s) {
+const char *velo_status_str(int s) {
     switch (s) {
         case VELO_OK: return "ok";
         case VELO_ERR_INVALID_ARG: return "invalid argument";
@@ -726,17 +747,22 @@ velo_status velo_adam_step(velo_ctx *c, float *params, const float *grad, float 
     return device_status(c, "velo_adam_step");
 }
 
+velo_status velo_set_tuning(velo_ctx *c, const int32_t *choice) {
+    if (!c) return VELO_ERR_INVALID_ARG;
+    using namespace tune;
+    if (choice)
+        for (int t : tunable)
+            if (choice[t] < 0 || choice[t] >= kCand) return fail(c, VELO_ERR_INVALID_ARG, "tuning candidate out of range");
+    for (int t : tunable) apply(c, t, choice ? choice[t] : 0);
+    return VELO_OK;
+}
+
 velo_status velo_autotune(velo_ctx *c, const velo_hits *h, velo_outputs *o, void *stream, int32_t *choice) {
     if (!c) return VELO_ERR_INVALID_ARG;
     // candidate launch parameters, applied to every tunable stage at once;
     // stages are timed separately, so each picks its own best candidate.
     // per_cu 0 = the stage's default (occupancy for MFMA kernels).
-    static const int kCand = 6;
-    static const int mlp_cu[kCand] = {0, 0, 1, 2, 0, 1};
-    static const int mem_cu[kCand] = {16, 16, 4, 8, 32, 32};
-    static const int xcd[kCand] = {0, 1, 1, 1, 1, 0};
-    static const int tunable[] = {VELO_STAGE_KNN, VELO_STAGE_EDGE_ENC, VELO_STAGE_MESSAGES, VELO_STAGE_NODE_NET,
-                                  VELO_STAGE_EDGE_NET, VELO_STAGE_EDGE_CLS};
+    using namespace tune;
     const bool was_timing = c->timing;
     velo_status st = velo_set_timing(c, 1);
     if (st) return st;
@@ -746,11 +772,7 @@ velo_status velo_autotune(velo_ctx *c, const velo_hits *h, velo_outputs *o, void
     double ms[VELO_N_STAGES];
     int64_t n[VELO_N_STAGES];
     for (int cand = 0; cand < kCand; cand++) {
-        for (int t : tunable) {
-            const bool mem = t == VELO_STAGE_KNN || t == VELO_STAGE_MESSAGES;
-            c->tune_per_cu[t] = mem ? mem_cu[cand] : mlp_cu[cand];
-            c->tune_xcd[t] = xcd[cand];
-        }
+        for (int t : tunable) apply(c, t, cand);
         // one untimed call, then two timed ones
         if ((st = velo_infer(c, h, o, stream))) break;
         if ((st = velo_read_timing(c, ms, n))) break;
@@ -762,11 +784,7 @@ velo_status velo_autotune(velo_ctx *c, const velo_hits *h, velo_outputs *o, void
                 pick[t] = cand;
             }
     }
-    for (int t : tunable) {
-        const bool mem = t == VELO_STAGE_KNN || t == VELO_STAGE_MESSAGES;
-        c->tune_per_cu[t] = mem ? mem_cu[pick[t]] : mlp_cu[pick[t]];
-        c->tune_xcd[t] = xcd[pick[t]];
-    }
+    for (int t : tunable) apply(c, t, pick[t]);
     if (choice)
         for (int k = 0; k < VELO_N_STAGES; k++) choice[k] = pick[k];
     velo_set_timing(c, was_timing ? 1 : 0);

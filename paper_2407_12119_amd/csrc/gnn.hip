@@ -292,6 +292,20 @@ __device__ inline float row_sum16(float v) {
     return dpp_add<0xB1>(v);   // quad_perm [1,0,3,2]
 }
 
+// The first layer of an MLP: every input segment but the node network's two
+// message sums is a stored encoding (bf16 already in 2-byte precisions, so a
+// split operand's lo part is 0 there).
+template <class P, int MO, int KB, int NSEG, int MODE>
+__device__ inline void gemm_first(const typename P::wfrag_t *sW1, const typename P::frag_t *X, f32x4 *acc,
+                                  int lane) {
+    if constexpr (MODE == NODE) {
+        gemm<P, MO, NSEG * KB, 0, KB, true>(sW1, X, acc, lane);
+        gemm<P, MO, NSEG * KB, KB, NSEG * KB, false>(sW1, X, acc, lane);
+    } else {
+        gemm<P, MO, NSEG * KB, 0, NSEG * KB, true>(sW1, X, acc, lane);
+    }
+}
+
 template <class P, int H>
 // sCB: the classifier's hidden bias divided by its fp8 descale factor, then
 // its output weights (2H floats in LDS); b_out: its output bias
@@ -507,7 +521,7 @@ __global__ __launch_bounds__(512) void k_mlp(MlpArgs A) {
                     hid[mo] += G[MO + mo];
                 }
             }
-            if constexpr (NSEG > 0) gemm<P, MO, NSEG * KB>(sW1, X, hid, lane);
+            if constexpr (NSEG > 0) gemm_first<P, MO, KB, NSEG, MODE>(sW1, X, hid, lane);
             if (P::kScaled) rescale<MO>(hid, SC.d1);
             relu<MO>(hid);
             if (A.amax) record_amax(absmax4<MO>(hid), A.amax + 1);
@@ -634,7 +648,7 @@ __global__ __launch_bounds__(512) void k_mlp(MlpArgs A) {
                     hid[mo] += G[MO + mo];
                 }
             }
-            if constexpr (NSEG > 0) gemm<P, MO, NSEG * KB>(sW1, X, hid, lane);
+            if constexpr (NSEG > 0) gemm_first<P, MO, KB, NSEG, MODE>(sW1, X, hid, lane);
             if (P::kScaled) rescale<MO>(hid, SC.d1);
             relu<MO>(hid);
             if (A.amax) record_amax(absmax4<MO>(hid), A.amax + 1);
@@ -756,9 +770,15 @@ inline int blocks_per_cu(const void *kernel, int block, size_t lds) {
 template <class P, int H, int MODE, bool CLS>
 void run_mlp(velo_ctx *c, int stage, MlpArgs a, hipStream_t s) {
     constexpr size_t lds = mlp_lds<P, H, MODE, CLS>();
-    static const int occ = blocks_per_cu(reinterpret_cast<const void *>(&k_mlp<P, H, MODE, CLS>), kMlpBlock, lds);
+    // workgroup shape: 8 wavefronts sharing one staged copy of the weights,
+    // or 4 (twice the copies, finer-grained residency); chosen by velo_autotune
+    const void *kernel = reinterpret_cast<const void *>(&k_mlp<P, H, MODE, CLS>);
+    static const int occ8 = blocks_per_cu(kernel, kMlpBlock, lds), occ4 = blocks_per_cu(kernel, kMlpBlock / 2, lds);
+    const bool four = c->tune_mlp_block[stage] == kMlpBlock / 2;
+    const int occ = four ? occ4 : occ8;
     a.xcd = c->tune_xcd[stage];
-    k_mlp<P, H, MODE, CLS><<<persistent_grid(c, stage_per_cu(c, stage, occ, occ)), kMlpBlock, lds, s>>>(a);
+    k_mlp<P, H, MODE, CLS><<<persistent_grid(c, stage_per_cu(c, stage, occ, occ)), four ? kMlpBlock / 2 : kMlpBlock,
+                             lds, s>>>(a);
 }
 
 // float32 MLPs are MFMA-bound: their edge MLPs take the hit segments'
@@ -972,6 +992,7 @@ size_t state_bytes(int precision) { return precision == VELO_FP32 ? sizeof(float
 bool gnn_supported(int hidden, int precision) {
     if (precision == VELO_FP32) return hidden == 32 || hidden == 64;
     if (precision == VELO_BF16 || precision == VELO_FP8) return hidden == 32 || hidden == 64 || hidden == 128;
+    if (precision == VELO_BF16X2) return hidden == 32 || hidden == 64 || hidden == 128;
     return false;
 }
 
@@ -993,7 +1014,7 @@ void launch_embed(velo_ctx *c, const velo_hits *h, float *emb, bool calib, hipSt
     const int p = c->cfg.precision;
     if (c->emb_int8 && !calib)
         embed_p<I8>(c, h, emb, c->ws.i8_scales, nullptr, s);
-    else if (p == VELO_FP32)
+    else if (p == VELO_FP32 || p == VELO_BF16X2)   // bf16x2: bf16 weights would move pairs across the radius
         embed_p<F32>(c, h, emb, nullptr, nullptr, s);
     else if (p == VELO_BF16 || calib)
         embed_p<BF16>(c, h, emb, nullptr, calib ? c->ws.amax + 2 * kSlotEmbed : nullptr, s);
@@ -1012,6 +1033,10 @@ void launch_gnn(velo_ctx *c, const velo_hits *h, float *logit, const float *para
     if (p == VELO_FP32) {
         if (H == 32) gnn_ph<F32, 32>(c, h, logit, params, train, false, s);
         if (H == 64) gnn_ph<F32, 64>(c, h, logit, params, train, false, s);
+    } else if (p == VELO_BF16X2) {
+        if (H == 32) gnn_ph<BF16X2, 32>(c, h, logit, params, train, false, s);
+        if (H == 64) gnn_ph<BF16X2, 64>(c, h, logit, params, train, false, s);
+        if (H == 128) gnn_ph<BF16X2, 128>(c, h, logit, params, train, false, s);
     } else if (p == VELO_BF16 || calib) {
         if (H == 32) gnn_ph<BF16, 32>(c, h, logit, params, train, calib, s);
         if (H == 64) gnn_ph<BF16, 64>(c, h, logit, params, train, calib, s);

@@ -92,7 +92,10 @@ __device__ inline unsigned cand_key(const f32x4 *__restrict__ emb, int64_t base,
     return s < d2max ? __float_as_uint(s) : kInvalidKey;
 }
 
-constexpr int kKnnRun = 16;   // consecutive query hits per wavefront task
+// A wavefront task is a run of RUN consecutive query hits (8, 16 or 32;
+// velo_autotune picks one): longer runs reuse the candidate embeddings held
+// in registers over more queries, shorter ones balance uneven planes better.
+constexpr int kKnnRunDefault = 16;
 constexpr int kKnnBlock = 256;
 constexpr int kHistBins = 256;   // key histogram of one query: four bins per lane
 
@@ -139,6 +142,7 @@ __device__ inline void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
+template <int RUN>
 __global__ __launch_bounds__(kKnnBlock) void k_knn(int64_t n_hits, const int *__restrict__ off,
                                              const int *__restrict__ plane_off,
                                              const int *__restrict__ hit_event,
@@ -155,7 +159,7 @@ __global__ __launch_bounds__(kKnnBlock) void k_knn(int64_t n_hits, const int *__
     const_as<int> *off4 = (const_as<int> *)off;
     const_as<int> *plane_off4 = (const_as<int> *)plane_off;
     const_as<f32x4> *emb4 = (const_as<f32x4> *)emb;
-    const int64_t n_runs = (n_hits + kKnnRun - 1) / kKnnRun;
+    const int64_t n_runs = (n_hits + RUN - 1) / RUN;
     const WaveRange wv = wave_range(n_runs, xcd != 0);
     const WaveRange wr{uniform64(wv.first), uniform64(wv.step), uniform64(wv.end)};
     for (int64_t r = wr.first; r < wr.end; r += wr.step) {
@@ -166,8 +170,8 @@ __global__ __launch_bounds__(kKnnBlock) void k_knn(int64_t n_hits, const int *__
         int c0 = 0, C = 0, nch = 0;
         int64_t base = 0;
         f32x4 cand[kKeyChunks];
-        const int64_t i_end = min(r * kKnnRun + kKnnRun, n_hits);
-        for (int64_t i = r * kKnnRun; i < i_end; i++) {
+        const int64_t i_end = min(r * RUN + RUN, n_hits);
+        for (int64_t i = r * RUN; i < i_end; i++) {
             const int b = hit_event4[i], p = plane4[i];
             if (b != cb || p != cp) {
                 cb = b;
@@ -774,9 +778,16 @@ void launch_knn_into(velo_ctx *c, const velo_hits *h, const float *emb, int kmax
                      hipStream_t s) {
     if (h->n_hits <= 0) return;
     const int blocks = persistent_grid(c, stage_per_cu(c, VELO_STAGE_KNN, 16));
-    k_knn<<<blocks, kKnnBlock, 0, s>>>(h->n_hits, h->event_offsets, c->ws.plane_off, c->ws.hit_event,
-                                       h->plane, (const f32x4 *)emb, d2max, kmax, nbr, deg,
-                                       c->tune_xcd[VELO_STAGE_KNN], c->ws.flags);
+    auto go = [&](auto kernel) {
+        kernel<<<blocks, kKnnBlock, 0, s>>>(h->n_hits, h->event_offsets, c->ws.plane_off, c->ws.hit_event, h->plane,
+                                            (const f32x4 *)emb, d2max, kmax, nbr, deg, c->tune_xcd[VELO_STAGE_KNN],
+                                            c->ws.flags);
+    };
+    switch (c->tune_knn_run > 0 ? c->tune_knn_run : kKnnRunDefault) {
+        case 8: go(k_knn<8>); break;
+        case 32: go(k_knn<32>); break;
+        default: go(k_knn<16>); break;
+    }
 }
 
 void launch_knn_loop(velo_ctx *c, const velo_hits *h, const float *emb, hipStream_t s) {

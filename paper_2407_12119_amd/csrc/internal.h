@@ -131,6 +131,8 @@ struct velo_ctx {
     // launch parameters per stage, chosen by velo_autotune (0 = built-in default)
     int tune_per_cu[VELO_N_STAGES] = {};
     int tune_xcd[VELO_N_STAGES] = {};   // 1: XCD-blocked work mapping
+    int tune_knn_run = 0;                // neighbour search: query hits per wavefront task (0 = 16)
+    int tune_mlp_block[VELO_N_STAGES] = {};   // MLP stages: threads per workgroup (0 = 512)
     // per-stage timing
     bool timing = false;
     std::vector<StageEvents> ev_pool;     // created on first enable

@@ -22,6 +22,7 @@ __device__ inline f32x4 zero4() { return f32x4{0.f, 0.f, 0.f, 0.f}; }
 // ------------------------------------------------------------------------
 struct F32 {
     static constexpr bool kScaled = false;
+    static constexpr bool kSplit = false;
     using state_t = float;       // hit/edge encodings in HBM
     using frag_t = f32x4;        // per-lane B operand of one K block
     using wfrag_t = f32x4;       // per-lane A operand of one (output block, K block)
@@ -66,6 +67,7 @@ struct F32 {
 
 struct BF16 {
     static constexpr bool kScaled = false;
+    static constexpr bool kSplit = false;
     using state_t = bf16;
     using frag_t = bf16x8;
     using wfrag_t = bf16x8;
@@ -118,12 +120,78 @@ struct BF16 {
     }
 };
 
+// BF16X2: bf16 weights; an activation that is not already a bf16 value
+// (hidden layers, message sums, the final edge state entering the
+// classifier) enters as two bf16 operands, v = hi + lo with hi = bf16(v) and
+// lo = bf16(v - hi) (v - hi is exact in float32), and two MFMA products per
+// block, W lo + W hi, so products keep the weight's bf16 rounding but not the
+// activation's (about 2^-16 of it remains).  Operands read from stored
+// encodings are bf16 already: gemm<..., true> gives them the single product
+// W hi (their lo is 0).  Same fragment layout, weight fragments and stored
+// (bf16, permuted) encodings as BF16.
+struct bf16x8x2 {
+    bf16x8 hi, lo;
+};
+struct BF16X2 {
+    static constexpr bool kScaled = false;
+    static constexpr bool kSplit = true;
+    using state_t = bf16;
+    using frag_t = bf16x8x2;
+    using wfrag_t = bf16x8;
+    static constexpr int KBLK = 32;
+    static constexpr int WJ = 8;
+    __device__ static int col(int kb, int g, int j) { return BF16::col(kb, g, j); }
+    __device__ static bf16x4 rest(f32x4 v, bf16x4 h) {
+        return bf16x4{(bf16)(v[0] - (float)h[0]), (bf16)(v[1] - (float)h[1]), (bf16)(v[2] - (float)h[2]),
+                      (bf16)(v[3] - (float)h[3])};
+    }
+    __device__ static frag_t split(f32x4 a, f32x4 b) {
+        const bf16x4 ha = BF16::cvt(a), hb = BF16::cvt(b);
+        return frag_t{BF16::cat(ha, hb), BF16::cat(rest(a, ha), rest(b, hb))};
+    }
+    __device__ static frag_t load(const bf16 *row, int kb, int g, float = 1.f) {
+        return frag_t{BF16::load(row, kb, g), bf16x8{}};
+    }
+    __device__ static frag_t load_f32(const float *row, int kb, int g, float = 1.f) {
+        return split(*(const f32x4 *)(row + 32 * kb + 8 * g), *(const f32x4 *)(row + 32 * kb + 8 * g + 4));
+    }
+    template <int MO>
+    __device__ static void chain(const f32x4 *h, frag_t *x, float = 1.f) {
+#pragma unroll
+        for (int kb = 0; kb < MO / 2; kb++) x[kb] = split(h[2 * kb], h[2 * kb + 1]);
+    }
+    template <int MO>
+    __device__ static void mma(const wfrag_t *a, const frag_t &x, f32x4 *acc) {
+#pragma unroll
+        for (int mo = 0; mo < MO; mo++) {
+            acc[mo] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mo], x.lo, acc[mo], 0, 0, 0);
+            acc[mo] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mo], x.hi, acc[mo], 0, 0, 0);
+        }
+    }
+    // operands whose lo is 0 (read from stored encodings)
+    template <int MO>
+    __device__ static void mma_hi(const wfrag_t *a, const frag_t &x, f32x4 *acc) {
+#pragma unroll
+        for (int mo = 0; mo < MO; mo++) acc[mo] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mo], x.hi, acc[mo], 0, 0, 0);
+    }
+    __device__ static float seg0(const frag_t *x, int mo, int i) {
+        const int j = 4 * (mo & 1) + i;
+        return (float)x[mo >> 1].hi[j] + (float)x[mo >> 1].lo[j];
+    }
+    __device__ static int stored(int mo, int g) { return BF16::stored(mo, g); }
+    template <int MO>
+    __device__ static void store_all(bf16 *row, int g, const f32x4 *o) { BF16::store_all<MO>(row, g, o); }
+    __device__ static f32x4 load4(const bf16 *p) { return BF16::load4(p); }
+    __device__ static float absmax(const frag_t &f) { return BF16::absmax(f.hi); }
+};
+
 // FP8: OCP E4M3 matrix operands (v_mfma_f32_16x16x32_fp8_fp8, same fragment
 // layout as bf16) with static per-tensor scales: an operand v is fed as
 // e4m3(v / s) and every product is descaled by s_x * s_w after the MFMAs.
 // Encodings stay stored in the permuted bf16 layout.
 struct FP8 {
     static constexpr bool kScaled = true;
+    static constexpr bool kSplit = false;
     using state_t = bf16;
     using frag_t = long;         // 8 e4m3 values
     using wfrag_t = long;
@@ -177,6 +245,7 @@ struct FP8 {
 typedef int i32x4 __attribute__((ext_vector_type(4)));
 struct I8 {
     static constexpr bool kScaled = true;
+    static constexpr bool kSplit = false;
     using state_t = float;
     using frag_t = i32x4;        // 16 int8 codes
     using wfrag_t = i32x4;
@@ -246,6 +315,10 @@ __device__ inline bf16x8 pack_weights<BF16>(const float *w, float) {
     return bf16x8{(bf16)w[0], (bf16)w[1], (bf16)w[2], (bf16)w[3], (bf16)w[4], (bf16)w[5], (bf16)w[6], (bf16)w[7]};
 }
 template <>
+__device__ inline bf16x8 pack_weights<BF16X2>(const float *w, float inv) {
+    return pack_weights<BF16>(w, inv);
+}
+template <>
 __device__ inline long pack_weights<FP8>(const float *w, float inv) {
     return FP8::pack8(f32x4{w[0], w[1], w[2], w[3]}, f32x4{w[4], w[5], w[6], w[7]}, inv);
 }
@@ -261,17 +334,22 @@ constexpr size_t frag_bytes(int rows_pad, int K) {
     return (size_t)rows_pad * K * sizeof(typename P::wfrag_t) / P::WJ;
 }
 
-// acc[mo] += W[16 mo .., K] * X   (KB = K / KBLK blocks)
-template <class P, int MO, int KB>
+// acc[mo] += W[16 mo .., K] * X   (KB = K / KBLK blocks; K blocks
+// [KB0, KB1) of it).  STATE: the operands were read from stored encodings
+// (for split traits their lo part is 0 and is not multiplied).
+template <class P, int MO, int KB, int KB0 = 0, int KB1 = KB, bool STATE = false>
 __device__ inline void gemm(const typename P::wfrag_t *sW, const typename P::frag_t *X, f32x4 *acc, int lane) {
 #pragma unroll
-    for (int kb = 0; kb < KB; kb++) {
+    for (int kb = KB0; kb < KB1; kb++) {
         // keep one K block of weight fragments live at a time
         __builtin_amdgcn_sched_barrier(0);
         typename P::wfrag_t a[MO];
 #pragma unroll
         for (int mo = 0; mo < MO; mo++) a[mo] = sW[(mo * KB + kb) * 64 + lane];
-        P::template mma<MO>(a, X[kb], acc);
+        if constexpr (STATE && P::kSplit)
+            P::template mma_hi<MO>(a, X[kb], acc);
+        else
+            P::template mma<MO>(a, X[kb], acc);
     }
 }
 

@@ -177,7 +177,7 @@ __global__ __launch_bounds__(512) void k_tri_cls(const int *__restrict__ n_dev, 
         }
         f32x4 hid[MO];
         load_bias<MO>(sB, hid, g);
-        gemm<P, MO, 2 * KB>(sW1, X, hid, lane);
+        gemm<P, MO, 2 * KB, 0, 2 * KB, true>(sW1, X, hid, lane);   // both inputs are stored encodings
         f32x4 w2[MO];
         load_bias<MO>(sB + H, w2, g);
         float part = 0.f;
@@ -429,6 +429,9 @@ void launch_triplets(velo_ctx *c, const velo_hits *h, const velo_outputs *g, con
     if (c->cfg.precision == VELO_FP32) {
         tri_cls<F32>(c, T.n_int, T.art_g, P_art, t->art_logit, s);
         tri_cls<F32>(c, T.n_int + 1, T.elb_g, P_elb, t->elb_logit, s);
+    } else if (c->cfg.precision == VELO_BF16X2) {
+        tri_cls<BF16X2>(c, T.n_int, T.art_g, P_art, t->art_logit, s);
+        tri_cls<BF16X2>(c, T.n_int + 1, T.elb_g, P_elb, t->elb_logit, s);
     } else {
         tri_cls<BF16>(c, T.n_int, T.art_g, P_art, t->art_logit, s);
         tri_cls<BF16>(c, T.n_int + 1, T.elb_g, P_elb, t->elb_logit, s);

@@ -14,12 +14,13 @@ from typing import Dict, Optional
 import numpy as np
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libvelognn.so")
+# VELO_LIB: another build of the library to load (the host-sanitizer test builds one)
+LIB_PATH = os.environ.get("VELO_LIB") or os.path.join(_PKG, "libvelognn.so")
 
 VELO_OK, VELO_ERR_INVALID_ARG, VELO_ERR_CAPACITY, VELO_ERR_OOM = 0, 1, 2, 3
 VELO_ERR_DEVICE, VELO_ERR_UNSUPPORTED, VELO_ERR_INPUT, VELO_ERR_NOT_CALIBRATED = 4, 5, 6, 7
-VELO_FP32, VELO_BF16, VELO_FP8 = 0, 1, 2
-PRECISIONS = {"fp32": VELO_FP32, "bf16": VELO_BF16, "fp8": VELO_FP8}
+VELO_FP32, VELO_BF16, VELO_FP8, VELO_BF16X2 = 0, 1, 2, 3
+PRECISIONS = {"fp32": VELO_FP32, "bf16": VELO_BF16, "fp8": VELO_FP8, "bf16x2": VELO_BF16X2}
 N_PLANES, EMB_HIDDEN, EMB_DIM = 26, 128, 4
 
 EXPORTS = ("velo_param_count", "velo_create", "velo_destroy", "velo_set_params", "velo_infer",
@@ -29,7 +30,14 @@ EXPORTS = ("velo_param_count", "velo_create", "velo_destroy", "velo_set_params",
            "velo_graph_capture", "velo_graph_launch", "velo_graph_destroy", "velo_calibrate",
            "velo_autotune", "velo_embed_train_grad", "velo_focal", "velo_components_sweep",
            "velo_build_graph_loop", "velo_set_embed_int8", "velo_calibrate_embed_int8",
-           "velo_triplet_param_count", "velo_set_triplet_params", "velo_triplets", "velo_components_noalloc")
+           "velo_triplet_param_count", "velo_set_triplet_params", "velo_triplets", "velo_components_noalloc", "velo_set_tuning")
+# velo_autotune's candidate configurations (the table of include/velognn.h):
+# MLP blocks per CU (0: by occupancy), MLP workgroup threads, k-NN / message
+# blocks per CU, k-NN query hits per wavefront task, XCD-blocked mapping
+AUTOTUNE_CANDIDATES = [
+    {"mlp_per_cu": m, "mlp_block": b, "mem_per_cu": q, "knn_run": r, "xcd": x}
+    for m, b, q, r, x in zip((0, 0, 1, 2, 0, 1, 0, 2), (512, 512, 512, 512, 256, 256, 256, 256),
+                             (16, 16, 4, 8, 32, 32, 8, 16), (16, 16, 8, 32, 8, 32, 32, 8), (0, 1, 1, 1, 1, 0, 0, 1))]
 STAGES = ("prepare", "embed", "knn", "compact", "lists", "node_enc", "edge_enc", "messages",
           "node_net", "edge_net", "edge_cls", "components", "bce", "bwd_mlp", "bwd_dw", "bwd_graph", "adam",
           "hit_proj", "emb_loss", "emb_bwd", "triplets")
@@ -122,6 +130,8 @@ def lib() -> C.CDLL:
         L.velo_calibrate.restype = st
         L.velo_autotune.argtypes = [vp, C.POINTER(_Hits), C.POINTER(_Outputs), vp, vp]
         L.velo_autotune.restype = st
+        L.velo_set_tuning.argtypes = [vp, vp]
+        L.velo_set_tuning.restype = st
         L.velo_embed_train_grad.argtypes = [vp, C.POINTER(_Hits), C.POINTER(_EmbedTruth), vp, C.c_int32,
                                             C.c_float, C.c_float, C.c_float, vp, vp, vp, vp, vp]
         L.velo_embed_train_grad.restype = st
@@ -323,6 +333,21 @@ class Context:
         self._raise(self._lib.velo_autotune(self._h, C.byref(hc), C.byref(oc), _stream(), choice.ctypes.data),
                     "velo_autotune")
         return {k: int(choice[i]) for i, k in enumerate(STAGES)}
+
+    def set_tuning(self, choice=None):
+        """Apply velo_autotune candidates: a {stage: index} dict (stages not
+        named keep candidate 0), an int for every tuned stage, or None for
+        the built-in launch parameters."""
+        if choice is None:
+            self._raise(self._lib.velo_set_tuning(self._h, None), "velo_set_tuning")
+            return
+        arr = np.zeros(len(STAGES), np.int32)
+        if isinstance(choice, int):
+            arr[:] = choice
+        else:
+            for k, v in choice.items():
+                arr[STAGES.index(k)] = v
+        self._raise(self._lib.velo_set_tuning(self._h, arr.ctypes.data), "velo_set_tuning")
 
     def check(self):
         self._raise(self._lib.velo_check(self._h, _stream()), "velo_check")

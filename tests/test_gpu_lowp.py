@@ -250,3 +250,49 @@ def test_hidden_width_32_on_a_given_graph(precision):
         la, lr = logit_bound(wl.iters)
         assert np.all(err <= la + lr * np.abs(z)), err.max()
     print(f"  {len(z)} edges, max |dz| {err.max():.3g}", flush=True)
+
+
+@pytest.mark.parametrize("name,events_from", [("batch256", "batch256"), ("batch1000_h128", "single_event")])
+def test_bf16x2_embedding_graph_and_gnn_against_the_oracle(name, events_from):
+    """bf16x2: bf16 weights; activations that are not stored encodings enter
+    as two bf16 operands (hi + lo), two products.  The embedding runs in
+    float32 (within 1e-5 of the oracle) and the rough graph equals the
+    oracle's on the GPU's embedding; the GNN's logits carry the bf16 rounding
+    of the weights and of the stored states but not that of the hidden
+    activations and message sums, so they stay within the bf16 bound and
+    closer to the oracle than bf16's."""
+    wl = synth.WORKLOADS[name]
+    src_wl = synth.WORKLOADS[events_from]
+    batch = synth.make_batch(src_wl, n_events=min(3, src_wl.n_events), first=0 if src_wl.n_events == 1 else 5)
+    blob = synth.centred_params(wl)
+    ctx, hits = _setup(wl, batch, "bf16x2", blob)
+    emb = ctx.embed(hits).cpu().numpy()
+    for b in range(batch.n_events):
+        ev = batch.event(b)
+        o0 = int(batch.event_offsets[b])
+        e_or = oracle.embed(ev.x, ev.y, ev.z, blob)
+        err = np.abs(emb[o0:o0 + ev.n] - e_or).max() / max(np.abs(e_or).max(), 1.0)
+        assert err <= 1e-5
+    r2 = oracle.d2max_f32(wl.radius)
+    cbf, _ = _setup(wl, batch, "bf16", blob)
+    gd = ctx.build_graph(hits, torch.from_numpy(emb).cuda())
+    gb = {k: (v.clone() if hasattr(v, "clone") else v) for k, v in gd.items()}
+    ctx.gnn(hits, gd)
+    cbf.gnn(hits, gb)
+    g3, gbh = velo.graph_to_host(gd, batch.n_hits), velo.graph_to_host(gb, batch.n_hits)
+    la, lr = logit_bound(wl.iters)
+    for b in range(batch.n_events):
+        ev = batch.event(b)
+        o0 = int(batch.event_offsets[b])
+        rp, col = oracle.neighbours(ev.plane, emb[o0:o0 + ev.n], r2, wl.k_max)
+        src, dst = oracle.csr_to_edges(rp, col)
+        s, e = int(g3["edge_offsets"][b]), int(g3["edge_offsets"][b + 1])
+        np.testing.assert_array_equal(g3["src"][s:e], src)
+        np.testing.assert_array_equal(g3["dst"][s:e], dst)
+        z = oracle.gnn_forward(ev.x, ev.y, ev.z, src, dst, blob, wl.hidden, wl.iters)
+        e2 = np.abs(g3["logit"][s:e] - z)
+        eb = np.abs(gbh["logit"][s:e] - z)
+        print(f"  event {b}: {len(z)} edges, bf16x2 max |dz| {e2.max():.3g} mean {e2.mean():.3g}; "
+              f"bf16 max {eb.max():.3g} mean {eb.mean():.3g}", flush=True)
+        assert np.all(e2 <= la + lr * np.abs(z))
+        assert e2.mean() < eb.mean()

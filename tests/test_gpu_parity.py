@@ -430,9 +430,10 @@ def test_captured_graph_replays_match_eager_calls():
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16"])
 def test_autotuned_launches_give_identical_results(precision):
-    """Launch parameters (blocks per CU, XCD-blocked work mapping) change only
-    which wave processes which unit: outputs are bitwise those of the default
-    launches."""
+    """Launch parameters and tile shapes (blocks per CU, MLP workgroup size,
+    k-NN query run length, XCD-blocked work mapping) change only which wave
+    processes which unit: outputs are bitwise those of the default launches,
+    for every candidate of the autotuner's table and for its pick."""
     wl = synth.WORKLOADS["batch256"]
     batch = synth.make_batch(wl, n_events=24, first=40)
     print(f"\n[case] autotune {precision} events={batch.n_events} hits={batch.n_hits}", flush=True)
@@ -442,12 +443,20 @@ def test_autotuned_launches_give_identical_results(precision):
     ctx.set_params(torch.from_numpy(synth.centred_params(wl)).cuda())
     hits = velo.DeviceHits.from_batch(batch)
     ref = velo.graph_to_host(ctx.infer(hits), batch.n_hits)
+    for cand in range(len(velo.AUTOTUNE_CANDIDATES)):
+        ctx.set_tuning(cand)
+        got = velo.graph_to_host(ctx.infer(hits), batch.n_hits)
+        for k in ("edge_offsets", "src", "dst", "logit", "labels"):
+            np.testing.assert_array_equal(got[k], ref[k], err_msg=f"candidate {cand}: {k}")
+    ctx.set_tuning(None)
     out = ctx.alloc_outputs(hits)
     choice = ctx.autotune(hits, out)
     print(f"  choice {choice}", flush=True)
     got = velo.graph_to_host(ctx.infer(hits), batch.n_hits)
     for k in ("edge_offsets", "src", "dst", "logit", "labels"):
         np.testing.assert_array_equal(got[k], ref[k], err_msg=k)
+    with pytest.raises(velo.VeloError):
+        ctx.set_tuning(len(velo.AUTOTUNE_CANDIDATES))
 
 
 def test_plane_sweep_variant_matches_oracle_sweep():
