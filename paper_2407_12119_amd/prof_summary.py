@@ -2,6 +2,12 @@
 
     python -m paper_2407_12119_amd.prof_summary trace STATS_CSV [--top N]
         markdown table of the kernel-trace statistics (rocprofv3 --stats)
+    python -m paper_2407_12119_amd.prof_summary mfma COUNTER_CSV [--stats STATS_CSV] [--top N]
+        per-kernel matrix-core use from one --pmc run of the derived counters
+        MfmaUtil (percent of cycles the MFMA units are busy, over all SIMDs)
+        and MfmaFlopsBF16 / MfmaFlopsF32 / MfmaFlopsF16 (flops issued to the
+        matrix cores); with the kernel-trace statistics of the same command,
+        the MFMA rate those flops reach over the kernel's average duration
     python -m paper_2407_12119_amd.prof_summary traffic FETCH_CSV WRITE_CSV --workload W
                                                 [--json profiles/edge_net_traffic.json] [--git-rev REV]
         per-kernel HBM bytes per dispatch from two --pmc runs (FETCH_SIZE, then
@@ -29,7 +35,7 @@ KERNEL_SOURCES = ["paper_2407_12119_amd/csrc/gnn.hip", "paper_2407_12119_amd/csr
 # the non-final edge network of each precision's inference path (k_mlp<P, H,
 # mode, classifier>: mode 1 = concatenated first layer, 4 = factorised)
 EDGE_NET = {"fp32": "k_mlp<F32, {H}, 4, false>", "bf16": "k_mlp<BF16, {H}, 1, false>",
-            "fp8": "k_mlp<FP8, {H}, 1, false>"}
+            "bf16x2": "k_mlp<BF16X2, {H}, 1, false>", "fp8": "k_mlp<FP8, {H}, 1, false>"}
 PROBE = "CUDAFunctorOnSelf_add"
 
 
@@ -116,12 +122,39 @@ def traffic(fetch_csv, write_csv, workload, hidden, json_path=None, rev=None) ->
     return "\n".join(out)
 
 
+def mfma(counter_csv: str, stats_csv=None, top: int = 16) -> str:
+    vals = collections.defaultdict(lambda: collections.defaultdict(list))
+    for r in csv.DictReader(open(counter_csv)):
+        vals[short(r["Kernel_Name"])][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    avg_ms = {}
+    if stats_csv:
+        for r in csv.DictReader(open(stats_csv)):
+            avg_ms[short(r["Name"])] = float(r["AverageNs"]) / 1e6
+    util = lambda k: sum(vals[k].get("MfmaUtil", [0.0])) / max(len(vals[k].get("MfmaUtil", [])), 1)
+    flops = lambda k, c: sum(vals[k].get(c, [0.0])) / max(len(vals[k].get(c, [])), 1)
+    keys = [k for k in vals if any(flops(k, c) > 0 for c in ("MfmaFlopsBF16", "MfmaFlopsF32", "MfmaFlopsF16"))]
+    keys.sort(key=lambda k: -sum(flops(k, c) for c in ("MfmaFlopsBF16", "MfmaFlopsF32", "MfmaFlopsF16")) *
+              len(vals[k].get("MfmaUtil", [1])))
+    out = ["| kernel | dispatches | MFMA busy | bf16 GFLOP / dispatch | fp32 GFLOP / dispatch | "
+           "MFMA TFLOP/s over the average duration |", "|---|---|---|---|---|---|"]
+    for k in keys[:top]:
+        fb, ff = flops(k, "MfmaFlopsBF16") + flops(k, "MfmaFlopsF16"), flops(k, "MfmaFlopsF32")
+        rate = f"{(fb + ff) / (avg_ms[k] * 1e-3) / 1e12:.1f}" if k in avg_ms and avg_ms[k] > 0 else "—"
+        out.append(f"| `{k}` | {len(vals[k].get('MfmaUtil', []))} | {util(k):.1f}% | {fb / 1e9:.2f} | "
+                   f"{ff / 1e9:.2f} | {rate} |")
+    return "\n".join(out)
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
     t = sub.add_parser("trace")
     t.add_argument("stats_csv")
     t.add_argument("--top", type=int, default=20)
+    m = sub.add_parser("mfma")
+    m.add_argument("counter_csv")
+    m.add_argument("--stats")
+    m.add_argument("--top", type=int, default=16)
     c = sub.add_parser("traffic")
     c.add_argument("fetch_csv")
     c.add_argument("write_csv")
@@ -132,6 +165,8 @@ def main():
     a = ap.parse_args()
     if a.cmd == "trace":
         print(trace(a.stats_csv, a.top))
+    elif a.cmd == "mfma":
+        print(mfma(a.counter_csv, a.stats, a.top))
     else:
         print(traffic(a.fetch_csv, a.write_csv, a.workload, a.hidden, a.json, a.git_rev))
 

@@ -1,0 +1,50 @@
+"""bench.py's host-side contract, without a GPU: more than one GPU is
+refused with a message, and the algorithmic work it prices the edge network
+and the stages with follows the counts it documents."""
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr or "--gpus 1" in r.stderr
+    assert r.stdout == ""
+
+
+def test_edge_network_work_counts():
+    H, E, N = 64, 1000, 100
+    # 2-byte states: two layers 3H -> H -> H on every edge; edge state read and
+    # written, two indices, every hit state read once, outgoing sums written
+    f, b = bench.edge_net_work(H, "bf16", E, N)
+    assert f == 2 * (3 * H * H + H * H) * E
+    assert b == (2 * H * 2 + 8) * E + H * 2 * N + 4 * H * N
+    assert bench.edge_net_work(H, "bf16x2", E, N) == (f, b)
+    # float32, factorised: the e segment and the second layer per edge
+    f, b = bench.edge_net_work(H, "fp32", E, N)
+    assert f == 2 * (H * H + H * H) * E
+    assert b == (2 * H * 4 + 8) * E + 2 * H * 4 * N
+
+
+def test_stage_roofline_is_max_of_compute_and_bytes():
+    H, n, N, E = 64, 4, 1000, 30000
+    stages = {k: (1.0, 1) for k in ("embed", "prepare", "knn", "compact", "lists", "node_enc", "edge_enc",
+                                     "hit_proj", "messages", "node_net", "edge_net", "edge_cls", "components")}
+    r = bench.stage_roofline(stages, 1, H, n, "bf16", N, E)
+    g = r["graph"]
+    assert g["flops"] == 0 and g["bytes"] == 24 * N + 16 * E
+    assert abs(g["t_roof_ms"] - g["bytes"] / (bench.PEAK_HBM_GBS * 1e9) * 1e3) < 1e-4
+    mp = r["message_passing"]
+    assert mp["flops"] == n * 8 * H * H * (N + E) + 2 * (H * H + H) * E
+    assert abs(r["total"]["t_ms"] - sum(v["t_ms"] for k, v in r.items() if k != "total")) < 1e-3
+    for k, v in r.items():
+        if k != "total":
+            roof = max(v["flops"] / (bench.PEAK_TFLOPS["bf16"] * 1e12), v["bytes"] / (bench.PEAK_HBM_GBS * 1e9))
+            assert abs(v["t_roof_ms"] - roof * 1e3) < 1e-4
