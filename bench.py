@@ -404,6 +404,24 @@ def run_quality(velo, synth, torch, precisions):
                 "d_efficiency_pts": round(100 * (ms["efficiency"] - res[precisions[0]]["efficiency"]), 4)}
         ctx.close()
         res[prec] = r
+    # the INT8 embedding (Sec. 7.4, Table 5: INT8 adds a few percent of edges),
+    # calibrated on 16 other events, with the rest of the path in float32
+    cal = synth.calibration_batch(wl, 16)
+    ctx = velo.Context(wl.hidden, wl.iters, r2, wl.k_max, wl.edge_logit_min, "fp32",
+                       max_hits=max(batch.n_hits, cal.n_hits), max_events=max(batch.n_events, cal.n_events),
+                       max_event_hits=max(batch.max_event_hits(), cal.max_event_hits()))
+    ctx.set_params(torch.from_numpy(blob).cuda())
+    ctx.calibrate_embed_int8(velo.DeviceHits.from_batch(cal))
+    g = velo.graph_to_host(ctx.infer(hits), batch.n_hits)
+    ctx.close()
+    m = metrics.track_metrics(g["labels"], batch.pid, batch.event_offsets)
+    a = metrics.edge_agreement(ref["edge_offsets"], ref["src"], ref["dst"], ref["logit"] >= wl.edge_logit_min,
+                               g["edge_offsets"], g["src"], g["dst"], g["logit"] >= wl.edge_logit_min)
+    res["int8_embedding"] = {"edges": g["n_edges"], "extra_edges_frac": round(g["n_edges"] / ref["n_edges"] - 1.0, 5),
+                             "jaccard": round(a["jaccard"], 6), "decision_agreement": round(a["decision_agreement"], 6),
+                             "efficiency": round(m["efficiency"], 5),
+                             "d_efficiency_pts": round(100 * (m["efficiency"] - res[precisions[0]]["efficiency"]), 4),
+                             "what": "INT8 embedding (calibrated on 16 other events), float32 GNN, against fp32"}
     res["weights"] = "trained by the float64 oracle (embedding 300 steps, GNN 300 steps; see trained_h64_n4.json)"
     res["workload"] = f"{wl.name}: the {batch.n_events} benchmark events, d2 < 0.9, k_max = {wl.k_max}"
     log(f"quality: {json.dumps(res)}")
@@ -777,6 +795,8 @@ def main():
     multi = None
     if args.streams > 0 and args.workload == "batch256":
         multi = run_multistream(synth, torch, wl, blob, "bf16", args.streams, args.stream_events)
+        # the form that meets the precision targets on trained weights
+        multi["bf16x2"] = run_multistream(synth, torch, wl, blob, "bf16x2", args.streams, args.stream_events)
     training = None
     embed_training = None
     if not args.no_train and args.workload == "batch256":

@@ -560,7 +560,10 @@ __global__ __launch_bounds__(512) void k_mlp(MlpArgs A) {
             }
         };
         constexpr int NG = AB ? 2 * MO : 1;
-        if constexpr (sizeof(S) == 4) {   // MFMA-bound: no prefetch, fewer registers
+        // float32 edge networks are MFMA-bound: no prefetch, fewer registers.
+        // The factorised edge encoder (one matrix layer) prefetches like the
+        // 2-byte precisions: its gathers of the per-hit products dominate.
+        if constexpr (sizeof(S) == 4 && MODE != ENC_AB) {
             typename P::frag_t X[NX];
             raw_t R[RAW ? KB : 1];
             f32x4 G[NG];
