@@ -446,14 +446,17 @@ velo_status velo_embed_train_grad(velo_ctx *ctx, const velo_hits *hits, const ve
  *   k                          0    1    2    3    4    5    6    7
  *   MLP blocks per CU (0: by occupancy)
  *                              0    0    1    2    0    1    0    2
- *   MLP workgroup (threads)  512  512  512  512  256  256  256  256
+ *   MLP workgroup (threads)  512  512  512  512  256  256 1024 1024
  *   k-NN / message blocks per CU
  *                             16   16    4    8   32   32    8   16
  *   k-NN query hits per wavefront task
  *                             16   16    8   32    8   32   32    8
  *   XCD-blocked work mapping   0    1    1    1    1    0    0    1
- * The tunable stages are the neighbour search, the edge encoder, the
- * messages, the node and edge networks and the classifier-fused edge network.
+ * A 1024-thread workgroup applies to the H = 128 edge encoder and edge
+ * networks with 2-byte states (16 wavefronts share the LDS weights, one
+ * 16-edge chunk each); elsewhere it means 512.  The tunable stages are the
+ * neighbour search, the edge encoder, the messages, the node and edge
+ * networks and the classifier-fused edge network.
  * choice_host (optional, VELO_N_STAGES entries) receives the candidate index
  * picked per stage (0 for stages that are not tuned).  Synchronises the
  * stream. */

@@ -111,7 +111,7 @@ struct DeviceGuard {
 namespace tune {
 constexpr int kCand = 8;
 constexpr int mlp_cu[kCand] = {0, 0, 1, 2, 0, 1, 0, 2};        // MLP blocks per CU (0: by occupancy)
-constexpr int mlp_block[kCand] = {512, 512, 512, 512, 256, 256, 256, 256};
+constexpr int mlp_block[kCand] = {512, 512, 512, 512, 256, 256, 1024, 1024};   // 1024: H = 128 only
 constexpr int mem_cu[kCand] = {16, 16, 4, 8, 32, 32, 8, 16};   // k-NN and message blocks per CU
 constexpr int knn_run[kCand] = {16, 16, 8, 32, 8, 32, 32, 8};  // query hits per k-NN wavefront task
 constexpr int xcd[kCand] = {0, 1, 1, 1, 1, 0, 0, 1};

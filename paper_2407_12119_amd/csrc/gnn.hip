@@ -270,11 +270,20 @@ constexpr size_t mlp_w_bytes() {
     return MODE == CLS_ONLY ? 0 : (nseg<MODE>() ? frag_bytes<P>(H, nseg<MODE>() * H) : 0) + frag_bytes<P>(H, H);
 }
 
+// WIDE: workgroups of 16 wavefronts (H = 128 source-walking edge MLPs):
+// twice the wavefronts share one LDS copy of the weights, each holding one
+// chunk at a time and half a K block of weight fragments, so that a lane
+// needs at most 128 VGPRs and a SIMD runs four wavefronts instead of two.
 template <class P, int H, int MODE, bool CLS>
+constexpr bool wide_ok() {
+    return H == 128 && sizeof(typename P::state_t) == 2 && src_aligned<P, MODE, CLS>();
+}
+
+template <class P, int H, int MODE, bool CLS, bool WIDE = false>
 constexpr size_t mlp_lds() {
     return mlp_w_bytes<P, H, MODE>() + (MODE == CLS_ONLY ? 0 : sizeof(float) * 2 * H) +
            (CLS ? frag_bytes<P>(H, H) + sizeof(float) * 2 * H : 0) +
-           (src_aligned<P, MODE, CLS>() ? sizeof(float) * H * (kMlpBlock / 64) : 0);
+           (src_aligned<P, MODE, CLS>() ? sizeof(float) * H * ((WIDE ? 2 : 1) * kMlpBlock / 64) : 0);
 }
 
 // Sum over the 16 lanes of each DPP row (every lane gets the row's sum):
@@ -295,14 +304,14 @@ __device__ inline float row_sum16(float v) {
 // The first layer of an MLP: every input segment but the node network's two
 // message sums is a stored encoding (bf16 already in 2-byte precisions, so a
 // split operand's lo part is 0 there).
-template <class P, int MO, int KB, int NSEG, int MODE>
+template <class P, int MO, int KB, int NSEG, int MODE, int AG = MO>
 __device__ inline void gemm_first(const typename P::wfrag_t *sW1, const typename P::frag_t *X, f32x4 *acc,
                                   int lane) {
     if constexpr (MODE == NODE) {
-        gemm<P, MO, NSEG * KB, 0, KB, true>(sW1, X, acc, lane);
-        gemm<P, MO, NSEG * KB, KB, NSEG * KB, false>(sW1, X, acc, lane);
+        gemm<P, MO, NSEG * KB, 0, KB, true, AG>(sW1, X, acc, lane);
+        gemm<P, MO, NSEG * KB, KB, NSEG * KB, false, AG>(sW1, X, acc, lane);
     } else {
-        gemm<P, MO, NSEG * KB, 0, NSEG * KB, true>(sW1, X, acc, lane);
+        gemm<P, MO, NSEG * KB, 0, NSEG * KB, true, AG>(sW1, X, acc, lane);
     }
 }
 
@@ -333,8 +342,8 @@ __device__ inline void classify(const typename P::wfrag_t *sC1, const float *sCB
     if (g == 0 && ok) logit[q] = part + b_out;
 }
 
-template <class P, int H, int MODE, bool CLS>
-__global__ __launch_bounds__(512) void k_mlp(MlpArgs A) {
+template <class P, int H, int MODE, bool CLS, bool WIDE = false>
+__global__ __launch_bounds__(WIDE ? 1024 : 512) void k_mlp(MlpArgs A) {
     using S = typename P::state_t;
     using W = typename P::wfrag_t;
     constexpr int MO = H / 16, KB = H / P::KBLK, NSEG = nseg<MODE>();
@@ -521,14 +530,15 @@ __global__ __launch_bounds__(512) void k_mlp(MlpArgs A) {
                     hid[mo] += G[MO + mo];
                 }
             }
-            if constexpr (NSEG > 0) gemm_first<P, MO, KB, NSEG, MODE>(sW1, X, hid, lane);
+            constexpr int AG = WIDE ? MO / 2 : MO;   // weight fragments held at a time
+            if constexpr (NSEG > 0) gemm_first<P, MO, KB, NSEG, MODE, AG>(sW1, X, hid, lane);
             if (P::kScaled) rescale<MO>(hid, SC.d1);
             relu<MO>(hid);
             if (A.amax) record_amax(absmax4<MO>(hid), A.amax + 1);
             typename P::frag_t xh[KB];
             P::template chain<MO>(hid, xh, SC.ix2);
             load_bias<MO>(sB + H, o, g);
-            gemm<P, MO, KB>(sW2, xh, o, lane);
+            gemm<P, MO, KB, 0, KB, false, AG>(sW2, xh, o, lane);
             if (P::kScaled) rescale<MO>(o, SC.d2);
             if constexpr (edge_update<MODE>()) {   // residual (Sec. 5.2), from the unquantised state
 #pragma unroll
@@ -560,6 +570,17 @@ __global__ __launch_bounds__(512) void k_mlp(MlpArgs A) {
             }
         };
         constexpr int NG = AB ? 2 * MO : 1;
+        if constexpr (WIDE) {   // one chunk at a time: occupancy hides the loads
+            static_assert(wide_ok<P, H, MODE, CLS>(), "WIDE is for the H = 128 2-byte edge MLPs");
+            typename P::frag_t X[NX];
+            raw_t R[RAW ? KB : 1];
+            f32x4 G[NG];
+            for (Chunk c = from_hit(wr.first); c.i < wr.end; c = next(c)) {
+                load_chunk(c, X, R, G);
+                process(c, X, R, G);
+            }
+            return;
+        }
         // float32 edge networks are MFMA-bound: no prefetch, fewer registers.
         // The factorised edge encoder (one matrix layer) prefetches like the
         // 2-byte precisions: its gathers of the per-hit products dominate.
@@ -592,8 +613,13 @@ __global__ __launch_bounds__(512) void k_mlp(MlpArgs A) {
         }
         return;
     }
-    // memory-bound precisions prefetch the next unit's inputs during the MFMAs
-    constexpr bool PREFETCH = sizeof(S) < 4 && MLP;
+    // memory-bound precisions prefetch the next unit's inputs during the MFMAs,
+    // except split operands at H = 128: one unit's inputs alone take about 80
+    // registers there (the prefetch spilled and ran slower), and the weight
+    // fragments are held half a K block at a time
+    constexpr bool LEAN = P::kSplit && H == 128;
+    constexpr bool PREFETCH = sizeof(S) < 4 && MLP && !LEAN;
+    constexpr int AGU = LEAN ? MO / 2 : MO;
     constexpr int NG = AB ? 2 * MO : 1;
     // two units in flight: Xn holds unit u + step, Xm unit u + 2 step
     typename P::frag_t Xn[NX], Xm[NX];
@@ -651,14 +677,14 @@ __global__ __launch_bounds__(512) void k_mlp(MlpArgs A) {
                     hid[mo] += G[MO + mo];
                 }
             }
-            if constexpr (NSEG > 0) gemm_first<P, MO, KB, NSEG, MODE>(sW1, X, hid, lane);
+            if constexpr (NSEG > 0) gemm_first<P, MO, KB, NSEG, MODE, AGU>(sW1, X, hid, lane);
             if (P::kScaled) rescale<MO>(hid, SC.d1);
             relu<MO>(hid);
             if (A.amax) record_amax(absmax4<MO>(hid), A.amax + 1);
             typename P::frag_t xh[KB];
             P::template chain<MO>(hid, xh, SC.ix2);
             load_bias<MO>(sB + H, o, g);
-            gemm<P, MO, KB>(sW2, xh, o, lane);
+            gemm<P, MO, KB, 0, KB, false, AGU>(sW2, xh, o, lane);
             if (P::kScaled) rescale<MO>(o, SC.d2);
 #pragma unroll
             for (int mo = 0; mo < MO; mo++) {
@@ -772,6 +798,17 @@ inline int blocks_per_cu(const void *kernel, int block, size_t lds) {
 
 template <class P, int H, int MODE, bool CLS>
 void run_mlp(velo_ctx *c, int stage, MlpArgs a, hipStream_t s) {
+    if constexpr (wide_ok<P, H, MODE, CLS>()) {
+        if (c->tune_mlp_block[stage] == 2 * kMlpBlock) {
+            constexpr size_t lds = mlp_lds<P, H, MODE, CLS, true>();
+            const void *kernel = reinterpret_cast<const void *>(&k_mlp<P, H, MODE, CLS, true>);
+            static const int occ = blocks_per_cu(kernel, 2 * kMlpBlock, lds);
+            a.xcd = c->tune_xcd[stage];
+            k_mlp<P, H, MODE, CLS, true><<<persistent_grid(c, stage_per_cu(c, stage, occ, occ)), 2 * kMlpBlock,
+                                           lds, s>>>(a);
+            return;
+        }
+    }
     constexpr size_t lds = mlp_lds<P, H, MODE, CLS>();
     // workgroup shape: 8 wavefronts sharing one staged copy of the weights,
     // or 4 (twice the copies, finer-grained residency); chosen by velo_autotune

@@ -336,20 +336,26 @@ constexpr size_t frag_bytes(int rows_pad, int K) {
 
 // acc[mo] += W[16 mo .., K] * X   (KB = K / KBLK blocks; K blocks
 // [KB0, KB1) of it).  STATE: the operands were read from stored encodings
-// (for split traits their lo part is 0 and is not multiplied).
-template <class P, int MO, int KB, int KB0 = 0, int KB1 = KB, bool STATE = false>
+// (for split traits their lo part is 0 and is not multiplied).  AG: weight
+// fragments held at a time (MO: a whole K block; fewer: fewer registers);
+// every accumulator takes the same products in the same order either way.
+template <class P, int MO, int KB, int KB0 = 0, int KB1 = KB, bool STATE = false, int AG = MO>
 __device__ inline void gemm(const typename P::wfrag_t *sW, const typename P::frag_t *X, f32x4 *acc, int lane) {
+    static_assert(MO % AG == 0, "fragment groups divide the output blocks");
 #pragma unroll
     for (int kb = KB0; kb < KB1; kb++) {
-        // keep one K block of weight fragments live at a time
-        __builtin_amdgcn_sched_barrier(0);
-        typename P::wfrag_t a[MO];
 #pragma unroll
-        for (int mo = 0; mo < MO; mo++) a[mo] = sW[(mo * KB + kb) * 64 + lane];
-        if constexpr (STATE && P::kSplit)
-            P::template mma_hi<MO>(a, X[kb], acc);
-        else
-            P::template mma<MO>(a, X[kb], acc);
+        for (int m0 = 0; m0 < MO; m0 += AG) {
+            // keep one group of weight fragments live at a time
+            __builtin_amdgcn_sched_barrier(0);
+            typename P::wfrag_t a[AG];
+#pragma unroll
+            for (int mo = 0; mo < AG; mo++) a[mo] = sW[((m0 + mo) * KB + kb) * 64 + lane];
+            if constexpr (STATE && P::kSplit)
+                P::template mma_hi<AG>(a, X[kb], acc + m0);
+            else
+                P::template mma<AG>(a, X[kb], acc + m0);
+        }
     }
 }
 

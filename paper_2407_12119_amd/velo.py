@@ -36,7 +36,7 @@ EXPORTS = ("velo_param_count", "velo_create", "velo_destroy", "velo_set_params",
 # blocks per CU, k-NN query hits per wavefront task, XCD-blocked mapping
 AUTOTUNE_CANDIDATES = [
     {"mlp_per_cu": m, "mlp_block": b, "mem_per_cu": q, "knn_run": r, "xcd": x}
-    for m, b, q, r, x in zip((0, 0, 1, 2, 0, 1, 0, 2), (512, 512, 512, 512, 256, 256, 256, 256),
+    for m, b, q, r, x in zip((0, 0, 1, 2, 0, 1, 0, 2), (512, 512, 512, 512, 256, 256, 1024, 1024),
                              (16, 16, 4, 8, 32, 32, 8, 16), (16, 16, 8, 32, 8, 32, 32, 8), (0, 1, 1, 1, 1, 0, 0, 1))]
 STAGES = ("prepare", "embed", "knn", "compact", "lists", "node_enc", "edge_enc", "messages",
           "node_net", "edge_net", "edge_cls", "components", "bce", "bwd_mlp", "bwd_dw", "bwd_graph", "adam",

@@ -442,6 +442,8 @@ def test_autotuned_launches_give_identical_results(precision):
                        max_hits=batch.n_hits, max_events=batch.n_events, max_event_hits=batch.max_event_hits())
     ctx.set_params(torch.from_numpy(synth.centred_params(wl)).cuda())
     hits = velo.DeviceHits.from_batch(batch)
+    if precision == "fp8":
+        ctx.calibrate(hits)          # fixed scales for every candidate
     ref = velo.graph_to_host(ctx.infer(hits), batch.n_hits)
     for cand in range(len(velo.AUTOTUNE_CANDIDATES)):
         ctx.set_tuning(cand)
@@ -457,6 +459,30 @@ def test_autotuned_launches_give_identical_results(precision):
         np.testing.assert_array_equal(got[k], ref[k], err_msg=k)
     with pytest.raises(velo.VeloError):
         ctx.set_tuning(len(velo.AUTOTUNE_CANDIDATES))
+
+
+@pytest.mark.parametrize("precision", ["bf16", "bf16x2", "fp8"])
+def test_tile_shapes_at_width_128_give_identical_results(precision):
+    """H = 128: every candidate of the autotuner's table, including the
+    16-wavefront workgroups of the edge MLPs (one chunk per wavefront, half a
+    K block of weight fragments at a time), gives bitwise the default
+    results."""
+    wl = synth.WORKLOADS["batch1000_h128"]
+    batch = synth.make_batch(wl, n_events=5, first=11)
+    print(f"\n[case] tile shapes H=128 {precision} events={batch.n_events} hits={batch.n_hits}", flush=True)
+    ctx = velo.Context(wl.hidden, wl.iters, oracle.d2max_f32(wl.radius), wl.k_max, wl.edge_logit_min, precision,
+                       max_hits=batch.n_hits, max_events=batch.n_events, max_event_hits=batch.max_event_hits())
+    ctx.set_params(torch.from_numpy(synth.centred_params(wl)).cuda())
+    hits = velo.DeviceHits.from_batch(batch)
+    if precision == "fp8":
+        ctx.calibrate(hits)          # fixed scales for every candidate
+    ref = velo.graph_to_host(ctx.infer(hits), batch.n_hits)
+    for cand in range(len(velo.AUTOTUNE_CANDIDATES)):
+        ctx.set_tuning(cand)
+        got = velo.graph_to_host(ctx.infer(hits), batch.n_hits)
+        for k in ("edge_offsets", "src", "dst", "logit", "labels"):
+            np.testing.assert_array_equal(got[k], ref[k], err_msg=f"candidate {cand}: {k}")
+    print(f"  {ref['n_edges']} edges, {len(velo.AUTOTUNE_CANDIDATES)} candidates identical", flush=True)
 
 
 def test_plane_sweep_variant_matches_oracle_sweep():
