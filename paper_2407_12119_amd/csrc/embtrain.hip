@@ -98,32 +98,32 @@ __global__ __launch_bounds__(kPairBlock) void k_emb_pairs(int B, const int *__re
         if (!query[i]) continue;                            // uniform over the wavefront
         const f32x4 q = emb[i];
         const int pq = pid[i];
-        // this lane's share of the query's own sums (genuine 0..3, fake 4..7),
-        // added up over the wavefront before one atomic per entry
-        unsigned long long qs[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        // this lane's share of the query's own sums (genuine qg, fake qf; two
+        // arrays, so that every index is a constant and they stay in
+        // registers), added up over the wavefront before one atomic per entry
+        unsigned long long qg[kD] = {0, 0, 0, 0}, qf[kD] = {0, 0, 0, 0};
         auto same = [&](int64_t j) { return pq >= 0 && pid[j] == pq; };
         // one pair (i, j), handled by the calling lane
+        // (the genuine and fake sums are updated by selected values, not
+        // through a selected pointer, so that they stay in registers)
         auto pair = [&](int64_t j) {
             const f32x4 e = emb[j];
             const float d2 = sqdist(q, e);
             const bool gen = same(j);
-            float sign;
-            if (gen) {
-                ng++;
-                sg += to_fix(d2, kLossFix);
-                sign = 1.f;
-            } else {
-                nf++;
-                if (!(d2 < margin)) return;
-                sf += to_fix(margin - d2, kLossFix);
-                sign = -1.f;
-            }
+            ng += gen;
+            nf += !gen;
+            if (!gen && !(d2 < margin)) return;
+            sg += gen ? to_fix(d2, kLossFix) : 0ull;
+            sf += gen ? 0ull : to_fix(margin - d2, kLossFix);
+            const float sign = gen ? 1.f : -1.f;
             unsigned long long *aj = in_lds ? win + (j - base) * 8 : acc + j * 8;
             aj += gen ? 0 : 4;
 #pragma unroll
             for (int c = 0; c < kD; c++) {
                 const float v = sign * 2.f * (q[c] - e[c]);
-                qs[(gen ? 0 : 4) + c] += to_fix(v, kGradFix);
+                const unsigned long long f = to_fix(v, kGradFix);
+                qg[c] += gen ? f : 0ull;
+                qf[c] += gen ? 0ull : f;
                 atomicAdd(aj + c, to_fix(-v, kGradFix));
             }
         };
@@ -139,12 +139,15 @@ __global__ __launch_bounds__(kPairBlock) void k_emb_pairs(int B, const int *__re
         // the random pair
         if (C > 0 && lane == 0) pair(base + (int64_t)(((unsigned long long)rnd[i] * (unsigned)C) >> 32));
 #pragma unroll
-        for (int c = 0; c < 8; c++)
-            for (int o = 32; o > 0; o >>= 1) qs[c] += (unsigned long long)__shfl_xor((long long)qs[c], o);
+        for (int c = 0; c < kD; c++)
+            for (int o = 32; o > 0; o >>= 1) {
+                qg[c] += (unsigned long long)__shfl_xor((long long)qg[c], o);
+                qf[c] += (unsigned long long)__shfl_xor((long long)qf[c], o);
+            }
         if (lane < 8) {
-            unsigned long long v = qs[0];
+            unsigned long long v = qg[0];
 #pragma unroll
-            for (int c = 1; c < 8; c++) v = lane == c ? qs[c] : v;
+            for (int c = 1; c < 2 * kD; c++) v = lane == c ? (c < kD ? qg[c] : qf[c - kD]) : v;
             if (v) atomicAdd(acc + i * 8 + lane, v);
         }
     }
