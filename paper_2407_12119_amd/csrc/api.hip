@@ -61,7 +61,7 @@ bool dalloc(T **p, int64_t count) {
 void free_ws(Workspace &w) {
     void *ptrs[] = {w.emb, w.hit_event, w.plane_off, w.deg, w.row_ptr, w.nbr, w.src_g, w.dst_g,
                     w.in_ptr, w.in_list, w.scan_tmp, w.h[0], w.h[1],
-                    w.m, w.ab, w.e, w.n_edges, w.flags, w.eoff_tmp, w.ck_h, w.ck_e, w.ck_m, w.ck_ab, w.g_sd, w.g_e[0], w.g_e[1],
+                    w.m, w.ab, w.e, w.n_edges, w.flags, w.grab, w.eoff_tmp, w.ck_h, w.ck_e, w.ck_m, w.ck_ab, w.g_sd, w.g_e[0], w.g_e[1],
                     w.g_h[0], w.g_h[1], w.g_da, w.g_r, w.g_m, w.g_part, w.g_red, w.g_loss,
                     w.scales, w.amax, w.tmp_logit, w.i8_scales, w.i8_amax, w.t_u, w.t_a1, w.t_a2, w.t_dz1, w.t_dz2, w.t_dz3,
                     w.t_nbr, w.t_deg, w.t_acc, w.t_stat, w.t_part};
@@ -194,7 +194,7 @@ velo_status velo_create(const velo_config *cfg, velo_ctx **out) {
               dalloc(&w.in_list, E) && dalloc(&w.scan_tmp, w.scan_tmp_len) &&
               dalloc((char **)&w.h[0], N * H * sb) && dalloc((char **)&w.h[1], N * H * sb) &&
               dalloc(&w.m, N * 2 * H) && dalloc(&w.ab, N * 2 * H) && dalloc((char **)&w.e, E * H * sb) && dalloc(&w.n_edges, 1) &&
-              dalloc(&w.flags, 1) &&
+              dalloc(&w.flags, 1) && dalloc(&w.grab, kXcds * 32) &&
               dalloc(&w.eoff_tmp, B + 1) && dalloc(&w.i8_scales, 4) && dalloc(&w.i8_amax, 2);
     if (ok && k.precision == VELO_FP8) {
         const int ns = n_slots(k.gnn_iters);

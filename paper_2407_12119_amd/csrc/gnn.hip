@@ -235,7 +235,13 @@ struct MlpArgs {
     float *mout;
     const float *ab;               // EDGE_AB / ENC_AB: per-hit first-layer products [N x 2H]
     const unsigned *flags;
+    // 16-wavefront source-hit walks: per-XCD work counters, zeroed before the
+    // launch (null: the static mapping)
+    int *grab;
 };
+
+// source hits a wavefront takes at a time from its XCD's work counter
+constexpr int kGrab = 4;
 
 constexpr int kMlpBlock = 512;
 
@@ -336,13 +342,15 @@ __device__ inline void classify(const typename P::wfrag_t *sC1, const float *sCB
 #pragma unroll
     for (int mo = 0; mo < MO; mo++)
 #pragma unroll
-        for (int i = 0; i < 4; i++) part += w2[mo][i] * fmaxf(hc[mo][i], 0.f);
+        for (int i = 0; i < 4; i++) part += w2[mo][i] * relu1(hc[mo][i]);
     part += __shfl_xor(part, 16);
     part += __shfl_xor(part, 32);
     if (g == 0 && ok) logit[q] = part + b_out;
 }
 
-template <class P, int H, int MODE, bool CLS, bool WIDE = false>
+// AMAX: the launch records its inputs' calibration maxima (A.amax,
+// A.amax_cls); only then is that code compiled in.
+template <class P, int H, int MODE, bool CLS, bool WIDE = false, bool AMAX = false>
 __global__ __launch_bounds__(WIDE ? 1024 : 512) void k_mlp(MlpArgs A) {
     using S = typename P::state_t;
     using W = typename P::wfrag_t;
@@ -515,7 +523,7 @@ __global__ __launch_bounds__(WIDE ? 1024 : 512) void k_mlp(MlpArgs A) {
         auto process = [&](const Chunk &cur, const typename P::frag_t *X, const raw_t *R, const f32x4 *G) {
             const int64_t q = cur.c0 + n;
             const bool ok = q < cur.a1;
-            if (!AB && A.amax) {   // calibration runs the unsplit modes
+            if (AMAX && !AB && A.amax) {   // calibration runs the unsplit modes
                 float mx = 0.f;
 #pragma unroll
                 for (int k = 0; k < NX; k++) mx = fmaxf(mx, P::absmax(X[k]));
@@ -534,7 +542,7 @@ __global__ __launch_bounds__(WIDE ? 1024 : 512) void k_mlp(MlpArgs A) {
             if constexpr (NSEG > 0) gemm_first<P, MO, KB, NSEG, MODE, AG>(sW1, X, hid, lane);
             if (P::kScaled) rescale<MO>(hid, SC.d1);
             relu<MO>(hid);
-            if (A.amax) record_amax(absmax4<MO>(hid), A.amax + 1);
+            if (AMAX && A.amax) record_amax(absmax4<MO>(hid), A.amax + 1);
             typename P::frag_t xh[KB];
             P::template chain<MO>(hid, xh, SC.ix2);
             load_bias<MO>(sB + H, o, g);
@@ -549,13 +557,15 @@ __global__ __launch_bounds__(WIDE ? 1024 : 512) void k_mlp(MlpArgs A) {
                         else o[mo][i] += P::seg0(X, mo, i);
                     }
             }
-            if (ok) P::template store_all<MO>((S *)A.out + q * H, g, o);
-            if (A.mout) {
+            if (!A.mout) {
+                if (ok) P::template store_all<MO>((S *)A.out + q * H, g, o);
+            } else {
                 // the states as stored, summed over the chunk's edges
+                P::template store_round<MO>((S *)A.out + q * H, g, o, ok);
 #pragma unroll
                 for (int mo = 0; mo < MO; mo++)
 #pragma unroll
-                    for (int i = 0; i < 4; i++) o[mo][i] = row_sum16(ok ? (float)(S)o[mo][i] : 0.f);
+                    for (int i = 0; i < 4; i++) o[mo][i] = row_sum16(o[mo][i]);
                 if (n == 0) {
 #pragma unroll
                     for (int mo = 0; mo < MO; mo++) {
@@ -575,9 +585,34 @@ __global__ __launch_bounds__(WIDE ? 1024 : 512) void k_mlp(MlpArgs A) {
             typename P::frag_t X[NX];
             raw_t R[RAW ? KB : 1];
             f32x4 G[NG];
-            for (Chunk c = from_hit(wr.first); c.i < wr.end; c = next(c)) {
-                load_chunk(c, X, R, G);
-                process(c, X, R, G);
+            // Dynamic, XCD-blocked: workgroups are dispatched round-robin over
+            // the XCDs, and the wavefronts of XCD x take its slice of source
+            // hits kGrab at a time from its counter (A.grab, zeroed before the
+            // launch).  They then stay within a window of about kGrab hits per
+            // wavefront, so the destination rows they gather are shared in that
+            // XCD's L2 (a static stride lets them drift apart by several
+            // events).  With fewer workgroups than XCDs there are as many
+            // slices as workgroups; a wavefront stops at the first grab past
+            // its slice's end.
+            const int nsl = min((int)gridDim.x, kXcds);
+            const int x = blockIdx.x % nsl;
+            const int64_t per = (A.n_rows + nsl - 1) / nsl;
+            const int64_t lo = per * x, hi = min(A.n_rows, lo + per);
+            int *ctr = A.grab + 32 * x;
+            for (;;) {
+                int v = 0;
+                if (lane == 0) v = atomicAdd(ctr, kGrab);
+                const int64_t s0 = lo + __builtin_amdgcn_readfirstlane(v);
+                if (s0 >= hi) break;
+                const int64_t s1 = min(s0 + kGrab, hi);
+                for (int64_t i = s0; i < s1; i++) {
+                    const int64_t a0 = rows4[i], a1 = min((int64_t)rows4[i + 1], N);
+                    for (int64_t c0 = a0; c0 < a1; c0 += 16) {
+                        const Chunk c{i, a0, c0, a1};
+                        load_chunk(c, X, R, G);
+                        process(c, X, R, G);
+                    }
+                }
             }
             return;
         }
@@ -662,7 +697,7 @@ __global__ __launch_bounds__(WIDE ? 1024 : 512) void k_mlp(MlpArgs A) {
         }
         f32x4 o[MO];
         if (MLP) {
-            if (!AB && A.amax) {   // calibration runs the unsplit modes
+            if (AMAX && !AB && A.amax) {   // calibration runs the unsplit modes
                 float mx = 0.f;
 #pragma unroll
                 for (int k = 0; k < NX; k++) mx = fmaxf(mx, P::absmax(X[k]));
@@ -680,7 +715,7 @@ __global__ __launch_bounds__(WIDE ? 1024 : 512) void k_mlp(MlpArgs A) {
             if constexpr (NSEG > 0) gemm_first<P, MO, KB, NSEG, MODE, AGU>(sW1, X, hid, lane);
             if (P::kScaled) rescale<MO>(hid, SC.d1);
             relu<MO>(hid);
-            if (A.amax) record_amax(absmax4<MO>(hid), A.amax + 1);
+            if (AMAX && A.amax) record_amax(absmax4<MO>(hid), A.amax + 1);
             typename P::frag_t xh[KB];
             P::template chain<MO>(hid, xh, SC.ix2);
             load_bias<MO>(sB + H, o, g);
@@ -703,7 +738,7 @@ __global__ __launch_bounds__(WIDE ? 1024 : 512) void k_mlp(MlpArgs A) {
 #pragma unroll
             for (int mo = 0; mo < MO; mo++) o[mo] = P::load4(sa + qc * H + P::stored(mo, g));
         }
-        if (CLS) classify<P, H>(sC1, sCB, b_out, o, SCc, A.amax_cls, lane, ok, q, A.logit);
+        if (CLS) classify<P, H>(sC1, sCB, b_out, o, SCc, AMAX ? A.amax_cls : nullptr, lane, ok, q, A.logit);
     }
 }
 
@@ -798,12 +833,27 @@ inline int blocks_per_cu(const void *kernel, int block, size_t lds) {
 
 template <class P, int H, int MODE, bool CLS>
 void run_mlp(velo_ctx *c, int stage, MlpArgs a, hipStream_t s) {
+    if (a.amax || a.amax_cls) {
+        // calibration (bf16 kernels of an fp8 context): 8-wavefront workgroups
+        if constexpr (std::is_same<P, BF16>::value) {
+            constexpr size_t lds = mlp_lds<P, H, MODE, CLS>();
+            const void *kernel = reinterpret_cast<const void *>(&k_mlp<P, H, MODE, CLS, false, true>);
+            static const int occ = blocks_per_cu(kernel, kMlpBlock, lds);
+            a.xcd = c->tune_xcd[stage];
+            k_mlp<P, H, MODE, CLS, false, true><<<persistent_grid(c, stage_per_cu(c, stage, occ, occ)), kMlpBlock,
+                                                  lds, s>>>(a);
+            return;
+        }
+    }
     if constexpr (wide_ok<P, H, MODE, CLS>()) {
         if (c->tune_mlp_block[stage] == 2 * kMlpBlock) {
             constexpr size_t lds = mlp_lds<P, H, MODE, CLS, true>();
             const void *kernel = reinterpret_cast<const void *>(&k_mlp<P, H, MODE, CLS, true>);
             static const int occ = blocks_per_cu(kernel, 2 * kMlpBlock, lds);
             a.xcd = c->tune_xcd[stage];
+            // the dynamic walk over per-XCD work counters, zeroed here
+            a.grab = c->ws.grab;
+            launch_fill(a.grab, 0, kXcds * 32, s);
             k_mlp<P, H, MODE, CLS, true><<<persistent_grid(c, stage_per_cu(c, stage, occ, occ)), 2 * kMlpBlock,
                                            lds, s>>>(a);
             return;

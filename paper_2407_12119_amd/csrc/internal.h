@@ -51,6 +51,8 @@ struct Workspace {
     void *e = nullptr;           // [max_edges x H] edge encodings (updated in place), fp32 or bf16
     int *n_edges = nullptr;      // [1] internal edge count
     unsigned *flags = nullptr;   // [1] latched device errors
+    int *grab = nullptr;         // [8 x 32] per-XCD work counters of the dynamic source-hit walk
+                                 // (one 128-byte line each)
     int *eoff_tmp = nullptr;     // [max_events + 1]
     float *scales = nullptr;     // [4 x n_slots] fp8 per-tensor scales
     float *amax = nullptr;       // [2 x n_slots] calibration maxima of the MLP inputs

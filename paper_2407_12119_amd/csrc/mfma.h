@@ -59,6 +59,15 @@ struct F32 {
 #pragma unroll
         for (int mo = 0; mo < MO; mo++) *(f32x4 *)(row + 16 * mo + 4 * g) = o[mo];
     }
+    // store_all where ok; o becomes the stored values (0 where not ok)
+    template <int MO>
+    __device__ static void store_round(float *row, int g, f32x4 *o, bool ok) {
+        if (ok) store_all<MO>(row, g, o);
+#pragma unroll
+        for (int mo = 0; mo < MO; mo++)
+#pragma unroll
+            for (int i = 0; i < 4; i++) o[mo][i] = ok ? o[mo][i] : 0.f;
+    }
     __device__ static f32x4 load4(const float *p) { return *(const f32x4 *)p; }
     __device__ static float absmax(const frag_t &f) {
         return fmaxf(fmaxf(fabsf(f[0]), fabsf(f[1])), fmaxf(fabsf(f[2]), fabsf(f[3])));
@@ -96,6 +105,21 @@ struct BF16 {
     __device__ static void store_all(bf16 *row, int g, const f32x4 *o) {
 #pragma unroll
         for (int kb = 0; kb < MO / 2; kb++) *(bf16x8 *)(row + 32 * kb + 8 * g) = cat(cvt(o[2 * kb]), cvt(o[2 * kb + 1]));
+    }
+    // store_all where ok; o becomes the stored (rounded) values, 0 where not
+    // ok: each value is rounded once, for the store and for the caller
+    template <int MO>
+    __device__ static void store_round(bf16 *row, int g, f32x4 *o, bool ok) {
+#pragma unroll
+        for (int kb = 0; kb < MO / 2; kb++) {
+            const bf16x8 v = cat(cvt(o[2 * kb]), cvt(o[2 * kb + 1]));
+            if (ok) *(bf16x8 *)(row + 32 * kb + 8 * g) = v;
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                o[2 * kb][j] = ok ? (float)v[j] : 0.f;
+                o[2 * kb + 1][j] = ok ? (float)v[4 + j] : 0.f;
+            }
+        }
     }
     template <int MO>
     __device__ static void mma(const wfrag_t *a, const frag_t &x, f32x4 *acc) {
@@ -181,6 +205,8 @@ struct BF16X2 {
     __device__ static int stored(int mo, int g) { return BF16::stored(mo, g); }
     template <int MO>
     __device__ static void store_all(bf16 *row, int g, const f32x4 *o) { BF16::store_all<MO>(row, g, o); }
+    template <int MO>
+    __device__ static void store_round(bf16 *row, int g, f32x4 *o, bool ok) { BF16::store_round<MO>(row, g, o, ok); }
     __device__ static f32x4 load4(const bf16 *p) { return BF16::load4(p); }
     __device__ static float absmax(const frag_t &f) { return BF16::absmax(f.hi); }
 };
@@ -229,6 +255,8 @@ struct FP8 {
     __device__ static int stored(int mo, int g) { return BF16::stored(mo, g); }
     template <int MO>
     __device__ static void store_all(bf16 *row, int g, const f32x4 *o) { BF16::store_all<MO>(row, g, o); }
+    template <int MO>
+    __device__ static void store_round(bf16 *row, int g, f32x4 *o, bool ok) { BF16::store_round<MO>(row, g, o, ok); }
     __device__ static f32x4 load4(const bf16 *p) { return BF16::load4(p); }
     __device__ static float absmax(const frag_t &) { return 0.f; }
 };
@@ -365,12 +393,17 @@ __device__ inline void load_bias(const float *__restrict__ b, f32x4 *rb, int g) 
     for (int mo = 0; mo < MO; mo++) rb[mo] = *(const f32x4 *)(b + 16 * mo + 4 * g);
 }
 
+// max(x, 0) as one integer max on the bit pattern: a float with its sign
+// bit set is a negative int32 and becomes +0, any other keeps its value (a
+// float max would first canonicalise a matrix-core result: two instructions)
+__device__ inline float relu1(float x) { return __int_as_float(max(__float_as_int(x), 0)); }
+
 template <int MO>
 __device__ inline void relu(f32x4 *acc) {
 #pragma unroll
     for (int mo = 0; mo < MO; mo++)
 #pragma unroll
-        for (int i = 0; i < 4; i++) acc[mo][i] = fmaxf(acc[mo][i], 0.f);
+        for (int i = 0; i < 4; i++) acc[mo][i] = relu1(acc[mo][i]);
 }
 
 template <int MO>
@@ -378,7 +411,7 @@ __device__ inline void bias_relu(f32x4 *acc, const f32x4 *rb) {
 #pragma unroll
     for (int mo = 0; mo < MO; mo++)
 #pragma unroll
-        for (int i = 0; i < 4; i++) acc[mo][i] = fmaxf(acc[mo][i] + rb[mo][i], 0.f);
+        for (int i = 0; i < 4; i++) acc[mo][i] = relu1(acc[mo][i] + rb[mo][i]);
 }
 
 template <int MO>
