@@ -110,12 +110,18 @@ def stage_roofline(stages, steps, H, iters, prec, N, E):
     group of stages, the algorithmic flops F and HBM bytes B of the method
     (not of this implementation), T_roof = max(F / MFMA peak, B / HBM peak),
     the measured time T and T_roof / T.  s = bytes per stored encoding
-    element; messages are float32 in every precision.
+    element; messages are float32 in every precision.  F is the method's
+    cheapest exact form: a first layer over concatenated hit encodings
+    [h_i; h_j] is W_s h_i + W_d h_j, with the products taken once per hit
+    (2 H^2 flops per hit and segment) and only the edge's own segment per
+    edge; the 2-byte paths multiply the concatenation per edge instead, which
+    is more matrix work for the same result.
       embedding       F = 34,560 N                 B = 28 N (inputs, embedding)
       graph           F = 0 (integer/ALU)          B = 24 N + 16 E (embedding read, row pointers and
                                                    the event-local edge pairs out; incoming lists 8 E + 4 N)
-      encoders        F = 2(3H + H^2) N + 6 H^2 E  B = 12 N + s H N + (s H + 8) E
-      message passing F = n 8 H^2 (N + E) + 2 (H^2 + H) E (with the classifier)
+      encoders        F = 2(3H + H^2) N + 4 H^2 N + 2 H^2 E
+                                                   B = 12 N + s H N + (s H + 8) E
+      message passing F = n (12 H^2 N + 4 H^2 E) + 2 (H^2 + H) E (with the classifier)
                       B = n ((2 s H + 8) E + (2 s H + 16 H) N) + 4 E
       components      F = 0                        B = 9 E + 16 N
     The float32 path's per-hit first-layer products (hit_proj) count with
@@ -126,10 +132,10 @@ def stage_roofline(stages, steps, H, iters, prec, N, E):
     groups = {
         "embedding": (["embed"], 34560 * N, 28 * N),
         "graph": (["prepare", "knn", "compact", "lists"], 0, 24 * N + 16 * E),
-        "encoders": (["node_enc", "edge_enc"], 2 * (3 * H + H * H) * N + 6 * H * H * E,
+        "encoders": (["node_enc", "edge_enc"], 2 * (3 * H + H * H) * N + 4 * H * H * N + 2 * H * H * E,
                      12 * N + s * H * N + (s * H + 8) * E),
         "message_passing": (["hit_proj", "messages", "node_net", "edge_net", "edge_cls"],
-                            iters * 8 * H * H * (N + E) + 2 * (H * H + H) * E,
+                            iters * (12 * H * H * N + 4 * H * H * E) + 2 * (H * H + H) * E,
                             iters * ((2 * s * H + 8) * E + (2 * s * H + 16 * H) * N) + 4 * E),
         "components": (["components"], 0, 9 * E + 16 * N),
     }
@@ -624,6 +630,20 @@ def run_multistream(synth, torch, wl, blob, prec, n_streams, events_per_stream, 
     return res
 
 
+def parse_tuning(velo, text):
+    """'stage=k,stage=k' -> {stage: k}, checked against the stage names and
+    the candidate table."""
+    choice = {}
+    for item in text.split(","):
+        stage, _, k = item.partition("=")
+        stage = stage.strip()
+        if stage not in velo.STAGES or not k.strip().isdigit() or int(k) >= len(velo.AUTOTUNE_CANDIDATES):
+            raise SystemExit(f"--tuning: bad entry {item!r} (stages {', '.join(velo.STAGES)}; "
+                             f"candidates 0..{len(velo.AUTOTUNE_CANDIDATES) - 1})")
+        choice[stage] = int(k)
+    return choice
+
+
 def run_batched(velo, synth, torch, wl, batch, hits, blob, prec, steps, warmup, graph=False, latency=False,
                 autotune=True, copy_gbs=None, samples=None):
     import numpy as np
@@ -639,12 +659,16 @@ def run_batched(velo, synth, torch, wl, batch, hits, blob, prec, steps, warmup, 
         log(f"fp8: calibrating on {calib.n_events} events")
         ctx.calibrate(velo.DeviceHits.from_batch(calib))
     out = ctx.alloc_outputs(hits)
+    tuned = None
+    if isinstance(autotune, dict):   # a stored choice (--tuning), applied instead of measured
+        ctx.set_tuning(autotune)
+        tuned = {k: autotune.get(k, 0) for k in velo.STAGES}
+        log(f"{prec}: tuning {autotune}")
     log(f"{prec}: warmup {warmup}")
     for _ in range(warmup):
         ctx.infer(hits, out, check=False)
     ctx.check()
-    tuned = None
-    if autotune:
+    if tuned is None and autotune:
         tuned = ctx.autotune(hits, out)
         log(f"{prec}: autotune choice {tuned}")
     n_edges = int(out["n_edges"].cpu()[0])
@@ -739,6 +763,9 @@ def main():
     ap.add_argument("--graph", action="store_true", help="also time hipGraph replays of the whole path")
     ap.add_argument("--latency", action="store_true", help="per-batch p50/p99 latency (with --graph: of replays)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the built-in launch parameters")
+    ap.add_argument("--tuning", default="",
+                    help="apply this candidate choice instead of autotuning (stage=k,...; stages not named: 0), "
+                         "e.g. to profile only the launches a tuned run makes")
     ap.add_argument("--no-quality", action="store_true", help="skip the track-finding quality block")
     ap.add_argument("--streams", type=int, default=16,
                     help="multi-stream throughput mode: streams (0 to skip)")
@@ -780,8 +807,9 @@ def main():
     log(f"device copy probe: {copy_gbs} GB/s (read + write)")
 
     samples = {}
+    tune = parse_tuning(velo, args.tuning) if args.tuning else not args.no_autotune
     ctx, main_res = run_batched(velo, synth, torch, wl, batch, hits, blob, args.precision, args.steps,
-                                args.warmup, args.graph, args.latency, not args.no_autotune, copy_gbs, samples)
+                                args.warmup, args.graph, args.latency, tune, copy_gbs, samples)
     sweep = sweep_compare(ctx, torch, hits)
     log(f"components, exact vs the paper's plane sweeps: {json.dumps(sweep)}")
     knn_loop = knn_compare(ctx, torch, hits)
@@ -789,7 +817,7 @@ def main():
     variants = {}
     for prec in [p for p in args.variants.split(",") if p and p != args.precision]:
         vctx, vres = run_batched(velo, synth, torch, wl, batch, hits, blob, prec, args.steps, args.warmup,
-                                 args.graph, args.latency, not args.no_autotune, copy_gbs, samples)
+                                 args.graph, args.latency, tune, copy_gbs, samples)
         vctx.close()
         variants[prec] = vres
     multi = None
@@ -839,7 +867,7 @@ def main():
     large = None
     if not args.no_large and args.workload == "batch256":
         ctx.close()
-        large = run_large(velo, synth, torch, args.large_steps, 2, not args.no_autotune)
+        large = run_large(velo, synth, torch, args.large_steps, 2, tune)
 
     recipe = wl.recipe
     comp = (f"1 vertex x {recipe.fixed_tracks} tracks" if recipe.fixed_tracks else

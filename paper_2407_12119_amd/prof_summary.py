@@ -6,8 +6,9 @@
         per-kernel matrix-core use from one --pmc run of the derived counters
         MfmaUtil (percent of cycles the MFMA units are busy, over all SIMDs)
         and MfmaFlopsBF16 / MfmaFlopsF32 / MfmaFlopsF16 (flops issued to the
-        matrix cores); with the kernel-trace statistics of the same command,
-        the MFMA rate those flops reach over the kernel's average duration
+        matrix cores; fp8 has no such counter); with the kernel-trace
+        statistics of the same command, the MFMA rate those flops reach over
+        the kernel's average duration
     python -m paper_2407_12119_amd.prof_summary traffic FETCH_CSV WRITE_CSV --workload W
                                                 [--json profiles/edge_net_traffic.json] [--git-rev REV]
         per-kernel HBM bytes per dispatch from two --pmc runs (FETCH_SIZE, then
@@ -33,9 +34,11 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 KERNEL_SOURCES = ["paper_2407_12119_amd/csrc/gnn.hip", "paper_2407_12119_amd/csrc/mfma.h",
                   "paper_2407_12119_amd/csrc/internal.h"]
 # the non-final edge network of each precision's inference path (k_mlp<P, H,
-# mode, classifier>: mode 1 = concatenated first layer, 4 = factorised)
-EDGE_NET = {"fp32": "k_mlp<F32, {H}, 4, false>", "bf16": "k_mlp<BF16, {H}, 1, false>",
-            "bf16x2": "k_mlp<BF16X2, {H}, 1, false>", "fp8": "k_mlp<FP8, {H}, 1, false>"}
+# mode, classifier, 16-wavefront workgroups, calibrating>: mode 1 =
+# concatenated first layer, 4 = factorised; W = true at H = 128, where the
+# autotuner picks the 16-wavefront workgroups)
+EDGE_NET = {"fp32": "k_mlp<F32, {H}, 4, false, false, false>", "bf16": "k_mlp<BF16, {H}, 1, false, {W}, false>",
+            "bf16x2": "k_mlp<BF16X2, {H}, 1, false, {W}, false>", "fp8": "k_mlp<FP8, {H}, 1, false, {W}, false>"}
 PROBE = "CUDAFunctorOnSelf_add"
 
 
@@ -112,7 +115,7 @@ def traffic(fetch_csv, write_csv, workload, hidden, json_path=None, rev=None) ->
             js = {"source_sha1": sha}
         ent = js.setdefault(workload, {})
         for prec, pat in EDGE_NET.items():
-            k = pat.format(H=hidden)
+            k = pat.format(H=hidden, W="true" if hidden == 128 else "false")
             if k in res:
                 ent[prec] = {"kernel": k, "fetch_bytes": round(res[k][0]), "write_bytes": round(res[k][1]),
                              "bytes_per_launch": round(res[k][0] + res[k][1])}
@@ -132,9 +135,11 @@ def mfma(counter_csv: str, stats_csv=None, top: int = 16) -> str:
             avg_ms[short(r["Name"])] = float(r["AverageNs"]) / 1e6
     util = lambda k: sum(vals[k].get("MfmaUtil", [0.0])) / max(len(vals[k].get("MfmaUtil", [])), 1)
     flops = lambda k, c: sum(vals[k].get(c, [0.0])) / max(len(vals[k].get(c, [])), 1)
-    keys = [k for k in vals if any(flops(k, c) > 0 for c in ("MfmaFlopsBF16", "MfmaFlopsF32", "MfmaFlopsF16"))]
-    keys.sort(key=lambda k: -sum(flops(k, c) for c in ("MfmaFlopsBF16", "MfmaFlopsF32", "MfmaFlopsF16")) *
-              len(vals[k].get("MfmaUtil", [1])))
+    # kernels that use the matrix cores (fp8 products have no flops counter:
+    # they show their busy share only), by busy time
+    keys = [k for k in vals if util(k) > 0 or
+            any(flops(k, c) > 0 for c in ("MfmaFlopsBF16", "MfmaFlopsF32", "MfmaFlopsF16"))]
+    keys.sort(key=lambda k: -util(k) * avg_ms.get(k, 1.0) * len(vals[k].get("MfmaUtil", [1])))
     out = ["| kernel | dispatches | MFMA busy | bf16 GFLOP / dispatch | fp32 GFLOP / dispatch | "
            "MFMA TFLOP/s over the average duration |", "|---|---|---|---|---|---|"]
     for k in keys[:top]:

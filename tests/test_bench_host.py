@@ -42,9 +42,23 @@ def test_stage_roofline_is_max_of_compute_and_bytes():
     assert g["flops"] == 0 and g["bytes"] == 24 * N + 16 * E
     assert abs(g["t_roof_ms"] - g["bytes"] / (bench.PEAK_HBM_GBS * 1e9) * 1e3) < 1e-4
     mp = r["message_passing"]
-    assert mp["flops"] == n * 8 * H * H * (N + E) + 2 * (H * H + H) * E
+    # node network 3H -> H -> H per hit; edge network: the hit segments' products
+    # once per hit, the edge segment and the second layer per edge; classifier
+    assert mp["flops"] == n * (2 * 3 * H * H * N + 2 * H * H * N + 2 * 2 * H * H * N + 2 * H * H * E
+                               + 2 * H * H * E) + 2 * (H * H + H) * E
+    enc = r["encoders"]
+    assert enc["flops"] == 2 * (3 * H + H * H) * N + 2 * 2 * H * H * N + 2 * H * H * E
     assert abs(r["total"]["t_ms"] - sum(v["t_ms"] for k, v in r.items() if k != "total")) < 1e-3
     for k, v in r.items():
         if k != "total":
             roof = max(v["flops"] / (bench.PEAK_TFLOPS["bf16"] * 1e12), v["bytes"] / (bench.PEAK_HBM_GBS * 1e9))
             assert abs(v["t_roof_ms"] - roof * 1e3) < 1e-4
+
+
+def test_stored_tuning_is_parsed_and_checked():
+    from paper_2407_12119_amd import velo
+    assert bench.parse_tuning(velo, "edge_net=7, knn=5") == {"edge_net": 7, "knn": 5}
+    import pytest
+    for bad in ("edge_net=8", "edge_net", "nope=1", "knn=-1"):
+        with pytest.raises(SystemExit):
+            bench.parse_tuning(velo, bad)
