@@ -428,10 +428,69 @@ def run_quality(velo, synth, torch, precisions):
                              "efficiency": round(m["efficiency"], 5),
                              "d_efficiency_pts": round(100 * (m["efficiency"] - res[precisions[0]]["efficiency"]), 4),
                              "what": "INT8 embedding (calibrated on 16 other events), float32 GNN, against fp32"}
+    res["triplets"] = run_triplet_quality(velo, torch, wl, batch, hits, blob, r2)
     res["weights"] = "trained by the float64 oracle (embedding 300 steps, GNN 300 steps; see trained_h64_n4.json)"
     res["workload"] = f"{wl.name}: the {batch.n_events} benchmark events, d2 < 0.9, k_max = {wl.k_max}"
     log(f"quality: {json.dumps(res)}")
     return res
+
+
+TRAINED_TRIPLETS = os.path.join(ROOT, "tests", "golden", "trained_triplets_h64.npy")
+
+
+def run_triplet_quality(velo, torch, wl, batch, hits, blob, r2, reps=10):
+    """The triplet stage (Sec. 5.3, 5.4) on the benchmark batch with the
+    trained network and the triplet classifiers trained by the oracle on its
+    final edge encodings (tests/golden/make_trained_triplets.py): tracks
+    built from the purified edge graph against the connected components of
+    the purified hit graph (the paper's with and without triplets), and the
+    stage's time per batch (triplet building, both classifiers, track
+    building), with the classifiers' matrix work."""
+    import numpy as np
+    from paper_2407_12119_amd import metrics
+    if not os.path.exists(TRAINED_TRIPLETS):
+        return {"skipped": "trained triplet classifiers not generated"}
+    tb = np.load(TRAINED_TRIPLETS)
+    keys = ("efficiency", "clone_rate", "fake_rate", "hit_efficiency", "hit_purity")
+    out = {"classifiers": "trained by the float64 oracle (see trained_triplets_h64.json)"}
+    for prec in ("fp32", "bf16x2"):
+        ctx = velo.Context(wl.hidden, wl.iters, r2, wl.k_max, wl.edge_logit_min, prec, max_hits=batch.n_hits,
+                           max_events=batch.n_events, max_event_hits=batch.max_event_hits())
+        ctx.set_params(torch.from_numpy(blob).cuda())
+        ctx.set_triplet_params(torch.from_numpy(tb).cuda(), 0.0, 1 << 22)
+        g = ctx.infer(hits)
+        t = ctx.triplets(hits, g)
+        ctx.set_timing(True)
+        ctx.read_timing()
+        for _ in range(reps):
+            ctx.triplets(hits, g, out=t, check=False)
+        ms = ctx.read_timing()["triplets"][0] / reps
+        ctx.set_timing(False)
+        ctx.check()
+        gh, th = velo.graph_to_host(g, batch.n_hits), velo.triplets_to_host(t)
+        tracks = []
+        for b in range(batch.n_events):
+            s0, s1 = int(gh["edge_offsets"][b]), int(gh["edge_offsets"][b + 1])
+            k0, k1 = int(th["track_offsets"][b]), int(th["track_offsets"][b + 1])
+            tracks.append(metrics.track_hit_lists(gh["src"][s0:s1], gh["dst"][s0:s1], th["edge_seg"][s0:s1],
+                                                  th["tracks"][k0:k1]))
+        mt = metrics.track_list_metrics(tracks, batch.pid, batch.event_offsets)
+        mw = metrics.track_metrics(gh["labels"], batch.pid, batch.event_offsets)
+        H = wl.hidden
+        n_tri = th["n_art"] + th["n_elb"]
+        flops = n_tri * 2 * (2 * H * H + H)        # hidden layer [2H -> H] and output [H -> 1] per triplet
+        out[prec] = {"with_triplets": {k: round(mt[k], 5) for k in keys},
+                     "without_triplets": {k: round(mw[k], 5) for k in keys},
+                     "d_efficiency_pts": round(100 * (mt["efficiency"] - mw["efficiency"]), 3),
+                     "articulations": th["n_art"], "articulations_kept": round(float(np.mean(th["art_logit"] >= 0)), 4),
+                     "elbows": th["n_elb"], "elbows_kept": round(float(np.mean(th["elb_logit"] >= 0)), 4)
+                     if th["n_elb"] else 0.0,
+                     "tracks": th["n_tracks"], "stage_ms": round(ms, 4),
+                     "classifier_gflop": round(flops / 1e9, 3),
+                     "classifier_tflops_over_stage": round(flops / (ms * 1e-3) / 1e12, 3) if ms > 0 else None}
+        log(f"triplets {prec}: {json.dumps(out[prec])}")
+        ctx.close()
+    return out
 
 
 def transfer_times(torch, batch, out, n_edges, reps=5):

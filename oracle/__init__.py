@@ -262,6 +262,35 @@ def triplet_logits(pairs, e, tblob, which: int) -> np.ndarray:
     return z
 
 
+def triplet_classifier_grad(pairs, e, tblob, which: int, dlogit) -> np.ndarray:
+    """Gradient of sum_t dlogit_t * z_t with respect to the parameters of
+    triplet classifier `which` (0: articulations, 1: elbows), where z_t =
+    W1 relu(W0 [e_a || e_b] + b0) + b1 (Sec. 5.3) and e [E x H] are the final
+    edge encodings, taken as fixed.  Returned over the classifier's slice of
+    the blob, in its layout (W0 [H x 2H] row-major, b0 [H], W1 [H], b1).
+    Written with numpy in float64 for training the classifiers; the forward
+    pass it differentiates is oracle_triplet_logits (C)."""
+    pairs = np.asarray(pairs, np.int64).reshape(-1, 2)
+    e = np.asarray(e, np.float64)
+    H = e.shape[1]
+    n = 2 * H * H + 2 * H + 1
+    p = np.asarray(tblob, np.float64)[which * n:(which + 1) * n]
+    W0 = p[:2 * H * H].reshape(H, 2 * H)
+    b0 = p[2 * H * H:2 * H * H + H]
+    W1 = p[2 * H * H + H:2 * H * H + 2 * H]
+    dz = np.asarray(dlogit, np.float64)
+    X = np.concatenate([e[pairs[:, 0]], e[pairs[:, 1]]], axis=1)     # [T x 2H]
+    A = X @ W0.T + b0                                                 # hidden pre-activations
+    R = np.where(A > 0.0, A, 0.0)
+    dA = np.outer(dz, W1) * (A > 0.0)
+    g = np.empty(n)
+    g[:2 * H * H] = (dA.T @ X).ravel()
+    g[2 * H * H:2 * H * H + H] = dA.sum(axis=0)
+    g[2 * H * H + H:2 * H * H + 2 * H] = R.T @ dz
+    g[-1] = dz.sum()
+    return g
+
+
 def build_tracks(n: int, src, dst, plane, keep, art, art_keep, elb, elb_keep):
     """Tracks from the purified edge graph (Sec. 5.4): (edge_seg [E], tracks
     [T x 2] of segment labels, the second -1 for one-segment tracks)."""

@@ -146,6 +146,32 @@ def track_list_metrics(tracks, pid, event_offsets) -> dict:
     }
 
 
+def track_hit_lists(src, dst, edge_seg, tracks):
+    """One event's tracks from the purified edge graph (Sec. 5.4) as hit
+    lists: a track is one or two segments (`tracks` [T x 2] of segment
+    labels, the second -1 for one segment), a segment the kept edges with
+    that label (`edge_seg`, -1 for other edges), and a track's hits the ends
+    of its edges, ascending, without repeats (step 4, edges replaced by
+    hits)."""
+    src, dst = np.asarray(src, np.int64), np.asarray(dst, np.int64)
+    seg = np.asarray(edge_seg, np.int64)
+    tracks = np.asarray(tracks, np.int64).reshape(-1, 2)
+    ends = {}
+    kept = np.nonzero(seg >= 0)[0]
+    if kept.shape[0]:
+        order = kept[np.argsort(seg[kept], kind="stable")]
+        labs, first = np.unique(seg[order], return_index=True)
+        for lab, grp in zip(labs.tolist(), np.split(order, first[1:])):
+            ends[lab] = np.unique(np.concatenate([src[grp], dst[grp]]))
+    out = []
+    for a, b in tracks.tolist():
+        h = ends.get(a, np.zeros(0, np.int64))
+        if b >= 0:
+            h = np.union1d(h, ends.get(b, np.zeros(0, np.int64)))
+        out.append(h.astype(np.int32))
+    return out
+
+
 def labels_to_tracks(labels, event_offsets):
     """Connected-component labels -> per-event lists of hit arrays (one per component)."""
     labels = np.asarray(labels, np.int64)

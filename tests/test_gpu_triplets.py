@@ -25,6 +25,7 @@ pytestmark = pytest.mark.gpu
 
 U = 2.0 ** -8
 TRAINED = os.path.join(os.path.dirname(__file__), "golden", "trained_h64_n4.npy")
+TRAINED_TRIPLETS = os.path.join(os.path.dirname(__file__), "golden", "trained_triplets_h64.npy")
 
 
 def _centred_triplet_params(wl, blob, ev):
@@ -134,6 +135,22 @@ def test_triplets_on_trained_weights():
     tblob = _centred_triplet_params(wl, blob, batch.event(0))
     _, _, g, t = _run(wl, batch, blob, tblob, "fp32")
     _check(wl, batch, blob, tblob, g, t, lambda z: 1e-4 * np.maximum(np.abs(z), 1.0))
+
+
+def test_trained_triplet_classifiers_against_the_oracle():
+    """The triplet classifiers trained by the oracle on the trained network's
+    encodings (tests/golden/make_trained_triplets.py), float32: logits
+    within 1e-4 max(|z|, 1) of the oracle's on the GPU's graph; lists,
+    segments and tracks exact from the GPU's decisions."""
+    if not (os.path.exists(TRAINED) and os.path.exists(TRAINED_TRIPLETS)):
+        pytest.skip("trained weights not generated")
+    wl = synth.WORKLOADS["batch256_trained"]
+    blob = np.load(TRAINED)
+    tblob = np.load(TRAINED_TRIPLETS)
+    batch = synth.make_batch(wl, n_events=8, first=40)
+    _, _, g, t = _run(wl, batch, blob, tblob, "fp32")
+    th, _ = _check(wl, batch, blob, tblob, g, t, lambda z: 1e-4 * np.maximum(np.abs(z), 1.0))
+    assert th["n_art"] > 0 and 0.5 < float(np.mean(th["art_logit"] >= 0)) < 1.0
 
 
 def test_triplets_empty_events_overflow_and_order_of_calls():

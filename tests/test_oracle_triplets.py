@@ -197,3 +197,59 @@ def test_track_list_metrics_equal_label_metrics_on_components():
     b = metrics.track_list_metrics(metrics.labels_to_tracks(labels, off), pid, off)
     for k in ("efficiency", "clone_rate", "fake_rate", "hit_efficiency", "hit_purity", "n_tracks", "n_pairs"):
         assert a[k] == pytest.approx(b[k], rel=1e-12), k
+
+
+@pytest.mark.parametrize("which", [0, 1])
+def test_triplet_classifier_gradient_against_finite_differences(which):
+    """The numpy backward of the triplet classifiers against central
+    differences of the C forward (independent code).  Inputs are dyadic, so
+    every perturbed float32 parameter is exact, and every hidden unit's
+    pre-activation stays on one side of zero (|W0 x| <= 1/2 < |b0|): the
+    logits are then linear in each parameter and the differences exact up to
+    float64 rounding."""
+    H = 4
+    rng = np.random.default_rng(11 + which)
+    q = lambda a: np.round(a * 1024) / 1024
+    e = q(rng.uniform(-1, 1, (7, H)))
+    pairs = np.array([[0, 1], [2, 1], [0, 3], [4, 5], [6, 2], [5, 0]], np.int32)
+    per = 2 * H * H + 2 * H + 1
+    tb = np.zeros(2 * per, np.float32)
+    for w in (0, 1):
+        o = w * per
+        tb[o:o + 2 * H * H] = q(rng.uniform(-1, 1, 2 * H * H) / 16)
+        tb[o + 2 * H * H:o + 2 * H * H + H] = [1.0, -1.0, 1.5, -0.75]
+        tb[o + 2 * H * H + H:o + per] = q(rng.uniform(-1, 1, H + 1))
+    dz = rng.normal(0, 1, len(pairs))
+    g = oracle.triplet_classifier_grad(pairs, e, tb, which, dz)
+    assert g.shape == (per,)
+    h = 2.0 ** -6
+    f = lambda b: float(dz @ oracle.triplet_logits(pairs, e, b, which))
+    for k in range(per):
+        bp, bm = tb.copy(), tb.copy()
+        bp[which * per + k] += h
+        bm[which * per + k] -= h
+        assert bp[which * per + k] - tb[which * per + k] == h      # exact in float32
+        fd = (f(bp) - f(bm)) / (2 * h)
+        assert abs(fd - g[k]) <= 1e-12 * max(1.0, abs(fd)), (k, fd, g[k])
+    # the other classifier's parameters do not move these logits
+    other = tb.copy()
+    other[(1 - which) * per:(2 - which) * per] += np.float32(0.5)
+    assert f(other) == f(tb)
+
+
+def test_track_hit_lists_equal_the_oracle_track_hits():
+    """metrics.track_hit_lists (host code that scores the GPU's tracks) gives
+    the oracle's hit lists on random graphs with random triplet decisions."""
+    for seed in range(4):
+        rng = np.random.default_rng(100 + seed)
+        plane, src, dst = _random_graph(rng, n=30, m=60)
+        keep = (rng.random(len(src)) < 0.7).astype(np.uint8)
+        art, elb, et = oracle.triplets(30, src, dst, keep)
+        ak = (rng.random(len(art)) < 0.6).astype(np.uint8)
+        ek = (rng.random(len(elb)) < 0.3).astype(np.uint8)
+        seg, tracks = oracle.build_tracks(30, src, dst, plane, keep, art, ak, elb, ek)
+        want = oracle.track_hits(src, dst, seg, tracks)
+        got = metrics.track_hit_lists(src, dst, seg, tracks)
+        assert len(got) == len(want)
+        for a, b in zip(got, want):
+            np.testing.assert_array_equal(a, b)
