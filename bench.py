@@ -10,9 +10,9 @@ the float64 CPU oracle timed on a bounded sample of the same workload, and
 the plain per-event float32 path (one call per event).
 
 usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload batch256]
-                       [--precision fp32|bf16|bf16x2|fp8] [--variants bf16,bf16x2,fp8] [--graph] [--latency]
+                       [--precision fp32|bf16|bf16x2|fp8] [--variants bf16,bf16x2,fp8] [--no-graph] [--latency]
        the 1000-event workload: --workload batch1000_h128 --precision bf16 --variants fp8
-                                --graph --latency --no-cpu-baseline
+                                --latency --no-cpu-baseline
 """
 import argparse
 import json
@@ -819,8 +819,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-event", action="store_true")
     ap.add_argument("--no-train", action="store_true", help="skip the training-step measurement")
-    ap.add_argument("--graph", action="store_true", help="also time hipGraph replays of the whole path")
-    ap.add_argument("--latency", action="store_true", help="per-batch p50/p99 latency (with --graph: of replays)")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="skip the hipGraph replays of the whole path (timed beside the eager steps by default)")
+    ap.add_argument("--latency", action="store_true", help="per-batch p50/p99 latency (of the hipGraph replays unless --no-graph)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the built-in launch parameters")
     ap.add_argument("--tuning", default="",
                     help="apply this candidate choice instead of autotuning (stage=k,...; stages not named: 0), "
@@ -868,7 +869,7 @@ def main():
     samples = {}
     tune = parse_tuning(velo, args.tuning) if args.tuning else not args.no_autotune
     ctx, main_res = run_batched(velo, synth, torch, wl, batch, hits, blob, args.precision, args.steps,
-                                args.warmup, args.graph, args.latency, tune, copy_gbs, samples)
+                                args.warmup, not args.no_graph, args.latency, tune, copy_gbs, samples)
     sweep = sweep_compare(ctx, torch, hits)
     log(f"components, exact vs the paper's plane sweeps: {json.dumps(sweep)}")
     knn_loop = knn_compare(ctx, torch, hits)
@@ -876,7 +877,7 @@ def main():
     variants = {}
     for prec in [p for p in args.variants.split(",") if p and p != args.precision]:
         vctx, vres = run_batched(velo, synth, torch, wl, batch, hits, blob, prec, args.steps, args.warmup,
-                                 args.graph, args.latency, tune, copy_gbs, samples)
+                                 not args.no_graph, args.latency, tune, copy_gbs, samples)
         vctx.close()
         variants[prec] = vres
     multi = None
