@@ -23,6 +23,7 @@ __device__ inline f32x4 zero4() { return f32x4{0.f, 0.f, 0.f, 0.f}; }
 struct F32 {
     static constexpr bool kScaled = false;
     static constexpr bool kSplit = false;
+    static constexpr bool kPrefetchW = true;   // matrix-core-bound: prefetch weight fragments
     using state_t = float;       // hit/edge encodings in HBM
     using frag_t = f32x4;        // per-lane B operand of one K block
     using wfrag_t = f32x4;       // per-lane A operand of one (output block, K block)
@@ -77,6 +78,7 @@ struct F32 {
 struct BF16 {
     static constexpr bool kScaled = false;
     static constexpr bool kSplit = false;
+    static constexpr bool kPrefetchW = false;
     using state_t = bf16;
     using frag_t = bf16x8;
     using wfrag_t = bf16x8;
@@ -159,6 +161,7 @@ struct bf16x8x2 {
 struct BF16X2 {
     static constexpr bool kScaled = false;
     static constexpr bool kSplit = true;
+    static constexpr bool kPrefetchW = false;
     using state_t = bf16;
     using frag_t = bf16x8x2;
     using wfrag_t = bf16x8;
@@ -218,6 +221,7 @@ struct BF16X2 {
 struct FP8 {
     static constexpr bool kScaled = true;
     static constexpr bool kSplit = false;
+    static constexpr bool kPrefetchW = false;
     using state_t = bf16;
     using frag_t = long;         // 8 e4m3 values
     using wfrag_t = long;
@@ -274,6 +278,7 @@ typedef int i32x4 __attribute__((ext_vector_type(4)));
 struct I8 {
     static constexpr bool kScaled = true;
     static constexpr bool kSplit = false;
+    static constexpr bool kPrefetchW = false;
     using state_t = float;
     using frag_t = i32x4;        // 16 int8 codes
     using wfrag_t = i32x4;
@@ -370,19 +375,42 @@ constexpr size_t frag_bytes(int rows_pad, int K) {
 template <class P, int MO, int KB, int KB0 = 0, int KB1 = KB, bool STATE = false, int AG = MO>
 __device__ inline void gemm(const typename P::wfrag_t *sW, const typename P::frag_t *X, f32x4 *acc, int lane) {
     static_assert(MO % AG == 0, "fragment groups divide the output blocks");
+    if constexpr (P::kPrefetchW) {
+        // matrix-core-bound traits: the next group's weight fragments are
+        // read from LDS while this group's products run (two groups live)
+        constexpr int NGM = MO / AG, NG = (KB1 - KB0) * NGM;
+        typename P::wfrag_t a[2][AG];
 #pragma unroll
-    for (int kb = KB0; kb < KB1; kb++) {
+        for (int mo = 0; mo < AG; mo++) a[0][mo] = sW[(mo * KB + KB0) * 64 + lane];
 #pragma unroll
-        for (int m0 = 0; m0 < MO; m0 += AG) {
-            // keep one group of weight fragments live at a time
+        for (int gi = 0; gi < NG; gi++) {
+            const int kb = KB0 + gi / NGM, m0 = (gi % NGM) * AG;
             __builtin_amdgcn_sched_barrier(0);
-            typename P::wfrag_t a[AG];
+            if (gi + 1 < NG) {
+                const int kn = KB0 + (gi + 1) / NGM, mn = ((gi + 1) % NGM) * AG;
 #pragma unroll
-            for (int mo = 0; mo < AG; mo++) a[mo] = sW[((m0 + mo) * KB + kb) * 64 + lane];
+                for (int mo = 0; mo < AG; mo++) a[(gi + 1) & 1][mo] = sW[((mn + mo) * KB + kn) * 64 + lane];
+            }
             if constexpr (STATE && P::kSplit)
-                P::template mma_hi<AG>(a, X[kb], acc + m0);
+                P::template mma_hi<AG>(a[gi & 1], X[kb], acc + m0);
             else
-                P::template mma<AG>(a, X[kb], acc + m0);
+                P::template mma<AG>(a[gi & 1], X[kb], acc + m0);
+        }
+    } else {
+#pragma unroll
+        for (int kb = KB0; kb < KB1; kb++) {
+#pragma unroll
+            for (int m0 = 0; m0 < MO; m0 += AG) {
+                // keep one group of weight fragments live at a time
+                __builtin_amdgcn_sched_barrier(0);
+                typename P::wfrag_t a[AG];
+#pragma unroll
+                for (int mo = 0; mo < AG; mo++) a[mo] = sW[((m0 + mo) * KB + kb) * 64 + lane];
+                if constexpr (STATE && P::kSplit)
+                    P::template mma_hi<AG>(a, X[kb], acc + m0);
+                else
+                    P::template mma<AG>(a, X[kb], acc + m0);
+            }
         }
     }
 }
