@@ -454,7 +454,9 @@ velo_status velo_embed_train_grad(velo_ctx *ctx, const velo_hits *hits, const ve
  *   XCD-blocked work mapping   0    1    1    1    1    0    0    1
  * A 1024-thread workgroup applies to the H = 128 edge encoder and edge
  * networks with 2-byte states (16 wavefronts share the LDS weights, one
- * 16-edge chunk each); elsewhere it means 512.  The tunable stages are the
+ * 16-edge chunk each, and take their source hits from a work counter per
+ * XCD, so those launches ignore the XCD-mapping row); elsewhere it means
+ * 512.  Every candidate gives bitwise the same results.  The tunable stages are the
  * neighbour search, the edge encoder, the messages, the node and edge
  * networks and the classifier-fused edge network.
  * choice_host (optional, VELO_N_STAGES entries) receives the candidate index
