@@ -428,6 +428,41 @@ def test_captured_graph_replays_match_eager_calls():
     torch.cuda.set_stream(torch.cuda.default_stream())
 
 
+def test_captured_graph_replays_with_the_xcd_work_counters():
+    """H = 128 with the 16-wavefront edge MLPs (candidate 7): their per-XCD
+    work counters are cleared by a fill kernel before every launch, which a
+    captured graph replays too.  Every replay, with eager calls in between,
+    equals the eager result bitwise."""
+    wl = synth.WORKLOADS["batch1000_h128"]
+    batch = synth.make_batch(wl, n_events=5, first=7)
+    print(f"\n[case] graph replays H=128 bf16 candidate 7 events={batch.n_events} hits={batch.n_hits}", flush=True)
+    side = torch.cuda.Stream()
+    torch.cuda.set_stream(side)
+    ctx = velo.Context(wl.hidden, wl.iters, oracle.d2max_f32(wl.radius), wl.k_max, wl.edge_logit_min, "bf16",
+                       max_hits=batch.n_hits, max_events=batch.n_events, max_event_hits=batch.max_event_hits())
+    ctx.set_params(torch.from_numpy(synth.centred_params(wl)).cuda())
+    ctx.set_tuning(7)
+    hits = velo.DeviceHits.from_batch(batch)
+    out = ctx.alloc_outputs(hits)
+    graph = ctx.capture(hits, out)
+    eager = velo.graph_to_host(ctx.infer(hits), batch.n_hits)
+    for rep in range(3):
+        for k in ("edge_logit", "labels"):
+            out[k].fill_(-7)
+        graph.launch()
+        torch.cuda.synchronize()
+        ctx.check()
+        got = velo.graph_to_host(out, batch.n_hits)
+        for k in ("edge_offsets", "src", "dst", "logit", "labels"):
+            np.testing.assert_array_equal(got[k], eager[k], err_msg=f"replay {rep} {k}")
+        ctx.infer(hits)
+        torch.cuda.synchronize()
+    graph.close()
+    torch.cuda.synchronize()
+    torch.cuda.set_stream(torch.cuda.default_stream())
+    print(f"  {eager['n_edges']} edges, 3 replays identical", flush=True)
+
+
 @pytest.mark.parametrize("precision", ["fp32", "bf16"])
 def test_autotuned_launches_give_identical_results(precision):
     """Launch parameters and tile shapes (blocks per CU, MLP workgroup size,
