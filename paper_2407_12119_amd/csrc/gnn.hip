@@ -453,7 +453,8 @@ __global__ __launch_bounds__(WIDE ? 1024 : 512) void k_mlp(MlpArgs A) {
     };
     if constexpr (src_aligned<P, MODE, CLS>()) {
         // Work units are source hits (edges are grouped by source), walked in
-        // chunks of 16 of their out-edges, two chunks in flight.  After a
+        // chunks of 16 of their out-edges (two chunks in flight for the
+        // 2-byte states and the factorised encoder, one otherwise).  After a
         // chunk's states are stored, their stored values are summed over the
         // chunk's edges per channel (row_sum16) and added up over the hit's
         // chunks in order: the outgoing message sum of the hit (Sec. 5.2),
