@@ -307,6 +307,41 @@ __device__ inline float row_sum16(float v) {
     return dpp_add<0xB1>(v);   // quad_perm [1,0,3,2]
 }
 
+// Row sums of V values per lane over the 16 lanes of each DPP row, with the
+// same four partner steps: at each step a lane keeps half of its values (the
+// even or odd ones of each pair, by the bit of its row position n in which it
+// differs from the partner: 8, 4, 2, 1) and adds the partner's copy of them,
+// so the work halves at every step.  Afterwards v[t] (t < V / 16, or t = 0
+// for V = 8) is the row total of value 16 t + r(n), r(n) = 8 b0 + 4 b1 + 2 b2
+// + b3 with b_k bit k of n (for V = 8: value r(n) & 7, the last step a plain
+// sum, so lanes n and n ^ 1 agree).  Fixed order, so deterministic.
+template <int CTRL>
+__device__ inline float dpp_move(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, true));
+}
+template <int CTRL, int BIT, int C>
+__device__ inline void row_sums_step(float *v, int n) {
+    if constexpr (C == 1) {
+        v[0] += dpp_move<CTRL>(v[0]);
+    } else {
+        const bool hi = (n & BIT) != 0;
+#pragma unroll
+        for (int j = 0; j < C / 2; j++) {
+            const float keep = hi ? v[2 * j + 1] : v[2 * j];
+            const float send = hi ? v[2 * j] : v[2 * j + 1];
+            v[j] = keep + dpp_move<CTRL>(send);
+        }
+    }
+}
+template <int V>
+__device__ inline void row_sums(float *v, int n) {
+    static_assert(V == 8 || V == 16 || V == 32, "4 MO values per lane");
+    row_sums_step<0x128, 8, V>(v, n);
+    row_sums_step<0x141, 4, V / 2>(v, n);
+    row_sums_step<0x4E, 2, V / 4>(v, n);
+    row_sums_step<0xB1, 1, (V / 8 > 1 ? V / 8 : 1)>(v, n);
+}
+
 // The first layer of an MLP: every input segment but the node network's two
 // message sums is a stored encoding (bf16 already in 2-byte precisions, so a
 // split operand's lo part is 0 there).
@@ -456,10 +491,11 @@ __global__ __launch_bounds__(WIDE ? 1024 : 512) void k_mlp(MlpArgs A) {
         // chunks of 16 of their out-edges (two chunks in flight for the
         // 2-byte states and the factorised encoder, one otherwise).  After a
         // chunk's states are stored, their stored values are summed over the
-        // chunk's edges per channel (row_sum16) and added up over the hit's
-        // chunks in order: the outgoing message sum of the hit (Sec. 5.2),
-        // written by lane n = 0 of each row.  Partial sums of a hit with more
-        // than 16 edges wait in this wave's LDS slot.
+        // chunk's edges per channel (row_sums: each lane ends with the totals
+        // of H / 64 channels) and added up over the hit's chunks in order: the
+        // outgoing message sum of the hit (Sec. 5.2), written by every lane
+        // for its channels.  Partial sums of a hit with more than 16 edges
+        // wait in this wave's LDS slot.
         float *carry = sB + 2 * H + (threadIdx.x >> 6) * H;
         // the walk is uniform over the wavefront: keep it in scalar registers
         const WaveRange wv = wave_range(A.n_rows, A.xcd != 0);
@@ -561,21 +597,28 @@ __global__ __launch_bounds__(WIDE ? 1024 : 512) void k_mlp(MlpArgs A) {
             if (!A.mout) {
                 if (ok) P::template store_all<MO>((S *)A.out + q * H, g, o);
             } else {
-                // the states as stored, summed over the chunk's edges
+                // the states as stored, summed over the chunk's edges: lane n
+                // of a row keeps the totals of values 16 t + r(n) (row_sums)
                 P::template store_round<MO>((S *)A.out + q * H, g, o, ok);
+                constexpr int V = 4 * MO, T = V >= 16 ? V / 16 : 1;
+                float v[V];
 #pragma unroll
                 for (int mo = 0; mo < MO; mo++)
 #pragma unroll
-                    for (int i = 0; i < 4; i++) o[mo][i] = row_sum16(o[mo][i]);
-                if (n == 0) {
+                    for (int i = 0; i < 4; i++) v[4 * mo + i] = o[mo][i];
+                row_sums<V>(v, n);
+                const int r = 8 * (n & 1) + 4 * ((n >> 1) & 1) + 2 * ((n >> 2) & 1) + ((n >> 3) & 1);
+                if (V >= 16 || (n & 1) == 0) {
 #pragma unroll
-                    for (int mo = 0; mo < MO; mo++) {
-                        f32x4 *cm = (f32x4 *)(carry + P::stored(mo, g));
-                        if (cur.c0 != cur.a0) o[mo] = *cm + o[mo];
+                    for (int t = 0; t < T; t++) {
+                        const int k = V >= 16 ? 16 * t + r : (r & 7);
+                        const int c = P::stored(k >> 2, g) + (k & 3);
+                        float tot = v[t];
+                        if (cur.c0 != cur.a0) tot += carry[c];
                         if (cur.c0 + 16 >= cur.a1)
-                            *(f32x4 *)(A.mout + cur.i * 2 * H + P::stored(mo, g)) = o[mo];
+                            A.mout[cur.i * 2 * H + c] = tot;
                         else
-                            *cm = o[mo];
+                            carry[c] = tot;
                     }
                 }
             }
