@@ -603,7 +603,35 @@ def oracle_agreement(synth, wl, sample, ref, gpu):
     err = np.abs(g["z"][ib] - zr) / np.maximum(np.abs(zr), 1.0) if ia.size else np.zeros(1)
     mo = metrics.track_metrics(ref["labels"], sample.pid, sample.event_offsets)
     mg = metrics.track_metrics(g["labels"], sample.pid, sample.event_offsets)
+    # the pairs in one edge set only, by the oracle's float64 embedding
+    # distance: within 1e-6 relative of the radius (reported separately), at
+    # the row's k_max-th distance (within 1e-5 relative: the bounded list's
+    # cut), or neither
+    kd = np.setxor1d(kr, kg)
+    eoff = np.asarray(sample.event_offsets, np.int64)
+    ev, i, j = kd >> 42, (kd >> 21) & ((1 << 21) - 1), kd & ((1 << 21) - 1)
+    emb = np.asarray(ref["emb"], np.float64)
+    d2 = ((emb[eoff[ev] + i] - emb[eoff[ev] + j]) ** 2).sum(1) if kd.size else np.zeros(0)
+    rs = np.repeat(np.arange(S, dtype=np.int64), np.diff(np.asarray(ref["edge_offsets"], np.int64)))
+    ref_d2 = ((emb[eoff[rs] + ref["src"]] - emb[eoff[rs] + ref["dst"]]) ** 2).sum(1)
+    row_key = (rs << 21) | np.asarray(ref["src"], np.int64)
+    kth = {}
+    if row_key.size:
+        order = np.argsort(row_key, kind="stable")
+        keys, first, counts = np.unique(row_key[order], return_index=True, return_counts=True)
+        mx = np.maximum.reduceat(ref_d2[order], first)
+        kth = {int(k): float(m) for k, m, c in zip(keys, mx, counts) if c >= wl.k_max}
+    near_r = int(np.sum(np.abs(np.sqrt(d2) - wl.radius) <= 1e-6 * wl.radius))
+    at_k = 0
+    for e in range(kd.size):
+        if abs(math.sqrt(d2[e]) - wl.radius) <= 1e-6 * wl.radius:
+            continue
+        dk = kth.get(int((ev[e] << 21) | i[e]))
+        if dk is not None and abs(d2[e] - dk) <= 1e-5 * max(dk, 1e-12):
+            at_k += 1
     return {"jaccard": round(a["jaccard"], 6), "decision_agreement": round(a["decision_agreement"], 6),
+            "edges_in_one_set": int(kd.size), "of_which_within_1e-6_of_radius": near_r,
+            "of_which_at_k_max_cut": at_k, "of_which_other": int(kd.size) - near_r - at_k,
             "max_logit_err": round(float(err.max()), 6), "p99_logit_err": round(float(np.percentile(err, 99)), 6),
             "labels_identical": round(float(np.mean(g["labels"] == ref["labels"])), 6),
             "efficiency_oracle": round(mo["efficiency"], 5),

@@ -62,3 +62,25 @@ def test_stored_tuning_is_parsed_and_checked():
     for bad in ("edge_net=8", "edge_net", "nope=1", "knn=-1"):
         with pytest.raises(SystemExit):
             bench.parse_tuning(velo, bad)
+
+
+def test_oracle_agreement_counts_the_edges_in_one_set_only():
+    """bench.py's comparison with the oracle counts the pairs that are in one
+    edge set only, by their distance class (radius band, k_max cut, other)."""
+    import numpy as np
+    import oracle
+    from paper_2407_12119_amd import synth
+    wl = synth.WORKLOADS["batch256"]
+    b = synth.make_batch(wl, n_events=2, first=3)
+    ref = oracle.pipeline(b, synth.centred_params(wl), wl.hidden, wl.iters, wl.radius, wl.k_max, wl.edge_logit_min)
+    g = {"edge_offsets": ref["edge_offsets"].astype(np.int64), "src": ref["src"].copy(), "dst": ref["dst"].copy(),
+         "logit": ref["logit"].astype(np.float32), "labels": ref["labels"].copy()}
+    r = bench.oracle_agreement(synth, wl, b, ref, g)
+    assert r["edges_in_one_set"] == 0 and r["jaccard"] == 1.0 and r["labels_identical"] == 1.0
+    # drop an edge of event 0 from the "GPU" set: one pair in one set only
+    h = dict(g, src=np.delete(g["src"], 5), dst=np.delete(g["dst"], 5), logit=np.delete(g["logit"], 5))
+    h["edge_offsets"] = g["edge_offsets"].copy()
+    h["edge_offsets"][1:] -= 1
+    r = bench.oracle_agreement(synth, wl, b, ref, h)
+    assert r["edges_in_one_set"] == 1
+    assert r["of_which_within_1e-6_of_radius"] + r["of_which_at_k_max_cut"] + r["of_which_other"] == 1
