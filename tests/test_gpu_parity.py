@@ -428,6 +428,41 @@ def test_captured_graph_replays_match_eager_calls():
     torch.cuda.set_stream(torch.cuda.default_stream())
 
 
+@pytest.mark.parametrize("kind", ["empty_and_tiny", "one_hit_per_plane"])
+def test_xcd_work_walk_on_degenerate_batches(kind):
+    """H = 128 with the 16-wavefront edge MLPs and their per-XCD work walk
+    (candidate 7) on batches with empty events, one-hit events and hits
+    without out-edges: bitwise the results of the default launches."""
+    wl = synth.WORKLOADS["batch1000_h128"]
+    empty = synth.Event(*(np.zeros(0, dt) for dt in (np.float32, np.float32, np.float32, np.int32, np.int64,
+                                                      np.int32)))
+    if kind == "empty_and_tiny":
+        evs = [empty, synth.make_batch(wl, n_events=1, first=3).event(0), empty, empty]
+        one = synth.make_batch(wl, n_events=1, first=4).event(0)
+        k = np.arange(1)
+        evs.append(synth.Event(one.x[k], one.y[k], one.z[k], one.plane[k], one.pid[k], one.next_hit[k] * 0 - 1))
+        evs.append(empty)
+    else:
+        # one hit on each plane: every hit has at most two out-edges
+        plane = np.arange(26, dtype=np.int32)
+        evs = [synth.Event(np.full(26, 10.0, np.float32), np.full(26, 10.0, np.float32),
+                           synth.PLANE_Z[plane].astype(np.float32), plane, np.zeros(26, np.int64),
+                           np.full(26, -1, np.int32))]
+    batch = synth.to_batch(evs)
+    print(f"\n[case] xcd work walk {kind} events={batch.n_events} hits={batch.n_hits}", flush=True)
+    ctx = velo.Context(wl.hidden, wl.iters, oracle.d2max_f32(wl.radius), wl.k_max, wl.edge_logit_min, "bf16",
+                       max_hits=max(batch.n_hits, 1), max_events=batch.n_events,
+                       max_event_hits=max(batch.max_event_hits(), 1))
+    ctx.set_params(torch.from_numpy(synth.centred_params(wl)).cuda())
+    hits = velo.DeviceHits.from_batch(batch)
+    ref = velo.graph_to_host(ctx.infer(hits), batch.n_hits)
+    ctx.set_tuning(7)
+    got = velo.graph_to_host(ctx.infer(hits), batch.n_hits)
+    for k in ("edge_offsets", "src", "dst", "logit", "labels"):
+        np.testing.assert_array_equal(got[k], ref[k], err_msg=k)
+    print(f"  {ref['n_edges']} edges identical", flush=True)
+
+
 def test_captured_graph_replays_with_the_xcd_work_counters():
     """H = 128 with the 16-wavefront edge MLPs (candidate 7): their per-XCD
     work counters are cleared by a fill kernel before every launch, which a
