@@ -292,26 +292,12 @@ constexpr size_t mlp_lds() {
            (src_aligned<P, MODE, CLS>() ? sizeof(float) * H * ((WIDE ? 2 : 1) * kMlpBlock / 64) : 0);
 }
 
-// Sum over the 16 lanes of each DPP row (every lane gets the row's sum):
+// Row sums of V values per lane over the 16 lanes of each DPP row.  The
 // partners n^8 (row rotate by 8), n^7 (half-row mirror), n^2 and n^1 (quad
-// permutations) generate the whole row.  Fixed order, so deterministic.
-template <int CTRL>
-__device__ inline float dpp_add(float v) {
-    return v + __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF,
-                                                                     true));
-}
-__device__ inline float row_sum16(float v) {
-    v = dpp_add<0x128>(v);     // row_ror:8
-    v = dpp_add<0x141>(v);     // row_half_mirror
-    v = dpp_add<0x4E>(v);      // quad_perm [2,3,0,1]
-    return dpp_add<0xB1>(v);   // quad_perm [1,0,3,2]
-}
-
-// Row sums of V values per lane over the 16 lanes of each DPP row, with the
-// same four partner steps: at each step a lane keeps half of its values (the
-// even or odd ones of each pair, by the bit of its row position n in which it
-// differs from the partner: 8, 4, 2, 1) and adds the partner's copy of them,
-// so the work halves at every step.  Afterwards v[t] (t < V / 16, or t = 0
+// permutations) generate the whole row; at each step a lane keeps half of
+// its values (the even or odd ones of each pair, by the bit of its row
+// position n in which it differs from the partner: 8, 4, 2, 1) and adds the
+// partner's copy of them, so the work halves at every step.  Afterwards v[t] (t < V / 16, or t = 0
 // for V = 8) is the row total of value 16 t + r(n), r(n) = 8 b0 + 4 b1 + 2 b2
 // + b3 with b_k bit k of n (for V = 8: value r(n) & 7, the last step a plain
 // sum, so lanes n and n ^ 1 agree).  Fixed order, so deterministic.
