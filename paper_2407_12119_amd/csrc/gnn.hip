@@ -562,6 +562,13 @@ __global__ __launch_bounds__(WIDE ? 1024 : 512) void k_mlp(MlpArgs A) {
                 }
             }
             constexpr int AG = WIDE ? MO / 2 : MO;   // weight fragments held at a time
+            // The products run at raised wavefront priority: a wavefront with
+            // its inputs in registers keeps the matrix cores until its chunk's
+            // products are done, and the other wavefronts of the SIMD issue
+            // their loads and epilogues in the gaps.  The wavefronts stay
+            // staggered rather than reaching their loads together (measured:
+            // -4% per float32 edge network launch; not in the 16-wavefront form)
+            if constexpr (!WIDE) __builtin_amdgcn_s_setprio(1);
             if constexpr (NSEG > 0) gemm_first<P, MO, KB, NSEG, MODE, AG>(sW1, X, hid, lane);
             if (P::kScaled) rescale<MO>(hid, SC.d1);
             relu<MO>(hid);
@@ -570,6 +577,7 @@ __global__ __launch_bounds__(WIDE ? 1024 : 512) void k_mlp(MlpArgs A) {
             P::template chain<MO>(hid, xh, SC.ix2);
             load_bias<MO>(sB + H, o, g);
             gemm<P, MO, KB, 0, KB, false, AG>(sW2, xh, o, lane);
+            if constexpr (!WIDE) __builtin_amdgcn_s_setprio(0);
             if (P::kScaled) rescale<MO>(o, SC.d2);
             if constexpr (edge_update<MODE>()) {   // residual (Sec. 5.2), from the unquantised state
 #pragma unroll
@@ -742,6 +750,9 @@ __global__ __launch_bounds__(WIDE ? 1024 : 512) void k_mlp(MlpArgs A) {
                     hid[mo] += G[MO + mo];
                 }
             }
+            // raised priority over the products, as in the source walk (in the
+            // classifier-fused edge network only: the node network ran slower)
+            if constexpr (CLS) __builtin_amdgcn_s_setprio(1);
             if constexpr (NSEG > 0) gemm_first<P, MO, KB, NSEG, MODE, AGU>(sW1, X, hid, lane);
             if (P::kScaled) rescale<MO>(hid, SC.d1);
             relu<MO>(hid);
@@ -769,6 +780,7 @@ __global__ __launch_bounds__(WIDE ? 1024 : 512) void k_mlp(MlpArgs A) {
             for (int mo = 0; mo < MO; mo++) o[mo] = P::load4(sa + qc * H + P::stored(mo, g));
         }
         if (CLS) classify<P, H>(sC1, sCB, b_out, o, SCc, AMAX ? A.amax_cls : nullptr, lane, ok, q, A.logit);
+        if constexpr (CLS) __builtin_amdgcn_s_setprio(0);
     }
 }
 
