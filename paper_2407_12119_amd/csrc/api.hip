@@ -66,7 +66,7 @@ void free_ws(Workspace &w) {
                     w.scales, w.amax, w.tmp_logit, w.i8_scales, w.i8_amax, w.t_u, w.t_a1, w.t_a2, w.t_dz1, w.t_dz2, w.t_dz3,
                     w.t_nbr, w.t_deg, w.t_acc, w.t_stat, w.t_part};
     for (void *p : ptrs)
-        if (p) hipFree(p);
+        if (p) (void)hipFree(p);
     w = Workspace();
 }
 
@@ -98,11 +98,12 @@ velo_status device_status(velo_ctx *c, const char *where) {
 struct DeviceGuard {
     int prev = -1;
     explicit DeviceGuard(int dev) {
-        if (hipGetDevice(&prev) == hipSuccess && prev != dev) hipSetDevice(dev);
+        // a failed switch shows as the error of the calls that follow
+        if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
         else prev = -1;
     }
     ~DeviceGuard() {
-        if (prev >= 0) hipSetDevice(prev);
+        if (prev >= 0) (void)hipSetDevice(prev);
     }
 };
 
@@ -174,8 +175,11 @@ velo_status velo_create(const velo_config *cfg, velo_ctx **out) {
         return VELO_ERR_DEVICE;
     }
     int ncu = 0, lds = 0;
-    hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device);
-    hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device);
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess ||
+        hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) != hipSuccess) {
+        delete c;
+        return VELO_ERR_DEVICE;
+    }
     c->n_cu = ncu > 0 ? ncu : 1;
     c->lds_max = (size_t)lds;
     // one event's hits must fit the LDS of one workgroup (lists, components)
@@ -223,17 +227,16 @@ velo_status velo_create(const velo_config *cfg, velo_ctx **out) {
              dalloc(&w.t_part, emb_train_chunks(N) * (Ce * 3 + Ce + Ce * Ce + Ce + VELO_EMB_DIM * Ce + VELO_EMB_DIM));
     }
     if (!ok) {
-        hipGetLastError();
+        (void)hipGetLastError();   // clear the failed allocation's error
         free_ws(w);
-        if (c->params) hipFree(c->params);
+        if (c->params) (void)hipFree(c->params);
         delete c;
         return VELO_ERR_OOM;
     }
-    hipMemset(w.flags, 0, sizeof(unsigned));
-    hipMemset(w.n_edges, 0, sizeof(int));
-    if (hipDeviceSynchronize() != hipSuccess) {
+    if (hipMemset(w.flags, 0, sizeof(unsigned)) != hipSuccess || hipMemset(w.n_edges, 0, sizeof(int)) != hipSuccess ||
+        hipDeviceSynchronize() != hipSuccess) {
         free_ws(w);
-        hipFree(c->params);
+        (void)hipFree(c->params);
         delete c;
         return VELO_ERR_DEVICE;
     }
@@ -246,14 +249,14 @@ static void free_triplet_ws(TripletWs &T);
 void velo_destroy(velo_ctx *c) {
     if (!c) return;
     DeviceGuard g(c->device);
-    hipDeviceSynchronize();
+    (void)hipDeviceSynchronize();   // teardown goes on whatever an earlier failure left
     for (auto &e : c->ev_pool) {
-        hipEventDestroy(e.start);
-        hipEventDestroy(e.stop);
+        (void)hipEventDestroy(e.start);
+        (void)hipEventDestroy(e.stop);
     }
     free_ws(c->ws);
     free_triplet_ws(c->tri);
-    if (c->params) hipFree(c->params);
+    if (c->params) (void)hipFree(c->params);
     delete c;
 }
 
@@ -488,7 +491,7 @@ static void free_triplet_ws(TripletWs &T) {
                     T.first, T.second, T.dup, T.touched, T.single, T.single_ptr, T.shared, T.shared_ptr,
                     T.scan_tmp};
     for (void *p : ptrs)
-        if (p) hipFree(p);
+        if (p) (void)hipFree(p);
     T = TripletWs();
 }
 
@@ -497,10 +500,10 @@ velo_status velo_set_triplet_params(velo_ctx *c, const float *params, int64_t n,
     if (!c) return VELO_ERR_INVALID_ARG;
     DeviceGuard gd(c->device);
     if (!params && n == 0) {
-        hipDeviceSynchronize();
+        const bool synced = hipDeviceSynchronize() == hipSuccess;
         free_triplet_ws(c->tri);
         c->tri_set = false;
-        return VELO_OK;
+        return synced ? VELO_OK : fail(c, VELO_ERR_DEVICE, "hipDeviceSynchronize failed");
     }
     if (!triplet_supported(c->cfg.gnn_hidden))
         return fail(c, VELO_ERR_UNSUPPORTED, "triplet stage: unsupported hidden width");
@@ -511,7 +514,7 @@ velo_status velo_set_triplet_params(velo_ctx *c, const float *params, int64_t n,
         return fail(c, VELO_ERR_INVALID_ARG, "max_triplets must be in 0 .. 2^30 - 1");
     TripletWs &T = c->tri;
     if (!T.params || T.cap != max_triplets) {
-        hipDeviceSynchronize();
+        if (hipDeviceSynchronize() != hipSuccess) return fail(c, VELO_ERR_DEVICE, "hipDeviceSynchronize failed");
         free_triplet_ws(T);
         const int64_t N = c->cfg.max_hits, E = c->cfg.max_edges, Tc = max_triplets;
         const int64_t big = std::max(std::max(N, E), Tc);
@@ -592,7 +595,8 @@ velo_status velo_read_timing(velo_ctx *c, double *ms, int64_t *launches) {
         StageEvents &e = c->ev_pool[i];
         if (hipEventSynchronize(e.stop) != hipSuccess) return fail(c, VELO_ERR_DEVICE, "hipEventSynchronize failed");
         float t = 0.f;
-        hipEventElapsedTime(&t, e.start, e.stop);
+        if (hipEventElapsedTime(&t, e.start, e.stop) != hipSuccess)
+            return fail(c, VELO_ERR_DEVICE, "hipEventElapsedTime failed");
         c->stage_ms[e.stage] += t;
         c->stage_launches[e.stage] += 1;
     }
@@ -646,9 +650,9 @@ velo_status velo_graph_capture(velo_ctx *c, const velo_hits *h, velo_outputs *o,
     st = velo_infer(c, h, o, stream);
     const hipError_t e = hipStreamEndCapture(s, &g->graph);
     if (st || e != hipSuccess || hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) != hipSuccess) {
-        if (g->graph) hipGraphDestroy(g->graph);
+        if (g->graph) (void)hipGraphDestroy(g->graph);
         delete g;
-        hipGetLastError();
+        (void)hipGetLastError();   // clear the capture's error
         return st ? st : fail(c, VELO_ERR_DEVICE, "graph capture or instantiation failed");
     }
     *out = g;
@@ -665,8 +669,8 @@ velo_status velo_graph_launch(velo_graph *g, void *stream) {
 void velo_graph_destroy(velo_graph *g) {
     if (!g) return;
     DeviceGuard gd(g->ctx->device);
-    if (g->exec) hipGraphExecDestroy(g->exec);
-    if (g->graph) hipGraphDestroy(g->graph);
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
     delete g;
 }
 
@@ -825,7 +829,8 @@ velo_status velo_check(velo_ctx *c, void *stream) {
         return fail(c, VELO_ERR_DEVICE, "velo_check: stream synchronisation failed");
     if (f) {
         const unsigned zero = 0;
-        hipMemcpy(c->ws.flags, &zero, sizeof zero, hipMemcpyHostToDevice);
+        if (hipMemcpy(c->ws.flags, &zero, sizeof zero, hipMemcpyHostToDevice) != hipSuccess)
+            return fail(c, VELO_ERR_DEVICE, "velo_check: clearing the error flags failed");
     }
     if (f & kErrInput) return fail(c, VELO_ERR_INPUT, "device validation of the hits failed");
     if (f & kErrCapacity) return fail(c, VELO_ERR_CAPACITY, "edge count exceeds the edge capacity");

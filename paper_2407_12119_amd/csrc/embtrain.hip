@@ -328,7 +328,7 @@ __global__ void k_emb_loss(const unsigned long long *__restrict__ stat, float w_
 }
 
 inline int blocks_per_cu_dyn(const void *kernel, int block, size_t lds) {
-    hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    (void)hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);   // a failure is the launch's error
     int n = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, block, lds) != hipSuccess || n < 1) n = 1;
     return n;

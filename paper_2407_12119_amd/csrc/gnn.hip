@@ -867,7 +867,7 @@ __global__ __launch_bounds__(256) void k_messages(int64_t n_hits, const int *__r
 // Blocks of `block` threads with `lds` bytes of LDS that fit on one compute
 // unit together (at least 1); also lifts the dynamic-LDS launch limit.
 inline int blocks_per_cu(const void *kernel, int block, size_t lds) {
-    hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    (void)hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);   // a failure is the launch's error
     int n = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, block, lds) != hipSuccess || n < 1) n = 1;
     return n;

@@ -232,13 +232,13 @@ struct StageTimer {
         if (c->ev_used < c->ev_pool.size()) {
             ev = &c->ev_pool[c->ev_used++];
             ev->stage = stage;
-            hipEventRecord(ev->start, s);
+            (void)hipEventRecord(ev->start, s);   // a failed record fails velo_read_timing
         } else {
             c->ev_dropped++;         // reported by velo_read_timing
         }
     }
     ~StageTimer() {
-        if (ev) hipEventRecord(ev->stop, s);
+        if (ev) (void)hipEventRecord(ev->stop, s);
     }
 };
 

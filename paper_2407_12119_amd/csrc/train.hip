@@ -760,10 +760,10 @@ void run_bwd(velo_ctx *c, const BwdArgs &a, hipStream_t s) {
     constexpr bool CLS = MODE == B_CLS;
     constexpr size_t lds = frag_bytes<P>(H, K1) + (CLS ? 0 : frag_bytes<P>(H, H)) + frag_bytes<P>(K1, H);
     static const int per_cu = [] {
-        hipFuncSetAttribute(reinterpret_cast<const void *>(&k_bwd<H, MODE>), hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)lds);
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_bwd<H, MODE>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);   // a failure is the launch's error
         int n = 0;
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void *>(&k_bwd<H, MODE>), kBwdBlock, lds);
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void *>(&k_bwd<H, MODE>), kBwdBlock, lds);
         return n < 1 ? 1 : n;
     }();
     k_bwd<H, MODE><<<persistent_grid(c, per_cu), kBwdBlock, lds, s>>>(a);
@@ -826,10 +826,10 @@ void backward_h(velo_ctx *c, const velo_hits *hits, const float *Pw, const float
             StageTimer t(c, VELO_STAGE_BWD_MLP, s);
             constexpr size_t lds = 2 * frag_bytes<P>(H, H);
             static const int per_cu = [] {
-                hipFuncSetAttribute(reinterpret_cast<const void *>(&k_hit_dual<H>),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+                (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_hit_dual<H>),
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
                 int m = 0;
-                hipOccupancyMaxActiveBlocksPerMultiprocessor(&m, reinterpret_cast<const void *>(&k_hit_dual<H>),
+                (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&m, reinterpret_cast<const void *>(&k_hit_dual<H>),
                                                              kBwdBlock, lds);
                 return m < 1 ? 1 : m;
             }();

@@ -379,8 +379,8 @@ template <class P, int H>
 void run_tri_cls(velo_ctx *c, const int *n_dev, const int *pairs, const float *Pw, float *logit, hipStream_t s) {
     const size_t lds = frag_bytes<P>(H, 2 * H) + sizeof(float) * 2 * H;
     int per_cu = 0;
-    hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(&k_tri_cls<P, H>), 512,
-                                                 lds);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(&k_tri_cls<P, H>),
+                                                       512, lds);   // 0 on failure: one block per CU
     if (per_cu < 1) per_cu = 1;
     k_tri_cls<P, H><<<persistent_grid(c, per_cu), 512, lds, s>>>(n_dev, pairs,
                                                                  (const typename P::state_t *)c->ws.e, Pw, logit,

@@ -168,9 +168,9 @@ void launch_components_sweep(velo_ctx *c, const velo_hits *h, const velo_outputs
     static bool attr = false;
     if (!attr) {
         // the kernel's static LDS (the plane ranges) comes out of the same budget
-        hipFuncSetAttribute(reinterpret_cast<const void *>(&k_wcc_sweep),
-                            hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)(c->lds_max - sizeof(int) * kPlaneSlots));
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_wcc_sweep),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)(c->lds_max - sizeof(int) * kPlaneSlots));   // a failure is the launch's error
         attr = true;
     }
     k_wcc_sweep<<<h->n_events, 1024, lds, s>>>(h->n_events, h->event_offsets, g->edge_offsets, c->ws.n_edges, cap,
