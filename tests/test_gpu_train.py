@@ -344,7 +344,7 @@ def test_autograd_function_gives_the_library_gradient():
     ctx.train_forward(hits, graph, params)
     loss2, dz = ctx.bce(graph["edge_logit"], yt, 3.0, n)
     g2 = ctx.train_backward(hits, params, dz)
-    assert float(loss) == float(loss2.cpu()[0])
+    assert float(loss.detach()) == float(loss2.cpu()[0])
     assert torch.equal(p.grad, g2)
     z = train.edge_logits(ctx, p, hits, graph, n)
     ctx.train_forward(hits, graph, params)
